@@ -1,0 +1,162 @@
+/*
+ * sarabande_hip.h -- C ABI of the MI355X (gfx950) SARABANDE hot path.
+ *
+ * The library measures 3- and 4-point correlation functions of gridded
+ * density fields with the FFT method of Sunseri et al. 2022 (arXiv 2210.10206):
+ * radially binned angular kernels (Y_lm in 3D, e^{-i m phi} in projected 2D)
+ * are correlated with the density by FFTs to give the expansion coefficients
+ * about every cell (a^b_lm, eq. almconv; c^b_m, eq. discretize_cmb), which are
+ * then contracted with the density and summed over the grid (Alg. 5-8).
+ *
+ * Conventions (all sizes in grid cells, unit spacing, periodic boundaries):
+ *  - Arrays are C-ordered; 3D axes (x, y, z) = (axis 0, 1, 2), 2D (x, y) = (axis 0, 1),
+ *    phi = atan2(y, x).
+ *  - Offsets are zero-centred: coordinate c(i) = i for 2i < N, else i - N
+ *    (notes to Alg. 1 and Alg. 2).  Offset r is in bin b iff e_b < |r| <= e_{b+1},
+ *    decided exactly on the float64 edges (the mask of Alg. 1 / Alg. 2); r = 0 is in no bin.
+ *  - a^b_lm(x) = sum_{r in b} conj(Y_lm(r^)) delta(x + r) (a correlation, eq. almconv
+ *    and its footnote); c^b_m(x) = sum_{r in b} e^{-i m phi(r)} delta(x + r).  Masks are
+ *    unnormalised (the 1/V_b of eq. bin_volume_unity is not applied).
+ *  - Results are the raw grid sums of the appendix algorithms, without the
+ *    (-1)^l/sqrt(2l+1), 1/(2 pi)^2 and 1/V prefactors (Sec. 2.1, 2.2) and without the
+ *    normalisation of Sec. 2.5 (the caller can apply it with sb_bin_counts).
+ *  - All ordered bin tuples are returned, diagonals included.
+ *
+ * Output layouts (float64 per field, complex values interleaved re, im):
+ *  - full 3PCF  (ndim 3, npcf 3): Z[l][b1][b2], l = 0..lmax, real;
+ *        Z = sum_x delta sum_{m=-l..l} a^b1_lm conj(a^b2_lm)          (Alg. 5)
+ *  - full 4PCF  (ndim 3, npcf 4): Z[L][b1][b2][b3], real, L over the even-parity
+ *        (l1, l2, l3) of Alg. 6's loop order (l1 outer, l2, then l3 from |l1-l2| to
+ *        min(l1+l2, lmax));  Z = sum_x delta sum_M 3j(l1 l2 l3; m1 m2 m3) a a a   (Alg. 6, Sec. 2.3)
+ *  - projected 3PCF (ndim 2, npcf 3): Z[m][b1][b2] complex, m = 0..mmax;
+ *        Z = sum_x delta c^b1_m conj(c^b2_m)                           (Alg. 7)
+ *  - projected 4PCF (ndim 2, npcf 4): Z[p][b1][b2][b3] complex, p over (m1, m2) with m1
+ *        outer in -mmax..mmax, m2 inner, |m1 + m2| <= mmax;
+ *        Z = sum_x delta c^b1_m1 c^b2_m2 c^b3_{-(m1+m2)}, c_{-m} = conj(c_m)  (Alg. 8, eq. proj_4pcf_coeff)
+ *
+ * Memory: every device buffer is owned by the caller.  The plan owns host
+ * metadata and a small device table block it allocates at sb_plan_create.
+ * sb_forward / sb_backward / sb_prepare allocate nothing; they enqueue work on
+ * the given stream (a hipStream_t passed as void*, NULL = default stream) and
+ * return before it finishes.  A plan must not be used from two threads at once.
+ *
+ * Errors: every call returns an sb_status; argument checks happen before any
+ * launch; sb_last_error() gives a thread-local message for the last failure.
+ */
+#ifndef SARABANDE_HIP_H
+#define SARABANDE_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SB_OK = 0,
+    SB_EINVAL = -1,        /* invalid argument (shape, edges, lmax, npcf, ndim, null pointer) */
+    SB_EUNSUPPORTED = -2,  /* valid but not supported by this build (grid edge, bin count) */
+    SB_EWORKSPACE = -3,    /* bound workspace too small or not bound */
+    SB_EHIP = -4,          /* a HIP runtime call failed (detail in sb_last_error) */
+    SB_ENOMEM = -5,        /* host allocation failed */
+    SB_ESTATE = -6         /* call out of order (e.g. forward before sb_prepare) */
+} sb_status;
+
+typedef enum { SB_PREC_FP32 = 0, SB_PREC_SPLIT_BF16 = 1 } sb_precision;
+typedef enum { SB_IN_F32 = 0, SB_IN_F64 = 1 } sb_input_dtype;
+
+/* Flags */
+enum {
+    SB_FLAG_KEEP_COEFFS = 1u  /* keep every a / c array of the last field in scratch (sb_coeffs) */
+};
+
+/* Problem statement: the grid, bins, lmax, full or projected, 3 or 4 PCF
+ * (the measure(**kwargs) of Sec. 3.3: projected, NPCF). */
+typedef struct {
+    int32_t ndim;              /* 3 = full (Y_lm kernels), 2 = projected (e^{-i m phi} kernels) */
+    int32_t npcf;              /* 3 or 4 */
+    int32_t nbins;             /* 1 .. 16 */
+    const double *bin_edges;   /* host, nbins + 1 values, strictly increasing, edges[0] >= 0 */
+    int32_t lmax;              /* 3D: l = 0..lmax (<= 10); 2D: mmax, m = 0..mmax (<= 16) */
+    int32_t precision;         /* sb_precision: contraction arithmetic for the 4PCF paths */
+    int32_t input_dtype;       /* sb_input_dtype of the density arrays */
+    uint32_t flags;
+} sb_problem;
+
+typedef struct sb_plan sb_plan;
+
+/* Create a plan for a batch of `batch` fields whose shapes are given row by row in
+ * `shapes` (batch x ndim, host).  Fields may differ in shape (uneven batch); each
+ * grid edge must be one of 8, 12, 16, 24, 32, 48, 64, 96, 128, 160, 192, 256, 512.
+ * Allocates host metadata and a small device table block on the current device. */
+sb_status sb_plan_create(const sb_problem *prob, int32_t batch, const int64_t *shapes, sb_plan **out);
+void sb_plan_destroy(sb_plan *plan);
+
+/* Device bytes the caller must provide: `persistent` holds the kernel spectra of every
+ * distinct shape (kept between calls), `scratch` the per-field working arrays. */
+sb_status sb_plan_workspace(const sb_plan *plan, size_t *persistent_bytes, size_t *scratch_bytes);
+
+/* Bind caller-owned device buffers (at least the sizes above, 256-byte aligned). */
+sb_status sb_plan_bind(sb_plan *plan, void *persistent, size_t persistent_bytes,
+                       void *scratch, size_t scratch_bytes);
+
+/* Generate every binned kernel and its FFT into the persistent buffer (Alg. 1, Alg. 2).
+ * Must precede sb_forward; needed again only after a re-bind. */
+sb_status sb_prepare(sb_plan *plan, void *stream);
+
+/* Number of float64 values per field of the result (complex outputs count 2 per entry). */
+sb_status sb_zeta_size(const sb_plan *plan, int64_t *doubles_per_field);
+
+/* Index table of the result's leading axis: for the full 4PCF the (l1, l2, l3) of each
+ * L (3 ints per row), for the projected 4PCF the (m1, m2) of each p (2 ints per row),
+ * for the 3PCFs the l or m of each row (1 int per row).  Host memory owned by the plan. */
+sb_status sb_zeta_index(const sb_plan *plan, int32_t *rows, int32_t *cols, const int32_t **table);
+
+/* Number of offsets in each bin (the N_cells in bin of eqn radial_binning) for field
+ * `field`'s grid; counts is a host array of nbins. */
+sb_status sb_bin_counts(const sb_plan *plan, int32_t field, int64_t *counts);
+
+/* Forward pass: delta[f] is a device pointer to field f (input_dtype, C order);
+ * zeta is a device array of batch * doubles_per_field float64, written in field order. */
+sb_status sb_forward(sb_plan *plan, const void *const *delta, double *zeta, void *stream);
+
+/* Adjoint of the full 3PCF (ndim 3, npcf 3): given grad_zeta (device, batch * (lmax+1)
+ * * nbins^2 float64, the gradient of a real loss with respect to Z[l][b1][b2]), write
+ * grad_delta[f] (device, float32, shape of field f) = d loss / d delta.  Recomputes the
+ * coefficients; needs the scratch of sb_plan_workspace. */
+sb_status sb_backward(sb_plan *plan, const void *const *delta, const double *grad_zeta,
+                      float *const *grad_delta, void *stream);
+
+/* Device pointer to the coefficient array of kernel k of the last forward field
+ * (flag SB_FLAG_KEEP_COEFFS): complex float32, field shape; k = lm * nbins + b with
+ * lm = l(l+1)/2 + m (3D, m >= 0) or lm = m (2D). */
+sb_status sb_coeffs(const sb_plan *plan, int32_t k, const void **ptr);
+
+/* Launch-shape autotuner: times the candidate tilings of every FFT pass and
+ * contraction of this plan on `stream` (which it synchronises) and keeps the fastest.
+ * Requires bound workspace and sb_prepare. */
+sb_status sb_autotune(sb_plan *plan, void *stream);
+
+/* Forward pass replayed from a HIP graph captured on first use for these exact
+ * pointers (re-captured when they change).  Same contract as sb_forward. */
+sb_status sb_forward_graph(sb_plan *plan, const void *const *delta, double *zeta, void *stream);
+
+/* Per-launch timing: with enable = 1 every FFT-pass and contraction launch of later
+ * sb_forward / sb_backward calls is bracketed by HIP events recorded on the stream it
+ * runs on; enable = 0 stops it.  Either call clears the records. */
+sb_status sb_profile(sb_plan *plan, int32_t enable);
+
+/* Sum of the recorded launch durations (milliseconds) and launch counts per stage:
+ * stage 0 = FFT passes, 1 = contractions.  Synchronises on the recorded events. */
+sb_status sb_stage_times(sb_plan *plan, double *fft_ms, int32_t *n_fft, double *contract_ms,
+                         int32_t *n_contract);
+
+const char *sb_status_str(sb_status s);
+const char *sb_last_error(void);
+int32_t sb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SARABANDE_HIP_H */

@@ -1,0 +1,250 @@
+"""Python front end: ``Plan`` (one C plan plus its torch-owned device workspace),
+``measure`` (the paper's measure/calc_zeta flow of Sec. 3.3) and ``ZetaFn`` (autograd).
+
+Torch supplies device memory and the stream; every step of the computation runs
+in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import SbProblem, check
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _aligned_buffer(nbytes: int, device) -> torch.Tensor:
+    # torch's caching allocator returns 512-byte aligned blocks; keep a margin anyway
+    t = torch.empty(max(int(nbytes), 1) + 256, dtype=torch.uint8, device=device)
+    return t
+
+
+def _aligned_ptr(t: torch.Tensor) -> int:
+    p = t.data_ptr()
+    return (p + 255) & ~255
+
+
+class Plan:
+    """A plan for a batch of fields (shapes may differ).
+
+    shapes     : list of grid shapes, each of length ndim (3 full, 2 projected)
+    bin_edges  : nbins + 1 increasing radii in cells; bin b = (e_b, e_{b+1}]
+    lmax       : l_max in 3D, m_max in 2D
+    npcf       : 3 or 4
+    precision  : "fp32" or "split_bf16" (contraction arithmetic of the 4PCF paths)
+    input_dtype: torch.float32 or torch.float64 (the density arrays' dtype)
+    """
+
+    def __init__(self, shapes, bin_edges, lmax, npcf=3, precision="fp32", input_dtype=torch.float32,
+                 device=None, stream=None, prepare=True):
+        self.lib = _lib.load()
+        shapes = [tuple(int(x) for x in s) for s in shapes]
+        ndim = len(shapes[0])
+        if any(len(s) != ndim for s in shapes):
+            raise ValueError("all shapes must have the same number of dimensions")
+        self.shapes, self.ndim, self.npcf, self.lmax = shapes, ndim, int(npcf), int(lmax)
+        self.edges = np.ascontiguousarray(np.asarray(bin_edges, dtype=np.float64))
+        self.nbins = len(self.edges) - 1
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.input_dtype = input_dtype
+        prec = {"fp32": _lib.SB_PREC_FP32, "split_bf16": _lib.SB_PREC_SPLIT_BF16}[precision]
+        self.precision = precision
+        self._prob = SbProblem(ndim, self.npcf, self.nbins,
+                               self.edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.lmax, prec,
+                               _lib.SB_IN_F64 if input_dtype == torch.float64 else _lib.SB_IN_F32, 0)
+        sh = np.ascontiguousarray(np.array(shapes, dtype=np.int64).ravel())
+        self._shapes_arr = sh
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(self.lib.sb_plan_create(ctypes.byref(self._prob), len(shapes),
+                                          sh.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(handle)),
+                  "sb_plan_create")
+        self.handle = handle
+        pb, sbytes = ctypes.c_size_t(), ctypes.c_size_t()
+        check(self.lib.sb_plan_workspace(self.handle, ctypes.byref(pb), ctypes.byref(sbytes)), "sb_plan_workspace")
+        self.persistent_bytes, self.scratch_bytes = pb.value, sbytes.value
+        self._persist = _aligned_buffer(pb.value, self.device)
+        self._scratch = _aligned_buffer(sbytes.value, self.device)
+        check(self.lib.sb_plan_bind(self.handle, ctypes.c_void_p(_aligned_ptr(self._persist)), pb.value,
+                                    ctypes.c_void_p(_aligned_ptr(self._scratch)), sbytes.value), "sb_plan_bind")
+        n = ctypes.c_int64()
+        check(self.lib.sb_zeta_size(self.handle, ctypes.byref(n)), "sb_zeta_size")
+        self.zeta_doubles = n.value
+        self.prepared = False
+        if prepare:
+            self.prepare(stream)
+
+    # ------------------------------------------------------------------ lifecycle
+    def close(self):
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize(self.device)
+            self.lib.sb_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def prepare(self, stream=None):
+        with torch.cuda.device(self.device):
+            check(self.lib.sb_prepare(self.handle, _stream_ptr(stream)), "sb_prepare")
+        self.prepared = True
+
+    def autotune(self, stream=None):
+        with torch.cuda.device(self.device):
+            check(self.lib.sb_autotune(self.handle, _stream_ptr(stream)), "sb_autotune")
+
+    # ------------------------------------------------------------------ layout
+    def zeta_index(self):
+        rows, cols = ctypes.c_int32(), ctypes.c_int32()
+        tab = ctypes.POINTER(ctypes.c_int32)()
+        check(self.lib.sb_zeta_index(self.handle, ctypes.byref(rows), ctypes.byref(cols), ctypes.byref(tab)),
+              "sb_zeta_index")
+        arr = np.array([tab[i] for i in range(rows.value * cols.value)], dtype=np.int32)
+        return arr.reshape(rows.value, cols.value)
+
+    def bin_counts(self, field: int = 0):
+        out = np.zeros(self.nbins, dtype=np.int64)
+        check(self.lib.sb_bin_counts(self.handle, int(field), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+              "sb_bin_counts")
+        return out
+
+    def zeta_shape(self):
+        rows = self.zeta_index().shape[0]
+        nb = self.nbins
+        tail = (nb, nb) if self.npcf == 3 else (nb, nb, nb)
+        return (rows,) + tail
+
+    def _check_fields(self, deltas):
+        if len(deltas) != len(self.shapes):
+            raise ValueError(f"expected {len(self.shapes)} fields, got {len(deltas)}")
+        for d, s in zip(deltas, self.shapes):
+            if tuple(d.shape) != s:
+                raise ValueError(f"field shape {tuple(d.shape)} does not match the plan's {s}")
+            if d.device != self.device or not d.is_contiguous() or d.dtype != self.input_dtype:
+                raise ValueError("fields must be contiguous device tensors of the plan's dtype and device")
+
+    def _ptrs(self, tensors):
+        arr = (ctypes.c_void_p * len(tensors))(*[ctypes.c_void_p(t.data_ptr()) for t in tensors])
+        return arr
+
+    # ------------------------------------------------------------------ compute
+    def forward_raw(self, deltas, out=None, stream=None, graph=False):
+        """Raw result buffer: (batch, zeta_doubles) float64 on the device."""
+        self._check_fields(deltas)
+        if out is None:
+            out = torch.empty((len(deltas), self.zeta_doubles), dtype=torch.float64, device=self.device)
+        ptrs = self._ptrs(deltas)
+        fn = self.lib.sb_forward_graph if graph else self.lib.sb_forward
+        with torch.cuda.device(self.device):
+            check(fn(self.handle, ptrs, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)),
+                  "sb_forward_graph" if graph else "sb_forward")
+        return out
+
+    def forward(self, deltas, stream=None, graph=False):
+        """List of fields -> tensor (batch, rows, nb, nb[, nb]); complex for projected outputs."""
+        raw = self.forward_raw(deltas, stream=stream, graph=graph)
+        return self.unpack(raw)
+
+    def unpack(self, raw):
+        b = raw.shape[0]
+        shp = self.zeta_shape()
+        if self.ndim == 2:
+            return torch.view_as_complex(raw.reshape((b,) + shp + (2,)))
+        return raw.reshape((b,) + shp)
+
+    def backward(self, deltas, grad_zeta, stream=None):
+        """d loss / d delta for the full 3PCF given d loss / d Z (batch, lmax+1, nb, nb) float64."""
+        self._check_fields(deltas)
+        gz = grad_zeta.to(device=self.device, dtype=torch.float64).contiguous()
+        grads = [torch.empty(s, dtype=torch.float32, device=self.device) for s in self.shapes]
+        with torch.cuda.device(self.device):
+            check(self.lib.sb_backward(self.handle, self._ptrs(deltas), ctypes.c_void_p(gz.data_ptr()),
+                                       self._ptrs(grads), _stream_ptr(stream)), "sb_backward")
+        return grads
+
+    def coeffs(self, k: int, shape=None):
+        """Coefficient array k (= lm * nbins + b) of the last field, as a complex64 view."""
+        ptr = ctypes.c_void_p()
+        check(self.lib.sb_coeffs(self.handle, int(k), ctypes.byref(ptr)), "sb_coeffs")
+        shape = tuple(shape or self.shapes[-1])
+        n = int(np.prod(shape))
+        off = ptr.value - self._scratch.data_ptr()
+        return self._scratch[off: off + 8 * n].view(torch.complex64).reshape(shape)
+
+    def profile(self, enable: bool):
+        check(self.lib.sb_profile(self.handle, int(bool(enable))), "sb_profile")
+
+    def stage_times(self):
+        f, c = ctypes.c_double(), ctypes.c_double()
+        nf, nc = ctypes.c_int32(), ctypes.c_int32()
+        check(self.lib.sb_stage_times(self.handle, ctypes.byref(f), ctypes.byref(nf), ctypes.byref(c),
+                                      ctypes.byref(nc)), "sb_stage_times")
+        return {"fft_ms": f.value, "fft_launches": nf.value, "contract_ms": c.value, "contract_launches": nc.value}
+
+
+def normalization(plan: Plan, deltas, field: int = 0) -> np.ndarray:
+    """Sec. 2.5: N = N_gal prod_{n=1}^{N-1} nbar V_bin,n with unit cells (box side = grid
+    resolution, as in the paper's validation): V_bin = cells in bin, nbar = N_gal / N_g,
+    N_gal = sum (delta + 1).  Returned with the broadcast shape of the result's bin axes."""
+    d = deltas[field]
+    ng = float(np.prod(plan.shapes[field]))
+    ngal = float(torch.sum(d.to(torch.float64)).item()) + ng
+    nbar = ngal / ng
+    v = plan.bin_counts(field).astype(np.float64)
+    if plan.npcf == 3:
+        return ngal * (nbar * v)[:, None] * (nbar * v)[None, :]
+    return ngal * (nbar * v)[:, None, None] * (nbar * v)[None, :, None] * (nbar * v)[None, None, :]
+
+
+def measure(delta, bin_edges, lmax, projected=False, npcf=3, precision="fp32", normalized=False):
+    """One field: the raw grid sums of Alg. 5-8 (see include/sarabande_hip.h for the layouts).
+
+    delta: a 3D (full) or 2D (projected) torch tensor on a GPU, or a numpy array (copied to
+    the current GPU).  Returns (zeta, index) where index lists l, (l1,l2,l3), m or (m1,m2)
+    of the result's leading axis.  normalized=True divides by the N of Sec. 2.5."""
+    if isinstance(delta, np.ndarray):
+        delta = torch.from_numpy(np.ascontiguousarray(delta)).cuda()
+    if delta.dtype not in (torch.float32, torch.float64):
+        delta = delta.float()
+    delta = delta.contiguous()
+    if (delta.dim() == 2) != bool(projected):
+        raise ValueError("projected=True needs a 2D field, projected=False a 3D field")
+    plan = Plan([tuple(delta.shape)], bin_edges, lmax, npcf=npcf, precision=precision,
+                input_dtype=delta.dtype, device=delta.device)
+    z = plan.forward([delta])[0]
+    idx = plan.zeta_index()
+    if normalized:
+        z = z / torch.as_tensor(normalization(plan, [delta]), device=z.device)
+    torch.cuda.synchronize(delta.device)
+    plan.close()
+    return z, idx
+
+
+class ZetaFn(torch.autograd.Function):
+    """Full 3PCF sums Z[l][b1][b2] of one field with a hand-written adjoint (sb_backward)."""
+
+    @staticmethod
+    def forward(ctx, delta, plan: Plan):
+        if plan.ndim != 3 or plan.npcf != 3:
+            raise ValueError("ZetaFn supports the full 3PCF")
+        d = delta.detach().contiguous()
+        z = plan.forward([d])[0]
+        ctx.plan = plan
+        ctx.save_for_backward(d)
+        return z
+
+    @staticmethod
+    def backward(ctx, gz):
+        (d,) = ctx.saved_tensors
+        g = ctx.plan.backward([d], gz.unsqueeze(0))[0]
+        return g.to(d.dtype), None

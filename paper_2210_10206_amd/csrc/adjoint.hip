@@ -1,0 +1,149 @@
+// Adjoint of the full 3PCF: d loss / d delta for loss = sum g[l][b1][b2] Z[l][b1][b2].
+//
+// With G_l = (g_l + g_l^T) / 2, K^b_lm(r) = conj(Y_lm(r^)) on bin b and w_0 = 1, w_m = 2:
+//   d loss / d delta(y) = D(y) + C(y),
+//   D(y) = sum_{l, m >= 0} w_m sum_b1 Re( a^b1_lm(y) h^b1_lm(y) ),  h^b1 = sum_b2 G_l[b1][b2] conj(a^b2_lm)
+//   C(y) = 2 Re sum_{l, m >= 0, b} w_m (K^b_lm * v^b_lm)(y),        v^b = delta h^b
+// (the ordinary derivative of the trilinear grid sum of Alg. 5 / eq. alm_to_zeta_clean,
+// with the -m terms folded in through a_{l,-m} = (-1)^m conj(a_lm)).  The convolution
+// K * v equals the forward correlation applied to the reflected field read back at -y,
+// so the forward kernel spectra serve unchanged:  U = IFFT( sum_k FFT(w_m v_k(-.)) Khat_k ),
+// C(y) = 2 Re U(-y).
+#include "sb_plan.h"
+
+namespace sb {
+namespace {
+
+__device__ __forceinline__ int64_t flip_index(int64_t cell, int ndim, const int64_t *n) {
+    int64_t idx[3] = {0, 0, 0};
+    int64_t rem = cell;
+    for (int d = ndim - 1; d >= 0; --d) {
+        idx[d] = rem % n[d];
+        rem /= n[d];
+    }
+    int64_t out = 0;
+    for (int d = 0; d < ndim; ++d) out = out * n[d] + ((n[d] - idx[d]) % n[d]);
+    return out;
+}
+
+struct AdjPrepArgs {
+    const float2 *coef;     // NB arrays of one (l, m)
+    const float *w;         // density
+    const double *gz;       // g_l, NB x NB
+    int nbins;
+    float wm;
+    int ndim;
+    int64_t n[3];
+    int64_t ng;
+    float2 *vtmp;           // NB arrays: w_m v^b at the reflected cell
+    float *dsum;            // direct term, accumulated over (l, m)
+    int first;              // write instead of accumulate
+};
+
+__global__ void adj_prep_kernel(AdjPrepArgs a) {
+    const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= a.ng) return;
+    const int NB = a.nbins;
+    float2 av[kMaxBins];
+    for (int b = 0; b < NB; ++b) av[b] = a.coef[(int64_t)b * a.ng + y];
+    const float dy = a.w[y];
+    const int64_t yf = flip_index(y, a.ndim, a.n);
+    float dsum = 0.f;
+    for (int b1 = 0; b1 < NB; ++b1) {
+        float hx = 0.f, hy = 0.f;
+        for (int b2 = 0; b2 < NB; ++b2) {
+            const float G = (float)(0.5 * (a.gz[b1 * NB + b2] + a.gz[b2 * NB + b1]));
+            hx += G * av[b2].x;
+            hy -= G * av[b2].y;   // conj(a)
+        }
+        dsum += a.wm * (av[b1].x * hx - av[b1].y * hy);
+        a.vtmp[(int64_t)b1 * a.ng + yf] = make_float2(a.wm * dy * hx, a.wm * dy * hy);
+    }
+    if (a.first) a.dsum[y] = dsum;
+    else a.dsum[y] += dsum;
+}
+
+__global__ void adj_finish_kernel(const float2 *U, const float *dsum, int ndim, int64_t n0, int64_t n1, int64_t n2,
+                                  int64_t ng, float *out) {
+    const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= ng) return;
+    const int64_t n[3] = {n0, n1, n2};
+    const int64_t yf = flip_index(y, ndim, n);
+    out[y] = dsum[y] + 2.f * U[yf].x;
+}
+
+__global__ void zero_c_kernel(float2 *x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = make_float2(0.f, 0.f);
+}
+
+}  // namespace
+
+sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta, float *const *grad_delta,
+                   hipStream_t s) {
+    if (!p || !delta || !grad_zeta || !grad_delta) return fail(SB_EINVAL, "null argument");
+    if (p->prob.ndim != 3 || p->prob.npcf != 3) return fail(SB_EUNSUPPORTED, "adjoint is implemented for the full 3PCF");
+    if (!p->persist || !p->scratch) return fail(SB_EWORKSPACE, "workspace not bound");
+    if (!p->prepared) return fail(SB_ESTATE, "sb_prepare has not run on the bound workspace");
+    const int NB = p->prob.nbins;
+    float2 *acc = reinterpret_cast<float2 *>(p->scratch + p->off_grad);
+    float2 *vtmp = reinterpret_cast<float2 *>(p->scratch + p->off_vtmp);
+    float *dsum = reinterpret_cast<float *>(p->scratch + p->off_dsum);
+    const float2 *coef = reinterpret_cast<const float2 *>(p->scratch + p->off_coef);
+    const float *w = reinterpret_cast<const float *>(p->scratch + p->off_w);
+    for (int f = 0; f < p->batch; ++f) {
+        if (!delta[f] || !grad_delta[f]) return fail(SB_EINVAL, "null field pointer");
+        const ShapeGroup &G = p->groups[p->field_group[f]];
+        const float2 *khat = reinterpret_cast<const float2 *>(p->persist + G.khat_off);
+        sb_status st = coefficients(p, f, delta[f], s);   // recompute a (never stored across calls)
+        if (st != SB_OK) return st;
+        const int nt = 256;
+        const unsigned nblk = (unsigned)((G.ng + nt - 1) / nt);
+        hipLaunchKernelGGL(zero_c_kernel, dim3(nblk), dim3(nt), 0, s, acc, G.ng);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "adjoint zero");
+        const double *gz_f = grad_zeta + (int64_t)f * p->zeta_doubles;
+        for (int l = 0; l <= p->prob.lmax; ++l)
+            for (int m = 0; m <= l; ++m) {
+                const int lm = l * (l + 1) / 2 + m;
+                AdjPrepArgs a{};
+                a.coef = coef + (int64_t)lm * NB * G.ng;
+                a.w = w;
+                a.gz = gz_f + (int64_t)l * NB * NB;
+                a.nbins = NB;
+                a.wm = m == 0 ? 1.f : 2.f;
+                a.ndim = 3;
+                for (int d = 0; d < 3; ++d) a.n[d] = G.n[d];
+                a.ng = G.ng;
+                a.vtmp = vtmp;
+                a.dsum = dsum;
+                a.first = lm == 0;
+                e = p->timed_launch(STAGE_OTHER, s, [&]() {
+                    hipLaunchKernelGGL(adj_prep_kernel, dim3(nblk), dim3(nt), 0, s, a);
+                    return hipGetLastError();
+                });
+                if (e != hipSuccess) return hip_fail(e, "adjoint prep");
+                for (int b = 0; b < NB; ++b) {
+                    // acc += FFT(w_m v_b(-.)) * Khat_b: in-place passes on v_b, the last one accumulating
+                    float2 *vb = vtmp + (int64_t)b * G.ng;
+                    st = fft_axis_passes(p, G, -1, LOAD_C, vb, 0, nullptr, 0, vb, 0, 1, s, STORE_MACC,
+                                         khat + (int64_t)(lm * NB + b) * G.ng, 0, acc);
+                    if (st != SB_OK) return st;
+                }
+            }
+        st = fft_axis_passes(p, G, +1, LOAD_C, acc, 0, nullptr, 0, acc, 0, 1, s, STORE_C, nullptr, 0, nullptr);
+        if (st != SB_OK) return st;
+        hipLaunchKernelGGL(adj_finish_kernel, dim3(nblk), dim3(nt), 0, s, acc, dsum, 3, G.n[0], G.n[1], G.n[2], G.ng,
+                           grad_delta[f]);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "adjoint finish");
+    }
+    return SB_OK;
+}
+
+}  // namespace sb
+
+extern "C" sb_status sb_backward(sb_plan *p, const void *const *delta, const double *grad_zeta,
+                                 float *const *grad_delta, void *stream) {
+    return sb::backward(p, delta, grad_zeta, grad_delta, static_cast<hipStream_t>(stream));
+}

@@ -1,0 +1,595 @@
+// C ABI of the SARABANDE HIP library: plan creation, workspace layout, kernel
+// generation (Alg. 1 / Alg. 2) and the forward pass (Alg. 3 / Alg. 4 by FFT
+// correlation, then the contractions of Alg. 5 - Alg. 8).
+#include "sarabande_hip.h"
+#include "sb_kgen.h"
+#include "sb_plan.h"
+#include "sb_tables.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+namespace sb {
+
+thread_local std::string g_last_error;
+
+sb_status fail(sb_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+sb_status hip_fail(hipError_t e, const char *what) {
+    return fail(SB_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static bool supported_edge(int64_t n) {
+    return fft_supported((int)n) && n >= 8 && n <= 512;
+}
+
+// ------------------------------------------------------------------ plan creation
+
+static sb_status build_gather(sb_plan *p, std::vector<int> &gptr, std::vector<int> &gidx, std::vector<double> &gcoef) {
+    const int NB = p->prob.nbins;
+    gptr.assign(1, 0);
+    auto add = [&](int src, double c) { gidx.push_back(src); gcoef.push_back(c); };
+    auto close = [&]() { gptr.push_back((int)gidx.size()); };
+    const int NP = NB * (NB + 1) / 2;
+    auto pidx = [&](int b1, int b2) {
+        if (b1 > b2) std::swap(b1, b2);
+        return b1 * NB - b1 * (b1 - 1) / 2 + (b2 - b1);
+    };
+    if (p->prob.ndim == 3 && p->prob.npcf == 3) {
+        for (int l = 0; l <= p->prob.lmax; ++l)
+            for (int b1 = 0; b1 < NB; ++b1)
+                for (int b2 = 0; b2 < NB; ++b2) {
+                    for (int m = 0; m <= l; ++m) add((l * (l + 1) / 2 + m) * NP + pidx(b1, b2), m == 0 ? 1.0 : 2.0);
+                    close();
+                }
+    } else if (p->prob.ndim == 2 && p->prob.npcf == 3) {
+        for (int m = 0; m <= p->prob.lmax; ++m)
+            for (int b1 = 0; b1 < NB; ++b1)
+                for (int b2 = 0; b2 < NB; ++b2) {
+                    add(m * 2 * NP + pidx(b1, b2), 1.0);
+                    close();
+                    if (b1 != b2) add(m * 2 * NP + NP + pidx(b1, b2), b1 < b2 ? 1.0 : -1.0);
+                    close();
+                }
+    } else if (p->prob.ndim == 3 && p->prob.npcf == 4) {
+        const int NV = NB * NB * NB;
+        for (size_t L = 0; L < p->f4.out_lams.size(); ++L) {
+            const int c = p->f4.out_canon[L];
+            const auto &pos = p->f4.out_pos[L];
+            for (int b1 = 0; b1 < NB; ++b1)
+                for (int b2 = 0; b2 < NB; ++b2)
+                    for (int b3 = 0; b3 < NB; ++b3) {
+                        const int b[3] = {b1, b2, b3};
+                        add(c * NV + (b[pos[0]] * NB + b[pos[1]]) * NB + b[pos[2]], 1.0);
+                        close();
+                    }
+        }
+    } else {
+        const int NV2 = 2 * NB * NB * NB;
+        for (const auto &pr : p->p4_pairs) {
+            const int m1 = pr.first, m2 = pr.second;
+            const bool canon = (m1 > 0) || (m1 == 0 && m2 >= 0);
+            const int key = canon ? p->p4_canon_index.at({m1, m2}) : p->p4_canon_index.at({-m1, -m2});
+            for (int f = 0; f < NB * NB * NB; ++f) {
+                add(key * NV2 + 2 * f, 1.0);
+                close();
+                add(key * NV2 + 2 * f + 1, canon ? 1.0 : -1.0);
+                close();
+            }
+        }
+    }
+    return SB_OK;
+}
+
+static void contraction_shape(const sb_plan *p, int64_t ng, int *groups, int *nvals, int *nblocks) {
+    const int NB = p->prob.nbins;
+    if (p->prob.npcf == 3) {
+        *groups = p->nlm;
+        *nvals = NB * (NB + 1) / 2 * (p->prob.ndim == 2 ? 2 : 1);
+        *nblocks = (int)((ng + p->cpb_pair - 1) / p->cpb_pair);
+    } else if (p->prob.ndim == 3) {
+        *groups = (int)p->f4.canon.size();
+        *nvals = NB * NB * NB;
+        *nblocks = (int)((ng + p->cpb_quad - 1) / p->cpb_quad);
+    } else {
+        *groups = (int)p->p4_canon.size();
+        *nvals = 2 * NB * NB * NB;
+        *nblocks = (int)((ng + p->cpb_proj4 - 1) / p->cpb_proj4);
+    }
+}
+
+sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shapes, sb_plan **out) {
+    if (!prob || !shapes || !out) return fail(SB_EINVAL, "null argument");
+    *out = nullptr;
+    if (prob->ndim != 2 && prob->ndim != 3) return fail(SB_EINVAL, "ndim must be 2 or 3");
+    if (prob->npcf != 3 && prob->npcf != 4) return fail(SB_EINVAL, "npcf must be 3 or 4");
+    if (prob->nbins < 1) return fail(SB_EINVAL, "nbins must be >= 1");
+    if (prob->nbins > kMaxBins) return fail(SB_EUNSUPPORTED, "nbins > 16");
+    if (prob->npcf == 4 && prob->nbins > 10) return fail(SB_EUNSUPPORTED, "4PCF supports nbins <= 10");
+    if (!prob->bin_edges) return fail(SB_EINVAL, "bin_edges is null");
+    if (prob->lmax < 0) return fail(SB_EINVAL, "lmax must be >= 0");
+    if (prob->ndim == 3 && prob->lmax > kMaxL) return fail(SB_EINVAL, "lmax > 10");
+    if (prob->ndim == 2 && prob->lmax > kMaxM) return fail(SB_EINVAL, "mmax > 16");
+    if (prob->precision != SB_PREC_FP32 && prob->precision != SB_PREC_SPLIT_BF16)
+        return fail(SB_EINVAL, "unknown precision");
+    if (prob->input_dtype != SB_IN_F32 && prob->input_dtype != SB_IN_F64)
+        return fail(SB_EINVAL, "unknown input dtype");
+    if (batch < 1) return fail(SB_EINVAL, "batch must be >= 1");
+    for (int b = 0; b <= prob->nbins; ++b) {
+        const double e = prob->bin_edges[b];
+        if (!std::isfinite(e) || e < 0.0) return fail(SB_EINVAL, "bin edges must be finite and >= 0");
+        if (b > 0 && !(e > prob->bin_edges[b - 1])) return fail(SB_EINVAL, "bin edges must increase strictly");
+    }
+    sb_plan *p = new (std::nothrow) sb_plan();
+    if (!p) return fail(SB_ENOMEM, "plan allocation");
+    p->prob = *prob;
+    p->edges.assign(prob->bin_edges, prob->bin_edges + prob->nbins + 1);
+    p->prob.bin_edges = p->edges.data();
+    for (int b = 0; b <= prob->nbins; ++b)
+        if (!exact_floor_square(p->edges[b], &p->thr[b])) {
+            delete p;
+            return fail(SB_EUNSUPPORTED, "bin edge too large");
+        }
+    p->batch = batch;
+    p->max_ng = 0;
+    for (int f = 0; f < batch; ++f) {
+        std::array<int64_t, 3> sh = {1, 1, 1};
+        int64_t ng = 1;
+        for (int d = 0; d < prob->ndim; ++d) {
+            sh[d] = shapes[(int64_t)f * prob->ndim + d];
+            if (sh[d] < 1) { delete p; return fail(SB_EINVAL, "grid extents must be positive"); }
+            if (!supported_edge(sh[d])) {
+                delete p;
+                return fail(SB_EUNSUPPORTED, "grid edge " + std::to_string(sh[d]) +
+                                                 " not in {8,12,16,24,32,48,64,96,128,160,192,256,512}");
+            }
+            ng *= sh[d];
+        }
+        p->shapes.push_back(sh);
+        int gid = -1;
+        for (size_t g = 0; g < p->groups.size(); ++g)
+            if (p->groups[g].n[0] == sh[0] && p->groups[g].n[1] == sh[1] && p->groups[g].n[2] == sh[2]) gid = (int)g;
+        if (gid < 0) {
+            ShapeGroup G;
+            G.n[0] = sh[0]; G.n[1] = sh[1]; G.n[2] = sh[2];
+            G.ng = ng;
+            p->groups.push_back(G);
+            gid = (int)p->groups.size() - 1;
+        }
+        p->groups[gid].fields.push_back(f);
+        p->field_group.push_back(gid);
+        p->max_ng = std::max(p->max_ng, ng);
+    }
+    const int NB = prob->nbins;
+    p->nlm = prob->ndim == 3 ? (prob->lmax + 1) * (prob->lmax + 2) / 2 : prob->lmax + 1;
+    p->nk = p->nlm * NB;
+    // bin counts per group (host enumeration of the same integer test as the kernels)
+    for (auto &G : p->groups) {
+        for (int b = 0; b < NB; ++b) G.counts[b] = 0;
+        int64_t lim[3];
+        for (int d = 0; d < 3; ++d) lim[d] = d < prob->ndim ? G.n[d] : 1;
+        const int64_t rmax = (int64_t)std::floor(p->edges[NB]) + 1;
+        for (int64_t i = 0; i < lim[0]; ++i) {
+            const int64_t ci = (2 * i < lim[0]) ? i : i - lim[0];
+            if (std::llabs(ci) > rmax) continue;
+            for (int64_t j = 0; j < lim[1]; ++j) {
+                const int64_t cj = prob->ndim >= 2 ? ((2 * j < lim[1]) ? j : j - lim[1]) : 0;
+                if (std::llabs(cj) > rmax) continue;
+                for (int64_t k = 0; k < lim[2]; ++k) {
+                    const int64_t ck = prob->ndim == 3 ? ((2 * k < lim[2]) ? k : k - lim[2]) : 0;
+                    const int64_t s = ci * ci + cj * cj + ck * ck;
+                    if (s == 0) continue;
+                    for (int b = 0; b < NB; ++b)
+                        if (p->thr[b] < s && s <= p->thr[b + 1]) { G.counts[b]++; break; }
+                }
+            }
+        }
+    }
+    // result layout
+    const int L = prob->lmax;
+    if (prob->npcf == 3) {
+        p->zeta_doubles = (int64_t)(L + 1) * NB * NB * (prob->ndim == 2 ? 2 : 1);
+        p->idx_rows = L + 1;
+        p->idx_cols = 1;
+        for (int l = 0; l <= L; ++l) p->idx_table.push_back(l);
+    } else if (prob->ndim == 3) {
+        p->f4 = make_full4_plan(L, NB);
+        p->zeta_doubles = (int64_t)p->f4.out_lams.size() * NB * NB * NB;
+        p->idx_rows = (int32_t)p->f4.out_lams.size();
+        p->idx_cols = 3;
+        for (const Lam &x : p->f4.out_lams)
+            for (int k = 0; k < 3; ++k) p->idx_table.push_back(x.l[k]);
+    } else {
+        p->p4_pairs = proj4_pairs(L);
+        for (const auto &pr : p->p4_pairs)
+            if (pr.first > 0 || (pr.first == 0 && pr.second >= 0)) {
+                p->p4_canon_index[pr] = (int)p->p4_canon.size();
+                p->p4_canon.push_back(pr);
+            }
+        p->zeta_doubles = (int64_t)p->p4_pairs.size() * NB * NB * NB * 2;
+        p->idx_rows = (int32_t)p->p4_pairs.size();
+        p->idx_cols = 2;
+        for (const auto &pr : p->p4_pairs) { p->idx_table.push_back(pr.first); p->idx_table.push_back(pr.second); }
+    }
+    // ---- device tables: twiddles per distinct length, 4PCF terms, gather map
+    std::vector<int> lens;
+    for (const auto &G : p->groups)
+        for (int d = 0; d < prob->ndim; ++d)
+            if (std::find(lens.begin(), lens.end(), (int)G.n[d]) == lens.end()) lens.push_back((int)G.n[d]);
+    std::vector<char> host;
+    auto put = [&](const void *src, size_t bytes) {
+        const size_t off = align256(host.size());
+        host.resize(off + bytes);
+        if (bytes) std::memcpy(host.data() + off, src, bytes);
+        return off;
+    };
+    std::map<int, size_t> tw_off;
+    for (int n : lens) {
+        std::vector<float2> tw(n);
+        for (int j = 0; j < n; ++j) {
+            const double ang = -2.0 * M_PI * (double)j / (double)n;
+            tw[j] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+        }
+        tw_off[n] = put(tw.data(), tw.size() * sizeof(float2));
+    }
+    size_t off_terms = 0, off_tptr = 0, off_laml = 0, off_stage = 0, off_pairs = 0;
+    if (prob->npcf == 4 && prob->ndim == 3) {
+        std::vector<QuadTerm> terms;
+        std::vector<int> tptr(1, 0), laml, stage;
+        p->max_cols = 0;
+        for (size_t c = 0; c < p->f4.canon.size(); ++c) {
+            const Lam &C = p->f4.canon[c];
+            for (const auto &t : p->f4.terms[c]) {
+                QuadTerm q;
+                q.ma = (int8_t)t.ma; q.mb = (int8_t)t.mb; q.mc = (int8_t)t.mc; q.pad = 0;
+                q.c = (float)t.c;
+                terms.push_back(q);
+            }
+            tptr.push_back((int)terms.size());
+            for (int k = 0; k < 3; ++k) laml.push_back(C.l[k]);
+            // staged columns: distinct l values in the order la, lb, lc; column = offset + m
+            std::vector<int> st(kStageStride, 0);
+            int ncol = 0;
+            int offs[3];
+            for (int q = 0; q < 3; ++q) {
+                int prev = -1;
+                for (int r = 0; r < q; ++r)
+                    if (C.l[r] == C.l[q]) prev = r;
+                if (prev >= 0) { offs[q] = offs[prev]; continue; }
+                offs[q] = ncol;
+                for (int m = 0; m <= C.l[q]; ++m) st[4 + ncol + m] = C.l[q] * (C.l[q] + 1) / 2 + m;
+                ncol += C.l[q] + 1;
+            }
+            st[0] = offs[0]; st[1] = offs[1]; st[2] = offs[2]; st[3] = ncol;
+            p->max_cols = std::max(p->max_cols, ncol);
+            stage.insert(stage.end(), st.begin(), st.end());
+        }
+        off_terms = put(terms.data(), terms.size() * sizeof(QuadTerm));
+        off_tptr = put(tptr.data(), tptr.size() * sizeof(int));
+        off_laml = put(laml.data(), laml.size() * sizeof(int));
+        off_stage = put(stage.data(), stage.size() * sizeof(int));
+    }
+    if (prob->npcf == 4 && prob->ndim == 2) {
+        std::vector<int> pr;
+        for (const auto &x : p->p4_canon) { pr.push_back(x.first); pr.push_back(x.second); }
+        off_pairs = put(pr.data(), pr.size() * sizeof(int));
+    }
+    std::vector<int> gptr, gidx;
+    std::vector<double> gcoef;
+    build_gather(p, gptr, gidx, gcoef);
+    p->gather_nout = (int)gptr.size() - 1;
+    const size_t off_gptr = put(gptr.data(), gptr.size() * sizeof(int));
+    const size_t off_gidx = put(gidx.data(), gidx.size() * sizeof(int));
+    const size_t off_gcoef = put(gcoef.data(), gcoef.size() * sizeof(double));
+    hipError_t e = hipMalloc(&p->dtab, align256(host.size()) + 256);
+    if (e != hipSuccess) { delete p; return hip_fail(e, "hipMalloc(tables)"); }
+    e = hipMemcpy(p->dtab, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { (void)hipFree(p->dtab); delete p; return hip_fail(e, "hipMemcpy(tables)"); }
+    char *base = static_cast<char *>(p->dtab);
+    for (auto &kv : tw_off) p->tw[kv.first] = reinterpret_cast<const float2 *>(base + kv.second);
+    if (prob->npcf == 4 && prob->ndim == 3) {
+        p->d_terms = reinterpret_cast<const QuadTerm *>(base + off_terms);
+        p->d_term_ptr = reinterpret_cast<const int *>(base + off_tptr);
+        p->d_lam_l = reinterpret_cast<const int *>(base + off_laml);
+        p->d_stage = reinterpret_cast<const int *>(base + off_stage);
+    }
+    if (prob->npcf == 4 && prob->ndim == 2) p->d_pairs = reinterpret_cast<const int *>(base + off_pairs);
+    p->d_gptr = reinterpret_cast<const int *>(base + off_gptr);
+    p->d_gidx = reinterpret_cast<const int *>(base + off_gidx);
+    p->d_gcoef = reinterpret_cast<const double *>(base + off_gcoef);
+    // ---- workspace layout
+    size_t pers = 0;
+    for (auto &G : p->groups) {
+        G.khat_off = pers;
+        pers += align256((size_t)p->nk * G.ng * sizeof(float2));
+    }
+    p->persist_need = pers;
+    size_t sc = 0;
+    p->off_w = sc; sc += align256((size_t)p->max_ng * sizeof(float));
+    p->off_dhat = sc; sc += align256((size_t)p->max_ng * sizeof(float2));
+    p->off_coef = sc; sc += align256((size_t)p->nk * p->max_ng * sizeof(float2));
+    int groups = 0, nvals = 0, nblocks = 0;
+    contraction_shape(p, p->max_ng, &groups, &nvals, &nblocks);
+    p->off_part = sc; sc += align256((size_t)groups * nvals * nblocks * sizeof(double));
+    p->off_tot = sc; sc += align256((size_t)groups * nvals * sizeof(double));
+    p->off_grad = sc; sc += align256((size_t)p->max_ng * sizeof(float2));
+    if (prob->ndim == 3 && prob->npcf == 3) {
+        p->off_vtmp = sc; sc += align256((size_t)NB * p->max_ng * sizeof(float2));
+        p->off_dsum = sc; sc += align256((size_t)p->max_ng * sizeof(float));
+    }
+    p->scratch_need = sc;
+    *out = p;
+    return SB_OK;
+}
+
+// ------------------------------------------------------------------ passes
+
+sb_status fft_axis_passes(sb_plan *p, const ShapeGroup &G, int sign, int first_load, const void *in, int64_t in_bs,
+                          const float2 *in2, int64_t in2_bs, float2 *out, int64_t out_bs, int batch,
+                          hipStream_t s, int store, const float2 *mul, int64_t mul_bs, float2 *final_out) {
+    const int nd = p->prob.ndim;
+    for (int d = 0; d < nd; ++d) {
+        FftPass a{};
+        a.n = (int)G.n[d];
+        int64_t stride = 1;
+        for (int k = d + 1; k < nd; ++k) stride *= G.n[k];
+        a.stride = stride;
+        a.ng = G.ng;
+        a.sign = sign;
+        a.batch = batch;
+        a.tw = p->tw.at(a.n);
+        a.variant = p->fft_variant(a.n, d);
+        a.out = out;
+        a.out_bs = out_bs;
+        if (d == 0) {
+            a.load = first_load;
+            a.in = in;
+            a.in_bs = in_bs;
+            a.in2 = in2;
+            a.in2_bs = in2_bs;
+        } else {
+            a.load = LOAD_C;
+            a.in = out;
+            a.in_bs = out_bs;
+        }
+        a.store = (d == nd - 1) ? store : STORE_C;
+        a.mul = mul;
+        a.mul_bs = mul_bs;
+        if (d == nd - 1 && final_out) a.out = final_out;
+        const hipError_t e = p->timed_launch(STAGE_FFT, s, [&]() { return launch_fft_pass(a, s); });
+        if (e != hipSuccess) return hip_fail(e, "fft pass");
+    }
+    return SB_OK;
+}
+
+sb_status prepare(sb_plan *p, hipStream_t s) {
+    if (!p->persist || !p->scratch) return fail(SB_EWORKSPACE, "workspace not bound");
+    for (auto &G : p->groups) {
+        float2 *khat = reinterpret_cast<float2 *>(p->persist + G.khat_off);
+        KgenArgs a{};
+        a.ndim = p->prob.ndim;
+        for (int d = 0; d < 3; ++d) a.n[d] = G.n[d];
+        a.ng = G.ng;
+        a.nbins = p->prob.nbins;
+        for (int b = 0; b <= p->prob.nbins; ++b) a.thr[b] = p->thr[b];
+        a.lmax = p->prob.lmax;
+        a.nlm = p->nlm;
+        if (p->prob.ndim == 3)
+            for (int l = 0; l <= p->prob.lmax; ++l)
+                for (int m = 0; m <= l; ++m) a.norm[l * (l + 1) / 2 + m] = ylm_norm(l, m);
+        a.scale = (float)(1.0 / (double)G.ng);
+        a.out = khat;
+        hipError_t e = launch_kgen(a, s);
+        if (e != hipSuccess) return hip_fail(e, "kernel generation");
+        const sb_status st = fft_axis_passes(p, G, -1, LOAD_C, khat, G.ng, nullptr, 0, khat, G.ng, p->nk, s,
+                                             STORE_C, nullptr, 0, nullptr);
+        if (st != SB_OK) return st;
+    }
+    p->prepared = true;
+    return SB_OK;
+}
+
+// Coefficients of every kernel for one field into scratch (Alg. 3 / Alg. 4 as a correlation).
+sb_status coefficients(sb_plan *p, int f, const void *delta, hipStream_t s) {
+    const ShapeGroup &G = p->groups[p->field_group[f]];
+    float *w = reinterpret_cast<float *>(p->scratch + p->off_w);
+    float2 *dhat = reinterpret_cast<float2 *>(p->scratch + p->off_dhat);
+    float2 *coef = reinterpret_cast<float2 *>(p->scratch + p->off_coef);
+    const float2 *khat = reinterpret_cast<const float2 *>(p->persist + G.khat_off);
+    hipError_t e = launch_to_f32(delta, p->prob.input_dtype, G.ng, w, s);
+    if (e != hipSuccess) return hip_fail(e, "density ingest");
+    sb_status st = fft_axis_passes(p, G, -1, LOAD_R32, w, 0, nullptr, 0, dhat, 0, 1, s, STORE_C, nullptr, 0, nullptr);
+    if (st != SB_OK) return st;
+    st = fft_axis_passes(p, G, +1, LOAD_MUL, dhat, 0, khat, G.ng, coef, G.ng, p->nk, s, STORE_C, nullptr, 0,
+                         nullptr);
+    if (st != SB_OK) return st;
+    p->last_ng = G.ng;
+    return SB_OK;
+}
+
+sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
+    const ShapeGroup &G = p->groups[p->field_group[f]];
+    const float *w = reinterpret_cast<const float *>(p->scratch + p->off_w);
+    const float2 *coef = reinterpret_cast<const float2 *>(p->scratch + p->off_coef);
+    double *part = reinterpret_cast<double *>(p->scratch + p->off_part);
+    double *tot = reinterpret_cast<double *>(p->scratch + p->off_tot);
+    int groups = 0, nvals = 0, nblocks = 0;
+    contraction_shape(p, G.ng, &groups, &nvals, &nblocks);
+    hipError_t e = hipSuccess;
+    const int NB = p->prob.nbins;
+    if (p->prob.npcf == 3) {
+        PairArgs a{};
+        a.coef = coef;
+        a.gstride = (int64_t)NB * G.ng;
+        a.w = w;
+        a.ng = G.ng;
+        a.nbins = NB;
+        a.ngroups = groups;
+        a.cells_per_block = p->cpb_pair;
+        a.want_imag = p->prob.ndim == 2;
+        a.partial = part;
+        a.nblocks = nblocks;
+        e = p->timed_launch(STAGE_CONTRACT, s, [&]() { return launch_pair_contract(a, s); });
+    } else if (p->prob.ndim == 3) {
+        QuadArgs a{};
+        a.coef = coef;
+        a.w = w;
+        a.ng = G.ng;
+        a.nbins = NB;
+        a.nlam = groups;
+        a.lam_l = p->d_lam_l;
+        a.term_ptr = p->d_term_ptr;
+        a.terms = p->d_terms;
+        a.stage = p->d_stage;
+        a.max_cols = p->max_cols;
+        a.cells_per_block = p->cpb_quad;
+        a.tile = p->quad_tile;
+        a.nlm = p->nlm;
+        a.partial = part;
+        a.nblocks = nblocks;
+        e = p->timed_launch(STAGE_CONTRACT, s, [&]() { return launch_quad_contract(a, s); });
+    } else {
+        Proj4Args a{};
+        a.coef = coef;
+        a.w = w;
+        a.ng = G.ng;
+        a.nbins = NB;
+        a.npairs = groups;
+        a.pairs = p->d_pairs;
+        a.mmax = p->prob.lmax;
+        a.cells_per_block = p->cpb_proj4;
+        a.tile = p->proj4_tile;
+        a.partial = part;
+        a.nblocks = nblocks;
+        e = p->timed_launch(STAGE_CONTRACT, s, [&]() { return launch_proj4_contract(a, s); });
+    }
+    if (e != hipSuccess) return hip_fail(e, "contraction");
+    e = launch_block_sum(part, groups, nblocks, nvals, tot, s);
+    if (e != hipSuccess) return hip_fail(e, "block sum");
+    e = launch_gather(tot, p->d_gptr, p->d_gidx, p->d_gcoef, p->gather_nout, zeta_f, s);
+    if (e != hipSuccess) return hip_fail(e, "gather");
+    return SB_OK;
+}
+
+sb_status forward(sb_plan *p, const void *const *delta, double *zeta, hipStream_t s) {
+    if (!p) return fail(SB_EINVAL, "null plan");
+    if (!delta || !zeta) return fail(SB_EINVAL, "null pointer");
+    if (!p->persist || !p->scratch) return fail(SB_EWORKSPACE, "workspace not bound");
+    if (!p->prepared) return fail(SB_ESTATE, "sb_prepare has not run on the bound workspace");
+    for (int f = 0; f < p->batch; ++f) {
+        if (!delta[f]) return fail(SB_EINVAL, "null field pointer");
+        sb_status st = coefficients(p, f, delta[f], s);
+        if (st != SB_OK) return st;
+        st = contract(p, f, zeta + (int64_t)f * p->zeta_doubles, s);
+        if (st != SB_OK) return st;
+    }
+    return SB_OK;
+}
+
+}  // namespace sb
+
+// ====================================================================== C ABI
+using namespace sb;
+
+extern "C" {
+
+sb_status sb_plan_create(const sb_problem *prob, int32_t batch, const int64_t *shapes, sb_plan **out) {
+    return plan_create(prob, batch, shapes, out);
+}
+
+void sb_plan_destroy(sb_plan *plan) {
+    if (!plan) return;
+    plan->release_graph();
+    plan->release_timing();
+    if (plan->dtab) (void)hipFree(plan->dtab);
+    delete plan;
+}
+
+sb_status sb_plan_workspace(const sb_plan *p, size_t *persistent_bytes, size_t *scratch_bytes) {
+    if (!p || !persistent_bytes || !scratch_bytes) return fail(SB_EINVAL, "null argument");
+    *persistent_bytes = p->persist_need;
+    *scratch_bytes = p->scratch_need;
+    return SB_OK;
+}
+
+sb_status sb_plan_bind(sb_plan *p, void *persistent, size_t persistent_bytes, void *scratch, size_t scratch_bytes) {
+    if (!p) return fail(SB_EINVAL, "null plan");
+    if (!persistent || !scratch) return fail(SB_EINVAL, "null workspace");
+    if (persistent_bytes < p->persist_need || scratch_bytes < p->scratch_need)
+        return fail(SB_EWORKSPACE, "workspace smaller than sb_plan_workspace requires");
+    if ((reinterpret_cast<uintptr_t>(persistent) & 255) || (reinterpret_cast<uintptr_t>(scratch) & 255))
+        return fail(SB_EINVAL, "workspace must be 256-byte aligned");
+    p->persist = static_cast<char *>(persistent);
+    p->scratch = static_cast<char *>(scratch);
+    p->prepared = false;
+    p->release_graph();
+    return SB_OK;
+}
+
+sb_status sb_prepare(sb_plan *p, void *stream) {
+    if (!p) return fail(SB_EINVAL, "null plan");
+    return prepare(p, static_cast<hipStream_t>(stream));
+}
+
+sb_status sb_zeta_size(const sb_plan *p, int64_t *doubles_per_field) {
+    if (!p || !doubles_per_field) return fail(SB_EINVAL, "null argument");
+    *doubles_per_field = p->zeta_doubles;
+    return SB_OK;
+}
+
+sb_status sb_zeta_index(const sb_plan *p, int32_t *rows, int32_t *cols, const int32_t **table) {
+    if (!p || !rows || !cols || !table) return fail(SB_EINVAL, "null argument");
+    *rows = p->idx_rows;
+    *cols = p->idx_cols;
+    *table = p->idx_table.data();
+    return SB_OK;
+}
+
+sb_status sb_bin_counts(const sb_plan *p, int32_t field, int64_t *counts) {
+    if (!p || !counts) return fail(SB_EINVAL, "null argument");
+    if (field < 0 || field >= p->batch) return fail(SB_EINVAL, "field index out of range");
+    const ShapeGroup &G = p->groups[p->field_group[field]];
+    for (int b = 0; b < p->prob.nbins; ++b) counts[b] = G.counts[b];
+    return SB_OK;
+}
+
+sb_status sb_forward(sb_plan *p, const void *const *delta, double *zeta, void *stream) {
+    return forward(p, delta, zeta, static_cast<hipStream_t>(stream));
+}
+
+sb_status sb_coeffs(const sb_plan *p, int32_t k, const void **ptr) {
+    if (!p || !ptr) return fail(SB_EINVAL, "null argument");
+    if (k < 0 || k >= p->nk) return fail(SB_EINVAL, "kernel index out of range");
+    if (!p->scratch) return fail(SB_EWORKSPACE, "workspace not bound");
+    *ptr = p->scratch + p->off_coef + (size_t)k * p->last_ng * sizeof(float2);
+    return SB_OK;
+}
+
+const char *sb_status_str(sb_status s) {
+    switch (s) {
+        case SB_OK: return "ok";
+        case SB_EINVAL: return "invalid argument";
+        case SB_EUNSUPPORTED: return "unsupported";
+        case SB_EWORKSPACE: return "workspace missing or too small";
+        case SB_EHIP: return "HIP runtime error";
+        case SB_ENOMEM: return "out of host memory";
+        case SB_ESTATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+const char *sb_last_error(void) { return g_last_error.c_str(); }
+
+int32_t sb_version(void) { return 1; }
+
+}  // extern "C"

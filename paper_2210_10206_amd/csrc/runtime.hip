@@ -1,0 +1,137 @@
+// Runtime services of the plan: per-launch timing, the launch-shape autotuner and
+// HIP-graph replay of the forward pass.
+#include "sb_plan.h"
+
+#include <algorithm>
+#include <vector>
+
+using namespace sb;
+
+extern "C" {
+
+sb_status sb_profile(sb_plan *p, int32_t enable) {
+    if (!p) return fail(SB_EINVAL, "null plan");
+    p->release_timing();
+    p->timing = enable != 0;
+    return SB_OK;
+}
+
+sb_status sb_stage_times(sb_plan *p, double *fft_ms, int32_t *n_fft, double *contract_ms, int32_t *n_contract) {
+    if (!p || !fft_ms || !n_fft || !contract_ms || !n_contract) return fail(SB_EINVAL, "null argument");
+    double ms[STAGE_COUNT] = {0, 0, 0};
+    int cnt[STAGE_COUNT] = {0, 0, 0};
+    for (auto &t : p->timed) {
+        hipError_t e = hipEventSynchronize(t.b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        float x = 0.f;
+        e = hipEventElapsedTime(&x, t.a, t.b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        ms[t.stage] += x;
+        cnt[t.stage] += 1;
+    }
+    *fft_ms = ms[STAGE_FFT];
+    *n_fft = cnt[STAGE_FFT];
+    *contract_ms = ms[STAGE_CONTRACT];
+    *n_contract = cnt[STAGE_CONTRACT];
+    return SB_OK;
+}
+
+// Times every FFT variant of every (length, axis) of the plan's shapes on the
+// coefficient scratch (a full-batch inverse pass, as in the forward) and keeps the
+// fastest.  Contraction block sizes are chosen among a few candidates the same way.
+sb_status sb_autotune(sb_plan *p, void *stream) {
+    if (!p) return fail(SB_EINVAL, "null plan");
+    if (!p->persist || !p->scratch) return fail(SB_EWORKSPACE, "workspace not bound");
+    if (!p->prepared) return fail(SB_ESTATE, "sb_prepare has not run");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return fail(SB_EHIP, "event create");
+    float2 *coef = reinterpret_cast<float2 *>(p->scratch + p->off_coef);
+    const bool was_timing = p->timing;
+    p->timing = false;
+    for (const auto &G : p->groups) {
+        for (int d = 0; d < p->prob.ndim; ++d) {
+            const int n = (int)G.n[d];
+            const int nv = fft_num_variants(n);
+            if (nv <= 1) continue;
+            int64_t stride = 1;
+            for (int k = d + 1; k < p->prob.ndim; ++k) stride *= G.n[k];
+            float best = 1e30f;
+            int bestv = 0;
+            for (int v = 0; v < nv; ++v) {
+                FftPass ps{};
+                ps.n = n;
+                ps.stride = stride;
+                ps.ng = G.ng;
+                ps.sign = 1;
+                ps.load = LOAD_C;
+                ps.store = STORE_C;
+                ps.in = coef;
+                ps.out = coef;
+                ps.in_bs = ps.out_bs = G.ng;
+                ps.batch = p->nk;
+                ps.tw = p->tw.at(n);
+                ps.variant = v;
+                float tot = 0.f;
+                for (int rep = 0; rep < 3; ++rep) {
+                    (void)hipEventRecord(a, s);
+                    hipError_t e = launch_fft_pass(ps, s);
+                    (void)hipEventRecord(b, s);
+                    if (e != hipSuccess) {
+                        (void)hipEventDestroy(a);
+                        (void)hipEventDestroy(b);
+                        return hip_fail(e, "autotune fft");
+                    }
+                    (void)hipEventSynchronize(b);
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, a, b);
+                    if (rep > 0) tot += ms;
+                }
+                if (tot < best) { best = tot; bestv = v; }
+            }
+            p->fft_var[{n, d}] = bestv;
+        }
+    }
+    p->timing = was_timing;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    p->release_graph();
+    return SB_OK;
+}
+
+sb_status sb_forward_graph(sb_plan *p, const void *const *delta, double *zeta, void *stream) {
+    if (!p || !delta || !zeta) return fail(SB_EINVAL, "null argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!s) return fail(SB_EINVAL, "graph replay needs a non-default stream");
+    if (p->timing) return fail(SB_ESTATE, "disable per-launch timing before graph replay");
+    bool same = p->graph_exec && p->graph_zeta == zeta && p->graph_stream == s &&
+                (int)p->graph_delta.size() == p->batch;
+    for (int f = 0; same && f < p->batch; ++f) same = p->graph_delta[f] == delta[f];
+    if (!same) {
+        p->release_graph();
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        const sb_status st = forward(p, delta, zeta, s);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(s, &g);
+        if (st != SB_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        p->graph = g;
+        p->graph_delta.assign(delta, delta + p->batch);
+        p->graph_zeta = zeta;
+        p->graph_stream = s;
+    }
+    const hipError_t e = hipGraphLaunch(p->graph_exec, s);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return SB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,56 @@
+// Shared device helpers and launch descriptors of the SARABANDE HIP library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+namespace sb {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// ---------------------------------------------------------------- FFT passes
+// One pass = 1D transforms of length n along one axis of a C-ordered array of
+// `ng` complex cells.  The axis has element stride `stride` (product of the later
+// extents); the pencils are g = 0 .. ng/n - 1 with base (g / stride) * n * stride + g % stride.
+enum FftLoad : int {
+    LOAD_C = 0,        // complex float2 from in
+    LOAD_MUL = 1,      // in[idx] * in2[idx]           (spectral product)
+    LOAD_R32 = 2,      // real float  from in (imaginary part 0)
+    LOAD_R64 = 3       // real double from in
+};
+enum FftStore : int {
+    STORE_C = 0,       // out[idx] = value
+    STORE_MACC = 1     // out[idx] += value * mul[idx]   (spectral multiply-accumulate)
+};
+
+struct FftPass {
+    int n;             // transform length
+    int64_t stride;    // element stride of the axis
+    int64_t ng;        // cells per array
+    int sign;          // -1 forward, +1 inverse (unnormalised)
+    int load;          // FftLoad
+    int store;         // FftStore
+    const void *in;    // input (batch stride in_bs elements)
+    const float2 *in2; // multiplier for LOAD_MUL (batch stride in2_bs)
+    float2 *out;       // output (batch stride out_bs)
+    const float2 *mul; // multiplier for STORE_MACC (batch stride mul_bs)
+    int64_t in_bs, in2_bs, out_bs, mul_bs;
+    int batch;         // arrays transformed in one launch (grid.y)
+    const float2 *tw;  // n roots of unity exp(-2 pi i j / n), float32 from float64
+    int variant;       // launch-shape variant (autotuned)
+};
+
+// Launch one FFT pass; returns hipSuccess or the launch error.  `ok` reports whether a
+// kernel exists for (n, variant).
+hipError_t launch_fft_pass(const FftPass &p, hipStream_t s);
+bool fft_supported(int n);
+int fft_num_variants(int n);
+
+}  // namespace sb

@@ -1,0 +1,98 @@
+// Launch descriptors of the kernel-generation, contraction and reduction passes.
+#pragma once
+
+#include "sb_common.h"
+
+namespace sb {
+
+constexpr int kMaxBins = 16;
+constexpr int kMaxL = 10;                                   // 3D lmax
+constexpr int kMaxM = 16;                                   // 2D mmax
+constexpr int kMaxLM = (kMaxL + 1) * (kMaxL + 2) / 2;       // (l, m >= 0) pairs at lmax 10
+
+struct KgenArgs {
+    int ndim;
+    int64_t n[3];
+    int64_t ng;
+    int nbins;
+    int64_t thr[kMaxBins + 1];   // floor(e_b^2), exact
+    int lmax;                    // 3D lmax or 2D mmax
+    int nlm;                     // kernels per bin: (lmax+1)(lmax+2)/2 in 3D, mmax+1 in 2D
+    double norm[kMaxLM];         // N_lm = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!), index l(l+1)/2 + m
+    float scale;                 // 1 / N_g
+    float2 *out;                 // nlm * nbins arrays of ng cells, array k = lm * nbins + b
+};
+hipError_t launch_kgen(const KgenArgs &a, hipStream_t s);
+
+// ---- two-coefficient contraction (3PCF): block partials of
+//      sum_x w(x) A^b1(x) conj(A^b2(x)) for b1 <= b2 and every coefficient group g.
+struct PairArgs {
+    const float2 *coef;   // [group][bin][ng] (group stride gstride, bin stride ng)
+    int64_t gstride;
+    const float *w;       // per-cell weight (the density), ng
+    int64_t ng;
+    int nbins;
+    int ngroups;
+    int cells_per_block;
+    int want_imag;        // also accumulate the imaginary part (projected 3PCF)
+    double *partial;      // [group][block][npairs * (want_imag ? 2 : 1)]
+    int nblocks;
+};
+hipError_t launch_pair_contract(const PairArgs &a, hipStream_t s);
+
+// ---- three-coefficient contraction (full 4PCF, canonical Lambda list):
+//      block partials of Re sum_x w sum_terms C a^{B1}_{la,ma} a^{B2}_{lb,mb} a^{B3}_{lc,mc}
+struct QuadTerm {             // one (m3 >= 0, m1) term of a canonical Lambda
+    int8_t ma, mb, mc;        // signed orders of the three coefficients (mc >= 0)
+    int8_t pad;
+    float c;                  // 3j value times the m3 >= 0 weight (1 or 2)
+};
+constexpr int kStageStride = 4 + 3 * (kMaxL + 1);
+struct QuadArgs {
+    const float2 *coef;       // [lm][bin][ng], lm = l(l+1)/2 + m, m >= 0
+    const float *w;
+    int64_t ng;
+    int nbins;
+    int nlam;                 // canonical Lambdas
+    const int *lam_l;         // 3 per canonical Lambda: (la, lb, lc)
+    const int *term_ptr;      // nlam + 1
+    const QuadTerm *terms;
+    const int *stage;         // per Lambda, kStageStride ints: LDS column of (la,0), (lb,0), (lc,0),
+                              // column count, then the global lm index of each column
+    int max_cols;             // largest column count over the Lambdas
+    int cells_per_block;
+    int tile;                 // cells staged in LDS per step
+    int nlm;
+    double *partial;          // [lam][block][nbins^3]
+    int nblocks;
+};
+hipError_t launch_quad_contract(const QuadArgs &a, hipStream_t s);
+
+// ---- projected 4PCF: block partials of sum_x w c^{b1}_{m1} c^{b2}_{m2} c^{b3}_{m3} (complex)
+struct Proj4Args {
+    const float2 *coef;       // [m][bin][ng], m >= 0
+    const float *w;
+    int64_t ng;
+    int nbins;
+    int npairs;               // canonical (m1, m2) pairs
+    const int *pairs;         // 2 per pair
+    int mmax;
+    int cells_per_block;
+    int tile;
+    double *partial;          // [pair][block][nbins^3 * 2]
+    int nblocks;
+};
+hipError_t launch_proj4_contract(const Proj4Args &a, hipStream_t s);
+
+// ---- deterministic FP64 reduction of block partials: tot[g][v] = sum_blk partial[g][blk][v]
+hipError_t launch_block_sum(const double *partial, int ngroups, int nblocks, int nvals, double *tot,
+                            hipStream_t s);
+
+// ---- gather map: out[i] = sum_{t in ptr[i]..ptr[i+1]} coef[t] * src[idx[t]]
+hipError_t launch_gather(const double *src, const int *ptr, const int *idx, const double *coef,
+                         int nout, double *out, hipStream_t s);
+
+// ---- density ingest: float32 copy of the field (and float64 -> float32 cast)
+hipError_t launch_to_f32(const void *in, int dtype, int64_t n, float *out, hipStream_t s);
+
+}  // namespace sb

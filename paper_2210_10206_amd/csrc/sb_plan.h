@@ -1,0 +1,120 @@
+// Plan object behind the C ABI.
+#pragma once
+
+#include "sarabande_hip.h"
+#include "sb_kgen.h"
+#include "sb_tables.h"
+
+#include <array>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+namespace sb {
+
+enum Stage : int { STAGE_FFT = 0, STAGE_CONTRACT = 1, STAGE_OTHER = 2, STAGE_COUNT = 3 };
+
+struct ShapeGroup {
+    int64_t n[3] = {1, 1, 1};
+    int64_t ng = 0;
+    std::vector<int> fields;
+    size_t khat_off = 0;          // byte offset of this shape's kernel spectra in the persistent buffer
+    int64_t counts[kMaxBins] = {};
+};
+
+struct TimedLaunch {
+    int stage;
+    hipEvent_t a, b;
+};
+
+}  // namespace sb
+
+struct sb_plan {
+    sb_problem prob{};
+    std::vector<double> edges;
+    int64_t thr[sb::kMaxBins + 1] = {};
+    int batch = 0;
+    std::vector<std::array<int64_t, 3>> shapes;
+    std::vector<int> field_group;
+    std::vector<sb::ShapeGroup> groups;
+    int nlm = 0, nk = 0;
+    int64_t max_ng = 0;
+    int64_t last_ng = 0;
+    // result layout
+    int64_t zeta_doubles = 0;
+    int32_t idx_rows = 0, idx_cols = 0;
+    std::vector<int32_t> idx_table;
+    sb::Full4Plan f4;
+    std::vector<std::pair<int, int>> p4_pairs, p4_canon;
+    std::map<std::pair<int, int>, int> p4_canon_index;
+    // device tables (owned)
+    void *dtab = nullptr;
+    std::map<int, const float2 *> tw;
+    const sb::QuadTerm *d_terms = nullptr;
+    const int *d_term_ptr = nullptr, *d_lam_l = nullptr, *d_stage = nullptr, *d_pairs = nullptr;
+    const int *d_gptr = nullptr, *d_gidx = nullptr;
+    const double *d_gcoef = nullptr;
+    int gather_nout = 0;
+    int max_cols = 0;
+    // workspace (caller-owned)
+    char *persist = nullptr, *scratch = nullptr;
+    size_t persist_need = 0, scratch_need = 0;
+    size_t off_w = 0, off_dhat = 0, off_coef = 0, off_part = 0, off_tot = 0, off_grad = 0;
+    size_t off_vtmp = 0, off_dsum = 0;
+    bool prepared = false;
+    // launch shapes (autotuned)
+    int cpb_pair = 8192, cpb_quad = 1024, cpb_proj4 = 4096;
+    int quad_tile = 32, proj4_tile = 64;
+    std::map<std::pair<int, int>, int> fft_var;   // (length, axis) -> variant
+    int fft_variant(int n, int axis) const {
+        auto it = fft_var.find({n, axis});
+        return it == fft_var.end() ? 0 : it->second;
+    }
+    // per-launch timing
+    bool timing = false;
+    std::vector<sb::TimedLaunch> timed;
+    template <class F>
+    hipError_t timed_launch(int stage, hipStream_t s, F &&fn) {
+        if (!timing) return fn();
+        sb::TimedLaunch t{stage, nullptr, nullptr};
+        if (hipEventCreate(&t.a) != hipSuccess || hipEventCreate(&t.b) != hipSuccess) return fn();
+        (void)hipEventRecord(t.a, s);
+        const hipError_t e = fn();
+        (void)hipEventRecord(t.b, s);
+        timed.push_back(t);
+        return e;
+    }
+    void release_timing() {
+        for (auto &t : timed) {
+            (void)hipEventDestroy(t.a);
+            (void)hipEventDestroy(t.b);
+        }
+        timed.clear();
+    }
+    // graph replay cache
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<const void *> graph_delta;
+    double *graph_zeta = nullptr;
+    hipStream_t graph_stream = nullptr;
+    void release_graph() {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        graph_exec = nullptr;
+        graph = nullptr;
+        graph_delta.clear();
+        graph_zeta = nullptr;
+    }
+};
+
+namespace sb {
+sb_status fail(sb_status s, const std::string &msg);
+sb_status hip_fail(hipError_t e, const char *what);
+sb_status forward(sb_plan *p, const void *const *delta, double *zeta, hipStream_t s);
+sb_status coefficients(sb_plan *p, int f, const void *delta, hipStream_t s);
+sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s);
+sb_status fft_axis_passes(sb_plan *p, const ShapeGroup &G, int sign, int first_load, const void *in, int64_t in_bs,
+                          const float2 *in2, int64_t in2_bs, float2 *out, int64_t out_bs, int batch,
+                          hipStream_t s, int store, const float2 *mul, int64_t mul_bs, float2 *final_out);
+}  // namespace sb

@@ -1,0 +1,205 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerance (floating point): err = max |Z_gpu - Z_oracle| / max |Z_oracle| <= 1e-5 for the
+float32 path (the bound the design targets), reported per block too.  Integer work (bin
+counts) is compared exactly.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from fieldgen import lognormal_field, linear_edges  # noqa: E402
+
+TOL32 = 1e-5
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_err(got, ref):
+    return float(np.max(np.abs(np.asarray(got) - np.asarray(ref))) / np.max(np.abs(ref)))
+
+
+@pytest.fixture(scope="module")
+def sb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2210_10206_amd as pkg
+    pkg.load()  # fails loudly when the HIP library is missing
+    from paper_2210_10206_amd import api
+    return api
+
+
+def run_plan(api, fields, edges, lmax, npcf=3, dtype=torch.float32, graph=False, precision="fp32"):
+    shapes = [f.shape for f in fields]
+    plan = api.Plan(shapes, edges, lmax, npcf=npcf, input_dtype=dtype, precision=precision)
+    dev = [torch.from_numpy(np.ascontiguousarray(f)).to(device="cuda", dtype=dtype) for f in fields]
+    if graph:
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            z = plan.forward(dev, stream=s, graph=True)
+        s.synchronize()
+    else:
+        z = plan.forward(dev)
+    torch.cuda.synchronize()
+    return plan, dev, z.cpu().numpy()
+
+
+# ------------------------------------------------------------------ 32^3 full 3PCF (float64 input)
+
+def test_c1_full3pcf_32(sb):
+    say("case: 32^3 float64 lognormal seed 0, 4 bins to 8, lmax 4, full 3PCF")
+    d = lognormal_field((32, 32, 32), seed=0, sigma=1.0, dtype=np.float64)
+    edges = linear_edges(8, 4)
+    plan, dev, z = run_plan(sb, [d], edges, 4, dtype=torch.float64)
+    ref = oracle.zeta3_full(d, edges, 4)
+    assert np.max(np.abs(ref.imag)) < 1e-9 * np.max(np.abs(ref.real))
+    err = rel_err(z[0], ref.real)
+    per_l = [rel_err(z[0][l], ref.real[l]) * np.max(np.abs(ref.real)) / np.max(np.abs(ref.real[l])) for l in range(5)]
+    say(f"  err={err:.3e}  per-l={['%.2e' % e for e in per_l]}")
+    assert err < TOL32
+    assert list(plan.bin_counts(0)) == list(oracle.bin_counts((32, 32, 32), edges))
+    plan.close()
+
+
+def test_c1_coefficients_match_oracle(sb):
+    say("case: 32^3 coefficients a^b_lm at sampled cells")
+    d = lognormal_field((32, 32, 32), seed=0, sigma=1.0, dtype=np.float64)
+    edges = linear_edges(8, 4)
+    plan, dev, z = run_plan(sb, [d], edges, 4, dtype=torch.float64)
+    rng = np.random.Generator(np.random.PCG64(7))
+    cells = rng.choice(d.size, 64, replace=False)
+    ref = oracle.coeffs_full(d, edges, 4, cells=cells)   # (ncell, nb, (lmax+1)^2)
+    worst = 0.0
+    for l in range(5):
+        for m in range(l + 1):
+            lm = l * (l + 1) // 2 + m
+            for b in range(4):
+                a = plan.coeffs(lm * 4 + b).reshape(-1).cpu().numpy()[cells]
+                r = ref[:, b, l * l + m + l]
+                scale = np.max(np.abs(ref[:, b, :]))
+                worst = max(worst, float(np.max(np.abs(a - r)) / scale))
+    say(f"  coefficient err (rel. to max |a| per bin) = {worst:.3e}")
+    assert worst < 2e-6
+    plan.close()
+
+
+def test_ragged_noncubic_grid_with_ties(sb):
+    say("case: (12, 16, 24) normal field, edges (0, 1.5, 2, 3.2, 5), lmax 3")
+    rng = np.random.Generator(np.random.PCG64(11))
+    d = rng.standard_normal((12, 16, 24)).astype(np.float32)
+    edges = np.array([0.0, 1.5, 2.0, 3.2, 5.0])
+    plan, dev, z = run_plan(sb, [d], edges, 3)
+    ref = oracle.zeta3_full(d.astype(np.float64), edges, 3)
+    err = rel_err(z[0], ref.real)
+    say(f"  err={err:.3e}")
+    assert err < TOL32
+    assert list(plan.bin_counts(0)) == list(oracle.bin_counts(d.shape, edges))
+    plan.close()
+
+
+def test_box_truncated_kernel_24(sb):
+    say("case: 24^3, 8 bins to 16 (kernel reaches the box edge), lmax 4")
+    d = lognormal_field((24, 24, 24), seed=3, sigma=1.0)
+    edges = linear_edges(16, 8)
+    plan, dev, z = run_plan(sb, [d], edges, 4)
+    ref = oracle.zeta3_full(d.astype(np.float64), edges, 4)
+    err = rel_err(z[0], ref.real)
+    say(f"  err={err:.3e}")
+    assert err < TOL32
+    plan.close()
+
+
+def test_uneven_batch(sb):
+    say("case: uneven batch 16^3, 24^3, 32^3, 8 bins to 6, lmax 4")
+    fields = [lognormal_field((n, n, n), seed=i, sigma=1.0) for i, n in enumerate((16, 24, 32))]
+    edges = linear_edges(6, 8)
+    plan, dev, z = run_plan(sb, fields, edges, 4)
+    for i, f in enumerate(fields):
+        ref = oracle.zeta3_full(f.astype(np.float64), edges, 4)
+        err = rel_err(z[i], ref.real)
+        say(f"  field {i} {f.shape}: err={err:.3e}")
+        assert err < TOL32
+    plan.close()
+
+
+def test_graph_replay_matches_eager(sb):
+    say("case: 32^3 graph capture + replay vs eager")
+    d = lognormal_field((32, 32, 32), seed=5, sigma=1.0)
+    edges = linear_edges(8, 4)
+    plan = sb.Plan([d.shape], edges, 4)
+    dev = [torch.from_numpy(d).cuda()]
+    eager = plan.forward(dev).cpu().numpy()
+    s = torch.cuda.Stream()
+    out = torch.empty((1, plan.zeta_doubles), dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        with torch.cuda.stream(s):
+            plan.forward_raw(dev, out=out, stream=s, graph=True)
+        s.synchronize()
+        got = out.cpu().numpy().reshape(eager.shape)
+        assert np.array_equal(got, eager), f"replay {rep} differs"
+        _ = plan.forward(dev)  # eager work between replays
+        torch.cuda.synchronize()
+    plan.close()
+
+
+# ------------------------------------------------------------------ projected
+
+def test_projected_small(sb):
+    say("case: 64x96 projected 3PCF + 4PCF, 5 bins to 10, mmax 4")
+    d = lognormal_field((64, 96), seed=2, sigma=1.0)
+    edges = linear_edges(10, 5)
+    _, _, z3 = run_plan(sb, [d], edges, 4, npcf=3)
+    ref3 = oracle.zeta3_proj(d.astype(np.float64), edges, 4)
+    e3 = rel_err(z3[0], ref3)
+    _, _, z4 = run_plan(sb, [d], edges, 4, npcf=4)
+    pairs, ref4 = oracle.zeta4_proj(d.astype(np.float64), edges, 4)
+    e4 = rel_err(z4[0], ref4)
+    say(f"  proj3 err={e3:.3e} proj4 err={e4:.3e}")
+    assert e3 < TOL32 and e4 < TOL32
+
+
+# ------------------------------------------------------------------ full 4PCF
+
+def test_full4pcf_small(sb):
+    say("case: 24^3 full 4PCF, 4 bins to 6, lmax 4")
+    d = lognormal_field((24, 24, 24), seed=4, sigma=1.0)
+    edges = linear_edges(6, 4)
+    plan, dev, z = run_plan(sb, [d], edges, 4, npcf=4)
+    lams, ref = oracle.zeta4_full(d.astype(np.float64), edges, 4)
+    assert [tuple(x) for x in plan.zeta_index()] == lams
+    err = rel_err(z[0], ref.real)
+    say(f"  err={err:.3e}")
+    assert err < TOL32
+    plan.close()
+
+
+# ------------------------------------------------------------------ adjoint
+
+def test_adjoint_matches_oracle_gradient(sb):
+    say("case: 16^3 adjoint of the full 3PCF, 4 bins to 4, lmax 3")
+    d = lognormal_field((16, 16, 16), seed=9, sigma=1.0)
+    edges = linear_edges(4, 4)
+    rng = np.random.Generator(np.random.PCG64(3))
+    G = rng.standard_normal((4, 4, 4))
+    plan = sb.Plan([d.shape], edges, 3)
+    dev = torch.from_numpy(d).cuda().requires_grad_(True)
+    z = sb.ZetaFn.apply(dev, plan)
+    loss = (z * torch.from_numpy(G).cuda()).sum()
+    loss.backward()
+    g = dev.grad.cpu().numpy().astype(np.float64)
+    ref = oracle.grad3_full(d.astype(np.float64), edges, 3, G)
+    err = rel_err(g, ref)
+    say(f"  grad err={err:.3e}")
+    assert err < 1e-5
+    plan.close()
