@@ -251,7 +251,7 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
             const Lam &C = p->f4.canon[c];
             for (const auto &t : p->f4.terms[c]) {
                 QuadTerm q;
-                q.ma = (int8_t)t.ma; q.mb = (int8_t)t.mb; q.mc = (int8_t)t.mc; q.pad = 0;
+                q.ma = t.ma; q.mb = t.mb; q.mc = t.mc;
                 q.c = (float)t.c;
                 terms.push_back(q);
             }

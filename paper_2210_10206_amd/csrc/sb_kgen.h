@@ -43,8 +43,9 @@ hipError_t launch_pair_contract(const PairArgs &a, hipStream_t s);
 // ---- three-coefficient contraction (full 4PCF, canonical Lambda list):
 //      block partials of Re sum_x w sum_terms C a^{B1}_{la,ma} a^{B2}_{lb,mb} a^{B3}_{lc,mc}
 struct QuadTerm {             // one (m3 >= 0, m1) term of a canonical Lambda
-    int8_t ma, mb, mc;        // signed orders of the three coefficients (mc >= 0)
-    int8_t pad;
+    // All fields are 32-bit: terms are read with scalar loads, which need every field
+    // dword aligned (byte-sized fields let the compiler form a base address that is not).
+    int32_t ma, mb, mc;       // signed orders of the three coefficients (mc >= 0)
     float c;                  // 3j value times the m3 >= 0 weight (1 or 2)
 };
 constexpr int kStageStride = 4 + 3 * (kMaxL + 1);
