@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Throughput of the SARABANDE hot path on one MI355X.
+
+Default workload: the full 3PCF of two 256^3 float32 lognormal fields (sigma 0.5
+and 1.5, P(k) ~ k^-11/3), 10 linear bins over (0, 32] cells, l_max = 6.  One step =
+one forward pass over that batch: density FFT, correlation of all 280 binned Y_lm
+kernels by FFT, 3PCF contraction and the float64 grid sum.  The kernel spectra are
+generated once (the cold set-up, reported separately) and stay resident in HBM.
+
+Prints one JSON line (metric, value in fields/s, roofline of the dominant kernel,
+the CPU oracle's throughput on a bounded sample of the same workload).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "3PCF/4PCF fields/sec at 256^3 & 128^3 vs plain FP32 GPU at stated err; %HBM/MFMA peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def source_hash(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel_key, src_files):
+    """HBM bytes per launch measured with rocprofv3 counters (committed under profiles/),
+    or None when the kernel source changed after the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    e = t.get(kernel_key)
+    if not e or e.get("source_hash") != source_hash(src_files):
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(field, edges, lmax, target_s=10.0):
+    import numpy as np
+    import oracle
+    d = field.astype(np.float64)
+    ng = d.size
+    probe = 1024
+    t0 = time.perf_counter()
+    oracle.zeta3_full(d, edges, lmax, cells=np.arange(probe))
+    dt = time.perf_counter() - t0
+    n = int(min(ng, max(probe, probe * target_s / max(dt, 1e-6))))
+    n = max(probe, (n // 256) * 256)
+    t0 = time.perf_counter()
+    oracle.zeta3_full(d, edges, lmax, cells=np.arange(n))
+    dt = time.perf_counter() - t0
+    return {"value": (n / ng) / dt, "unit": "fields/s", "cores": int(oracle.max_threads()), "kind": "oracle",
+            "sample": f"full-3PCF oracle (direct FP64 correlation + contraction) over the first {n} of the "
+                      f"{ng} cells of field 0, {dt:.1f} s wall; value scaled to whole fields"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--grid", type=int, default=256)
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="replay the forward from a HIP graph")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from fieldgen import lognormal_field, linear_edges
+    from paper_2210_10206_amd import api
+
+    n = args.grid
+    nbins, rmax, lmax = 10, 32.0, 6
+    edges = linear_edges(rmax, nbins)
+    print(f"bench: generating 2 lognormal {n}^3 fields", file=sys.stderr, flush=True)
+    fields = [lognormal_field((n, n, n), seed=0, sigma=0.5), lognormal_field((n, n, n), seed=1, sigma=1.5)]
+    dev = [torch.from_numpy(f).cuda() for f in fields]
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    plan = api.Plan([f.shape for f in fields], edges, lmax, npcf=3, prepare=False)
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        plan.prepare(stream)
+    stream.synchronize()
+    cold_ms = (time.perf_counter() - t0) * 1e3
+    if args.autotune:
+        plan.autotune(stream)
+    out = torch.empty((len(dev), plan.zeta_doubles), dtype=torch.float64, device="cuda")
+    print("bench: warmup", file=sys.stderr, flush=True)
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            plan.forward_raw(dev, out=out, stream=stream, graph=args.graph)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    print("bench: timed steps", file=sys.stderr, flush=True)
+    if not args.graph:
+        plan.profile(True)
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(args.steps):
+            plan.forward_raw(dev, out=out, stream=stream, graph=args.graph)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    recs = plan.launch_records() if not args.graph else []
+    plan.profile(False)
+    value = len(dev) * args.steps / elapsed
+
+    # parity of this very run against the stored oracle values (when present)
+    z = out.cpu().numpy().reshape(len(dev), lmax + 1, nbins, nbins)
+    errs = []
+    for i in range(len(dev)):
+        g = os.path.join(ROOT, "tests", "golden", f"c3_full3_256_seed{i}.npz")
+        if n == 256 and os.path.exists(g):
+            ref = np.load(g)["zeta3"].real
+            errs.append(float(np.max(np.abs(z[i] - ref)) / np.max(np.abs(ref))))
+
+    # roofline of the dominant kernel: the batched inverse FFT pass (all kernels at once)
+    nk = (lmax + 1) * (lmax + 2) // 2 * nbins
+    dom = [r for r in recs if r["stage"] == 0 and r["fft_sign"] == 1 and r["batch"] == nk]
+    roof = None
+    if dom:
+        tot_b = sum(r["bytes"] for r in dom)
+        tot_ms = sum(r["ms"] for r in dom)
+        achieved = tot_b / (tot_ms * 1e-3) / 1e9
+        src = ["paper_2210_10206_amd/csrc/fft.hip", "paper_2210_10206_amd/csrc/sb_common.h"]
+        traffic = traffic_for("fft_pass_n256_inverse_batched", src)
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "fft_pass_kernel<256,...,+1> (inverse pass over all 280 kernel arrays)",
+                "launches": len(dom), "avg_launch_ms": round(tot_ms / len(dom), 4),
+                "algorithmic_bytes_per_launch": tot_b / len(dom)}
+    stages = {}
+    for r in recs:
+        k = {0: "fft", 1: "contract", 2: "other"}[r["stage"]]
+        stages.setdefault(k, [0.0, 0])
+        stages[k][0] += r["ms"]
+        stages[k][1] += 1
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(fields[0], edges, lmax)
+    line = {
+        "metric": METRIC, "value": round(value, 4), "unit": "fields/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"full 3PCF, 2 lognormal {n}^3 float32 fields (sigma 0.5, 1.5), 10 bins over (0,32], "
+                               f"lmax 6, kernel spectra resident", "grid": n, "nbins": nbins, "lmax": lmax,
+                   "batch": len(dev), "graph": bool(args.graph)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "cold_setup_ms": round(cold_ms, 1),
+        "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
+        "max_rel_err_vs_oracle": errs or None,
+    }
+    print(json.dumps(line), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -152,6 +152,24 @@ sb_status sb_profile(sb_plan *plan, int32_t enable);
 sb_status sb_stage_times(sb_plan *plan, double *fft_ms, int32_t *n_fft, double *contract_ms,
                          int32_t *n_contract);
 
+/* One recorded launch.  `bytes` is the algorithmic HBM traffic of the launch (every array
+ * it must read or write once: 16 B per complex cell per transformed array for an FFT
+ * pass, plus 8 B per cell and array for a fused spectral product); `flops` the
+ * algorithmic floating-point work of a contraction. */
+typedef struct {
+    int32_t stage;       /* 0 FFT pass, 1 contraction, 2 other */
+    int32_t fft_n;       /* transform length (FFT passes) */
+    int32_t fft_sign;    /* -1 forward, +1 inverse */
+    int32_t batch;       /* arrays in the launch */
+    double bytes;
+    double flops;
+    double ms;           /* event-measured duration */
+} sb_launch_record;
+
+/* Copy up to `max` recorded launches (oldest first) into `out`; `count` receives the
+ * number of records available.  Synchronises on the recorded events. */
+sb_status sb_profile_read(sb_plan *plan, int32_t max, int32_t *count, sb_launch_record *out);
+
 const char *sb_status_str(sb_status s);
 const char *sb_last_error(void);
 int32_t sb_version(void);

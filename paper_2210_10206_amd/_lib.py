@@ -22,6 +22,11 @@ class SbProblem(ctypes.Structure):
                 ("input_dtype", c_i32), ("flags", c_u32)]
 
 
+class SbLaunchRecord(ctypes.Structure):
+    _fields_ = [("stage", c_i32), ("fft_n", c_i32), ("fft_sign", c_i32), ("batch", c_i32),
+                ("bytes", c_dbl), ("flops", c_dbl), ("ms", c_dbl)]
+
+
 P = ctypes.POINTER
 SIGNATURES = {
     "sb_plan_create": (c_i32, [P(SbProblem), c_i32, P(c_i64), P(c_vp)]),
@@ -39,6 +44,7 @@ SIGNATURES = {
     "sb_forward_graph": (c_i32, [c_vp, P(c_vp), c_vp, c_vp]),
     "sb_profile": (c_i32, [c_vp, c_i32]),
     "sb_stage_times": (c_i32, [c_vp, P(c_dbl), P(c_i32), P(c_dbl), P(c_i32)]),
+    "sb_profile_read": (c_i32, [c_vp, c_i32, P(c_i32), P(SbLaunchRecord)]),
     "sb_status_str": (ctypes.c_char_p, [c_i32]),
     "sb_last_error": (ctypes.c_char_p, []),
     "sb_version": (c_i32, []),

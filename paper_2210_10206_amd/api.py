@@ -184,6 +184,16 @@ class Plan:
     def profile(self, enable: bool):
         check(self.lib.sb_profile(self.handle, int(bool(enable))), "sb_profile")
 
+    def launch_records(self):
+        """Per-launch records of the profiled calls: list of dicts (stage, fft_n, fft_sign,
+        batch, bytes, flops, ms)."""
+        n = ctypes.c_int32()
+        check(self.lib.sb_profile_read(self.handle, 0, ctypes.byref(n), None), "sb_profile_read")
+        arr = (_lib.SbLaunchRecord * max(n.value, 1))()
+        check(self.lib.sb_profile_read(self.handle, n.value, ctypes.byref(n), arr), "sb_profile_read")
+        keys = ["stage", "fft_n", "fft_sign", "batch", "bytes", "flops", "ms"]
+        return [{k: getattr(arr[i], k) for k in keys} for i in range(n.value)]
+
     def stage_times(self):
         f, c = ctypes.c_double(), ctypes.c_double()
         nf, nc = ctypes.c_int32(), ctypes.c_int32()

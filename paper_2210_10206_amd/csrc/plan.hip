@@ -366,7 +366,13 @@ sb_status fft_axis_passes(sb_plan *p, const ShapeGroup &G, int sign, int first_l
         a.mul = mul;
         a.mul_bs = mul_bs;
         if (d == nd - 1 && final_out) a.out = final_out;
-        const hipError_t e = p->timed_launch(STAGE_FFT, s, [&]() { return launch_fft_pass(a, s); });
+        // algorithmic traffic: read + write of every transformed array, plus the spectral
+        // product's second operand (one array per batch item) and its shared first operand
+        double bytes = 16.0 * (double)G.ng * batch;
+        if (a.load == LOAD_MUL) bytes += 8.0 * (double)G.ng * batch + 8.0 * (double)G.ng;
+        if (a.store == STORE_MACC) bytes += 16.0 * (double)G.ng * batch;
+        const hipError_t e = p->timed_launch(STAGE_FFT, s, [&]() { return launch_fft_pass(a, s); }, a.n, sign,
+                                             batch, bytes);
         if (e != hipSuccess) return hip_fail(e, "fft pass");
     }
     return SB_OK;
@@ -439,7 +445,10 @@ sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
         a.want_imag = p->prob.ndim == 2;
         a.partial = part;
         a.nblocks = nblocks;
-        e = p->timed_launch(STAGE_CONTRACT, s, [&]() { return launch_pair_contract(a, s); });
+        const double np_ = NB * (NB + 1) / 2.0;
+        const double fl = (double)G.ng * groups * (2.0 + np_ * (a.want_imag ? 8.0 : 4.0));
+        const double by = (double)G.ng * (8.0 * p->nk + 4.0);
+        e = p->timed_launch(STAGE_CONTRACT, s, [&]() { return launch_pair_contract(a, s); }, 0, 0, groups, by, fl);
     } else if (p->prob.ndim == 3) {
         QuadArgs a{};
         a.coef = coef;
@@ -457,7 +466,14 @@ sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
         a.nlm = p->nlm;
         a.partial = part;
         a.nblocks = nblocks;
-        e = p->timed_launch(STAGE_CONTRACT, s, [&]() { return launch_quad_contract(a, s); });
+        double fl = 0.0;
+        for (size_t c = 0; c < p->f4.canon.size(); ++c) {
+            const double nt = (double)p->f4.terms[c].size();
+            fl += (double)NB * NB * (nt * 8.0 + (p->f4.canon[c].l[2] + 1) * (2.0 + 4.0 * NB));
+        }
+        fl *= (double)G.ng;
+        const double by = (double)G.ng * (8.0 * p->nk + 4.0);
+        e = p->timed_launch(STAGE_CONTRACT, s, [&]() { return launch_quad_contract(a, s); }, 0, 0, groups, by, fl);
     } else {
         Proj4Args a{};
         a.coef = coef;
@@ -471,7 +487,9 @@ sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
         a.tile = p->proj4_tile;
         a.partial = part;
         a.nblocks = nblocks;
-        e = p->timed_launch(STAGE_CONTRACT, s, [&]() { return launch_proj4_contract(a, s); });
+        const double fl = (double)G.ng * groups * NB * NB * (8.0 + 8.0 * NB);
+        const double by = (double)G.ng * (8.0 * p->nk + 4.0);
+        e = p->timed_launch(STAGE_CONTRACT, s, [&]() { return launch_proj4_contract(a, s); }, 0, 0, groups, by, fl);
     }
     if (e != hipSuccess) return hip_fail(e, "contraction");
     e = launch_block_sum(part, groups, nblocks, nvals, tot, s);

@@ -16,6 +16,27 @@ sb_status sb_profile(sb_plan *p, int32_t enable) {
     return SB_OK;
 }
 
+sb_status sb_profile_read(sb_plan *p, int32_t max, int32_t *count, sb_launch_record *out) {
+    if (!p || !count || (max > 0 && !out)) return fail(SB_EINVAL, "null argument");
+    *count = (int32_t)p->timed.size();
+    for (int32_t i = 0; i < max && i < (int32_t)p->timed.size(); ++i) {
+        const auto &t = p->timed[i];
+        hipError_t e = hipEventSynchronize(t.b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        float x = 0.f;
+        e = hipEventElapsedTime(&x, t.a, t.b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        out[i].stage = t.stage;
+        out[i].fft_n = t.fft_n;
+        out[i].fft_sign = t.fft_sign;
+        out[i].batch = t.batch;
+        out[i].bytes = t.bytes;
+        out[i].flops = t.flops;
+        out[i].ms = x;
+    }
+    return SB_OK;
+}
+
 sb_status sb_stage_times(sb_plan *p, double *fft_ms, int32_t *n_fft, double *contract_ms, int32_t *n_contract) {
     if (!p || !fft_ms || !n_fft || !contract_ms || !n_contract) return fail(SB_EINVAL, "null argument");
     double ms[STAGE_COUNT] = {0, 0, 0};

@@ -25,6 +25,8 @@ struct ShapeGroup {
 
 struct TimedLaunch {
     int stage;
+    int fft_n, fft_sign, batch;
+    double bytes, flops;
     hipEvent_t a, b;
 };
 
@@ -75,9 +77,10 @@ struct sb_plan {
     bool timing = false;
     std::vector<sb::TimedLaunch> timed;
     template <class F>
-    hipError_t timed_launch(int stage, hipStream_t s, F &&fn) {
+    hipError_t timed_launch(int stage, hipStream_t s, F &&fn, int fft_n = 0, int fft_sign = 0, int batch = 0,
+                            double bytes = 0.0, double flops = 0.0) {
         if (!timing) return fn();
-        sb::TimedLaunch t{stage, nullptr, nullptr};
+        sb::TimedLaunch t{stage, fft_n, fft_sign, batch, bytes, flops, nullptr, nullptr};
         if (hipEventCreate(&t.a) != hipSuccess || hipEventCreate(&t.b) != hipSuccess) return fn();
         (void)hipEventRecord(t.a, s);
         const hipError_t e = fn();
