@@ -68,7 +68,10 @@ typedef enum { SB_IN_F32 = 0, SB_IN_F64 = 1 } sb_input_dtype;
 
 /* Flags */
 enum {
-    SB_FLAG_KEEP_COEFFS = 1u  /* keep every a / c array of the last field in scratch (sb_coeffs) */
+    SB_FLAG_KEEP_COEFFS = 1u, /* keep every a / c array of the last field in scratch (sb_coeffs) */
+    SB_FLAG_UNFUSED = 2u      /* 3PCFs: write every coefficient array, then contract in a separate
+                                 pass (the plain path; the default fuses the contraction into the
+                                 last FFT pass and never writes the coefficients) */
 };
 
 /* Problem statement: the grid, bins, lmax, full or projected, 3 or 4 PCF
@@ -158,6 +161,9 @@ sb_status sb_stage_times(sb_plan *plan, double *fft_ms, int32_t *n_fft, double *
  * algorithmic floating-point work of a contraction. */
 typedef struct {
     int32_t stage;       /* 0 FFT pass, 1 contraction, 2 other */
+    int32_t kernel;      /* 0 FFT pass, 1 axis-0 correlation pass, 2 fused last pass + contraction,
+                            3 pair contraction, 4 full-4PCF contraction, 5 projected-4PCF contraction,
+                            6 adjoint preparation */
     int32_t fft_n;       /* transform length (FFT passes) */
     int32_t fft_sign;    /* -1 forward, +1 inverse */
     int32_t batch;       /* arrays in the launch */

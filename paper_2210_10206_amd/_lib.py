@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(_HERE, "libsarabande_hip.so")
 SB_OK, SB_EINVAL, SB_EUNSUPPORTED, SB_EWORKSPACE, SB_EHIP, SB_ENOMEM, SB_ESTATE = 0, -1, -2, -3, -4, -5, -6
 SB_PREC_FP32, SB_PREC_SPLIT_BF16 = 0, 1
 SB_IN_F32, SB_IN_F64 = 0, 1
+SB_FLAG_KEEP_COEFFS, SB_FLAG_UNFUSED = 1, 2
 
 # Every function the header declares, with its ctypes signature.
 c_i32, c_i64, c_u32, c_dbl, c_vp, c_sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double,
@@ -23,7 +24,7 @@ class SbProblem(ctypes.Structure):
 
 
 class SbLaunchRecord(ctypes.Structure):
-    _fields_ = [("stage", c_i32), ("fft_n", c_i32), ("fft_sign", c_i32), ("batch", c_i32),
+    _fields_ = [("stage", c_i32), ("kernel", c_i32), ("fft_n", c_i32), ("fft_sign", c_i32), ("batch", c_i32),
                 ("bytes", c_dbl), ("flops", c_dbl), ("ms", c_dbl)]
 
 

@@ -35,6 +35,8 @@ class Plan:
     """A plan for a batch of fields (shapes may differ).
 
     shapes     : list of grid shapes, each of length ndim (3 full, 2 projected)
+    keep_coeffs: keep the coefficient arrays of the last field readable through coeffs()
+    fused      : 3PCFs: contract inside the last FFT pass (False = the plain unfused path)
     bin_edges  : nbins + 1 increasing radii in cells; bin b = (e_b, e_{b+1}]
     lmax       : l_max in 3D, m_max in 2D
     npcf       : 3 or 4
@@ -43,7 +45,7 @@ class Plan:
     """
 
     def __init__(self, shapes, bin_edges, lmax, npcf=3, precision="fp32", input_dtype=torch.float32,
-                 device=None, stream=None, prepare=True):
+                 device=None, stream=None, prepare=True, keep_coeffs=False, fused=True):
         self.lib = _lib.load()
         shapes = [tuple(int(x) for x in s) for s in shapes]
         ndim = len(shapes[0])
@@ -58,7 +60,8 @@ class Plan:
         self.precision = precision
         self._prob = SbProblem(ndim, self.npcf, self.nbins,
                                self.edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.lmax, prec,
-                               _lib.SB_IN_F64 if input_dtype == torch.float64 else _lib.SB_IN_F32, 0)
+                               _lib.SB_IN_F64 if input_dtype == torch.float64 else _lib.SB_IN_F32,
+                               (_lib.SB_FLAG_KEEP_COEFFS if keep_coeffs else 0) | (0 if fused else _lib.SB_FLAG_UNFUSED))
         sh = np.ascontiguousarray(np.array(shapes, dtype=np.int64).ravel())
         self._shapes_arr = sh
         handle = ctypes.c_void_p()
@@ -191,7 +194,7 @@ class Plan:
         check(self.lib.sb_profile_read(self.handle, 0, ctypes.byref(n), None), "sb_profile_read")
         arr = (_lib.SbLaunchRecord * max(n.value, 1))()
         check(self.lib.sb_profile_read(self.handle, n.value, ctypes.byref(n), arr), "sb_profile_read")
-        keys = ["stage", "fft_n", "fft_sign", "batch", "bytes", "flops", "ms"]
+        keys = ["stage", "kernel", "fft_n", "fft_sign", "batch", "bytes", "flops", "ms"]
         return [{k: getattr(arr[i], k) for k in keys} for i in range(n.value)]
 
     def stage_times(self):

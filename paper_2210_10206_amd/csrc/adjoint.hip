@@ -118,20 +118,35 @@ sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta
                 a.vtmp = vtmp;
                 a.dsum = dsum;
                 a.first = lm == 0;
-                e = p->timed_launch(STAGE_OTHER, s, [&]() {
+                e = p->timed_launch(STAGE_OTHER, K_ADJPREP, s, [&]() {
                     hipLaunchKernelGGL(adj_prep_kernel, dim3(nblk), dim3(nt), 0, s, a);
                     return hipGetLastError();
                 });
                 if (e != hipSuccess) return hip_fail(e, "adjoint prep");
-                for (int b = 0; b < NB; ++b) {
-                    // acc += FFT(w_m v_b(-.)) * Khat_b: in-place passes on v_b, the last one accumulating
-                    float2 *vb = vtmp + (int64_t)b * G.ng;
-                    st = fft_axis_passes(p, G, -1, LOAD_C, vb, 0, nullptr, 0, vb, 0, 1, s, STORE_MACC,
-                                         khat + (int64_t)(lm * NB + b) * G.ng, 0, acc);
-                    if (st != SB_OK) return st;
-                }
+                // acc += sum_b FFT(w_m v_b(-.)) * Khat_b: transform v_b along axes 2..1 in place,
+                // then the axis-0 pass regenerates each kernel spectrum and accumulates
+                const int axes[2] = {2, 1};
+                st = fft_axes(p, G.n, 3, G.ng, axes, 2, -1, LOAD_C, vtmp, G.ng, vtmp, G.ng, NB, s);
+                if (st != SB_OK) return st;
+                Axis0Args x{};
+                x.n = (int)G.n[0];
+                x.plane = G.plane;
+                x.ng = G.ng;
+                x.np = G.np;
+                x.r0 = G.r0;
+                x.mode = 1;
+                x.kc = khat;
+                x.out = acc;
+                x.vin = vtmp;
+                x.nb = NB;
+                x.groups = 1;
+                x.kfirst = lm * NB;
+                x.tw = p->tw.at(x.n);
+                e = p->timed_launch(STAGE_FFT, K_AXIS0, s, [&]() { return launch_axis0(x, s); }, x.n, -1, NB,
+                                    (double)NB * (8.0 * G.ng + 8.0 * G.np * G.plane) + 16.0 * G.ng);
+                if (e != hipSuccess) return hip_fail(e, "adjoint axis-0 pass");
             }
-        st = fft_axis_passes(p, G, +1, LOAD_C, acc, 0, nullptr, 0, acc, 0, 1, s, STORE_C, nullptr, 0, nullptr);
+        st = fft_all_axes(p, G, +1, LOAD_C, acc, 0, acc, 0, 1, s);
         if (st != SB_OK) return st;
         hipLaunchKernelGGL(adj_finish_kernel, dim3(nblk), dim3(nt), 0, s, acc, dsum, 3, G.n[0], G.n[1], G.n[2], G.ng,
                            grad_delta[f]);

@@ -6,143 +6,12 @@
 // the contiguous axis), runs the radix stages in LDS with TPP threads per
 // pencil, and writes the tile back.  Loads can fuse the spectral product
 // (delta_hat * kernel_hat) or read a real field; stores can fuse a spectral
-// multiply-accumulate.  Twiddles come from a float64-computed table of the n-th
-// roots of unity, so every twiddle is correctly rounded to float32.
-//
-// Stockham autosort (decimation in time): with the radices R_0..R_{S-1} and
-// Ns = R_0 * .. * R_{s-1}, stage s takes butterfly k in [0, n/R) from
-// x[k + r n/R], multiplies input r by w^{(k mod Ns) r} with w = e^{sign 2 pi i/(Ns R)},
-// applies the R-point DFT and writes output r to (k div Ns) Ns R + (k mod Ns) + r Ns.
-// The result is in natural order.
-#include "sb_common.h"
+// multiply-accumulate.  The radix stages are in fft_core.h.
+#include "fft_core.h"
 
 namespace sb {
 namespace {
-
-template <int SIGN>
-__device__ __forceinline__ float2 mul_i(float2 a) {  // a * (SIGN * i)
-    return SIGN < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
-}
-
-template <int R, int SIGN> struct Dft;
-
-template <int SIGN> struct Dft<2, SIGN> {
-    __device__ __forceinline__ static void run(float2 *v) {
-        float2 a = v[0], b = v[1];
-        v[0] = cadd(a, b);
-        v[1] = csub(a, b);
-    }
-};
-
-template <int SIGN> struct Dft<3, SIGN> {
-    __device__ __forceinline__ static void run(float2 *v) {
-        const float s3 = 0.86602540378443864676f;  // sin(2 pi / 3)
-        float2 t1 = cadd(v[1], v[2]);
-        float2 t2 = csub(v[1], v[2]);
-        float2 y0 = cadd(v[0], t1);
-        float2 t = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
-        float2 u = mul_i<SIGN>(cscale(t2, s3));
-        v[0] = y0;
-        v[1] = cadd(t, u);
-        v[2] = csub(t, u);
-    }
-};
-
-template <int SIGN> struct Dft<4, SIGN> {
-    __device__ __forceinline__ static void run(float2 *v) {
-        float2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
-        float2 c = cadd(v[1], v[3]), d = mul_i<SIGN>(csub(v[1], v[3]));
-        v[0] = cadd(a, c);
-        v[2] = csub(a, c);
-        v[1] = cadd(b, d);
-        v[3] = csub(b, d);
-    }
-};
-
-template <int SIGN> struct Dft<5, SIGN> {
-    __device__ __forceinline__ static void run(float2 *v) {
-        const float c1 = 0.30901699437494742410f;   // cos(2 pi / 5)
-        const float c2 = -0.80901699437494742410f;  // cos(4 pi / 5)
-        const float s1 = 0.95105651629515357212f;   // sin(2 pi / 5)
-        const float s2 = 0.58778525229247312917f;   // sin(4 pi / 5)
-        float2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
-        float2 t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
-        float2 y0 = cadd(v[0], cadd(t1, t2));
-        float2 a1 = make_float2(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
-        float2 a2 = make_float2(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
-        float2 b1 = mul_i<SIGN>(make_float2(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y));
-        float2 b2 = mul_i<SIGN>(make_float2(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y));
-        v[0] = y0;
-        v[1] = cadd(a1, b1);
-        v[4] = csub(a1, b1);
-        v[2] = cadd(a2, b2);
-        v[3] = csub(a2, b2);
-    }
-};
-
-template <int SIGN> struct Dft<8, SIGN> {
-    // Radix-2 split into two 4-point DFTs of the even and odd inputs.
-    __device__ __forceinline__ static void run(float2 *v) {
-        const float r = 0.70710678118654752440f;
-        float2 e[4] = {v[0], v[2], v[4], v[6]};
-        float2 o[4] = {v[1], v[3], v[5], v[7]};
-        Dft<4, SIGN>::run(e);
-        Dft<4, SIGN>::run(o);
-        // w8^k = e^{SIGN 2 pi i k / 8}
-        float2 o1 = cmul(o[1], make_float2(r, SIGN * r));
-        float2 o2 = mul_i<SIGN>(o[2]);
-        float2 o3 = cmul(o[3], make_float2(-r, SIGN * r));
-        v[0] = cadd(e[0], o[0]);
-        v[4] = csub(e[0], o[0]);
-        v[1] = cadd(e[1], o1);
-        v[5] = csub(e[1], o1);
-        v[2] = cadd(e[2], o2);
-        v[6] = csub(e[2], o2);
-        v[3] = cadd(e[3], o3);
-        v[7] = csub(e[3], o3);
-    }
-};
-
-template <int N, int TPP, int P, int SIGN, int NS, int R>
-__device__ __forceinline__ void stage(float2 *sm, const float2 *tw, int p, int q) {
-    constexpr int PITCH = P + 1;
-    constexpr int NB = N / R;
-    static_assert(N % R == 0, "radix must divide n");
-    static_assert(NB % TPP == 0, "threads per pencil must divide n / R");
-    constexpr int PER = NB / TPP;
-    float2 v[PER][R];
-#pragma unroll
-    for (int t = 0; t < PER; ++t) {
-        const int k = q + t * TPP;
-#pragma unroll
-        for (int r = 0; r < R; ++r) v[t][r] = sm[(k + r * NB) * PITCH + p];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < PER; ++t) {
-        const int k = q + t * TPP;
-        const int kk = k % NS;
-        if (NS > 1) {
-#pragma unroll
-            for (int r = 1; r < R; ++r) {
-                float2 w = tw[kk * r * (N / (NS * R))];
-                if (SIGN > 0) w.y = -w.y;
-                v[t][r] = cmul(v[t][r], w);
-            }
-        }
-        Dft<R, SIGN>::run(v[t]);
-        const int base = (k / NS) * NS * R + kk;
-#pragma unroll
-        for (int r = 0; r < R; ++r) sm[(base + r * NS) * PITCH + p] = v[t][r];
-    }
-    __syncthreads();
-}
-
-template <int N, int TPP, int P, int SIGN, int NS, int R, int... REST>
-__device__ __forceinline__ void stages(float2 *sm, const float2 *tw, int p, int q) {
-    stage<N, TPP, P, SIGN, NS, R>(sm, tw, p, q);
-    if constexpr (sizeof...(REST) > 0) stages<N, TPP, P, SIGN, NS * R, REST...>(sm, tw, p, q);
-}
+using namespace fftcore;
 
 __device__ __forceinline__ float2 load_elem(const FftPass &a, int y, int64_t idx) {
     switch (a.load) {
@@ -203,7 +72,7 @@ __global__ __launch_bounds__(NT) void fft_pass_kernel(FftPass a) {
         }
     }
     __syncthreads();
-    stages<N, TPP, P, SIGN, 1, RAD...>(sm, tw, tid % P, tid / P);
+    stages<N, TPP, SIGN, 1, RAD...>(sm, tw, tid % P, tid / P, PITCH);
     if (a.stride == 1) {
         for (int f = tid; f < P * N; f += NT) {
             const int p = f / N, j = f % N;
@@ -215,6 +84,116 @@ __global__ __launch_bounds__(NT) void fft_pass_kernel(FftPass a) {
             if (g0 + p < npencil) store_elem(a, y, base[p] + (int64_t)j * a.stride, sm[j * PITCH + p]);
         }
     }
+}
+
+// ------------------------------------------------------------------------------
+// First inverse pass of the correlation, along axis 0, with the kernel spectrum
+// regenerated on the fly.  The kernels are stored transformed along the other axes
+// and compacted along axis 0 to the np planes of their support (|c_0| <= r0).  For a
+// tile of P pencils (P adjacent positions of the (axis 1, axis 2) plane):
+//   CORR : for each of the nb kernels of the group: K = FFT_0(stored kernel pencil),
+//          T = IFFT_0(delta_hat * K), written out;  delta_hat is read once per group.
+//   ADJ  : acc += sum_b FFT_0(v_b) * FFT_0(stored kernel pencil b)   (adjoint)
+template <int N, int TPP, int NT, int... RAD>
+__global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
+    constexpr int P = NT / TPP;
+    constexpr int PITCH = P + 1;
+    constexpr int EPT = N * P / NT;   // tile elements owned per thread
+    __shared__ float2 sm[N * PITCH];
+    __shared__ float2 tw[N];
+    const int tid = threadIdx.x;
+    const int64_t g0 = (int64_t)blockIdx.x * P;
+    for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
+    // ownership: element e of thread tid is (p, j) = (f % P, f / P), f = tid + e NT
+    int own_p[EPT], own_j[EPT], own_pl[EPT];
+    bool own_ok[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int f = tid + e * NT;
+        own_p[e] = f % P;
+        own_j[e] = f / P;
+        own_ok[e] = (g0 + own_p[e]) < a.plane;
+        const int j = own_j[e];
+        int pl = -1;
+        if (a.np == N) pl = j;
+        else if (j <= a.r0) pl = j;
+        else if (j >= N - a.r0) pl = a.np - (N - j);
+        own_pl[e] = pl;
+    }
+    const int64_t kstride = (int64_t)a.np * a.plane;
+    if (a.mode == 0) {
+        float2 dr[EPT];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e)
+            dr[e] = own_ok[e] ? a.dhat[(int64_t)own_j[e] * a.plane + g0 + own_p[e]] : make_float2(0.f, 0.f);
+        const int64_t kbase = (int64_t)blockIdx.y * a.nb;
+        for (int b = 0; b < a.nb; ++b) {
+            __syncthreads();
+            const float2 *kc = a.kc + (kbase + b) * kstride;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                float2 v = make_float2(0.f, 0.f);
+                if (own_ok[e] && own_pl[e] >= 0) v = kc[(int64_t)own_pl[e] * a.plane + g0 + own_p[e]];
+                sm[own_j[e] * PITCH + own_p[e]] = v;
+            }
+            __syncthreads();
+            stages<N, TPP, -1, 1, RAD...>(sm, tw, tid % P, tid / P, PITCH);
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                float2 *x = &sm[own_j[e] * PITCH + own_p[e]];
+                *x = cmul(*x, dr[e]);
+            }
+            __syncthreads();
+            stages<N, TPP, 1, 1, RAD...>(sm, tw, tid % P, tid / P, PITCH);
+            float2 *out = a.out + (kbase + b) * a.ng;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e)
+                if (own_ok[e]) out[(int64_t)own_j[e] * a.plane + g0 + own_p[e]] = sm[own_j[e] * PITCH + own_p[e]];
+        }
+    } else {
+        float2 acc[EPT];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) acc[e] = make_float2(0.f, 0.f);
+        for (int b = 0; b < a.nb; ++b) {
+            __syncthreads();
+            const float2 *vb = a.vin + (int64_t)b * a.ng;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e)
+                sm[own_j[e] * PITCH + own_p[e]] =
+                    own_ok[e] ? vb[(int64_t)own_j[e] * a.plane + g0 + own_p[e]] : make_float2(0.f, 0.f);
+            __syncthreads();
+            stages<N, TPP, -1, 1, RAD...>(sm, tw, tid % P, tid / P, PITCH);
+            float2 vr[EPT];
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) vr[e] = sm[own_j[e] * PITCH + own_p[e]];
+            __syncthreads();
+            const float2 *kc = a.kc + (int64_t)(a.kfirst + b) * kstride;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                float2 v = make_float2(0.f, 0.f);
+                if (own_ok[e] && own_pl[e] >= 0) v = kc[(int64_t)own_pl[e] * a.plane + g0 + own_p[e]];
+                sm[own_j[e] * PITCH + own_p[e]] = v;
+            }
+            __syncthreads();
+            stages<N, TPP, -1, 1, RAD...>(sm, tw, tid % P, tid / P, PITCH);
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) acc[e] = cadd(acc[e], cmul(vr[e], sm[own_j[e] * PITCH + own_p[e]]));
+        }
+#pragma unroll
+        for (int e = 0; e < EPT; ++e)
+            if (own_ok[e]) {
+                float2 *o = a.out + (int64_t)own_j[e] * a.plane + g0 + own_p[e];
+                *o = cadd(*o, acc[e]);
+            }
+    }
+}
+
+template <int N, int TPP, int NT, int... RAD>
+hipError_t launch_axis0_t(const Axis0Args &a, hipStream_t s) {
+    constexpr int P = NT / TPP;
+    dim3 grid((unsigned)((a.plane + P - 1) / P), (unsigned)a.groups);
+    hipLaunchKernelGGL((axis0_kernel<N, TPP, NT, RAD...>), grid, dim3(NT), 0, s, a);
+    return hipGetLastError();
 }
 
 template <int N, int TPP, int NT, int... RAD>
@@ -249,6 +228,34 @@ hipError_t launch_fft_pass(const FftPass &a, hipStream_t s) {
         case 192: return launch<192, 8, 128, 8, 8, 3>(a, s);
         case 256: return v == 1 ? launch<256, 32, 256, 8, 8, 4>(a, s) : launch<256, 16, 256, 8, 8, 4>(a, s);
         case 512: return v == 1 ? launch<512, 64, 256, 8, 8, 8>(a, s) : launch<512, 32, 256, 8, 8, 8>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_axis0(const Axis0Args &a, hipStream_t s) {
+    switch (a.n) {
+#define SB_X(N, TPP, NT, ...) case N: return launch_axis0_t<N, TPP, NT, __VA_ARGS__>(a, s);
+        SB_FFT_CONFIGS(SB_X)
+#undef SB_X
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int fft_threads_per_pencil(int n) {
+    switch (n) {
+#define SB_X(N, TPP, NT, ...) case N: return TPP;
+        SB_FFT_CONFIGS(SB_X)
+#undef SB_X
+        default: return 0;
+    }
+}
+
+hipError_t launch_last_contract(const LastArgs &a, hipStream_t s) {
+    if (a.nb * a.rows * fft_threads_per_pencil(a.n) > 1024) return hipErrorInvalidValue;
+    switch (a.n) {
+#define SB_X(N, TPP, NT, ...) case N: return launch_last_for<N>(a, s);
+        SB_FFT_CONFIGS(SB_X)
+#undef SB_X
         default: return hipErrorInvalidValue;
     }
 }

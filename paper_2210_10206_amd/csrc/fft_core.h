@@ -1,0 +1,167 @@
+// Mixed-radix Stockham FFT building blocks for gfx950 (shared by the FFT translation units).
+//
+// A launch transforms every pencil of one axis of a batch of C-ordered complex
+// arrays.  A workgroup owns P pencils: it stages them in LDS (coalesced: P
+// adjacent pencils along the fastest axis for a strided axis, P whole rows for
+// the contiguous axis), runs the radix stages in LDS with TPP threads per
+// pencil, and writes the tile back.  Loads can fuse the spectral product
+// (delta_hat * kernel_hat) or read a real field; stores can fuse a spectral
+// multiply-accumulate.  Twiddles come from a float64-computed table of the n-th
+// roots of unity, so every twiddle is correctly rounded to float32.
+//
+// Stockham autosort (decimation in time): with the radices R_0..R_{S-1} and
+// Ns = R_0 * .. * R_{s-1}, stage s takes butterfly k in [0, n/R) from
+// x[k + r n/R], multiplies input r by w^{(k mod Ns) r} with w = e^{sign 2 pi i/(Ns R)},
+// applies the R-point DFT and writes output r to (k div Ns) Ns R + (k mod Ns) + r Ns.
+// The result is in natural order.
+#pragma once
+#include "sb_common.h"
+
+namespace sb {
+namespace fftcore {
+
+template <int SIGN>
+__device__ __forceinline__ float2 mul_i(float2 a) {  // a * (SIGN * i)
+    return SIGN < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+}
+
+template <int R, int SIGN> struct Dft;
+
+template <int SIGN> struct Dft<2, SIGN> {
+    __device__ __forceinline__ static void run(float2 *v) {
+        float2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+
+template <int SIGN> struct Dft<3, SIGN> {
+    __device__ __forceinline__ static void run(float2 *v) {
+        const float s3 = 0.86602540378443864676f;  // sin(2 pi / 3)
+        float2 t1 = cadd(v[1], v[2]);
+        float2 t2 = csub(v[1], v[2]);
+        float2 y0 = cadd(v[0], t1);
+        float2 t = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
+        float2 u = mul_i<SIGN>(cscale(t2, s3));
+        v[0] = y0;
+        v[1] = cadd(t, u);
+        v[2] = csub(t, u);
+    }
+};
+
+template <int SIGN> struct Dft<4, SIGN> {
+    __device__ __forceinline__ static void run(float2 *v) {
+        float2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+        float2 c = cadd(v[1], v[3]), d = mul_i<SIGN>(csub(v[1], v[3]));
+        v[0] = cadd(a, c);
+        v[2] = csub(a, c);
+        v[1] = cadd(b, d);
+        v[3] = csub(b, d);
+    }
+};
+
+template <int SIGN> struct Dft<5, SIGN> {
+    __device__ __forceinline__ static void run(float2 *v) {
+        const float c1 = 0.30901699437494742410f;   // cos(2 pi / 5)
+        const float c2 = -0.80901699437494742410f;  // cos(4 pi / 5)
+        const float s1 = 0.95105651629515357212f;   // sin(2 pi / 5)
+        const float s2 = 0.58778525229247312917f;   // sin(4 pi / 5)
+        float2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+        float2 t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+        float2 y0 = cadd(v[0], cadd(t1, t2));
+        float2 a1 = make_float2(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
+        float2 a2 = make_float2(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
+        float2 b1 = mul_i<SIGN>(make_float2(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y));
+        float2 b2 = mul_i<SIGN>(make_float2(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y));
+        v[0] = y0;
+        v[1] = cadd(a1, b1);
+        v[4] = csub(a1, b1);
+        v[2] = cadd(a2, b2);
+        v[3] = csub(a2, b2);
+    }
+};
+
+template <int SIGN> struct Dft<8, SIGN> {
+    // Radix-2 split into two 4-point DFTs of the even and odd inputs.
+    __device__ __forceinline__ static void run(float2 *v) {
+        const float r = 0.70710678118654752440f;
+        float2 e[4] = {v[0], v[2], v[4], v[6]};
+        float2 o[4] = {v[1], v[3], v[5], v[7]};
+        Dft<4, SIGN>::run(e);
+        Dft<4, SIGN>::run(o);
+        // w8^k = e^{SIGN 2 pi i k / 8}
+        float2 o1 = cmul(o[1], make_float2(r, SIGN * r));
+        float2 o2 = mul_i<SIGN>(o[2]);
+        float2 o3 = cmul(o[3], make_float2(-r, SIGN * r));
+        v[0] = cadd(e[0], o[0]);
+        v[4] = csub(e[0], o[0]);
+        v[1] = cadd(e[1], o1);
+        v[5] = csub(e[1], o1);
+        v[2] = cadd(e[2], o2);
+        v[6] = csub(e[2], o2);
+        v[3] = cadd(e[3], o3);
+        v[7] = csub(e[3], o3);
+    }
+};
+
+// One Stockham stage on pencils stored in LDS as sm[j * pitch + p] (p = pencil in the
+// tile, j = element), TPP threads per pencil, thread (p, q).
+template <int N, int TPP, int SIGN, int NS, int R>
+__device__ __forceinline__ void stage(float2 *sm, const float2 *tw, int p, int q, int pitch) {
+    constexpr int NB = N / R;
+    static_assert(N % R == 0, "radix must divide n");
+    static_assert(NB % TPP == 0, "threads per pencil must divide n / R");
+    constexpr int PER = NB / TPP;
+    float2 v[PER][R];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int k = q + t * TPP;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[t][r] = sm[(k + r * NB) * pitch + p];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int k = q + t * TPP;
+        const int kk = k % NS;
+        if (NS > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                float2 w = tw[kk * r * (N / (NS * R))];
+                if (SIGN > 0) w.y = -w.y;
+                v[t][r] = cmul(v[t][r], w);
+            }
+        }
+        Dft<R, SIGN>::run(v[t]);
+        const int base = (k / NS) * NS * R + kk;
+#pragma unroll
+        for (int r = 0; r < R; ++r) sm[(base + r * NS) * pitch + p] = v[t][r];
+    }
+    __syncthreads();
+}
+
+template <int N, int TPP, int SIGN, int NS, int R, int... REST>
+__device__ __forceinline__ void stages(float2 *sm, const float2 *tw, int p, int q, int pitch) {
+    stage<N, TPP, SIGN, NS, R>(sm, tw, p, q, pitch);
+    if constexpr (sizeof...(REST) > 0) stages<N, TPP, SIGN, NS * R, REST...>(sm, tw, p, q, pitch);
+}
+
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+}  // namespace fftcore
+
+// Default shape (threads per pencil, workgroup threads, radices) of each length.
+#define SB_FFT_CONFIGS(X)                                                                   \
+    X(8, 1, 64, 8) X(12, 1, 64, 4, 3) X(16, 4, 64, 4, 4) X(24, 2, 128, 4, 2, 3)             \
+    X(32, 4, 64, 4, 8) X(48, 4, 64, 4, 4, 3) X(64, 8, 128, 8, 8) X(96, 4, 64, 4, 8, 3)      \
+    X(128, 16, 256, 8, 8, 2) X(160, 4, 64, 4, 8, 5) X(192, 8, 128, 8, 8, 3)                  \
+    X(256, 16, 256, 8, 8, 4) X(512, 32, 256, 8, 8, 8)
+
+// Fused last pass + contraction for one length (defined in fft_last_*.hip).
+template <int N> hipError_t launch_last_for(const LastArgs &a, hipStream_t s);
+
+}  // namespace sb

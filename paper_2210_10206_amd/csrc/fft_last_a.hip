@@ -1,0 +1,30 @@
+// Fused last pass + contraction: instantiations for lengths 8, 12, 16, 24, 32, 48.
+#include "fft_last.h"
+
+namespace sb {
+
+template <> hipError_t launch_last_for<8>(const LastArgs &a, hipStream_t s) {
+    return fftlast::launch_last_nb<8, 1, 8>(a, s);
+}
+
+template <> hipError_t launch_last_for<12>(const LastArgs &a, hipStream_t s) {
+    return fftlast::launch_last_nb<12, 1, 4, 3>(a, s);
+}
+
+template <> hipError_t launch_last_for<16>(const LastArgs &a, hipStream_t s) {
+    return fftlast::launch_last_nb<16, 4, 4, 4>(a, s);
+}
+
+template <> hipError_t launch_last_for<24>(const LastArgs &a, hipStream_t s) {
+    return fftlast::launch_last_nb<24, 2, 4, 2, 3>(a, s);
+}
+
+template <> hipError_t launch_last_for<32>(const LastArgs &a, hipStream_t s) {
+    return fftlast::launch_last_nb<32, 4, 4, 8>(a, s);
+}
+
+template <> hipError_t launch_last_for<48>(const LastArgs &a, hipStream_t s) {
+    return fftlast::launch_last_nb<48, 4, 4, 4, 3>(a, s);
+}
+
+}  // namespace sb

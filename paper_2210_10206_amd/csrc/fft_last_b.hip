@@ -1,0 +1,18 @@
+// Fused last pass + contraction: instantiations for lengths 64, 96, 128.
+#include "fft_last.h"
+
+namespace sb {
+
+template <> hipError_t launch_last_for<64>(const LastArgs &a, hipStream_t s) {
+    return fftlast::launch_last_nb<64, 8, 8, 8>(a, s);
+}
+
+template <> hipError_t launch_last_for<96>(const LastArgs &a, hipStream_t s) {
+    return fftlast::launch_last_nb<96, 4, 4, 8, 3>(a, s);
+}
+
+template <> hipError_t launch_last_for<128>(const LastArgs &a, hipStream_t s) {
+    return fftlast::launch_last_nb<128, 16, 8, 8, 2>(a, s);
+}
+
+}  // namespace sb

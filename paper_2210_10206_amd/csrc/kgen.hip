@@ -1,7 +1,9 @@
 // Binned angular kernels on the grid (Alg. 1 for Y_lm, Alg. 2 for e^{i m phi}).
 //
-// Every cell of the grid is visited once.  Its offset is the zero-centred
-// coordinate of the *reflected* cell, d_a = c((n_a - i_a) mod n_a), so the array
+// Every stored cell is visited once.  Only the axis-0 planes that meet the support
+// (|c_0| <= r0, at most 2 r0 + 1 planes) are stored; the FFT along the other axes is
+// applied afterwards and the axis-0 transform is redone on the fly by the first
+// inverse pass.  A cell's offset is the zero-centred coordinate of the *reflected* cell, d_a = c((n_a - i_a) mod n_a), so the array
 // written is K(-r): the FFT of that array turns the FFT product of the
 // correlation (eq. almconv, a correlation per its footnote) into a plain
 // spectral multiplication.  The bin test e_b < |d| <= e_{b+1} is done in
@@ -24,11 +26,16 @@ __device__ __forceinline__ int64_t centred(int64_t i, int64_t n) { return (2 * i
 __global__ void kgen_kernel(KgenArgs a) {
     const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= a.ng) return;
+    // stored cell -> grid index: axes 1.. in full, axis 0 through the plane map
     int64_t idx[3] = {0, 0, 0};
     int64_t rem = cell;
-    for (int d = a.ndim - 1; d >= 0; --d) {
+    for (int d = a.ndim - 1; d >= 1; --d) {
         idx[d] = rem % a.n[d];
         rem /= a.n[d];
+    }
+    {
+        const int64_t p = rem;   // stored plane
+        idx[0] = (a.np == a.n[0] || p <= a.r0) ? p : a.n[0] - (a.np - p);
     }
     int64_t c[3] = {0, 0, 0};
     for (int d = 0; d < a.ndim; ++d) c[d] = centred((a.n[d] - idx[d]) % a.n[d], a.n[d]);

@@ -307,11 +307,38 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
     p->d_gptr = reinterpret_cast<const int *>(base + off_gptr);
     p->d_gidx = reinterpret_cast<const int *>(base + off_gidx);
     p->d_gcoef = reinterpret_cast<const double *>(base + off_gcoef);
-    // ---- workspace layout
+    // ---- kernel support along axis 0, fused-pass tiling, workspace layout
+    int64_t r0 = 0;
+    while ((r0 + 1) * (r0 + 1) <= p->thr[NB]) ++r0;      // largest |c_0| with c_0^2 <= e_max^2
+    p->fused = (prob->flags & (SB_FLAG_UNFUSED | SB_FLAG_KEEP_COEFFS)) == 0;
     size_t pers = 0;
     for (auto &G : p->groups) {
+        G.plane = G.ng / G.n[0];
+        G.r0 = (int)std::min<int64_t>(r0, G.n[0]);
+        G.np = support_planes(G.n[0], G.r0);
         G.khat_off = pers;
-        pers += align256((size_t)p->nk * G.ng * sizeof(float2));
+        pers += align256((size_t)p->nk * G.np * G.plane * sizeof(float2));
+        // fused last pass: rows per tile so that nb * rows pencils of tpp threads fill whole
+        // waves (>= 256 threads when possible) within 1024 threads and 96 KB of LDS
+        const int nl = (int)G.n[prob->ndim - 1];
+        const int tpp = fft_threads_per_pencil(nl);
+        G.rows = 0;
+        for (int R = 1; R <= 64 && tpp > 0; ++R) {
+            const int nt = NB * R * tpp;
+            if (nt > 1024) break;
+            const size_t lds = (size_t)(nl * (NB * R + 1) + nl) * sizeof(float2);
+            if (lds > 98304) break;
+            if (nt % 64) continue;
+            G.rows = R;
+            if (nt >= 256) break;
+        }
+        if (G.rows > 0) {
+            const int64_t nrows = G.ng / nl;
+            int64_t rpb = (nrows + 1023) / 1024;
+            rpb = std::max<int64_t>(rpb, 16);
+            rpb = (rpb + G.rows - 1) / G.rows * G.rows;
+            G.rows_per_block = rpb;
+        }
     }
     p->persist_need = pers;
     size_t sc = 0;
@@ -320,6 +347,11 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
     p->off_coef = sc; sc += align256((size_t)p->nk * p->max_ng * sizeof(float2));
     int groups = 0, nvals = 0, nblocks = 0;
     contraction_shape(p, p->max_ng, &groups, &nvals, &nblocks);
+    for (const auto &G : p->groups)
+        if (G.rows > 0 && prob->npcf == 3) {
+            const int64_t nrows = G.ng / G.n[prob->ndim - 1];
+            nblocks = std::max<int>(nblocks, (int)((nrows + G.rows_per_block - 1) / G.rows_per_block));
+        }
     p->off_part = sc; sc += align256((size_t)groups * nvals * nblocks * sizeof(double));
     p->off_tot = sc; sc += align256((size_t)groups * nvals * sizeof(double));
     p->off_grad = sc; sc += align256((size_t)p->max_ng * sizeof(float2));
@@ -334,92 +366,176 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
 
 // ------------------------------------------------------------------ passes
 
-sb_status fft_axis_passes(sb_plan *p, const ShapeGroup &G, int sign, int first_load, const void *in, int64_t in_bs,
-                          const float2 *in2, int64_t in2_bs, float2 *out, int64_t out_bs, int batch,
-                          hipStream_t s, int store, const float2 *mul, int64_t mul_bs, float2 *final_out) {
-    const int nd = p->prob.ndim;
-    for (int d = 0; d < nd; ++d) {
+sb_status fft_axes(sb_plan *p, const int64_t *n, int ndim, int64_t ncell, const int *axes, int naxes, int sign,
+                   int first_load, const void *in, int64_t in_bs, float2 *out, int64_t out_bs, int batch,
+                   hipStream_t s, int store, const float2 *mul, int64_t mul_bs, float2 *final_out) {
+    for (int i = 0; i < naxes; ++i) {
+        const int d = axes[i];
         FftPass a{};
-        a.n = (int)G.n[d];
+        a.n = (int)n[d];
         int64_t stride = 1;
-        for (int k = d + 1; k < nd; ++k) stride *= G.n[k];
+        for (int k = d + 1; k < ndim; ++k) stride *= n[k];
         a.stride = stride;
-        a.ng = G.ng;
+        a.ng = ncell;
         a.sign = sign;
         a.batch = batch;
         a.tw = p->tw.at(a.n);
         a.variant = p->fft_variant(a.n, d);
         a.out = out;
         a.out_bs = out_bs;
-        if (d == 0) {
+        if (i == 0) {
             a.load = first_load;
             a.in = in;
             a.in_bs = in_bs;
-            a.in2 = in2;
-            a.in2_bs = in2_bs;
         } else {
             a.load = LOAD_C;
             a.in = out;
             a.in_bs = out_bs;
         }
-        a.store = (d == nd - 1) ? store : STORE_C;
+        const bool last = i == naxes - 1;
+        a.store = last ? store : STORE_C;
         a.mul = mul;
         a.mul_bs = mul_bs;
-        if (d == nd - 1 && final_out) a.out = final_out;
-        // algorithmic traffic: read + write of every transformed array, plus the spectral
-        // product's second operand (one array per batch item) and its shared first operand
-        double bytes = 16.0 * (double)G.ng * batch;
-        if (a.load == LOAD_MUL) bytes += 8.0 * (double)G.ng * batch + 8.0 * (double)G.ng;
-        if (a.store == STORE_MACC) bytes += 16.0 * (double)G.ng * batch;
-        const hipError_t e = p->timed_launch(STAGE_FFT, s, [&]() { return launch_fft_pass(a, s); }, a.n, sign,
+        if (last && final_out) a.out = final_out;
+        // algorithmic traffic: read + write of every transformed array
+        double bytes = 16.0 * (double)ncell * batch;
+        if (a.store == STORE_MACC) bytes += 16.0 * (double)ncell * batch;
+        const hipError_t e = p->timed_launch(STAGE_FFT, K_FFT, s, [&]() { return launch_fft_pass(a, s); }, a.n, sign,
                                              batch, bytes);
         if (e != hipSuccess) return hip_fail(e, "fft pass");
     }
     return SB_OK;
 }
 
+sb_status fft_all_axes(sb_plan *p, const ShapeGroup &G, int sign, int first_load, const void *in, int64_t in_bs,
+                       float2 *out, int64_t out_bs, int batch, hipStream_t s) {
+    const int axes[3] = {0, 1, 2};
+    return fft_axes(p, G.n, p->prob.ndim, G.ng, axes, p->prob.ndim, sign, first_load, in, in_bs, out, out_bs, batch, s);
+}
+
 sb_status prepare(sb_plan *p, hipStream_t s) {
     if (!p->persist || !p->scratch) return fail(SB_EWORKSPACE, "workspace not bound");
+    const int nd = p->prob.ndim;
     for (auto &G : p->groups) {
-        float2 *khat = reinterpret_cast<float2 *>(p->persist + G.khat_off);
+        float2 *kc = reinterpret_cast<float2 *>(p->persist + G.khat_off);
+        const int64_t ncell = (int64_t)G.np * G.plane;
         KgenArgs a{};
-        a.ndim = p->prob.ndim;
+        a.ndim = nd;
         for (int d = 0; d < 3; ++d) a.n[d] = G.n[d];
-        a.ng = G.ng;
+        a.ng = ncell;
+        a.np = G.np;
+        a.r0 = G.r0;
         a.nbins = p->prob.nbins;
         for (int b = 0; b <= p->prob.nbins; ++b) a.thr[b] = p->thr[b];
         a.lmax = p->prob.lmax;
         a.nlm = p->nlm;
-        if (p->prob.ndim == 3)
+        if (nd == 3)
             for (int l = 0; l <= p->prob.lmax; ++l)
                 for (int m = 0; m <= l; ++m) a.norm[l * (l + 1) / 2 + m] = ylm_norm(l, m);
         a.scale = (float)(1.0 / (double)G.ng);
-        a.out = khat;
+        a.out = kc;
         hipError_t e = launch_kgen(a, s);
         if (e != hipSuccess) return hip_fail(e, "kernel generation");
-        const sb_status st = fft_axis_passes(p, G, -1, LOAD_C, khat, G.ng, nullptr, 0, khat, G.ng, p->nk, s,
-                                             STORE_C, nullptr, 0, nullptr);
+        // forward transform along every axis but 0 (axis 0 is redone per field in the first pass)
+        const int64_t cn[3] = {G.np, G.n[1], G.n[2]};
+        const int axes[2] = {1, 2};
+        const sb_status st = fft_axes(p, cn, nd, ncell, axes, nd - 1, -1, LOAD_C, kc, ncell, kc, ncell, p->nk, s);
         if (st != SB_OK) return st;
     }
     p->prepared = true;
     return SB_OK;
 }
 
+// First inverse pass: axis-0 correlation of every kernel group with the density spectrum.
+static sb_status axis0_corr(sb_plan *p, const ShapeGroup &G, const float2 *dhat, float2 *out, hipStream_t s) {
+    Axis0Args a{};
+    a.n = (int)G.n[0];
+    a.plane = G.plane;
+    a.ng = G.ng;
+    a.np = G.np;
+    a.r0 = G.r0;
+    a.mode = 0;
+    a.dhat = dhat;
+    a.kc = reinterpret_cast<const float2 *>(p->persist + G.khat_off);
+    a.out = out;
+    a.nb = p->prob.nbins;
+    a.groups = p->nlm;
+    a.tw = p->tw.at(a.n);
+    // traffic: stored kernel planes read, outputs written, density spectrum read once per group
+    const double bytes = (double)p->nk * (8.0 * G.np * G.plane + 8.0 * G.ng) + (double)p->nlm * 8.0 * G.ng;
+    const hipError_t e = p->timed_launch(STAGE_FFT, K_AXIS0, s, [&]() { return launch_axis0(a, s); }, a.n, 1, p->nk, bytes);
+    if (e != hipSuccess) return hip_fail(e, "axis-0 correlation pass");
+    return SB_OK;
+}
+
+// Density ingest and spectrum (the first step of Alg. 3 / Alg. 4).
+static sb_status density_spectrum(sb_plan *p, const ShapeGroup &G, const void *delta, hipStream_t s) {
+    float *w = reinterpret_cast<float *>(p->scratch + p->off_w);
+    float2 *dhat = reinterpret_cast<float2 *>(p->scratch + p->off_dhat);
+    hipError_t e = launch_to_f32(delta, p->prob.input_dtype, G.ng, w, s);
+    if (e != hipSuccess) return hip_fail(e, "density ingest");
+    return fft_all_axes(p, G, -1, LOAD_R32, w, 0, dhat, 0, 1, s);
+}
+
 // Coefficients of every kernel for one field into scratch (Alg. 3 / Alg. 4 as a correlation).
 sb_status coefficients(sb_plan *p, int f, const void *delta, hipStream_t s) {
     const ShapeGroup &G = p->groups[p->field_group[f]];
-    float *w = reinterpret_cast<float *>(p->scratch + p->off_w);
     float2 *dhat = reinterpret_cast<float2 *>(p->scratch + p->off_dhat);
     float2 *coef = reinterpret_cast<float2 *>(p->scratch + p->off_coef);
-    const float2 *khat = reinterpret_cast<const float2 *>(p->persist + G.khat_off);
-    hipError_t e = launch_to_f32(delta, p->prob.input_dtype, G.ng, w, s);
-    if (e != hipSuccess) return hip_fail(e, "density ingest");
-    sb_status st = fft_axis_passes(p, G, -1, LOAD_R32, w, 0, nullptr, 0, dhat, 0, 1, s, STORE_C, nullptr, 0, nullptr);
+    sb_status st = density_spectrum(p, G, delta, s);
     if (st != SB_OK) return st;
-    st = fft_axis_passes(p, G, +1, LOAD_MUL, dhat, 0, khat, G.ng, coef, G.ng, p->nk, s, STORE_C, nullptr, 0,
-                         nullptr);
+    st = axis0_corr(p, G, dhat, coef, s);
+    if (st != SB_OK) return st;
+    const int axes[2] = {1, 2};
+    st = fft_axes(p, G.n, p->prob.ndim, G.ng, axes, p->prob.ndim - 1, +1, LOAD_C, coef, G.ng, coef, G.ng, p->nk, s);
     if (st != SB_OK) return st;
     p->last_ng = G.ng;
+    return SB_OK;
+}
+
+// 3PCF of one field with the contraction fused into the last inverse pass (the
+// coefficient arrays are never written).
+static sb_status fused_3pcf(sb_plan *p, int f, const void *delta, double *zeta_f, hipStream_t s) {
+    const ShapeGroup &G = p->groups[p->field_group[f]];
+    const int nd = p->prob.ndim, NB = p->prob.nbins;
+    float2 *dhat = reinterpret_cast<float2 *>(p->scratch + p->off_dhat);
+    float2 *coef = reinterpret_cast<float2 *>(p->scratch + p->off_coef);
+    const float *w = reinterpret_cast<const float *>(p->scratch + p->off_w);
+    double *part = reinterpret_cast<double *>(p->scratch + p->off_part);
+    double *tot = reinterpret_cast<double *>(p->scratch + p->off_tot);
+    sb_status st = density_spectrum(p, G, delta, s);
+    if (st != SB_OK) return st;
+    st = axis0_corr(p, G, dhat, coef, s);
+    if (st != SB_OK) return st;
+    if (nd == 3) {
+        const int axes[1] = {1};
+        st = fft_axes(p, G.n, nd, G.ng, axes, 1, +1, LOAD_C, coef, G.ng, coef, G.ng, p->nk, s);
+        if (st != SB_OK) return st;
+    }
+    LastArgs a{};
+    a.n = (int)G.n[nd - 1];
+    a.ng = G.ng;
+    a.in = coef;
+    a.w = w;
+    a.nb = NB;
+    a.groups = p->nlm;
+    a.rows = G.rows;
+    a.rows_per_block = G.rows_per_block;
+    const int64_t nrows = G.ng / a.n;
+    a.nblocks = (int)((nrows + G.rows_per_block - 1) / G.rows_per_block);
+    a.want_imag = nd == 2;
+    a.partial = part;
+    a.tw = p->tw.at(a.n);
+    const int nv = NB * (NB + 1) / 2 * (nd == 2 ? 2 : 1);
+    const double bytes = (double)p->nk * 8.0 * G.ng + (double)p->nlm * 4.0 * G.ng;
+    const double flops = (double)G.ng * p->nlm * (2.0 * NB + NB * (NB + 1) / 2.0 * (nd == 2 ? 8.0 : 4.0));
+    hipError_t e = p->timed_launch(STAGE_CONTRACT, K_LAST, s, [&]() { return launch_last_contract(a, s); }, a.n, 1, p->nk,
+                                   bytes, flops);
+    if (e != hipSuccess) return hip_fail(e, "fused last pass");
+    e = launch_block_sum(part, p->nlm, a.nblocks, nv, tot, s);
+    if (e != hipSuccess) return hip_fail(e, "block sum");
+    e = launch_gather(tot, p->d_gptr, p->d_gidx, p->d_gcoef, p->gather_nout, zeta_f, s);
+    if (e != hipSuccess) return hip_fail(e, "gather");
     return SB_OK;
 }
 
@@ -448,7 +564,7 @@ sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
         const double np_ = NB * (NB + 1) / 2.0;
         const double fl = (double)G.ng * groups * (2.0 + np_ * (a.want_imag ? 8.0 : 4.0));
         const double by = (double)G.ng * (8.0 * p->nk + 4.0);
-        e = p->timed_launch(STAGE_CONTRACT, s, [&]() { return launch_pair_contract(a, s); }, 0, 0, groups, by, fl);
+        e = p->timed_launch(STAGE_CONTRACT, K_PAIR, s, [&]() { return launch_pair_contract(a, s); }, 0, 0, groups, by, fl);
     } else if (p->prob.ndim == 3) {
         QuadArgs a{};
         a.coef = coef;
@@ -473,7 +589,7 @@ sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
         }
         fl *= (double)G.ng;
         const double by = (double)G.ng * (8.0 * p->nk + 4.0);
-        e = p->timed_launch(STAGE_CONTRACT, s, [&]() { return launch_quad_contract(a, s); }, 0, 0, groups, by, fl);
+        e = p->timed_launch(STAGE_CONTRACT, K_QUAD, s, [&]() { return launch_quad_contract(a, s); }, 0, 0, groups, by, fl);
     } else {
         Proj4Args a{};
         a.coef = coef;
@@ -489,7 +605,7 @@ sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
         a.nblocks = nblocks;
         const double fl = (double)G.ng * groups * NB * NB * (8.0 + 8.0 * NB);
         const double by = (double)G.ng * (8.0 * p->nk + 4.0);
-        e = p->timed_launch(STAGE_CONTRACT, s, [&]() { return launch_proj4_contract(a, s); }, 0, 0, groups, by, fl);
+        e = p->timed_launch(STAGE_CONTRACT, K_PROJ4, s, [&]() { return launch_proj4_contract(a, s); }, 0, 0, groups, by, fl);
     }
     if (e != hipSuccess) return hip_fail(e, "contraction");
     e = launch_block_sum(part, groups, nblocks, nvals, tot, s);
@@ -506,9 +622,15 @@ sb_status forward(sb_plan *p, const void *const *delta, double *zeta, hipStream_
     if (!p->prepared) return fail(SB_ESTATE, "sb_prepare has not run on the bound workspace");
     for (int f = 0; f < p->batch; ++f) {
         if (!delta[f]) return fail(SB_EINVAL, "null field pointer");
-        sb_status st = coefficients(p, f, delta[f], s);
-        if (st != SB_OK) return st;
-        st = contract(p, f, zeta + (int64_t)f * p->zeta_doubles, s);
+        double *zf = zeta + (int64_t)f * p->zeta_doubles;
+        const ShapeGroup &G = p->groups[p->field_group[f]];
+        sb_status st;
+        if (p->prob.npcf == 3 && p->fused && G.rows > 0) {
+            st = fused_3pcf(p, f, delta[f], zf, s);
+        } else {
+            st = coefficients(p, f, delta[f], s);
+            if (st == SB_OK) st = contract(p, f, zf, s);
+        }
         if (st != SB_OK) return st;
     }
     return SB_OK;

@@ -27,6 +27,7 @@ sb_status sb_profile_read(sb_plan *p, int32_t max, int32_t *count, sb_launch_rec
         e = hipEventElapsedTime(&x, t.a, t.b);
         if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
         out[i].stage = t.stage;
+        out[i].kernel = t.kernel;
         out[i].fft_n = t.fft_n;
         out[i].fft_sign = t.fft_sign;
         out[i].batch = t.batch;

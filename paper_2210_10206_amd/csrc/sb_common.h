@@ -47,10 +47,48 @@ struct FftPass {
     int variant;       // launch-shape variant (autotuned)
 };
 
-// Launch one FFT pass; returns hipSuccess or the launch error.  `ok` reports whether a
-// kernel exists for (n, variant).
+// Launch one FFT pass; returns hipSuccess or the launch error (hipErrorInvalidValue when
+// no kernel exists for the length).
 hipError_t launch_fft_pass(const FftPass &p, hipStream_t s);
 bool fft_supported(int n);
 int fft_num_variants(int n);
+int fft_threads_per_pencil(int n);
+
+// First inverse pass along axis 0 with the kernel spectra regenerated from their
+// compact storage (transformed along the other axes, np planes along axis 0: stored
+// plane p holds axis-0 index p for p <= r0 and n - (np - p) above; all n when np == n).
+struct Axis0Args {
+    int n;                // axis-0 length
+    int64_t plane;        // product of the other extents (= axis-0 stride)
+    int64_t ng;           // n * plane
+    int np, r0;
+    int mode;             // 0: correlation (writes out[k]), 1: adjoint (accumulates into out)
+    const float2 *dhat;   // mode 0: density spectrum
+    const float2 *kc;     // compact kernels [k][np][plane]
+    float2 *out;          // mode 0: [k][ng]; mode 1: accumulator [ng]
+    const float2 *vin;    // mode 1: [b][ng] arrays already transformed along the other axes
+    int nb;               // kernels per group (mode 0: per grid.y; mode 1: in this launch)
+    int groups;           // grid.y (mode 0: kernel groups; mode 1: 1)
+    int kfirst;           // mode 1: index of the first kernel of this launch
+    const float2 *tw;
+};
+hipError_t launch_axis0(const Axis0Args &a, hipStream_t s);
+
+// Last inverse pass (contiguous axis) fused with the two-coefficient contraction.
+struct LastArgs {
+    int n;                // last-axis length
+    int64_t ng;
+    const float2 *in;     // [group][b][ng] arrays transformed along every other axis
+    const float *w;       // density (float32)
+    int nb;               // bins
+    int groups;           // coefficient groups (grid.y)
+    int rows;             // rows per tile (P = nb * rows pencils)
+    int64_t rows_per_block;
+    int nblocks;
+    int want_imag;
+    double *partial;      // [group][value][block], value = b1 <= b2 pair (then imaginary parts)
+    const float2 *tw;
+};
+hipError_t launch_last_contract(const LastArgs &a, hipStream_t s);
 
 }  // namespace sb

@@ -13,7 +13,8 @@ constexpr int kMaxLM = (kMaxL + 1) * (kMaxL + 2) / 2;       // (l, m >= 0) pairs
 struct KgenArgs {
     int ndim;
     int64_t n[3];
-    int64_t ng;
+    int64_t ng;                  // cells written per kernel: np * (product of the extents after axis 0)
+    int np, r0;                  // stored axis-0 planes: index p <= r0 -> p, above -> n0 - (np - p)
     int nbins;
     int64_t thr[kMaxBins + 1];   // floor(e_b^2), exact
     int lmax;                    // 3D lmax or 2D mmax
@@ -22,6 +23,8 @@ struct KgenArgs {
     float scale;                 // 1 / N_g
     float2 *out;                 // nlm * nbins arrays of ng cells, array k = lm * nbins + b
 };
+// Axis-0 planes kept for a kernel support of radius r0 (|c_0| <= r0) on an axis of n cells.
+inline int support_planes(int64_t n, int64_t r0) { return (int)((2 * r0 + 1 >= n) ? n : 2 * r0 + 1); }
 hipError_t launch_kgen(const KgenArgs &a, hipStream_t s);
 
 // ---- two-coefficient contraction (3PCF): block partials of

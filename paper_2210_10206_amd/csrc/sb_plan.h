@@ -18,13 +18,19 @@ enum Stage : int { STAGE_FFT = 0, STAGE_CONTRACT = 1, STAGE_OTHER = 2, STAGE_COU
 struct ShapeGroup {
     int64_t n[3] = {1, 1, 1};
     int64_t ng = 0;
+    int64_t plane = 0;            // cells per axis-0 plane
+    int np = 0, r0 = 0;           // stored axis-0 planes of the kernels, support radius along axis 0
+    int rows = 0;                 // rows per tile of the fused last pass (0: not available)
+    int64_t rows_per_block = 0;
     std::vector<int> fields;
     size_t khat_off = 0;          // byte offset of this shape's kernel spectra in the persistent buffer
     int64_t counts[kMaxBins] = {};
 };
 
+enum KernelId : int { K_FFT = 0, K_AXIS0 = 1, K_LAST = 2, K_PAIR = 3, K_QUAD = 4, K_PROJ4 = 5, K_ADJPREP = 6 };
+
 struct TimedLaunch {
-    int stage;
+    int stage, kernel;
     int fft_n, fft_sign, batch;
     double bytes, flops;
     hipEvent_t a, b;
@@ -67,6 +73,7 @@ struct sb_plan {
     bool prepared = false;
     // launch shapes (autotuned)
     int cpb_pair = 8192, cpb_quad = 1024, cpb_proj4 = 4096;
+    bool fused = true;            // fused last pass + contraction for the 3PCFs (flag SB_FLAG_UNFUSED clears it)
     int quad_tile = 32, proj4_tile = 64;
     std::map<std::pair<int, int>, int> fft_var;   // (length, axis) -> variant
     int fft_variant(int n, int axis) const {
@@ -77,10 +84,10 @@ struct sb_plan {
     bool timing = false;
     std::vector<sb::TimedLaunch> timed;
     template <class F>
-    hipError_t timed_launch(int stage, hipStream_t s, F &&fn, int fft_n = 0, int fft_sign = 0, int batch = 0,
-                            double bytes = 0.0, double flops = 0.0) {
+    hipError_t timed_launch(int stage, int kernel, hipStream_t s, F &&fn, int fft_n = 0, int fft_sign = 0,
+                            int batch = 0, double bytes = 0.0, double flops = 0.0) {
         if (!timing) return fn();
-        sb::TimedLaunch t{stage, fft_n, fft_sign, batch, bytes, flops, nullptr, nullptr};
+        sb::TimedLaunch t{stage, kernel, fft_n, fft_sign, batch, bytes, flops, nullptr, nullptr};
         if (hipEventCreate(&t.a) != hipSuccess || hipEventCreate(&t.b) != hipSuccess) return fn();
         (void)hipEventRecord(t.a, s);
         const hipError_t e = fn();
@@ -117,7 +124,13 @@ sb_status hip_fail(hipError_t e, const char *what);
 sb_status forward(sb_plan *p, const void *const *delta, double *zeta, hipStream_t s);
 sb_status coefficients(sb_plan *p, int f, const void *delta, hipStream_t s);
 sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s);
-sb_status fft_axis_passes(sb_plan *p, const ShapeGroup &G, int sign, int first_load, const void *in, int64_t in_bs,
-                          const float2 *in2, int64_t in2_bs, float2 *out, int64_t out_bs, int batch,
-                          hipStream_t s, int store, const float2 *mul, int64_t mul_bs, float2 *final_out);
+// FFT passes over the listed axes (in order) of arrays with extents n[0..ndim) and ncell
+// cells; the first pass reads `in` with load mode `first_load`, later passes work in place
+// on `out`; the last pass stores with `store` into final_out (or out).
+sb_status fft_axes(sb_plan *p, const int64_t *n, int ndim, int64_t ncell, const int *axes, int naxes, int sign,
+                   int first_load, const void *in, int64_t in_bs, float2 *out, int64_t out_bs, int batch,
+                   hipStream_t s, int store = STORE_C, const float2 *mul = nullptr, int64_t mul_bs = 0,
+                   float2 *final_out = nullptr);
+sb_status fft_all_axes(sb_plan *p, const ShapeGroup &G, int sign, int first_load, const void *in, int64_t in_bs,
+                       float2 *out, int64_t out_bs, int batch, hipStream_t s);
 }  // namespace sb

@@ -40,9 +40,9 @@ def sb():
     return api
 
 
-def run_plan(api, fields, edges, lmax, npcf=3, dtype=torch.float32, graph=False, precision="fp32"):
+def run_plan(api, fields, edges, lmax, npcf=3, dtype=torch.float32, graph=False, precision="fp32", **kw):
     shapes = [f.shape for f in fields]
-    plan = api.Plan(shapes, edges, lmax, npcf=npcf, input_dtype=dtype, precision=precision)
+    plan = api.Plan(shapes, edges, lmax, npcf=npcf, input_dtype=dtype, precision=precision, **kw)
     dev = [torch.from_numpy(np.ascontiguousarray(f)).to(device="cuda", dtype=dtype) for f in fields]
     if graph:
         s = torch.cuda.Stream()
@@ -76,7 +76,7 @@ def test_c1_coefficients_match_oracle(sb):
     say("case: 32^3 coefficients a^b_lm at sampled cells")
     d = lognormal_field((32, 32, 32), seed=0, sigma=1.0, dtype=np.float64)
     edges = linear_edges(8, 4)
-    plan, dev, z = run_plan(sb, [d], edges, 4, dtype=torch.float64)
+    plan, dev, z = run_plan(sb, [d], edges, 4, dtype=torch.float64, keep_coeffs=True)
     rng = np.random.Generator(np.random.PCG64(7))
     cells = rng.choice(d.size, 64, replace=False)
     ref = oracle.coeffs_full(d, edges, 4, cells=cells)   # (ncell, nb, (lmax+1)^2)
@@ -91,6 +91,18 @@ def test_c1_coefficients_match_oracle(sb):
                 worst = max(worst, float(np.max(np.abs(a - r)) / scale))
     say(f"  coefficient err (rel. to max |a| per bin) = {worst:.3e}")
     assert worst < 2e-6
+    plan.close()
+
+
+def test_unfused_path_matches_oracle(sb):
+    say("case: 32^3 unfused path (coefficients written, separate contraction), 4 bins to 8, lmax 4")
+    d = lognormal_field((32, 32, 32), seed=0, sigma=1.0)
+    edges = linear_edges(8, 4)
+    plan, dev, z = run_plan(sb, [d], edges, 4, fused=False)
+    ref = oracle.zeta3_full(d.astype(np.float64), edges, 4)
+    err = rel_err(z[0], ref.real)
+    say(f"  err={err:.3e}")
+    assert err < TOL32
     plan.close()
 
 
