@@ -98,57 +98,54 @@ template <int N, int TPP, int NT, int... RAD>
 __global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
     constexpr int P = NT / TPP;
     constexpr int PITCH = P + 1;
-    constexpr int EPT = N * P / NT;   // tile elements owned per thread
+    constexpr int EPT = N / TPP;      // tile elements per thread: pencil p, rows q0 + e TPP
     __shared__ float2 sm[N * PITCH];
     __shared__ float2 tw[N];
     const int tid = threadIdx.x;
-    const int64_t g0 = (int64_t)blockIdx.x * P;
+    const int p = tid % P, q0 = tid / P;
+    const int64_t g = (int64_t)blockIdx.x * P + p;
+    const bool ok = g < a.plane;
     for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
-    // ownership: element e of thread tid is (p, j) = (f % P, f / P), f = tid + e NT
-    int own_p[EPT], own_j[EPT], own_pl[EPT];
-    bool own_ok[EPT];
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-        const int f = tid + e * NT;
-        own_p[e] = f % P;
-        own_j[e] = f / P;
-        own_ok[e] = (g0 + own_p[e]) < a.plane;
-        const int j = own_j[e];
-        int pl = -1;
-        if (a.np == N) pl = j;
-        else if (j <= a.r0) pl = j;
-        else if (j >= N - a.r0) pl = a.np - (N - j);
-        own_pl[e] = pl;
-    }
     const int64_t kstride = (int64_t)a.np * a.plane;
+    // stored plane of axis-0 row j (-1: outside the kernel support)
+    auto plane_of = [&](int j) -> int {
+        if (a.np == N || j <= a.r0) return j;
+        if (j >= N - a.r0) return a.np - (N - j);
+        return -1;
+    };
+    auto load_kernel = [&](int64_t k, float2 *dst) {
+        const float2 *kc = a.kc + k * kstride;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int pl = plane_of(q0 + e * TPP);
+            dst[e] = (ok && pl >= 0) ? kc[(int64_t)pl * a.plane + g] : make_float2(0.f, 0.f);
+        }
+    };
+    float2 nx[EPT];
     if (a.mode == 0) {
         float2 dr[EPT];
 #pragma unroll
-        for (int e = 0; e < EPT; ++e)
-            dr[e] = own_ok[e] ? a.dhat[(int64_t)own_j[e] * a.plane + g0 + own_p[e]] : make_float2(0.f, 0.f);
+        for (int e = 0; e < EPT; ++e) dr[e] = ok ? a.dhat[(int64_t)(q0 + e * TPP) * a.plane + g] : make_float2(0.f, 0.f);
         const int64_t kbase = (int64_t)blockIdx.y * a.nb;
+        load_kernel(kbase, nx);
         for (int b = 0; b < a.nb; ++b) {
             __syncthreads();
-            const float2 *kc = a.kc + (kbase + b) * kstride;
 #pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                float2 v = make_float2(0.f, 0.f);
-                if (own_ok[e] && own_pl[e] >= 0) v = kc[(int64_t)own_pl[e] * a.plane + g0 + own_p[e]];
-                sm[own_j[e] * PITCH + own_p[e]] = v;
-            }
+            for (int e = 0; e < EPT; ++e) sm[(q0 + e * TPP) * PITCH + p] = nx[e];
+            if (b + 1 < a.nb) load_kernel(kbase + b + 1, nx);   // in flight during the transforms
             __syncthreads();
-            stages<N, TPP, -1, 1, RAD...>(sm, tw, tid % P, tid / P, PITCH);
+            stages<N, TPP, -1, 1, RAD...>(sm, tw, p, q0, PITCH);
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
-                float2 *x = &sm[own_j[e] * PITCH + own_p[e]];
+                float2 *x = &sm[(q0 + e * TPP) * PITCH + p];
                 *x = cmul(*x, dr[e]);
             }
             __syncthreads();
-            stages<N, TPP, 1, 1, RAD...>(sm, tw, tid % P, tid / P, PITCH);
+            stages<N, TPP, 1, 1, RAD...>(sm, tw, p, q0, PITCH);
             float2 *out = a.out + (kbase + b) * a.ng;
+            if (ok)
 #pragma unroll
-            for (int e = 0; e < EPT; ++e)
-                if (own_ok[e]) out[(int64_t)own_j[e] * a.plane + g0 + own_p[e]] = sm[own_j[e] * PITCH + own_p[e]];
+                for (int e = 0; e < EPT; ++e) out[(int64_t)(q0 + e * TPP) * a.plane + g] = sm[(q0 + e * TPP) * PITCH + p];
         }
     } else {
         float2 acc[EPT];
@@ -159,30 +156,25 @@ __global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
             const float2 *vb = a.vin + (int64_t)b * a.ng;
 #pragma unroll
             for (int e = 0; e < EPT; ++e)
-                sm[own_j[e] * PITCH + own_p[e]] =
-                    own_ok[e] ? vb[(int64_t)own_j[e] * a.plane + g0 + own_p[e]] : make_float2(0.f, 0.f);
+                sm[(q0 + e * TPP) * PITCH + p] = ok ? vb[(int64_t)(q0 + e * TPP) * a.plane + g] : make_float2(0.f, 0.f);
+            load_kernel(a.kfirst + b, nx);
             __syncthreads();
-            stages<N, TPP, -1, 1, RAD...>(sm, tw, tid % P, tid / P, PITCH);
+            stages<N, TPP, -1, 1, RAD...>(sm, tw, p, q0, PITCH);
             float2 vr[EPT];
 #pragma unroll
-            for (int e = 0; e < EPT; ++e) vr[e] = sm[own_j[e] * PITCH + own_p[e]];
+            for (int e = 0; e < EPT; ++e) vr[e] = sm[(q0 + e * TPP) * PITCH + p];
             __syncthreads();
-            const float2 *kc = a.kc + (int64_t)(a.kfirst + b) * kstride;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) sm[(q0 + e * TPP) * PITCH + p] = nx[e];
+            __syncthreads();
+            stages<N, TPP, -1, 1, RAD...>(sm, tw, p, q0, PITCH);
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) acc[e] = cadd(acc[e], cmul(vr[e], sm[(q0 + e * TPP) * PITCH + p]));
+        }
+        if (ok)
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
-                float2 v = make_float2(0.f, 0.f);
-                if (own_ok[e] && own_pl[e] >= 0) v = kc[(int64_t)own_pl[e] * a.plane + g0 + own_p[e]];
-                sm[own_j[e] * PITCH + own_p[e]] = v;
-            }
-            __syncthreads();
-            stages<N, TPP, -1, 1, RAD...>(sm, tw, tid % P, tid / P, PITCH);
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) acc[e] = cadd(acc[e], cmul(vr[e], sm[own_j[e] * PITCH + own_p[e]]));
-        }
-#pragma unroll
-        for (int e = 0; e < EPT; ++e)
-            if (own_ok[e]) {
-                float2 *o = a.out + (int64_t)own_j[e] * a.plane + g0 + own_p[e];
+                float2 *o = a.out + (int64_t)(q0 + e * TPP) * a.plane + g;
                 *o = cadd(*o, acc[e]);
             }
     }
@@ -235,7 +227,7 @@ hipError_t launch_fft_pass(const FftPass &a, hipStream_t s) {
 hipError_t launch_axis0(const Axis0Args &a, hipStream_t s) {
     switch (a.n) {
 #define SB_X(N, TPP, NT, ...) case N: return launch_axis0_t<N, TPP, NT, __VA_ARGS__>(a, s);
-        SB_FFT_CONFIGS(SB_X)
+        SB_FUSED_CONFIGS(SB_X)
 #undef SB_X
         default: return hipErrorInvalidValue;
     }
@@ -244,14 +236,14 @@ hipError_t launch_axis0(const Axis0Args &a, hipStream_t s) {
 int fft_threads_per_pencil(int n) {
     switch (n) {
 #define SB_X(N, TPP, NT, ...) case N: return TPP;
-        SB_FFT_CONFIGS(SB_X)
+        SB_FUSED_CONFIGS(SB_X)
 #undef SB_X
         default: return 0;
     }
 }
 
 hipError_t launch_last_contract(const LastArgs &a, hipStream_t s) {
-    if (a.nb * a.rows * fft_threads_per_pencil(a.n) > 1024) return hipErrorInvalidValue;
+    if (a.nb * a.rows * fft_threads_per_pencil(a.n) > 512) return hipErrorInvalidValue;
     switch (a.n) {
 #define SB_X(N, TPP, NT, ...) case N: return launch_last_for<N>(a, s);
         SB_FFT_CONFIGS(SB_X)

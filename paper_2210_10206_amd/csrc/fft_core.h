@@ -161,6 +161,16 @@ __device__ __forceinline__ double wave_sum64(double v) {
     X(128, 16, 256, 8, 8, 2) X(160, 4, 64, 4, 8, 5) X(192, 8, 128, 8, 8, 3)                  \
     X(256, 16, 256, 8, 8, 4) X(512, 32, 256, 8, 8, 8)
 
+// Shape of the fused passes (axis-0 correlation, last pass + contraction): more threads
+// per pencil than the plain passes, so that each thread holds at most ~12 elements and
+// the extra live state of the fusion (prefetch buffer, density spectrum, pair totals)
+// fits the register file: (length, threads per pencil, axis-0 workgroup threads, radices).
+#define SB_FUSED_CONFIGS(X)                                                                  \
+    X(8, 1, 64, 8) X(12, 1, 64, 4, 3) X(16, 4, 64, 4, 4) X(24, 2, 128, 4, 2, 3)              \
+    X(32, 4, 64, 4, 8) X(48, 4, 64, 4, 4, 3) X(64, 8, 128, 8, 8) X(96, 8, 128, 4, 4, 2, 3)   \
+    X(128, 16, 256, 8, 8, 2) X(160, 8, 128, 4, 4, 2, 5) X(192, 16, 256, 4, 4, 4, 3)          \
+    X(256, 32, 512, 8, 8, 4) X(512, 64, 512, 8, 8, 8)
+
 // Fused last pass + contraction for one length (defined in fft_last_*.hip).
 template <int N> hipError_t launch_last_for(const LastArgs &a, hipStream_t s);
 

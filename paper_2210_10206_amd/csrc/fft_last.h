@@ -14,9 +14,10 @@ using namespace fftcore;
 // w(x) A^b1 conj(A^b2) for b1 <= b2 to float32 per-thread totals; the coefficient
 // arrays are never written.  Block totals are combined in float64.
 template <int N, int TPP, int NBT, bool IMAG, int... RAD>
-__global__ __launch_bounds__(1024) void last_contract_kernel(LastArgs a) {
+__global__ __launch_bounds__(512) void last_contract_kernel(LastArgs a) {
     constexpr int NPT = NBT * (NBT + 1) / 2;
     constexpr int NACC = NPT * (IMAG ? 2 : 1);
+    constexpr int EPT = N / TPP;      // tile elements loaded per thread (P N / (P TPP))
     extern __shared__ float2 smem[];
     const int nb = a.nb, R = a.rows;
     const int P = nb * R, pitch = P + 1;
@@ -32,16 +33,26 @@ __global__ __launch_bounds__(1024) void last_contract_kernel(LastArgs a) {
     const int64_t r_begin = (int64_t)blockIdx.x * a.rows_per_block;
     const int64_t r_end = min(r_begin + a.rows_per_block, nrows);
     const float2 *in = a.in + (int64_t)blockIdx.y * nb * a.ng;
+    // element e of the load pattern: f = tid + e NT, pencil pp = f / N (bin pp / R, row pp % R), column f % N
+    auto load_tile = [&](int64_t row0, float2 *dst) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int f = tid + e * NT;
+            const int pp = f / N, j = f % N;
+            const int64_t row = row0 + pp % R;
+            dst[e] = row < r_end ? in[(int64_t)(pp / R) * a.ng + row * N + j] : make_float2(0.f, 0.f);
+        }
+    };
+    float2 nx[EPT];
+    if (r_begin < r_end) load_tile(r_begin, nx);
     for (int64_t row0 = r_begin; row0 < r_end; row0 += R) {
         __syncthreads();
-        for (int f = tid; f < P * N; f += NT) {
-            const int pp = f / N, j = f % N;
-            const int b = pp / R, r = pp % R;
-            const int64_t row = row0 + r;
-            float2 v = make_float2(0.f, 0.f);
-            if (row < r_end) v = in[(int64_t)b * a.ng + row * N + j];
-            sm[j * pitch + pp] = v;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int f = tid + e * NT;
+            sm[(f % N) * pitch + f / N] = nx[e];
         }
+        if (row0 + R < r_end) load_tile(row0 + R, nx);     // next tile in flight during this one
         __syncthreads();
         stages<N, TPP, 1, 1, RAD...>(sm, tw, tid % P, tid / P, pitch);
         for (int c = tid; c < R * N; c += NT) {

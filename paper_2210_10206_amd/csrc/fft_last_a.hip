@@ -1,4 +1,5 @@
-// Fused last pass + contraction: instantiations for lengths 8, 12, 16, 24, 32, 48.
+// Fused last pass + contraction: instantiations for lengths 8, 12, 16, 24, 32, 48
+// (shapes of SB_FUSED_CONFIGS).
 #include "fft_last.h"
 
 namespace sb {

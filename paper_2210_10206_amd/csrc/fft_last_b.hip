@@ -1,4 +1,5 @@
-// Fused last pass + contraction: instantiations for lengths 64, 96, 128.
+// Fused last pass + contraction: instantiations for lengths 64, 96, 128
+// (shapes of SB_FUSED_CONFIGS).
 #include "fft_last.h"
 
 namespace sb {
@@ -8,7 +9,7 @@ template <> hipError_t launch_last_for<64>(const LastArgs &a, hipStream_t s) {
 }
 
 template <> hipError_t launch_last_for<96>(const LastArgs &a, hipStream_t s) {
-    return fftlast::launch_last_nb<96, 4, 4, 8, 3>(a, s);
+    return fftlast::launch_last_nb<96, 8, 4, 4, 2, 3>(a, s);
 }
 
 template <> hipError_t launch_last_for<128>(const LastArgs &a, hipStream_t s) {

@@ -1,10 +1,11 @@
-// Fused last pass + contraction: instantiations for lengths 256.
+// Fused last pass + contraction: instantiations for lengths 256
+// (shapes of SB_FUSED_CONFIGS).
 #include "fft_last.h"
 
 namespace sb {
 
 template <> hipError_t launch_last_for<256>(const LastArgs &a, hipStream_t s) {
-    return fftlast::launch_last_nb<256, 16, 8, 8, 4>(a, s);
+    return fftlast::launch_last_nb<256, 32, 8, 8, 4>(a, s);
 }
 
 }  // namespace sb

@@ -319,13 +319,13 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
         G.khat_off = pers;
         pers += align256((size_t)p->nk * G.np * G.plane * sizeof(float2));
         // fused last pass: rows per tile so that nb * rows pencils of tpp threads fill whole
-        // waves (>= 256 threads when possible) within 1024 threads and 96 KB of LDS
+        // waves (>= 256 threads when possible) within 512 threads and 96 KB of LDS
         const int nl = (int)G.n[prob->ndim - 1];
         const int tpp = fft_threads_per_pencil(nl);
         G.rows = 0;
         for (int R = 1; R <= 64 && tpp > 0; ++R) {
             const int nt = NB * R * tpp;
-            if (nt > 1024) break;
+            if (nt > 512) break;
             const size_t lds = (size_t)(nl * (NB * R + 1) + nl) * sizeof(float2);
             if (lds > 98304) break;
             if (nt % 64) continue;
