@@ -188,6 +188,78 @@ hipError_t launch_axis0_t(const Axis0Args &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Persistent form of the plain pass (complex in, complex out): a workgroup walks
+// `tiles` consecutive tiles and loads tile t + 1 into registers while tile t is
+// transformed, so the memory pipe stays busy across the LDS stages.
+template <int N, int TPP, int NT, int SIGN, int... RAD>
+__global__ __launch_bounds__(NT) void fft_pass_pf_kernel(FftPass a, int tiles) {
+    constexpr int P = NT / TPP;
+    constexpr int PITCH = P + 1;
+    constexpr int EPT = N / TPP;
+    __shared__ float2 sm[N * PITCH];
+    __shared__ float2 tw[N];
+    const int tid = threadIdx.x;
+    const int y = blockIdx.y;
+    const int64_t npencil = a.ng / N;
+    const int64_t ntile = (npencil + P - 1) / P;
+    const float2 *in = reinterpret_cast<const float2 *>(a.in) + y * a.in_bs;
+    float2 *out = a.out + y * a.out_bs;
+    for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
+    const bool rows = a.stride == 1;
+    // element e of thread tid: f = tid + e NT -> (pencil, column) by the coalesced pattern
+    auto elem = [&](int e, int &p, int &j) {
+        const int f = tid + e * NT;
+        if (rows) { p = f / N; j = f % N; } else { p = f % P; j = f / P; }
+    };
+    auto addr = [&](int64_t g, int j) -> int64_t {
+        return (g / a.stride) * (int64_t)N * a.stride + (g % a.stride) + (int64_t)j * a.stride;
+    };
+    const int64_t t0 = (int64_t)blockIdx.x * tiles;
+    const int64_t t1 = min(t0 + tiles, ntile);
+    float2 nx[EPT];
+    auto load = [&](int64_t t) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            int p, j;
+            elem(e, p, j);
+            const int64_t g = t * P + p;
+            nx[e] = g < npencil ? in[addr(g, j)] : make_float2(0.f, 0.f);
+        }
+    };
+    if (t0 < t1) load(t0);
+    for (int64_t t = t0; t < t1; ++t) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            int p, j;
+            elem(e, p, j);
+            sm[j * PITCH + p] = nx[e];
+        }
+        if (t + 1 < t1) load(t + 1);
+        __syncthreads();
+        stages<N, TPP, SIGN, 1, RAD...>(sm, tw, tid % P, tid / P, PITCH);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            int p, j;
+            elem(e, p, j);
+            const int64_t g = t * P + p;
+            if (g < npencil) out[addr(g, j)] = sm[j * PITCH + p];
+        }
+    }
+}
+
+template <int N, int TPP, int NT, int... RAD>
+hipError_t launch_pf(const FftPass &a, hipStream_t s, int tiles) {
+    constexpr int P = NT / TPP;
+    const int64_t ntile = (a.ng / N + P - 1) / P;
+    dim3 grid((unsigned)((ntile + tiles - 1) / tiles), (unsigned)a.batch);
+    if (a.sign < 0)
+        hipLaunchKernelGGL((fft_pass_pf_kernel<N, TPP, NT, -1, RAD...>), grid, dim3(NT), 0, s, a, tiles);
+    else
+        hipLaunchKernelGGL((fft_pass_pf_kernel<N, TPP, NT, 1, RAD...>), grid, dim3(NT), 0, s, a, tiles);
+    return hipGetLastError();
+}
+
 template <int N, int TPP, int NT, int... RAD>
 hipError_t launch(const FftPass &a, hipStream_t s) {
     constexpr int P = NT / TPP;
@@ -206,6 +278,16 @@ hipError_t launch(const FftPass &a, hipStream_t s) {
 // The variants are the autotuner's candidates.
 hipError_t launch_fft_pass(const FftPass &a, hipStream_t s) {
     const int v = a.variant;
+    // variants 2 and 3: persistent passes with register prefetch (plain loads and stores only)
+    if (v >= 2 && a.load == LOAD_C && a.store == STORE_C) {
+        const int tiles = v == 2 ? 4 : 16;
+        switch (a.n) {
+#define SB_X(N, TPP, NT, ...) case N: return launch_pf<N, TPP, NT, __VA_ARGS__>(a, s, tiles);
+            SB_FFT_CONFIGS(SB_X)
+#undef SB_X
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (a.n) {
         case 8: return launch<8, 1, 64, 8>(a, s);
         case 12: return launch<12, 1, 64, 4, 3>(a, s);
@@ -242,8 +324,16 @@ int fft_threads_per_pencil(int n) {
     }
 }
 
+int fused_last_rows(int n, int nb) {
+    switch (n) {
+#define SB_X(N, TPP, ...) case N: return last_rows<N>(nb);
+        SB_LAST_CONFIGS(SB_X)
+#undef SB_X
+        default: return 0;
+    }
+}
+
 hipError_t launch_last_contract(const LastArgs &a, hipStream_t s) {
-    if (a.nb * a.rows * fft_threads_per_pencil(a.n) > 512) return hipErrorInvalidValue;
     switch (a.n) {
 #define SB_X(N, TPP, NT, ...) case N: return launch_last_for<N>(a, s);
         SB_FFT_CONFIGS(SB_X)
@@ -261,10 +351,8 @@ bool fft_supported(int n) {
 }
 
 int fft_num_variants(int n) {
-    switch (n) {
-        case 32: case 64: case 96: case 128: case 160: case 256: case 512: return 2;
-        default: return 1;
-    }
+    (void)n;
+    return 4;   // 0, 1: one tile per workgroup (two shapes where defined); 2, 3: persistent, 4 / 16 tiles
 }
 
 }  // namespace sb

@@ -171,7 +171,16 @@ __device__ __forceinline__ double wave_sum64(double v) {
     X(128, 16, 256, 8, 8, 2) X(160, 8, 128, 4, 4, 2, 5) X(192, 16, 256, 4, 4, 4, 3)          \
     X(256, 32, 512, 8, 8, 4) X(512, 64, 512, 8, 8, 8)
 
-// Fused last pass + contraction for one length (defined in fft_last_*.hip).
+// Threads per pencil of the fused last pass (the axis-0 pass uses SB_FUSED_CONFIGS):
+// at most 512 threads per workgroup for up to 16 bins.
+#define SB_LAST_CONFIGS(X)                                                                   \
+    X(8, 1, 8) X(12, 1, 4, 3) X(16, 4, 4, 4) X(24, 2, 4, 2, 3) X(32, 4, 4, 8) X(48, 4, 4, 4, 3) \
+    X(64, 8, 8, 8) X(96, 8, 4, 4, 2, 3) X(128, 16, 8, 8, 2) X(160, 8, 4, 4, 2, 5)              \
+    X(192, 16, 4, 4, 4, 3) X(256, 32, 8, 8, 4) X(512, 32, 8, 8, 8)
+
+// Fused last pass + contraction for one length (defined in fft_last_*.hip), and the
+// rows per tile it needs for nb bins.
 template <int N> hipError_t launch_last_for(const LastArgs &a, hipStream_t s);
+template <int N> int last_rows(int nb);
 
 }  // namespace sb

@@ -318,20 +318,9 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
         G.np = support_planes(G.n[0], G.r0);
         G.khat_off = pers;
         pers += align256((size_t)p->nk * G.np * G.plane * sizeof(float2));
-        // fused last pass: rows per tile so that nb * rows pencils of tpp threads fill whole
-        // waves (>= 256 threads when possible) within 512 threads and 96 KB of LDS
+        // fused last pass: rows per tile fixed by the kernel's compile-time tile shape
         const int nl = (int)G.n[prob->ndim - 1];
-        const int tpp = fft_threads_per_pencil(nl);
-        G.rows = 0;
-        for (int R = 1; R <= 64 && tpp > 0; ++R) {
-            const int nt = NB * R * tpp;
-            if (nt > 512) break;
-            const size_t lds = (size_t)(nl * (NB * R + 1) + nl) * sizeof(float2);
-            if (lds > 98304) break;
-            if (nt % 64) continue;
-            G.rows = R;
-            if (nt >= 256) break;
-        }
+        G.rows = NB <= kMaxBins ? fused_last_rows(nl, NB) : 0;
         if (G.rows > 0) {
             const int64_t nrows = G.ng / nl;
             int64_t rpb = (nrows + 1023) / 1024;

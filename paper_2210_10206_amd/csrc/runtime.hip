@@ -75,7 +75,6 @@ sb_status sb_autotune(sb_plan *p, void *stream) {
         for (int d = 0; d < p->prob.ndim; ++d) {
             const int n = (int)G.n[d];
             const int nv = fft_num_variants(n);
-            if (nv <= 1) continue;
             int64_t stride = 1;
             for (int k = d + 1; k < p->prob.ndim; ++k) stride *= G.n[k];
             float best = 1e30f;

@@ -90,5 +90,6 @@ struct LastArgs {
     const float2 *tw;
 };
 hipError_t launch_last_contract(const LastArgs &a, hipStream_t s);
+int fused_last_rows(int n, int nb);   // rows per tile the fused last pass uses (0: no kernel)
 
 }  // namespace sb
