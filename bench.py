@@ -73,16 +73,18 @@ def cpu_baseline(field, edges, lmax, target_s=10.0):
                       f"fields"}
 
 
-def run_4pcf_batch(api, steps, warmup, count=16):
+def run_4pcf_batch(api, steps, warmup, count=16, precision="fp32", mfma=True):
     """Full 4PCF of the 16-field 128^3 batch (sigma_i ~ U[0.5, 2]), 8 bins to 24, even
     Lambda with l <= 4, one plan and one forward per step; the fields/s of the batch and the
-    live rate of its dominant kernel (the 3j-coupled contraction)."""
+    live rate of its dominant kernel (the 3j-coupled contraction: on the matrix cores in
+    float32 or split-BF16, or the plain float32 vector-ALU kernel with mfma=False)."""
     import torch
     from fieldgen import c4_batch, linear_edges
     fields, _ = c4_batch(128, count)
     dev = [torch.from_numpy(f).cuda() for f in fields]
     stream = torch.cuda.Stream()
-    plan = api.Plan([f.shape for f in fields], linear_edges(24, 8), 4, npcf=4, prepare=False)
+    plan = api.Plan([f.shape for f in fields], linear_edges(24, 8), 4, npcf=4, prepare=False,
+                    precision=precision, mfma=mfma)
     with torch.cuda.stream(stream):
         plan.prepare(stream)
     out = torch.empty((len(dev), plan.zeta_doubles), dtype=torch.float64, device="cuda")
@@ -99,19 +101,26 @@ def run_4pcf_batch(api, steps, warmup, count=16):
     el = time.perf_counter() - t0
     recs = plan.launch_records()
     plan.profile(False)
-    q = [r for r in recs if r["kernel"] == 4]
+    q = [r for r in recs if r["kernel"] in (4, 7)]
     ms = sum(r["ms"] for r in q)
     fl = sum(r["flops"] for r in q)
+    if mfma:
+        kname = ("quad_mfma_kernel<la,lb,lc," + ("1> (split-BF16 MFMA" if precision == "split_bf16" else "0> (float32 MFMA")
+                 + ", one launch per canonical Lambda)")
+        peak = 2500.0 if precision == "split_bf16" else 157.3
+    else:
+        kname, peak = "quad_kernel (3j-coupled contraction, float32 VALU)", 157.3
     res = {"workload": f"full 4PCF, {count} lognormal 128^3 float32 fields (sigma ~ U[0.5,2]), 8 bins over (0,24], "
                        "even Lambda with l <= 4 (42)",
+           "precision": precision, "matrix_cores": bool(mfma),
            "value": round(count * steps / el, 3), "unit": "fields/s", "ms_per_step": round(el / steps * 1e3, 2),
-           "contraction": {"kernel": "quad_kernel (3j-coupled contraction, float32 VALU)",
+           "contraction": {"kernel": kname,
                            "achieved_tflops": round(fl / (ms * 1e-3) / 1e12, 2) if ms else None,
-                           "peak_tflops": 157.3, "frac": round(fl / (ms * 1e-3) / 1e12 / 157.3, 4) if ms else None,
+                           "peak_tflops": peak, "frac": round(fl / (ms * 1e-3) / 1e12 / peak, 4) if ms else None,
                            "ms_per_field": round(ms / (count * steps), 3)},
            "stage_ms_per_field": {}}
     for r in recs:
-        k = {0: "fft", 1: "fft", 4: "contract"}.get(r["kernel"], "other")
+        k = {0: "fft", 1: "fft", 4: "contract", 7: "contract"}.get(r["kernel"], "other")
         res["stage_ms_per_field"][k] = res["stage_ms_per_field"].get(k, 0.0) + r["ms"] / (count * steps)
     res["stage_ms_per_field"] = {k: round(v, 3) for k, v in res["stage_ms_per_field"].items()}
     plan.close()
@@ -124,7 +133,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--grid", type=int, default=256)
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip sb_autotune (the plain-pass variant choice) before the warmup")
     ap.add_argument("--graph", action="store_true", help="replay the forward from a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unfused", action="store_true", help="plain path: write the coefficients, then contract")
@@ -154,7 +164,7 @@ def main():
         plan.prepare(stream)
     stream.synchronize()
     cold_ms = (time.perf_counter() - t0) * 1e3
-    if args.autotune:
+    if not args.no_autotune:
         plan.autotune(stream)
     out = torch.empty((len(dev), plan.zeta_doubles), dtype=torch.float64, device="cuda")
     print("bench: warmup", file=sys.stderr, flush=True)
@@ -232,6 +242,13 @@ def main():
     if args.c4_steps > 0:
         print("bench: 128^3 4PCF batch", file=sys.stderr, flush=True)
         c4 = run_4pcf_batch(api, args.c4_steps, 1)
+        variants = {}
+        for prec, mf in (("split_bf16", True), ("fp32", False)):
+            r = run_4pcf_batch(api, args.c4_steps, 1, precision=prec, mfma=mf)
+            variants[f"{prec}_{'mfma' if mf else 'valu'}"] = {
+                "value": r["value"], "contraction_ms_per_field": r["contraction"]["ms_per_field"],
+                "achieved_tflops": r["contraction"]["achieved_tflops"], "kernel": r["contraction"]["kernel"]}
+        c4["other_contraction_paths"] = variants
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle sample)", file=sys.stderr, flush=True)
@@ -242,7 +259,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"full 3PCF, 2 lognormal {n}^3 float32 fields (sigma 0.5, 1.5), 10 bins over (0,32], "
                                f"lmax 6, kernel spectra resident", "grid": n, "nbins": nbins, "lmax": lmax,
-                   "batch": len(dev), "graph": bool(args.graph), "fused": not args.unfused},
+                   "batch": len(dev), "graph": bool(args.graph), "fused": not args.unfused,
+                   "autotuned": not args.no_autotune},
         "roofline": roof,
         "cpu_baseline": cpu,
         "cold_setup_ms": round(cold_ms, 1),

@@ -69,9 +69,11 @@ typedef enum { SB_IN_F32 = 0, SB_IN_F64 = 1 } sb_input_dtype;
 /* Flags */
 enum {
     SB_FLAG_KEEP_COEFFS = 1u, /* keep every a / c array of the last field in scratch (sb_coeffs) */
-    SB_FLAG_UNFUSED = 2u      /* 3PCFs: write every coefficient array, then contract in a separate
+    SB_FLAG_UNFUSED = 2u,     /* 3PCFs: write every coefficient array, then contract in a separate
                                  pass (the plain path; the default fuses the contraction into the
                                  last FFT pass and never writes the coefficients) */
+    SB_FLAG_NO_MFMA = 4u      /* full 4PCF: use the plain float32 vector-ALU contraction even where
+                                 the matrix-core one exists (lmax <= 4, nbins <= 8) */
 };
 
 /* Problem statement: the grid, bins, lmax, full or projected, 3 or 4 PCF
@@ -82,7 +84,12 @@ typedef struct {
     int32_t nbins;             /* 1 .. 16 */
     const double *bin_edges;   /* host, nbins + 1 values, strictly increasing, edges[0] >= 0 */
     int32_t lmax;              /* 3D: l = 0..lmax (<= 10); 2D: mmax, m = 0..mmax (<= 16) */
-    int32_t precision;         /* sb_precision: contraction arithmetic for the 4PCF paths */
+    int32_t precision;         /* sb_precision, the arithmetic of the full-4PCF contraction on the
+                                  matrix cores (lmax <= 4, nbins <= 8): SB_PREC_FP32 uses float32
+                                  MFMA, SB_PREC_SPLIT_BF16 bf16 MFMA on hi + lo splits of both
+                                  operands (hi*hi + hi*lo + lo*hi, float32 accumulation, about
+                                  1e-5 relative per product).  Every other contraction is float32
+                                  vector arithmetic whatever the value. */
     int32_t input_dtype;       /* sb_input_dtype of the density arrays */
     uint32_t flags;
 } sb_problem;

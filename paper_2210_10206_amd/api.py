@@ -45,7 +45,7 @@ class Plan:
     """
 
     def __init__(self, shapes, bin_edges, lmax, npcf=3, precision="fp32", input_dtype=torch.float32,
-                 device=None, stream=None, prepare=True, keep_coeffs=False, fused=True):
+                 device=None, stream=None, prepare=True, keep_coeffs=False, fused=True, mfma=True):
         self.lib = _lib.load()
         shapes = [tuple(int(x) for x in s) for s in shapes]
         ndim = len(shapes[0])
@@ -61,7 +61,8 @@ class Plan:
         self._prob = SbProblem(ndim, self.npcf, self.nbins,
                                self.edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.lmax, prec,
                                _lib.SB_IN_F64 if input_dtype == torch.float64 else _lib.SB_IN_F32,
-                               (_lib.SB_FLAG_KEEP_COEFFS if keep_coeffs else 0) | (0 if fused else _lib.SB_FLAG_UNFUSED))
+                               (_lib.SB_FLAG_KEEP_COEFFS if keep_coeffs else 0) | (0 if fused else _lib.SB_FLAG_UNFUSED)
+                               | (0 if mfma else _lib.SB_FLAG_NO_MFMA))
         sh = np.ascontiguousarray(np.array(shapes, dtype=np.int64).ravel())
         self._shapes_arr = sh
         handle = ctypes.c_void_p()

@@ -13,7 +13,7 @@ OUT = os.path.join(HERE, "libsarabande_hip.so")
 OBJ = os.path.join(HERE, "_build")
 ARCH = os.environ.get("SB_OFFLOAD_ARCH", "gfx950")
 
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+FLAGS = ["-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions stay off (the compiler would otherwise form them from float2 code)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument", "-I", INCLUDE, "-I", CSRC]

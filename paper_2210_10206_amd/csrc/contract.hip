@@ -340,4 +340,19 @@ hipError_t launch_to_f32(const void *in, int dtype, int64_t n, float *out, hipSt
     return hipGetLastError();
 }
 
+hipError_t launch_quad_mfma_part0(int la, int lb, int lc, const QuadMArgs &a, hipStream_t s);
+hipError_t launch_quad_mfma_part1(int la, int lb, int lc, const QuadMArgs &a, hipStream_t s);
+hipError_t launch_quad_mfma_part2(int la, int lb, int lc, const QuadMArgs &a, hipStream_t s);
+
+bool quad_mfma_available(int la, int lb, int lc, int nbins) {
+    return nbins <= 8 && la <= 4 && lb <= 4 && lc <= 4;
+}
+
+hipError_t launch_quad_mfma(int la, int lb, int lc, const QuadMArgs &a, hipStream_t s) {
+    if (!quad_mfma_available(la, lb, lc, a.nbins)) return hipErrorInvalidValue;
+    if (la <= 1) return launch_quad_mfma_part0(la, lb, lc, a, s);
+    if (la <= 3) return launch_quad_mfma_part1(la, lb, lc, a, s);
+    return launch_quad_mfma_part2(la, lb, lc, a, s);
+}
+
 }  // namespace sb

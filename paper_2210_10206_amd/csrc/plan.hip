@@ -242,14 +242,18 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
         }
         tw_off[n] = put(tw.data(), tw.size() * sizeof(float2));
     }
-    size_t off_terms = 0, off_tptr = 0, off_laml = 0, off_stage = 0, off_pairs = 0;
+    size_t off_terms = 0, off_tptr = 0, off_laml = 0, off_stage = 0, off_pairs = 0, off_coefw = 0;
     if (prob->npcf == 4 && prob->ndim == 3) {
         std::vector<QuadTerm> terms;
         std::vector<int> tptr(1, 0), laml, stage;
+        std::vector<float> coefw;
         p->max_cols = 0;
         for (size_t c = 0; c < p->f4.canon.size(); ++c) {
             const Lam &C = p->f4.canon[c];
+            p->coefw_off.push_back((int)coefw.size());
             for (const auto &t : p->f4.terms[c]) {
+                coefw.push_back((float)t.c);
+                if (t.c == 0.0) continue;   // the generic kernel skips vanishing symbols
                 QuadTerm q;
                 q.ma = t.ma; q.mb = t.mb; q.mc = t.mc;
                 q.c = (float)t.c;
@@ -278,6 +282,7 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
         off_tptr = put(tptr.data(), tptr.size() * sizeof(int));
         off_laml = put(laml.data(), laml.size() * sizeof(int));
         off_stage = put(stage.data(), stage.size() * sizeof(int));
+        off_coefw = put(coefw.data(), coefw.size() * sizeof(float));
     }
     if (prob->npcf == 4 && prob->ndim == 2) {
         std::vector<int> pr;
@@ -302,6 +307,9 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
         p->d_term_ptr = reinterpret_cast<const int *>(base + off_tptr);
         p->d_lam_l = reinterpret_cast<const int *>(base + off_laml);
         p->d_stage = reinterpret_cast<const int *>(base + off_stage);
+        p->d_coefw = reinterpret_cast<const float *>(base + off_coefw);
+        p->quad_mfma = (prob->flags & SB_FLAG_NO_MFMA) == 0;
+        for (const Lam &C : p->f4.canon) p->quad_mfma &= quad_mfma_available(C.l[0], C.l[1], C.l[2], prob->nbins);
     }
     if (prob->npcf == 4 && prob->ndim == 2) p->d_pairs = reinterpret_cast<const int *>(base + off_pairs);
     p->d_gptr = reinterpret_cast<const int *>(base + off_gptr);
@@ -571,14 +579,47 @@ sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
         a.nlm = p->nlm;
         a.partial = part;
         a.nblocks = nblocks;
-        double fl = 0.0;
-        for (size_t c = 0; c < p->f4.canon.size(); ++c) {
-            const double nt = (double)p->f4.terms[c].size();
-            fl += (double)NB * NB * (nt * 8.0 + (p->f4.canon[c].l[2] + 1) * (2.0 + 4.0 * NB));
+        // algorithmic flops per cell and Lambda: 8 per nonzero coupling term and bin pair, then
+        // per mc the weight (2) and the b3 contraction (4 per bin) for each bin pair
+        auto lam_flops = [&](size_t c) {
+            double nt = 0.0;
+            for (const auto &t : p->f4.terms[c]) nt += t.c != 0.0 ? 1.0 : 0.0;
+            return (double)NB * NB * (nt * 8.0 + (p->f4.canon[c].l[2] + 1) * (2.0 + 4.0 * NB));
+        };
+        if (p->quad_mfma) {
+            // one launch per canonical Lambda: its coefficients stay in registers
+            double by = 0.0;
+            for (size_t c = 0; c < p->f4.canon.size() && e == hipSuccess; ++c) {
+                const Lam &C = p->f4.canon[c];
+                QuadMArgs m{};
+                m.coef = coef;
+                m.w = w;
+                m.ng = G.ng;
+                m.nbins = NB;
+                m.lam = (int)c;
+                m.coefw = p->d_coefw + p->coefw_off[c];
+                m.cells_per_block = p->cpb_quad;
+                m.nblocks = nblocks;
+                m.precision = p->prob.precision == SB_PREC_SPLIT_BF16 ? 1 : 0;
+                m.partial = part;
+                int ncol = 0;
+                for (int q = 0; q < 3; ++q) {
+                    bool dup = false;
+                    for (int r = 0; r < q; ++r) dup |= C.l[r] == C.l[q];
+                    if (!dup) ncol += C.l[q] + 1;
+                }
+                by = (double)G.ng * (8.0 * NB * ncol + 4.0);
+                e = p->timed_launch(STAGE_CONTRACT, K_QUAD_MFMA, s,
+                                    [&]() { return launch_quad_mfma(C.l[0], C.l[1], C.l[2], m, s); }, 0, 0, 1, by,
+                                    (double)G.ng * lam_flops(c));
+            }
+        } else {
+            double fl = 0.0;
+            for (size_t c = 0; c < p->f4.canon.size(); ++c) fl += lam_flops(c);
+            fl *= (double)G.ng;
+            const double by = (double)G.ng * (8.0 * p->nk + 4.0);
+            e = p->timed_launch(STAGE_CONTRACT, K_QUAD, s, [&]() { return launch_quad_contract(a, s); }, 0, 0, groups, by, fl);
         }
-        fl *= (double)G.ng;
-        const double by = (double)G.ng * (8.0 * p->nk + 4.0);
-        e = p->timed_launch(STAGE_CONTRACT, K_QUAD, s, [&]() { return launch_quad_contract(a, s); }, 0, 0, groups, by, fl);
     } else {
         Proj4Args a{};
         a.coef = coef;

@@ -1,0 +1,212 @@
+// Full-4PCF contraction on the matrix cores, one kernel per ordered Lambda = (LA, LB, LC).
+//
+// For one Lambda, with mc >= 0 and the weighted 3j symbols C (factor 2 for mc > 0, Alg. 6):
+//   L_mc[b1 b2](x) = w(x) sum_ma C(ma, mb, mc) a^b1_{LA,ma}(x) a^b2_{LB,mb}(x),  mb = -ma - mc
+//   Z[b1 b2][b3]  += sum_x Re( L_mc[b1 b2](x) a^b3_{LC,mc}(x) )
+// The coupling (first line) runs on the vector ALUs with every coefficient index known at
+// compile time, so the per-lane coefficients stay in registers; the contraction over the
+// cells (second line) is a real GEMM with M = b1 b2 pairs (tiles of 16), N = b3 (padded to
+// 16) and K = (cell, re/im) that runs on MFMA:
+//   PREC 0: v_mfma_f32_16x16x4f32, K = the cells of the four lane groups, re and im in turn;
+//   PREC 1: v_mfma_f32_16x16x32_bf16 with both operands split into bf16 hi + lo parts and
+//           hi*hi + hi*lo + lo*hi accumulated in float32 (split-BF16).
+// Lane l of a wave is (i = l % 16, g = l / 16): row i of the A tile (pair 16 mt + i), column i
+// of the B tile (bin b3 = i), cells 4 g .. 4 g + 3 of the wave's 16-cell step.
+#pragma once
+#include <utility>
+#include "sb_kgen.h"
+
+namespace sb {
+namespace quadm {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+constexpr int kTileCells = 64;   // cells staged per LDS tile (16 per wave)
+constexpr int kMaxNB = 8;        // bins (pairs fill at most 4 tiles of 16)
+constexpr int kMT = 4;           // M tiles of 16 pairs
+
+// staged columns: distinct l values in the order LA, LB, LC; column = offset + m
+template <int LA, int LB, int LC> struct Cols {
+    static constexpr int offA = 0;
+    static constexpr int offB = (LB == LA) ? 0 : LA + 1;
+    static constexpr int offC = (LC == LA) ? 0 : (LC == LB ? offB : ((LB == LA) ? LA + 1 : LA + 1 + LB + 1));
+    static constexpr int ncol = (LB == LA ? LA + 1 : LA + 1 + LB + 1) + ((LC == LA || LC == LB) ? 0 : LC + 1);
+    static constexpr int lm_of(int col) {
+        return col < LA + 1 ? LA * (LA + 1) / 2 + col
+               : (LB != LA && col < LA + 1 + LB + 1) ? LB * (LB + 1) / 2 + (col - LA - 1)
+                                                      : LC * (LC + 1) / 2 + (col - offC);
+    }
+};
+
+// a_{l,m} for a signed m from the stored m >= 0 value: a_{l,-m} = (-1)^m conj(a_{l,m})
+template <int M>
+__device__ __forceinline__ float2 signed_m(float2 v) {
+    if constexpr (M >= 0) return v;
+    else if constexpr (((-M) & 1) == 0) return make_float2(v.x, -v.y);
+    else return make_float2(-v.x, v.y);
+}
+
+template <int LA, int LB, int MC, int MA, int T>
+struct Couple {
+    // accumulate the terms ma = MA .. LA of one mc into L; T = index of the term in the table
+    __device__ __forceinline__ static void run(const float *cw, const float2 *A1, const float2 *A2, float2 &L) {
+        if constexpr (MA > LA) {
+            return;
+        } else {
+            constexpr int MB = -MA - MC;
+            if constexpr (MB >= -LB && MB <= LB) {
+                const float c = cw[T];
+                const float2 x = signed_m<MA>(A1[MA >= 0 ? MA : -MA]);
+                const float2 y = signed_m<MB>(A2[MB >= 0 ? MB : -MB]);
+                L.x += c * (x.x * y.x - x.y * y.y);
+                L.y += c * (x.x * y.y + x.y * y.x);
+                Couple<LA, LB, MC, MA + 1, T + 1>::run(cw, A1, A2, L);
+            } else {
+                Couple<LA, LB, MC, MA + 1, T>::run(cw, A1, A2, L);
+            }
+        }
+    }
+};
+
+// number of terms with mc < MC (offset of mc's first term in the table)
+template <int LA, int LB> constexpr int terms_before(int MC) {
+    int t = 0;
+    for (int mc = 0; mc < MC; ++mc)
+        for (int ma = -LA; ma <= LA; ++ma) {
+            const int mb = -ma - mc;
+            if (mb >= -LB && mb <= LB) ++t;
+        }
+    return t;
+}
+
+__device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
+    hi = (__bf16)v;
+    lo = (__bf16)(v - (float)hi);
+}
+
+template <int LA, int LB, int LC, int PREC>
+__global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
+    using CL = Cols<LA, LB, LC>;
+    constexpr int NCOL = CL::ncol;
+    constexpr int TC = kTileCells;
+    __shared__ float2 tile[TC * NCOL * kMaxNB];
+    __shared__ float wt[TC];
+    __shared__ float red[4 * kMaxNB * kMaxNB * kMaxNB];
+    const int nb = a.nbins;
+    const int npair = nb * nb;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i = lane & 15, g = lane >> 4;
+    const float *cw = a.coefw;   // weighted 3j values of this Lambda, table order (mc outer, ma inner)
+    f4v acc[kMT];
+#pragma unroll
+    for (int mt = 0; mt < kMT; ++mt) acc[mt] = f4v{0.f, 0.f, 0.f, 0.f};
+    const int64_t c0 = (int64_t)blockIdx.x * a.cells_per_block;
+    const int64_t c1 = min(c0 + a.cells_per_block, a.ng);
+    for (int64_t tc = c0; tc < c1; tc += TC) {
+        const int ncell = (int)min((int64_t)TC, c1 - tc);
+        __syncthreads();
+        for (int f = tid; f < TC * NCOL * kMaxNB; f += 256) {
+            const int c = f % TC, kb = f / TC;
+            const int col = kb / kMaxNB, b = kb % kMaxNB;
+            float2 v = make_float2(0.f, 0.f);
+            if (c < ncell && b < nb) v = a.coef[((int64_t)CL::lm_of(col) * nb + b) * a.ng + tc + c];
+            tile[(c * NCOL + col) * kMaxNB + b] = v;
+        }
+        for (int c = tid; c < TC; c += 256) wt[c] = c < ncell ? a.w[tc + c] : 0.f;
+        __syncthreads();
+        // this lane's cells: 16 wave + 4 g + cc
+        const int cbase = 16 * wave + 4 * g;
+        // B operand: bin i of the LC coefficients, per mc and cell
+        float2 bv[LC + 1][4];
+#pragma unroll
+        for (int mc = 0; mc <= LC; ++mc)
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc)
+                bv[mc][cc] = i < kMaxNB ? tile[((cbase + cc) * NCOL + CL::offC + mc) * kMaxNB + i] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int mt = 0; mt < kMT; ++mt) {
+            if (16 * mt >= npair) break;
+            const int p = 16 * mt + i;
+            const bool ok = p < npair;
+            const int b1 = ok ? p / nb : 0, b2 = ok ? p % nb : 0;
+            float2 A1[4][LA + 1], A2[4][LB + 1];
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+                const float2 *row = tile + (cbase + cc) * NCOL * kMaxNB;
+                const float wv = ok ? wt[cbase + cc] : 0.f;
+#pragma unroll
+                for (int m = 0; m <= LA; ++m) {
+                    const float2 v = row[(CL::offA + m) * kMaxNB + b1];
+                    A1[cc][m] = make_float2(wv * v.x, wv * v.y);
+                }
+#pragma unroll
+                for (int m = 0; m <= LB; ++m) A2[cc][m] = row[(CL::offB + m) * kMaxNB + b2];
+            }
+            f4v &am = acc[mt];
+            // one mc: couple, then contract on the matrix cores (the mc loop is unrolled below)
+            auto step = [&](auto mc_c) {
+                constexpr int MC = decltype(mc_c)::value;
+                float2 L[4];
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc) {
+                    L[cc] = make_float2(0.f, 0.f);
+                    Couple<LA, LB, MC, -LA, terms_before<LA, LB>(MC)>::run(cw, A1[cc], A2[cc], L[cc]);
+                }
+                if constexpr (PREC == 0) {
+#pragma unroll
+                    for (int cc = 0; cc < 4; ++cc) {
+                        am = __builtin_amdgcn_mfma_f32_16x16x4f32(L[cc].x, bv[MC][cc].x, am, 0, 0, 0);
+                        am = __builtin_amdgcn_mfma_f32_16x16x4f32(-L[cc].y, bv[MC][cc].y, am, 0, 0, 0);
+                    }
+                } else {
+                    bf8v ah, al, bh, bl;
+#pragma unroll
+                    for (int cc = 0; cc < 4; ++cc) {
+                        __bf16 h, l;
+                        split_bf16(L[cc].x, h, l); ah[2 * cc] = h; al[2 * cc] = l;
+                        split_bf16(-L[cc].y, h, l); ah[2 * cc + 1] = h; al[2 * cc + 1] = l;
+                        split_bf16(bv[MC][cc].x, h, l); bh[2 * cc] = h; bl[2 * cc] = l;
+                        split_bf16(bv[MC][cc].y, h, l); bh[2 * cc + 1] = h; bl[2 * cc + 1] = l;
+                    }
+                    am = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, am, 0, 0, 0);
+                    am = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, am, 0, 0, 0);
+                    am = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, am, 0, 0, 0);
+                }
+            };
+            [&]<int... MCS>(std::integer_sequence<int, MCS...>) {
+                (step(std::integral_constant<int, MCS>{}), ...);
+            }(std::make_integer_sequence<int, LC + 1>{});
+        }
+    }
+    // accumulator tile mt: lane l holds rows 4 g + r (pair 16 mt + 4 g + r), column i (bin b3)
+    __syncthreads();
+    const int nv = npair * nb;
+    for (int v = tid; v < 4 * nv; v += 256) red[v] = 0.f;
+    __syncthreads();
+#pragma unroll
+    for (int mt = 0; mt < kMT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = 16 * mt + 4 * g + r;
+            if (p < npair && i < nb) red[wave * nv + p * nb + i] = acc[mt][r];
+        }
+    __syncthreads();
+    for (int v = tid; v < nv; v += 256) {
+        const double s = ((double)red[v] + (double)red[nv + v]) + ((double)red[2 * nv + v] + (double)red[3 * nv + v]);
+        a.partial[((int64_t)a.lam * nv + v) * a.nblocks + blockIdx.x] = s;
+    }
+}
+
+template <int LA, int LB, int LC>
+hipError_t launch_lambda(const QuadMArgs &a, hipStream_t s) {
+    dim3 grid((unsigned)a.nblocks);
+    if (a.precision == 1)
+        hipLaunchKernelGGL((quad_mfma_kernel<LA, LB, LC, 1>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((quad_mfma_kernel<LA, LB, LC, 0>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace quadm
+}  // namespace sb

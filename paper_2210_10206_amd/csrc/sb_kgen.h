@@ -72,6 +72,23 @@ struct QuadArgs {
 };
 hipError_t launch_quad_contract(const QuadArgs &a, hipStream_t s);
 
+// Matrix-core form for one ordered Lambda with l <= 4 and at most 8 bins (quad_mfma.h).
+struct QuadMArgs {
+    const float2 *coef;       // [lm][bin][ng]
+    const float *w;
+    int64_t ng;
+    int nbins;
+    int lam;                  // canonical index (partial layout)
+    const float *coefw;       // weighted 3j values of this Lambda in table order
+    int cells_per_block;
+    int nblocks;
+    int precision;            // 0 float32 MFMA, 1 split-BF16 MFMA
+    double *partial;          // [lam][nbins^3][block]
+};
+// Returns hipErrorInvalidValue when no kernel exists for (la, lb, lc).
+hipError_t launch_quad_mfma(int la, int lb, int lc, const QuadMArgs &a, hipStream_t s);
+bool quad_mfma_available(int la, int lb, int lc, int nbins);
+
 // ---- projected 4PCF: block partials of sum_x w c^{b1}_{m1} c^{b2}_{m2} c^{b3}_{m3} (complex)
 struct Proj4Args {
     const float2 *coef;       // [m][bin][ng], m >= 0

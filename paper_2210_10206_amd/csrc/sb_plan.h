@@ -27,7 +27,7 @@ struct ShapeGroup {
     int64_t counts[kMaxBins] = {};
 };
 
-enum KernelId : int { K_FFT = 0, K_AXIS0 = 1, K_LAST = 2, K_PAIR = 3, K_QUAD = 4, K_PROJ4 = 5, K_ADJPREP = 6 };
+enum KernelId : int { K_FFT = 0, K_AXIS0 = 1, K_LAST = 2, K_PAIR = 3, K_QUAD = 4, K_PROJ4 = 5, K_ADJPREP = 6, K_QUAD_MFMA = 7 };
 
 struct TimedLaunch {
     int stage, kernel;
@@ -73,6 +73,9 @@ struct sb_plan {
     bool prepared = false;
     // launch shapes (autotuned)
     int cpb_pair = 8192, cpb_quad = 1024, cpb_proj4 = 4096;
+    const float *d_coefw = nullptr;   // weighted 3j values, every term, per canonical Lambda
+    std::vector<int> coefw_off;
+    bool quad_mfma = false;       // full 4PCF contraction on the matrix cores (l <= 4, <= 8 bins)
     bool fused = true;            // fused last pass + contraction for the 3PCFs (flag SB_FLAG_UNFUSED clears it)
     int quad_tile = 32, proj4_tile = 64;
     std::map<std::pair<int, int>, int> fft_var;   // (length, axis) -> variant

@@ -83,8 +83,9 @@ static void terms_of(int la, int lb, int lc, std::vector<QuadTermH> *t) {
         for (int ma = -la; ma <= la; ++ma) {
             const int mb = -ma - mc;
             if (std::abs(mb) > lb) continue;
+            // zero symbols are kept: the matrix-core kernels walk the same (mc, ma) order at
+            // compile time and index this table by position
             const double w = wigner3j(la, lb, lc, ma, mb, mc);
-            if (w == 0.0) continue;
             t->push_back({ma, mb, mc, (mc == 0 ? 1.0 : 2.0) * w});
         }
 }

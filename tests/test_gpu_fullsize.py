@@ -77,12 +77,15 @@ def test_projected_512(api):
     p4.close()
 
 
-def test_full4pcf_128_batch_fields(api):
-    say("case: fields 0 and 1 of the 16-field 128^3 batch, 8 bins to 24, even Lambda, lmax 4")
+@pytest.mark.parametrize("precision,mfma,tol", [("fp32", True, TOL32), ("split_bf16", True, 3e-4),
+                                                ("fp32", False, TOL32)])
+def test_full4pcf_128_batch_fields(api, precision, mfma, tol):
+    say(f"case: fields 0 and 1 of the 16-field 128^3 batch, 8 bins to 24, even Lambda, lmax 4, "
+        f"{precision}, matrix cores {mfma}")
     gs = [golden(f"c4_full4_128_field{i}.npz") for i in (0, 1)]
     fields = [lognormal_field((128,) * 3, seed=i, sigma=float(gs[i]["sigma"])) for i in (0, 1)]
     edges = linear_edges(24, 8)
-    plan = api.Plan([f.shape for f in fields], edges, 4, npcf=4)
+    plan = api.Plan([f.shape for f in fields], edges, 4, npcf=4, precision=precision, mfma=mfma)
     z = plan.forward([torch.from_numpy(f).cuda() for f in fields]).cpu().numpy()
     torch.cuda.synchronize()
     assert [tuple(x) for x in plan.zeta_index()] == [tuple(x) for x in gs[0]["lams"]]
@@ -91,7 +94,7 @@ def test_full4pcf_128_batch_fields(api):
         assert np.max(np.abs(ref.imag)) < 1e-9 * np.max(np.abs(ref.real))
         e = rel_err(z[i], ref.real)
         say(f"  field {i}: err={e:.3e} (worst Lambda block {worst_block(z[i], ref.real):.3e})")
-        assert e < TOL32
+        assert e < tol
     plan.close()
 
 

@@ -183,13 +183,46 @@ def test_projected_small(sb):
 
 # ------------------------------------------------------------------ full 4PCF
 
-def test_full4pcf_small(sb):
-    say("case: 24^3 full 4PCF, 4 bins to 6, lmax 4")
+# split-BF16 keeps ~16 mantissa bits of each operand (the lo*lo term is dropped): 2^-16 per
+# product, which grows to a few 1e-5 on sums that cancel
+TOL_SPLIT = 3e-4
+
+
+@pytest.mark.parametrize("precision,mfma", [("fp32", True), ("split_bf16", True), ("fp32", False)])
+def test_full4pcf_small(sb, precision, mfma):
+    say(f"case: 24^3 full 4PCF, 4 bins to 6, lmax 4, {precision}, matrix cores {mfma}")
     d = lognormal_field((24, 24, 24), seed=4, sigma=1.0)
     edges = linear_edges(6, 4)
-    plan, dev, z = run_plan(sb, [d], edges, 4, npcf=4)
+    plan, dev, z = run_plan(sb, [d], edges, 4, npcf=4, precision=precision, mfma=mfma)
     lams, ref = oracle.zeta4_full(d.astype(np.float64), edges, 4)
     assert [tuple(x) for x in plan.zeta_index()] == lams
+    err = rel_err(z[0], ref.real)
+    say(f"  err={err:.3e}")
+    assert err < (TOL_SPLIT if precision == "split_bf16" else TOL32)
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_full4pcf_eight_bins_ragged_blocks(sb, precision):
+    # 8 bins fill all four 16-pair tiles; 12 x 16 x 24 = 4608 cells leave a half block
+    say(f"case: (12,16,24) full 4PCF, 8 bins to 5, lmax 4, {precision}")
+    d = lognormal_field((12, 16, 24), seed=6, sigma=1.0)
+    edges = linear_edges(5, 8)
+    plan, dev, z = run_plan(sb, [d], edges, 4, npcf=4, precision=precision)
+    lams, ref = oracle.zeta4_full(d.astype(np.float64), edges, 4)
+    err = rel_err(z[0], ref.real)
+    say(f"  err={err:.3e}")
+    assert err < (TOL_SPLIT if precision == "split_bf16" else TOL32)
+    plan.close()
+
+
+def test_full4pcf_lmax3_six_bins(sb):
+    # lmax 3: a different canonical Lambda set on the matrix-core path
+    say("case: 16^3 full 4PCF, 6 bins to 6, lmax 3")
+    d = lognormal_field((16, 16, 16), seed=8, sigma=1.0)
+    edges = linear_edges(6, 6)
+    plan, dev, z = run_plan(sb, [d], edges, 3, npcf=4)
+    lams, ref = oracle.zeta4_full(d.astype(np.float64), edges, 3)
     err = rel_err(z[0], ref.real)
     say(f"  err={err:.3e}")
     assert err < TOL32
