@@ -48,6 +48,65 @@ def traffic_for(kernel_key, src_files):
     return e.get("bytes_per_launch")
 
 
+TRAFFIC_SRCS = {0: ["paper_2210_10206_amd/csrc/fft.hip", "paper_2210_10206_amd/csrc/fft_core.h"],
+                1: ["paper_2210_10206_amd/csrc/fft.hip", "paper_2210_10206_amd/csrc/fft_core.h"],
+                2: ["paper_2210_10206_amd/csrc/fft_last.h", "paper_2210_10206_amd/csrc/fft_core.h"],
+                3: ["paper_2210_10206_amd/csrc/contract.hip"]}
+
+
+def write_traffic(counter_dir, n=256, copy_mib=1024, min_gib=4.0):
+    """Turn two rocprofv3 counter runs of `bench.py --steps 1 --copy-probe-mib <copy_mib>`
+    (counter_dir/FETCH_SIZE and counter_dir/WRITE_SIZE, csv output) into
+    profiles/traffic.json.  Each counter is scaled by bytes / counter of the plain
+    copy_mib MiB device copy in the same run (the __amd_rocclr_copyBuffer dispatches of that
+    size); the passes over all kernel arrays are the dispatches of each kernel family with at
+    least min_gib GiB of either counter, and of the middle pass only the variant the run
+    launched most often (the one the autotuner picked and the timed steps used)."""
+    import csv
+    import re
+    fams = {0: re.compile(rf"fft_pass(_pf)?_kernel<{n}, \d+, \d+, 1,"),
+            1: re.compile(rf"axis0_kernel<{n},"),
+            2: re.compile(rf"last_contract_kernel<{n},")}
+    raw = {}
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        path = os.path.join(counter_dir, ctr, "run_counter_collection.csv")
+        with open(path) as f:
+            raw[ctr] = {int(r["Dispatch_Id"]): (r["Kernel_Name"], float(r["Counter_Value"]))
+                        for r in csv.DictReader(f) if r["Counter_Name"] == ctr}
+    copy_bytes = copy_mib * 2 ** 20
+    scale = {}
+    for ctr, want in (("FETCH_SIZE", copy_bytes), ("WRITE_SIZE", copy_bytes)):
+        vals = sorted(v for name, v in raw[ctr].values() if "copyBuffer" in name)
+        big = [v for v in vals if v * 1024 > 0.25 * want]          # KiB -> bytes
+        if not big:
+            raise SystemExit(f"no {copy_mib} MiB copy dispatch in the {ctr} run")
+        scale[ctr] = want / (sum(big) / len(big) * 1024)
+    out = {"_note": f"HBM bytes per dispatch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB), each scaled by "
+                    f"bytes / counter of a plain {copy_mib} MiB device copy in the same run",
+           "_scale": {k: round(v, 4) for k, v in scale.items()}}
+    for k, rx in fams.items():
+        per_name = {}
+        for did, (name, fv) in raw["FETCH_SIZE"].items():
+            if not rx.search(name) or did not in raw["WRITE_SIZE"]:
+                continue
+            wv = raw["WRITE_SIZE"][did][1]
+            if max(fv, wv) * 1024 < min_gib * 2 ** 30:
+                continue
+            per_name.setdefault(name, []).append((fv, wv))
+        if not per_name:
+            continue
+        name = max(per_name, key=lambda q: len(per_name[q]))
+        v = per_name[name]
+        fetch = sum(x[0] for x in v) / len(v) * 1024 * scale["FETCH_SIZE"]
+        write = sum(x[1] for x in v) / len(v) * 1024 * scale["WRITE_SIZE"]
+        out[f"kernel{k}_n{n}"] = {"kernel": name, "dispatches": len(v), "fetch_bytes": round(fetch),
+                                  "write_bytes": round(write), "bytes_per_launch": round(fetch + write),
+                                  "source_hash": source_hash(TRAFFIC_SRCS[k])}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def cpu_baseline(field, edges, lmax, target_s=10.0):
     """Oracle throughput on a bounded sample of cells of field 0: two probe sizes give the
     per-cell rate without the oracle's one-off table set-up, then a sample sized for about
@@ -139,7 +198,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unfused", action="store_true", help="plain path: write the coefficients, then contract")
     ap.add_argument("--c4-steps", type=int, default=1, help="steps of the 128^3 4PCF batch (0 skips it)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB three times (the reference "
+                         "dispatch that scales the HBM byte counters of a counter run)")
+    ap.add_argument("--write-traffic", metavar="COUNTER_DIR",
+                    help="no GPU work: write profiles/traffic.json from two counter runs and exit")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(args.write_traffic, n=args.grid, copy_mib=1024)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
@@ -156,6 +223,13 @@ def main():
     print(f"bench: generating 2 lognormal {n}^3 fields", file=sys.stderr, flush=True)
     fields = [lognormal_field((n, n, n), seed=0, sigma=0.5), lognormal_field((n, n, n), seed=1, sigma=1.5)]
     dev = [torch.from_numpy(f).cuda() for f in fields]
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
     plan = api.Plan([f.shape for f in fields], edges, lmax, npcf=3, prepare=False, fused=not args.unfused)
@@ -199,14 +273,12 @@ def main():
     # roofline of the dominant kernel (largest share of the timed region among the passes
     # over all kernel arrays), from the live per-launch HIP-event records
     nk = (lmax + 1) * (lmax + 2) // 2 * nbins
-    names = {0: f"fft_pass_kernel<{n},...,+1> (inverse pass over all {nk} kernel arrays)",
+    names = {0: f"fft_pass(_pf)_kernel<{n},...,+1> (middle inverse pass over all {nk} kernel arrays, "
+                f"variant chosen by sb_autotune)",
              1: f"axis0_kernel<{n},...> (axis-0 kernel-spectrum + product + inverse pass)",
              2: f"last_contract_kernel<{n},...,{nbins}> (last inverse pass fused with the contraction)",
              3: "pair_kernel (unfused 3PCF contraction)"}
-    srcs = {0: ["paper_2210_10206_amd/csrc/fft.hip", "paper_2210_10206_amd/csrc/fft_core.h"],
-            1: ["paper_2210_10206_amd/csrc/fft.hip", "paper_2210_10206_amd/csrc/fft_core.h"],
-            2: ["paper_2210_10206_amd/csrc/fft_last.h", "paper_2210_10206_amd/csrc/fft_core.h"],
-            3: ["paper_2210_10206_amd/csrc/contract.hip"]}
+    srcs = TRAFFIC_SRCS
     per = {}
     for r in recs:
         if r["batch"] != nk or r["kernel"] not in names:
