@@ -19,29 +19,42 @@ using namespace fftcore;
 constexpr int fused_rows(int n, int tpp, int nbt) {
     int r = 1;
     while ((nbt * r * tpp) % 64 != 0) ++r;
-    while (nbt * r * tpp < 128 && nbt * 2 * r * tpp <= 512 && (n * (nbt * 2 * r + 1) + n) * 8 <= 65536) r *= 2;
+    while (nbt * r * tpp < 128 && nbt * 2 * r * tpp <= 512 && (n * (nbt * 2 * r + 1) + n) * 8 + 2 * r * n * 4 <= 65536) r *= 2;
     return r;
 }
 
-// Each thread owns whole cells: it reads the nb coefficients of a cell once from LDS and
-// adds every pair b1 <= b2 to its float32 totals (nb (nb + 1) / 2 of them).  The tile
-// shape (NBT bins x R rows, TPP threads per pencil) is fixed at compile time so that every
-// LDS address folds into an immediate offset.
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// The pair sums run on the matrix cores: for a quad of cells, Z[b1][b2] += w A^b1 conj(A^b2)
+// is a 16 x 16 x 4 float32 MFMA whose row and column index is the bin (padded to 16) and
+// whose K index is the cell, once with the real and once with the imaginary parts (twice
+// more for the imaginary part of projected sums).  Lane l = i + 16 g holds bin i of cell g of
+// the quad, which is both its A value (row i) and its B value (column i); the 16 x 16 result
+// has b1 = 4 g + r and b2 = i in register r of lane l.  Each tile's float32 result is added
+// to float64 totals, so float32 sums never span more than one tile.  The tile shape (NBT bins
+// x R rows, TPP threads per pencil) is fixed at compile time so that every LDS address folds
+// into an immediate offset.
 template <int N, int TPP, int NBT, int R, bool IMAG, int... RAD>
 __global__ __launch_bounds__(NBT * R * TPP) void last_contract_kernel(LastArgs a) {
     constexpr int P = NBT * R, PITCH = P + 1, NT = P * TPP;
-    constexpr int NPT = NBT * (NBT + 1) / 2;
-    constexpr int NACC = NPT * (IMAG ? 2 : 1);
+    constexpr int NW = NT / 64;       // waves
+    constexpr int NQ = R * N / 4;     // cell quads per tile
+    constexpr int NPART = IMAG ? 2 : 1;
     constexpr int EPT = N / TPP;      // tile elements loaded per thread
+    static_assert(NT % 64 == 0, "whole waves");
     extern __shared__ float2 smem[];
     const int nb = a.nb;
     float2 *sm = smem;
     float2 *tw = smem + N * PITCH;
-    const int tid = threadIdx.x;
+    float *wsm = reinterpret_cast<float *>(tw + N);   // the tile's weights w(x), R N values
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
     for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
-    float acc[NACC];
+    double tot[NPART][4];
 #pragma unroll
-    for (int v = 0; v < NACC; ++v) acc[v] = 0.f;
+    for (int q = 0; q < NPART; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tot[q][r] = 0.0;
     const int64_t nrows = a.ng / N;
     const int64_t r_begin = (int64_t)blockIdx.x * a.rows_per_block;
     const int64_t r_end = min(r_begin + a.rows_per_block, nrows);
@@ -57,8 +70,18 @@ __global__ __launch_bounds__(NBT * R * TPP) void last_contract_kernel(LastArgs a
             dst[e] = (row < r_end && b < nb) ? in[(int64_t)b * a.ng + row * N + j] : make_float2(0.f, 0.f);
         }
     };
+    constexpr int WPT = (R * N + NT - 1) / NT;          // weights loaded per thread
+    auto load_w = [&](int64_t row0, float *dst) {
+#pragma unroll
+        for (int e = 0; e < WPT; ++e) {
+            const int c = tid + e * NT;
+            const int64_t row = row0 + c / N;
+            dst[e] = (c < R * N && row < r_end) ? a.w[row * N + c % N] : 0.f;
+        }
+    };
     float2 nx[EPT];
-    if (r_begin < r_end) load_tile(r_begin, nx);
+    float nw[WPT];
+    if (r_begin < r_end) { load_tile(r_begin, nx); load_w(r_begin, nw); }
     for (int64_t row0 = r_begin; row0 < r_end; row0 += R) {
         __syncthreads();
 #pragma unroll
@@ -66,47 +89,56 @@ __global__ __launch_bounds__(NBT * R * TPP) void last_contract_kernel(LastArgs a
             const int f = tid + e * NT;
             sm[(f % N) * PITCH + f / N] = nx[e];
         }
-        if (row0 + R < r_end) load_tile(row0 + R, nx);     // next tile in flight during this one
+#pragma unroll
+        for (int e = 0; e < WPT; ++e)
+            if (tid + e * NT < R * N) wsm[tid + e * NT] = nw[e];
+        if (row0 + R < r_end) { load_tile(row0 + R, nx); load_w(row0 + R, nw); }   // next tile in flight
         __syncthreads();
         stages<N, TPP, 1, 1, RAD...>(sm, tw, tid % P, tid / P, PITCH);
-        for (int c = tid; c < R * N; c += NT) {
-            const int r = c / N, j = c % N;
-            const int64_t row = row0 + r;
-            if (row >= r_end) continue;
-            const float wv = a.w[row * N + j];
-            float2 v[NBT];
+        // two independent accumulator chains per part (real and imaginary operand halves)
+        f4v acc[2 * NPART];
 #pragma unroll
-            for (int b = 0; b < NBT; ++b) v[b] = sm[j * PITCH + b * R + r];   // zero beyond nb
-            int q = 0;
+        for (int q = 0; q < 2 * NPART; ++q) acc[q] = f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int b1 = 0; b1 < NBT; ++b1) {
-                const float2 u = make_float2(wv * v[b1].x, wv * v[b1].y);
-#pragma unroll
-                for (int b2 = b1; b2 < NBT; ++b2, ++q) {
-                    acc[q] += u.x * v[b2].x + u.y * v[b2].y;
-                    if (IMAG) acc[NPT + q] += u.y * v[b2].x - u.x * v[b2].y;
+        for (int k = 0; k < (NQ + NW - 1) / NW; ++k) {
+            const int qd = wave + k * NW;
+            if (qd < NQ) {
+                const int c = 4 * qd + lg;                 // this lane's cell of the quad
+                const int r = c / N, j = c % N;
+                const float wv = wsm[c];                   // zero beyond the last row
+                const float2 v = li < NBT ? sm[j * PITCH + li * R + r] : make_float2(0.f, 0.f);   // zero beyond nb
+                const float wx = wv * v.x, wy = wv * v.y;
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx, v.x, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(wy, v.y, acc[1], 0, 0, 0);
+                if constexpr (IMAG) {
+                    acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(wy, v.x, acc[2], 0, 0, 0);
+                    acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(-wx, v.y, acc[3], 0, 0, 0);
                 }
             }
         }
-    }
-    // float64 combine: every thread stores its float32 totals, then pair v sums them over
-    // the block's threads in thread order; partial[(g * nv + v) * nblocks + blk]
-    __syncthreads();
-    float *red = reinterpret_cast<float *>(smem);   // [tid][NACC]
 #pragma unroll
-    for (int u = 0; u < NACC; ++u) red[tid * NACC + u] = acc[u];
+        for (int q = 0; q < NPART; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tot[q][r] += (double)acc[2 * q][r] + (double)acc[2 * q + 1][r];
+    }
+    // float64 combine over the waves in wave order; partial[(g * nv + v) * nblocks + blk] with
+    // v = part * npairs + pair (b1 <= b2, b1 outer)
+    __syncthreads();
+    double *red = reinterpret_cast<double *>(smem);   // [wave][part][b1 * 16 + b2]
+#pragma unroll
+    for (int q = 0; q < NPART; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[(wave * NPART + q) * 256 + (4 * lg + r) * 16 + li] = tot[q][r];
     __syncthreads();
     const int npn = nb * (nb + 1) / 2;
-    const int nv = npn * (IMAG ? 2 : 1);
-    const int ncontrib = min(NT, R * N);           // threads that own cells
+    const int nv = npn * NPART;
     for (int v = tid; v < nv; v += NT) {
         const int vp = v % npn, part = v / npn;
         int b1 = 0, rem = vp;                      // pair index (nb layout) -> (b1, b2)
         while (rem >= nb - b1) { rem -= nb - b1; ++b1; }
         const int b2 = b1 + rem;
-        const int q = b1 * NBT - b1 * (b1 - 1) / 2 + (b2 - b1) + part * NPT;   // NBT layout
         double sum = 0.0;
-        for (int t = 0; t < ncontrib; ++t) sum += (double)red[t * NACC + q];
+        for (int w = 0; w < NW; ++w) sum += red[(w * NPART + part) * 256 + b1 * 16 + b2];
         a.partial[((int64_t)blockIdx.y * nv + v) * a.nblocks + blockIdx.x] = sum;
     }
 }
@@ -116,8 +148,8 @@ hipError_t launch_last_t(const LastArgs &a, hipStream_t s) {
     constexpr int R = fused_rows(N, TPP, NBT);
     constexpr int P = NBT * R, NT = P * TPP;
     if (a.rows != R) return hipErrorInvalidValue;
-    const size_t tile = (size_t)(N * (P + 1) + N) * sizeof(float2);
-    const size_t red = (size_t)NT * (NBT * (NBT + 1) / 2) * (IMAG ? 2 : 1) * sizeof(float);
+    const size_t tile = (size_t)(N * (P + 1) + N) * sizeof(float2) + (size_t)R * N * sizeof(float);
+    const size_t red = (size_t)(NT / 64) * (IMAG ? 2 : 1) * 256 * sizeof(double);
     const size_t shm = tile > red ? tile : red;
     dim3 grid((unsigned)a.nblocks, (unsigned)a.groups);
     hipLaunchKernelGGL((last_contract_kernel<N, TPP, NBT, R, IMAG, RAD...>), grid, dim3(NT), shm, s, a);
