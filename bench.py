@@ -186,6 +186,56 @@ def run_4pcf_batch(api, steps, warmup, count=16, precision="fp32", mfma=True):
     return res
 
 
+def run_c5(api, steps, warmup, synth_steps=200):
+    """Forward + adjoint of the uneven 48-field batch (edges drawn from 64/96/128/160/192,
+    sigma 1 lognormal), 8 bins to 16, lmax 4, one plan; then the synthesis demo: 200 Adam
+    steps at 128^3 from a Gaussian field towards the sums of the seed-100 lognormal field."""
+    import numpy as np
+    import torch
+    from fieldgen import c5_batch, gaussian_field, lognormal_field, linear_edges
+    from paper_2210_10206_amd.synthesis import synthesize
+    fields, edges_list = c5_batch()
+    dev = [torch.from_numpy(f).cuda() for f in fields]
+    edges = linear_edges(16, 8)
+    plan = api.Plan([f.shape for f in fields], edges, 4, npcf=3)
+    G = torch.from_numpy(np.random.Generator(np.random.PCG64(5)).standard_normal((len(dev), 5, 8, 8))).cuda()
+    for _ in range(warmup):
+        plan.forward(dev)
+        plan.backward(dev, G)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.forward_raw(dev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        plan.backward(dev, G)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ncell = sum(int(np.prod(f.shape)) for f in fields)
+    plan.close()
+    del dev
+    n = 128
+    sp = api.Plan([(n, n, n)], edges, 4, npcf=3)
+    target = sp.forward([torch.from_numpy(lognormal_field((n,) * 3, seed=100, sigma=1.0)).cuda()])[0]
+    init = torch.from_numpy(gaussian_field((n,) * 3, seed=101)).cuda()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    _, losses = synthesize(sp, target, init, steps=synth_steps, lr=0.05, history_every=max(1, synth_steps // 10))
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    sp.close()
+    return {"workload": f"uneven batch of {len(fields)} sigma-1 lognormal float32 cubes, edges from "
+                        f"64/96/128/160/192 ({ncell / len(fields) / 1e6:.2f} M cells on average), 8 bins over "
+                        "(0,16], lmax 4, one plan",
+            "forward_fields_per_s": round(len(fields) * steps / (t1 - t0), 2),
+            "adjoint_fields_per_s": round(len(fields) * steps / (t2 - t1), 2),
+            "forward_plus_adjoint_fields_per_s": round(len(fields) * steps / (t2 - t0), 2),
+            "synthesis": {"grid": n, "steps": synth_steps, "seconds": round(t4 - t3, 3),
+                          "ms_per_step": round((t4 - t3) / synth_steps * 1e3, 3),
+                          "loss_start": losses[0], "loss_end": losses[-1]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +248,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unfused", action="store_true", help="plain path: write the coefficients, then contract")
     ap.add_argument("--c4-steps", type=int, default=1, help="steps of the 128^3 4PCF batch (0 skips it)")
+    ap.add_argument("--c5-steps", type=int, default=1,
+                    help="steps of the uneven-batch forward + adjoint and the synthesis demo (0 skips them)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times (the reference "
                          "dispatch that scales the HBM byte counters of a counter run)")
@@ -321,6 +373,10 @@ def main():
                 "value": r["value"], "contraction_ms_per_field": r["contraction"]["ms_per_field"],
                 "achieved_tflops": r["contraction"]["achieved_tflops"], "kernel": r["contraction"]["kernel"]}
         c4["other_contraction_paths"] = variants
+    c5 = None
+    if args.c5_steps > 0:
+        print("bench: uneven batch forward + adjoint, synthesis demo", file=sys.stderr, flush=True)
+        c5 = run_c5(api, args.c5_steps, 1)
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle sample)", file=sys.stderr, flush=True)
@@ -340,6 +396,7 @@ def main():
         "per_kernel": per_kernel,
         "max_rel_err_vs_oracle": errs or None,
         "secondary_4pcf_128": c4,
+        "secondary_uneven_adjoint": c5,
     }
     print(json.dumps(line), flush=True)
 

@@ -18,7 +18,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["lognormal_field", "c3_fields", "c4_batch", "c5_batch", "sparse_unit_field",
+__all__ = ["lognormal_field", "gaussian_field", "c3_fields", "c4_batch", "c5_batch", "sparse_unit_field",
            "linear_edges"]
 
 
@@ -27,12 +27,8 @@ def linear_edges(rmax: float, nbins: int) -> np.ndarray:
     return np.array([rmax * b / nbins for b in range(nbins + 1)], dtype=np.float64)
 
 
-def lognormal_field(shape, seed: int, sigma: float = 1.0, spectral_index: float | None = None,
-                    dtype=np.float32) -> np.ndarray:
-    """Lognormal density contrast on a periodic grid of the given shape.
-
-    ``spectral_index`` n_s defaults to 11/3 in 3D and 8/3 in 2D (Kolmogorov-like
-    slopes for a 3D cube and a 2D slice)."""
+def _gaussian(shape, seed: int, spectral_index: float | None) -> np.ndarray:
+    """Steps 1-3 of the recipe: the zero-mean, unit-variance Gaussian field (float64)."""
     shape = tuple(int(s) for s in shape)
     nd = len(shape)
     if spectral_index is None:
@@ -48,7 +44,22 @@ def lognormal_field(shape, seed: int, sigma: float = 1.0, spectral_index: float 
     nz = kmag > 0
     amp[nz] = kmag[nz] ** (-0.5 * spectral_index)
     g = np.fft.ifftn(np.fft.fftn(w) * amp).real
-    g = (g - g.mean()) / g.std()
+    return (g - g.mean()) / g.std()
+
+
+def gaussian_field(shape, seed: int, spectral_index: float | None = None, dtype=np.float32) -> np.ndarray:
+    """Gaussian field with the power spectrum of lognormal_field (steps 1-3 only): the
+    starting point of the synthesis demo."""
+    return np.ascontiguousarray(_gaussian(shape, seed, spectral_index).astype(dtype))
+
+
+def lognormal_field(shape, seed: int, sigma: float = 1.0, spectral_index: float | None = None,
+                    dtype=np.float32) -> np.ndarray:
+    """Lognormal density contrast on a periodic grid of the given shape.
+
+    ``spectral_index`` n_s defaults to 11/3 in 3D and 8/3 in 2D (Kolmogorov-like
+    slopes for a 3D cube and a 2D slice)."""
+    g = _gaussian(shape, seed, spectral_index)
     rho = np.exp(sigma * g)
     delta = rho / rho.mean() - 1.0
     delta = delta - delta.mean()

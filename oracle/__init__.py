@@ -18,8 +18,8 @@ correlation in float64 instead of by FFTs:
   density (no counterpart in the paper; it is the derivative of the same sums).
 
 Prefactors ((-1)^l / sqrt(2l+1), 1/(2 pi)^2, 1/V, 1/V_b) are not applied: the
-returned values are the raw sums of the appendix listings.  Every reading of a
-passage that is ambiguous in the paper is listed in the design doc of the repository.
+returned values are the raw sums of the appendix listings.  Where the paper is
+ambiguous, the reading taken is stated in the docstring of the function concerned.
 
 Parity pins (all in ``tests/``): brute-force triplet / quadruplet counting on
 tiny grids, 3j closed forms and orthogonality, rotation / reflection
@@ -30,5 +30,5 @@ their docstring ("parity unpinned").
 from .api import (  # noqa: F401
     support, bin_counts, basis_full, basis_proj, lambdas, mpairs, threej,
     coeffs_full, coeffs_proj, zeta3_full, zeta4_full, zeta3_proj, zeta4_proj,
-    grad3_full, max_threads,
+    grad3_full, normalization, max_threads,
 )

@@ -44,7 +44,7 @@ def _lib():
         lib.oc_coeffs.restype = i32
         lib.oc_zeta.argtypes = [i32, P, P, i64, P, P, i32, i32, P, i32, i32, P, P, P, i64, P, P, i32]
         lib.oc_zeta.restype = i32
-        lib.oc_grad3.argtypes = [i32, P, P, i64, P, P, i32, i32, P, i32, P, P, P, P, P, i32]
+        lib.oc_grad3.argtypes = [i32, P, P, i64, P, P, i32, i32, P, i32, P, P, P, P, P, i64, P, P, i32]
         lib.oc_grad3.restype = i32
         lib.oc_max_threads.restype = i32
         _LIB = lib
@@ -298,26 +298,58 @@ def zeta4_proj(delta, edges, mmax, cells=None, nthreads=0):
     return pairs, Z
 
 
-def grad3_full(delta, edges, lmax, G, nthreads=0):
+def grad3_full(delta, edges, lmax, G, cells=None, nthreads=0):
     """d/d delta(y) of L = sum_{l,b1,b2} G[l,b1,b2] Z[l,b1,b2] for the full 3PCF sums.
 
     Derivative of the trilinear sum of zeta3_full: the direct term
     sum G a^b1 conj(a^b2) at y plus, for every neighbour x = y - r, the terms
     through d a^b(x) / d delta(y) = conj(Y_lm(r^)) for r in bin b.  Returns the
-    real gradient (the imaginary part is rounding noise and is dropped after a check)."""
+    real gradient (the imaginary part is rounding noise and is dropped after a check):
+    the whole field, or the values at the flat cell indices `cells` (then the coefficients
+    are evaluated only at those cells and their neighbours y - r)."""
     d, shape, off, bins, _ = _prep(delta, edges)
     nb = len(edges) - 1
     B = basis_full(off, lmax)
-    a_all = np.ascontiguousarray(_coeffs(d, shape, off, bins, nb, B, None, nthreads))
+    if cells is None:
+        ys, amap = None, None
+        a_all = np.ascontiguousarray(_coeffs(d, shape, off, bins, nb, B, None, nthreads))
+        ny = d.size
+    else:
+        ys = np.ascontiguousarray(np.asarray(cells, dtype=np.int64).ravel())
+        ny = ys.size
+        # every x = y - r (and y itself), as flat indices
+        coords = np.stack(np.unravel_index(ys, d.shape), axis=1)
+        nbr = (coords[:, None, :] - off[None, :, :]) % np.array(d.shape)
+        need = np.unique(np.concatenate([ys, np.ravel_multi_index(nbr.reshape(-1, d.ndim).T, d.shape)]))
+        amap = np.full(d.size, -1, dtype=np.int64)
+        amap[need] = np.arange(need.size, dtype=np.int64)
+        a_all = np.ascontiguousarray(_coeffs(d, shape, off, bins, nb, B, need, nthreads))
     ptr = np.array([l * l for l in range(lmax + 2)], np.int32)
     js = np.arange((lmax + 1) ** 2, dtype=np.int32)
     Gd = np.ascontiguousarray(np.asarray(G, np.float64).reshape(lmax + 1, nb, nb))
-    out = np.zeros(d.size, dtype=np.complex128)
+    out = np.zeros(ny, dtype=np.complex128)
     Bc = np.ascontiguousarray(B)
     _lib().oc_grad3(d.ndim, _ptr(shape), _ptr(d), off.shape[0], _ptr(off), _ptr(bins), nb,
                     B.shape[1], _ptr(Bc), lmax + 1, _ptr(ptr), _ptr(js), _ptr(Gd), _ptr(a_all),
+                    None if amap is None else _ptr(amap), int(ny), None if ys is None else _ptr(ys),
                     _ptr(out), int(nthreads))
     scale = max(1.0, float(np.max(np.abs(out.real))))
     if np.max(np.abs(out.imag)) > 1e-9 * scale:
         raise AssertionError("oracle gradient has a non-negligible imaginary part")
-    return out.real.reshape(d.shape)
+    return out.real.reshape(d.shape) if cells is None else out.real
+
+
+def normalization(delta, edges, npcf):
+    """The N of Sec. 2.5 with unit cells (box side = grid resolution, the paper's validation
+    set-up): N = N_gal prod_{n=1}^{N-1} (nbar V_bin,n), N_gal = sum over cells of (delta + 1),
+    nbar = N_gal / N_g, V_bin = number of cells in the bin (cell volume or area 1).  Returned
+    with the broadcast shape of the bin axes of the result: (nb, nb) for npcf 3, (nb, nb, nb)
+    for npcf 4; the raw sums divided by it are the normalized coefficients."""
+    d = np.asarray(delta, dtype=np.float64)
+    ngal = float(np.sum(d + 1.0))
+    nbar = ngal / d.size
+    v = nbar * bin_counts(d.shape, edges).astype(np.float64)
+    if npcf == 3:
+        return ngal * np.multiply.outer(v, v)
+    return ngal * np.multiply.outer(np.multiply.outer(v, v), v)
+

@@ -232,22 +232,28 @@ int oc_zeta(int ndim, const int64_t *shape, const double *delta,
  * a_all holds the coefficients at every cell: a_all[x][b][j].
  * Output: complex gradient per cell (the real part is the gradient of a real L).
  */
+/* Gradient at the cells ys[0..ny) (all cells when ys is NULL).  The coefficients of cell x
+ * are row amap[x] of a_all (row x when amap is NULL); every x = y - r of a requested y must
+ * have a row. */
 int oc_grad3(int ndim, const int64_t *shape, const double *delta,
              int64_t n_off, const int32_t *off, const int32_t *bin, int nbins,
              int nbasis, const double *basis_ri,
              int ngroups, const int32_t *group_ptr, const int32_t *term_j,
              const double *G /* ngroups*nbins*nbins real */,
-             const double *a_all_ri, double *out_ri, int nthreads) {
+             const double *a_all_ri, const int64_t *amap, int64_t ny, const int64_t *ys,
+             double *out_ri, int nthreads) {
     const double complex *basis = (const double complex *)basis_ri;
     const double complex *a_all = (const double complex *)a_all_ri;
     double complex *out = (double complex *)out_ri;
     int64_t ng = 1;
     for (int d = 0; d < ndim; ++d) ng *= shape[d];
+    if (!ys) ny = ng;
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(static)
-    for (int64_t y = 0; y < ng; ++y) {
+    for (int64_t iy = 0; iy < ny; ++iy) {
+        const int64_t y = ys ? ys[iy] : iy;
         double complex s = 0;
-        const double complex *ay = a_all + (size_t)y * nbins * nbasis;
+        const double complex *ay = a_all + (size_t)(amap ? amap[y] : y) * nbins * nbasis;
         /* direct term */
         for (int g = 0; g < ngroups; ++g)
             for (int e = group_ptr[g]; e < group_ptr[g + 1]; ++e) {
@@ -266,7 +272,7 @@ int oc_grad3(int ndim, const int64_t *shape, const double *delta,
             const int64_t x = shifted_index(ndim, shape, cy, mr);
             const double dx = delta[x];
             const int b = bin[o];
-            const double complex *ax = a_all + (size_t)x * nbins * nbasis;
+            const double complex *ax = a_all + (size_t)(amap ? amap[x] : x) * nbins * nbasis;
             const double complex *K = basis + (size_t)o * nbasis;
             for (int g = 0; g < ngroups; ++g)
                 for (int e = group_ptr[g]; e < group_ptr[g + 1]; ++e) {
@@ -277,7 +283,7 @@ int oc_grad3(int ndim, const int64_t *shape, const double *delta,
                         s += G[((size_t)g * nbins + b1) * nbins + b] * dx * ax[(size_t)b1 * nbasis + j] * conj(K[j]);
                 }
         }
-        out[y] = s;
+        out[iy] = s;
     }
     return 0;
 }

@@ -8,6 +8,7 @@ Calls only the FP64 oracle (``oracle/``) and the seeded field generator
       10 bins to 32 (edges 3.2 b), lmax 6                      (about an hour per field)
   c4  fields 0 and 1 of the 16-field 128^3 batch, 8 bins to 24, even Lambda, lmax 4
   c5  one field of each grid edge of the uneven 48-field batch, 8 bins to 16, lmax 4
+  c5g the same fields: gradient of sum G Z (G seeded normal) at 32 seeded cells each
 """
 from __future__ import annotations
 
@@ -79,13 +80,31 @@ def make_c5(nt):
         _save(f"c5_full3_{n}_field{i}.npz", zeta3=z, edges=edges, field=i, seconds=time.time() - t)
 
 
+def make_c5g(nt):
+    edges_list = c5_shapes()
+    seen = {}
+    for i, n in enumerate(edges_list):
+        if n not in seen:
+            seen[n] = i
+    for n, i in sorted(seen.items()):
+        d = lognormal_field((n, n, n), seed=i, sigma=1.0)
+        edges = linear_edges(16, 8)
+        rng = np.random.Generator(np.random.PCG64(5500 + i))
+        G = rng.standard_normal((5, 8, 8))
+        cells = np.sort(rng.choice(d.size, 32, replace=False))
+        t = time.time()
+        g = oracle.grad3_full(d.astype(np.float64), edges, 4, G, cells=cells, nthreads=nt)
+        _save(f"c5_grad3_{n}_field{i}.npz", grad=g, cells=cells, G=G, edges=edges, field=i,
+              seconds=time.time() - t)
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("what", choices=["c2", "c3", "c4", "c5", "c5g"])
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--seeds", type=int, nargs="*", default=None)
     a = ap.parse_args()
     if a.what == "c3":
         make_c3(a.threads, tuple(a.seeds) if a.seeds else (0, 1))
     else:
-        {"c2": make_c2, "c4": make_c4, "c5": make_c5}[a.what](a.threads)
+        {"c2": make_c2, "c4": make_c4, "c5": make_c5, "c5g": make_c5g}[a.what](a.threads)

@@ -304,3 +304,57 @@ def test_grad3_box_truncated_kernel(rng):
         e = e.reshape(d.shape)
         fd = (L(d + e) - L(d - e)) / 2e-3
         assert abs(fd - g.reshape(-1)[y]) < 1e-8 * max(1.0, abs(fd))
+
+
+def test_grad3_at_cells_matches_whole_field(rng):
+    """The gradient evaluated at a subset of cells (coefficients only where needed) equals
+    the whole-field gradient at those cells."""
+    d = rng.standard_normal((8, 6, 10))
+    edges = [0.0, 1.5, 2.5, 3.0]
+    lmax = 3
+    G = rng.standard_normal((lmax + 1, 3, 3))
+    full = oracle.grad3_full(d, edges, lmax, G).reshape(-1)
+    cells = np.array([0, 7, 61, 200, 479])
+    sub = oracle.grad3_full(d, edges, lmax, G, cells=cells)
+    assert np.allclose(sub, full[cells], rtol=1e-12, atol=1e-12 * np.max(np.abs(full)))
+
+
+def test_grad3_fd_24_box_truncated():
+    """The adjoint finite-difference case of the uneven-batch workload: 24^3 lognormal field,
+    8 bins out to r = 16 (> N/2, kernels reach the box edge), lmax 4, central differences
+    with h = 1e-3 at 16 random cells against the gradient at those cells."""
+    d = lognormal_field((24, 24, 24), seed=24, sigma=1.0, dtype=np.float64)
+    edges = linear_edges(16, 8)
+    lmax = 4
+    g_rng = np.random.Generator(np.random.PCG64(240))
+    G = g_rng.standard_normal((lmax + 1, 8, 8))
+    cells = np.sort(g_rng.choice(d.size, 16, replace=False))
+    g = oracle.grad3_full(d, edges, lmax, G, cells=cells)
+    L = lambda f: float(np.sum(G * oracle.zeta3_full(f, edges, lmax).real))  # noqa: E731
+    h = 1e-3
+    for y, gy in zip(cells, g):
+        e = np.zeros(d.size)
+        e[y] = h
+        e = e.reshape(d.shape)
+        fd = (L(d + e) - L(d - e)) / (2 * h)
+        assert abs(fd - gy) < 1e-7 * max(1.0, np.max(np.abs(g))), (y, fd, gy)
+
+
+# ---------------------------------------------------------------- normalization (Sec. 2.5)
+
+def test_normalization_constant_field_closed_form():
+    """delta = c everywhere: the l = 0 sums are N_g c^3 n_b1 n_b2 / (4 pi) (counts n_b), the N
+    of Sec. 2.5 is N_g (1 + c) ((1 + c) n_b1) ((1 + c) n_b2), so the normalized l = 0 3PCF is
+    c^3 / (4 pi (1 + c)^3) for every bin pair."""
+    c = 0.7
+    d = np.full((10, 10, 10), c)
+    edges = [0.0, 1.0, 2.0, 3.5]
+    z = oracle.zeta3_full(d, edges, 1).real
+    N = oracle.normalization(d, edges, 3)
+    assert np.allclose(z[0] / N, c ** 3 / (4 * np.pi * (1 + c) ** 3), rtol=1e-12)
+    # the 4PCF with Lambda = (0, 0, 0): 3j = 1, sums N_g c^4 n n n / (4 pi)^(3/2) over
+    # N = N_g (1 + c)^4 n n n
+    lams, z4 = oracle.zeta4_full(d, edges, 0)
+    N4 = oracle.normalization(d, edges, 4)
+    assert np.allclose(z4[0].real / N4, c ** 4 / ((4 * np.pi) ** 1.5 * (1 + c) ** 4), rtol=1e-12)
+
