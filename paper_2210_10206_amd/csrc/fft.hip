@@ -278,6 +278,9 @@ hipError_t launch(const FftPass &a, hipStream_t s) {
 // The variants are the autotuner's candidates.
 hipError_t launch_fft_pass(const FftPass &a, hipStream_t s) {
     const int v = a.variant;
+    // variants 4 and 5 (length 256): persistent, two radix-16 stages, 4 / 16 tiles
+    if (v >= 4 && a.n == 256 && a.load == LOAD_C && a.store == STORE_C)
+        return launch_pf<256, 16, 256, 16, 16>(a, s, v == 4 ? 4 : 16);
     // variants 2 and 3: persistent passes with register prefetch (plain loads and stores only)
     if (v >= 2 && a.load == LOAD_C && a.store == STORE_C) {
         const int tiles = v == 2 ? 4 : 16;
@@ -351,8 +354,9 @@ bool fft_supported(int n) {
 }
 
 int fft_num_variants(int n) {
-    (void)n;
-    return 4;   // 0, 1: one tile per workgroup (two shapes where defined); 2, 3: persistent, 4 / 16 tiles
+    // 0, 1: one tile per workgroup (two shapes where defined); 2, 3: persistent, 4 / 16 tiles;
+    // 4, 5 (length 256): persistent with two radix-16 stages
+    return n == 256 ? 6 : 4;
 }
 
 }  // namespace sb

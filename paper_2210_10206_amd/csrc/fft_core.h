@@ -104,6 +104,41 @@ template <int SIGN> struct Dft<8, SIGN> {
     }
 };
 
+template <int SIGN> struct Dft<16, SIGN> {
+    // 4 x 4 split (decimation in time): n = 4 n1 + n2, k = k1 + 4 k2; 4-point DFTs over n1,
+    // twiddles w16^{n2 k1}, 4-point DFTs over n2.
+    __device__ __forceinline__ static void run(float2 *v) {
+        const float c1 = 0.92387953251128675613f;   // cos(pi / 8)
+        const float s1 = 0.38268343236508977173f;   // sin(pi / 8)
+        const float r = 0.70710678118654752440f;
+        float2 a[4][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < 4; ++n1) a[n2][n1] = v[4 * n1 + n2];
+            Dft<4, SIGN>::run(a[n2]);
+        }
+        const float2 w1 = make_float2(c1, SIGN * s1), w2 = make_float2(r, SIGN * r);
+        const float2 w3 = make_float2(s1, SIGN * c1), w6 = make_float2(-r, SIGN * r);
+        a[1][1] = cmul(a[1][1], w1);
+        a[1][2] = cmul(a[1][2], w2);
+        a[1][3] = cmul(a[1][3], w3);
+        a[2][1] = cmul(a[2][1], w2);
+        a[2][2] = mul_i<SIGN>(a[2][2]);
+        a[2][3] = cmul(a[2][3], w6);
+        a[3][1] = cmul(a[3][1], w3);
+        a[3][2] = cmul(a[3][2], w6);
+        a[3][3] = cmul(a[3][3], make_float2(-c1, -SIGN * s1));   // w16^9 = -w16
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            float2 b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+            Dft<4, SIGN>::run(b);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = b[k2];
+        }
+    }
+};
+
 // One Stockham stage on pencils stored in LDS as sm[j * pitch + p] (p = pencil in the
 // tile, j = element), TPP threads per pencil, thread (p, q).
 template <int N, int TPP, int SIGN, int NS, int R>
@@ -169,7 +204,7 @@ __device__ __forceinline__ double wave_sum64(double v) {
     X(8, 1, 64, 8) X(12, 1, 64, 4, 3) X(16, 4, 64, 4, 4) X(24, 2, 128, 4, 2, 3)              \
     X(32, 4, 64, 4, 8) X(48, 4, 64, 4, 4, 3) X(64, 8, 128, 8, 8) X(96, 8, 128, 4, 4, 2, 3)   \
     X(128, 16, 256, 8, 8, 2) X(160, 8, 128, 4, 4, 2, 5) X(192, 16, 256, 4, 4, 4, 3)          \
-    X(256, 32, 512, 8, 8, 4) X(512, 64, 512, 8, 8, 8)
+    X(256, 16, 256, 16, 16) X(512, 64, 512, 8, 8, 8)
 
 // Threads per pencil of the fused last pass (the axis-0 pass uses SB_FUSED_CONFIGS):
 // at most 512 threads per workgroup for up to 16 bins.
