@@ -7,6 +7,8 @@
 // pencil, and writes the tile back.  Loads can fuse the spectral product
 // (delta_hat * kernel_hat) or read a real field; stores can fuse a spectral
 // multiply-accumulate.  The radix stages are in fft_core.h.
+#include <utility>
+
 #include "fft_core.h"
 
 namespace sb {
@@ -180,6 +182,72 @@ __global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
     }
 }
 
+// Axis-0 correlation pass for n = R * R held in registers: thread q of a pencil owns rows
+// q + R r (r < R), which are both the inputs of radix-R butterfly q of the first Stockham
+// stage and the outputs of butterfly q of the second.  So the forward transform of the
+// kernel pencil, the product with the density spectrum and the inverse transform touch LDS
+// only for the two stage exchanges (positions R q + r written, q + R r read), with one
+// barrier each (the exchanges alternate between two buffers).  Loads and stores take P
+// adjacent pencils of the contiguous axes per row, as in the LDS-staged kernel.
+template <int R, int P>
+__global__ __launch_bounds__(P * R) void axis0_reg_kernel(Axis0Args a) {
+    constexpr int N = R * R;
+    constexpr int PITCH = P + 1;
+    __shared__ float2 ex[2][N * PITCH];
+    const int tid = threadIdx.x;
+    const int p = tid % P, q = tid / P;
+    const int64_t g = (int64_t)blockIdx.x * P + p;
+    const bool ok = g < a.plane;
+    // second-stage twiddles w^{q r}, w = e^{-2 pi i / N} (the inverse takes the conjugate)
+    float2 tw[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) tw[r] = a.tw[(q * r) % N];
+    const int64_t kstride = (int64_t)a.np * a.plane;
+    auto load_kernel = [&](int64_t k, float2 *dst) {
+        const float2 *kc = a.kc + k * kstride;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int j = q + R * r;
+            const int pl = (a.np == N || j <= a.r0) ? j : (j >= N - a.r0 ? a.np - (N - j) : -1);
+            dst[r] = (ok && pl >= 0) ? kc[(int64_t)pl * a.plane + g] : make_float2(0.f, 0.f);
+        }
+    };
+    // one transform: radix-R DFT of the own rows, exchange, twiddle, radix-R DFT -> own rows
+    auto transform = [&](float2 *v, float2 *buf, auto sign_c) {
+        constexpr int SIGN = decltype(sign_c)::value;
+        Dft<R, SIGN>::run(v);
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[(R * q + r) * PITCH + p] = v[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float2 x = buf[(q + R * r) * PITCH + p];
+            const float2 w = SIGN < 0 ? tw[r] : make_float2(tw[r].x, -tw[r].y);
+            v[r] = r == 0 ? x : cmul(x, w);
+        }
+        Dft<R, SIGN>::run(v);
+    };
+    float2 dr[R], nx[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) dr[r] = ok ? a.dhat[(int64_t)(q + R * r) * a.plane + g] : make_float2(0.f, 0.f);
+    const int64_t kbase = (int64_t)blockIdx.y * a.nb;
+    load_kernel(kbase, nx);
+    for (int b = 0; b < a.nb; ++b) {
+        float2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = nx[r];
+        if (b + 1 < a.nb) load_kernel(kbase + b + 1, nx);   // in flight during the transforms
+        transform(v, ex[0], std::integral_constant<int, -1>{});
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = cmul(v[r], dr[r]);
+        transform(v, ex[1], std::integral_constant<int, 1>{});
+        float2 *out = a.out + (kbase + b) * a.ng;
+        if (ok)
+#pragma unroll
+            for (int r = 0; r < R; ++r) out[(int64_t)(q + R * r) * a.plane + g] = v[r];
+    }
+}
+
 template <int N, int TPP, int NT, int... RAD>
 hipError_t launch_axis0_t(const Axis0Args &a, hipStream_t s) {
     constexpr int P = NT / TPP;
@@ -310,6 +378,12 @@ hipError_t launch_fft_pass(const FftPass &a, hipStream_t s) {
 }
 
 hipError_t launch_axis0(const Axis0Args &a, hipStream_t s) {
+    if (a.n == 256 && a.mode == 0) {
+        constexpr int P = 16;
+        dim3 grid((unsigned)((a.plane + P - 1) / P), (unsigned)a.groups);
+        hipLaunchKernelGGL((axis0_reg_kernel<16, P>), grid, dim3(16 * P), 0, s, a);
+        return hipGetLastError();
+    }
     switch (a.n) {
 #define SB_X(N, TPP, NT, ...) case N: return launch_axis0_t<N, TPP, NT, __VA_ARGS__>(a, s);
         SB_FUSED_CONFIGS(SB_X)
