@@ -143,6 +143,145 @@ __global__ __launch_bounds__(NBT * R * TPP) void last_contract_kernel(LastArgs a
     }
 }
 
+// Register-resident form for n = RX * RX (RX threads per row): a tile is one row of the
+// NBT (padded) bins of one (l, m).  Thread q of a pencil loads elements q + RX r (coalesced:
+// the RX threads of a pencil are adjacent lanes), runs the first radix-RX stage in
+// registers, exchanges through LDS (positions RX q + r written, q + RX r read), runs the
+// second stage and holds elements q + RX r of the transformed row, which it writes once to
+// the [cell][bin] tile read by the MFMA pair sums.  The exchange and the contraction tile
+// are separate LDS buffers, so a tile needs two barriers.
+template <int RX, int NBT, bool IMAG>
+__global__ __launch_bounds__(NBT * RX, 3) void last_reg_kernel(LastArgs a) {
+    constexpr int N = RX * RX;
+    constexpr int P = NBT;                 // pencils (bins) per tile
+    constexpr int NT = P * RX;
+    constexpr int NW = NT / 64;
+    constexpr int NQ = N / 4;              // cell quads per tile
+    constexpr int NPART = IMAG ? 2 : 1;
+    constexpr int EXP = RX * (RX + 1);     // exchange floats2 per pencil (rows padded by one)
+    constexpr int PITCH = P + 1;
+    constexpr int WPT = (N + NT - 1) / NT;
+    static_assert(NT % 64 == 0, "whole waves");
+    __shared__ float2 ex[P * EXP];
+    __shared__ float2 cs[N * PITCH];
+    __shared__ float wsm[N];
+    const int nb = a.nb;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int q = tid % RX, pp = tid / RX;  // element column, pencil (= bin)
+    float2 tw[RX];                          // w^{q r}, w = e^{-2 pi i / N}; the inverse takes the conjugate
+#pragma unroll
+    for (int r = 0; r < RX; ++r) tw[r] = a.tw[(q * r) % N];
+    double tot[NPART][4];
+#pragma unroll
+    for (int u = 0; u < NPART; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tot[u][r] = 0.0;
+    const int64_t nrows = a.ng / N;
+    const int64_t r_begin = (int64_t)blockIdx.x * a.rows_per_block;
+    const int64_t r_end = min(r_begin + a.rows_per_block, nrows);
+    const float2 *in = a.in + ((int64_t)blockIdx.y * nb + pp) * a.ng;
+    const bool live = pp < nb;
+    auto load_row = [&](int64_t row, float2 *dst, float *wdst) {
+#pragma unroll
+        for (int r = 0; r < RX; ++r) dst[r] = live ? in[row * N + q + RX * r] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int e = 0; e < WPT; ++e) {
+            const int c = tid + e * NT;
+            wdst[e] = c < N ? a.w[row * N + c] : 0.f;
+        }
+    };
+    float2 nx[RX];
+    float nw[WPT];
+    if (r_begin < r_end) load_row(r_begin, nx, nw);
+    for (int64_t row = r_begin; row < r_end; ++row) {
+        float2 v[RX];
+#pragma unroll
+        for (int r = 0; r < RX; ++r) v[r] = nx[r];
+        float wv[WPT];
+#pragma unroll
+        for (int e = 0; e < WPT; ++e) wv[e] = nw[e];
+        if (row + 1 < r_end) load_row(row + 1, nx, nw);    // next row in flight
+        Dft<RX, 1>::run(v);
+#pragma unroll
+        for (int r = 0; r < RX; ++r) ex[pp * EXP + q * (RX + 1) + r] = v[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RX; ++r) {
+            const float2 x = ex[pp * EXP + r * (RX + 1) + q];
+            v[r] = r == 0 ? x : cmul(x, make_float2(tw[r].x, -tw[r].y));
+        }
+        Dft<RX, 1>::run(v);
+#pragma unroll
+        for (int r = 0; r < RX; ++r) cs[(q + RX * r) * PITCH + pp] = v[r];
+#pragma unroll
+        for (int e = 0; e < WPT; ++e)
+            if (tid + e * NT < N) wsm[tid + e * NT] = wv[e];
+        __syncthreads();
+        f4v acc[2 * NPART];
+#pragma unroll
+        for (int u = 0; u < 2 * NPART; ++u) acc[u] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+        for (int k = 0; k < (NQ + NW - 1) / NW; ++k) {
+            const int qd = wave + k * NW;
+            if (qd < NQ) {
+                const int c = 4 * qd + lg;
+                const float w = wsm[c];
+                const float2 x = li < NBT ? cs[c * PITCH + li] : make_float2(0.f, 0.f);   // zero beyond nb
+                const float wx = w * x.x, wy = w * x.y;
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx, x.x, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(wy, x.y, acc[1], 0, 0, 0);
+                if constexpr (IMAG) {
+                    acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(wy, x.x, acc[2], 0, 0, 0);
+                    acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(-wx, x.y, acc[3], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NPART; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tot[u][r] += (double)acc[2 * u][r] + (double)acc[2 * u + 1][r];
+    }
+    // float64 combine over the waves in wave order (as in last_contract_kernel)
+    __syncthreads();
+    double *red = reinterpret_cast<double *>(cs);
+#pragma unroll
+    for (int u = 0; u < NPART; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[(wave * NPART + u) * 256 + (4 * lg + r) * 16 + li] = tot[u][r];
+    __syncthreads();
+    const int npn = nb * (nb + 1) / 2;
+    const int nv = npn * NPART;
+    for (int vv = tid; vv < nv; vv += NT) {
+        const int vp = vv % npn, part = vv / npn;
+        int b1 = 0, rem = vp;
+        while (rem >= nb - b1) { rem -= nb - b1; ++b1; }
+        const int b2 = b1 + rem;
+        double sum = 0.0;
+        for (int w = 0; w < NW; ++w) sum += red[(w * NPART + part) * 256 + b1 * 16 + b2];
+        a.partial[((int64_t)blockIdx.y * nv + vv) * a.nblocks + blockIdx.x] = sum;
+    }
+}
+
+template <int RX>
+hipError_t launch_last_reg(const LastArgs &a, hipStream_t s) {
+    if (a.rows != 1) return hipErrorInvalidValue;
+    dim3 grid((unsigned)a.nblocks, (unsigned)a.groups);
+    const bool im = a.want_imag != 0;
+    const int nbt = (a.nb + 3) / 4 * 4;
+#define SB_LR(NBT)                                                                                    \
+    case NBT:                                                                                          \
+        if (im) hipLaunchKernelGGL((last_reg_kernel<RX, NBT, true>), grid, dim3(NBT * RX), 0, s, a);   \
+        else hipLaunchKernelGGL((last_reg_kernel<RX, NBT, false>), grid, dim3(NBT * RX), 0, s, a);     \
+        break;
+    switch (nbt) {
+        SB_LR(4) SB_LR(8) SB_LR(12) SB_LR(16)
+        default: return hipErrorInvalidValue;
+    }
+#undef SB_LR
+    return hipGetLastError();
+}
+
 template <int N, int TPP, int NBT, bool IMAG, int... RAD>
 hipError_t launch_last_t(const LastArgs &a, hipStream_t s) {
     constexpr int R = fused_rows(N, TPP, NBT);

@@ -165,6 +165,32 @@ def test_graph_replay_matches_eager(sb):
     plan.close()
 
 
+@pytest.mark.parametrize("nbins", [3, 8, 10, 16])
+def test_last_axis_256_bin_counts(sb, nbins):
+    # a contiguous axis of 256 takes the register-resident fused last pass; every padded bin
+    # count (4, 8, 12, 16) of its tile
+    say(f"case: (8, 16, 256) full 3PCF, {nbins} bins to 8, lmax 4")
+    d = lognormal_field((8, 16, 256), seed=30 + nbins, sigma=1.0)
+    edges = linear_edges(8, nbins)
+    plan, dev, z = run_plan(sb, [d], edges, 4)
+    ref = oracle.zeta3_full(d.astype(np.float64), edges, 4)
+    err = rel_err(z[0], ref.real)
+    say(f"  err={err:.3e}")
+    assert err < TOL32
+    plan.close()
+
+
+def test_projected_last_axis_256(sb):
+    say("case: 128 x 256 projected 3PCF, 6 bins to 12, mmax 5")
+    d = lognormal_field((128, 256), seed=12, sigma=1.0)
+    edges = linear_edges(12, 6)
+    _, _, z3 = run_plan(sb, [d], edges, 5, npcf=3)
+    ref3 = oracle.zeta3_proj(d.astype(np.float64), edges, 5)
+    e3 = rel_err(z3[0], ref3)
+    say(f"  proj3 err={e3:.3e}")
+    assert e3 < TOL32
+
+
 # ------------------------------------------------------------------ projected
 
 def test_projected_small(sb):
