@@ -9,9 +9,10 @@
 // 16) and K = (cell, re/im) that runs on MFMA:
 //   PREC 0: v_mfma_f32_16x16x4f32, K = the cells of the four lane groups, re and im in turn;
 //   PREC 1: v_mfma_f32_16x16x32_bf16 with both operands split into bf16 hi + lo parts and
-//           hi*hi + hi*lo + lo*hi accumulated in float32 (split-BF16).
-// Lane l of a wave is (i = l % 16, g = l / 16): row i of the A tile (pair 16 mt + i), column i
-// of the B tile (bin b3 = i), cells 4 g .. 4 g + 3 of the wave's 16-cell step.
+//           hi*hi + hi*lo + lo*hi accumulated in float32 (split-BF16); each lane group
+//           fills two of its eight K slots (re, im of its cell).
+// Lane l of a wave is (i = l % 16, g = l / 16): row i of each A tile, column i of the B tile
+// (bin b3 = i); the lane walks cells 4 g .. 4 g + 3 of the wave's 16-cell step in turn.
 #pragma once
 #include <utility>
 #include "sb_kgen.h"
@@ -49,18 +50,25 @@ __device__ __forceinline__ float2 signed_m(float2 v) {
 
 template <int LA, int LB, int MC, int MA, int T>
 struct Couple {
-    // accumulate the terms ma = MA .. LA of one mc into L; T = index of the term in the table
-    __device__ __forceinline__ static void run(const float *cw, const float2 *A1, const float2 *A2, float2 &L) {
+    // add the terms ma = MA .. LA of one mc to L[mt] for every M tile; T = index of the term
+    // in the table.  The 3j weight multiplies the b2 operand once (it is the same bin b2 in
+    // every tile of a lane) and the product with the b1 operand of each tile is 4 FMAs.
+    __device__ __forceinline__ static void run(const float *cw, const float2 (*A1)[LA + 1], const float2 *A2,
+                                               float2 *L) {
         if constexpr (MA > LA) {
             return;
         } else {
             constexpr int MB = -MA - MC;
             if constexpr (MB >= -LB && MB <= LB) {
                 const float c = cw[T];
-                const float2 x = signed_m<MA>(A1[MA >= 0 ? MA : -MA]);
                 const float2 y = signed_m<MB>(A2[MB >= 0 ? MB : -MB]);
-                L.x += c * (x.x * y.x - x.y * y.y);
-                L.y += c * (x.x * y.y + x.y * y.x);
+                const float2 u = make_float2(c * y.x, c * y.y);
+#pragma unroll
+                for (int mt = 0; mt < kMT; ++mt) {
+                    const float2 x = signed_m<MA>(A1[mt][MA >= 0 ? MA : -MA]);
+                    L[mt].x += x.x * u.x - x.y * u.y;
+                    L[mt].y += x.x * u.y + x.y * u.x;
+                }
                 Couple<LA, LB, MC, MA + 1, T + 1>::run(cw, A1, A2, L);
             } else {
                 Couple<LA, LB, MC, MA + 1, T>::run(cw, A1, A2, L);
@@ -85,6 +93,8 @@ __device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
     lo = (__bf16)(v - (float)hi);
 }
 
+// Pair layout of the M tiles: lane row i of tile mt is (b1, b2) = (2 mt + i / 8, i % 8), so a
+// lane keeps the same b2 in all four tiles; pairs with a bin >= nbins hold zeros.
 template <int LA, int LB, int LC, int PREC>
 __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
     using CL = Cols<LA, LB, LC>;
@@ -94,9 +104,9 @@ __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
     __shared__ float wt[TC];
     __shared__ float red[4 * kMaxNB * kMaxNB * kMaxNB];
     const int nb = a.nbins;
-    const int npair = nb * nb;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i = lane & 15, g = lane >> 4;
+    const int b2 = i & 7, bh = i >> 3;
     const float *cw = a.coefw;   // weighted 3j values of this Lambda, table order (mc outer, ma inner)
     f4v acc[kMT];
 #pragma unroll
@@ -115,63 +125,52 @@ __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
         }
         for (int c = tid; c < TC; c += 256) wt[c] = c < ncell ? a.w[tc + c] : 0.f;
         __syncthreads();
-        // this lane's cells: 16 wave + 4 g + cc
-        const int cbase = 16 * wave + 4 * g;
-        // B operand: bin i of the LC coefficients, per mc and cell
-        float2 bv[LC + 1][4];
+        // this lane's cells: 16 wave + 4 g + cc, one at a time (K of the MFMA = the lane groups)
 #pragma unroll
-        for (int mc = 0; mc <= LC; ++mc)
+        for (int cc = 0; cc < 4; ++cc) {
+            const float2 *row = tile + (16 * wave + 4 * g + cc) * NCOL * kMaxNB;
+            const float wv = wt[16 * wave + 4 * g + cc];
+            float2 A1[kMT][LA + 1], A2[LB + 1], bv[LC + 1];
 #pragma unroll
-            for (int cc = 0; cc < 4; ++cc)
-                bv[mc][cc] = i < kMaxNB ? tile[((cbase + cc) * NCOL + CL::offC + mc) * kMaxNB + i] : make_float2(0.f, 0.f);
-#pragma unroll
-        for (int mt = 0; mt < kMT; ++mt) {
-            if (16 * mt >= npair) break;
-            const int p = 16 * mt + i;
-            const bool ok = p < npair;
-            const int b1 = ok ? p / nb : 0, b2 = ok ? p % nb : 0;
-            float2 A1[4][LA + 1], A2[4][LB + 1];
-#pragma unroll
-            for (int cc = 0; cc < 4; ++cc) {
-                const float2 *row = tile + (cbase + cc) * NCOL * kMaxNB;
-                const float wv = ok ? wt[cbase + cc] : 0.f;
+            for (int mt = 0; mt < kMT; ++mt)
 #pragma unroll
                 for (int m = 0; m <= LA; ++m) {
-                    const float2 v = row[(CL::offA + m) * kMaxNB + b1];
-                    A1[cc][m] = make_float2(wv * v.x, wv * v.y);
+                    const float2 v = row[(CL::offA + m) * kMaxNB + 2 * mt + bh];   // zero beyond nbins
+                    A1[mt][m] = make_float2(wv * v.x, wv * v.y);
                 }
 #pragma unroll
-                for (int m = 0; m <= LB; ++m) A2[cc][m] = row[(CL::offB + m) * kMaxNB + b2];
-            }
-            f4v &am = acc[mt];
-            // one mc: couple, then contract on the matrix cores (the mc loop is unrolled below)
+            for (int m = 0; m <= LB; ++m) A2[m] = row[(CL::offB + m) * kMaxNB + b2];
+#pragma unroll
+            for (int mc = 0; mc <= LC; ++mc)
+                bv[mc] = i < kMaxNB ? row[(CL::offC + mc) * kMaxNB + i] : make_float2(0.f, 0.f);
+            // one mc: couple, then contract on the matrix cores (unrolled over mc below)
             auto step = [&](auto mc_c) {
                 constexpr int MC = decltype(mc_c)::value;
-                float2 L[4];
+                float2 L[kMT];
 #pragma unroll
-                for (int cc = 0; cc < 4; ++cc) {
-                    L[cc] = make_float2(0.f, 0.f);
-                    Couple<LA, LB, MC, -LA, terms_before<LA, LB>(MC)>::run(cw, A1[cc], A2[cc], L[cc]);
-                }
+                for (int mt = 0; mt < kMT; ++mt) L[mt] = make_float2(0.f, 0.f);
+                Couple<LA, LB, MC, -LA, terms_before<LA, LB>(MC)>::run(cw, A1, A2, L);
                 if constexpr (PREC == 0) {
 #pragma unroll
-                    for (int cc = 0; cc < 4; ++cc) {
-                        am = __builtin_amdgcn_mfma_f32_16x16x4f32(L[cc].x, bv[MC][cc].x, am, 0, 0, 0);
-                        am = __builtin_amdgcn_mfma_f32_16x16x4f32(-L[cc].y, bv[MC][cc].y, am, 0, 0, 0);
+                    for (int mt = 0; mt < kMT; ++mt) {
+                        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(L[mt].x, bv[MC].x, acc[mt], 0, 0, 0);
+                        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-L[mt].y, bv[MC].y, acc[mt], 0, 0, 0);
                     }
                 } else {
-                    bf8v ah, al, bh, bl;
+                    // K slots 0 and 1 of each lane group carry (re, im) of its cell, the rest zero
+                    bf8v bhv = {}, blv = {};
+                    __bf16 h, l;
+                    split_bf16(bv[MC].x, h, l); bhv[0] = h; blv[0] = l;
+                    split_bf16(bv[MC].y, h, l); bhv[1] = h; blv[1] = l;
 #pragma unroll
-                    for (int cc = 0; cc < 4; ++cc) {
-                        __bf16 h, l;
-                        split_bf16(L[cc].x, h, l); ah[2 * cc] = h; al[2 * cc] = l;
-                        split_bf16(-L[cc].y, h, l); ah[2 * cc + 1] = h; al[2 * cc + 1] = l;
-                        split_bf16(bv[MC][cc].x, h, l); bh[2 * cc] = h; bl[2 * cc] = l;
-                        split_bf16(bv[MC][cc].y, h, l); bh[2 * cc + 1] = h; bl[2 * cc + 1] = l;
+                    for (int mt = 0; mt < kMT; ++mt) {
+                        bf8v ahv = {}, alv = {};
+                        split_bf16(L[mt].x, h, l); ahv[0] = h; alv[0] = l;
+                        split_bf16(-L[mt].y, h, l); ahv[1] = h; alv[1] = l;
+                        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahv, bhv, acc[mt], 0, 0, 0);
+                        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahv, blv, acc[mt], 0, 0, 0);
+                        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alv, bhv, acc[mt], 0, 0, 0);
                     }
-                    am = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, am, 0, 0, 0);
-                    am = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, am, 0, 0, 0);
-                    am = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, am, 0, 0, 0);
                 }
             };
             [&]<int... MCS>(std::integer_sequence<int, MCS...>) {
@@ -179,17 +178,19 @@ __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
             }(std::make_integer_sequence<int, LC + 1>{});
         }
     }
-    // accumulator tile mt: lane l holds rows 4 g + r (pair 16 mt + 4 g + r), column i (bin b3)
+    // accumulator tile mt: lane l holds rows 4 g + r (pair (b1, b2) = ((16 mt + 4 g + r) / 8,
+    // (16 mt + 4 g + r) % 8)), column i (bin b3)
     __syncthreads();
-    const int nv = npair * nb;
+    const int nv = nb * nb * nb;
     for (int v = tid; v < 4 * nv; v += 256) red[v] = 0.f;
     __syncthreads();
 #pragma unroll
     for (int mt = 0; mt < kMT; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int p = 16 * mt + 4 * g + r;
-            if (p < npair && i < nb) red[wave * nv + p * nb + i] = acc[mt][r];
+            const int pr = 16 * mt + 4 * g + r;
+            const int p1 = pr >> 3, p2 = pr & 7;
+            if (p1 < nb && p2 < nb && i < nb) red[wave * nv + (p1 * nb + p2) * nb + i] = acc[mt][r];
         }
     __syncthreads();
     for (int v = tid; v < nv; v += 256) {
