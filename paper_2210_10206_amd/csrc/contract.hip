@@ -345,7 +345,7 @@ hipError_t launch_quad_mfma_part1(int la, int lb, int lc, const QuadMArgs &a, hi
 hipError_t launch_quad_mfma_part2(int la, int lb, int lc, const QuadMArgs &a, hipStream_t s);
 
 bool quad_mfma_available(int la, int lb, int lc, int nbins) {
-    return nbins <= 8 && la <= 4 && lb <= 4 && lc <= 4;
+    return nbins <= 8 && la <= 4 && lb <= 4 && lc <= 4 && ((la + lb + lc) & 1) == 0;
 }
 
 hipError_t launch_quad_mfma(int la, int lb, int lc, const QuadMArgs &a, hipStream_t s) {

@@ -62,17 +62,59 @@ struct Couple {
             if constexpr (MB >= -LB && MB <= LB) {
                 const float c = cw[T];
                 const float2 y = signed_m<MB>(A2[MB >= 0 ? MB : -MB]);
-                const float2 u = make_float2(c * y.x, c * y.y);
+                // a_{l0} is real (real field, real Y_l0): m = 0 operands use their real part only
+                const float2 u = MB == 0 ? make_float2(c * y.x, 0.f) : make_float2(c * y.x, c * y.y);
 #pragma unroll
                 for (int mt = 0; mt < kMT; ++mt) {
                     const float2 x = signed_m<MA>(A1[mt][MA >= 0 ? MA : -MA]);
-                    L[mt].x += x.x * u.x - x.y * u.y;
-                    L[mt].y += x.x * u.y + x.y * u.x;
+                    if constexpr (MA == 0) {
+                        L[mt].x = __builtin_fmaf(x.x, u.x, L[mt].x);
+                        L[mt].y = __builtin_fmaf(x.x, u.y, L[mt].y);
+                    } else if constexpr (MB == 0) {
+                        L[mt].x = __builtin_fmaf(x.x, u.x, L[mt].x);
+                        L[mt].y = __builtin_fmaf(x.y, u.x, L[mt].y);
+                    } else {
+                        L[mt].x = __builtin_fmaf(x.x, u.x, L[mt].x);
+                        L[mt].x = __builtin_fmaf(-x.y, u.y, L[mt].x);
+                        L[mt].y = __builtin_fmaf(x.x, u.y, L[mt].y);
+                        L[mt].y = __builtin_fmaf(x.y, u.x, L[mt].y);
+                    }
                 }
                 Couple<LA, LB, MC, MA + 1, T + 1>::run(cw, A1, A2, L);
             } else {
                 Couple<LA, LB, MC, MA + 1, T>::run(cw, A1, A2, L);
             }
+        }
+    }
+};
+
+// mc = 0 of an even Lambda: the terms ma and -ma are complex conjugates of each other
+// (a_{l,-m} = (-1)^m conj a_{lm} and the 3j symbol is even under m -> -m when l1 + l2 + l3 is
+// even), so L_0 = C_0 a^b1_{LA,0} a^b2_{LB,0} + sum_{ma > 0} 2 (-1)^ma C_ma Re(a^b1_{LA,ma}
+// conj a^b2_{LB,ma}) is real: 2 FMAs per ma > 0 instead of 8, and one MFMA instead of two.
+// C_ma is the table entry of (ma, -ma, 0), at position ma + min(LA, LB) of the mc = 0 terms.
+template <int LA, int LB, int MA>
+struct Couple0 {
+    __device__ __forceinline__ static void run(const float *cw, const float2 (*A1)[LA + 1], const float2 *A2,
+                                               float2 *L) {
+        if constexpr (MA > LA || MA > LB) {
+            return;
+        } else {
+            constexpr int T = MA + (LA < LB ? LA : LB);
+            if constexpr (MA == 0) {
+                const float u = cw[T] * A2[0].x;
+#pragma unroll
+                for (int mt = 0; mt < kMT; ++mt) L[mt].x = __builtin_fmaf(A1[mt][0].x, u, L[mt].x);
+            } else {
+                const float c = ((MA & 1) ? -2.f : 2.f) * cw[T];
+                const float2 u = make_float2(c * A2[MA].x, c * A2[MA].y);
+#pragma unroll
+                for (int mt = 0; mt < kMT; ++mt) {
+                    L[mt].x = __builtin_fmaf(A1[mt][MA].x, u.x, L[mt].x);
+                    L[mt].x = __builtin_fmaf(A1[mt][MA].y, u.y, L[mt].x);
+                }
+            }
+            Couple0<LA, LB, MA + 1>::run(cw, A1, A2, L);
         }
     }
 };
@@ -149,12 +191,16 @@ __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
                 float2 L[kMT];
 #pragma unroll
                 for (int mt = 0; mt < kMT; ++mt) L[mt] = make_float2(0.f, 0.f);
-                Couple<LA, LB, MC, -LA, terms_before<LA, LB>(MC)>::run(cw, A1, A2, L);
+                if constexpr (MC == 0)
+                    Couple0<LA, LB, 0>::run(cw, A1, A2, L);
+                else
+                    Couple<LA, LB, MC, -LA, terms_before<LA, LB>(MC)>::run(cw, A1, A2, L);
                 if constexpr (PREC == 0) {
 #pragma unroll
                     for (int mt = 0; mt < kMT; ++mt) {
                         acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(L[mt].x, bv[MC].x, acc[mt], 0, 0, 0);
-                        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-L[mt].y, bv[MC].y, acc[mt], 0, 0, 0);
+                        if constexpr (MC > 0)   // L_0 and a_{l0} are real
+                            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-L[mt].y, bv[MC].y, acc[mt], 0, 0, 0);
                     }
                 } else {
                     // K slots 0 and 1 of each lane group carry (re, im) of its cell, the rest zero
