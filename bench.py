@@ -236,6 +236,42 @@ def run_c5(api, steps, warmup, synth_steps=200):
                           "loss_start": losses[0], "loss_end": losses[-1]}}
 
 
+def run_512(api, steps, warmup):
+    """Full 3PCF of one 512^3 field (the 2x2x2 tiling of the sigma 0.5 seed 0 256^3 field: the
+    generator's 512^3 FFT would dominate the run), 10 bins to 32, lmax 6: cold set-up and
+    warm fields/s with the kernel arrays in chunks of (l, m) groups."""
+    import torch
+    from fieldgen import lognormal_field, linear_edges
+    d = torch.from_numpy(lognormal_field((256,) * 3, seed=0, sigma=0.5)).cuda().repeat(2, 2, 2).contiguous()
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = api.Plan([tuple(d.shape)], linear_edges(32, 10), 6, npcf=3, prepare=False)
+    with torch.cuda.stream(stream):
+        plan.prepare(stream)
+    stream.synchronize()
+    cold = time.perf_counter() - t0
+    out = torch.empty((1, plan.zeta_doubles), dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            plan.forward_raw([d], out=out, stream=stream)
+    stream.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(steps):
+            plan.forward_raw([d], out=out, stream=stream)
+    stream.synchronize()
+    el = time.perf_counter() - t0
+    res = {"workload": "full 3PCF of one 512^3 float32 field (2x2x2 tiling of the 256^3 sigma 0.5 field), "
+                       "10 bins over (0,32], lmax 6",
+           "value": round(steps / el, 3), "unit": "fields/s", "ms_per_field": round(el / steps * 1e3, 2),
+           "cold_setup_ms": round(cold * 1e3, 1),
+           "persistent_GiB": round(plan.persistent_bytes / 2 ** 30, 2),
+           "scratch_GiB": round(plan.scratch_bytes / 2 ** 30, 2)}
+    plan.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,6 +286,7 @@ def main():
     ap.add_argument("--c4-steps", type=int, default=1, help="steps of the 128^3 4PCF batch (0 skips it)")
     ap.add_argument("--c5-steps", type=int, default=1,
                     help="steps of the uneven-batch forward + adjoint and the synthesis demo (0 skips them)")
+    ap.add_argument("--big-steps", type=int, default=1, help="steps of the 512^3 3PCF line (0 skips it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times (the reference "
                          "dispatch that scales the HBM byte counters of a counter run)")
@@ -373,6 +410,11 @@ def main():
                 "value": r["value"], "contraction_ms_per_field": r["contraction"]["ms_per_field"],
                 "achieved_tflops": r["contraction"]["achieved_tflops"], "kernel": r["contraction"]["kernel"]}
         c4["other_contraction_paths"] = variants
+    big = None
+    if args.big_steps > 0:
+        print("bench: 512^3 3PCF", file=sys.stderr, flush=True)
+        big = run_512(api, args.big_steps, 1)
+        torch.cuda.empty_cache()
     c5 = None
     if args.c5_steps > 0:
         print("bench: uneven batch forward + adjoint, synthesis demo", file=sys.stderr, flush=True)
@@ -397,6 +439,7 @@ def main():
         "max_rel_err_vs_oracle": errs or None,
         "secondary_4pcf_128": c4,
         "secondary_uneven_adjoint": c5,
+        "secondary_3pcf_512": big,
     }
     print(json.dumps(line), flush=True)
 

@@ -107,6 +107,15 @@ void sb_plan_destroy(sb_plan *plan);
  * distinct shape (kept between calls), `scratch` the per-field working arrays. */
 sb_status sb_plan_workspace(const sb_plan *plan, size_t *persistent_bytes, size_t *scratch_bytes);
 
+/* Cap the scratch a 3PCF plan uses for its kernel arrays (default 48 GiB).  When all
+ * N_k = nbins (lmax+1)(lmax+2)/2 arrays of the largest field would exceed `bytes`, sb_forward
+ * (fused path) and sb_backward run the three passes over chunks of (l, m) groups, so that
+ * grids such as 512^3 fit next to their kernel cache.  Call between sb_plan_create and
+ * sb_plan_bind (SB_ESTATE afterwards); sb_plan_workspace then reports the new scratch size.
+ * Plans that need every array at once (4PCFs, SB_FLAG_KEEP_COEFFS) ignore the cap;
+ * SB_FLAG_UNFUSED 3PCF plans return SB_EUNSUPPORTED from sb_forward when chunked. */
+sb_status sb_plan_set_scratch_limit(sb_plan *plan, uint64_t bytes);
+
 /* Bind caller-owned device buffers (at least the sizes above, 256-byte aligned). */
 sb_status sb_plan_bind(sb_plan *plan, void *persistent, size_t persistent_bytes,
                        void *scratch, size_t scratch_bytes);

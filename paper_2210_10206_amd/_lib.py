@@ -33,6 +33,7 @@ SIGNATURES = {
     "sb_plan_create": (c_i32, [P(SbProblem), c_i32, P(c_i64), P(c_vp)]),
     "sb_plan_destroy": (None, [c_vp]),
     "sb_plan_workspace": (c_i32, [c_vp, P(c_sz), P(c_sz)]),
+    "sb_plan_set_scratch_limit": (c_i32, [c_vp, ctypes.c_uint64]),
     "sb_plan_bind": (c_i32, [c_vp, c_vp, c_sz, c_vp, c_sz]),
     "sb_prepare": (c_i32, [c_vp, c_vp]),
     "sb_zeta_size": (c_i32, [c_vp, P(c_i64)]),

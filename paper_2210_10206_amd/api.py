@@ -42,10 +42,14 @@ class Plan:
     npcf       : 3 or 4
     precision  : "fp32" or "split_bf16" (contraction arithmetic of the 4PCF paths)
     input_dtype: torch.float32 or torch.float64 (the density arrays' dtype)
+    mfma       : full 4PCF: use the matrix-core contraction where it exists (l <= 4, <= 8 bins)
+    scratch_limit: bytes of kernel arrays a 3PCF plan keeps at once (default 48 GiB); above it
+                 the passes run over chunks of (l, m) groups (sb_plan_set_scratch_limit)
     """
 
     def __init__(self, shapes, bin_edges, lmax, npcf=3, precision="fp32", input_dtype=torch.float32,
-                 device=None, stream=None, prepare=True, keep_coeffs=False, fused=True, mfma=True):
+                 device=None, stream=None, prepare=True, keep_coeffs=False, fused=True, mfma=True,
+                 scratch_limit=None):
         self.lib = _lib.load()
         shapes = [tuple(int(x) for x in s) for s in shapes]
         ndim = len(shapes[0])
@@ -71,6 +75,9 @@ class Plan:
                                           sh.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(handle)),
                   "sb_plan_create")
         self.handle = handle
+        if scratch_limit is not None:
+            check(self.lib.sb_plan_set_scratch_limit(self.handle, ctypes.c_uint64(int(scratch_limit))),
+                  "sb_plan_set_scratch_limit")
         pb, sbytes = ctypes.c_size_t(), ctypes.c_size_t()
         check(self.lib.sb_plan_workspace(self.handle, ctypes.byref(pb), ctypes.byref(sbytes)), "sb_plan_workspace")
         self.persistent_bytes, self.scratch_bytes = pb.value, sbytes.value

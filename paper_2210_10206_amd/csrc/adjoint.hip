@@ -95,7 +95,7 @@ sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta
         if (!delta[f] || !grad_delta[f]) return fail(SB_EINVAL, "null field pointer");
         const ShapeGroup &G = p->groups[p->field_group[f]];
         const float2 *khat = reinterpret_cast<const float2 *>(p->persist + G.khat_off);
-        sb_status st = coefficients(p, f, delta[f], s);   // recompute a (never stored across calls)
+        sb_status st = density_spectrum(p, G, delta[f], s);
         if (st != SB_OK) return st;
         const int nt = 256;
         const unsigned nblk = (unsigned)((G.ng + nt - 1) / nt);
@@ -103,11 +103,18 @@ sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "adjoint zero");
         const double *gz_f = grad_zeta + (int64_t)f * p->zeta_doubles;
+        int g0 = 0, gend = 0;   // kernel groups whose coefficients are in scratch
         for (int l = 0; l <= p->prob.lmax; ++l)
             for (int m = 0; m <= l; ++m) {
                 const int lm = l * (l + 1) / 2 + m;
+                if (lm >= gend) {   // recompute a for the next chunk of groups (never stored across calls)
+                    g0 = lm;
+                    gend = std::min(p->nlm, lm + p->chunk_groups);
+                    st = coefficients(p, f, g0, gend - g0, s);
+                    if (st != SB_OK) return st;
+                }
                 AdjPrepArgs a{};
-                a.coef = coef + (int64_t)lm * NB * G.ng;
+                a.coef = coef + (int64_t)(lm - g0) * NB * G.ng;
                 a.w = w;
                 a.gz = gz_f + (int64_t)l * NB * NB;
                 a.nbins = NB;

@@ -108,6 +108,38 @@ static void contraction_shape(const sb_plan *p, int64_t ng, int *groups, int *nv
     }
 }
 
+// Scratch layout.  A 3PCF plan whose full set of kernel arrays exceeds coef_limit runs its
+// passes over chunks of kernel groups (the fused contraction and the adjoint only need one
+// group's bins at a time); every other plan keeps all arrays at once.
+void layout_scratch(sb_plan *p) {
+    const sb_problem *prob = &p->prob;
+    const int NB = prob->nbins;
+    const uint64_t per_group = (uint64_t)NB * p->max_ng * sizeof(float2);
+    p->chunk_groups = p->nlm;
+    const bool chunkable = prob->npcf == 3 && (prob->flags & SB_FLAG_KEEP_COEFFS) == 0;
+    if (chunkable && per_group * p->nlm > p->coef_limit)
+        p->chunk_groups = (int)std::max<uint64_t>(1, std::min<uint64_t>(p->nlm, p->coef_limit / per_group));
+    size_t sc = 0;
+    p->off_w = sc; sc += align256((size_t)p->max_ng * sizeof(float));
+    p->off_dhat = sc; sc += align256((size_t)p->max_ng * sizeof(float2));
+    p->off_coef = sc; sc += align256((size_t)p->chunk_groups * NB * p->max_ng * sizeof(float2));
+    int groups = 0, nvals = 0, nblocks = 0;
+    contraction_shape(p, p->max_ng, &groups, &nvals, &nblocks);
+    for (const auto &G : p->groups)
+        if (G.rows > 0 && prob->npcf == 3) {
+            const int64_t nrows = G.ng / G.n[prob->ndim - 1];
+            nblocks = std::max<int>(nblocks, (int)((nrows + G.rows_per_block - 1) / G.rows_per_block));
+        }
+    p->off_part = sc; sc += align256((size_t)groups * nvals * nblocks * sizeof(double));
+    p->off_tot = sc; sc += align256((size_t)groups * nvals * sizeof(double));
+    p->off_grad = sc; sc += align256((size_t)p->max_ng * sizeof(float2));
+    if (prob->ndim == 3 && prob->npcf == 3) {
+        p->off_vtmp = sc; sc += align256((size_t)NB * p->max_ng * sizeof(float2));
+        p->off_dsum = sc; sc += align256((size_t)p->max_ng * sizeof(float));
+    }
+    p->scratch_need = sc;
+}
+
 sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shapes, sb_plan **out) {
     if (!prob || !shapes || !out) return fail(SB_EINVAL, "null argument");
     *out = nullptr;
@@ -338,25 +370,7 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
         }
     }
     p->persist_need = pers;
-    size_t sc = 0;
-    p->off_w = sc; sc += align256((size_t)p->max_ng * sizeof(float));
-    p->off_dhat = sc; sc += align256((size_t)p->max_ng * sizeof(float2));
-    p->off_coef = sc; sc += align256((size_t)p->nk * p->max_ng * sizeof(float2));
-    int groups = 0, nvals = 0, nblocks = 0;
-    contraction_shape(p, p->max_ng, &groups, &nvals, &nblocks);
-    for (const auto &G : p->groups)
-        if (G.rows > 0 && prob->npcf == 3) {
-            const int64_t nrows = G.ng / G.n[prob->ndim - 1];
-            nblocks = std::max<int>(nblocks, (int)((nrows + G.rows_per_block - 1) / G.rows_per_block));
-        }
-    p->off_part = sc; sc += align256((size_t)groups * nvals * nblocks * sizeof(double));
-    p->off_tot = sc; sc += align256((size_t)groups * nvals * sizeof(double));
-    p->off_grad = sc; sc += align256((size_t)p->max_ng * sizeof(float2));
-    if (prob->ndim == 3 && prob->npcf == 3) {
-        p->off_vtmp = sc; sc += align256((size_t)NB * p->max_ng * sizeof(float2));
-        p->off_dsum = sc; sc += align256((size_t)p->max_ng * sizeof(float));
-    }
-    p->scratch_need = sc;
+    layout_scratch(p);
     *out = p;
     return SB_OK;
 }
@@ -444,7 +458,9 @@ sb_status prepare(sb_plan *p, hipStream_t s) {
 }
 
 // First inverse pass: axis-0 correlation of every kernel group with the density spectrum.
-static sb_status axis0_corr(sb_plan *p, const ShapeGroup &G, const float2 *dhat, float2 *out, hipStream_t s) {
+static sb_status axis0_corr(sb_plan *p, const ShapeGroup &G, const float2 *dhat, float2 *out, int g0, int ngr,
+                            hipStream_t s) {
+    const int NB = p->prob.nbins;
     Axis0Args a{};
     a.n = (int)G.n[0];
     a.plane = G.plane;
@@ -453,20 +469,21 @@ static sb_status axis0_corr(sb_plan *p, const ShapeGroup &G, const float2 *dhat,
     a.r0 = G.r0;
     a.mode = 0;
     a.dhat = dhat;
-    a.kc = reinterpret_cast<const float2 *>(p->persist + G.khat_off);
+    a.kc = reinterpret_cast<const float2 *>(p->persist + G.khat_off) + (int64_t)g0 * NB * G.np * G.plane;
     a.out = out;
-    a.nb = p->prob.nbins;
-    a.groups = p->nlm;
+    a.nb = NB;
+    a.groups = ngr;
     a.tw = p->tw.at(a.n);
     // traffic: stored kernel planes read, outputs written, density spectrum read once per group
-    const double bytes = (double)p->nk * (8.0 * G.np * G.plane + 8.0 * G.ng) + (double)p->nlm * 8.0 * G.ng;
-    const hipError_t e = p->timed_launch(STAGE_FFT, K_AXIS0, s, [&]() { return launch_axis0(a, s); }, a.n, 1, p->nk, bytes);
+    const int nk = ngr * NB;
+    const double bytes = (double)nk * (8.0 * G.np * G.plane + 8.0 * G.ng) + (double)ngr * 8.0 * G.ng;
+    const hipError_t e = p->timed_launch(STAGE_FFT, K_AXIS0, s, [&]() { return launch_axis0(a, s); }, a.n, 1, nk, bytes);
     if (e != hipSuccess) return hip_fail(e, "axis-0 correlation pass");
     return SB_OK;
 }
 
 // Density ingest and spectrum (the first step of Alg. 3 / Alg. 4).
-static sb_status density_spectrum(sb_plan *p, const ShapeGroup &G, const void *delta, hipStream_t s) {
+sb_status density_spectrum(sb_plan *p, const ShapeGroup &G, const void *delta, hipStream_t s) {
     float *w = reinterpret_cast<float *>(p->scratch + p->off_w);
     float2 *dhat = reinterpret_cast<float2 *>(p->scratch + p->off_dhat);
     hipError_t e = launch_to_f32(delta, p->prob.input_dtype, G.ng, w, s);
@@ -474,17 +491,17 @@ static sb_status density_spectrum(sb_plan *p, const ShapeGroup &G, const void *d
     return fft_all_axes(p, G, -1, LOAD_R32, w, 0, dhat, 0, 1, s);
 }
 
-// Coefficients of every kernel for one field into scratch (Alg. 3 / Alg. 4 as a correlation).
-sb_status coefficients(sb_plan *p, int f, const void *delta, hipStream_t s) {
+// Coefficients of kernel groups [g0, g0 + ngr) of one field into scratch (Alg. 3 / Alg. 4
+// as a correlation); the density spectrum is already in scratch.
+sb_status coefficients(sb_plan *p, int f, int g0, int ngr, hipStream_t s) {
     const ShapeGroup &G = p->groups[p->field_group[f]];
     float2 *dhat = reinterpret_cast<float2 *>(p->scratch + p->off_dhat);
     float2 *coef = reinterpret_cast<float2 *>(p->scratch + p->off_coef);
-    sb_status st = density_spectrum(p, G, delta, s);
-    if (st != SB_OK) return st;
-    st = axis0_corr(p, G, dhat, coef, s);
+    sb_status st = axis0_corr(p, G, dhat, coef, g0, ngr, s);
     if (st != SB_OK) return st;
     const int axes[2] = {1, 2};
-    st = fft_axes(p, G.n, p->prob.ndim, G.ng, axes, p->prob.ndim - 1, +1, LOAD_C, coef, G.ng, coef, G.ng, p->nk, s);
+    st = fft_axes(p, G.n, p->prob.ndim, G.ng, axes, p->prob.ndim - 1, +1, LOAD_C, coef, G.ng, coef, G.ng,
+                  ngr * p->prob.nbins, s);
     if (st != SB_OK) return st;
     p->last_ng = G.ng;
     return SB_OK;
@@ -502,34 +519,39 @@ static sb_status fused_3pcf(sb_plan *p, int f, const void *delta, double *zeta_f
     double *tot = reinterpret_cast<double *>(p->scratch + p->off_tot);
     sb_status st = density_spectrum(p, G, delta, s);
     if (st != SB_OK) return st;
-    st = axis0_corr(p, G, dhat, coef, s);
-    if (st != SB_OK) return st;
-    if (nd == 3) {
-        const int axes[1] = {1};
-        st = fft_axes(p, G.n, nd, G.ng, axes, 1, +1, LOAD_C, coef, G.ng, coef, G.ng, p->nk, s);
-        if (st != SB_OK) return st;
-    }
-    LastArgs a{};
-    a.n = (int)G.n[nd - 1];
-    a.ng = G.ng;
-    a.in = coef;
-    a.w = w;
-    a.nb = NB;
-    a.groups = p->nlm;
-    a.rows = G.rows;
-    a.rows_per_block = G.rows_per_block;
-    const int64_t nrows = G.ng / a.n;
-    a.nblocks = (int)((nrows + G.rows_per_block - 1) / G.rows_per_block);
-    a.want_imag = nd == 2;
-    a.partial = part;
-    a.tw = p->tw.at(a.n);
+    const int64_t nrows = G.ng / G.n[nd - 1];
+    const int nblocks = (int)((nrows + G.rows_per_block - 1) / G.rows_per_block);
     const int nv = NB * (NB + 1) / 2 * (nd == 2 ? 2 : 1);
-    const double bytes = (double)p->nk * 8.0 * G.ng + (double)p->nlm * 4.0 * G.ng;
-    const double flops = (double)G.ng * p->nlm * (2.0 * NB + NB * (NB + 1) / 2.0 * (nd == 2 ? 8.0 : 4.0));
-    hipError_t e = p->timed_launch(STAGE_CONTRACT, K_LAST, s, [&]() { return launch_last_contract(a, s); }, a.n, 1, p->nk,
-                                   bytes, flops);
-    if (e != hipSuccess) return hip_fail(e, "fused last pass");
-    e = launch_block_sum(part, p->nlm, a.nblocks, nv, tot, s);
+    hipError_t e = hipSuccess;
+    for (int g0 = 0; g0 < p->nlm; g0 += p->chunk_groups) {
+        const int ngr = std::min(p->chunk_groups, p->nlm - g0);
+        st = axis0_corr(p, G, dhat, coef, g0, ngr, s);
+        if (st != SB_OK) return st;
+        if (nd == 3) {
+            const int axes[1] = {1};
+            st = fft_axes(p, G.n, nd, G.ng, axes, 1, +1, LOAD_C, coef, G.ng, coef, G.ng, ngr * NB, s);
+            if (st != SB_OK) return st;
+        }
+        LastArgs a{};
+        a.n = (int)G.n[nd - 1];
+        a.ng = G.ng;
+        a.in = coef;
+        a.w = w;
+        a.nb = NB;
+        a.groups = ngr;
+        a.rows = G.rows;
+        a.rows_per_block = G.rows_per_block;
+        a.nblocks = nblocks;
+        a.want_imag = nd == 2;
+        a.partial = part + (int64_t)g0 * nv * nblocks;
+        a.tw = p->tw.at(a.n);
+        const double bytes = (double)ngr * NB * 8.0 * G.ng + (double)ngr * 4.0 * G.ng;
+        const double flops = (double)G.ng * ngr * (2.0 * NB + NB * (NB + 1) / 2.0 * (nd == 2 ? 8.0 : 4.0));
+        e = p->timed_launch(STAGE_CONTRACT, K_LAST, s, [&]() { return launch_last_contract(a, s); }, a.n, 1, ngr * NB,
+                            bytes, flops);
+        if (e != hipSuccess) return hip_fail(e, "fused last pass");
+    }
+    e = launch_block_sum(part, p->nlm, nblocks, nv, tot, s);
     if (e != hipSuccess) return hip_fail(e, "block sum");
     e = launch_gather(tot, p->d_gptr, p->d_gidx, p->d_gcoef, p->gather_nout, zeta_f, s);
     if (e != hipSuccess) return hip_fail(e, "gather");
@@ -655,10 +677,13 @@ sb_status forward(sb_plan *p, const void *const *delta, double *zeta, hipStream_
         double *zf = zeta + (int64_t)f * p->zeta_doubles;
         const ShapeGroup &G = p->groups[p->field_group[f]];
         sb_status st;
+        if (p->chunk_groups < p->nlm && !(p->prob.npcf == 3 && p->fused && G.rows > 0))
+            return fail(SB_EUNSUPPORTED, "this path needs every kernel array at once; raise the scratch limit");
         if (p->prob.npcf == 3 && p->fused && G.rows > 0) {
             st = fused_3pcf(p, f, delta[f], zf, s);
         } else {
-            st = coefficients(p, f, delta[f], s);
+            st = density_spectrum(p, G, delta[f], s);
+            if (st == SB_OK) st = coefficients(p, f, 0, p->nlm, s);
             if (st == SB_OK) st = contract(p, f, zf, s);
         }
         if (st != SB_OK) return st;
@@ -689,6 +714,15 @@ sb_status sb_plan_workspace(const sb_plan *p, size_t *persistent_bytes, size_t *
     if (!p || !persistent_bytes || !scratch_bytes) return fail(SB_EINVAL, "null argument");
     *persistent_bytes = p->persist_need;
     *scratch_bytes = p->scratch_need;
+    return SB_OK;
+}
+
+sb_status sb_plan_set_scratch_limit(sb_plan *p, uint64_t bytes) {
+    if (!p) return fail(SB_EINVAL, "null plan");
+    if (p->scratch) return fail(SB_ESTATE, "the scratch limit must be set before sb_plan_bind");
+    if (bytes == 0) return fail(SB_EINVAL, "limit must be positive");
+    p->coef_limit = bytes;
+    layout_scratch(p);
     return SB_OK;
 }
 

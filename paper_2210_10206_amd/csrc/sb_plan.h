@@ -70,6 +70,10 @@ struct sb_plan {
     size_t persist_need = 0, scratch_need = 0;
     size_t off_w = 0, off_dhat = 0, off_coef = 0, off_part = 0, off_tot = 0, off_grad = 0;
     size_t off_vtmp = 0, off_dsum = 0;
+    // kernel groups ((l, m) multiplets) whose arrays share the scratch at once: all of them,
+    // unless a 3PCF plan's full set would exceed coef_limit (then the passes run in chunks)
+    uint64_t coef_limit = 48ull << 30;
+    int chunk_groups = 0;
     bool prepared = false;
     // launch shapes (autotuned)
     int cpb_pair = 8192, cpb_quad = 1024, cpb_proj4 = 4096;
@@ -125,7 +129,11 @@ namespace sb {
 sb_status fail(sb_status s, const std::string &msg);
 sb_status hip_fail(hipError_t e, const char *what);
 sb_status forward(sb_plan *p, const void *const *delta, double *zeta, hipStream_t s);
-sb_status coefficients(sb_plan *p, int f, const void *delta, hipStream_t s);
+sb_status density_spectrum(sb_plan *p, const sb::ShapeGroup &G, const void *delta, hipStream_t s);
+// Coefficients of kernel groups [g0, g0 + ng) of field f into scratch (group g0 first); the
+// density spectrum must be in scratch already.
+sb_status coefficients(sb_plan *p, int f, int g0, int ngroups, hipStream_t s);
+void layout_scratch(sb_plan *p);
 sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s);
 // FFT passes over the listed axes (in order) of arrays with extents n[0..ndim) and ncell
 // cells; the first pass reads `in` with load mode `first_load`, later passes work in place

@@ -134,6 +134,30 @@ def test_full3pcf_256(api, seed, sigma):
     plan.close()
 
 
+def test_full3pcf_512_tiled(api):
+    """512^3 (kernel arrays in chunks of (l, m) groups next to the 38 GB compact cache): the
+    2 x 2 x 2 periodic tiling of a 256^3 field has the same coefficients at every cell as the
+    256^3 field (every kernel offset is shorter than the 256 period), so its sums are exactly
+    8 times the 256^3 sums."""
+    say("case: 512^3 = 2x2x2 tiling of the 256^3 sigma 0.5 seed 0 field, 10 bins to 32, lmax 6")
+    d = lognormal_field((256,) * 3, seed=0, sigma=0.5)
+    edges = linear_edges(32, 10)
+    p256 = api.Plan([d.shape], edges, 6, npcf=3)
+    z256 = p256.forward([torch.from_numpy(d).cuda()])[0].cpu().numpy()
+    p256.close()
+    del p256
+    torch.cuda.empty_cache()
+    big = torch.from_numpy(d).cuda().repeat(2, 2, 2).contiguous()
+    p512 = api.Plan([tuple(big.shape)], edges, 6, npcf=3)
+    say(f"  512^3 plan: persistent {p512.persistent_bytes / 2**30:.1f} GiB, scratch {p512.scratch_bytes / 2**30:.1f} GiB")
+    z512 = p512.forward([big])[0].cpu().numpy()
+    torch.cuda.synchronize()
+    p512.close()
+    e = rel_err(z512, 8.0 * z256)
+    say(f"  max |Z_512 - 8 Z_256| / max |8 Z_256| = {e:.3e}")
+    assert e < TOL32
+
+
 def test_coefficients_256_sampled(api):
     say("case: 256^3 coefficients at 24 sampled cells vs the oracle, 10 bins to 32, lmax 6")
     d = lognormal_field((256,) * 3, seed=0, sigma=0.5)
