@@ -27,7 +27,8 @@
  *        Z = sum_x delta sum_{m=-l..l} a^b1_lm conj(a^b2_lm)          (Alg. 5)
  *  - full 4PCF  (ndim 3, npcf 4): Z[L][b1][b2][b3], real, L over the even-parity
  *        (l1, l2, l3) of Alg. 6's loop order (l1 outer, l2, then l3 from |l1-l2| to
- *        min(l1+l2, lmax));  Z = sum_x delta sum_M 3j(l1 l2 l3; m1 m2 m3) a a a   (Alg. 6, Sec. 2.3)
+ *        min(l1+l2, lmax));  Z = sum_x delta sum_M 3j(l1 l2 l3; m1 m2 m3) a a a   (Alg. 6, Sec. 2.3);
+ *        with SB_FLAG_ODD_PARITY the odd-parity L in the same loop order and Z = Im of that sum
  *  - projected 3PCF (ndim 2, npcf 3): Z[m][b1][b2] complex, m = 0..mmax;
  *        Z = sum_x delta c^b1_m conj(c^b2_m)                           (Alg. 7)
  *  - projected 4PCF (ndim 2, npcf 4): Z[p][b1][b2][b3] complex, p over (m1, m2) with m1
@@ -72,8 +73,12 @@ enum {
     SB_FLAG_UNFUSED = 2u,     /* 3PCFs: write every coefficient array, then contract in a separate
                                  pass (the plain path; the default fuses the contraction into the
                                  last FFT pass and never writes the coefficients) */
-    SB_FLAG_NO_MFMA = 4u      /* full 4PCF: use the plain float32 vector-ALU contraction even where
+    SB_FLAG_NO_MFMA = 4u,     /* full 4PCF: use the plain float32 vector-ALU contraction even where
                                  the matrix-core one exists (lmax <= 4, nbins <= 8) */
+    SB_FLAG_ODD_PARITY = 8u   /* full 4PCF: the odd-parity Lambda (l1 + l2 + l3 odd, Sec. 2.3, the
+                                 ones Alg. 6 skips) instead of the even ones; each value is the
+                                 imaginary part of the sum, whose real part vanishes for a real
+                                 density */
 };
 
 /* Problem statement: the grid, bins, lmax, full or projected, 3 or 4 PCF

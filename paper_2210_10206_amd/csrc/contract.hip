@@ -81,8 +81,9 @@ hipError_t launch_pair_nb(const PairArgs &a, hipStream_t s) {
 // ----------------------------------------------------------------- quad contraction
 // Lanes of a wave own (b1, b2) pair slots p = lane + 64 s; the four waves take
 // interleaved cells of the LDS tile.  Per cell and per m3 group of terms:
-//   L = w(x) sum_terms C a^{b1}_{la,ma} a^{b2}_{lb,mb};   acc[b3] += Re(L a^{b3}_{lc,mc}).
-template <int NB>
+//   L = w(x) sum_terms C a^{b1}_{la,ma} a^{b2}_{lb,mb};   acc[b3] += Re(L a^{b3}_{lc,mc})
+// (Im for odd Lambda: the m3 < 0 half is minus the conjugate of the m3 > 0 half there).
+template <int NB, bool ODD>
 __global__ __launch_bounds__(256) void quad_kernel(QuadArgs a) {
     constexpr int NPAIR = NB * NB;
     constexpr int SLOTS = (NPAIR + 63) / 64;
@@ -145,7 +146,8 @@ __global__ __launch_bounds__(256) void quad_kernel(QuadArgs a) {
                     L.x *= wv; L.y *= wv;
                     const float2 *r3 = tc_ + (sl[2] + mc) * NB;
 #pragma unroll
-                    for (int b3 = 0; b3 < NB; ++b3) acc[s][b3] += L.x * r3[b3].x - L.y * r3[b3].y;
+                    for (int b3 = 0; b3 < NB; ++b3)
+                        acc[s][b3] += ODD ? L.x * r3[b3].y + L.y * r3[b3].x : L.x * r3[b3].x - L.y * r3[b3].y;
                 }
             }
         }
@@ -287,7 +289,10 @@ static hipError_t launch_quad_nb(const QuadArgs &a, hipStream_t s) {
     const size_t red_bytes = (size_t)4 * NV * sizeof(double);
     const size_t shm = tile_bytes > red_bytes ? tile_bytes : red_bytes;
     dim3 grid(a.nblocks, a.nlam);
-    hipLaunchKernelGGL((quad_kernel<NB>), grid, dim3(256), shm, s, a);
+    if (a.odd)
+        hipLaunchKernelGGL((quad_kernel<NB, true>), grid, dim3(256), shm, s, a);
+    else
+        hipLaunchKernelGGL((quad_kernel<NB, false>), grid, dim3(256), shm, s, a);
     return hipGetLastError();
 }
 
@@ -345,7 +350,7 @@ hipError_t launch_quad_mfma_part1(int la, int lb, int lc, const QuadMArgs &a, hi
 hipError_t launch_quad_mfma_part2(int la, int lb, int lc, const QuadMArgs &a, hipStream_t s);
 
 bool quad_mfma_available(int la, int lb, int lc, int nbins) {
-    return nbins <= 8 && la <= 4 && lb <= 4 && lc <= 4 && ((la + lb + lc) & 1) == 0;
+    return nbins <= 8 && la <= 4 && lb <= 4 && lc <= 4;
 }
 
 hipError_t launch_quad_mfma(int la, int lb, int lc, const QuadMArgs &a, hipStream_t s) {

@@ -70,7 +70,7 @@ static sb_status build_gather(sb_plan *p, std::vector<int> &gptr, std::vector<in
                 for (int b2 = 0; b2 < NB; ++b2)
                     for (int b3 = 0; b3 < NB; ++b3) {
                         const int b[3] = {b1, b2, b3};
-                        add(c * NV + (b[pos[0]] * NB + b[pos[1]]) * NB + b[pos[2]], 1.0);
+                        add(c * NV + (b[pos[0]] * NB + b[pos[1]]) * NB + b[pos[2]], (double)p->f4.out_sign[L]);
                         close();
                     }
         }
@@ -152,6 +152,8 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
     if (prob->lmax < 0) return fail(SB_EINVAL, "lmax must be >= 0");
     if (prob->ndim == 3 && prob->lmax > kMaxL) return fail(SB_EINVAL, "lmax > 10");
     if (prob->ndim == 2 && prob->lmax > kMaxM) return fail(SB_EINVAL, "mmax > 16");
+    if ((prob->flags & SB_FLAG_ODD_PARITY) && !(prob->npcf == 4 && prob->ndim == 3))
+        return fail(SB_EINVAL, "odd parity applies to the full 4PCF only");
     if (prob->precision != SB_PREC_FP32 && prob->precision != SB_PREC_SPLIT_BF16)
         return fail(SB_EINVAL, "unknown precision");
     if (prob->input_dtype != SB_IN_F32 && prob->input_dtype != SB_IN_F64)
@@ -235,7 +237,7 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
         p->idx_cols = 1;
         for (int l = 0; l <= L; ++l) p->idx_table.push_back(l);
     } else if (prob->ndim == 3) {
-        p->f4 = make_full4_plan(L, NB);
+        p->f4 = make_full4_plan(L, NB, (prob->flags & SB_FLAG_ODD_PARITY) == 0);
         p->zeta_doubles = (int64_t)p->f4.out_lams.size() * NB * NB * NB;
         p->idx_rows = (int32_t)p->f4.out_lams.size();
         p->idx_cols = 3;
@@ -601,6 +603,7 @@ sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
         a.nlm = p->nlm;
         a.partial = part;
         a.nblocks = nblocks;
+        a.odd = (p->prob.flags & SB_FLAG_ODD_PARITY) != 0;
         // algorithmic flops per cell and Lambda: 8 per nonzero coupling term and bin pair, then
         // per mc the weight (2) and the b3 contraction (4 per bin) for each bin pair
         auto lam_flops = [&](size_t c) {

@@ -1,4 +1,6 @@
 // Full-4PCF contraction on the matrix cores, one kernel per ordered Lambda = (LA, LB, LC).
+// Even Lambda give the real part of the sums below, odd Lambda (LA + LB + LC odd) the
+// imaginary part (the other part vanishes for a real density).
 //
 // For one Lambda, with mc >= 0 and the weighted 3j symbols C (factor 2 for mc > 0, Alg. 6):
 //   L_mc[b1 b2](x) = w(x) sum_ma C(ma, mb, mc) a^b1_{LA,ma}(x) a^b2_{LB,mb}(x),  mb = -ma - mc
@@ -93,6 +95,31 @@ struct Couple {
 // even), so L_0 = C_0 a^b1_{LA,0} a^b2_{LB,0} + sum_{ma > 0} 2 (-1)^ma C_ma Re(a^b1_{LA,ma}
 // conj a^b2_{LB,ma}) is real: 2 FMAs per ma > 0 instead of 8, and one MFMA instead of two.
 // C_ma is the table entry of (ma, -ma, 0), at position ma + min(LA, LB) of the mc = 0 terms.
+// mc = 0 of an odd Lambda: the pair (ma, -ma) gives 2 i (-1)^ma C_ma Im(a^b1_{LA,ma} conj
+// a^b2_{LB,ma}) (the 3j symbol is odd under m -> -m, and the ma = 0 symbol vanishes), so L_0
+// is imaginary: L_0.y = sum_{ma > 0} 2 (-1)^ma C_ma (x.y y.x - x.x y.y).
+template <int LA, int LB, int MA>
+struct Couple0Odd {
+    __device__ __forceinline__ static void run(const float *cw, const float2 (*A1)[LA + 1], const float2 *A2,
+                                               float2 *L) {
+        if constexpr (MA > LA || MA > LB) {
+            return;
+        } else {
+            if constexpr (MA > 0) {
+                constexpr int T = MA + (LA < LB ? LA : LB);
+                const float c = ((MA & 1) ? -2.f : 2.f) * cw[T];
+                const float2 u = make_float2(c * A2[MA].x, c * A2[MA].y);
+#pragma unroll
+                for (int mt = 0; mt < kMT; ++mt) {
+                    L[mt].y = __builtin_fmaf(A1[mt][MA].y, u.x, L[mt].y);
+                    L[mt].y = __builtin_fmaf(-A1[mt][MA].x, u.y, L[mt].y);
+                }
+            }
+            Couple0Odd<LA, LB, MA + 1>::run(cw, A1, A2, L);
+        }
+    }
+};
+
 template <int LA, int LB, int MA>
 struct Couple0 {
     __device__ __forceinline__ static void run(const float *cw, const float2 (*A1)[LA + 1], const float2 *A2,
@@ -139,6 +166,7 @@ __device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
 // lane keeps the same b2 in all four tiles; pairs with a bin >= nbins hold zeros.
 template <int LA, int LB, int LC, int PREC>
 __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
+    constexpr bool ODD = ((LA + LB + LC) & 1) != 0;
     using CL = Cols<LA, LB, LC>;
     constexpr int NCOL = CL::ncol;
     constexpr int TC = kTileCells;
@@ -191,19 +219,29 @@ __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
                 float2 L[kMT];
 #pragma unroll
                 for (int mt = 0; mt < kMT; ++mt) L[mt] = make_float2(0.f, 0.f);
-                if constexpr (MC == 0)
+                if constexpr (MC == 0 && !ODD)
                     Couple0<LA, LB, 0>::run(cw, A1, A2, L);
+                else if constexpr (MC == 0)
+                    Couple0Odd<LA, LB, 0>::run(cw, A1, A2, L);
                 else
                     Couple<LA, LB, MC, -LA, terms_before<LA, LB>(MC)>::run(cw, A1, A2, L);
+                // even: Re(L a) = L.x a.x - L.y a.y;  odd: Im(L a) = L.y a.x + L.x a.y.  For mc = 0
+                // a_{l0} is real and L_0 is real (even) or imaginary (odd): one product.
                 if constexpr (PREC == 0) {
 #pragma unroll
                     for (int mt = 0; mt < kMT; ++mt) {
-                        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(L[mt].x, bv[MC].x, acc[mt], 0, 0, 0);
-                        if constexpr (MC > 0)   // L_0 and a_{l0} are real
-                            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-L[mt].y, bv[MC].y, acc[mt], 0, 0, 0);
+                        if constexpr (!ODD) {
+                            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(L[mt].x, bv[MC].x, acc[mt], 0, 0, 0);
+                            if constexpr (MC > 0)
+                                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-L[mt].y, bv[MC].y, acc[mt], 0, 0, 0);
+                        } else {
+                            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(L[mt].y, bv[MC].x, acc[mt], 0, 0, 0);
+                            if constexpr (MC > 0)
+                                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(L[mt].x, bv[MC].y, acc[mt], 0, 0, 0);
+                        }
                     }
                 } else {
-                    // K slots 0 and 1 of each lane group carry (re, im) of its cell, the rest zero
+                    // K slots 0 and 1 of each lane group carry the two products of its cell, the rest zero
                     bf8v bhv = {}, blv = {};
                     __bf16 h, l;
                     split_bf16(bv[MC].x, h, l); bhv[0] = h; blv[0] = l;
@@ -211,8 +249,8 @@ __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
 #pragma unroll
                     for (int mt = 0; mt < kMT; ++mt) {
                         bf8v ahv = {}, alv = {};
-                        split_bf16(L[mt].x, h, l); ahv[0] = h; alv[0] = l;
-                        split_bf16(-L[mt].y, h, l); ahv[1] = h; alv[1] = l;
+                        split_bf16(ODD ? L[mt].y : L[mt].x, h, l); ahv[0] = h; alv[0] = l;
+                        split_bf16(ODD ? L[mt].x : -L[mt].y, h, l); ahv[1] = h; alv[1] = l;
                         acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahv, bhv, acc[mt], 0, 0, 0);
                         acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahv, blv, acc[mt], 0, 0, 0);
                         acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alv, bhv, acc[mt], 0, 0, 0);

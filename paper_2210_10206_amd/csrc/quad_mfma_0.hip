@@ -1,4 +1,4 @@
-// Matrix-core 4PCF contraction: ordered Lambdas with l1 in {0, 1}.
+// Matrix-core 4PCF contraction: ordered Lambdas (both parities) with l1 in {0, 1}.
 #include "quad_mfma.h"
 
 namespace sb {
@@ -13,12 +13,16 @@ hipError_t launch_quad_mfma_part0(int la, int lb, int lc, const QuadMArgs &a, hi
         case 44: return quadm::launch_lambda<0, 4, 4>(a, s);
         case 101: return quadm::launch_lambda<1, 0, 1>(a, s);
         case 110: return quadm::launch_lambda<1, 1, 0>(a, s);
+        case 111: return quadm::launch_lambda<1, 1, 1>(a, s);
         case 112: return quadm::launch_lambda<1, 1, 2>(a, s);
         case 121: return quadm::launch_lambda<1, 2, 1>(a, s);
+        case 122: return quadm::launch_lambda<1, 2, 2>(a, s);
         case 123: return quadm::launch_lambda<1, 2, 3>(a, s);
         case 132: return quadm::launch_lambda<1, 3, 2>(a, s);
+        case 133: return quadm::launch_lambda<1, 3, 3>(a, s);
         case 134: return quadm::launch_lambda<1, 3, 4>(a, s);
         case 143: return quadm::launch_lambda<1, 4, 3>(a, s);
+        case 144: return quadm::launch_lambda<1, 4, 4>(a, s);
         default: return hipErrorInvalidValue;
     }
 }

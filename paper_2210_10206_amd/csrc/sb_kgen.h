@@ -69,6 +69,7 @@ struct QuadArgs {
     int nlm;
     double *partial;          // [lam][block][nbins^3]
     int nblocks;
+    bool odd;                 // odd Lambda: the imaginary part of the sums (the real part vanishes)
 };
 hipError_t launch_quad_contract(const QuadArgs &a, hipStream_t s);
 

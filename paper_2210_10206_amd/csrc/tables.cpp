@@ -90,9 +90,12 @@ static void terms_of(int la, int lb, int lc, std::vector<QuadTermH> *t) {
         }
 }
 
-Full4Plan make_full4_plan(int lmax, int nbins) {
+// Odd Lambda: permuting the 3j columns multiplies the symbol by (-1)^(l1+l2+l3) for each
+// transposition, so an output Lambda is its canonical ordering's sums times the sign of the
+// permutation; the product of the three coefficients is symmetric.
+Full4Plan make_full4_plan(int lmax, int nbins, bool even) {
     Full4Plan p;
-    p.out_lams = full4_lambdas(lmax, true);
+    p.out_lams = full4_lambdas(lmax, even);
     // canonical = sorted triples; pick the ordering with the fewest flops per cell
     std::vector<Lam> sorted;
     for (const Lam &L : p.out_lams) {
@@ -135,6 +138,10 @@ Full4Plan make_full4_plan(int lmax, int nbins) {
         p.out_canon.push_back(found);
         // canonical position k holds original position pos[k]
         p.out_pos.push_back({pos[0], pos[1], pos[2]});
+        int inv = 0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = i + 1; j < 3; ++j) inv += pos[i] > pos[j];
+        p.out_sign.push_back(even || (inv % 2 == 0) ? 1 : -1);
     }
     return p;
 }

@@ -31,11 +31,12 @@ def test_library_exports_every_declared_symbol():
         assert n in _lib.SIGNATURES, n
 
 
-def _problem(ndim=3, npcf=3, edges=(0.0, 2.0, 4.0), lmax=2, prec=0, dtype=0):
+def _problem(ndim=3, npcf=3, edges=(0.0, 2.0, 4.0), lmax=2, prec=0, dtype=0, flags=0):
     from paper_2210_10206_amd import _lib
     import numpy as np
     e = np.asarray(edges, dtype=np.float64)
-    p = _lib.SbProblem(ndim, npcf, len(e) - 1, e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), lmax, prec, dtype, 0)
+    p = _lib.SbProblem(ndim, npcf, len(e) - 1, e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), lmax, prec, dtype,
+                       flags)
     return p, e
 
 
@@ -50,6 +51,8 @@ def _problem(ndim=3, npcf=3, edges=(0.0, 2.0, 4.0), lmax=2, prec=0, dtype=0):
     (dict(), (16, 16, 0), -1),
     (dict(), (16, 16, 14), -2),          # 14 = 2 * 7: no radix-7 pass
     (dict(npcf=4, edges=tuple(range(12))), (16, 16, 16), -2),
+    (dict(flags=8), (16, 16, 16), -1),                # odd parity is a full-4PCF option
+    (dict(ndim=2, npcf=4, flags=8), (16, 16, 16), -1),
 ])
 def test_argument_validation_without_gpu(kw, shape, expect):
     """Argument errors are reported before any device call, so they can be checked on a CPU host."""

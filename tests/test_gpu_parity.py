@@ -255,6 +255,22 @@ def test_full4pcf_small(sb, precision, mfma):
     plan.close()
 
 
+@pytest.mark.parametrize("precision,mfma", [("fp32", True), ("split_bf16", True), ("fp32", False)])
+def test_full4pcf_odd_parity(sb, precision, mfma):
+    # the 23 odd Lambda at lmax 4: the imaginary part of the sums (their real part vanishes)
+    say(f"case: 24^3 full 4PCF odd parity, 5 bins to 6, lmax 4, {precision}, matrix cores {mfma}")
+    d = lognormal_field((24, 24, 24), seed=14, sigma=1.0)
+    edges = linear_edges(6, 5)
+    plan, dev, z = run_plan(sb, [d], edges, 4, npcf=4, precision=precision, mfma=mfma, parity="odd")
+    lams, ref = oracle.zeta4_full(d.astype(np.float64), edges, 4, parity="odd")
+    assert [tuple(x) for x in plan.zeta_index()] == lams and len(lams) == 23
+    assert np.max(np.abs(ref.real)) < 1e-9 * np.max(np.abs(ref.imag))
+    err = rel_err(z[0], ref.imag)
+    say(f"  err={err:.3e}")
+    assert err < (TOL_SPLIT if precision == "split_bf16" else TOL32)
+    plan.close()
+
+
 @pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
 def test_full4pcf_eight_bins_ragged_blocks(sb, precision):
     # 8 bins fill all four 16-pair tiles; 12 x 16 x 24 = 4608 cells leave a half block
