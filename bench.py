@@ -132,7 +132,7 @@ def cpu_baseline(field, edges, lmax, target_s=10.0):
                       f"fields"}
 
 
-def run_4pcf_batch(api, steps, warmup, count=16, precision="fp32", mfma=True):
+def run_4pcf_batch(api, steps, warmup, count=16, precision="fp32", mfma=True, parity="even"):
     """Full 4PCF of the 16-field 128^3 batch (sigma_i ~ U[0.5, 2]), 8 bins to 24, even
     Lambda with l <= 4, one plan and one forward per step; the fields/s of the batch and the
     live rate of its dominant kernel (the 3j-coupled contraction: on the matrix cores in
@@ -143,7 +143,7 @@ def run_4pcf_batch(api, steps, warmup, count=16, precision="fp32", mfma=True):
     dev = [torch.from_numpy(f).cuda() for f in fields]
     stream = torch.cuda.Stream()
     plan = api.Plan([f.shape for f in fields], linear_edges(24, 8), 4, npcf=4, prepare=False,
-                    precision=precision, mfma=mfma)
+                    precision=precision, mfma=mfma, parity=parity)
     with torch.cuda.stream(stream):
         plan.prepare(stream)
     out = torch.empty((len(dev), plan.zeta_doubles), dtype=torch.float64, device="cuda")
@@ -404,9 +404,10 @@ def main():
         print("bench: 128^3 4PCF batch", file=sys.stderr, flush=True)
         c4 = run_4pcf_batch(api, args.c4_steps, 1)
         variants = {}
-        for prec, mf in (("split_bf16", True), ("fp32", False)):
-            r = run_4pcf_batch(api, args.c4_steps, 1, precision=prec, mfma=mf)
-            variants[f"{prec}_{'mfma' if mf else 'valu'}"] = {
+        for prec, mf, par in (("split_bf16", True, "even"), ("fp32", False, "even"), ("fp32", True, "odd")):
+            r = run_4pcf_batch(api, args.c4_steps, 1, precision=prec, mfma=mf, parity=par)
+            key = f"{prec}_{'mfma' if mf else 'valu'}" + ("_odd_parity_23_lambda" if par == "odd" else "")
+            variants[key] = {
                 "value": r["value"], "contraction_ms_per_field": r["contraction"]["ms_per_field"],
                 "achieved_tflops": r["contraction"]["achieved_tflops"], "kernel": r["contraction"]["kernel"]}
         c4["other_contraction_paths"] = variants
