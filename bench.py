@@ -64,9 +64,11 @@ def write_traffic(counter_dir, n=256, copy_mib=1024, min_gib=4.0):
     launched most often (the one the autotuner picked and the timed steps used)."""
     import csv
     import re
+    reg = {256: 16}.get(n)   # lengths with the register-resident forms (n = r * r)
     fams = {0: re.compile(rf"fft_pass(_pf)?_kernel<{n}, \d+, \d+, 1,"),
-            1: re.compile(rf"axis0_kernel<{n},"),
-            2: re.compile(rf"last_contract_kernel<{n},")}
+            1: re.compile(rf"axis0_kernel<{n},|axis0_reg_kernel<{reg}, " if reg else rf"axis0_kernel<{n},"),
+            2: re.compile(rf"last_contract_kernel<{n},|last_reg_kernel<{reg}, " if reg else
+                          rf"last_contract_kernel<{n},")}
     raw = {}
     for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
         path = os.path.join(counter_dir, ctr, "run_counter_collection.csv")
@@ -364,8 +366,10 @@ def main():
     nk = (lmax + 1) * (lmax + 2) // 2 * nbins
     names = {0: f"fft_pass(_pf)_kernel<{n},...,+1> (middle inverse pass over all {nk} kernel arrays, "
                 f"variant chosen by sb_autotune)",
-             1: f"axis0_kernel<{n},...> (axis-0 kernel-spectrum + product + inverse pass)",
-             2: f"last_contract_kernel<{n},...,{nbins}> (last inverse pass fused with the contraction)",
+             1: (f"axis0_reg_kernel<16,16>" if n == 256 else f"axis0_kernel<{n},...>")
+                + " (axis-0 pass: kernel-spectrum regeneration + product + inverse transform)",
+             2: (f"last_reg_kernel<16,{(nbins + 3) // 4 * 4},false>" if n == 256 else f"last_contract_kernel<{n},...>")
+                + " (last inverse pass fused with the MFMA pair sums)",
              3: "pair_kernel (unfused 3PCF contraction)"}
     srcs = TRAFFIC_SRCS
     per = {}
