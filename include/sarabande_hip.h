@@ -154,7 +154,8 @@ sb_status sb_backward(sb_plan *plan, const void *const *delta, const double *gra
 
 /* Device pointer to the coefficient array of kernel k of the last forward field
  * (flag SB_FLAG_KEEP_COEFFS): complex float32, field shape; k = lm * nbins + b with
- * lm = l(l+1)/2 + m (3D, m >= 0) or lm = m (2D). */
+ * lm = l(l+1)/2 + m (3D, m >= 0) or lm = m (2D).  An sb_backward call overwrites the
+ * arrays (it recomputes them only up to the last axis). */
 sb_status sb_coeffs(const sb_plan *plan, int32_t k, const void **ptr);
 
 /* Launch-shape autotuner: times the candidate tilings of every FFT pass and

@@ -1,0 +1,157 @@
+// Adjoint of the full 3PCF: the last inverse pass of the coefficients fused with the
+// per-cell adjoint weights and the forward transform of the reflected field along the same
+// (contiguous) axis.
+//
+// For one (l, m) group and a tile of R rows x NBT (padded) bins:
+//   a^b(x)   = inverse transform along the last axis of the group's arrays (axes 0, 1 done);
+//   h^b(x)   = sum_b' G_l[b][b'] conj(a^b'(x)),  G_l = (g_l + g_l^T) / 2;
+//   D(x)    += w_m sum_b Re(a^b(x) h^b(x))                     (direct term, float32 per cell);
+//   v^b(x)   = w_m delta(x) h^b(x);
+//   out^b    = forward transform along the last axis of v^b(-x): the row of -x is the row of
+//              x reflected in the other axes and, with k -> -k, the transform of v^b's row:
+//              out^b(flip(row), k) = V^b(row, (n - k) mod n).
+// This replaces a write and a read of the coefficient arrays, of v and of the first forward
+// pass of v, per (l, m) group.
+#pragma once
+#include "fft_core.h"
+
+namespace sb {
+
+struct AdjLastArgs {
+    int n;                  // last-axis length
+    int ndim;
+    int64_t shape[3];
+    int64_t ng;
+    const float2 *in;       // NB arrays of the group, transformed along every axis but the last
+    const float *w;         // density
+    const double *gz;       // g_l (NB x NB)
+    float wm;               // 1 for m = 0, 2 for m > 0
+    int nb;
+    int64_t rows_per_block; // rows walked by one workgroup
+    int first;              // 1: D is written, 0: accumulated
+    float *dsum;            // D, one float per cell
+    float2 *out;            // NB arrays: the reflected v, transformed along the last axis
+    const float2 *tw;
+};
+hipError_t launch_adj_last(const AdjLastArgs &a, hipStream_t s);
+
+namespace adjlast {
+using namespace fftcore;
+
+template <int N, int TPP, int NBT, int R, int... RAD>
+__global__ __launch_bounds__(NBT * R * TPP) void adj_last_kernel(AdjLastArgs a) {
+    constexpr int P = NBT * R, PITCH = P + 1, NT = P * TPP;
+    constexpr int EPT = N / TPP;
+    extern __shared__ float2 smem[];
+    float2 *sm = smem;
+    float2 *tw = smem + N * PITCH;
+    float *G = reinterpret_cast<float *>(tw + N);   // NBT x NBT, zero beyond nb
+    const int nb = a.nb;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
+    for (int i = tid; i < NBT * NBT; i += NT) {
+        const int b1 = i / NBT, b2 = i % NBT;
+        G[i] = (b1 < nb && b2 < nb) ? (float)(0.5 * (a.gz[b1 * nb + b2] + a.gz[b2 * nb + b1])) : 0.f;
+    }
+    const int64_t nrows = a.ng / N;
+    const int64_t r_begin = (int64_t)blockIdx.x * a.rows_per_block;
+    const int64_t r_end = min(r_begin + a.rows_per_block, nrows);
+    // row index -> row index of the reflected cell (every axis but the last reflected)
+    auto flip_row = [&](int64_t row) -> int64_t {
+        if (a.ndim == 3) {
+            const int64_t n1 = a.shape[1];
+            const int64_t i0 = row / n1, i1 = row % n1;
+            return ((a.shape[0] - i0) % a.shape[0]) * n1 + (n1 - i1) % n1;
+        }
+        return (a.shape[0] - row) % a.shape[0];
+    };
+    for (int64_t row0 = r_begin; row0 < r_end; row0 += R) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int f = tid + e * NT;
+            const int pp = f / N, j = f % N;
+            const int b = pp / R;
+            const int64_t row = row0 + pp % R;
+            sm[j * PITCH + pp] = (row < r_end && b < nb) ? a.in[(int64_t)b * a.ng + row * N + j] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        stages<N, TPP, 1, 1, RAD...>(sm, tw, tid % P, tid / P, PITCH);
+        // per cell: h, the direct term and v (each thread owns whole cells: all bins of a cell)
+        for (int c = tid; c < R * N; c += NT) {
+            const int r = c / N, j = c % N;
+            const int64_t row = row0 + r;
+            if (row >= r_end) continue;
+            const int64_t cell = row * N + j;
+            float2 av[NBT];
+#pragma unroll
+            for (int b = 0; b < NBT; ++b) av[b] = sm[j * PITCH + b * R + r];
+            const float dw = a.wm * a.w[cell];
+            float d = 0.f;
+#pragma unroll
+            for (int b1 = 0; b1 < NBT; ++b1) {
+                float hx = 0.f, hy = 0.f;
+#pragma unroll
+                for (int b2 = 0; b2 < NBT; ++b2) {
+                    const float g = G[b1 * NBT + b2];
+                    hx = __builtin_fmaf(g, av[b2].x, hx);
+                    hy = __builtin_fmaf(-g, av[b2].y, hy);   // conj(a)
+                }
+                d = __builtin_fmaf(av[b1].x, hx, d);
+                d = __builtin_fmaf(-av[b1].y, hy, d);
+                sm[j * PITCH + b1 * R + r] = make_float2(dw * hx, dw * hy);
+            }
+            if (a.first) a.dsum[cell] = a.wm * d;
+            else a.dsum[cell] += a.wm * d;
+        }
+        __syncthreads();
+        stages<N, TPP, -1, 1, RAD...>(sm, tw, tid % P, tid / P, PITCH);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int f = tid + e * NT;
+            const int pp = f / N, k = f % N;
+            const int b = pp / R;
+            const int64_t row = row0 + pp % R;
+            if (row < r_end && b < nb)
+                a.out[(int64_t)b * a.ng + flip_row(row) * N + (N - k) % N] = sm[k * PITCH + pp];
+        }
+    }
+}
+
+// rows per tile: the fewest that make whole waves
+constexpr int tile_rows(int tpp, int nbt) {
+    int r = 1;
+    while ((nbt * r * tpp) % 64 != 0) ++r;
+    return r;
+}
+
+template <int N, int TPP, int NBT, int... RAD>
+hipError_t launch_t(const AdjLastArgs &a, hipStream_t s) {
+    constexpr int R = tile_rows(TPP, NBT);
+    constexpr int P = NBT * R, NT = P * TPP;
+    static_assert(NT <= 1024, "workgroup size");
+    const size_t shm = (size_t)(N * (P + 1) + N) * sizeof(float2) + (size_t)NBT * NBT * sizeof(float);
+    if (shm > 160 * 1024) return hipErrorInvalidValue;
+    if (shm > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&adj_last_kernel<N, TPP, NBT, R, RAD...>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+    }
+    const int64_t nrows = a.ng / N;
+    dim3 grid((unsigned)((nrows + a.rows_per_block - 1) / a.rows_per_block));
+    hipLaunchKernelGGL((adj_last_kernel<N, TPP, NBT, R, RAD...>), grid, dim3(NT), shm, s, a);
+    return hipGetLastError();
+}
+
+template <int N, int TPP, int... RAD>
+hipError_t launch_n(const AdjLastArgs &a, hipStream_t s) {
+    const int nb = a.nb;
+    if (nb <= 4) return launch_t<N, TPP, 4, RAD...>(a, s);
+    if (nb <= 8) return launch_t<N, TPP, 8, RAD...>(a, s);
+    if (nb <= 12) return launch_t<N, TPP, 12, RAD...>(a, s);
+    if (nb <= 16) return launch_t<N, TPP, 16, RAD...>(a, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace adjlast
+}  // namespace sb

@@ -10,6 +10,7 @@
 // so the forward kernel spectra serve unchanged:  U = IFFT( sum_k FFT(w_m v_k(-.)) Khat_k ),
 // C(y) = 2 Re U(-y).
 #include "sb_plan.h"
+#include "adj_last.h"
 
 namespace sb {
 namespace {
@@ -79,6 +80,15 @@ __global__ void zero_c_kernel(float2 *x, int64_t n) {
 
 }  // namespace
 
+hipError_t launch_adj_last(const AdjLastArgs &a, hipStream_t s) {
+    switch (a.n) {
+#define SB_X(N, TPP, ...) case N: return adjlast::launch_n<N, TPP, __VA_ARGS__>(a, s);
+        SB_LAST_CONFIGS(SB_X)
+#undef SB_X
+        default: return hipErrorInvalidValue;
+    }
+}
+
 sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta, float *const *grad_delta,
                    hipStream_t s) {
     if (!p || !delta || !grad_zeta || !grad_delta) return fail(SB_EINVAL, "null argument");
@@ -110,31 +120,59 @@ sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta
                 if (lm >= gend) {   // recompute a for the next chunk of groups (never stored across calls)
                     g0 = lm;
                     gend = std::min(p->nlm, lm + p->chunk_groups);
-                    st = coefficients(p, f, g0, gend - g0, s);
+                    // a stops before the last axis: the fused pass below finishes it
+                    st = coefficients(p, f, g0, gend - g0, s, !p->adj_fused);
                     if (st != SB_OK) return st;
                 }
-                AdjPrepArgs a{};
-                a.coef = coef + (int64_t)(lm - g0) * NB * G.ng;
-                a.w = w;
-                a.gz = gz_f + (int64_t)l * NB * NB;
-                a.nbins = NB;
-                a.wm = m == 0 ? 1.f : 2.f;
-                a.ndim = 3;
-                for (int d = 0; d < 3; ++d) a.n[d] = G.n[d];
-                a.ng = G.ng;
-                a.vtmp = vtmp;
-                a.dsum = dsum;
-                a.first = lm == 0;
-                e = p->timed_launch(STAGE_OTHER, K_ADJPREP, s, [&]() {
-                    hipLaunchKernelGGL(adj_prep_kernel, dim3(nblk), dim3(nt), 0, s, a);
-                    return hipGetLastError();
-                });
-                if (e != hipSuccess) return hip_fail(e, "adjoint prep");
-                // acc += sum_b FFT(w_m v_b(-.)) * Khat_b: transform v_b along axes 2..1 in place,
-                // then the axis-0 pass regenerates each kernel spectrum and accumulates
-                const int axes[2] = {2, 1};
-                st = fft_axes(p, G.n, 3, G.ng, axes, 2, -1, LOAD_C, vtmp, G.ng, vtmp, G.ng, NB, s);
-                if (st != SB_OK) return st;
+                if (p->adj_fused) {
+                    // last inverse pass + h, D and v + forward transform of v(-x) along the last axis
+                    AdjLastArgs a{};
+                    a.n = (int)G.n[2];
+                    a.ndim = 3;
+                    for (int d = 0; d < 3; ++d) a.shape[d] = G.n[d];
+                    a.ng = G.ng;
+                    a.in = coef + (int64_t)(lm - g0) * NB * G.ng;
+                    a.w = w;
+                    a.gz = gz_f + (int64_t)l * NB * NB;
+                    a.wm = m == 0 ? 1.f : 2.f;
+                    a.nb = NB;
+                    const int64_t nrows = G.ng / a.n;
+                    a.rows_per_block = std::max<int64_t>(8, (nrows + 2047) / 2048);
+                    a.first = lm == 0;
+                    a.dsum = dsum;
+                    a.out = vtmp;
+                    a.tw = p->tw.at(a.n);
+                    e = p->timed_launch(STAGE_OTHER, K_ADJPREP, s, [&]() { return launch_adj_last(a, s); }, a.n, 0, NB,
+                                        16.0 * NB * G.ng + 8.0 * G.ng);
+                    if (e != hipSuccess) return hip_fail(e, "adjoint fused last pass");
+                    const int axes[1] = {1};
+                    st = fft_axes(p, G.n, 3, G.ng, axes, 1, -1, LOAD_C, vtmp, G.ng, vtmp, G.ng, NB, s);
+                    if (st != SB_OK) return st;
+                } else {
+                    AdjPrepArgs a{};
+                    a.coef = coef + (int64_t)(lm - g0) * NB * G.ng;
+                    a.w = w;
+                    a.gz = gz_f + (int64_t)l * NB * NB;
+                    a.nbins = NB;
+                    a.wm = m == 0 ? 1.f : 2.f;
+                    a.ndim = 3;
+                    for (int d = 0; d < 3; ++d) a.n[d] = G.n[d];
+                    a.ng = G.ng;
+                    a.vtmp = vtmp;
+                    a.dsum = dsum;
+                    a.first = lm == 0;
+                    e = p->timed_launch(STAGE_OTHER, K_ADJPREP, s, [&]() {
+                        hipLaunchKernelGGL(adj_prep_kernel, dim3(nblk), dim3(nt), 0, s, a);
+                        return hipGetLastError();
+                    });
+                    if (e != hipSuccess) return hip_fail(e, "adjoint prep");
+                    // transform v_b(-.) along axes 2..1 in place
+                    const int axes[2] = {2, 1};
+                    st = fft_axes(p, G.n, 3, G.ng, axes, 2, -1, LOAD_C, vtmp, G.ng, vtmp, G.ng, NB, s);
+                    if (st != SB_OK) return st;
+                }
+                // acc += sum_b FFT(w_m v_b(-.)) * Khat_b: the axis-0 pass regenerates each kernel
+                // spectrum and accumulates
                 Axis0Args x{};
                 x.n = (int)G.n[0];
                 x.plane = G.plane;

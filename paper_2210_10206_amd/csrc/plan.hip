@@ -353,6 +353,7 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
     int64_t r0 = 0;
     while ((r0 + 1) * (r0 + 1) <= p->thr[NB]) ++r0;      // largest |c_0| with c_0^2 <= e_max^2
     p->fused = (prob->flags & (SB_FLAG_UNFUSED | SB_FLAG_KEEP_COEFFS)) == 0;
+    p->adj_fused = (prob->flags & SB_FLAG_UNFUSED) == 0;
     size_t pers = 0;
     for (auto &G : p->groups) {
         G.plane = G.ng / G.n[0];
@@ -495,14 +496,19 @@ sb_status density_spectrum(sb_plan *p, const ShapeGroup &G, const void *delta, h
 
 // Coefficients of kernel groups [g0, g0 + ngr) of one field into scratch (Alg. 3 / Alg. 4
 // as a correlation); the density spectrum is already in scratch.
-sb_status coefficients(sb_plan *p, int f, int g0, int ngr, hipStream_t s) {
+sb_status coefficients(sb_plan *p, int f, int g0, int ngr, hipStream_t s, bool last_axis) {
     const ShapeGroup &G = p->groups[p->field_group[f]];
     float2 *dhat = reinterpret_cast<float2 *>(p->scratch + p->off_dhat);
     float2 *coef = reinterpret_cast<float2 *>(p->scratch + p->off_coef);
     sb_status st = axis0_corr(p, G, dhat, coef, g0, ngr, s);
     if (st != SB_OK) return st;
     const int axes[2] = {1, 2};
-    st = fft_axes(p, G.n, p->prob.ndim, G.ng, axes, p->prob.ndim - 1, +1, LOAD_C, coef, G.ng, coef, G.ng,
+    const int naxes = p->prob.ndim - 1 - (last_axis ? 0 : 1);
+    if (naxes == 0) {
+        p->last_ng = G.ng;
+        return SB_OK;
+    }
+    st = fft_axes(p, G.n, p->prob.ndim, G.ng, axes, naxes, +1, LOAD_C, coef, G.ng, coef, G.ng,
                   ngr * p->prob.nbins, s);
     if (st != SB_OK) return st;
     p->last_ng = G.ng;

@@ -81,6 +81,7 @@ struct sb_plan {
     std::vector<int> coefw_off;
     bool quad_mfma = false;       // full 4PCF contraction on the matrix cores (l <= 4, <= 8 bins)
     bool fused = true;            // fused last pass + contraction for the 3PCFs (flag SB_FLAG_UNFUSED clears it)
+    bool adj_fused = true;        // adjoint: last pass fused with the adjoint weights (SB_FLAG_UNFUSED clears it)
     int quad_tile = 32, proj4_tile = 64;
     std::map<std::pair<int, int>, int> fft_var;   // (length, axis) -> variant
     int fft_variant(int n, int axis) const {
@@ -131,8 +132,9 @@ sb_status hip_fail(hipError_t e, const char *what);
 sb_status forward(sb_plan *p, const void *const *delta, double *zeta, hipStream_t s);
 sb_status density_spectrum(sb_plan *p, const sb::ShapeGroup &G, const void *delta, hipStream_t s);
 // Coefficients of kernel groups [g0, g0 + ng) of field f into scratch (group g0 first); the
-// density spectrum must be in scratch already.
-sb_status coefficients(sb_plan *p, int f, int g0, int ngroups, hipStream_t s);
+// density spectrum must be in scratch already.  last_axis = false stops before the inverse
+// transform along the last axis.
+sb_status coefficients(sb_plan *p, int f, int g0, int ngroups, hipStream_t s, bool last_axis = true);
 void layout_scratch(sb_plan *p);
 sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s);
 // FFT passes over the listed axes (in order) of arrays with extents n[0..ndim) and ncell

@@ -300,13 +300,14 @@ def test_full4pcf_lmax3_six_bins(sb):
 
 # ------------------------------------------------------------------ adjoint
 
-def test_adjoint_matches_oracle_gradient(sb):
-    say("case: 16^3 adjoint of the full 3PCF, 4 bins to 4, lmax 3")
+@pytest.mark.parametrize("fused", [True, False])
+def test_adjoint_matches_oracle_gradient(sb, fused):
+    say(f"case: 16^3 adjoint of the full 3PCF, 4 bins to 4, lmax 3, fused last pass {fused}")
     d = lognormal_field((16, 16, 16), seed=9, sigma=1.0)
     edges = linear_edges(4, 4)
     rng = np.random.Generator(np.random.PCG64(3))
     G = rng.standard_normal((4, 4, 4))
-    plan = sb.Plan([d.shape], edges, 3)
+    plan = sb.Plan([d.shape], edges, 3, fused=fused)
     dev = torch.from_numpy(d).cuda().requires_grad_(True)
     z = sb.ZetaFn.apply(dev, plan)
     loss = (z * torch.from_numpy(G).cuda()).sum()
