@@ -289,6 +289,10 @@ def main():
     ap.add_argument("--c5-steps", type=int, default=1,
                     help="steps of the uneven-batch forward + adjoint and the synthesis demo (0 skips them)")
     ap.add_argument("--big-steps", type=int, default=1, help="steps of the 512^3 3PCF line (0 skips it)")
+    ap.add_argument("--step-samples", type=int, default=10,
+                    help="per-step HIP-event samples (eager and graph replay) after the timed steps")
+    ap.add_argument("--plain-steps", type=int, default=2,
+                    help="steps of the plain unfused float32 path on the same fields (0 skips it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times (the reference "
                          "dispatch that scales the HBM byte counters of a counter run)")
@@ -400,9 +404,47 @@ def main():
         stages.setdefault(k, [0.0, 0])
         stages[k][0] += r["ms"]
         stages[k][1] += 1
+    # per-step HIP-event times (median), eager and replayed from a HIP graph
+    step_ms = {}
+    if args.step_samples > 0:
+        for mode in ("eager", "graph"):
+            ms = []
+            with torch.cuda.stream(stream):
+                plan.forward_raw(dev, out=out, stream=stream, graph=mode == "graph")   # capture / warm
+                for _ in range(args.step_samples):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    plan.forward_raw(dev, out=out, stream=stream, graph=mode == "graph")
+                    e1.record(stream)
+                    e1.synchronize()
+                    ms.append(e0.elapsed_time(e1))
+            ms.sort()
+            step_ms[mode] = {"median_ms": round(ms[len(ms) // 2], 3), "min_ms": round(ms[0], 3),
+                             "samples": len(ms), "fields_per_s_at_median": round(len(dev) / (ms[len(ms) // 2] * 1e-3), 3)}
     plan.close()
     del plan, out
     torch.cuda.empty_cache()
+    # the plain float32 path of the same workload: every coefficient array written by the three
+    # passes, then the separate pair contraction (no fusion, no autotuning, no graph)
+    plain = None
+    if args.plain_steps > 0:
+        print("bench: plain unfused path", file=sys.stderr, flush=True)
+        pp = api.Plan([f.shape for f in fields], edges, lmax, npcf=3, fused=False)
+        pout = torch.empty((len(dev), pp.zeta_doubles), dtype=torch.float64, device="cuda")
+        pp.forward_raw(dev, out=pout)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            pp.forward_raw(dev, out=pout)
+        torch.cuda.synchronize()
+        pel = time.perf_counter() - t0
+        pz = pout.cpu().numpy().reshape(len(dev), lmax + 1, nbins, nbins)
+        plain = {"value": round(len(dev) * args.plain_steps / pel, 4), "unit": "fields/s",
+                 "speedup_of_default_path": round(value / (len(dev) * args.plain_steps / pel), 3),
+                 "max_abs_diff_vs_default_rel": float(np.max(np.abs(pz - z)) / np.max(np.abs(z)))}
+        pp.close()
+        del pp, pout
+        torch.cuda.empty_cache()
     c4 = None
     if args.c4_steps > 0:
         print("bench: 128^3 4PCF batch", file=sys.stderr, flush=True)
@@ -439,6 +481,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "cold_setup_ms": round(cold_ms, 1),
+        "step_times": step_ms or None,
+        "plain_fp32_unfused": plain,
         "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
         "per_kernel": per_kernel,
         "max_rel_err_vs_oracle": errs or None,
