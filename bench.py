@@ -148,6 +148,7 @@ def run_4pcf_batch(api, steps, warmup, count=16, precision="fp32", mfma=True, pa
                     precision=precision, mfma=mfma, parity=parity)
     with torch.cuda.stream(stream):
         plan.prepare(stream)
+    plan.autotune(stream)
     out = torch.empty((len(dev), plan.zeta_doubles), dtype=torch.float64, device="cuda")
     with torch.cuda.stream(stream):
         for _ in range(warmup):

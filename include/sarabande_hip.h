@@ -163,6 +163,13 @@ sb_status sb_coeffs(const sb_plan *plan, int32_t k, const void **ptr);
  * Requires bound workspace and sb_prepare. */
 sb_status sb_autotune(sb_plan *plan, void *stream);
 
+/* Number of launch shapes ("variants") of the FFT passes of length n (0: unsupported
+ * length), and the choice of one for the passes of length n along `axis` of this plan
+ * (what sb_autotune sets by timing; e.g. to reuse tuned choices).  Results do not depend on
+ * the variant beyond float32 rounding. */
+int32_t sb_fft_variants(int32_t n);
+sb_status sb_plan_set_fft_variant(sb_plan *plan, int32_t n, int32_t axis, int32_t variant);
+
 /* Forward pass replayed from a HIP graph captured on first use for these exact
  * pointers (re-captured when they change).  Same contract as sb_forward. */
 sb_status sb_forward_graph(sb_plan *plan, const void *const *delta, double *zeta, void *stream);

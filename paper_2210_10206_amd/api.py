@@ -197,6 +197,13 @@ class Plan:
         off = ptr.value - self._scratch.data_ptr()
         return self._scratch[off: off + 8 * n].view(torch.complex64).reshape(shape)
 
+    def fft_variants(self, n: int) -> int:
+        return int(self.lib.sb_fft_variants(int(n)))
+
+    def set_fft_variant(self, n: int, axis: int, variant: int):
+        check(self.lib.sb_plan_set_fft_variant(self.handle, int(n), int(axis), int(variant)),
+              "sb_plan_set_fft_variant")
+
     def profile(self, enable: bool):
         check(self.lib.sb_profile(self.handle, int(bool(enable))), "sb_profile")
 

@@ -182,69 +182,80 @@ __global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
     }
 }
 
-// Axis-0 correlation pass for n = R * R held in registers: thread q of a pencil owns rows
-// q + R r (r < R), which are both the inputs of radix-R butterfly q of the first Stockham
-// stage and the outputs of butterfly q of the second.  So the forward transform of the
-// kernel pencil, the product with the density spectrum and the inverse transform touch LDS
-// only for the two stage exchanges (positions R q + r written, q + R r read), with one
-// barrier each (the exchanges alternate between two buffers).  Loads and stores take P
-// adjacent pencils of the contiguous axes per row, as in the LDS-staged kernel.
-template <int R, int P>
-__global__ __launch_bounds__(P * R) void axis0_reg_kernel(Axis0Args a) {
-    constexpr int N = R * R;
+// Axis-0 correlation pass for n = R1 * R2 (R2 divides R1) held in registers: thread q < R2 of a
+// pencil owns rows q + R2 s (s < R1).  Those are the inputs of radix-R1 butterfly q of the first
+// Stockham stage, and the outputs of butterflies q + R2 t (t < R1 / R2) of the second
+// (radix R2), which read positions q + R2 t + R1 r'.  So the forward transform of the kernel
+// pencil, the product with the density spectrum and the inverse transform touch LDS only for
+// the two stage exchanges (positions R1 q + r written), with one barrier each (the exchanges
+// alternate between two buffers).  Loads and stores take P adjacent pencils of the contiguous
+// axes per row, as in the LDS-staged kernel.
+template <int R1, int R2, int P>
+__global__ __launch_bounds__(P * R2) void axis0_reg_kernel(Axis0Args a) {
+    constexpr int N = R1 * R2;
+    constexpr int T = R1 / R2;   // second-stage butterflies per thread
+    static_assert(R1 % R2 == 0, "R2 must divide R1");
     constexpr int PITCH = P + 1;
     __shared__ float2 ex[2][N * PITCH];
     const int tid = threadIdx.x;
     const int p = tid % P, q = tid / P;
     const int64_t g = (int64_t)blockIdx.x * P + p;
     const bool ok = g < a.plane;
-    // second-stage twiddles w^{q r}, w = e^{-2 pi i / N} (the inverse takes the conjugate)
-    float2 tw[R];
+    // second-stage twiddles w^{(q + R2 t) r'}, w = e^{-2 pi i / N} (the inverse takes the conjugate)
+    float2 tw[T][R2];
 #pragma unroll
-    for (int r = 0; r < R; ++r) tw[r] = a.tw[(q * r) % N];
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int r = 0; r < R2; ++r) tw[t][r] = a.tw[((q + R2 * t) * r) % N];
     const int64_t kstride = (int64_t)a.np * a.plane;
     auto load_kernel = [&](int64_t k, float2 *dst) {
         const float2 *kc = a.kc + k * kstride;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int j = q + R * r;
+        for (int r = 0; r < R1; ++r) {
+            const int j = q + R2 * r;
             const int pl = (a.np == N || j <= a.r0) ? j : (j >= N - a.r0 ? a.np - (N - j) : -1);
             dst[r] = (ok && pl >= 0) ? kc[(int64_t)pl * a.plane + g] : make_float2(0.f, 0.f);
         }
     };
-    // one transform: radix-R DFT of the own rows, exchange, twiddle, radix-R DFT -> own rows
+    // one transform: radix-R1 DFT of the own rows, exchange, twiddle, radix-R2 DFTs -> own rows
     auto transform = [&](float2 *v, float2 *buf, auto sign_c) {
         constexpr int SIGN = decltype(sign_c)::value;
-        Dft<R, SIGN>::run(v);
+        Dft<R1, SIGN>::run(v);
 #pragma unroll
-        for (int r = 0; r < R; ++r) buf[(R * q + r) * PITCH + p] = v[r];
+        for (int r = 0; r < R1; ++r) buf[(R1 * q + r) * PITCH + p] = v[r];
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const float2 x = buf[(q + R * r) * PITCH + p];
-            const float2 w = SIGN < 0 ? tw[r] : make_float2(tw[r].x, -tw[r].y);
-            v[r] = r == 0 ? x : cmul(x, w);
-        }
-        Dft<R, SIGN>::run(v);
-    };
-    float2 dr[R], nx[R];
+        for (int t = 0; t < T; ++t) {
+            float2 u[R2];
 #pragma unroll
-    for (int r = 0; r < R; ++r) dr[r] = ok ? a.dhat[(int64_t)(q + R * r) * a.plane + g] : make_float2(0.f, 0.f);
+            for (int r = 0; r < R2; ++r) {
+                const float2 x = buf[(q + R2 * t + R1 * r) * PITCH + p];
+                const float2 w = SIGN < 0 ? tw[t][r] : make_float2(tw[t][r].x, -tw[t][r].y);
+                u[r] = r == 0 ? x : cmul(x, w);
+            }
+            Dft<R2, SIGN>::run(u);
+#pragma unroll
+            for (int r = 0; r < R2; ++r) v[t + T * r] = u[r];   // element q + R2 t + R1 r
+        }
+    };
+    float2 dr[R1], nx[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) dr[r] = ok ? a.dhat[(int64_t)(q + R2 * r) * a.plane + g] : make_float2(0.f, 0.f);
     const int64_t kbase = (int64_t)blockIdx.y * a.nb;
     load_kernel(kbase, nx);
     for (int b = 0; b < a.nb; ++b) {
-        float2 v[R];
+        float2 v[R1];
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = nx[r];
+        for (int r = 0; r < R1; ++r) v[r] = nx[r];
         if (b + 1 < a.nb) load_kernel(kbase + b + 1, nx);   // in flight during the transforms
         transform(v, ex[0], std::integral_constant<int, -1>{});
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = cmul(v[r], dr[r]);
+        for (int r = 0; r < R1; ++r) v[r] = cmul(v[r], dr[r]);
         transform(v, ex[1], std::integral_constant<int, 1>{});
         float2 *out = a.out + (kbase + b) * a.ng;
         if (ok)
 #pragma unroll
-            for (int r = 0; r < R; ++r) out[(int64_t)(q + R * r) * a.plane + g] = v[r];
+            for (int r = 0; r < R1; ++r) out[(int64_t)(q + R2 * r) * a.plane + g] = v[r];
     }
 }
 
@@ -346,9 +357,14 @@ hipError_t launch(const FftPass &a, hipStream_t s) {
 // The variants are the autotuner's candidates.
 hipError_t launch_fft_pass(const FftPass &a, hipStream_t s) {
     const int v = a.variant;
-    // variants 4 and 5 (length 256): persistent, two radix-16 stages, 4 / 16 tiles
-    if (v >= 4 && a.n == 256 && a.load == LOAD_C && a.store == STORE_C)
-        return launch_pf<256, 16, 256, 16, 16>(a, s, v == 4 ? 4 : 16);
+    // variants 4 and 5 (lengths 64, 128, 256): persistent, two stages (radix 8 x 8, 16 x 8,
+    // 16 x 16), 4 / 16 tiles
+    if (v >= 4 && a.load == LOAD_C && a.store == STORE_C) {
+        const int tiles = v == 4 ? 4 : 16;
+        if (a.n == 256) return launch_pf<256, 16, 256, 16, 16>(a, s, tiles);
+        if (a.n == 128) return launch_pf<128, 8, 256, 16, 8>(a, s, tiles);
+        if (a.n == 64) return launch_pf<64, 8, 256, 8, 8>(a, s, tiles);
+    }
     // variants 2 and 3: persistent passes with register prefetch (plain loads and stores only)
     if (v >= 2 && a.load == LOAD_C && a.store == STORE_C) {
         const int tiles = v == 2 ? 4 : 16;
@@ -378,10 +394,12 @@ hipError_t launch_fft_pass(const FftPass &a, hipStream_t s) {
 }
 
 hipError_t launch_axis0(const Axis0Args &a, hipStream_t s) {
-    if (a.n == 256 && a.mode == 0) {
+    if (a.mode == 0 && (a.n == 256 || a.n == 128 || a.n == 64)) {
         constexpr int P = 16;
         dim3 grid((unsigned)((a.plane + P - 1) / P), (unsigned)a.groups);
-        hipLaunchKernelGGL((axis0_reg_kernel<16, P>), grid, dim3(16 * P), 0, s, a);
+        if (a.n == 256) hipLaunchKernelGGL((axis0_reg_kernel<16, 16, P>), grid, dim3(16 * P), 0, s, a);
+        else if (a.n == 128) hipLaunchKernelGGL((axis0_reg_kernel<16, 8, P>), grid, dim3(8 * P), 0, s, a);
+        else hipLaunchKernelGGL((axis0_reg_kernel<8, 8, P>), grid, dim3(8 * P), 0, s, a);
         return hipGetLastError();
     }
     switch (a.n) {
@@ -429,8 +447,8 @@ bool fft_supported(int n) {
 
 int fft_num_variants(int n) {
     // 0, 1: one tile per workgroup (two shapes where defined); 2, 3: persistent, 4 / 16 tiles;
-    // 4, 5 (length 256): persistent with two radix-16 stages
-    return n == 256 ? 6 : 4;
+    // 4, 5 (lengths 64, 128, 256): persistent with two register-sized radix stages
+    return (n == 256 || n == 128 || n == 64) ? 6 : 4;
 }
 
 }  // namespace sb

@@ -90,7 +90,7 @@ sb_status sb_autotune(sb_plan *p, void *stream) {
                 ps.in = coef;
                 ps.out = coef;
                 ps.in_bs = ps.out_bs = G.ng;
-                ps.batch = p->nk;
+                ps.batch = p->chunk_groups * p->prob.nbins;   // the arrays the scratch holds at once
                 ps.tw = p->tw.at(n);
                 ps.variant = v;
                 float tot = 0.f;
@@ -116,6 +116,18 @@ sb_status sb_autotune(sb_plan *p, void *stream) {
     p->timing = was_timing;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
+    p->release_graph();
+    return SB_OK;
+}
+
+int32_t sb_fft_variants(int32_t n) { return fft_supported(n) ? fft_num_variants(n) : 0; }
+
+sb_status sb_plan_set_fft_variant(sb_plan *p, int32_t n, int32_t axis, int32_t variant) {
+    if (!p) return fail(SB_EINVAL, "null plan");
+    if (!fft_supported(n)) return fail(SB_EINVAL, "unsupported length");
+    if (axis < 0 || axis >= p->prob.ndim) return fail(SB_EINVAL, "axis out of range");
+    if (variant < 0 || variant >= fft_num_variants(n)) return fail(SB_EINVAL, "variant out of range");
+    p->fft_var[{n, axis}] = variant;
     p->release_graph();
     return SB_OK;
 }

@@ -172,6 +172,29 @@ def test_chunked_kernel_groups_match_whole(sb):
     chunked.close()
 
 
+@pytest.mark.parametrize("shape", [(8, 64, 16), (8, 128, 16), (8, 256, 16)])
+def test_every_fft_variant(sb, shape):
+    # every launch shape of the passes of each axis (what the autotuner may pick) gives the
+    # oracle's sums; the middle axis (a plain pass in the forward, kernel-cache and density
+    # transforms too) has length 64 / 128 / 256
+    say(f"case: {shape} full 3PCF, 4 bins to 4, lmax 3, every FFT variant of every axis")
+    d = lognormal_field(shape, seed=40, sigma=1.0)
+    edges = linear_edges(4, 4)
+    ref = oracle.zeta3_full(d.astype(np.float64), edges, 3).real
+    plan = sb.Plan([d.shape], edges, 3)
+    dev = [torch.from_numpy(d).cuda()]
+    worst = 0.0
+    for axis, n in enumerate(shape):
+        for v in range(plan.fft_variants(n)):
+            plan.set_fft_variant(n, axis, v)
+            z = plan.forward(dev).cpu().numpy()
+            worst = max(worst, rel_err(z[0], ref))
+        plan.set_fft_variant(n, axis, 0)
+    say(f"  worst err over the variants={worst:.3e}")
+    assert worst < TOL32
+    plan.close()
+
+
 def test_graph_replay_matches_eager(sb):
     say("case: 32^3 graph capture + replay vs eager")
     d = lognormal_field((32, 32, 32), seed=5, sigma=1.0)
