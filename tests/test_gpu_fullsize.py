@@ -15,7 +15,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import oracle  # noqa: E402
-from fieldgen import lognormal_field, linear_edges, c5_shapes  # noqa: E402
+from fieldgen import lognormal_field, linear_edges, c5_shapes, sparse_unit_field  # noqa: E402
 
 TOL32 = 1e-5
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -179,3 +179,47 @@ def test_coefficients_256_sampled(api):
     say(f"  coefficient err (rel. to max |a| per bin) = {worst:.3e}")
     assert worst < 2e-6
     plan.close()
+
+
+def test_particles_on_grid_full_128(api):
+    """The validation set-up of Sec. 3.2 with our own draws: 104 unit-weight cells on a 128^3
+    grid (delta = the weight grid), 10 linear bins; the sums only involve the occupied cells,
+    which the oracle evaluates directly (its sum restricted to those cells is the whole sum)."""
+    say("case: 104 particles on 128^3, 10 bins to 20: full 3PCF (lmax 4) and even 4PCF (lmax 2)")
+    d = sparse_unit_field((128,) * 3, 104, seed=2210)
+    cells = np.flatnonzero(d.reshape(-1))
+    edges = linear_edges(20, 10)
+    dev = [torch.from_numpy(d.astype(np.float32)).cuda()]
+    p3 = api.Plan([d.shape], edges, 4, npcf=3)
+    z3 = p3.forward(dev)[0].cpu().numpy()
+    p3.close()
+    r3 = oracle.zeta3_full(d, edges, 4, cells=cells).real
+    p4 = api.Plan([d.shape], edges, 2, npcf=4)
+    z4 = p4.forward(dev)[0].cpu().numpy()
+    p4.close()
+    lams, r4 = oracle.zeta4_full(d, edges, 2, cells=cells)
+    e3, e4 = rel_err(z3, r3), rel_err(z4, r4.real)
+    say(f"  3PCF err={e3:.3e}; 4PCF err={e4:.3e} ({len(lams)} Lambda)")
+    assert e3 < TOL32 and e4 < TOL32
+
+
+def test_particles_on_grid_projected_256(api):
+    """41 unit-weight cells on a 256^2 grid, 10 linear bins (the projected validation set-up
+    of Sec. 3.2 with our own draw): projected 3PCF and 4PCF, m up to 4."""
+    say("case: 41 particles on 256^2, 10 bins to 30, mmax 4: projected 3PCF and 4PCF")
+    d = sparse_unit_field((256, 256), 41, seed=41)
+    cells = np.flatnonzero(d.reshape(-1))
+    edges = linear_edges(30, 10)
+    dev = [torch.from_numpy(d.astype(np.float32)).cuda()]
+    p3 = api.Plan([d.shape], edges, 4, npcf=3)
+    z3 = p3.forward(dev)[0].cpu().numpy()
+    p3.close()
+    r3 = oracle.zeta3_proj(d, edges, 4, cells=cells)
+    p4 = api.Plan([d.shape], edges, 4, npcf=4)
+    z4 = p4.forward(dev)[0].cpu().numpy()
+    p4.close()
+    pairs, r4 = oracle.zeta4_proj(d, edges, 4, cells=cells)
+    e3, e4 = rel_err(z3, r3), rel_err(z4, r4)
+    say(f"  proj3 err={e3:.3e}; proj4 err={e4:.3e}")
+    assert e3 < TOL32 and e4 < TOL32
+
