@@ -259,6 +259,52 @@ __global__ __launch_bounds__(P * R2) void axis0_reg_kernel(Axis0Args a) {
     }
 }
 
+// Axis-0 correlation pass on the register-resident Stockham stages of reg_stages (any radix
+// list whose last radix divides the first; two or more stages): thread q < T = n / R0 of a
+// pencil owns rows q + T s.  P adjacent pencils of the contiguous axes per workgroup.
+template <int N, int P, int R0, int... REST>
+__global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
+    constexpr int T = N / R0;
+    constexpr int PITCH = P + 1;
+    __shared__ float2 ex[2][N * PITCH];
+    __shared__ float2 tw[N];
+    const int tid = threadIdx.x;
+    const int p = tid % P, q = tid / P;
+    const int64_t g = (int64_t)blockIdx.x * P + p;
+    const bool ok = g < a.plane;
+    for (int i = tid; i < N; i += P * T) tw[i] = a.tw[i];
+    const int64_t kstride = (int64_t)a.np * a.plane;
+    auto load_kernel = [&](int64_t k, float2 *dst) {
+        const float2 *kc = a.kc + k * kstride;
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int j = q + T * r;
+            const int pl = (a.np == N || j <= a.r0) ? j : (j >= N - a.r0 ? a.np - (N - j) : -1);
+            dst[r] = (ok && pl >= 0) ? kc[(int64_t)pl * a.plane + g] : make_float2(0.f, 0.f);
+        }
+    };
+    float2 dr[R0], nx[R0];
+#pragma unroll
+    for (int r = 0; r < R0; ++r) dr[r] = ok ? a.dhat[(int64_t)(q + T * r) * a.plane + g] : make_float2(0.f, 0.f);
+    const int64_t kbase = (int64_t)blockIdx.y * a.nb;
+    load_kernel(kbase, nx);
+    __syncthreads();   // twiddle table
+    for (int b = 0; b < a.nb; ++b) {
+        float2 v[R0];
+#pragma unroll
+        for (int r = 0; r < R0; ++r) v[r] = nx[r];
+        if (b + 1 < a.nb) load_kernel(kbase + b + 1, nx);   // in flight during the transforms
+        reg_stages<N, -1, R0, REST...>(v, ex[0], ex[1], tw, q, p, PITCH);
+#pragma unroll
+        for (int r = 0; r < R0; ++r) v[r] = cmul(v[r], dr[r]);
+        reg_stages<N, 1, R0, REST...>(v, ex[0], ex[1], tw, q, p, PITCH);
+        float2 *out = a.out + (kbase + b) * a.ng;
+        if (ok)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) out[(int64_t)(q + T * r) * a.plane + g] = v[r];
+    }
+}
+
 template <int N, int TPP, int NT, int... RAD>
 hipError_t launch_axis0_t(const Axis0Args &a, hipStream_t s) {
     constexpr int P = NT / TPP;
@@ -394,6 +440,12 @@ hipError_t launch_fft_pass(const FftPass &a, hipStream_t s) {
 }
 
 hipError_t launch_axis0(const Axis0Args &a, hipStream_t s) {
+    if (a.mode == 0 && a.n == 512) {
+        constexpr int P = 16;
+        dim3 grid((unsigned)((a.plane + P - 1) / P), (unsigned)a.groups);
+        hipLaunchKernelGGL((axis0_rs_kernel<512, P, 16, 8, 4>), grid, dim3(32 * P), 0, s, a);
+        return hipGetLastError();
+    }
     if (a.mode == 0 && (a.n == 256 || a.n == 128 || a.n == 64)) {
         constexpr int P = 16;
         dim3 grid((unsigned)((a.plane + P - 1) / P), (unsigned)a.groups);

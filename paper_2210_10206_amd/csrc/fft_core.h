@@ -181,6 +181,66 @@ __device__ __forceinline__ void stages(float2 *sm, const float2 *tw, int p, int 
     if constexpr (sizeof...(REST) > 0) stages<N, TPP, SIGN, NS * R, REST...>(sm, tw, p, q, pitch);
 }
 
+// Stockham stages with the first stage's inputs and the last stage's outputs in registers.
+// With radices R0, ..., RL (RL divides R0) thread q < T = n / R0 of a pencil owns elements
+// q + T s (s < R0): the inputs of first-stage butterfly q and the outputs of last-stage
+// butterflies q + T t (t < R0 / RL), which write positions q + T t + (n / RL) r.  The stages in
+// between exchange through two LDS buffers stored as buf[j * pitch + p] (pencil p), used
+// alternately, so each exchange needs one barrier.  v[s] holds element q + T s on entry and
+// on exit.
+template <int N, int T, int SIGN, int NS, int R, int... REST>
+__device__ __forceinline__ void reg_stage_rest(float2 *v, float2 *b0, float2 *b1, const float2 *tw, int q, int p,
+                                               int pitch) {
+    constexpr int NBF = N / R;        // butterflies of this stage
+    constexpr int PER = NBF / T;      // per thread
+    static_assert(NBF % T == 0, "butterflies must split evenly over the threads");
+    constexpr bool LAST = sizeof...(REST) == 0;
+    float2 u[PER][R];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int k = q + T * t;
+        const int kk = k % NS;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float2 x = b0[(k + r * NBF) * pitch + p];
+            if (r > 0) {
+                float2 w = tw[kk * r * (N / (NS * R))];
+                if (SIGN > 0) w.y = -w.y;
+                x = cmul(x, w);
+            }
+            u[t][r] = x;
+        }
+        Dft<R, SIGN>::run(u[t]);
+    }
+    if constexpr (LAST) {
+        static_assert(NS % T == 0, "the last radix must divide the first");
+#pragma unroll
+        for (int t = 0; t < PER; ++t)
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[t + (NS / T) * r] = u[t][r];
+    } else {
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            const int k = q + T * t;
+            const int base = (k / NS) * NS * R + k % NS;
+#pragma unroll
+            for (int r = 0; r < R; ++r) b1[(base + r * NS) * pitch + p] = u[t][r];
+        }
+        __syncthreads();
+        reg_stage_rest<N, T, SIGN, NS * R, REST...>(v, b1, b0, tw, q, p, pitch);
+    }
+}
+
+template <int N, int SIGN, int R0, int... REST>
+__device__ __forceinline__ void reg_stages(float2 *v, float2 *b0, float2 *b1, const float2 *tw, int q, int p,
+                                           int pitch) {
+    Dft<R0, SIGN>::run(v);   // first stage: butterfly q on the own elements, no twiddles
+#pragma unroll
+    for (int r = 0; r < R0; ++r) b0[(q * R0 + r) * pitch + p] = v[r];
+    __syncthreads();
+    reg_stage_rest<N, N / R0, SIGN, R0, REST...>(v, b0, b1, tw, q, p, pitch);
+}
+
 __device__ __forceinline__ double wave_sum64(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

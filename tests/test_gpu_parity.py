@@ -195,6 +195,21 @@ def test_every_fft_variant(sb, shape):
     plan.close()
 
 
+@pytest.mark.parametrize("shape", [(512, 8, 16), (8, 16, 512), (64, 16, 128)])
+def test_long_axes(sb, shape):
+    # axis lengths of 512 (the three-stage register-resident forms) and the 64 / 128 pairs,
+    # each on the axis-0 pass and on the fused last pass
+    say(f"case: {shape} full 3PCF, 4 bins to 4, lmax 3")
+    d = lognormal_field(shape, seed=41, sigma=1.0)
+    edges = linear_edges(4, 4)
+    plan, dev, z = run_plan(sb, [d], edges, 3)
+    ref = oracle.zeta3_full(d.astype(np.float64), edges, 3).real
+    err = rel_err(z[0], ref)
+    say(f"  err={err:.3e}")
+    assert err < TOL32
+    plan.close()
+
+
 def test_graph_replay_matches_eager(sb):
     say("case: 32^3 graph capture + replay vs eager")
     d = lognormal_field((32, 32, 32), seed=5, sigma=1.0)
