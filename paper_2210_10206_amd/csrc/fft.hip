@@ -403,13 +403,16 @@ hipError_t launch(const FftPass &a, hipStream_t s) {
 // The variants are the autotuner's candidates.
 hipError_t launch_fft_pass(const FftPass &a, hipStream_t s) {
     const int v = a.variant;
-    // variants 4 and 5 (lengths 64, 128, 256): persistent, two stages (radix 8 x 8, 16 x 8,
-    // 16 x 16), 4 / 16 tiles
+    // variants 4 and 5: persistent with few, wide radix stages (64: 8 x 8, 96: 12 x 4 x 2,
+    // 128: 16 x 8, 160: 20 x 4 x 2, 192: 12 x 4 x 4, 256: 16 x 16), 4 / 16 tiles
     if (v >= 4 && a.load == LOAD_C && a.store == STORE_C) {
         const int tiles = v == 4 ? 4 : 16;
         if (a.n == 256) return launch_pf<256, 16, 256, 16, 16>(a, s, tiles);
         if (a.n == 128) return launch_pf<128, 8, 256, 16, 8>(a, s, tiles);
         if (a.n == 64) return launch_pf<64, 8, 256, 8, 8>(a, s, tiles);
+        if (a.n == 192) return launch_pf<192, 16, 256, 12, 4, 4>(a, s, tiles);
+        if (a.n == 160) return launch_pf<160, 8, 256, 20, 4, 2>(a, s, tiles);
+        if (a.n == 96) return launch_pf<96, 8, 256, 12, 4, 2>(a, s, tiles);
     }
     // variants 2 and 3: persistent passes with register prefetch (plain loads and stores only)
     if (v >= 2 && a.load == LOAD_C && a.store == STORE_C) {
@@ -440,10 +443,14 @@ hipError_t launch_fft_pass(const FftPass &a, hipStream_t s) {
 }
 
 hipError_t launch_axis0(const Axis0Args &a, hipStream_t s) {
-    if (a.mode == 0 && a.n == 512) {
+    if (a.mode == 0 && (a.n == 512 || a.n == 192 || a.n == 160 || a.n == 96)) {
+        // register-resident stages: 512 = 16 x 8 x 4, 192 = 12 x 4 x 4, 160 = 20 x 4 x 2, 96 = 12 x 4 x 2
         constexpr int P = 16;
         dim3 grid((unsigned)((a.plane + P - 1) / P), (unsigned)a.groups);
-        hipLaunchKernelGGL((axis0_rs_kernel<512, P, 16, 8, 4>), grid, dim3(32 * P), 0, s, a);
+        if (a.n == 512) hipLaunchKernelGGL((axis0_rs_kernel<512, P, 16, 8, 4>), grid, dim3(32 * P), 0, s, a);
+        else if (a.n == 192) hipLaunchKernelGGL((axis0_rs_kernel<192, P, 12, 4, 4>), grid, dim3(16 * P), 0, s, a);
+        else if (a.n == 160) hipLaunchKernelGGL((axis0_rs_kernel<160, P, 20, 4, 2>), grid, dim3(8 * P), 0, s, a);
+        else hipLaunchKernelGGL((axis0_rs_kernel<96, P, 12, 4, 2>), grid, dim3(8 * P), 0, s, a);
         return hipGetLastError();
     }
     if (a.mode == 0 && (a.n == 256 || a.n == 128 || a.n == 64)) {
@@ -500,7 +507,7 @@ bool fft_supported(int n) {
 int fft_num_variants(int n) {
     // 0, 1: one tile per workgroup (two shapes where defined); 2, 3: persistent, 4 / 16 tiles;
     // 4, 5 (lengths 64, 128, 256): persistent with two register-sized radix stages
-    return (n == 256 || n == 128 || n == 64) ? 6 : 4;
+    return (n == 256 || n == 128 || n == 64 || n == 192 || n == 160 || n == 96) ? 6 : 4;
 }
 
 }  // namespace sb

@@ -139,6 +139,75 @@ template <int SIGN> struct Dft<16, SIGN> {
     }
 };
 
+// e^{SIGN 2 pi i j / N} for the composite radices below (angles in steps of 30 and 18 degrees)
+template <int N, int SIGN>
+__device__ __forceinline__ float2 root_of_unity(int j) {
+    static_assert(N == 12 || N == 20, "tabulated for 12 and 20");
+    float c = 1.f, s = 0.f;
+    if constexpr (N == 12) {
+        const float c30 = 0.86602540378443864676f;
+        switch (j % 12) {
+            case 1: c = c30; s = 0.5f; break;
+            case 2: c = 0.5f; s = c30; break;
+            case 3: c = 0.f; s = 1.f; break;
+            case 4: c = -0.5f; s = c30; break;
+            case 5: c = -c30; s = 0.5f; break;
+            case 6: c = -1.f; s = 0.f; break;
+            default: break;   // the 4 x 3 split uses j <= 6
+        }
+    } else {
+        const float c18 = 0.95105651629515357212f, s18 = 0.30901699437494742410f;
+        const float c36 = 0.80901699437494742410f, s36 = 0.58778525229247312917f;
+        switch (j % 20) {
+            case 1: c = c18; s = s18; break;
+            case 2: c = c36; s = s36; break;
+            case 3: c = s36; s = c36; break;
+            case 4: c = s18; s = c18; break;
+            case 5: c = 0.f; s = 1.f; break;
+            case 6: c = -s18; s = c18; break;
+            case 7: c = -s36; s = c36; break;
+            case 8: c = -c36; s = s36; break;
+            case 9: c = -c18; s = s18; break;
+            case 10: c = -1.f; s = 0.f; break;
+            case 11: c = -c18; s = -s18; break;
+            case 12: c = -c36; s = -s36; break;
+            default: break;   // the 4 x 5 split uses j <= 12
+        }
+    }
+    return make_float2(c, SIGN * s);
+}
+
+// 4 x N2 split (decimation in time), as for 16: n = N2 n1 + n2, k = k1 + 4 k2; 4-point DFTs
+// over n1, twiddles w_N^{n2 k1}, N2-point DFTs over n2.
+template <int N2, int SIGN>
+struct Dft4xN {
+    __device__ __forceinline__ static void run(float2 *v) {
+        constexpr int N = 4 * N2;
+        float2 a[N2][4];
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < 4; ++n1) a[n2][n1] = v[N2 * n1 + n2];
+            Dft<4, SIGN>::run(a[n2]);
+        }
+#pragma unroll
+        for (int n2 = 1; n2 < N2; ++n2)
+#pragma unroll
+            for (int k1 = 1; k1 < 4; ++k1) a[n2][k1] = cmul(a[n2][k1], root_of_unity<N, SIGN>(n2 * k1));
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            float2 b[N2];
+#pragma unroll
+            for (int n2 = 0; n2 < N2; ++n2) b[n2] = a[n2][k1];
+            Dft<N2, SIGN>::run(b);
+#pragma unroll
+            for (int k2 = 0; k2 < N2; ++k2) v[k1 + 4 * k2] = b[k2];
+        }
+    }
+};
+template <int SIGN> struct Dft<12, SIGN> : Dft4xN<3, SIGN> {};
+template <int SIGN> struct Dft<20, SIGN> : Dft4xN<5, SIGN> {};
+
 // One Stockham stage on pencils stored in LDS as sm[j * pitch + p] (p = pencil in the
 // tile, j = element), TPP threads per pencil, thread (p, q).
 template <int N, int TPP, int SIGN, int NS, int R>

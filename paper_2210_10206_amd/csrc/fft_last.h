@@ -150,15 +150,17 @@ __global__ __launch_bounds__(NBT * R * TPP) void last_contract_kernel(LastArgs a
 // second stage and holds elements q + RX r of the transformed row, which it writes once to
 // the [cell][bin] tile read by the MFMA pair sums.  The exchange and the contraction tile
 // are separate LDS buffers, so a tile needs two barriers.
-template <int RX, int NBT, bool IMAG>
-__global__ __launch_bounds__(NBT * RX, 3) void last_reg_kernel(LastArgs a) {
-    constexpr int N = RX * RX;
+template <int R1, int R2, int NBT, bool IMAG>
+__global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
+    constexpr int N = R1 * R2;
+    constexpr int T = R1 / R2;             // second-stage butterflies per thread
+    static_assert(R1 % R2 == 0, "R2 must divide R1");
     constexpr int P = NBT;                 // pencils (bins) per tile
-    constexpr int NT = P * RX;
+    constexpr int NT = P * R2;
     constexpr int NW = NT / 64;
     constexpr int NQ = N / 4;              // cell quads per tile
     constexpr int NPART = IMAG ? 2 : 1;
-    constexpr int EXP = RX * (RX + 1);     // exchange floats2 per pencil (rows padded by one)
+    constexpr int EXP = R2 * (R1 + 1);     // exchange float2 per pencil: R2 rows of R1, padded by one
     constexpr int PITCH = P + 1;
     constexpr int WPT = (N + NT - 1) / NT;
     static_assert(NT % 64 == 0, "whole waves");
@@ -168,10 +170,12 @@ __global__ __launch_bounds__(NBT * RX, 3) void last_reg_kernel(LastArgs a) {
     const int nb = a.nb;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
-    const int q = tid % RX, pp = tid / RX;  // element column, pencil (= bin)
-    float2 tw[RX];                          // w^{q r}, w = e^{-2 pi i / N}; the inverse takes the conjugate
+    const int q = tid % R2, pp = tid / R2;  // element column, pencil (= bin)
+    float2 tw[T][R2];                       // w^{(q + R2 t) r}, w = e^{-2 pi i / N}; the inverse takes the conjugate
 #pragma unroll
-    for (int r = 0; r < RX; ++r) tw[r] = a.tw[(q * r) % N];
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int r = 0; r < R2; ++r) tw[t][r] = a.tw[((q + R2 * t) * r) % N];
     double tot[NPART][4];
 #pragma unroll
     for (int u = 0; u < NPART; ++u)
@@ -184,36 +188,42 @@ __global__ __launch_bounds__(NBT * RX, 3) void last_reg_kernel(LastArgs a) {
     const bool live = pp < nb;
     auto load_row = [&](int64_t row, float2 *dst, float *wdst) {
 #pragma unroll
-        for (int r = 0; r < RX; ++r) dst[r] = live ? in[row * N + q + RX * r] : make_float2(0.f, 0.f);
+        for (int r = 0; r < R1; ++r) dst[r] = live ? in[row * N + q + R2 * r] : make_float2(0.f, 0.f);
 #pragma unroll
         for (int e = 0; e < WPT; ++e) {
             const int c = tid + e * NT;
             wdst[e] = c < N ? a.w[row * N + c] : 0.f;
         }
     };
-    float2 nx[RX];
+    float2 nx[R1];
     float nw[WPT];
     if (r_begin < r_end) load_row(r_begin, nx, nw);
     for (int64_t row = r_begin; row < r_end; ++row) {
-        float2 v[RX];
+        float2 v[R1];
 #pragma unroll
-        for (int r = 0; r < RX; ++r) v[r] = nx[r];
+        for (int r = 0; r < R1; ++r) v[r] = nx[r];
         float wv[WPT];
 #pragma unroll
         for (int e = 0; e < WPT; ++e) wv[e] = nw[e];
         if (row + 1 < r_end) load_row(row + 1, nx, nw);    // next row in flight
-        Dft<RX, 1>::run(v);
+        // first stage: radix-R1 butterfly q (elements q + R2 s) -> positions R1 q + r
+        Dft<R1, 1>::run(v);
 #pragma unroll
-        for (int r = 0; r < RX; ++r) ex[pp * EXP + q * (RX + 1) + r] = v[r];
+        for (int r = 0; r < R1; ++r) ex[pp * EXP + q * (R1 + 1) + r] = v[r];
         __syncthreads();
+        // second stage: radix-R2 butterflies q + R2 t, positions q + R2 t + R1 r
 #pragma unroll
-        for (int r = 0; r < RX; ++r) {
-            const float2 x = ex[pp * EXP + r * (RX + 1) + q];
-            v[r] = r == 0 ? x : cmul(x, make_float2(tw[r].x, -tw[r].y));
+        for (int t = 0; t < T; ++t) {
+            float2 u[R2];
+#pragma unroll
+            for (int r = 0; r < R2; ++r) {
+                const float2 x = ex[pp * EXP + r * (R1 + 1) + q + R2 * t];
+                u[r] = r == 0 ? x : cmul(x, make_float2(tw[t][r].x, -tw[t][r].y));
+            }
+            Dft<R2, 1>::run(u);
+#pragma unroll
+            for (int r = 0; r < R2; ++r) cs[(q + R2 * t + R1 * r) * PITCH + pp] = u[r];
         }
-        Dft<RX, 1>::run(v);
-#pragma unroll
-        for (int r = 0; r < RX; ++r) cs[(q + RX * r) * PITCH + pp] = v[r];
 #pragma unroll
         for (int e = 0; e < WPT; ++e)
             if (tid + e * NT < N) wsm[tid + e * NT] = wv[e];
@@ -263,17 +273,161 @@ __global__ __launch_bounds__(NBT * RX, 3) void last_reg_kernel(LastArgs a) {
     }
 }
 
-template <int RX>
+// bins padded so that NBT * R2 threads make whole waves
+constexpr int reg_padded_bins(int nb, int r2) {
+    const int step = 64 / r2 < 1 ? 1 : 64 / r2;
+    return (nb + step - 1) / step * step;
+}
+
+template <int R1, int R2>
 hipError_t launch_last_reg(const LastArgs &a, hipStream_t s) {
     if (a.rows != 1) return hipErrorInvalidValue;
     dim3 grid((unsigned)a.nblocks, (unsigned)a.groups);
     const bool im = a.want_imag != 0;
-    const int nbt = (a.nb + 3) / 4 * 4;
-#define SB_LR(NBT)                                                                                    \
-    case NBT:                                                                                          \
-        if (im) hipLaunchKernelGGL((last_reg_kernel<RX, NBT, true>), grid, dim3(NBT * RX), 0, s, a);   \
-        else hipLaunchKernelGGL((last_reg_kernel<RX, NBT, false>), grid, dim3(NBT * RX), 0, s, a);     \
-        break;
+    const int nbt = reg_padded_bins(a.nb, R2);
+#define SB_LR(NBT)                                                                                          \
+    case NBT:                                                                                                \
+        if constexpr ((NBT * R2) % 64 == 0) {                                                                \
+            if (im) hipLaunchKernelGGL((last_reg_kernel<R1, R2, NBT, true>), grid, dim3(NBT * R2), 0, s, a);   \
+            else hipLaunchKernelGGL((last_reg_kernel<R1, R2, NBT, false>), grid, dim3(NBT * R2), 0, s, a);     \
+            break;                                                                                           \
+        } else {                                                                                             \
+            return hipErrorInvalidValue;                                                                     \
+        }
+    switch (nbt) {
+        SB_LR(4) SB_LR(8) SB_LR(12) SB_LR(16)
+        default: return hipErrorInvalidValue;
+    }
+#undef SB_LR
+    return hipGetLastError();
+}
+
+// Register-resident form for any radix list R0, ... (each radix divides R0; see reg_stages):
+// a tile is one row of the NBT (padded) bins of one (l, m); thread q < T = n / R0 of a
+// pencil loads elements q + T s.  The stages exchange through two LDS buffers laid out
+// [position][bin]; the transformed row is written to the buffer the last stage did not read,
+// which is then the [cell][bin] tile of the MFMA pair sums.
+template <int N, int NBT, bool IMAG, int R0, int... REST>
+__global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
+    constexpr int T = N / R0;
+    constexpr int P = NBT;
+    constexpr int NT = P * T;
+    constexpr int NW = NT / 64;
+    constexpr int NQ = N / 4;
+    constexpr int NPART = IMAG ? 2 : 1;
+    constexpr int PITCH = P + 1;
+    constexpr int NSTAGE = 1 + sizeof...(REST);
+    constexpr int CSB = (NSTAGE - 1) % 2;       // buffer the last stage does not read
+    constexpr int WPT = (N + NT - 1) / NT;
+    static_assert(NT % 64 == 0 && NSTAGE >= 2, "whole waves, two stages or more");
+    __shared__ float2 ex[2][N * PITCH];
+    __shared__ float2 tw[N];
+    __shared__ float wsm[N];
+    const int nb = a.nb;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int q = tid % T, pp = tid / T;        // element column, pencil (= bin)
+    for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
+    double tot[NPART][4];
+#pragma unroll
+    for (int u = 0; u < NPART; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tot[u][r] = 0.0;
+    const int64_t nrows = a.ng / N;
+    const int64_t r_begin = (int64_t)blockIdx.x * a.rows_per_block;
+    const int64_t r_end = min(r_begin + a.rows_per_block, nrows);
+    const float2 *in = a.in + ((int64_t)blockIdx.y * nb + pp) * a.ng;
+    const bool live = pp < nb;
+    auto load_row = [&](int64_t row, float2 *dst, float *wdst) {
+#pragma unroll
+        for (int r = 0; r < R0; ++r) dst[r] = live ? in[row * N + q + T * r] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int e = 0; e < WPT; ++e) {
+            const int c = tid + e * NT;
+            wdst[e] = c < N ? a.w[row * N + c] : 0.f;
+        }
+    };
+    float2 nx[R0];
+    float nw[WPT];
+    if (r_begin < r_end) load_row(r_begin, nx, nw);
+    for (int64_t row = r_begin; row < r_end; ++row) {
+        float2 v[R0];
+#pragma unroll
+        for (int r = 0; r < R0; ++r) v[r] = nx[r];
+        float wv[WPT];
+#pragma unroll
+        for (int e = 0; e < WPT; ++e) wv[e] = nw[e];
+        if (row + 1 < r_end) load_row(row + 1, nx, nw);    // next row in flight
+        __syncthreads();                                    // the previous row's pair sums are done
+        reg_stages<N, 1, R0, REST...>(v, ex[0], ex[1], tw, q, pp, PITCH);
+        float2 *cs = ex[CSB];
+#pragma unroll
+        for (int r = 0; r < R0; ++r) cs[(q + T * r) * PITCH + pp] = v[r];
+#pragma unroll
+        for (int e = 0; e < WPT; ++e)
+            if (tid + e * NT < N) wsm[tid + e * NT] = wv[e];
+        __syncthreads();
+        f4v acc[2 * NPART];
+#pragma unroll
+        for (int u = 0; u < 2 * NPART; ++u) acc[u] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+        for (int k = 0; k < (NQ + NW - 1) / NW; ++k) {
+            const int qd = wave + k * NW;
+            if (qd < NQ) {
+                const int c = 4 * qd + lg;
+                const float w = wsm[c];
+                const float2 x = li < NBT ? cs[c * PITCH + li] : make_float2(0.f, 0.f);   // zero beyond nb
+                const float wx = w * x.x, wy = w * x.y;
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx, x.x, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(wy, x.y, acc[1], 0, 0, 0);
+                if constexpr (IMAG) {
+                    acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(wy, x.x, acc[2], 0, 0, 0);
+                    acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(-wx, x.y, acc[3], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NPART; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tot[u][r] += (double)acc[2 * u][r] + (double)acc[2 * u + 1][r];
+    }
+    // float64 combine over the waves in wave order (as in last_contract_kernel)
+    __syncthreads();
+    double *red = reinterpret_cast<double *>(&ex[0][0]);
+#pragma unroll
+    for (int u = 0; u < NPART; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[(wave * NPART + u) * 256 + (4 * lg + r) * 16 + li] = tot[u][r];
+    __syncthreads();
+    const int npn = nb * (nb + 1) / 2;
+    const int nv = npn * NPART;
+    for (int vv = tid; vv < nv; vv += NT) {
+        const int vp = vv % npn, part = vv / npn;
+        int b1 = 0, rem = vp;
+        while (rem >= nb - b1) { rem -= nb - b1; ++b1; }
+        const int b2 = b1 + rem;
+        double sum = 0.0;
+        for (int w = 0; w < NW; ++w) sum += red[(w * NPART + part) * 256 + b1 * 16 + b2];
+        a.partial[((int64_t)blockIdx.y * nv + vv) * a.nblocks + blockIdx.x] = sum;
+    }
+}
+
+template <int N, int R0, int... REST>
+hipError_t launch_last_rs(const LastArgs &a, hipStream_t s) {
+    constexpr int T = N / R0;
+    if (a.rows != 1) return hipErrorInvalidValue;
+    dim3 grid((unsigned)a.nblocks, (unsigned)a.groups);
+    const bool im = a.want_imag != 0;
+    const int nbt = reg_padded_bins(a.nb, T);
+#define SB_LR(NBT)                                                                                               \
+    case NBT:                                                                                                     \
+        if constexpr ((NBT * T) % 64 == 0 && NBT * T <= 1024) {                                                   \
+            if (im) hipLaunchKernelGGL((last_rs_kernel<N, NBT, true, R0, REST...>), grid, dim3(NBT * T), 0, s, a);  \
+            else hipLaunchKernelGGL((last_rs_kernel<N, NBT, false, R0, REST...>), grid, dim3(NBT * T), 0, s, a);    \
+            break;                                                                                                \
+        } else {                                                                                                  \
+            return hipErrorInvalidValue;                                                                          \
+        }
     switch (nbt) {
         SB_LR(4) SB_LR(8) SB_LR(12) SB_LR(16)
         default: return hipErrorInvalidValue;

@@ -6,7 +6,7 @@ namespace sb {
 
 // 256 = 16 x 16: the register-resident form, one row per tile
 template <> hipError_t launch_last_for<256>(const LastArgs &a, hipStream_t s) {
-    return fftlast::launch_last_reg<16>(a, s);
+    return fftlast::launch_last_reg<16, 16>(a, s);
 }
 template <> int last_rows<256>(int nb) { return nb <= 16 ? 1 : 0; }
 

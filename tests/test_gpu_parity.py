@@ -195,7 +195,8 @@ def test_every_fft_variant(sb, shape):
     plan.close()
 
 
-@pytest.mark.parametrize("shape", [(512, 8, 16), (8, 16, 512), (64, 16, 128)])
+@pytest.mark.parametrize("shape", [(512, 8, 16), (8, 16, 512), (64, 16, 128), (160, 8, 192), (96, 8, 160),
+                                   (192, 8, 96)])
 def test_long_axes(sb, shape):
     # axis lengths of 512 (the three-stage register-resident forms) and the 64 / 128 pairs,
     # each on the axis-0 pass and on the fused last pass
@@ -208,6 +209,48 @@ def test_long_axes(sb, shape):
     say(f"  err={err:.3e}")
     assert err < TOL32
     plan.close()
+
+
+def test_call_order_and_argument_errors(sb):
+    # error paths of the C ABI that need a plan (whose creation allocates device tables)
+    import ctypes
+    from paper_2210_10206_amd import _lib
+    lib = _lib.load()
+    say("case: C-ABI state and argument errors on a 16^3 plan")
+    edges = np.array([0.0, 2.0, 4.0])
+    prob = _lib.SbProblem(3, 3, 2, edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 2, 0, 0, 0)
+    sh = np.array([16, 16, 16], dtype=np.int64)
+    h = ctypes.c_void_p()
+    assert lib.sb_plan_create(ctypes.byref(prob), 1, sh.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                              ctypes.byref(h)) == 0
+    d = torch.zeros((16, 16, 16), dtype=torch.float32, device="cuda")
+    z = torch.zeros(64, dtype=torch.float64, device="cuda")
+    ptrs = (ctypes.c_void_p * 1)(d.data_ptr())
+    assert lib.sb_forward(h, ptrs, ctypes.c_void_p(z.data_ptr()), None) == -3          # not bound
+    pb, sbytes = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.sb_plan_workspace(h, ctypes.byref(pb), ctypes.byref(sbytes)) == 0
+    pers = torch.empty(pb.value + 256, dtype=torch.uint8, device="cuda")
+    scr = torch.empty(sbytes.value + 256, dtype=torch.uint8, device="cuda")
+    pp, sp = (pers.data_ptr() + 255) & ~255, (scr.data_ptr() + 255) & ~255
+    assert lib.sb_plan_bind(h, ctypes.c_void_p(pp), pb.value - 1, ctypes.c_void_p(sp), sbytes.value) == -3
+    assert lib.sb_plan_bind(h, ctypes.c_void_p(pp + 8), pb.value, ctypes.c_void_p(sp), sbytes.value) == -1
+    assert lib.sb_plan_bind(h, ctypes.c_void_p(pp), pb.value, ctypes.c_void_p(sp), sbytes.value) == 0
+    assert lib.sb_forward(h, ptrs, ctypes.c_void_p(z.data_ptr()), None) == -6          # not prepared
+    assert lib.sb_plan_set_scratch_limit(h, ctypes.c_uint64(1 << 20)) == -6            # after bind
+    assert lib.sb_plan_set_fft_variant(h, 7, 0, 0) == -1                              # no such length
+    assert lib.sb_plan_set_fft_variant(h, 16, 0, 99) == -1                            # no such variant
+    assert lib.sb_plan_set_fft_variant(h, 16, 3, 0) == -1                             # no such axis
+    assert lib.sb_fft_variants(7) == 0 and lib.sb_fft_variants(16) >= 1
+    assert lib.sb_prepare(h, None) == 0
+    assert lib.sb_forward(h, ptrs, None, None) == -1                                  # null output
+    assert lib.sb_forward(h, ptrs, ctypes.c_void_p(z.data_ptr()), None) == 0
+    torch.cuda.synchronize()
+    lib.sb_plan_destroy(h)
+    # the adjoint exists for the full 3PCF only
+    p4 = sb.Plan([(16, 16, 16)], edges, 2, npcf=4)
+    with pytest.raises(Exception):
+        p4.backward([d], torch.zeros((1, 100), dtype=torch.float64, device="cuda"))
+    p4.close()
 
 
 def test_graph_replay_matches_eager(sb):
@@ -243,6 +286,18 @@ def test_last_axis_256_bin_counts(sb, nbins):
     say(f"  err={err:.3e}")
     assert err < TOL32
     plan.close()
+
+
+@pytest.mark.parametrize("shape", [(16, 160), (12, 192), (24, 96), (16, 128), (16, 64)])
+def test_projected_register_last_pass(sb, shape):
+    say(f"case: {shape} projected 3PCF, 4 bins to 6, mmax 4")
+    d = lognormal_field(shape, seed=13, sigma=1.0)
+    edges = linear_edges(6, 4)
+    _, _, z3 = run_plan(sb, [d], edges, 4, npcf=3)
+    ref3 = oracle.zeta3_proj(d.astype(np.float64), edges, 4)
+    e3 = rel_err(z3[0], ref3)
+    say(f"  proj3 err={e3:.3e}")
+    assert e3 < TOL32
 
 
 def test_projected_last_axis_256(sb):
