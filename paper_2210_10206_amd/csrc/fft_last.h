@@ -273,10 +273,12 @@ __global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
     }
 }
 
-// bins padded so that NBT * R2 threads make whole waves
-constexpr int reg_padded_bins(int nb, int r2) {
-    const int step = 64 / r2 < 1 ? 1 : 64 / r2;
-    return (nb + step - 1) / step * step;
+// bins padded to the instantiated tile widths 4, 8, 12, 16 so that NBT * t threads make whole
+// waves (0: none fits)
+constexpr int reg_padded_bins(int nb, int t) {
+    for (int c = 4; c <= 16; c += 4)
+        if (c >= nb && (c * t) % 64 == 0) return c;
+    return 0;
 }
 
 template <int R1, int R2>
