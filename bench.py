@@ -201,6 +201,7 @@ def run_c5(api, steps, warmup, synth_steps=200):
     dev = [torch.from_numpy(f).cuda() for f in fields]
     edges = linear_edges(16, 8)
     plan = api.Plan([f.shape for f in fields], edges, 4, npcf=3)
+    plan.autotune(torch.cuda.current_stream())
     G = torch.from_numpy(np.random.Generator(np.random.PCG64(5)).standard_normal((len(dev), 5, 8, 8))).cuda()
     for _ in range(warmup):
         plan.forward(dev)
@@ -220,6 +221,7 @@ def run_c5(api, steps, warmup, synth_steps=200):
     del dev
     n = 128
     sp = api.Plan([(n, n, n)], edges, 4, npcf=3)
+    sp.autotune(torch.cuda.current_stream())
     target = sp.forward([torch.from_numpy(lognormal_field((n,) * 3, seed=100, sigma=1.0)).cuda()])[0]
     init = torch.from_numpy(gaussian_field((n,) * 3, seed=101)).cuda()
     torch.cuda.synchronize()
@@ -254,6 +256,7 @@ def run_512(api, steps, warmup):
         plan.prepare(stream)
     stream.synchronize()
     cold = time.perf_counter() - t0
+    plan.autotune(stream)
     out = torch.empty((1, plan.zeta_doubles), dtype=torch.float64, device="cuda")
     with torch.cuda.stream(stream):
         for _ in range(warmup):
