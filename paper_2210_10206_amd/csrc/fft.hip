@@ -469,15 +469,6 @@ hipError_t launch_axis0(const Axis0Args &a, hipStream_t s) {
     }
 }
 
-int fft_threads_per_pencil(int n) {
-    switch (n) {
-#define SB_X(N, TPP, NT, ...) case N: return TPP;
-        SB_FUSED_CONFIGS(SB_X)
-#undef SB_X
-        default: return 0;
-    }
-}
-
 int fused_last_rows(int n, int nb) {
     switch (n) {
 #define SB_X(N, TPP, ...) case N: return last_rows<N>(nb);

@@ -52,7 +52,6 @@ struct FftPass {
 hipError_t launch_fft_pass(const FftPass &p, hipStream_t s);
 bool fft_supported(int n);
 int fft_num_variants(int n);
-int fft_threads_per_pencil(int n);   // threads per pencil of the fused passes
 
 // First inverse pass along axis 0 with the kernel spectra regenerated from their
 // compact storage (transformed along the other axes, np planes along axis 0: stored
