@@ -169,6 +169,7 @@ sb_status sb_autotune(sb_plan *plan, void *stream);
  * the variant beyond float32 rounding. */
 int32_t sb_fft_variants(int32_t n);
 sb_status sb_plan_set_fft_variant(sb_plan *plan, int32_t n, int32_t axis, int32_t variant);
+sb_status sb_plan_get_fft_variant(const sb_plan *plan, int32_t n, int32_t axis, int32_t *variant);
 
 /* Forward pass replayed from a HIP graph captured on first use for these exact
  * pointers (re-captured when they change).  Same contract as sb_forward. */

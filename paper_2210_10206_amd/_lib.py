@@ -36,6 +36,7 @@ SIGNATURES = {
     "sb_plan_set_scratch_limit": (c_i32, [c_vp, ctypes.c_uint64]),
     "sb_fft_variants": (c_i32, [c_i32]),
     "sb_plan_set_fft_variant": (c_i32, [c_vp, c_i32, c_i32, c_i32]),
+    "sb_plan_get_fft_variant": (c_i32, [c_vp, c_i32, c_i32, P(c_i32)]),
     "sb_plan_bind": (c_i32, [c_vp, c_vp, c_sz, c_vp, c_sz]),
     "sb_prepare": (c_i32, [c_vp, c_vp]),
     "sb_zeta_size": (c_i32, [c_vp, P(c_i64)]),

@@ -204,6 +204,23 @@ class Plan:
         check(self.lib.sb_plan_set_fft_variant(self.handle, int(n), int(axis), int(variant)),
               "sb_plan_set_fft_variant")
 
+    def fft_choices(self):
+        """The FFT launch shape of every (length, axis) of this plan's shapes: a dict
+        {"n,axis": variant} that set_fft_choices() restores (e.g. tuned once, saved as JSON)."""
+        out = {}
+        for shape in self.shapes:
+            for axis, n in enumerate(shape):
+                v = ctypes.c_int32()
+                check(self.lib.sb_plan_get_fft_variant(self.handle, int(n), axis, ctypes.byref(v)),
+                      "sb_plan_get_fft_variant")
+                out[f"{n},{axis}"] = v.value
+        return out
+
+    def set_fft_choices(self, choices):
+        for key, v in choices.items():
+            n, axis = (int(x) for x in key.split(","))
+            self.set_fft_variant(n, axis, int(v))
+
     def profile(self, enable: bool):
         check(self.lib.sb_profile(self.handle, int(bool(enable))), "sb_profile")
 

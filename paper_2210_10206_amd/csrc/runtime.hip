@@ -132,6 +132,14 @@ sb_status sb_plan_set_fft_variant(sb_plan *p, int32_t n, int32_t axis, int32_t v
     return SB_OK;
 }
 
+sb_status sb_plan_get_fft_variant(const sb_plan *p, int32_t n, int32_t axis, int32_t *variant) {
+    if (!p || !variant) return fail(SB_EINVAL, "null argument");
+    if (!fft_supported(n)) return fail(SB_EINVAL, "unsupported length");
+    if (axis < 0 || axis >= p->prob.ndim) return fail(SB_EINVAL, "axis out of range");
+    *variant = p->fft_variant(n, axis);
+    return SB_OK;
+}
+
 sb_status sb_forward_graph(sb_plan *p, const void *const *delta, double *zeta, void *stream) {
     if (!p || !delta || !zeta) return fail(SB_EINVAL, "null argument");
     hipStream_t s = static_cast<hipStream_t>(stream);

@@ -192,6 +192,13 @@ def test_every_fft_variant(sb, shape):
         plan.set_fft_variant(n, axis, 0)
     say(f"  worst err over the variants={worst:.3e}")
     assert worst < TOL32
+    # tuned choices round-trip through fft_choices / set_fft_choices
+    plan.autotune(torch.cuda.current_stream())
+    tuned = plan.fft_choices()
+    plan.set_fft_choices({k: 0 for k in tuned})
+    assert all(v == 0 for v in plan.fft_choices().values())
+    plan.set_fft_choices(tuned)
+    assert plan.fft_choices() == tuned
     plan.close()
 
 
