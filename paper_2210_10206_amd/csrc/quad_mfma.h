@@ -164,17 +164,29 @@ __device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
 
 // Pair layout of the M tiles: lane row i of tile mt is (b1, b2) = (2 mt + i / 8, i % 8), so a
 // lane keeps the same b2 in all four tiles; pairs with a bin >= nbins hold zeros.
+//
+// Staging: a tile of 64 cells sits in LDS cell-major, one row of NCOL x 8 float2 per cell padded
+// to S = 8 NCOL + 2 float2.  S = 2 (mod 8) makes both LDS phases free of bank conflicts: the
+// stores (64 consecutive cells of one (column, bin) per wave instruction, c S mod 32 distinct
+// over 16 lanes) and the per-lane reads (cells 4 apart in the four lane groups land 8 float2
+// apart, bins fill the slots between).  The next tile's global loads are issued into registers
+// before the current tile is contracted, so their latency hides behind the coupling work.
 template <int LA, int LB, int LC, int PREC>
 __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
     constexpr bool ODD = ((LA + LB + LC) & 1) != 0;
     using CL = Cols<LA, LB, LC>;
     constexpr int NCOL = CL::ncol;
     constexpr int TC = kTileCells;
-    __shared__ float2 tile[TC * NCOL * kMaxNB];
+    constexpr int S = NCOL * kMaxNB + 2;          // float2 per staged cell row
+    constexpr int NLD = NCOL * kMaxNB * TC / 256; // float2 loads per thread and tile
+    constexpr int NRED = 4 * kMaxNB * kMaxNB * kMaxNB;
+    constexpr int NTILE = TC * S > NRED / 2 ? TC * S : NRED / 2;
+    __shared__ float2 tile[NTILE];
     __shared__ float wt[TC];
-    __shared__ float red[4 * kMaxNB * kMaxNB * kMaxNB];
+    float *red = reinterpret_cast<float *>(tile);   // reused for the block reduction at the end
     const int nb = a.nbins;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: row addresses stay scalar
     const int i = lane & 15, g = lane >> 4;
     const int b2 = i & 7, bh = i >> 3;
     const float *cw = a.coefw;   // weighted 3j values of this Lambda, table order (mc outer, ma inner)
@@ -183,22 +195,35 @@ __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
     for (int mt = 0; mt < kMT; ++mt) acc[mt] = f4v{0.f, 0.f, 0.f, 0.f};
     const int64_t c0 = (int64_t)blockIdx.x * a.cells_per_block;
     const int64_t c1 = min(c0 + a.cells_per_block, a.ng);
-    for (int64_t tc = c0; tc < c1; tc += TC) {
-        const int ncell = (int)min((int64_t)TC, c1 - tc);
-        __syncthreads();
-        for (int f = tid; f < TC * NCOL * kMaxNB; f += 256) {
-            const int c = f % TC, kb = f / TC;
+    // load k of this thread: cell = lane, (column, bin) row = wave + 4 k
+    float2 pf[NLD];
+    float pw = 0.f;
+    auto gload = [&](int64_t tc) {
+        const bool in = tc + lane < c1;
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int kb = wave + 4 * k;
             const int col = kb / kMaxNB, b = kb % kMaxNB;
-            float2 v = make_float2(0.f, 0.f);
-            if (c < ncell && b < nb) v = a.coef[((int64_t)CL::lm_of(col) * nb + b) * a.ng + tc + c];
-            tile[(c * NCOL + col) * kMaxNB + b] = v;
+            const float2 *src = a.coef + ((int64_t)CL::lm_of(col) * nb + b) * a.ng + tc;
+            pf[k] = (in && b < nb) ? src[lane] : make_float2(0.f, 0.f);
         }
-        for (int c = tid; c < TC; c += 256) wt[c] = c < ncell ? a.w[tc + c] : 0.f;
+        if (wave == 0) pw = in ? a.w[tc + lane] : 0.f;
+    };
+    gload(c0);
+    for (int64_t tc = c0; tc < c1; tc += TC) {
         __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int kb = wave + 4 * k;
+            tile[lane * S + kb] = pf[k];   // kb = column * 8 + bin
+        }
+        if (wave == 0) wt[lane] = pw;
+        __syncthreads();
+        if (tc + TC < c1) gload(tc + TC);
         // this lane's cells: 16 wave + 4 g + cc, one at a time (K of the MFMA = the lane groups)
 #pragma unroll
         for (int cc = 0; cc < 4; ++cc) {
-            const float2 *row = tile + (16 * wave + 4 * g + cc) * NCOL * kMaxNB;
+            const float2 *row = tile + (16 * wave + 4 * g + cc) * S;
             const float wv = wt[16 * wave + 4 * g + cc];
             float2 A1[kMT][LA + 1], A2[LB + 1], bv[LC + 1];
 #pragma unroll
