@@ -174,7 +174,7 @@ def run_4pcf_batch(api, steps, warmup, count=16, precision="fp32", mfma=True, pa
         kname, peak = "quad_kernel (3j-coupled contraction, float32 VALU)", 157.3
     res = {"workload": f"full 4PCF, {count} lognormal 128^3 float32 fields (sigma ~ U[0.5,2]), 8 bins over (0,24], "
                        "even Lambda with l <= 4 (42)",
-           "precision": precision, "matrix_cores": bool(mfma),
+           "precision": precision, "matrix_cores": bool(mfma), "contract_tile": plan.contract_tile()[0],
            "value": round(count * steps / el, 3), "unit": "fields/s", "ms_per_step": round(el / steps * 1e3, 2),
            "contraction": {"kernel": kname,
                            "achieved_tflops": round(fl / (ms * 1e-3) / 1e12, 2) if ms else None,

@@ -171,6 +171,15 @@ int32_t sb_fft_variants(int32_t n);
 sb_status sb_plan_set_fft_variant(sb_plan *plan, int32_t n, int32_t axis, int32_t variant);
 sb_status sb_plan_get_fft_variant(const sb_plan *plan, int32_t n, int32_t axis, int32_t *variant);
 
+/* Cells per workgroup ("contraction tile") of the cell-parallel contractions: the full
+ * 4PCF (Alg. 6), the projected 4PCF (Alg. 8) and the unfused 3PCF pair sums (Alg. 5, 7).
+ * A power of two within [lo, hi] = [512, 4096] (full 4PCF), [1024, 8192] (projected
+ * 4PCF), [2048, 16384] (3PCF); the workspace of sb_plan_workspace holds the partial sums
+ * of lo.  sb_autotune sets it by timing; set returns SB_EINVAL outside the range.  The
+ * choice only reorders the FP64 sum of per-workgroup partials.  get: lo and hi may be NULL. */
+sb_status sb_plan_set_contract_tile(sb_plan *plan, int32_t cells);
+sb_status sb_plan_get_contract_tile(const sb_plan *plan, int32_t *cells, int32_t *lo, int32_t *hi);
+
 /* Forward pass replayed from a HIP graph captured on first use for these exact
  * pointers (re-captured when they change).  Same contract as sb_forward. */
 sb_status sb_forward_graph(sb_plan *plan, const void *const *delta, double *zeta, void *stream);

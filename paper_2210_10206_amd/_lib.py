@@ -37,6 +37,8 @@ SIGNATURES = {
     "sb_fft_variants": (c_i32, [c_i32]),
     "sb_plan_set_fft_variant": (c_i32, [c_vp, c_i32, c_i32, c_i32]),
     "sb_plan_get_fft_variant": (c_i32, [c_vp, c_i32, c_i32, P(c_i32)]),
+    "sb_plan_set_contract_tile": (c_i32, [c_vp, c_i32]),
+    "sb_plan_get_contract_tile": (c_i32, [c_vp, P(c_i32), P(c_i32), P(c_i32)]),
     "sb_plan_bind": (c_i32, [c_vp, c_vp, c_sz, c_vp, c_sz]),
     "sb_prepare": (c_i32, [c_vp, c_vp]),
     "sb_zeta_size": (c_i32, [c_vp, P(c_i64)]),

@@ -204,22 +204,35 @@ class Plan:
         check(self.lib.sb_plan_set_fft_variant(self.handle, int(n), int(axis), int(variant)),
               "sb_plan_set_fft_variant")
 
-    def fft_choices(self):
-        """The FFT launch shape of every (length, axis) of this plan's shapes: a dict
-        {"n,axis": variant} that set_fft_choices() restores (e.g. tuned once, saved as JSON)."""
-        out = {}
+    def contract_tile(self):
+        """Cells per workgroup of the cell-parallel contraction and its allowed range (lo, hi)."""
+        c, lo, hi = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(self.lib.sb_plan_get_contract_tile(self.handle, ctypes.byref(c), ctypes.byref(lo), ctypes.byref(hi)),
+              "sb_plan_get_contract_tile")
+        return c.value, (lo.value, hi.value)
+
+    def set_contract_tile(self, cells: int):
+        check(self.lib.sb_plan_set_contract_tile(self.handle, int(cells)), "sb_plan_set_contract_tile")
+
+    def choices(self):
+        """The tuned launch shapes of this plan: {"fft": {"n,axis": variant} for every (length,
+        axis) of its shapes, "contract_tile": cells per workgroup}; set_choices() restores them
+        (e.g. tuned once, saved as JSON)."""
+        fft = {}
         for shape in self.shapes:
             for axis, n in enumerate(shape):
                 v = ctypes.c_int32()
                 check(self.lib.sb_plan_get_fft_variant(self.handle, int(n), axis, ctypes.byref(v)),
                       "sb_plan_get_fft_variant")
-                out[f"{n},{axis}"] = v.value
-        return out
+                fft[f"{n},{axis}"] = v.value
+        return {"fft": fft, "contract_tile": self.contract_tile()[0]}
 
-    def set_fft_choices(self, choices):
-        for key, v in choices.items():
+    def set_choices(self, choices):
+        for key, v in choices.get("fft", {}).items():
             n, axis = (int(x) for x in key.split(","))
             self.set_fft_variant(n, axis, int(v))
+        if "contract_tile" in choices:
+            self.set_contract_tile(choices["contract_tile"])
 
     def profile(self, enable: bool):
         check(self.lib.sb_profile(self.handle, int(bool(enable))), "sb_profile")

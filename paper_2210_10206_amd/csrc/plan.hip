@@ -91,22 +91,23 @@ static sb_status build_gather(sb_plan *p, std::vector<int> &gptr, std::vector<in
     return SB_OK;
 }
 
-static void contraction_shape(const sb_plan *p, int64_t ng, int *groups, int *nvals, int *nblocks) {
+// cpb: cells per workgroup (0: the plan's current choice)
+static void contraction_shape(const sb_plan *p, int64_t ng, int *groups, int *nvals, int *nblocks, int cpb = 0) {
     const int NB = p->prob.nbins;
+    if (cpb == 0) cpb = p->contract_tile();
     if (p->prob.npcf == 3) {
         *groups = p->nlm;
         *nvals = NB * (NB + 1) / 2 * (p->prob.ndim == 2 ? 2 : 1);
-        *nblocks = (int)((ng + p->cpb_pair - 1) / p->cpb_pair);
     } else if (p->prob.ndim == 3) {
         *groups = (int)p->f4.canon.size();
         *nvals = NB * NB * NB;
-        *nblocks = (int)((ng + p->cpb_quad - 1) / p->cpb_quad);
     } else {
         *groups = (int)p->p4_canon.size();
         *nvals = 2 * NB * NB * NB;
-        *nblocks = (int)((ng + p->cpb_proj4 - 1) / p->cpb_proj4);
     }
+    *nblocks = (int)((ng + cpb - 1) / cpb);
 }
+
 
 // Scratch layout.  A 3PCF plan whose full set of kernel arrays exceeds coef_limit runs its
 // passes over chunks of kernel groups (the fused contraction and the adjoint only need one
@@ -123,8 +124,9 @@ void layout_scratch(sb_plan *p) {
     p->off_w = sc; sc += align256((size_t)p->max_ng * sizeof(float));
     p->off_dhat = sc; sc += align256((size_t)p->max_ng * sizeof(float2));
     p->off_coef = sc; sc += align256((size_t)p->chunk_groups * NB * p->max_ng * sizeof(float2));
-    int groups = 0, nvals = 0, nblocks = 0;
-    contraction_shape(p, p->max_ng, &groups, &nvals, &nblocks);
+    int groups = 0, nvals = 0, nblocks = 0, tile_lo = 0, tile_hi = 0;
+    p->contract_tile_range(&tile_lo, &tile_hi);
+    contraction_shape(p, p->max_ng, &groups, &nvals, &nblocks, tile_lo);
     for (const auto &G : p->groups)
         if (G.rows > 0 && prob->npcf == 3) {
             const int64_t nrows = G.ng / G.n[prob->ndim - 1];

@@ -113,6 +113,47 @@ sb_status sb_autotune(sb_plan *p, void *stream) {
             p->fft_var[{n, d}] = bestv;
         }
     }
+    // contraction tile: every candidate on the first field of the largest shape; the kernels
+    // read whatever the coefficient scratch holds (timing only; a forward call recomputes it)
+    if (p->uses_contract() && p->chunk_groups == p->nlm) {
+        int f0 = 0;
+        for (int f = 0; f < p->batch; ++f)
+            if (p->groups[p->field_group[f]].ng > p->groups[p->field_group[f0]].ng) f0 = f;
+        double *zt = nullptr;
+        if (hipMalloc(&zt, (size_t)p->zeta_doubles * sizeof(double)) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            p->timing = was_timing;
+            return fail(SB_EHIP, "autotune buffer");
+        }
+        int lo = 0, hi = 0;
+        p->contract_tile_range(&lo, &hi);
+        float best = 1e30f;
+        int bestc = p->contract_tile();
+        sb_status st = SB_OK;
+        for (int c = lo; c <= hi && st == SB_OK; c *= 2) {
+            p->contract_tile() = c;
+            float tot = 0.f;
+            for (int rep = 0; rep < 3 && st == SB_OK; ++rep) {
+                (void)hipEventRecord(a, s);
+                st = contract(p, f0, zt, s);
+                (void)hipEventRecord(b, s);
+                (void)hipEventSynchronize(b);
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, a, b);
+                if (rep > 0) tot += ms;
+            }
+            if (tot < best) { best = tot; bestc = c; }
+        }
+        p->contract_tile() = bestc;
+        (void)hipFree(zt);
+        if (st != SB_OK) {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            p->timing = was_timing;
+            return st;
+        }
+    }
     p->timing = was_timing;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
@@ -137,6 +178,27 @@ sb_status sb_plan_get_fft_variant(const sb_plan *p, int32_t n, int32_t axis, int
     if (!fft_supported(n)) return fail(SB_EINVAL, "unsupported length");
     if (axis < 0 || axis >= p->prob.ndim) return fail(SB_EINVAL, "axis out of range");
     *variant = p->fft_variant(n, axis);
+    return SB_OK;
+}
+
+sb_status sb_plan_set_contract_tile(sb_plan *p, int32_t cells) {
+    if (!p) return fail(SB_EINVAL, "null plan");
+    int lo = 0, hi = 0;
+    p->contract_tile_range(&lo, &hi);
+    if (cells < lo || cells > hi || (cells & (cells - 1)) != 0)
+        return fail(SB_EINVAL, "contraction tile must be a power of two within the plan's range");
+    p->contract_tile() = cells;
+    p->release_graph();
+    return SB_OK;
+}
+
+sb_status sb_plan_get_contract_tile(const sb_plan *p, int32_t *cells, int32_t *lo, int32_t *hi) {
+    if (!p || !cells) return fail(SB_EINVAL, "null argument");
+    int l = 0, h = 0;
+    p->contract_tile_range(&l, &h);
+    *cells = p->contract_tile();
+    if (lo) *lo = l;
+    if (hi) *hi = h;
     return SB_OK;
 }
 

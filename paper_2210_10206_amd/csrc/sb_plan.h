@@ -75,8 +75,24 @@ struct sb_plan {
     uint64_t coef_limit = 48ull << 30;
     int chunk_groups = 0;
     bool prepared = false;
-    // launch shapes (autotuned)
+    // launch shapes (autotuned): cells per workgroup of the cell-parallel contractions (unfused
+    // 3PCF pair sums, full 4PCF, projected 4PCF); the scratch holds the partial sums of the
+    // smallest candidate of contract_tile_range
     int cpb_pair = 8192, cpb_quad = 1024, cpb_proj4 = 4096;
+    int &contract_tile() { return prob.npcf == 3 ? cpb_pair : (prob.ndim == 3 ? cpb_quad : cpb_proj4); }
+    int contract_tile() const { return prob.npcf == 3 ? cpb_pair : (prob.ndim == 3 ? cpb_quad : cpb_proj4); }
+    void contract_tile_range(int *lo, int *hi) const {
+        if (prob.npcf == 3) { *lo = 2048; *hi = 16384; }
+        else if (prob.ndim == 3) { *lo = 512; *hi = 4096; }
+        else { *lo = 1024; *hi = 8192; }
+    }
+    // a forward call runs the cell-parallel contraction on some field
+    bool uses_contract() const {
+        if (prob.npcf == 4 || !fused) return true;
+        for (const auto &G : groups)
+            if (G.rows <= 0) return true;
+        return false;
+    }
     const float *d_coefw = nullptr;   // weighted 3j values, every term, per canonical Lambda
     std::vector<int> coefw_off;
     bool quad_mfma = false;       // full 4PCF contraction on the matrix cores (l <= 4, <= 8 bins)

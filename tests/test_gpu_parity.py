@@ -192,13 +192,13 @@ def test_every_fft_variant(sb, shape):
         plan.set_fft_variant(n, axis, 0)
     say(f"  worst err over the variants={worst:.3e}")
     assert worst < TOL32
-    # tuned choices round-trip through fft_choices / set_fft_choices
+    # tuned choices round-trip through choices / set_choices
     plan.autotune(torch.cuda.current_stream())
-    tuned = plan.fft_choices()
-    plan.set_fft_choices({k: 0 for k in tuned})
-    assert all(v == 0 for v in plan.fft_choices().values())
-    plan.set_fft_choices(tuned)
-    assert plan.fft_choices() == tuned
+    tuned = plan.choices()
+    plan.set_choices({"fft": {k: 0 for k in tuned["fft"]}})
+    assert all(v == 0 for v in plan.choices()["fft"].values())
+    plan.set_choices(tuned)
+    assert plan.choices() == tuned
     plan.close()
 
 
@@ -383,6 +383,49 @@ def test_full4pcf_eight_bins_ragged_blocks(sb, precision):
     say(f"  err={err:.3e}")
     assert err < (TOL_SPLIT if precision == "split_bf16" else TOL32)
     plan.close()
+
+
+def test_contract_tile_candidates(sb):
+    # every cells-per-workgroup choice of the three cell-parallel contractions, the range
+    # check, and the autotuner's pick: the tile only reorders the FP64 partial sums
+    say("case: contraction tile candidates: (12,16,24) full 4PCF 8 bins; 64x96 projected 4PCF; "
+        "(16,24,32) unfused 3PCF")
+    d4 = lognormal_field((12, 16, 24), seed=6, sigma=1.0)
+    e4 = linear_edges(5, 8)
+    _, ref4 = oracle.zeta4_full(d4.astype(np.float64), e4, 4)
+    dp = lognormal_field((64, 96), seed=2, sigma=1.0)
+    ep = linear_edges(10, 5)
+    _, refp = oracle.zeta4_proj(dp.astype(np.float64), ep, 4)
+    d3 = lognormal_field((16, 24, 32), seed=3, sigma=1.0)
+    e3 = linear_edges(8, 4)
+    ref3 = oracle.zeta3_full(d3.astype(np.float64), e3, 4).real
+    for d, edges, kw, ref, (lo_want, hi_want) in (
+            (d4, e4, dict(npcf=4), ref4.real, (512, 4096)),
+            (dp, ep, dict(npcf=4), refp, (1024, 8192)),
+            (d3, e3, dict(npcf=3, fused=False), ref3, (2048, 16384))):
+        plan = sb.Plan([d.shape], edges, 4, **kw)
+        dev = [torch.from_numpy(d).cuda()]
+        cur, (lo, hi) = plan.contract_tile()
+        assert (lo, hi) == (lo_want, hi_want) and lo <= cur <= hi
+        worst = 0.0
+        c = lo
+        while c <= hi:
+            plan.set_contract_tile(c)
+            z = plan.forward(dev)
+            torch.cuda.synchronize()
+            worst = max(worst, rel_err(z.cpu().numpy()[0], ref))
+            c *= 2
+        for bad in (lo // 2, 2 * hi, lo + 64):
+            with pytest.raises(RuntimeError):
+                plan.set_contract_tile(bad)
+        plan.autotune(torch.cuda.current_stream())
+        tuned = plan.contract_tile()[0]
+        z = plan.forward(dev)
+        torch.cuda.synchronize()
+        e_t = rel_err(z.cpu().numpy()[0], ref)
+        say(f"  {d.shape} npcf {kw['npcf']}: worst err over tiles {lo}..{hi} = {worst:.3e}; tuned {tuned}: {e_t:.3e}")
+        assert worst < TOL32 and e_t < TOL32 and lo <= tuned <= hi
+        plan.close()
 
 
 def test_full4pcf_lmax3_six_bins(sb):
