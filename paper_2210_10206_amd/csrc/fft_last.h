@@ -25,20 +25,131 @@ constexpr int fused_rows(int n, int tpp, int nbt) {
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-// The pair sums run on the matrix cores: for a quad of cells, Z[b1][b2] += w A^b1 conj(A^b2)
-// is a 16 x 16 x 4 float32 MFMA whose row and column index is the bin (padded to 16) and
-// whose K index is the cell, once with the real and once with the imaginary parts (twice
-// more for the imaginary part of projected sums).  Lane l = i + 16 g holds bin i of cell g of
-// the quad, which is both its A value (row i) and its B value (column i); the 16 x 16 result
-// has b1 = 4 g + r and b2 = i in register r of lane l.  Each tile's float32 result is added
-// to float64 totals, so float32 sums never span more than one tile.  The tile shape (NBT bins
-// x R rows, TPP threads per pencil) is fixed at compile time so that every LDS address folds
-// into an immediate offset.
+// The pair sums run on the matrix cores as 16-block 4 x 4 x 1 float32 MFMAs: block b of an
+// instruction is slot b, one (cell, part) of a group of 8 cells (slot b = cell b / 2, real part
+// for even b, imaginary for odd), and holds the 4 x 4 outer product of bins 4 qa .. 4 qa + 3
+// (weighted, rows) and 4 qb .. 4 qb + 3 (columns) of that slot.  The instructions of a group
+// walk the bin-quad pairs qa <= qb, so only the upper-triangle blocks of the NBT x NBT result
+// are computed (6 instructions per 8 cells for 12 padded bins), and each lane reads the values
+// of its slot once per group.  Lane 4 b + j supplies row j and column j of block b and holds
+// row r, column j of it in register r.  Each tile's float32 result is added to float64 totals
+// per lane; at the end the 16 slots are summed by a fixed butterfly over lanes and the waves
+// in wave order.  For the imaginary part of projected sums, Im(A^b1 conj A^b2) =
+// Im A^b1 Re A^b2 - Re A^b1 Im A^b2 takes the other part of the column value with the sign of
+// the slot's part.
+template <int NBT, bool IMAG>
+struct PairSums {
+    static constexpr int Q = (NBT + 3) / 4;           // bin quads (bins >= NBT read as zero)
+    static constexpr int NPB = Q * (Q + 1) / 2;       // quad pairs qa <= qb
+    static constexpr int NPART = IMAG ? 2 : 1;
+    static constexpr int CPG = 8;                     // cells per group
+    static_assert(NBT >= 1 && NBT <= 16, "at most 16 bins");
+    static constexpr int red_doubles(int nw) { return nw * NPART * NPB * 16; }
+    static constexpr int NV = NPART * NPB * 4;        // accumulator values per lane
+    static constexpr int NT2 = (NV + 1) / 2;          // float64 totals per lane (see tile)
+    double tot[NT2];
+
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int m = 0; m < NT2; ++m) tot[m] = 0.0;
+    }
+
+    // One tile of NCELL cells: the value of bin b at cell c is stage[off(c) + b * bstride] and
+    // its weight wsm[c].  The waves take groups of 8 cells in turn.
+    template <int NCELL, int NW, class Off>
+    __device__ __forceinline__ void tile(const float2 *stage, int bstride, const float *wsm, Off off, int wave,
+                                         int lane) {
+        constexpr int NG = (NCELL + CPG - 1) / CPG;
+        const int slot = lane >> 2, j = lane & 3;
+        const int cg = slot >> 1;
+        const bool im_slot = (slot & 1) != 0;
+        f4v acc[NPART][NPB];
+#pragma unroll
+        for (int u = 0; u < NPART; ++u)
+#pragma unroll
+            for (int p = 0; p < NPB; ++p) acc[u][p] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+        for (int k = 0; k < (NG + NW - 1) / NW; ++k) {
+            const int grp = wave + k * NW;
+            if (grp < NG) {
+                const int c = grp * CPG + cg;
+                const bool ok = NCELL % CPG == 0 || c < NCELL;
+                const float w = ok ? wsm[c] : 0.f;
+                float x[Q], xo[Q];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const bool in = ok && (NBT % 4 == 0 || 4 * q + j < NBT);
+                    const float2 v = in ? stage[off(c) + (4 * q + j) * bstride] : make_float2(0.f, 0.f);
+                    x[q] = im_slot ? v.y : v.x;
+                    xo[q] = im_slot ? v.x : v.y;
+                }
+                int p = 0;
+#pragma unroll
+                for (int qa = 0; qa < Q; ++qa) {
+                    const float aw = w * x[qa];
+#pragma unroll
+                    for (int qb = qa; qb < Q; ++qb, ++p) {
+                        acc[0][p] = __builtin_amdgcn_mfma_f32_4x4x1f32(aw, x[qb], acc[0][p], 0, 0, 0);
+                        if constexpr (IMAG)
+                            acc[NPART - 1][p] =
+                                __builtin_amdgcn_mfma_f32_4x4x1f32(im_slot ? aw : -aw, xo[qb], acc[NPART - 1][p], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        // The two slots of a cell (lanes l and l ^ 4) always end up in the same sum: fold them
+        // here so that each lane keeps half of the values (value 2 m on even-slot lanes, 2 m + 1
+        // on odd-slot lanes) in float64.
+        float flat[2 * NT2];
+#pragma unroll
+        for (int u = 0; u < NPART; ++u)
+#pragma unroll
+            for (int p = 0; p < NPB; ++p)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) flat[(u * NPB + p) * 4 + r] = acc[u][p][r];
+        if constexpr (NV % 2 != 0) flat[NV] = 0.f;
+#pragma unroll
+        for (int m = 0; m < NT2; ++m) {
+            const float send = im_slot ? flat[2 * m] : flat[2 * m + 1];
+            const float keep = im_slot ? flat[2 * m + 1] : flat[2 * m];
+            tot[m] += (double)(keep + __shfl_xor(send, 4));
+        }
+    }
+
+    // Sum the 8 cells of the slots (lanes 8 c + 4 s + j, fixed butterfly over c) and write this
+    // wave's totals to red[((wave * NPART + part) * NPB + p) * 16 + r * 4 + j]; call with the
+    // whole block.  Lanes 0..3 end with the values 2 m, lanes 4..7 with the values 2 m + 1.
+    __device__ __forceinline__ void to_lds(double *red, int wave, int lane) {
+#pragma unroll
+        for (int m = 0; m < NT2; ++m) {
+            double v = tot[m];
+            v += __shfl_xor(v, 8);
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            const int idx = 2 * m + ((lane >> 2) & 1);   // flattened (part, pair, r)
+            if (lane < 8 && idx < NV) red[(wave * NV + idx) * 4 + (lane & 3)] = v;
+        }
+    }
+
+    // Block partial of output v = part * npairs + pair (b1 <= b2, b1 outer): the waves in order.
+    __device__ static double block_value(const double *red, int nw, int nb, int v) {
+        const int npn = nb * (nb + 1) / 2;
+        const int vp = v % npn, part = v / npn;
+        int b1 = 0, rem = vp;
+        while (rem >= nb - b1) { rem -= nb - b1; ++b1; }
+        const int b2 = b1 + rem;
+        const int qa = b1 >> 2, qb = b2 >> 2;
+        const int p = qa * Q - qa * (qa - 1) / 2 + (qb - qa);
+        double sum = 0.0;
+        for (int w = 0; w < nw; ++w) sum += red[((w * NPART + part) * NPB + p) * 16 + (b1 & 3) * 4 + (b2 & 3)];
+        return sum;
+    }
+};
+
 template <int N, int TPP, int NBT, int R, bool IMAG, int... RAD>
 __global__ __launch_bounds__(NBT * R * TPP) void last_contract_kernel(LastArgs a) {
     constexpr int P = NBT * R, PITCH = P + 1, NT = P * TPP;
     constexpr int NW = NT / 64;       // waves
-    constexpr int NQ = R * N / 4;     // cell quads per tile
     constexpr int NPART = IMAG ? 2 : 1;
     constexpr int EPT = N / TPP;      // tile elements loaded per thread
     static_assert(NT % 64 == 0, "whole waves");
@@ -48,13 +159,9 @@ __global__ __launch_bounds__(NBT * R * TPP) void last_contract_kernel(LastArgs a
     float2 *tw = smem + N * PITCH;
     float *wsm = reinterpret_cast<float *>(tw + N);   // the tile's weights w(x), R N values
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int li = lane & 15, lg = lane >> 4;
     for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
-    double tot[NPART][4];
-#pragma unroll
-    for (int q = 0; q < NPART; ++q)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) tot[q][r] = 0.0;
+    PairSums<NBT, IMAG> ps;
+    ps.zero();
     const int64_t nrows = a.ng / N;
     const int64_t r_begin = (int64_t)blockIdx.x * a.rows_per_block;
     const int64_t r_end = min(r_begin + a.rows_per_block, nrows);
@@ -95,52 +202,18 @@ __global__ __launch_bounds__(NBT * R * TPP) void last_contract_kernel(LastArgs a
         if (row0 + R < r_end) { load_tile(row0 + R, nx); load_w(row0 + R, nw); }   // next tile in flight
         __syncthreads();
         stages<N, TPP, 1, 1, RAD...>(sm, tw, tid % P, tid / P, PITCH);
-        // two independent accumulator chains per part (real and imaginary operand halves)
-        f4v acc[2 * NPART];
-#pragma unroll
-        for (int q = 0; q < 2 * NPART; ++q) acc[q] = f4v{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int k = 0; k < (NQ + NW - 1) / NW; ++k) {
-            const int qd = wave + k * NW;
-            if (qd < NQ) {
-                const int c = 4 * qd + lg;                 // this lane's cell of the quad
-                const int r = c / N, j = c % N;
-                const float wv = wsm[c];                   // zero beyond the last row
-                const float2 v = li < NBT ? sm[j * PITCH + li * R + r] : make_float2(0.f, 0.f);   // zero beyond nb
-                const float wx = wv * v.x, wy = wv * v.y;
-                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx, v.x, acc[0], 0, 0, 0);
-                acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(wy, v.y, acc[1], 0, 0, 0);
-                if constexpr (IMAG) {
-                    acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(wy, v.x, acc[2], 0, 0, 0);
-                    acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(-wx, v.y, acc[3], 0, 0, 0);
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < NPART; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) tot[q][r] += (double)acc[2 * q][r] + (double)acc[2 * q + 1][r];
+        ps.template tile<R * N, NW>(sm, R, wsm, [](int c) { return (c % N) * PITCH + c / N; }, wave, lane);
     }
     // float64 combine over the waves in wave order; partial[(g * nv + v) * nblocks + blk] with
     // v = part * npairs + pair (b1 <= b2, b1 outer)
     __syncthreads();
-    double *red = reinterpret_cast<double *>(smem);   // [wave][part][b1 * 16 + b2]
-#pragma unroll
-    for (int q = 0; q < NPART; ++q)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) red[(wave * NPART + q) * 256 + (4 * lg + r) * 16 + li] = tot[q][r];
+    double *red = reinterpret_cast<double *>(smem);   // [wave][part][quad pair][4 x 4]
+    ps.to_lds(red, wave, lane);
     __syncthreads();
-    const int npn = nb * (nb + 1) / 2;
-    const int nv = npn * NPART;
-    for (int v = tid; v < nv; v += NT) {
-        const int vp = v % npn, part = v / npn;
-        int b1 = 0, rem = vp;                      // pair index (nb layout) -> (b1, b2)
-        while (rem >= nb - b1) { rem -= nb - b1; ++b1; }
-        const int b2 = b1 + rem;
-        double sum = 0.0;
-        for (int w = 0; w < NW; ++w) sum += red[(w * NPART + part) * 256 + b1 * 16 + b2];
-        a.partial[((int64_t)blockIdx.y * nv + v) * a.nblocks + blockIdx.x] = sum;
-    }
+    const int nv = nb * (nb + 1) / 2 * NPART;
+    for (int v = tid; v < nv; v += NT)
+        a.partial[((int64_t)blockIdx.y * nv + v) * a.nblocks + blockIdx.x] =
+            PairSums<NBT, IMAG>::block_value(red, NW, nb, v);
 }
 
 // Register-resident form for n = RX * RX (RX threads per row): a tile is one row of the
@@ -158,7 +231,6 @@ __global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
     constexpr int P = NBT;                 // pencils (bins) per tile
     constexpr int NT = P * R2;
     constexpr int NW = NT / 64;
-    constexpr int NQ = N / 4;              // cell quads per tile
     constexpr int NPART = IMAG ? 2 : 1;
     constexpr int EXP = R2 * (R1 + 1);     // exchange float2 per pencil: R2 rows of R1, padded by one
     constexpr int PITCH = P + 1;
@@ -169,18 +241,14 @@ __global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
     __shared__ float wsm[N];
     const int nb = a.nb;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int li = lane & 15, lg = lane >> 4;
     const int q = tid % R2, pp = tid / R2;  // element column, pencil (= bin)
     float2 tw[T][R2];                       // w^{(q + R2 t) r}, w = e^{-2 pi i / N}; the inverse takes the conjugate
 #pragma unroll
     for (int t = 0; t < T; ++t)
 #pragma unroll
         for (int r = 0; r < R2; ++r) tw[t][r] = a.tw[((q + R2 * t) * r) % N];
-    double tot[NPART][4];
-#pragma unroll
-    for (int u = 0; u < NPART; ++u)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) tot[u][r] = 0.0;
+    PairSums<NBT, IMAG> ps;
+    ps.zero();
     const int64_t nrows = a.ng / N;
     const int64_t r_begin = (int64_t)blockIdx.x * a.rows_per_block;
     const int64_t r_end = min(r_begin + a.rows_per_block, nrows);
@@ -228,49 +296,18 @@ __global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
         for (int e = 0; e < WPT; ++e)
             if (tid + e * NT < N) wsm[tid + e * NT] = wv[e];
         __syncthreads();
-        f4v acc[2 * NPART];
-#pragma unroll
-        for (int u = 0; u < 2 * NPART; ++u) acc[u] = f4v{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-        for (int k = 0; k < (NQ + NW - 1) / NW; ++k) {
-            const int qd = wave + k * NW;
-            if (qd < NQ) {
-                const int c = 4 * qd + lg;
-                const float w = wsm[c];
-                const float2 x = li < NBT ? cs[c * PITCH + li] : make_float2(0.f, 0.f);   // zero beyond nb
-                const float wx = w * x.x, wy = w * x.y;
-                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx, x.x, acc[0], 0, 0, 0);
-                acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(wy, x.y, acc[1], 0, 0, 0);
-                if constexpr (IMAG) {
-                    acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(wy, x.x, acc[2], 0, 0, 0);
-                    acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(-wx, x.y, acc[3], 0, 0, 0);
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < NPART; ++u)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) tot[u][r] += (double)acc[2 * u][r] + (double)acc[2 * u + 1][r];
+        ps.template tile<N, NW>(cs, 1, wsm, [](int c) { return c * PITCH; }, wave, lane);
     }
     // float64 combine over the waves in wave order (as in last_contract_kernel)
     __syncthreads();
-    double *red = reinterpret_cast<double *>(cs);
-#pragma unroll
-    for (int u = 0; u < NPART; ++u)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) red[(wave * NPART + u) * 256 + (4 * lg + r) * 16 + li] = tot[u][r];
+    static_assert(PairSums<NBT, IMAG>::red_doubles(NW) * sizeof(double) <= sizeof(cs), "block reduction fits");
+    double *red = reinterpret_cast<double *>(cs);   // [wave][part][quad pair][4 x 4]
+    ps.to_lds(red, wave, lane);
     __syncthreads();
-    const int npn = nb * (nb + 1) / 2;
-    const int nv = npn * NPART;
-    for (int vv = tid; vv < nv; vv += NT) {
-        const int vp = vv % npn, part = vv / npn;
-        int b1 = 0, rem = vp;
-        while (rem >= nb - b1) { rem -= nb - b1; ++b1; }
-        const int b2 = b1 + rem;
-        double sum = 0.0;
-        for (int w = 0; w < NW; ++w) sum += red[(w * NPART + part) * 256 + b1 * 16 + b2];
-        a.partial[((int64_t)blockIdx.y * nv + vv) * a.nblocks + blockIdx.x] = sum;
-    }
+    const int nv = nb * (nb + 1) / 2 * NPART;
+    for (int vv = tid; vv < nv; vv += NT)
+        a.partial[((int64_t)blockIdx.y * nv + vv) * a.nblocks + blockIdx.x] =
+            PairSums<NBT, IMAG>::block_value(red, NW, nb, vv);
 }
 
 // bins padded to the instantiated tile widths 4, 8, 12, 16 so that NBT * t threads make whole
@@ -315,7 +352,6 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
     constexpr int P = NBT;
     constexpr int NT = P * T;
     constexpr int NW = NT / 64;
-    constexpr int NQ = N / 4;
     constexpr int NPART = IMAG ? 2 : 1;
     constexpr int PITCH = P + 1;
     constexpr int NSTAGE = 1 + sizeof...(REST);
@@ -327,14 +363,10 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
     __shared__ float wsm[N];
     const int nb = a.nb;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int li = lane & 15, lg = lane >> 4;
     const int q = tid % T, pp = tid / T;        // element column, pencil (= bin)
     for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
-    double tot[NPART][4];
-#pragma unroll
-    for (int u = 0; u < NPART; ++u)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) tot[u][r] = 0.0;
+    PairSums<NBT, IMAG> ps;
+    ps.zero();
     const int64_t nrows = a.ng / N;
     const int64_t r_begin = (int64_t)blockIdx.x * a.rows_per_block;
     const int64_t r_end = min(r_begin + a.rows_per_block, nrows);
@@ -369,49 +401,18 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
         for (int e = 0; e < WPT; ++e)
             if (tid + e * NT < N) wsm[tid + e * NT] = wv[e];
         __syncthreads();
-        f4v acc[2 * NPART];
-#pragma unroll
-        for (int u = 0; u < 2 * NPART; ++u) acc[u] = f4v{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-        for (int k = 0; k < (NQ + NW - 1) / NW; ++k) {
-            const int qd = wave + k * NW;
-            if (qd < NQ) {
-                const int c = 4 * qd + lg;
-                const float w = wsm[c];
-                const float2 x = li < NBT ? cs[c * PITCH + li] : make_float2(0.f, 0.f);   // zero beyond nb
-                const float wx = w * x.x, wy = w * x.y;
-                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx, x.x, acc[0], 0, 0, 0);
-                acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(wy, x.y, acc[1], 0, 0, 0);
-                if constexpr (IMAG) {
-                    acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(wy, x.x, acc[2], 0, 0, 0);
-                    acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(-wx, x.y, acc[3], 0, 0, 0);
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < NPART; ++u)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) tot[u][r] += (double)acc[2 * u][r] + (double)acc[2 * u + 1][r];
+        ps.template tile<N, NW>(cs, 1, wsm, [](int c) { return c * PITCH; }, wave, lane);
     }
     // float64 combine over the waves in wave order (as in last_contract_kernel)
     __syncthreads();
+    static_assert(PairSums<NBT, IMAG>::red_doubles(NW) * sizeof(double) <= sizeof(ex), "block reduction fits");
     double *red = reinterpret_cast<double *>(&ex[0][0]);
-#pragma unroll
-    for (int u = 0; u < NPART; ++u)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) red[(wave * NPART + u) * 256 + (4 * lg + r) * 16 + li] = tot[u][r];
+    ps.to_lds(red, wave, lane);
     __syncthreads();
-    const int npn = nb * (nb + 1) / 2;
-    const int nv = npn * NPART;
-    for (int vv = tid; vv < nv; vv += NT) {
-        const int vp = vv % npn, part = vv / npn;
-        int b1 = 0, rem = vp;
-        while (rem >= nb - b1) { rem -= nb - b1; ++b1; }
-        const int b2 = b1 + rem;
-        double sum = 0.0;
-        for (int w = 0; w < NW; ++w) sum += red[(w * NPART + part) * 256 + b1 * 16 + b2];
-        a.partial[((int64_t)blockIdx.y * nv + vv) * a.nblocks + blockIdx.x] = sum;
-    }
+    const int nv = nb * (nb + 1) / 2 * NPART;
+    for (int vv = tid; vv < nv; vv += NT)
+        a.partial[((int64_t)blockIdx.y * nv + vv) * a.nblocks + blockIdx.x] =
+            PairSums<NBT, IMAG>::block_value(red, NW, nb, vv);
 }
 
 template <int N, int R0, int... REST>
@@ -444,7 +445,7 @@ hipError_t launch_last_t(const LastArgs &a, hipStream_t s) {
     constexpr int P = NBT * R, NT = P * TPP;
     if (a.rows != R) return hipErrorInvalidValue;
     const size_t tile = (size_t)(N * (P + 1) + N) * sizeof(float2) + (size_t)R * N * sizeof(float);
-    const size_t red = (size_t)(NT / 64) * (IMAG ? 2 : 1) * 256 * sizeof(double);
+    const size_t red = (size_t)PairSums<NBT, IMAG>::red_doubles(NT / 64) * sizeof(double);
     const size_t shm = tile > red ? tile : red;
     dim3 grid((unsigned)a.nblocks, (unsigned)a.groups);
     hipLaunchKernelGGL((last_contract_kernel<N, TPP, NBT, R, IMAG, RAD...>), grid, dim3(NT), shm, s, a);
