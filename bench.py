@@ -278,6 +278,61 @@ def run_512(api, steps, warmup):
     return res
 
 
+def run_proj(api, steps, warmup):
+    """Projected 3PCF and 4PCF (Alg. 7, 8) of the 512^2 sigma 1 lognormal field (seed 0), 10
+    bins over (0,40], m up to 10: fields/s of each, the per-stage times and the live rate of the
+    projected 4PCF contraction, and the error against the stored oracle sums."""
+    import numpy as np
+    import torch
+    from fieldgen import lognormal_field, linear_edges
+    d = lognormal_field((512, 512), seed=0, sigma=1.0)
+    dev = [torch.from_numpy(d).cuda()]
+    gpath = os.path.join(ROOT, "tests", "golden", "c2_proj_512.npz")
+    gold = np.load(gpath) if os.path.exists(gpath) else None
+    stream = torch.cuda.Stream()
+    res = {"workload": "projected 3PCF and 4PCF of one 512^2 float32 lognormal field (sigma 1), 10 bins over (0,40], "
+                       "m up to 10 (331 (m1, m2) pairs)"}
+    for npcf in (3, 4):
+        plan = api.Plan([d.shape], linear_edges(40, 10), 10, npcf=npcf, prepare=False)
+        with torch.cuda.stream(stream):
+            plan.prepare(stream)
+        plan.autotune(stream)
+        out = torch.empty((1, plan.zeta_doubles), dtype=torch.float64, device="cuda")
+        with torch.cuda.stream(stream):
+            for _ in range(warmup):
+                plan.forward_raw(dev, out=out, stream=stream)
+        stream.synchronize()
+        plan.profile(True)
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            for _ in range(steps):
+                plan.forward_raw(dev, out=out, stream=stream)
+        stream.synchronize()
+        el = time.perf_counter() - t0
+        recs = plan.launch_records()
+        plan.profile(False)
+        r = {"value": round(steps / el, 2), "unit": "fields/s", "ms_per_field": round(el / steps * 1e3, 3),
+             "fft_ms_per_field": round(sum(x["ms"] for x in recs if x["stage"] == 0) / steps, 3),
+             "contract_ms_per_field": round(sum(x["ms"] for x in recs if x["stage"] == 1) / steps, 3)}
+        if npcf == 4:
+            q = [x for x in recs if x["kernel"] == 5]
+            ms, fl = sum(x["ms"] for x in q), sum(x["flops"] for x in q)
+            if ms:
+                r["contraction"] = {"kernel": "proj4_kernel (one launch per canonical (m1, m2) set, float32 VALU)",
+                                    "achieved_tflops": round(fl / (ms * 1e-3) / 1e12, 2),
+                                    "peak_tflops": 78.6, "peak_note": "float32 vector FMA without packed FP32",
+                                    "frac": round(fl / (ms * 1e-3) / 1e12 / 78.6, 4)}
+        if gold is not None:
+            z = out.cpu().numpy()[0]
+            ref = gold["zeta3" if npcf == 3 else "zeta4"].reshape(-1)
+            zz = z.view(np.complex128) if ref.dtype.kind == "c" else z
+            zz = zz.reshape(-1)[: ref.size]
+            r["max_rel_err_vs_oracle"] = float(np.max(np.abs(zz - ref)) / np.max(np.abs(ref)))
+        res[f"proj{npcf}pcf"] = r
+        plan.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,6 +348,7 @@ def main():
     ap.add_argument("--c5-steps", type=int, default=1,
                     help="steps of the uneven-batch forward + adjoint and the synthesis demo (0 skips them)")
     ap.add_argument("--big-steps", type=int, default=1, help="steps of the 512^3 3PCF line (0 skips it)")
+    ap.add_argument("--proj-steps", type=int, default=3, help="steps of the 512^2 projected line (0 skips it)")
     ap.add_argument("--step-samples", type=int, default=10,
                     help="per-step HIP-event samples (eager and graph replay) after the timed steps")
     ap.add_argument("--plain-steps", type=int, default=2,
@@ -362,12 +418,14 @@ def main():
 
     # parity of this very run against the stored oracle values (when present)
     z = out.cpu().numpy().reshape(len(dev), lmax + 1, nbins, nbins)
-    errs = []
+    errs, errs_l = [], []
     for i in range(len(dev)):
         g = os.path.join(ROOT, "tests", "golden", f"c3_full3_256_seed{i}.npz")
         if n == 256 and os.path.exists(g):
             ref = np.load(g)["zeta3"].real
             errs.append(float(np.max(np.abs(z[i] - ref)) / np.max(np.abs(ref))))
+            # per multipole: max over (b1, b2) of |Z - Z_oracle| / max |Z_oracle| of that l
+            errs_l.append([float(np.max(np.abs(z[i, l] - ref[l])) / np.max(np.abs(ref[l]))) for l in range(lmax + 1)])
 
     # roofline of the dominant kernel (largest share of the timed region among the passes
     # over all kernel arrays), from the live per-launch HIP-event records
@@ -466,6 +524,10 @@ def main():
         print("bench: 512^3 3PCF", file=sys.stderr, flush=True)
         big = run_512(api, args.big_steps, 1)
         torch.cuda.empty_cache()
+    proj = None
+    if args.proj_steps > 0:
+        print("bench: 512^2 projected 3PCF and 4PCF", file=sys.stderr, flush=True)
+        proj = run_proj(api, args.proj_steps, 1)
     c5 = None
     if args.c5_steps > 0:
         print("bench: uneven batch forward + adjoint, synthesis demo", file=sys.stderr, flush=True)
@@ -490,9 +552,11 @@ def main():
         "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
         "per_kernel": per_kernel,
         "max_rel_err_vs_oracle": errs or None,
+        "max_rel_err_vs_oracle_per_l": errs_l or None,
         "secondary_4pcf_128": c4,
         "secondary_uneven_adjoint": c5,
         "secondary_3pcf_512": big,
+        "secondary_projected_512": proj,
     }
     print(json.dumps(line), flush=True)
 

@@ -77,15 +77,18 @@ static sb_status build_gather(sb_plan *p, std::vector<int> &gptr, std::vector<in
     } else {
         const int NV2 = 2 * NB * NB * NB;
         for (const auto &pr : p->p4_pairs) {
-            const int m1 = pr.first, m2 = pr.second;
-            const bool canon = (m1 > 0) || (m1 == 0 && m2 >= 0);
-            const int key = canon ? p->p4_canon_index.at({m1, m2}) : p->p4_canon_index.at({-m1, -m2});
-            for (int f = 0; f < NB * NB * NB; ++f) {
-                add(key * NV2 + 2 * f, 1.0);
-                close();
-                add(key * NV2 + 2 * f + 1, canon ? 1.0 : -1.0);
-                close();
-            }
+            const P4Canon cn = p4_canonical(pr.first, pr.second);
+            const int key = p->p4_canon_index.at({cn.m[0], cn.m[1]});
+            for (int b1 = 0; b1 < NB; ++b1)
+                for (int b2 = 0; b2 < NB; ++b2)
+                    for (int b3 = 0; b3 < NB; ++b3) {
+                        const int b[3] = {b1, b2, b3};
+                        const int f = (b[cn.pos[0]] * NB + b[cn.pos[1]]) * NB + b[cn.pos[2]];
+                        add(key * NV2 + 2 * f, 1.0);
+                        close();
+                        add(key * NV2 + 2 * f + 1, cn.neg ? -1.0 : 1.0);
+                        close();
+                    }
         }
     }
     return SB_OK;
@@ -247,11 +250,13 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
             for (int k = 0; k < 3; ++k) p->idx_table.push_back(x.l[k]);
     } else {
         p->p4_pairs = proj4_pairs(L);
-        for (const auto &pr : p->p4_pairs)
-            if (pr.first > 0 || (pr.first == 0 && pr.second >= 0)) {
-                p->p4_canon_index[pr] = (int)p->p4_canon.size();
-                p->p4_canon.push_back(pr);
+        for (const auto &pr : p->p4_pairs) {
+            const P4Canon cn = p4_canonical(pr.first, pr.second);
+            if (!p->p4_canon_index.count({cn.m[0], cn.m[1]})) {
+                p->p4_canon_index[{cn.m[0], cn.m[1]}] = (int)p->p4_canon.size();
+                p->p4_canon.push_back({cn.m[0], cn.m[1]});
             }
+        }
         p->zeta_doubles = (int64_t)p->p4_pairs.size() * NB * NB * NB * 2;
         p->idx_rows = (int32_t)p->p4_pairs.size();
         p->idx_cols = 2;

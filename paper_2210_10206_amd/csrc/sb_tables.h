@@ -27,4 +27,17 @@ std::vector<Lam> full4_lambdas(int lmax, bool even);
 Full4Plan make_full4_plan(int lmax, int nbins, bool even = true);
 std::vector<std::pair<int, int>> proj4_pairs(int mmax);
 
+// Projected 4PCF symmetry (Alg. 8): the summand c^b1_m1 c^b2_m2 c^b3_m3, m3 = -(m1 + m2), is
+// symmetric under permutations of the three (m, bin) slots and goes to its complex conjugate
+// under m -> -m.  Every (m1, m2) maps to one canonical triple: the sorted (m1, m2, m3) or the
+// sorted negated triple, whichever is lexicographically smaller (the un-negated one when they
+// are equal).  Output bins (b1, b2, b3) read the canonical sums at position k <- b[pos[k]];
+// neg: conjugate.
+struct P4Canon {
+    int m[3];
+    int pos[3];
+    bool neg;
+};
+P4Canon p4_canonical(int m1, int m2);
+
 }  // namespace sb

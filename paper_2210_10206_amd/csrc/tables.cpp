@@ -146,6 +146,27 @@ Full4Plan make_full4_plan(int lmax, int nbins, bool even) {
     return p;
 }
 
+P4Canon p4_canonical(int m1, int m2) {
+    const int mo[3] = {m1, m2, -(m1 + m2)};
+    int t[3] = {mo[0], mo[1], mo[2]}, n[3] = {-mo[0], -mo[1], -mo[2]};
+    std::sort(t, t + 3);
+    std::sort(n, n + 3);
+    P4Canon c{};
+    c.neg = std::lexicographical_compare(n, n + 3, t, t + 3);
+    const int *rep = c.neg ? n : t;
+    bool used[3] = {false, false, false};
+    for (int k = 0; k < 3; ++k) {
+        c.m[k] = rep[k];
+        for (int i = 0; i < 3; ++i)
+            if (!used[i] && (c.neg ? -mo[i] : mo[i]) == rep[k]) {
+                used[i] = true;
+                c.pos[k] = i;
+                break;
+            }
+    }
+    return c;
+}
+
 std::vector<std::pair<int, int>> proj4_pairs(int mmax) {
     std::vector<std::pair<int, int>> out;
     for (int m1 = -mmax; m1 <= mmax; ++m1)
