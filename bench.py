@@ -163,6 +163,16 @@ def run_4pcf_batch(api, steps, warmup, count=16, precision="fp32", mfma=True, pa
     el = time.perf_counter() - t0
     recs = plan.launch_records()
     plan.profile(False)
+    # the same steps replayed from the HIP graph of the whole batch forward
+    with torch.cuda.stream(stream):
+        plan.forward_raw(dev, out=out, stream=stream, graph=True)   # capture
+    stream.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(steps):
+            plan.forward_raw(dev, out=out, stream=stream, graph=True)
+    stream.synchronize()
+    el_graph = time.perf_counter() - t0
     q = [r for r in recs if r["kernel"] in (4, 7)]
     ms = sum(r["ms"] for r in q)
     fl = sum(r["flops"] for r in q)
@@ -176,6 +186,7 @@ def run_4pcf_batch(api, steps, warmup, count=16, precision="fp32", mfma=True, pa
                        "even Lambda with l <= 4 (42)",
            "precision": precision, "matrix_cores": bool(mfma), "contract_tile": plan.contract_tile()[0],
            "value": round(count * steps / el, 3), "unit": "fields/s", "ms_per_step": round(el / steps * 1e3, 2),
+           "graph_replay": {"value": round(count * steps / el_graph, 3), "ms_per_step": round(el_graph / steps * 1e3, 2)},
            "contraction": {"kernel": kname,
                            "achieved_tflops": round(fl / (ms * 1e-3) / 1e12, 2) if ms else None,
                            "peak_tflops": peak, "frac": round(fl / (ms * 1e-3) / 1e12 / peak, 4) if ms else None,

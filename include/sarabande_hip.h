@@ -93,8 +93,11 @@ typedef struct {
                                   matrix cores (lmax <= 4, nbins <= 8): SB_PREC_FP32 uses float32
                                   MFMA, SB_PREC_SPLIT_BF16 bf16 MFMA on hi + lo splits of both
                                   operands (hi*hi + hi*lo + lo*hi, float32 accumulation, about
-                                  1e-5 relative per product).  Every other contraction is float32
-                                  vector arithmetic whatever the value. */
+                                  1e-5 relative per product).  Whatever the value, the pair sums
+                                  of the 3PCFs (fused or not) run on float32 MFMA (fused last pass)
+                                  or float32 vector arithmetic (unfused pair kernel), and the
+                                  projected 4PCF contraction and the plain 4PCF kernel
+                                  (SB_FLAG_NO_MFMA) on float32 vector arithmetic. */
     int32_t input_dtype;       /* sb_input_dtype of the density arrays */
     uint32_t flags;
 } sb_problem;

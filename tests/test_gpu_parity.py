@@ -72,6 +72,46 @@ def test_c1_full3pcf_32(sb):
     plan.close()
 
 
+def test_degenerate_cases(sb):
+    # one bin and lmax 0 (a single kernel array; the 3PCF reduces to sum_x delta a^2), the
+    # smallest supported grid, mmax 0 projected, an all-zero field and a single-cell spike (every
+    # sum is exactly zero: r = 0 lies in no bin, so a^b(y) vanishes at the spike)
+    say("case: degenerate inputs: 1 bin / lmax 0 at 16^3, 8^3 full 3PCF and 4PCF, 32x48 mmax 0, zero field, spike")
+    d = lognormal_field((16, 16, 16), seed=31, sigma=1.0)
+    e1 = linear_edges(4, 1)
+    _, _, z = run_plan(sb, [d], e1, 0)
+    ref = oracle.zeta3_full(d.astype(np.float64), e1, 0).real
+    assert z.shape == (1, 1, 1, 1)
+    err_a = rel_err(z[0], ref)
+    d8 = lognormal_field((8, 8, 8), seed=32, sigma=1.0)
+    e8 = linear_edges(3, 2)
+    _, _, z8 = run_plan(sb, [d8], e8, 2)
+    err_b = rel_err(z8[0], oracle.zeta3_full(d8.astype(np.float64), e8, 2).real)
+    _, _, z84 = run_plan(sb, [d8], e8, 2, npcf=4)
+    _, ref84 = oracle.zeta4_full(d8.astype(np.float64), e8, 2)
+    err_c = rel_err(z84[0], ref84.real)
+    dp = lognormal_field((32, 48), seed=33, sigma=1.0)
+    ep = linear_edges(6, 3)
+    _, _, zp = run_plan(sb, [dp], ep, 0)
+    err_d = rel_err(zp[0], oracle.zeta3_proj(dp.astype(np.float64), ep, 0))
+    say(f"  1 bin lmax 0: {err_a:.3e}; 8^3 3PCF {err_b:.3e}, 4PCF {err_c:.3e}; mmax 0 projected {err_d:.3e}")
+    assert max(err_a, err_b, err_c, err_d) < TOL32
+    zero = np.zeros((24, 24, 24), np.float32)
+    spike = zero.copy()
+    spike[5, 7, 11] = 3.0
+    e = linear_edges(8, 4)
+    for npcf in (3, 4):
+        plan, _, zz = run_plan(sb, [zero], e, 4, npcf=npcf)
+        assert np.all(zz == 0.0), f"npcf {npcf}: nonzero sums for the zero field"
+        # spike: exact sums vanish; the float32 transforms leave rounding noise in a^b(y), so the
+        # bound is 1e-5 of the size the sums would have with |a| at its largest (3 x bin count)
+        nmax = float(max(plan.bin_counts(0)))
+        plan, _, zz = run_plan(sb, [spike], e, 4, npcf=npcf)
+        bound = 1e-5 * 3.0 * (3.0 * nmax) ** (npcf - 1)
+        say(f"  spike npcf {npcf}: max |Z| = {np.max(np.abs(zz)):.3e} (bound {bound:.3e})")
+        assert np.max(np.abs(zz)) <= bound
+
+
 def test_c1_coefficients_match_oracle(sb):
     say("case: 32^3 coefficients a^b_lm at sampled cells")
     d = lognormal_field((32, 32, 32), seed=0, sigma=1.0, dtype=np.float64)
@@ -260,20 +300,22 @@ def test_call_order_and_argument_errors(sb):
     p4.close()
 
 
-def test_graph_replay_matches_eager(sb):
-    say("case: 32^3 graph capture + replay vs eager")
-    d = lognormal_field((32, 32, 32), seed=5, sigma=1.0)
+@pytest.mark.parametrize("shape,npcf,lmax", [((32, 32, 32), 3, 4), ((16, 24, 32), 4, 4), ((64, 96), 4, 4)])
+def test_graph_replay_matches_eager(sb, shape, npcf, lmax):
+    say(f"case: {shape} npcf {npcf} graph capture + replay vs eager (three replays, eager work between)")
+    d = lognormal_field(shape, seed=5, sigma=1.0)
     edges = linear_edges(8, 4)
-    plan = sb.Plan([d.shape], edges, 4)
+    plan = sb.Plan([d.shape], edges, lmax, npcf=npcf)
     dev = [torch.from_numpy(d).cuda()]
-    eager = plan.forward(dev).cpu().numpy()
+    eager = plan.forward_raw(dev).cpu().numpy()
+    torch.cuda.synchronize()
     s = torch.cuda.Stream()
     out = torch.empty((1, plan.zeta_doubles), dtype=torch.float64, device="cuda")
     for rep in range(3):
         with torch.cuda.stream(s):
             plan.forward_raw(dev, out=out, stream=s, graph=True)
         s.synchronize()
-        got = out.cpu().numpy().reshape(eager.shape)
+        got = out.cpu().numpy()
         assert np.array_equal(got, eager), f"replay {rep} differs"
         _ = plan.forward(dev)  # eager work between replays
         torch.cuda.synchronize()
