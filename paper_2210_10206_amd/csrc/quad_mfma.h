@@ -27,7 +27,34 @@ typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
 constexpr int kTileCells = 64;   // cells staged per LDS tile (16 per wave)
 constexpr int kMaxNB = 8;        // bins (pairs fill at most 4 tiles of 16)
-constexpr int kMT = 4;           // M tiles of 16 pairs
+
+// Pairs of the M tiles.  General Lambda: row i of tile mt is (b1, b2) = (2 mt + i / 8, i % 8),
+// 4 tiles.  LA == LB: swapping the first two 3j columns multiplies the symbol by
+// (-1)^(LA + LB + LC), so Z[b1][b2][b3] = +-Z[b2][b1][b3] and only the 36 pairs b1 <= b2 are
+// computed, in 3 tiles: row i has one b2 (rows 0-2: 7, 3-5: 6, 6-7: 5, 8-9: 4, 10-11: 3, 12: 2,
+// 13: 1, 14: 0, 15: none) and the b1 <= b2 of that b2 in turn over the tiles (-1: empty slot).
+// In both layouts a lane keeps one b2 in all its tiles.
+struct SymPairs {
+    int b2[16];
+    int b1[3][16];
+};
+constexpr SymPairs make_sym_pairs() {
+    SymPairs t{};
+    for (int i = 0; i < 16; ++i) {
+        t.b2[i] = 0;
+        for (int mt = 0; mt < 3; ++mt) t.b1[mt][i] = -1;
+    }
+    int row = 0;
+    for (int b2 = kMaxNB - 1; b2 >= 0; --b2)
+        for (int b1 = 0; b1 <= b2; ++row)
+            for (int mt = 0; mt < 3 && b1 <= b2; ++mt, ++b1) {
+                t.b2[row] = b2;
+                t.b1[mt][row] = b1;
+            }
+    return t;
+}
+constexpr SymPairs kSym = make_sym_pairs();
+static_assert(kSym.b2[14] == 0 && kSym.b1[0][14] == 0 && kSym.b1[0][15] == -1, "36 pairs in 15 rows");
 
 // staged columns: distinct l values in the order LA, LB, LC; column = offset + m
 template <int LA, int LB, int LC> struct Cols {
@@ -50,7 +77,7 @@ __device__ __forceinline__ float2 signed_m(float2 v) {
     else return make_float2(-v.x, v.y);
 }
 
-template <int LA, int LB, int MC, int MA, int T>
+template <int LA, int LB, int MC, int MA, int T, int NMT>
 struct Couple {
     // add the terms ma = MA .. LA of one mc to L[mt] for every M tile; T = index of the term
     // in the table.  The 3j weight multiplies the b2 operand once (it is the same bin b2 in
@@ -67,7 +94,7 @@ struct Couple {
                 // a_{l0} is real (real field, real Y_l0): m = 0 operands use their real part only
                 const float2 u = MB == 0 ? make_float2(c * y.x, 0.f) : make_float2(c * y.x, c * y.y);
 #pragma unroll
-                for (int mt = 0; mt < kMT; ++mt) {
+                for (int mt = 0; mt < NMT; ++mt) {
                     const float2 x = signed_m<MA>(A1[mt][MA >= 0 ? MA : -MA]);
                     if constexpr (MA == 0) {
                         L[mt].x = __builtin_fmaf(x.x, u.x, L[mt].x);
@@ -82,9 +109,9 @@ struct Couple {
                         L[mt].y = __builtin_fmaf(x.y, u.x, L[mt].y);
                     }
                 }
-                Couple<LA, LB, MC, MA + 1, T + 1>::run(cw, A1, A2, L);
+                Couple<LA, LB, MC, MA + 1, T + 1, NMT>::run(cw, A1, A2, L);
             } else {
-                Couple<LA, LB, MC, MA + 1, T>::run(cw, A1, A2, L);
+                Couple<LA, LB, MC, MA + 1, T, NMT>::run(cw, A1, A2, L);
             }
         }
     }
@@ -98,7 +125,7 @@ struct Couple {
 // mc = 0 of an odd Lambda: the pair (ma, -ma) gives 2 i (-1)^ma C_ma Im(a^b1_{LA,ma} conj
 // a^b2_{LB,ma}) (the 3j symbol is odd under m -> -m, and the ma = 0 symbol vanishes), so L_0
 // is imaginary: L_0.y = sum_{ma > 0} 2 (-1)^ma C_ma (x.y y.x - x.x y.y).
-template <int LA, int LB, int MA>
+template <int LA, int LB, int MA, int NMT>
 struct Couple0Odd {
     __device__ __forceinline__ static void run(const float *cw, const float2 (*A1)[LA + 1], const float2 *A2,
                                                float2 *L) {
@@ -110,17 +137,17 @@ struct Couple0Odd {
                 const float c = ((MA & 1) ? -2.f : 2.f) * cw[T];
                 const float2 u = make_float2(c * A2[MA].x, c * A2[MA].y);
 #pragma unroll
-                for (int mt = 0; mt < kMT; ++mt) {
+                for (int mt = 0; mt < NMT; ++mt) {
                     L[mt].y = __builtin_fmaf(A1[mt][MA].y, u.x, L[mt].y);
                     L[mt].y = __builtin_fmaf(-A1[mt][MA].x, u.y, L[mt].y);
                 }
             }
-            Couple0Odd<LA, LB, MA + 1>::run(cw, A1, A2, L);
+            Couple0Odd<LA, LB, MA + 1, NMT>::run(cw, A1, A2, L);
         }
     }
 };
 
-template <int LA, int LB, int MA>
+template <int LA, int LB, int MA, int NMT>
 struct Couple0 {
     __device__ __forceinline__ static void run(const float *cw, const float2 (*A1)[LA + 1], const float2 *A2,
                                                float2 *L) {
@@ -131,17 +158,17 @@ struct Couple0 {
             if constexpr (MA == 0) {
                 const float u = cw[T] * A2[0].x;
 #pragma unroll
-                for (int mt = 0; mt < kMT; ++mt) L[mt].x = __builtin_fmaf(A1[mt][0].x, u, L[mt].x);
+                for (int mt = 0; mt < NMT; ++mt) L[mt].x = __builtin_fmaf(A1[mt][0].x, u, L[mt].x);
             } else {
                 const float c = ((MA & 1) ? -2.f : 2.f) * cw[T];
                 const float2 u = make_float2(c * A2[MA].x, c * A2[MA].y);
 #pragma unroll
-                for (int mt = 0; mt < kMT; ++mt) {
+                for (int mt = 0; mt < NMT; ++mt) {
                     L[mt].x = __builtin_fmaf(A1[mt][MA].x, u.x, L[mt].x);
                     L[mt].x = __builtin_fmaf(A1[mt][MA].y, u.y, L[mt].x);
                 }
             }
-            Couple0<LA, LB, MA + 1>::run(cw, A1, A2, L);
+            Couple0<LA, LB, MA + 1, NMT>::run(cw, A1, A2, L);
         }
     }
 };
@@ -174,6 +201,8 @@ __device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
 template <int LA, int LB, int LC, int PREC>
 __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
     constexpr bool ODD = ((LA + LB + LC) & 1) != 0;
+    constexpr bool SYM = LA == LB;                // only the pairs b1 <= b2 (SymPairs)
+    constexpr int NMT = SYM ? 3 : 4;              // M tiles of 16 pairs
     using CL = Cols<LA, LB, LC>;
     constexpr int NCOL = CL::ncol;
     constexpr int TC = kTileCells;
@@ -188,11 +217,14 @@ __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: row addresses stay scalar
     const int i = lane & 15, g = lane >> 4;
-    const int b2 = i & 7, bh = i >> 3;
-    const float *cw = a.coefw;   // weighted 3j values of this Lambda, table order (mc outer, ma inner)
-    f4v acc[kMT];
+    const int b2 = SYM ? kSym.b2[i] : (i & 7);
+    int b1s[NMT];   // b1 of this lane's row in each tile (-1: empty slot)
 #pragma unroll
-    for (int mt = 0; mt < kMT; ++mt) acc[mt] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int mt = 0; mt < NMT; ++mt) b1s[mt] = SYM ? kSym.b1[mt][i] : 2 * mt + (i >> 3);
+    const float *cw = a.coefw;   // weighted 3j values of this Lambda, table order (mc outer, ma inner)
+    f4v acc[NMT];
+#pragma unroll
+    for (int mt = 0; mt < NMT; ++mt) acc[mt] = f4v{0.f, 0.f, 0.f, 0.f};
     const int64_t c0 = (int64_t)blockIdx.x * a.cells_per_block;
     const int64_t c1 = min(c0 + a.cells_per_block, a.ng);
     // load k of this thread: cell = lane, (column, bin) row = wave + 4 k
@@ -225,12 +257,13 @@ __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
         for (int cc = 0; cc < 4; ++cc) {
             const float2 *row = tile + (16 * wave + 4 * g + cc) * S;
             const float wv = wt[16 * wave + 4 * g + cc];
-            float2 A1[kMT][LA + 1], A2[LB + 1], bv[LC + 1];
+            float2 A1[NMT][LA + 1], A2[LB + 1], bv[LC + 1];
 #pragma unroll
-            for (int mt = 0; mt < kMT; ++mt)
+            for (int mt = 0; mt < NMT; ++mt)
 #pragma unroll
                 for (int m = 0; m <= LA; ++m) {
-                    const float2 v = row[(CL::offA + m) * kMaxNB + 2 * mt + bh];   // zero beyond nbins
+                    const float2 v = (!SYM || b1s[mt] >= 0) ? row[(CL::offA + m) * kMaxNB + b1s[mt]]   // zero beyond nbins
+                                                            : make_float2(0.f, 0.f);
                     A1[mt][m] = make_float2(wv * v.x, wv * v.y);
                 }
 #pragma unroll
@@ -241,20 +274,20 @@ __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
             // one mc: couple, then contract on the matrix cores (unrolled over mc below)
             auto step = [&](auto mc_c) {
                 constexpr int MC = decltype(mc_c)::value;
-                float2 L[kMT];
+                float2 L[NMT];
 #pragma unroll
-                for (int mt = 0; mt < kMT; ++mt) L[mt] = make_float2(0.f, 0.f);
+                for (int mt = 0; mt < NMT; ++mt) L[mt] = make_float2(0.f, 0.f);
                 if constexpr (MC == 0 && !ODD)
-                    Couple0<LA, LB, 0>::run(cw, A1, A2, L);
+                    Couple0<LA, LB, 0, NMT>::run(cw, A1, A2, L);
                 else if constexpr (MC == 0)
-                    Couple0Odd<LA, LB, 0>::run(cw, A1, A2, L);
+                    Couple0Odd<LA, LB, 0, NMT>::run(cw, A1, A2, L);
                 else
-                    Couple<LA, LB, MC, -LA, terms_before<LA, LB>(MC)>::run(cw, A1, A2, L);
+                    Couple<LA, LB, MC, -LA, terms_before<LA, LB>(MC), NMT>::run(cw, A1, A2, L);
                 // even: Re(L a) = L.x a.x - L.y a.y;  odd: Im(L a) = L.y a.x + L.x a.y.  For mc = 0
                 // a_{l0} is real and L_0 is real (even) or imaginary (odd): one product.
                 if constexpr (PREC == 0) {
 #pragma unroll
-                    for (int mt = 0; mt < kMT; ++mt) {
+                    for (int mt = 0; mt < NMT; ++mt) {
                         if constexpr (!ODD) {
                             acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(L[mt].x, bv[MC].x, acc[mt], 0, 0, 0);
                             if constexpr (MC > 0)
@@ -272,7 +305,7 @@ __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
                     split_bf16(bv[MC].x, h, l); bhv[0] = h; blv[0] = l;
                     split_bf16(bv[MC].y, h, l); bhv[1] = h; blv[1] = l;
 #pragma unroll
-                    for (int mt = 0; mt < kMT; ++mt) {
+                    for (int mt = 0; mt < NMT; ++mt) {
                         bf8v ahv = {}, alv = {};
                         split_bf16(ODD ? L[mt].y : L[mt].x, h, l); ahv[0] = h; alv[0] = l;
                         split_bf16(ODD ? L[mt].x : -L[mt].y, h, l); ahv[1] = h; alv[1] = l;
@@ -287,24 +320,34 @@ __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
             }(std::make_integer_sequence<int, LC + 1>{});
         }
     }
-    // accumulator tile mt: lane l holds rows 4 g + r (pair (b1, b2) = ((16 mt + 4 g + r) / 8,
-    // (16 mt + 4 g + r) % 8)), column i (bin b3)
+    // accumulator tile mt: lane l holds rows 4 g + r (their pairs as laid out above), column i
+    // (bin b3)
     __syncthreads();
     const int nv = nb * nb * nb;
     for (int v = tid; v < 4 * nv; v += 256) red[v] = 0.f;
     __syncthreads();
 #pragma unroll
-    for (int mt = 0; mt < kMT; ++mt)
+    for (int mt = 0; mt < NMT; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int pr = 16 * mt + 4 * g + r;
-            const int p1 = pr >> 3, p2 = pr & 7;
-            if (p1 < nb && p2 < nb && i < nb) red[wave * nv + (p1 * nb + p2) * nb + i] = acc[mt][r];
+            const int ro = 4 * g + r, pr = 16 * mt + ro;
+            const int p1 = SYM ? kSym.b1[mt][ro] : pr >> 3;
+            const int p2 = SYM ? kSym.b2[ro] : pr & 7;
+            if (p1 >= 0 && p1 < nb && p2 < nb && i < nb) red[wave * nv + (p1 * nb + p2) * nb + i] = acc[mt][r];
         }
     __syncthreads();
     for (int v = tid; v < nv; v += 256) {
-        const double s = ((double)red[v] + (double)red[nv + v]) + ((double)red[2 * nv + v] + (double)red[3 * nv + v]);
-        a.partial[((int64_t)a.lam * nv + v) * a.nblocks + blockIdx.x] = s;
+        int vs = v;
+        double sg = 1.0;
+        if constexpr (SYM) {   // b1 > b2: the mirrored pair (sign -1 for odd Lambda)
+            const int p1 = v / (nb * nb), p2 = (v / nb) % nb, b3 = v % nb;
+            if (p1 > p2) {
+                vs = (p2 * nb + p1) * nb + b3;
+                sg = ODD ? -1.0 : 1.0;
+            }
+        }
+        const double s = ((double)red[vs] + (double)red[nv + vs]) + ((double)red[2 * nv + vs] + (double)red[3 * nv + vs]);
+        a.partial[((int64_t)a.lam * nv + v) * a.nblocks + blockIdx.x] = sg * s;
     }
 }
 
