@@ -242,7 +242,10 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
         p->idx_cols = 1;
         for (int l = 0; l <= L; ++l) p->idx_table.push_back(l);
     } else if (prob->ndim == 3) {
-        p->f4 = make_full4_plan(L, NB, (prob->flags & SB_FLAG_ODD_PARITY) == 0);
+        // the matrix-core kernels cover l <= 4 and <= 8 bins; their canonical orderings are
+        // chosen for that kernel
+        const bool mfma = (prob->flags & SB_FLAG_NO_MFMA) == 0 && L <= 4 && NB <= 8;
+        p->f4 = make_full4_plan(L, NB, (prob->flags & SB_FLAG_ODD_PARITY) == 0, mfma);
         p->zeta_doubles = (int64_t)p->f4.out_lams.size() * NB * NB * NB;
         p->idx_rows = (int32_t)p->f4.out_lams.size();
         p->idx_cols = 3;

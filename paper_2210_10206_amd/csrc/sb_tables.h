@@ -24,7 +24,7 @@ bool exact_floor_square(double e, int64_t *out);
 double ylm_norm(int l, int m);
 double wigner3j(int j1, int j2, int j3, int m1, int m2, int m3);
 std::vector<Lam> full4_lambdas(int lmax, bool even);
-Full4Plan make_full4_plan(int lmax, int nbins, bool even = true);
+Full4Plan make_full4_plan(int lmax, int nbins, bool even = true, bool mfma = false);
 std::vector<std::pair<int, int>> proj4_pairs(int mmax);
 
 // Projected 4PCF symmetry (Alg. 8): the summand c^b1_m1 c^b2_m2 c^b3_m3, m3 = -(m1 + m2), is

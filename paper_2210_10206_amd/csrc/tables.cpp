@@ -93,10 +93,30 @@ static void terms_of(int la, int lb, int lc, std::vector<QuadTermH> *t) {
 // Odd Lambda: permuting the 3j columns multiplies the symbol by (-1)^(l1+l2+l3) for each
 // transposition, so an output Lambda is its canonical ordering's sums times the sign of the
 // permutation; the product of the three coefficients is symmetric.
-Full4Plan make_full4_plan(int lmax, int nbins, bool even) {
+// Issue cycles per 4-cell step of the matrix-core kernel for the ordering (la, lb, lc): the
+// vector coupling (2 multiplies + 4 FMAs per M tile for a general term, less where an m is 0,
+// the mc = 0 pairing, the weighting of the b1 operands) and the 16x16x4 MFMAs (32 cycles,
+// 2 per mc > 0 and M tile); la == lb computes 3 M tiles instead of 4 (pairs b1 <= b2).
+static double mfma_cost(int la, int lb, int lc, const std::vector<QuadTermH> &t, bool even) {
+    const int nmt = la == lb ? 3 : 4;
+    double valu = 2.0 * nmt * (la + 1);
+    for (const QuadTermH &q : t) {
+        if (q.mc == 0) {
+            if (q.ma < 0 || (!even && q.ma == 0)) continue;
+            valu += q.ma == 0 ? 1 + nmt : 2 + 2 * nmt;
+        } else {
+            valu += (q.ma == 0 || q.mb == 0) ? 2 + 2 * nmt : 2 + 4 * nmt;
+        }
+    }
+    const double mfma = nmt * (2.0 * lc + 1.0);
+    return std::max(4.0 * valu, 32.0 * mfma) + 0.01 * (4.0 * valu + 32.0 * mfma);
+}
+
+Full4Plan make_full4_plan(int lmax, int nbins, bool even, bool mfma) {
     Full4Plan p;
     p.out_lams = full4_lambdas(lmax, even);
-    // canonical = sorted triples; pick the ordering with the fewest flops per cell
+    // canonical = sorted triples; pick the cheapest ordering: fewest flops per cell for the
+    // vector kernel, fewest issue cycles (mfma_cost) for the matrix-core kernels
     std::vector<Lam> sorted;
     for (const Lam &L : p.out_lams) {
         Lam s = L;
@@ -115,7 +135,8 @@ Full4Plan make_full4_plan(int lmax, int nbins, bool even) {
             const int la = s.l[perm[0]], lb = s.l[perm[1]], lc = s.l[perm[2]];
             std::vector<QuadTermH> t;
             terms_of(la, lb, lc, &t);
-            const double cost = (double)t.size() * nb2 * 8.0 + (double)(lc + 1) * nb3 * 4.0;
+            const double cost = mfma ? mfma_cost(la, lb, lc, t, even)
+                                     : (double)t.size() * nb2 * 8.0 + (double)(lc + 1) * nb3 * 4.0;
             if (cost < best) { best = cost; bestL = {la, lb, lc}; bestT = t; }
         } while (std::next_permutation(perm, perm + 3));
         p.canon.push_back(bestL);
