@@ -65,28 +65,56 @@ __global__ __launch_bounds__(NBT * R * TPP) void adj_last_kernel(AdjLastArgs a) 
         }
         return (a.shape[0] - row) % a.shape[0];
     };
-    for (int64_t row0 = r_begin; row0 < r_end; row0 += R) {
-        __syncthreads();
+    // per thread: elements e of the load pattern (f = tid + e NT: pencil f / N, column f % N) and
+    // cells c = tid + k NT of the per-cell phase; the next tile's values are loaded into
+    // registers while the current one is processed
+    constexpr int CPT = (R * N + NT - 1) / NT;
+    auto load_tile = [&](int64_t row0, float2 *x, float *wv, float *dv) {
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const int f = tid + e * NT;
             const int pp = f / N, j = f % N;
             const int b = pp / R;
             const int64_t row = row0 + pp % R;
-            sm[j * PITCH + pp] = (row < r_end && b < nb) ? a.in[(int64_t)b * a.ng + row * N + j] : make_float2(0.f, 0.f);
+            x[e] = (row < r_end && b < nb) ? a.in[(int64_t)b * a.ng + row * N + j] : make_float2(0.f, 0.f);
         }
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            const int c = tid + k * NT;
+            const int64_t row = row0 + c / N;
+            const bool in = c < R * N && row < r_end;
+            wv[k] = in ? a.w[row * N + c % N] : 0.f;
+            dv[k] = (in && !a.first) ? a.dsum[row * N + c % N] : 0.f;
+        }
+    };
+    float2 nx[EPT];
+    float nw[CPT], nd[CPT];
+    if (r_begin < r_end) load_tile(r_begin, nx, nw, nd);
+    for (int64_t row0 = r_begin; row0 < r_end; row0 += R) {
+        float cw[CPT], cd[CPT];
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) { cw[k] = nw[k]; cd[k] = nd[k]; }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int f = tid + e * NT;
+            sm[(f % N) * PITCH + f / N] = nx[e];
+        }
+        if (row0 + R < r_end) load_tile(row0 + R, nx, nw, nd);   // next tile in flight
         __syncthreads();
         stages<N, TPP, 1, 1, RAD...>(sm, tw, tid % P, tid / P, PITCH);
         // per cell: h, the direct term and v (each thread owns whole cells: all bins of a cell)
-        for (int c = tid; c < R * N; c += NT) {
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            const int c = tid + k * NT;
             const int r = c / N, j = c % N;
             const int64_t row = row0 + r;
-            if (row >= r_end) continue;
+            if (c >= R * N || row >= r_end) continue;
             const int64_t cell = row * N + j;
             float2 av[NBT];
 #pragma unroll
             for (int b = 0; b < NBT; ++b) av[b] = sm[j * PITCH + b * R + r];
-            const float dw = a.wm * a.w[cell];
+            const float dw = a.wm * cw[k];
             float d = 0.f;
 #pragma unroll
             for (int b1 = 0; b1 < NBT; ++b1) {
@@ -101,8 +129,7 @@ __global__ __launch_bounds__(NBT * R * TPP) void adj_last_kernel(AdjLastArgs a) 
                 d = __builtin_fmaf(-av[b1].y, hy, d);
                 sm[j * PITCH + b1 * R + r] = make_float2(dw * hx, dw * hy);
             }
-            if (a.first) a.dsum[cell] = a.wm * d;
-            else a.dsum[cell] += a.wm * d;
+            a.dsum[cell] = cd[k] + a.wm * d;   // cd = 0 on the first group
         }
         __syncthreads();
         stages<N, TPP, -1, 1, RAD...>(sm, tw, tid % P, tid / P, PITCH);

@@ -137,7 +137,9 @@ sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta
                     a.wm = m == 0 ? 1.f : 2.f;
                     a.nb = NB;
                     const int64_t nrows = G.ng / a.n;
-                    a.rows_per_block = std::max<int64_t>(8, (nrows + 2047) / 2048);
+                    // about 4096 workgroups (the small grids need them all to fill the chip),
+                    // at most 16 rows each
+                    a.rows_per_block = std::max<int64_t>(1, std::min<int64_t>(16, nrows / 4096));
                     a.first = lm == 0;
                     a.dsum = dsum;
                     a.out = vtmp;

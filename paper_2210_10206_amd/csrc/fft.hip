@@ -153,13 +153,26 @@ __global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
         float2 acc[EPT];
 #pragma unroll
         for (int e = 0; e < EPT; ++e) acc[e] = make_float2(0.f, 0.f);
-        for (int b = 0; b < a.nb; ++b) {
-            __syncthreads();
+        // v of bin b + 1 and its kernel pencil are loaded into registers while bin b is processed
+        auto load_v = [&](int b, float2 *dst) {
             const float2 *vb = a.vin + (int64_t)b * a.ng;
 #pragma unroll
-            for (int e = 0; e < EPT; ++e)
-                sm[(q0 + e * TPP) * PITCH + p] = ok ? vb[(int64_t)(q0 + e * TPP) * a.plane + g] : make_float2(0.f, 0.f);
-            load_kernel(a.kfirst + b, nx);
+            for (int e = 0; e < EPT; ++e) dst[e] = ok ? vb[(int64_t)(q0 + e * TPP) * a.plane + g] : make_float2(0.f, 0.f);
+        };
+        float2 nv[EPT], kx[EPT];
+        load_v(0, nv);
+        load_kernel(a.kfirst, nx);
+        for (int b = 0; b < a.nb; ++b) {
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                sm[(q0 + e * TPP) * PITCH + p] = nv[e];
+                kx[e] = nx[e];
+            }
+            if (b + 1 < a.nb) {
+                load_v(b + 1, nv);
+                load_kernel(a.kfirst + b + 1, nx);
+            }
             __syncthreads();
             stages<N, TPP, -1, 1, RAD...>(sm, tw, p, q0, PITCH);
             float2 vr[EPT];
@@ -167,7 +180,7 @@ __global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
             for (int e = 0; e < EPT; ++e) vr[e] = sm[(q0 + e * TPP) * PITCH + p];
             __syncthreads();
 #pragma unroll
-            for (int e = 0; e < EPT; ++e) sm[(q0 + e * TPP) * PITCH + p] = nx[e];
+            for (int e = 0; e < EPT; ++e) sm[(q0 + e * TPP) * PITCH + p] = kx[e];
             __syncthreads();
             stages<N, TPP, -1, 1, RAD...>(sm, tw, p, q0, PITCH);
 #pragma unroll
