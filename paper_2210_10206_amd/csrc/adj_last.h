@@ -145,6 +145,138 @@ __global__ __launch_bounds__(NBT * R * TPP) void adj_last_kernel(AdjLastArgs a) 
     }
 }
 
+// Register-resident form for the lengths with a radix list R0, REST... whose last radix
+// divides the first (reg_stages): a tile is one row of the NBT (padded) bins; thread q < T =
+// N / R0 of pencil pp (= bin) holds elements q + T s of it, so the loads, both transforms and
+// the stores stay in registers and LDS is used for the stage exchanges and for the [cell][bin]
+// view of the per-cell phase.
+template <int N, int NBT, int R0, int... REST>
+__global__ __launch_bounds__(NBT * (N / R0)) void adj_rs_kernel(AdjLastArgs a) {
+    constexpr int T = N / R0;
+    constexpr int P = NBT, PITCH = P + 1, NT = P * T;
+    constexpr int NSTAGE = 1 + sizeof...(REST);
+    constexpr int CSB = (NSTAGE - 1) % 2;       // buffer the last inverse stage does not read
+    constexpr int CPT = (N + NT - 1) / NT;      // cells per thread in the per-cell phase
+    static_assert(NSTAGE >= 2, "two stages or more");
+    __shared__ float2 ex[2][N * PITCH];
+    __shared__ float2 tw[N];
+    __shared__ float G[NBT * NBT];               // NBT x NBT, zero beyond nb
+    const int nb = a.nb;
+    const int tid = threadIdx.x;
+    const int q = tid % T, pp = tid / T;         // element column, pencil (= bin)
+    for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
+    for (int i = tid; i < NBT * NBT; i += NT) {
+        const int b1 = i / NBT, b2 = i % NBT;
+        G[i] = (b1 < nb && b2 < nb) ? (float)(0.5 * (a.gz[b1 * nb + b2] + a.gz[b2 * nb + b1])) : 0.f;
+    }
+    const int64_t nrows = a.ng / N;
+    const int64_t r_begin = (int64_t)blockIdx.x * a.rows_per_block;
+    const int64_t r_end = min(r_begin + a.rows_per_block, nrows);
+    const bool live = pp < nb;
+    const float2 *in = a.in + (int64_t)(live ? pp : 0) * a.ng;
+    auto flip_row = [&](int64_t row) -> int64_t {
+        if (a.ndim == 3) {
+            const int64_t n1 = a.shape[1];
+            const int64_t i0 = row / n1, i1 = row % n1;
+            return ((a.shape[0] - i0) % a.shape[0]) * n1 + (n1 - i1) % n1;
+        }
+        return (a.shape[0] - row) % a.shape[0];
+    };
+    auto load_row = [&](int64_t row, float2 *x, float *wv, float *dv) {
+#pragma unroll
+        for (int r = 0; r < R0; ++r) x[r] = live ? in[row * N + q + T * r] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            const int c = tid + k * NT;
+            wv[k] = c < N ? a.w[row * N + c] : 0.f;
+            dv[k] = (c < N && !a.first) ? a.dsum[row * N + c] : 0.f;
+        }
+    };
+    float2 nx[R0];
+    float nw[CPT], nd[CPT];
+    if (r_begin < r_end) load_row(r_begin, nx, nw, nd);
+    for (int64_t row = r_begin; row < r_end; ++row) {
+        float2 v[R0];
+        float cw[CPT], cd[CPT];
+#pragma unroll
+        for (int r = 0; r < R0; ++r) v[r] = nx[r];
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) { cw[k] = nw[k]; cd[k] = nd[k]; }
+        if (row + 1 < r_end) load_row(row + 1, nx, nw, nd);   // next row in flight
+        __syncthreads();                                       // the previous row's buffers are free
+        reg_stages<N, 1, R0, REST...>(v, ex[0], ex[1], tw, q, pp, PITCH);   // inverse
+        float2 *cs = ex[CSB];
+#pragma unroll
+        for (int r = 0; r < R0; ++r) cs[(q + T * r) * PITCH + pp] = v[r];
+        __syncthreads();
+        // per cell: h = G conj(a), the direct term and v = w_m delta h (whole cells per thread)
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            const int c = tid + k * NT;
+            if (c >= N) continue;
+            float2 av[NBT];
+#pragma unroll
+            for (int b = 0; b < NBT; ++b) av[b] = cs[c * PITCH + b];
+            const float dw = a.wm * cw[k];
+            float d = 0.f;
+#pragma unroll
+            for (int b1 = 0; b1 < NBT; ++b1) {
+                float hx = 0.f, hy = 0.f;
+#pragma unroll
+                for (int b2 = 0; b2 < NBT; ++b2) {
+                    const float g = G[b1 * NBT + b2];
+                    hx = __builtin_fmaf(g, av[b2].x, hx);
+                    hy = __builtin_fmaf(-g, av[b2].y, hy);   // conj(a)
+                }
+                d = __builtin_fmaf(av[b1].x, hx, d);
+                d = __builtin_fmaf(-av[b1].y, hy, d);
+                cs[c * PITCH + b1] = make_float2(dw * hx, dw * hy);
+            }
+            a.dsum[row * N + c] = cd[k] + a.wm * d;   // cd = 0 on the first group
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R0; ++r) v[r] = cs[(q + T * r) * PITCH + pp];
+        __syncthreads();                                       // cs may be the first exchange buffer
+        reg_stages<N, -1, R0, REST...>(v, ex[0], ex[1], tw, q, pp, PITCH);  // forward
+        if (live) {
+            float2 *out = a.out + (int64_t)pp * a.ng + flip_row(row) * N;
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                const int k = q + T * r;
+                out[(N - k) % N] = v[r];
+            }
+        }
+    }
+}
+
+// bins padded to 4, 8, 12 or 16 so that NBT * t threads make whole waves (0: none fits)
+constexpr int rs_padded_bins(int nb, int t) {
+    for (int c = 4; c <= 16; c += 4)
+        if (c >= nb && (c * t) % 64 == 0 && c * t <= 1024) return c;
+    return 0;
+}
+
+template <int N, int R0, int... REST>
+hipError_t launch_rs(const AdjLastArgs &a, hipStream_t s) {
+    constexpr int T = N / R0;
+    const int64_t nrows = a.ng / N;
+    dim3 grid((unsigned)((nrows + a.rows_per_block - 1) / a.rows_per_block));
+    switch (rs_padded_bins(a.nb, T)) {
+#define SB_AR(NBT)                                                                               \
+    case NBT:                                                                                    \
+        if constexpr ((NBT * T) % 64 == 0 && NBT * T <= 1024) {                                  \
+            hipLaunchKernelGGL((adj_rs_kernel<N, NBT, R0, REST...>), grid, dim3(NBT * T), 0, s, a); \
+            return hipGetLastError();                                                            \
+        } else {                                                                                 \
+            return hipErrorInvalidValue;                                                         \
+        }
+        SB_AR(4) SB_AR(8) SB_AR(12) SB_AR(16)
+#undef SB_AR
+        default: return hipErrorInvalidValue;
+    }
+}
+
 // rows per tile: the fewest that make whole waves
 constexpr int tile_rows(int tpp, int nbt) {
     int r = 1;

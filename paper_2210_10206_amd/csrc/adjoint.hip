@@ -81,6 +81,19 @@ __global__ void zero_c_kernel(float2 *x, int64_t n) {
 }  // namespace
 
 hipError_t launch_adj_last(const AdjLastArgs &a, hipStream_t s) {
+    // register-resident stages where the radix list allows (the forward fused pass uses the same
+    // lists), the LDS-staged tile kernel otherwise
+    hipError_t e = hipErrorInvalidValue;
+    switch (a.n) {
+        case 64: e = adjlast::launch_rs<64, 8, 8>(a, s); break;
+        case 96: e = adjlast::launch_rs<96, 12, 4, 2>(a, s); break;
+        case 128: e = adjlast::launch_rs<128, 16, 8>(a, s); break;
+        case 160: e = adjlast::launch_rs<160, 20, 4, 2>(a, s); break;
+        case 192: e = adjlast::launch_rs<192, 12, 4, 4>(a, s); break;
+        case 256: e = adjlast::launch_rs<256, 16, 16>(a, s); break;
+        default: break;
+    }
+    if (e == hipSuccess) return e;
     switch (a.n) {
 #define SB_X(N, TPP, ...) case N: return adjlast::launch_n<N, TPP, __VA_ARGS__>(a, s);
         SB_LAST_CONFIGS(SB_X)

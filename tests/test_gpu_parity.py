@@ -485,6 +485,26 @@ def test_full4pcf_lmax3_six_bins(sb):
 
 # ------------------------------------------------------------------ adjoint
 
+@pytest.mark.parametrize("shape,nbins", [((8, 16, 256), 10), ((8, 12, 64), 3), ((12, 8, 160), 16)])
+def test_adjoint_register_last_pass(sb, shape, nbins):
+    # the register-resident adjoint last pass at last-axis lengths 256, 64 and 160, with 12, 4
+    # and 16 padded bins, against the oracle's gradient at 24 sampled cells
+    say(f"case: {shape} adjoint, {nbins} bins to 6, lmax 3, gradient at 24 cells")
+    d = lognormal_field(shape, seed=41, sigma=1.0)
+    edges = linear_edges(6, nbins)
+    rng = np.random.Generator(np.random.PCG64(42))
+    G = rng.standard_normal((4, nbins, nbins))
+    cells = np.sort(rng.choice(d.size, 24, replace=False))
+    plan = sb.Plan([d.shape], edges, 3)
+    g = plan.backward([torch.from_numpy(d).cuda()], torch.from_numpy(G)[None].cuda())[0]
+    g = g.reshape(-1).double().cpu().numpy()[cells]
+    ref = oracle.grad3_full(d.astype(np.float64), edges, 3, G, cells=cells)
+    err = float(np.max(np.abs(g - ref)) / np.max(np.abs(ref)))
+    say(f"  grad err={err:.3e}")
+    assert err < 2e-5
+    plan.close()
+
+
 @pytest.mark.parametrize("fused", [True, False])
 def test_adjoint_matches_oracle_gradient(sb, fused):
     say(f"case: 16^3 adjoint of the full 3PCF, 4 bins to 4, lmax 3, fused last pass {fused}")
