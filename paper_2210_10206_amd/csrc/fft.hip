@@ -203,7 +203,7 @@ __global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
 // the two stage exchanges (positions R1 q + r written), with one barrier each (the exchanges
 // alternate between two buffers).  Loads and stores take P adjacent pencils of the contiguous
 // axes per row, as in the LDS-staged kernel.
-template <int R1, int R2, int P>
+template <int R1, int R2, int P, int MODE>
 __global__ __launch_bounds__(P * R2) void axis0_reg_kernel(Axis0Args a) {
     constexpr int N = R1 * R2;
     constexpr int T = R1 / R2;   // second-stage butterflies per thread
@@ -251,7 +251,38 @@ __global__ __launch_bounds__(P * R2) void axis0_reg_kernel(Axis0Args a) {
             for (int r = 0; r < R2; ++r) v[t + T * r] = u[r];   // element q + R2 t + R1 r
         }
     };
-    float2 dr[R1], nx[R1];
+    float2 nx[R1];
+    if constexpr (MODE == 1) {
+        // adjoint: out += sum_b FFT_0(v_b) FFT_0(kernel b); bin b + 1 loads during bin b
+        auto load_v = [&](int b, float2 *dst) {
+            const float2 *vb = a.vin + (int64_t)b * a.ng;
+#pragma unroll
+            for (int r = 0; r < R1; ++r) dst[r] = ok ? vb[(int64_t)(q + R2 * r) * a.plane + g] : make_float2(0.f, 0.f);
+        };
+        float2 acc[R1], nv[R1];
+#pragma unroll
+        for (int r = 0; r < R1; ++r) acc[r] = make_float2(0.f, 0.f);
+        load_v(0, nv);
+        load_kernel(a.kfirst, nx);
+        for (int b = 0; b < a.nb; ++b) {
+            float2 v[R1], k[R1];
+#pragma unroll
+            for (int r = 0; r < R1; ++r) { v[r] = nv[r]; k[r] = nx[r]; }
+            if (b + 1 < a.nb) { load_v(b + 1, nv); load_kernel(a.kfirst + b + 1, nx); }
+            transform(v, ex[0], std::integral_constant<int, -1>{});
+            transform(k, ex[1], std::integral_constant<int, -1>{});
+#pragma unroll
+            for (int r = 0; r < R1; ++r) acc[r] = cadd(acc[r], cmul(v[r], k[r]));
+        }
+        if (ok)
+#pragma unroll
+            for (int r = 0; r < R1; ++r) {
+                float2 *o = a.out + (int64_t)(q + R2 * r) * a.plane + g;
+                *o = cadd(*o, acc[r]);
+            }
+        return;
+    }
+    float2 dr[R1];
 #pragma unroll
     for (int r = 0; r < R1; ++r) dr[r] = ok ? a.dhat[(int64_t)(q + R2 * r) * a.plane + g] : make_float2(0.f, 0.f);
     const int64_t kbase = (int64_t)blockIdx.y * a.nb;
@@ -275,7 +306,7 @@ __global__ __launch_bounds__(P * R2) void axis0_reg_kernel(Axis0Args a) {
 // Axis-0 correlation pass on the register-resident Stockham stages of reg_stages (any radix
 // list whose last radix divides the first; two or more stages): thread q < T = n / R0 of a
 // pencil owns rows q + T s.  P adjacent pencils of the contiguous axes per workgroup.
-template <int N, int P, int R0, int... REST>
+template <int N, int P, int MODE, int R0, int... REST>
 __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
     constexpr int T = N / R0;
     constexpr int PITCH = P + 1;
@@ -296,7 +327,42 @@ __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
             dst[r] = (ok && pl >= 0) ? kc[(int64_t)pl * a.plane + g] : make_float2(0.f, 0.f);
         }
     };
-    float2 dr[R0], nx[R0];
+    float2 nx[R0];
+    if constexpr (MODE == 1) {
+        // adjoint: out += sum_b FFT_0(v_b) FFT_0(kernel b); bin b + 1 loads during bin b.  The
+        // stage buffers alternate, so consecutive transforms need no barrier between them
+        // (odd stage counts: the last stage reads the buffer the next first stage does not write).
+        static_assert(sizeof...(REST) % 2 == 0, "odd number of stages");
+        auto load_v = [&](int b, float2 *dst) {
+            const float2 *vb = a.vin + (int64_t)b * a.ng;
+#pragma unroll
+            for (int r = 0; r < R0; ++r) dst[r] = ok ? vb[(int64_t)(q + T * r) * a.plane + g] : make_float2(0.f, 0.f);
+        };
+        float2 acc[R0], nv[R0];
+#pragma unroll
+        for (int r = 0; r < R0; ++r) acc[r] = make_float2(0.f, 0.f);
+        load_v(0, nv);
+        load_kernel(a.kfirst, nx);
+        __syncthreads();   // twiddle table
+        for (int b = 0; b < a.nb; ++b) {
+            float2 v[R0], k[R0];
+#pragma unroll
+            for (int r = 0; r < R0; ++r) { v[r] = nv[r]; k[r] = nx[r]; }
+            if (b + 1 < a.nb) { load_v(b + 1, nv); load_kernel(a.kfirst + b + 1, nx); }
+            reg_stages<N, -1, R0, REST...>(v, ex[0], ex[1], tw, q, p, PITCH);
+            reg_stages<N, -1, R0, REST...>(k, ex[0], ex[1], tw, q, p, PITCH);
+#pragma unroll
+            for (int r = 0; r < R0; ++r) acc[r] = cadd(acc[r], cmul(v[r], k[r]));
+        }
+        if (ok)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                float2 *o = a.out + (int64_t)(q + T * r) * a.plane + g;
+                *o = cadd(*o, acc[r]);
+            }
+        return;
+    }
+    float2 dr[R0];
 #pragma unroll
     for (int r = 0; r < R0; ++r) dr[r] = ok ? a.dhat[(int64_t)(q + T * r) * a.plane + g] : make_float2(0.f, 0.f);
     const int64_t kbase = (int64_t)blockIdx.y * a.nb;
@@ -456,22 +522,38 @@ hipError_t launch_fft_pass(const FftPass &a, hipStream_t s) {
 }
 
 hipError_t launch_axis0(const Axis0Args &a, hipStream_t s) {
-    if (a.mode == 0 && (a.n == 512 || a.n == 192 || a.n == 160 || a.n == 96)) {
+    if ((a.n == 512 && a.mode == 0) || a.n == 192 || a.n == 160 || a.n == 96) {
         // register-resident stages: 512 = 16 x 8 x 4, 192 = 12 x 4 x 4, 160 = 20 x 4 x 2, 96 = 12 x 4 x 2
+        // (the adjoint accumulation at 512 keeps the LDS-staged kernel: its registers would spill)
         constexpr int P = 16;
         dim3 grid((unsigned)((a.plane + P - 1) / P), (unsigned)a.groups);
-        if (a.n == 512) hipLaunchKernelGGL((axis0_rs_kernel<512, P, 16, 8, 4>), grid, dim3(32 * P), 0, s, a);
-        else if (a.n == 192) hipLaunchKernelGGL((axis0_rs_kernel<192, P, 12, 4, 4>), grid, dim3(16 * P), 0, s, a);
-        else if (a.n == 160) hipLaunchKernelGGL((axis0_rs_kernel<160, P, 20, 4, 2>), grid, dim3(8 * P), 0, s, a);
-        else hipLaunchKernelGGL((axis0_rs_kernel<96, P, 12, 4, 2>), grid, dim3(8 * P), 0, s, a);
+        auto go = [&](auto mode_c) {
+            constexpr int M = decltype(mode_c)::value;
+            if constexpr (M == 0) {
+                if (a.n == 512) {
+                    hipLaunchKernelGGL((axis0_rs_kernel<512, P, 0, 16, 8, 4>), grid, dim3(32 * P), 0, s, a);
+                    return;
+                }
+            }
+            if (a.n == 192) hipLaunchKernelGGL((axis0_rs_kernel<192, P, M, 12, 4, 4>), grid, dim3(16 * P), 0, s, a);
+            else if (a.n == 160) hipLaunchKernelGGL((axis0_rs_kernel<160, P, M, 20, 4, 2>), grid, dim3(8 * P), 0, s, a);
+            else hipLaunchKernelGGL((axis0_rs_kernel<96, P, M, 12, 4, 2>), grid, dim3(8 * P), 0, s, a);
+        };
+        if (a.mode == 1) go(std::integral_constant<int, 1>{});
+        else go(std::integral_constant<int, 0>{});
         return hipGetLastError();
     }
-    if (a.mode == 0 && (a.n == 256 || a.n == 128 || a.n == 64)) {
+    if (a.n == 256 || a.n == 128 || a.n == 64) {
         constexpr int P = 16;
         dim3 grid((unsigned)((a.plane + P - 1) / P), (unsigned)a.groups);
-        if (a.n == 256) hipLaunchKernelGGL((axis0_reg_kernel<16, 16, P>), grid, dim3(16 * P), 0, s, a);
-        else if (a.n == 128) hipLaunchKernelGGL((axis0_reg_kernel<16, 8, P>), grid, dim3(8 * P), 0, s, a);
-        else hipLaunchKernelGGL((axis0_reg_kernel<8, 8, P>), grid, dim3(8 * P), 0, s, a);
+        auto go = [&](auto mode_c) {
+            constexpr int M = decltype(mode_c)::value;
+            if (a.n == 256) hipLaunchKernelGGL((axis0_reg_kernel<16, 16, P, M>), grid, dim3(16 * P), 0, s, a);
+            else if (a.n == 128) hipLaunchKernelGGL((axis0_reg_kernel<16, 8, P, M>), grid, dim3(8 * P), 0, s, a);
+            else hipLaunchKernelGGL((axis0_reg_kernel<8, 8, P, M>), grid, dim3(8 * P), 0, s, a);
+        };
+        if (a.mode == 1) go(std::integral_constant<int, 1>{});
+        else go(std::integral_constant<int, 0>{});
         return hipGetLastError();
     }
     switch (a.n) {
