@@ -256,7 +256,7 @@ __global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
     const bool live = pp < nb;
     auto load_row = [&](int64_t row, float2 *dst, float *wdst) {
 #pragma unroll
-        for (int r = 0; r < R1; ++r) dst[r] = live ? in[row * N + q + R2 * r] : make_float2(0.f, 0.f);
+        for (int r = 0; r < R1; ++r) dst[r] = live ? ld_stream(&in[row * N + q + R2 * r]) : make_float2(0.f, 0.f);
 #pragma unroll
         for (int e = 0; e < WPT; ++e) {
             const int c = tid + e * NT;

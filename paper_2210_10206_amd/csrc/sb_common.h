@@ -15,6 +15,17 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 
+// Streaming accesses of the passes over the kernel arrays (each element read or written once
+// per pass): non-temporal hints keep them from displacing reused data in the caches.
+typedef float f2nt __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ld_stream(const float2 *p) {
+    const f2nt v = __builtin_nontemporal_load(reinterpret_cast<const f2nt *>(p));
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void st_stream(float2 *p, float2 v) {
+    __builtin_nontemporal_store(f2nt{v.x, v.y}, reinterpret_cast<f2nt *>(p));
+}
+
 // ---------------------------------------------------------------- FFT passes
 // One pass = 1D transforms of length n along one axis of a C-ordered array of
 // `ng` complex cells.  The axis has element stride `stride` (product of the later
