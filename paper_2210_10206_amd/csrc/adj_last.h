@@ -184,7 +184,7 @@ __global__ __launch_bounds__(NBT * (N / R0)) void adj_rs_kernel(AdjLastArgs a) {
     };
     auto load_row = [&](int64_t row, float2 *x, float *wv, float *dv) {
 #pragma unroll
-        for (int r = 0; r < R0; ++r) x[r] = live ? in[row * N + q + T * r] : make_float2(0.f, 0.f);
+        for (int r = 0; r < R0; ++r) x[r] = live ? ld_stream(&in[row * N + q + T * r]) : make_float2(0.f, 0.f);
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
             const int c = tid + k * NT;
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(NBT * (N / R0)) void adj_rs_kernel(AdjLastArgs a) {
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
                 const int k = q + T * r;
-                out[(N - k) % N] = v[r];
+                st_stream(&out[(N - k) % N], v[r]);
             }
         }
     }

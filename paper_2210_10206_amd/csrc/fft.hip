@@ -324,7 +324,7 @@ __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
         for (int r = 0; r < R0; ++r) {
             const int j = q + T * r;
             const int pl = (a.np == N || j <= a.r0) ? j : (j >= N - a.r0 ? a.np - (N - j) : -1);
-            dst[r] = (ok && pl >= 0) ? kc[(int64_t)pl * a.plane + g] : make_float2(0.f, 0.f);
+            dst[r] = (ok && pl >= 0) ? ld_stream(&kc[(int64_t)pl * a.plane + g]) : make_float2(0.f, 0.f);
         }
     };
     float2 nx[R0];
@@ -380,7 +380,7 @@ __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
         float2 *out = a.out + (kbase + b) * a.ng;
         if (ok)
 #pragma unroll
-            for (int r = 0; r < R0; ++r) out[(int64_t)(q + T * r) * a.plane + g] = v[r];
+            for (int r = 0; r < R0; ++r) st_stream(&out[(int64_t)(q + T * r) * a.plane + g], v[r]);
     }
 }
 
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(NT) void fft_pass_pf_kernel(FftPass a, int tiles) {
             int p, j;
             elem(e, p, j);
             const int64_t g = t * P + p;
-            nx[e] = g < npencil ? ld_stream(&in[addr(g, j)]) : make_float2(0.f, 0.f);
+            nx[e] = g < npencil ? in[addr(g, j)] : make_float2(0.f, 0.f);
         }
     };
     if (t0 < t1) load(t0);

@@ -174,7 +174,7 @@ __global__ __launch_bounds__(NBT * R * TPP) void last_contract_kernel(LastArgs a
             const int pp = f / N, j = f % N;
             const int b = pp / R;
             const int64_t row = row0 + pp % R;
-            dst[e] = (row < r_end && b < nb) ? in[(int64_t)b * a.ng + row * N + j] : make_float2(0.f, 0.f);
+            dst[e] = (row < r_end && b < nb) ? ld_stream(&in[(int64_t)b * a.ng + row * N + j]) : make_float2(0.f, 0.f);
         }
     };
     constexpr int WPT = (R * N + NT - 1) / NT;          // weights loaded per thread
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
     const bool live = pp < nb;
     auto load_row = [&](int64_t row, float2 *dst, float *wdst) {
 #pragma unroll
-        for (int r = 0; r < R0; ++r) dst[r] = live ? in[row * N + q + T * r] : make_float2(0.f, 0.f);
+        for (int r = 0; r < R0; ++r) dst[r] = live ? ld_stream(&in[row * N + q + T * r]) : make_float2(0.f, 0.f);
 #pragma unroll
         for (int e = 0; e < WPT; ++e) {
             const int c = tid + e * NT;
