@@ -74,7 +74,8 @@ enum {
                                  pass (the plain path; the default fuses the contraction into the
                                  last FFT pass and never writes the coefficients) */
     SB_FLAG_NO_MFMA = 4u,     /* full 4PCF: use the plain float32 vector-ALU contraction even where
-                                 the matrix-core one exists (lmax <= 4, nbins <= 8) */
+                                 the matrix-core one exists (lmax <= 4, nbins <= 8); projected
+                                 4PCF: the vector-ALU contraction instead of the matrix cores */
     SB_FLAG_ODD_PARITY = 8u   /* full 4PCF: the odd-parity Lambda (l1 + l2 + l3 odd, Sec. 2.3, the
                                  ones Alg. 6 skips) instead of the even ones; each value is the
                                  imaginary part of the sum, whose real part vanishes for a real

@@ -42,7 +42,8 @@ class Plan:
     npcf       : 3 or 4
     precision  : "fp32" or "split_bf16" (contraction arithmetic of the 4PCF paths)
     input_dtype: torch.float32 or torch.float64 (the density arrays' dtype)
-    mfma       : full 4PCF: use the matrix-core contraction where it exists (l <= 4, <= 8 bins)
+    mfma       : full 4PCF: use the matrix-core contraction where it exists (l <= 4, <= 8 bins);
+                 projected 4PCF: the matrix-core contraction (False = the vector-ALU kernel)
     parity     : full 4PCF: "even" (Alg. 6) or "odd" Lambda (the imaginary part of those sums)
     scratch_limit: bytes of kernel arrays a 3PCF plan keeps at once (default 48 GiB); above it
                  the passes run over chunks of (l, m) groups (sb_plan_set_scratch_limit)

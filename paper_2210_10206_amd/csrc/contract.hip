@@ -318,6 +318,7 @@ static hipError_t launch_proj4_nb(const Proj4Args &a, hipStream_t s) {
 }
 
 hipError_t launch_proj4_contract(const Proj4Args &a, hipStream_t s) {
+    if (a.mfma) return launch_proj4_mfma(a, s);
     switch (a.nbins) {
 #define SB_CASE(N) case N: return launch_proj4_nb<N>(a, s);
         SB_CASE(1) SB_CASE(2) SB_CASE(3) SB_CASE(4) SB_CASE(5) SB_CASE(6) SB_CASE(7) SB_CASE(8)

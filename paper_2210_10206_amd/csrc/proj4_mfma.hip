@@ -1,0 +1,151 @@
+// Projected 4PCF contraction (Alg. 8) on the matrix cores, one launch per canonical m triple.
+//
+// For the triple (m1, m2, m3 = -(m1 + m2)) and every cell x:
+//   L[b1 b2](x)    = w(x) c^b1_m1(x) c^b2_m2(x)          (vector ALU, one complex product)
+//   Z[b1 b2][b3]  += L[b1 b2](x) c^b3_m3(x)               (complex, on MFMA)
+// with c_{-m} = conj(c_m).  The second line is a GEMM with M = the NB^2 bin pairs (tiles of 16
+// rows: row i of tile mt is pair p = 16 mt + i = b1 NB + b2), N = b3 (padded to 16) and K = the
+// cells, taken as v_mfma_f32_16x16x4f32 with the four lane groups' cells as K: the real part
+// Lr Br - Li Bi and the imaginary part Lr Bi + Li Br are two MFMAs each.  Lane l = i + 16 g
+// supplies row i of each A tile and column i (b3 = i) of B for cell g of the four.
+//
+// Staging as in the full-4PCF matrix-core kernels: a tile of 64 cells in LDS, cell-major, one
+// row of 3 NB float2 (the m1, m2, m3 columns) per cell padded to a stride = 2 (mod 8) float2
+// (bank-conflict free stores and reads), the next tile's global loads issued before the current
+// one is contracted.  Block partials: partial[(pair * NB^3 * 2 + (p NB + b3) 2 + part) * nblocks
+// + block], as for the vector kernel.
+#include "sb_kgen.h"
+
+namespace sb {
+namespace {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <int NB>
+__global__ __launch_bounds__(256) void proj4_mfma_kernel(Proj4Args a) {
+    constexpr int NP = NB * NB;
+    constexpr int NMT = (NP + 15) / 16;        // M tiles of 16 pairs
+    constexpr int TC = 64;                     // cells per staged tile (16 per wave)
+    constexpr int W = 3 * NB;                  // staged float2 per cell
+    constexpr int S = (W + 7) / 8 * 8 + 2;     // padded row stride, = 2 (mod 8)
+    constexpr int NLD = (TC * W + 255) / 256;  // staged float2 per thread and tile
+    constexpr int NV = NB * NB * NB * 2;
+    constexpr int NTILE = TC * S > 2 * NV ? TC * S : 2 * NV;   // also holds 4 NV floats of reduction
+    __shared__ float2 tile[NTILE];
+    __shared__ float wt[TC];
+    float *red = reinterpret_cast<float *>(tile);
+    const int pr_ = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int i = lane & 15, g = lane >> 4;
+    const int m1 = a.pairs[2 * pr_], m2 = a.pairs[2 * pr_ + 1];
+    const int ms[3] = {m1, m2, -(m1 + m2)};
+    int b1s[NMT], b2s[NMT];   // pair of this lane's row in each tile (-1: beyond NB^2)
+#pragma unroll
+    for (int mt = 0; mt < NMT; ++mt) {
+        const int p = 16 * mt + i;
+        b1s[mt] = p < NP ? p / NB : -1;
+        b2s[mt] = p < NP ? p % NB : 0;
+    }
+    f4v accr[NMT], acci[NMT];
+#pragma unroll
+    for (int mt = 0; mt < NMT; ++mt) {
+        accr[mt] = f4v{0.f, 0.f, 0.f, 0.f};
+        acci[mt] = f4v{0.f, 0.f, 0.f, 0.f};
+    }
+    const int64_t c0 = (int64_t)blockIdx.x * a.cells_per_block;
+    const int64_t c1 = min(c0 + a.cells_per_block, a.ng);
+    // load k of this thread: f = tid + 256 k -> cell f % 64, staged column (k3 = slot, bin) f / 64
+    float2 pf[NLD];
+    float pw = 0.f;
+    auto gload = [&](int64_t tc) {
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int f = tid + 256 * k;
+            const int c = f % TC, kb = f / TC;
+            float2 v = make_float2(0.f, 0.f);
+            if (kb < W && tc + c < c1) {
+                const int slot = kb / NB, b = kb % NB;
+                const int m = ms[slot];
+                v = a.coef[((int64_t)(m < 0 ? -m : m) * NB + b) * a.ng + tc + c];
+                if (m < 0) v.y = -v.y;   // c_{-m} = conj(c_m)
+            }
+            pf[k] = v;
+        }
+        if (wave == 0) pw = tc + lane < c1 ? a.w[tc + lane] : 0.f;
+    };
+    gload(c0);
+    for (int64_t tc = c0; tc < c1; tc += TC) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int f = tid + 256 * k;
+            const int c = f % TC, kb = f / TC;
+            if (kb < W) tile[c * S + kb] = pf[k];
+        }
+        if (wave == 0) wt[lane] = pw;
+        __syncthreads();
+        if (tc + TC < c1) gload(tc + TC);
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+            const int c = 16 * wave + 4 * g + cc;
+            const float2 *row = tile + c * S;
+            const float wv = wt[c];
+            const float2 bv = i < NB ? row[2 * NB + i] : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int mt = 0; mt < NMT; ++mt) {
+                float2 L = make_float2(0.f, 0.f);
+                if (b1s[mt] >= 0) {
+                    const float2 x1 = row[b1s[mt]], x2 = row[NB + b2s[mt]];
+                    const float2 u = make_float2(wv * x1.x, wv * x1.y);
+                    L.x = __builtin_fmaf(u.x, x2.x, -u.y * x2.y);
+                    L.y = __builtin_fmaf(u.x, x2.y, u.y * x2.x);
+                }
+                accr[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(L.x, bv.x, accr[mt], 0, 0, 0);
+                accr[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-L.y, bv.y, accr[mt], 0, 0, 0);
+                acci[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(L.x, bv.y, acci[mt], 0, 0, 0);
+                acci[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(L.y, bv.x, acci[mt], 0, 0, 0);
+            }
+        }
+    }
+    // accumulator tile mt: lane l holds rows 4 g + r (pair 16 mt + 4 g + r), column i (bin b3)
+    __syncthreads();
+    for (int v = tid; v < 4 * NV; v += 256) red[v] = 0.f;
+    __syncthreads();
+#pragma unroll
+    for (int mt = 0; mt < NMT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = 16 * mt + 4 * g + r;
+            if (p < NP && i < NB) {
+                red[wave * NV + (p * NB + i) * 2] = accr[mt][r];
+                red[wave * NV + (p * NB + i) * 2 + 1] = acci[mt][r];
+            }
+        }
+    __syncthreads();
+    for (int v = tid; v < NV; v += 256) {
+        const double s = ((double)red[v] + (double)red[NV + v]) + ((double)red[2 * NV + v] + (double)red[3 * NV + v]);
+        a.partial[((int64_t)pr_ * NV + v) * a.nblocks + blockIdx.x] = s;
+    }
+}
+
+template <int NB>
+hipError_t launch_nb(const Proj4Args &a, hipStream_t s) {
+    dim3 grid((unsigned)a.nblocks, (unsigned)a.npairs);
+    hipLaunchKernelGGL((proj4_mfma_kernel<NB>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_proj4_mfma(const Proj4Args &a, hipStream_t s) {
+    switch (a.nbins) {
+#define SB_CASE(N) case N: return launch_nb<N>(a, s);
+        SB_CASE(1) SB_CASE(2) SB_CASE(3) SB_CASE(4) SB_CASE(5) SB_CASE(6) SB_CASE(7) SB_CASE(8)
+        SB_CASE(9) SB_CASE(10)
+#undef SB_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace sb

@@ -103,8 +103,10 @@ struct Proj4Args {
     int tile;
     double *partial;          // [pair][block][nbins^3 * 2]
     int nblocks;
+    int mfma;                 // 1: the matrix-core kernel (proj4_mfma.hip), 0: the vector kernel
 };
 hipError_t launch_proj4_contract(const Proj4Args &a, hipStream_t s);
+hipError_t launch_proj4_mfma(const Proj4Args &a, hipStream_t s);
 
 // ---- deterministic FP64 reduction of block partials: tot[g][v] = sum_blk partial[g][blk][v]
 hipError_t launch_block_sum(const double *partial, int ngroups, int nblocks, int nvals, double *tot,

@@ -372,8 +372,10 @@ def test_projected_small(sb):
     _, _, z4 = run_plan(sb, [d], edges, 4, npcf=4)
     pairs, ref4 = oracle.zeta4_proj(d.astype(np.float64), edges, 4)
     e4 = rel_err(z4[0], ref4)
-    say(f"  proj3 err={e3:.3e} proj4 err={e4:.3e}")
-    assert e3 < TOL32 and e4 < TOL32
+    _, _, z4v = run_plan(sb, [d], edges, 4, npcf=4, mfma=False)   # the vector-ALU contraction
+    e4v = rel_err(z4v[0], ref4)
+    say(f"  proj3 err={e3:.3e} proj4 err={e4:.3e} (matrix cores), {e4v:.3e} (vector ALU)")
+    assert e3 < TOL32 and e4 < TOL32 and e4v < TOL32
 
 
 # ------------------------------------------------------------------ full 4PCF
