@@ -46,28 +46,32 @@ struct PairSums {
     static_assert(NBT >= 1 && NBT <= 16, "at most 16 bins");
     static constexpr int red_doubles(int nw) { return nw * NPART * NPB * 16; }
     static constexpr int NV = NPART * NPB * 4;        // accumulator values per lane
-    static constexpr int NT2 = (NV + 1) / 2;          // float64 totals per lane (see tile)
+    static constexpr int NT2 = (NV + 1) / 2;          // float64 totals per lane (see flush)
     double tot[NT2];
+    f4v acc[NPART][NPB];                              // float32 sums since the last flush
 
-    __device__ __forceinline__ void zero() {
-#pragma unroll
-        for (int m = 0; m < NT2; ++m) tot[m] = 0.0;
-    }
-
-    // One tile of NCELL cells: the value of bin b at cell c is stage[off(c) + b * bstride] and
-    // its weight wsm[c].  The waves take groups of 8 cells in turn.
-    template <int NCELL, int NW, class Off>
-    __device__ __forceinline__ void tile(const float2 *stage, int bstride, const float *wsm, Off off, int wave,
-                                         int lane) {
-        constexpr int NG = (NCELL + CPG - 1) / CPG;
-        const int slot = lane >> 2, j = lane & 3;
-        const int cg = slot >> 1;
-        const bool im_slot = (slot & 1) != 0;
-        f4v acc[NPART][NPB];
+    __device__ __forceinline__ void clear_acc() {
 #pragma unroll
         for (int u = 0; u < NPART; ++u)
 #pragma unroll
             for (int p = 0; p < NPB; ++p) acc[u][p] = f4v{0.f, 0.f, 0.f, 0.f};
+    }
+
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int m = 0; m < NT2; ++m) tot[m] = 0.0;
+        clear_acc();
+    }
+
+    // Adds one tile of NCELL cells to the float32 sums: the value of bin b at cell c is
+    // stage[off(c) + b * bstride] and its weight wsm[c].  The waves take groups of 8 cells in turn.
+    template <int NCELL, int NW, class Off>
+    __device__ __forceinline__ void accumulate(const float2 *stage, int bstride, const float *wsm, Off off, int wave,
+                                               int lane) {
+        constexpr int NG = (NCELL + CPG - 1) / CPG;
+        const int slot = lane >> 2, j = lane & 3;
+        const int cg = slot >> 1;
+        const bool im_slot = (slot & 1) != 0;
 #pragma unroll 1
         for (int k = 0; k < (NG + NW - 1) / NW; ++k) {
             const int grp = wave + k * NW;
@@ -97,9 +101,13 @@ struct PairSums {
                 }
             }
         }
-        // The two slots of a cell (lanes l and l ^ 4) always end up in the same sum: fold them
-        // here so that each lane keeps half of the values (value 2 m on even-slot lanes, 2 m + 1
-        // on odd-slot lanes) in float64.
+    }
+
+    // Adds the float32 sums to the float64 totals and clears them.  The two slots of a cell
+    // (lanes l and l ^ 4) always end up in the same sum: they are folded here so that each lane
+    // keeps half of the values (value 2 m on even-slot lanes, 2 m + 1 on odd-slot lanes).
+    __device__ __forceinline__ void flush(int lane) {
+        const bool im_slot = ((lane >> 2) & 1) != 0;
         float flat[2 * NT2];
 #pragma unroll
         for (int u = 0; u < NPART; ++u)
@@ -114,6 +122,15 @@ struct PairSums {
             const float keep = im_slot ? flat[2 * m + 1] : flat[2 * m];
             tot[m] += (double)(keep + __shfl_xor(send, 4));
         }
+        clear_acc();
+    }
+
+    // One tile added and flushed.
+    template <int NCELL, int NW, class Off>
+    __device__ __forceinline__ void tile(const float2 *stage, int bstride, const float *wsm, Off off, int wave,
+                                         int lane) {
+        accumulate<NCELL, NW>(stage, bstride, wsm, off, wave, lane);
+        flush(lane);
     }
 
     // Sum the 8 cells of the slots (lanes 8 c + 4 s + j, fixed butterfly over c) and write this
@@ -216,37 +233,57 @@ __global__ __launch_bounds__(NBT * R * TPP) void last_contract_kernel(LastArgs a
             PairSums<NBT, IMAG>::block_value(red, NW, nb, v);
 }
 
-// Register-resident form for n = RX * RX (RX threads per row): a tile is one row of the
-// NBT (padded) bins of one (l, m).  Thread q of a pencil loads elements q + RX r (coalesced:
-// the RX threads of a pencil are adjacent lanes), runs the first radix-RX stage in
-// registers, exchanges through LDS (positions RX q + r written, q + RX r read), runs the
-// second stage and holds elements q + RX r of the transformed row, which it writes once to
-// the [cell][bin] tile read by the MFMA pair sums.  The exchange and the contraction tile
-// are separate LDS buffers, so a tile needs two barriers.
+// LDS region of one pencil in the register-resident last pass: it holds the pencil's exchange
+// rows and then its transformed row.  The size is 8 mod 16 float2, so the pair sums' reads of
+// 4 bins (regions) at 8 adjacent cells fall into distinct banks.
+constexpr int pencil_region(int exch, int n) {
+    int s = exch > n ? exch : n;
+    while (s % 16 != 8) ++s;
+    return s;
+}
+
+// Orders the LDS accesses of one wave around the call; a pencil's threads are lanes of one wave,
+// so its exchange needs no workgroup barrier.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Register-resident form for n = R1 * R2 (R2 threads per row): a tile is one row of the NBT
+// (padded) bins of one (l, m).  Thread q of a pencil loads elements q + R2 s (coalesced: the R2
+// threads of a pencil are adjacent lanes), runs the first radix-R1 stage in registers, exchanges
+// through its pencil's LDS region (row q of R1 values written, column q + R2 t read), runs the
+// second stage and writes the transformed row into the same region as [bin][cell], which the MFMA
+// pair sums read.  The exchange stays inside a wave; the workgroup meets at two barriers per tile
+// (regions written, regions read).  The second-stage twiddles come from an LDS table ordered so
+// that the threads of a pencil read adjacent entries, and the pair sums are flushed to float64
+// every FLUSH rows.
 template <int R1, int R2, int NBT, bool IMAG>
 __global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
     constexpr int N = R1 * R2;
     constexpr int T = R1 / R2;             // second-stage butterflies per thread
-    static_assert(R1 % R2 == 0, "R2 must divide R1");
+    static_assert(R1 % R2 == 0 && 64 % R2 == 0, "R2 divides R1 and the wave");
     constexpr int P = NBT;                 // pencils (bins) per tile
     constexpr int NT = P * R2;
     constexpr int NW = NT / 64;
     constexpr int NPART = IMAG ? 2 : 1;
-    constexpr int EXP = R2 * (R1 + 1);     // exchange float2 per pencil: R2 rows of R1, padded by one
-    constexpr int PITCH = P + 1;
+    constexpr int EXR = R1 + 1;            // exchange row pitch (R2 rows)
+    constexpr int REG = pencil_region(R2 * EXR, N);
     constexpr int WPT = (N + NT - 1) / NT;
     static_assert(NT % 64 == 0, "whole waves");
-    __shared__ float2 ex[P * EXP];
-    __shared__ float2 cs[N * PITCH];
+    constexpr int FLUSH = NBT * NPART <= 12 ? 4 : 1;   // larger accumulators would not stay in registers
+    __shared__ float2 lds[P * REG];
+    __shared__ float2 twl[N];              // [t][r][q]: w^{(q + R2 t) r}, w = e^{-2 pi i / N}
     __shared__ float wsm[N];
     const int nb = a.nb;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int q = tid % R2, pp = tid / R2;  // element column, pencil (= bin)
-    float2 tw[T][R2];                       // w^{(q + R2 t) r}, w = e^{-2 pi i / N}; the inverse takes the conjugate
-#pragma unroll
-    for (int t = 0; t < T; ++t)
-#pragma unroll
-        for (int r = 0; r < R2; ++r) tw[t][r] = a.tw[((q + R2 * t) * r) % N];
+    float2 *own = lds + pp * REG;
+    for (int i = tid; i < N; i += NT) {
+        const int t = i / (R2 * R2), r = i / R2 % R2, qq = i % R2;
+        twl[i] = a.tw[((qq + R2 * t) * r) % N];
+    }
     PairSums<NBT, IMAG> ps;
     ps.zero();
     const int64_t nrows = a.ng / N;
@@ -274,34 +311,44 @@ __global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
 #pragma unroll
         for (int e = 0; e < WPT; ++e) wv[e] = nw[e];
         if (row + 1 < r_end) load_row(row + 1, nx, nw);    // next row in flight
-        // first stage: radix-R1 butterfly q (elements q + R2 s) -> positions R1 q + r
+        // first stage: radix-R1 butterfly q (elements q + R2 s) -> row q of the exchange
         Dft<R1, 1>::run(v);
+        __syncthreads();                                    // the previous tile's pair sums are done
 #pragma unroll
-        for (int r = 0; r < R1; ++r) ex[pp * EXP + q * (R1 + 1) + r] = v[r];
-        __syncthreads();
-        // second stage: radix-R2 butterflies q + R2 t, positions q + R2 t + R1 r
+        for (int r = 0; r < R1; ++r) own[q * EXR + r] = v[r];
+        wave_lds_sync();
+        // second stage: radix-R2 butterflies q + R2 t over the rows, positions q + R2 t + R1 r
 #pragma unroll
         for (int t = 0; t < T; ++t) {
-            float2 u[R2];
+            float2 *u = v + t * R2;
 #pragma unroll
             for (int r = 0; r < R2; ++r) {
-                const float2 x = ex[pp * EXP + r * (R1 + 1) + q + R2 * t];
-                u[r] = r == 0 ? x : cmul(x, make_float2(tw[t][r].x, -tw[t][r].y));
+                const float2 x = own[r * EXR + q + R2 * t];
+                if (r == 0) {
+                    u[r] = x;
+                } else {
+                    const float2 w = twl[(t * R2 + r) * R2 + q];   // the inverse takes the conjugate
+                    u[r] = cmul(x, make_float2(w.x, -w.y));
+                }
             }
             Dft<R2, 1>::run(u);
-#pragma unroll
-            for (int r = 0; r < R2; ++r) cs[(q + R2 * t + R1 * r) * PITCH + pp] = u[r];
         }
+        wave_lds_sync();                                    // the pencil's exchange rows are read
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int r = 0; r < R2; ++r) own[q + R2 * t + R1 * r] = v[t * R2 + r];
 #pragma unroll
         for (int e = 0; e < WPT; ++e)
             if (tid + e * NT < N) wsm[tid + e * NT] = wv[e];
         __syncthreads();
-        ps.template tile<N, NW>(cs, 1, wsm, [](int c) { return c * PITCH; }, wave, lane);
+        ps.template accumulate<N, NW>(lds, REG, wsm, [](int c) { return c; }, wave, lane);
+        if ((row - r_begin) % FLUSH == FLUSH - 1 || row + 1 == r_end) ps.flush(lane);
     }
     // float64 combine over the waves in wave order (as in last_contract_kernel)
     __syncthreads();
-    static_assert(PairSums<NBT, IMAG>::red_doubles(NW) * sizeof(double) <= sizeof(cs), "block reduction fits");
-    double *red = reinterpret_cast<double *>(cs);   // [wave][part][quad pair][4 x 4]
+    static_assert(PairSums<NBT, IMAG>::red_doubles(NW) * sizeof(double) <= sizeof(lds), "block reduction fits");
+    double *red = reinterpret_cast<double *>(lds);   // [wave][part][quad pair][4 x 4]
     ps.to_lds(red, wave, lane);
     __syncthreads();
     const int nv = nb * (nb + 1) / 2 * NPART;
