@@ -195,36 +195,53 @@ __global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
     }
 }
 
+// Rows r of a register-resident axis-0 thread (elements q + r2 r, q < r2) that can meet the
+// compact kernel support |c_0| <= r0: r <= kr or r >= r1 - kr.  A dense axis returns r1.
+inline int support_rows(const Axis0Args &a, int r1, int r2) {
+    if (a.np >= a.n) return r1;
+    const int pos = a.r0 / r2;                                   // rows holding some j <= r0
+    const int first_neg = (a.n - a.r0 - (r2 - 1) + r2 - 1) / r2;   // first row holding some j >= n - r0
+    const int neg = r1 - first_neg;
+    return pos > neg ? pos : neg;
+}
+
 // Axis-0 correlation pass for n = R1 * R2 (R2 divides R1) held in registers: thread q < R2 of a
 // pencil owns rows q + R2 s (s < R1).  Those are the inputs of radix-R1 butterfly q of the first
 // Stockham stage, and the outputs of butterflies q + R2 t (t < R1 / R2) of the second
 // (radix R2), which read positions q + R2 t + R1 r'.  So the forward transform of the kernel
 // pencil, the product with the density spectrum and the inverse transform touch LDS only for
-// the two stage exchanges (positions R1 q + r written), with one barrier each (the exchanges
-// alternate between two buffers).  Loads and stores take P adjacent pencils of the contiguous
-// axes per row, as in the LDS-staged kernel.
-template <int R1, int R2, int P, int MODE>
-__global__ __launch_bounds__(P * R2) void axis0_reg_kernel(Axis0Args a) {
+// the two stage exchanges (positions R1 q + r written).  One exchange buffer with two barriers
+// per exchange keeps the workgroup at 34 KB of LDS, so four of them share a CU.  Loads and
+// stores take P adjacent pencils of the contiguous axes per row, as in the LDS-staged kernel.
+// A compact kernel is nonzero on rows r <= KR and r >= R1 - KR of each thread at most (KR from
+// the support radius, see support_rows; KR >= R1 / 2 for a dense axis): the other rows are
+// compile-time zeros, so they are neither loaded nor held, and the first forward stage folds
+// them away.
+template <int R1, int R2, int P, int MODE, int KR>
+__global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void axis0_reg_kernel(Axis0Args a) {
     constexpr int N = R1 * R2;
     constexpr int T = R1 / R2;   // second-stage butterflies per thread
     static_assert(R1 % R2 == 0, "R2 must divide R1");
     constexpr int PITCH = P + 1;
-    __shared__ float2 ex[2][N * PITCH];
+    __shared__ float2 ex[N * PITCH];
+    __shared__ float2 twl[N];    // [t][r][q]: second-stage twiddles w^{(q + R2 t) r}, w = e^{-2 pi i / N}
     const int tid = threadIdx.x;
     const int p = tid % P, q = tid / P;
     const int64_t g = (int64_t)blockIdx.x * P + p;
     const bool ok = g < a.plane;
-    // second-stage twiddles w^{(q + R2 t) r'}, w = e^{-2 pi i / N} (the inverse takes the conjugate)
-    float2 tw[T][R2];
-#pragma unroll
-    for (int t = 0; t < T; ++t)
-#pragma unroll
-        for (int r = 0; r < R2; ++r) tw[t][r] = a.tw[((q + R2 * t) * r) % N];
+    for (int i = tid; i < N; i += P * R2) {
+        const int t = i / (R2 * R2), r = i / R2 % R2, qq = i % R2;
+        twl[i] = a.tw[((qq + R2 * t) * r) % N];
+    }
     const int64_t kstride = (int64_t)a.np * a.plane;
     auto load_kernel = [&](int64_t k, float2 *dst) {
         const float2 *kc = a.kc + k * kstride;
 #pragma unroll
         for (int r = 0; r < R1; ++r) {
+            if (r > KR && r < R1 - KR) {
+                dst[r] = make_float2(0.f, 0.f);
+                continue;
+            }
             const int j = q + R2 * r;
             const int pl = (a.np == N || j <= a.r0) ? j : (j >= N - a.r0 ? a.np - (N - j) : -1);
             dst[r] = (ok && pl >= 0) ? ld_stream(&kc[(int64_t)pl * a.plane + g]) : make_float2(0.f, 0.f);
@@ -234,6 +251,7 @@ __global__ __launch_bounds__(P * R2) void axis0_reg_kernel(Axis0Args a) {
     auto transform = [&](float2 *v, float2 *buf, auto sign_c) {
         constexpr int SIGN = decltype(sign_c)::value;
         Dft<R1, SIGN>::run(v);
+        __syncthreads();                 // the previous exchange has been read
 #pragma unroll
         for (int r = 0; r < R1; ++r) buf[(R1 * q + r) * PITCH + p] = v[r];
         __syncthreads();
@@ -243,7 +261,8 @@ __global__ __launch_bounds__(P * R2) void axis0_reg_kernel(Axis0Args a) {
 #pragma unroll
             for (int r = 0; r < R2; ++r) {
                 const float2 x = buf[(q + R2 * t + R1 * r) * PITCH + p];
-                const float2 w = SIGN < 0 ? tw[t][r] : make_float2(tw[t][r].x, -tw[t][r].y);
+                const float2 tv = twl[(t * R2 + r) * R2 + q];     // the inverse takes the conjugate
+                const float2 w = SIGN < 0 ? tv : make_float2(tv.x, -tv.y);
                 u[r] = r == 0 ? x : cmul(x, w);
             }
             Dft<R2, SIGN>::run(u);
@@ -269,8 +288,8 @@ __global__ __launch_bounds__(P * R2) void axis0_reg_kernel(Axis0Args a) {
 #pragma unroll
             for (int r = 0; r < R1; ++r) { v[r] = nv[r]; k[r] = nx[r]; }
             if (b + 1 < a.nb) { load_v(b + 1, nv); load_kernel(a.kfirst + b + 1, nx); }
-            transform(v, ex[0], std::integral_constant<int, -1>{});
-            transform(k, ex[1], std::integral_constant<int, -1>{});
+            transform(v, ex, std::integral_constant<int, -1>{});
+            transform(k, ex, std::integral_constant<int, -1>{});
 #pragma unroll
             for (int r = 0; r < R1; ++r) acc[r] = cadd(acc[r], cmul(v[r], k[r]));
         }
@@ -292,10 +311,10 @@ __global__ __launch_bounds__(P * R2) void axis0_reg_kernel(Axis0Args a) {
 #pragma unroll
         for (int r = 0; r < R1; ++r) v[r] = nx[r];
         if (b + 1 < a.nb) load_kernel(kbase + b + 1, nx);   // in flight during the transforms
-        transform(v, ex[0], std::integral_constant<int, -1>{});
+        transform(v, ex, std::integral_constant<int, -1>{});
 #pragma unroll
         for (int r = 0; r < R1; ++r) v[r] = cmul(v[r], dr[r]);
-        transform(v, ex[1], std::integral_constant<int, 1>{});
+        transform(v, ex, std::integral_constant<int, 1>{});
         float2 *out = a.out + (kbase + b) * a.ng;
         if (ok)
 #pragma unroll
@@ -548,9 +567,19 @@ hipError_t launch_axis0(const Axis0Args &a, hipStream_t s) {
         dim3 grid((unsigned)((a.plane + P - 1) / P), (unsigned)a.groups);
         auto go = [&](auto mode_c) {
             constexpr int M = decltype(mode_c)::value;
-            if (a.n == 256) hipLaunchKernelGGL((axis0_reg_kernel<16, 16, P, M>), grid, dim3(16 * P), 0, s, a);
-            else if (a.n == 128) hipLaunchKernelGGL((axis0_reg_kernel<16, 8, P, M>), grid, dim3(8 * P), 0, s, a);
-            else hipLaunchKernelGGL((axis0_reg_kernel<8, 8, P, M>), grid, dim3(8 * P), 0, s, a);
+            if (a.n == 256) {
+                const int kr = support_rows(a, 16, 16);
+                if (kr <= 2) hipLaunchKernelGGL((axis0_reg_kernel<16, 16, P, M, 2>), grid, dim3(16 * P), 0, s, a);
+                else if (kr <= 3) hipLaunchKernelGGL((axis0_reg_kernel<16, 16, P, M, 3>), grid, dim3(16 * P), 0, s, a);
+                else hipLaunchKernelGGL((axis0_reg_kernel<16, 16, P, M, 16>), grid, dim3(16 * P), 0, s, a);
+            } else if (a.n == 128) {
+                const int kr = support_rows(a, 16, 8);
+                if (kr <= 3) hipLaunchKernelGGL((axis0_reg_kernel<16, 8, P, M, 3>), grid, dim3(8 * P), 0, s, a);
+                else if (kr <= 4) hipLaunchKernelGGL((axis0_reg_kernel<16, 8, P, M, 4>), grid, dim3(8 * P), 0, s, a);
+                else hipLaunchKernelGGL((axis0_reg_kernel<16, 8, P, M, 16>), grid, dim3(8 * P), 0, s, a);
+            } else {
+                hipLaunchKernelGGL((axis0_reg_kernel<8, 8, P, M, 8>), grid, dim3(8 * P), 0, s, a);
+            }
         };
         if (a.mode == 1) go(std::integral_constant<int, 1>{});
         else go(std::integral_constant<int, 0>{});
