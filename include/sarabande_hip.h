@@ -76,10 +76,15 @@ enum {
     SB_FLAG_NO_MFMA = 4u,     /* full 4PCF: use the plain float32 vector-ALU contraction even where
                                  the matrix-core one exists (lmax <= 4, nbins <= 8); projected
                                  4PCF: the vector-ALU contraction instead of the matrix cores */
-    SB_FLAG_ODD_PARITY = 8u   /* full 4PCF: the odd-parity Lambda (l1 + l2 + l3 odd, Sec. 2.3, the
+    SB_FLAG_ODD_PARITY = 8u,  /* full 4PCF: the odd-parity Lambda (l1 + l2 + l3 odd, Sec. 2.3, the
                                  ones Alg. 6 skips) instead of the even ones; each value is the
                                  imaginary part of the sum, whose real part vanishes for a real
                                  density */
+    SB_FLAG_NO_PACK = 16u     /* full 3PCF, fused path: one complex transform per (l, m) array.  By
+                                 default the real m = 0 coefficient fields a_{l0} (Alg. 5, eq. 7:
+                                 the m = 0 kernels are real) are carried two to a transform, as
+                                 real and imaginary part, which removes floor((lmax + 1) / 2) of
+                                 the (lmax + 1)(lmax + 2) / 2 arrays per bin */
 };
 
 /* Problem statement: the grid, bins, lmax, full or projected, 3 or 4 PCF

@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(_HERE, "libsarabande_hip.so")
 SB_OK, SB_EINVAL, SB_EUNSUPPORTED, SB_EWORKSPACE, SB_EHIP, SB_ENOMEM, SB_ESTATE = 0, -1, -2, -3, -4, -5, -6
 SB_PREC_FP32, SB_PREC_SPLIT_BF16 = 0, 1
 SB_IN_F32, SB_IN_F64 = 0, 1
-SB_FLAG_KEEP_COEFFS, SB_FLAG_UNFUSED, SB_FLAG_NO_MFMA, SB_FLAG_ODD_PARITY = 1, 2, 4, 8
+SB_FLAG_KEEP_COEFFS, SB_FLAG_UNFUSED, SB_FLAG_NO_MFMA, SB_FLAG_ODD_PARITY, SB_FLAG_NO_PACK = 1, 2, 4, 8, 16
 
 # Every function the header declares, with its ctypes signature.
 c_i32, c_i64, c_u32, c_dbl, c_vp, c_sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double,

@@ -45,13 +45,15 @@ class Plan:
     mfma       : full 4PCF: use the matrix-core contraction where it exists (l <= 4, <= 8 bins);
                  projected 4PCF: the matrix-core contraction (False = the vector-ALU kernel)
     parity     : full 4PCF: "even" (Alg. 6) or "odd" Lambda (the imaginary part of those sums)
+    pack       : full 3PCF, fused path: carry the real m = 0 coefficient fields two to a complex
+                 transform (False = one transform per (l, m))
     scratch_limit: bytes of kernel arrays a 3PCF plan keeps at once (default 48 GiB); above it
                  the passes run over chunks of (l, m) groups (sb_plan_set_scratch_limit)
     """
 
     def __init__(self, shapes, bin_edges, lmax, npcf=3, precision="fp32", input_dtype=torch.float32,
                  device=None, stream=None, prepare=True, keep_coeffs=False, fused=True, mfma=True,
-                 scratch_limit=None, parity="even"):
+                 scratch_limit=None, parity="even", pack=True):
         self.lib = _lib.load()
         shapes = [tuple(int(x) for x in s) for s in shapes]
         ndim = len(shapes[0])
@@ -69,7 +71,8 @@ class Plan:
                                _lib.SB_IN_F64 if input_dtype == torch.float64 else _lib.SB_IN_F32,
                                (_lib.SB_FLAG_KEEP_COEFFS if keep_coeffs else 0) | (0 if fused else _lib.SB_FLAG_UNFUSED)
                                | (0 if mfma else _lib.SB_FLAG_NO_MFMA)
-                               | (_lib.SB_FLAG_ODD_PARITY if parity == "odd" else 0))
+                               | (_lib.SB_FLAG_ODD_PARITY if parity == "odd" else 0)
+                               | (0 if pack else _lib.SB_FLAG_NO_PACK))
         if parity not in ("even", "odd"):
             raise ValueError("parity must be 'even' or 'odd'")
         self.parity = parity

@@ -128,7 +128,8 @@ __global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
         float2 dr[EPT];
 #pragma unroll
         for (int e = 0; e < EPT; ++e) dr[e] = ok ? a.dhat[(int64_t)(q0 + e * TPP) * a.plane + g] : make_float2(0.f, 0.f);
-        const int64_t kbase = (int64_t)blockIdx.y * a.nb;
+        const int64_t kbase = (int64_t)(a.kmap ? a.kmap[blockIdx.y] : blockIdx.y) * a.nb;   // kernel group
+        const int64_t obase = (int64_t)blockIdx.y * a.nb;                                 // output arrays
         load_kernel(kbase, nx);
         for (int b = 0; b < a.nb; ++b) {
             __syncthreads();
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
             }
             __syncthreads();
             stages<N, TPP, 1, 1, RAD...>(sm, tw, p, q0, PITCH);
-            float2 *out = a.out + (kbase + b) * a.ng;
+            float2 *out = a.out + (obase + b) * a.ng;
             if (ok)
 #pragma unroll
                 for (int e = 0; e < EPT; ++e) out[(int64_t)(q0 + e * TPP) * a.plane + g] = sm[(q0 + e * TPP) * PITCH + p];
@@ -304,7 +305,8 @@ __global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void
     float2 dr[R1];
 #pragma unroll
     for (int r = 0; r < R1; ++r) dr[r] = ok ? a.dhat[(int64_t)(q + R2 * r) * a.plane + g] : make_float2(0.f, 0.f);
-    const int64_t kbase = (int64_t)blockIdx.y * a.nb;
+    const int64_t kbase = (int64_t)(a.kmap ? a.kmap[blockIdx.y] : blockIdx.y) * a.nb;   // kernel group
+    const int64_t obase = (int64_t)blockIdx.y * a.nb;                                 // output arrays
     load_kernel(kbase, nx);
     for (int b = 0; b < a.nb; ++b) {
         float2 v[R1];
@@ -315,7 +317,7 @@ __global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void
 #pragma unroll
         for (int r = 0; r < R1; ++r) v[r] = cmul(v[r], dr[r]);
         transform(v, ex, std::integral_constant<int, 1>{});
-        float2 *out = a.out + (kbase + b) * a.ng;
+        float2 *out = a.out + (obase + b) * a.ng;
         if (ok)
 #pragma unroll
             for (int r = 0; r < R1; ++r) st_stream(&out[(int64_t)(q + R2 * r) * a.plane + g], v[r]);
@@ -384,7 +386,8 @@ __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
     float2 dr[R0];
 #pragma unroll
     for (int r = 0; r < R0; ++r) dr[r] = ok ? a.dhat[(int64_t)(q + T * r) * a.plane + g] : make_float2(0.f, 0.f);
-    const int64_t kbase = (int64_t)blockIdx.y * a.nb;
+    const int64_t kbase = (int64_t)(a.kmap ? a.kmap[blockIdx.y] : blockIdx.y) * a.nb;   // kernel group
+    const int64_t obase = (int64_t)blockIdx.y * a.nb;                                 // output arrays
     load_kernel(kbase, nx);
     __syncthreads();   // twiddle table
     for (int b = 0; b < a.nb; ++b) {
@@ -396,7 +399,7 @@ __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
 #pragma unroll
         for (int r = 0; r < R0; ++r) v[r] = cmul(v[r], dr[r]);
         reg_stages<N, 1, R0, REST...>(v, ex[0], ex[1], tw, q, p, PITCH);
-        float2 *out = a.out + (kbase + b) * a.ng;
+        float2 *out = a.out + (obase + b) * a.ng;
         if (ok)
 #pragma unroll
             for (int r = 0; r < R0; ++r) st_stream(&out[(int64_t)(q + T * r) * a.plane + g], v[r]);

@@ -34,25 +34,33 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 // of its slot once per group.  Lane 4 b + j supplies row j and column j of block b and holds
 // row r, column j of it in register r.  Each tile's float32 result is added to float64 totals
 // per lane; at the end the 16 slots are summed by a fixed butterfly over lanes and the waves
-// in wave order.  For the imaginary part of projected sums, Im(A^b1 conj A^b2) =
-// Im A^b1 Re A^b2 - Re A^b1 Im A^b2 takes the other part of the column value with the sign of
-// the slot's part.
-template <int NBT, bool IMAG>
+// in wave order.  Three modes:
+//   PS_REAL    Re(A^b1 conj A^b2): the real- and imaginary-part slots of a cell are summed.
+//   PS_COMPLEX also Im(A^b1 conj A^b2) = Im A^b1 Re A^b2 - Re A^b1 Im A^b2 (projected sums): a
+//              second set of instructions takes the other part of the column value with the
+//              sign of the slot's part.
+//   PS_PACKED  Re A^b1 Re A^b2 and Im A^b1 Im A^b2 kept apart, for arrays that carry two real
+//              coefficient fields as real and imaginary part.
+// The outputs are part-major: value v = part * npairs + pair.
+enum PairMode : int { PS_REAL = 0, PS_COMPLEX = 1, PS_PACKED = 2 };
+
+template <int NBT, int MODE>
 struct PairSums {
     static constexpr int Q = (NBT + 3) / 4;           // bin quads (bins >= NBT read as zero)
     static constexpr int NPB = Q * (Q + 1) / 2;       // quad pairs qa <= qb
-    static constexpr int NPART = IMAG ? 2 : 1;
+    static constexpr int NACC = MODE == PS_COMPLEX ? 2 : 1;   // accumulator sets
+    static constexpr int NOUT = MODE == PS_REAL ? 1 : 2;      // output parts
     static constexpr int CPG = 8;                     // cells per group
     static_assert(NBT >= 1 && NBT <= 16, "at most 16 bins");
-    static constexpr int red_doubles(int nw) { return nw * NPART * NPB * 16; }
-    static constexpr int NV = NPART * NPB * 4;        // accumulator values per lane
+    static constexpr int red_doubles(int nw) { return nw * NOUT * NPB * 16; }
+    static constexpr int NV = NACC * NPB * 4;         // accumulator values per lane
     static constexpr int NT2 = (NV + 1) / 2;          // float64 totals per lane (see flush)
     double tot[NT2];
-    f4v acc[NPART][NPB];                              // float32 sums since the last flush
+    f4v acc[NACC][NPB];                               // float32 sums since the last flush
 
     __device__ __forceinline__ void clear_acc() {
 #pragma unroll
-        for (int u = 0; u < NPART; ++u)
+        for (int u = 0; u < NACC; ++u)
 #pragma unroll
             for (int p = 0; p < NPB; ++p) acc[u][p] = f4v{0.f, 0.f, 0.f, 0.f};
     }
@@ -94,23 +102,27 @@ struct PairSums {
 #pragma unroll
                     for (int qb = qa; qb < Q; ++qb, ++p) {
                         acc[0][p] = __builtin_amdgcn_mfma_f32_4x4x1f32(aw, x[qb], acc[0][p], 0, 0, 0);
-                        if constexpr (IMAG)
-                            acc[NPART - 1][p] =
-                                __builtin_amdgcn_mfma_f32_4x4x1f32(im_slot ? aw : -aw, xo[qb], acc[NPART - 1][p], 0, 0, 0);
+                        if constexpr (MODE == PS_COMPLEX)
+                            acc[NACC - 1][p] =
+                                __builtin_amdgcn_mfma_f32_4x4x1f32(im_slot ? aw : -aw, xo[qb], acc[NACC - 1][p], 0, 0, 0);
                     }
                 }
             }
         }
     }
 
-    // Adds the float32 sums to the float64 totals and clears them.  The two slots of a cell
-    // (lanes l and l ^ 4) always end up in the same sum: they are folded here so that each lane
-    // keeps half of the values (value 2 m on even-slot lanes, 2 m + 1 on odd-slot lanes).
+    // Lane distance of the fold in flush: lanes l and l ^ FOLD always end up in the same sum
+    // (the two part slots of a cell, or for PS_PACKED two cells of the same part).
+    static constexpr int FOLD = MODE == PS_PACKED ? 8 : 4;
+
+    // Adds the float32 sums to the float64 totals and clears them.  The slots of lanes l and
+    // l ^ FOLD are folded here so that each lane keeps half of the values (value 2 m on lanes
+    // with the FOLD bit clear, 2 m + 1 on the others).
     __device__ __forceinline__ void flush(int lane) {
-        const bool im_slot = ((lane >> 2) & 1) != 0;
+        const bool odd = (lane & FOLD) != 0;
         float flat[2 * NT2];
 #pragma unroll
-        for (int u = 0; u < NPART; ++u)
+        for (int u = 0; u < NACC; ++u)
 #pragma unroll
             for (int p = 0; p < NPB; ++p)
 #pragma unroll
@@ -118,9 +130,9 @@ struct PairSums {
         if constexpr (NV % 2 != 0) flat[NV] = 0.f;
 #pragma unroll
         for (int m = 0; m < NT2; ++m) {
-            const float send = im_slot ? flat[2 * m] : flat[2 * m + 1];
-            const float keep = im_slot ? flat[2 * m + 1] : flat[2 * m];
-            tot[m] += (double)(keep + __shfl_xor(send, 4));
+            const float send = odd ? flat[2 * m] : flat[2 * m + 1];
+            const float keep = odd ? flat[2 * m + 1] : flat[2 * m];
+            tot[m] += (double)(keep + __shfl_xor(send, FOLD));
         }
         clear_acc();
     }
@@ -133,18 +145,26 @@ struct PairSums {
         flush(lane);
     }
 
-    // Sum the 8 cells of the slots (lanes 8 c + 4 s + j, fixed butterfly over c) and write this
-    // wave's totals to red[((wave * NPART + part) * NPB + p) * 16 + r * 4 + j]; call with the
-    // whole block.  Lanes 0..3 end with the values 2 m, lanes 4..7 with the values 2 m + 1.
+    // Sum the cells of the slots (lanes 8 c + 4 s + j, fixed butterfly over c) and write this
+    // wave's totals to red[((wave * NOUT + part) * NPB + p) * 16 + r * 4 + j]; call with the
+    // whole block.  PS_REAL, PS_COMPLEX: lanes 0..3 end with the values 2 m, lanes 4..7 with
+    // the values 2 m + 1 (flattened (part, pair, r)).  PS_PACKED: lanes 4 s + 8 h + j end with
+    // value 2 m + h of part s.
     __device__ __forceinline__ void to_lds(double *red, int wave, int lane) {
 #pragma unroll
         for (int m = 0; m < NT2; ++m) {
             double v = tot[m];
-            v += __shfl_xor(v, 8);
+            if constexpr (MODE != PS_PACKED) v += __shfl_xor(v, 8);
             v += __shfl_xor(v, 16);
             v += __shfl_xor(v, 32);
-            const int idx = 2 * m + ((lane >> 2) & 1);   // flattened (part, pair, r)
-            if (lane < 8 && idx < NV) red[(wave * NV + idx) * 4 + (lane & 3)] = v;
+            if constexpr (MODE == PS_PACKED) {
+                const int i = 2 * m + ((lane >> 3) & 1);                // (pair, r) within the part
+                const int idx = ((lane >> 2) & 1) * NV + i;
+                if (lane < 16 && i < NV) red[(wave * 2 * NV + idx) * 4 + (lane & 3)] = v;
+            } else {
+                const int idx = 2 * m + ((lane >> 2) & 1);   // flattened (part, pair, r)
+                if (lane < 8 && idx < NV) red[(wave * NV + idx) * 4 + (lane & 3)] = v;
+            }
         }
     }
 
@@ -158,16 +178,23 @@ struct PairSums {
         const int qa = b1 >> 2, qb = b2 >> 2;
         const int p = qa * Q - qa * (qa - 1) / 2 + (qb - qa);
         double sum = 0.0;
-        for (int w = 0; w < nw; ++w) sum += red[((w * NPART + part) * NPB + p) * 16 + (b1 & 3) * 4 + (b2 & 3)];
+        for (int w = 0; w < nw; ++w) sum += red[((w * NOUT + part) * NPB + p) * 16 + (b1 & 3) * 4 + (b2 & 3)];
         return sum;
     }
 };
 
-template <int N, int TPP, int NBT, int R, bool IMAG, int... RAD>
+// Row of the block partials for output value v (part-major, npn pairs per part) of grid row y:
+// the plan's row map gives the coefficient group of each (grid row, part) when present.
+__device__ __forceinline__ int64_t partial_row(const LastArgs &a, int y, int nv, int npn, int v) {
+    if (!a.rowmap) return (int64_t)y * nv + v;
+    return (int64_t)a.rowmap[2 * y + v / npn] * npn + v % npn;
+}
+
+template <int N, int TPP, int NBT, int R, int MODE, int... RAD>
 __global__ __launch_bounds__(NBT * R * TPP) void last_contract_kernel(LastArgs a) {
     constexpr int P = NBT * R, PITCH = P + 1, NT = P * TPP;
     constexpr int NW = NT / 64;       // waves
-    constexpr int NPART = IMAG ? 2 : 1;
+    constexpr int NOUT = PairSums<NBT, MODE>::NOUT;
     constexpr int EPT = N / TPP;      // tile elements loaded per thread
     static_assert(NT % 64 == 0, "whole waves");
     extern __shared__ float2 smem[];
@@ -177,7 +204,7 @@ __global__ __launch_bounds__(NBT * R * TPP) void last_contract_kernel(LastArgs a
     float *wsm = reinterpret_cast<float *>(tw + N);   // the tile's weights w(x), R N values
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
-    PairSums<NBT, IMAG> ps;
+    PairSums<NBT, MODE> ps;
     ps.zero();
     const int64_t nrows = a.ng / N;
     const int64_t r_begin = (int64_t)blockIdx.x * a.rows_per_block;
@@ -222,15 +249,15 @@ __global__ __launch_bounds__(NBT * R * TPP) void last_contract_kernel(LastArgs a
         ps.template tile<R * N, NW>(sm, R, wsm, [](int c) { return (c % N) * PITCH + c / N; }, wave, lane);
     }
     // float64 combine over the waves in wave order; partial[(g * nv + v) * nblocks + blk] with
-    // v = part * npairs + pair (b1 <= b2, b1 outer)
+    // v = part * npairs + pair (b1 <= b2, b1 outer), row from partial_row
     __syncthreads();
     double *red = reinterpret_cast<double *>(smem);   // [wave][part][quad pair][4 x 4]
     ps.to_lds(red, wave, lane);
     __syncthreads();
-    const int nv = nb * (nb + 1) / 2 * NPART;
+    const int nv = nb * (nb + 1) / 2 * NOUT;
     for (int v = tid; v < nv; v += NT)
-        a.partial[((int64_t)blockIdx.y * nv + v) * a.nblocks + blockIdx.x] =
-            PairSums<NBT, IMAG>::block_value(red, NW, nb, v);
+        a.partial[partial_row(a, blockIdx.y, nv, nv / NOUT, v) * a.nblocks + blockIdx.x] =
+            PairSums<NBT, MODE>::block_value(red, NW, nb, v);
 }
 
 // LDS region of one pencil in the register-resident last pass: it holds the pencil's exchange
@@ -259,7 +286,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // (regions written, regions read).  The second-stage twiddles come from an LDS table ordered so
 // that the threads of a pencil read adjacent entries, and the pair sums are flushed to float64
 // every FLUSH rows.
-template <int R1, int R2, int NBT, bool IMAG>
+template <int R1, int R2, int NBT, int MODE>
 __global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
     constexpr int N = R1 * R2;
     constexpr int T = R1 / R2;             // second-stage butterflies per thread
@@ -267,12 +294,12 @@ __global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
     constexpr int P = NBT;                 // pencils (bins) per tile
     constexpr int NT = P * R2;
     constexpr int NW = NT / 64;
-    constexpr int NPART = IMAG ? 2 : 1;
+    constexpr int NOUT = PairSums<NBT, MODE>::NOUT;
     constexpr int EXR = R1 + 1;            // exchange row pitch (R2 rows)
     constexpr int REG = pencil_region(R2 * EXR, N);
     constexpr int WPT = (N + NT - 1) / NT;
     static_assert(NT % 64 == 0, "whole waves");
-    constexpr int FLUSH = NBT * NPART <= 12 ? 4 : 1;   // larger accumulators would not stay in registers
+    constexpr int FLUSH = NBT * PairSums<NBT, MODE>::NACC <= 12 ? 4 : 1;   // larger accumulators would not stay in registers
     __shared__ float2 lds[P * REG];
     __shared__ float2 twl[N];              // [t][r][q]: w^{(q + R2 t) r}, w = e^{-2 pi i / N}
     __shared__ float wsm[N];
@@ -284,7 +311,7 @@ __global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
         const int t = i / (R2 * R2), r = i / R2 % R2, qq = i % R2;
         twl[i] = a.tw[((qq + R2 * t) * r) % N];
     }
-    PairSums<NBT, IMAG> ps;
+    PairSums<NBT, MODE> ps;
     ps.zero();
     const int64_t nrows = a.ng / N;
     const int64_t r_begin = (int64_t)blockIdx.x * a.rows_per_block;
@@ -347,14 +374,14 @@ __global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
     }
     // float64 combine over the waves in wave order (as in last_contract_kernel)
     __syncthreads();
-    static_assert(PairSums<NBT, IMAG>::red_doubles(NW) * sizeof(double) <= sizeof(lds), "block reduction fits");
+    static_assert(PairSums<NBT, MODE>::red_doubles(NW) * sizeof(double) <= sizeof(lds), "block reduction fits");
     double *red = reinterpret_cast<double *>(lds);   // [wave][part][quad pair][4 x 4]
     ps.to_lds(red, wave, lane);
     __syncthreads();
-    const int nv = nb * (nb + 1) / 2 * NPART;
+    const int nv = nb * (nb + 1) / 2 * NOUT;
     for (int vv = tid; vv < nv; vv += NT)
-        a.partial[((int64_t)blockIdx.y * nv + vv) * a.nblocks + blockIdx.x] =
-            PairSums<NBT, IMAG>::block_value(red, NW, nb, vv);
+        a.partial[partial_row(a, blockIdx.y, nv, nv / NOUT, vv) * a.nblocks + blockIdx.x] =
+            PairSums<NBT, MODE>::block_value(red, NW, nb, vv);
 }
 
 // bins padded to the instantiated tile widths 4, 8, 12, 16 so that NBT * t threads make whole
@@ -365,20 +392,27 @@ constexpr int reg_padded_bins(int nb, int t) {
     return 0;
 }
 
+// Pair-sum mode of a launch.
+inline int pair_mode(const LastArgs &a) { return a.want_imag ? PS_COMPLEX : (a.packed ? PS_PACKED : PS_REAL); }
+
 template <int R1, int R2>
 hipError_t launch_last_reg(const LastArgs &a, hipStream_t s) {
     if (a.rows != 1) return hipErrorInvalidValue;
     dim3 grid((unsigned)a.nblocks, (unsigned)a.groups);
-    const bool im = a.want_imag != 0;
+    const int mode = pair_mode(a);
     const int nbt = reg_padded_bins(a.nb, R2);
-#define SB_LR(NBT)                                                                                          \
-    case NBT:                                                                                                \
-        if constexpr ((NBT * R2) % 64 == 0) {                                                                \
-            if (im) hipLaunchKernelGGL((last_reg_kernel<R1, R2, NBT, true>), grid, dim3(NBT * R2), 0, s, a);   \
-            else hipLaunchKernelGGL((last_reg_kernel<R1, R2, NBT, false>), grid, dim3(NBT * R2), 0, s, a);     \
-            break;                                                                                           \
-        } else {                                                                                             \
-            return hipErrorInvalidValue;                                                                     \
+#define SB_LR(NBT)                                                                                                  \
+    case NBT:                                                                                                        \
+        if constexpr ((NBT * R2) % 64 == 0) {                                                                        \
+            if (mode == PS_COMPLEX)                                                                                  \
+                hipLaunchKernelGGL((last_reg_kernel<R1, R2, NBT, PS_COMPLEX>), grid, dim3(NBT * R2), 0, s, a);       \
+            else if (mode == PS_PACKED)                                                                              \
+                hipLaunchKernelGGL((last_reg_kernel<R1, R2, NBT, PS_PACKED>), grid, dim3(NBT * R2), 0, s, a);        \
+            else                                                                                                     \
+                hipLaunchKernelGGL((last_reg_kernel<R1, R2, NBT, PS_REAL>), grid, dim3(NBT * R2), 0, s, a);          \
+            break;                                                                                                   \
+        } else {                                                                                                     \
+            return hipErrorInvalidValue;                                                                             \
         }
     switch (nbt) {
         SB_LR(4) SB_LR(8) SB_LR(12) SB_LR(16)
@@ -393,13 +427,13 @@ hipError_t launch_last_reg(const LastArgs &a, hipStream_t s) {
 // pencil loads elements q + T s.  The stages exchange through two LDS buffers laid out
 // [position][bin]; the transformed row is written to the buffer the last stage did not read,
 // which is then the [cell][bin] tile of the MFMA pair sums.
-template <int N, int NBT, bool IMAG, int R0, int... REST>
+template <int N, int NBT, int MODE, int R0, int... REST>
 __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
     constexpr int T = N / R0;
     constexpr int P = NBT;
     constexpr int NT = P * T;
     constexpr int NW = NT / 64;
-    constexpr int NPART = IMAG ? 2 : 1;
+    constexpr int NOUT = PairSums<NBT, MODE>::NOUT;
     constexpr int PITCH = P + 1;
     constexpr int NSTAGE = 1 + sizeof...(REST);
     constexpr int CSB = (NSTAGE - 1) % 2;       // buffer the last stage does not read
@@ -412,7 +446,7 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int q = tid % T, pp = tid / T;        // element column, pencil (= bin)
     for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
-    PairSums<NBT, IMAG> ps;
+    PairSums<NBT, MODE> ps;
     ps.zero();
     const int64_t nrows = a.ng / N;
     const int64_t r_begin = (int64_t)blockIdx.x * a.rows_per_block;
@@ -452,14 +486,14 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
     }
     // float64 combine over the waves in wave order (as in last_contract_kernel)
     __syncthreads();
-    static_assert(PairSums<NBT, IMAG>::red_doubles(NW) * sizeof(double) <= sizeof(ex), "block reduction fits");
+    static_assert(PairSums<NBT, MODE>::red_doubles(NW) * sizeof(double) <= sizeof(ex), "block reduction fits");
     double *red = reinterpret_cast<double *>(&ex[0][0]);
     ps.to_lds(red, wave, lane);
     __syncthreads();
-    const int nv = nb * (nb + 1) / 2 * NPART;
+    const int nv = nb * (nb + 1) / 2 * NOUT;
     for (int vv = tid; vv < nv; vv += NT)
-        a.partial[((int64_t)blockIdx.y * nv + vv) * a.nblocks + blockIdx.x] =
-            PairSums<NBT, IMAG>::block_value(red, NW, nb, vv);
+        a.partial[partial_row(a, blockIdx.y, nv, nv / NOUT, vv) * a.nblocks + blockIdx.x] =
+            PairSums<NBT, MODE>::block_value(red, NW, nb, vv);
 }
 
 template <int N, int R0, int... REST>
@@ -467,16 +501,20 @@ hipError_t launch_last_rs(const LastArgs &a, hipStream_t s) {
     constexpr int T = N / R0;
     if (a.rows != 1) return hipErrorInvalidValue;
     dim3 grid((unsigned)a.nblocks, (unsigned)a.groups);
-    const bool im = a.want_imag != 0;
+    const int mode = pair_mode(a);
     const int nbt = reg_padded_bins(a.nb, T);
-#define SB_LR(NBT)                                                                                               \
-    case NBT:                                                                                                     \
-        if constexpr ((NBT * T) % 64 == 0 && NBT * T <= 1024) {                                                   \
-            if (im) hipLaunchKernelGGL((last_rs_kernel<N, NBT, true, R0, REST...>), grid, dim3(NBT * T), 0, s, a);  \
-            else hipLaunchKernelGGL((last_rs_kernel<N, NBT, false, R0, REST...>), grid, dim3(NBT * T), 0, s, a);    \
-            break;                                                                                                \
-        } else {                                                                                                  \
-            return hipErrorInvalidValue;                                                                          \
+#define SB_LR(NBT)                                                                                                   \
+    case NBT:                                                                                                         \
+        if constexpr ((NBT * T) % 64 == 0 && NBT * T <= 1024) {                                                       \
+            if (mode == PS_COMPLEX)                                                                                   \
+                hipLaunchKernelGGL((last_rs_kernel<N, NBT, PS_COMPLEX, R0, REST...>), grid, dim3(NBT * T), 0, s, a);  \
+            else if (mode == PS_PACKED)                                                                               \
+                hipLaunchKernelGGL((last_rs_kernel<N, NBT, PS_PACKED, R0, REST...>), grid, dim3(NBT * T), 0, s, a);   \
+            else                                                                                                      \
+                hipLaunchKernelGGL((last_rs_kernel<N, NBT, PS_REAL, R0, REST...>), grid, dim3(NBT * T), 0, s, a);     \
+            break;                                                                                                    \
+        } else {                                                                                                      \
+            return hipErrorInvalidValue;                                                                              \
         }
     switch (nbt) {
         SB_LR(4) SB_LR(8) SB_LR(12) SB_LR(16)
@@ -486,30 +524,38 @@ hipError_t launch_last_rs(const LastArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int N, int TPP, int NBT, bool IMAG, int... RAD>
+template <int N, int TPP, int NBT, int MODE, int... RAD>
 hipError_t launch_last_t(const LastArgs &a, hipStream_t s) {
     constexpr int R = fused_rows(N, TPP, NBT);
     constexpr int P = NBT * R, NT = P * TPP;
     if (a.rows != R) return hipErrorInvalidValue;
     const size_t tile = (size_t)(N * (P + 1) + N) * sizeof(float2) + (size_t)R * N * sizeof(float);
-    const size_t red = (size_t)PairSums<NBT, IMAG>::red_doubles(NT / 64) * sizeof(double);
+    const size_t red = (size_t)PairSums<NBT, MODE>::red_doubles(NT / 64) * sizeof(double);
     const size_t shm = tile > red ? tile : red;
     dim3 grid((unsigned)a.nblocks, (unsigned)a.groups);
-    hipLaunchKernelGGL((last_contract_kernel<N, TPP, NBT, R, IMAG, RAD...>), grid, dim3(NT), shm, s, a);
+    hipLaunchKernelGGL((last_contract_kernel<N, TPP, NBT, R, MODE, RAD...>), grid, dim3(NT), shm, s, a);
     return hipGetLastError();
 }
 
 constexpr int padded_bins(int nb) { return nb <= 4 ? 4 : nb <= 8 ? 8 : nb <= 10 ? 10 : nb <= 12 ? 12 : 16; }
 
+template <int N, int TPP, int NBT, int... RAD>
+hipError_t launch_last_m(const LastArgs &a, hipStream_t s) {
+    switch (pair_mode(a)) {
+        case PS_COMPLEX: return launch_last_t<N, TPP, NBT, PS_COMPLEX, RAD...>(a, s);
+        case PS_PACKED: return launch_last_t<N, TPP, NBT, PS_PACKED, RAD...>(a, s);
+        default: return launch_last_t<N, TPP, NBT, PS_REAL, RAD...>(a, s);
+    }
+}
+
 template <int N, int TPP, int... RAD>
 hipError_t launch_last_nb(const LastArgs &a, hipStream_t s) {
-    const bool im = a.want_imag != 0;
     switch (padded_bins(a.nb)) {
-        case 4: return im ? launch_last_t<N, TPP, 4, true, RAD...>(a, s) : launch_last_t<N, TPP, 4, false, RAD...>(a, s);
-        case 8: return im ? launch_last_t<N, TPP, 8, true, RAD...>(a, s) : launch_last_t<N, TPP, 8, false, RAD...>(a, s);
-        case 10: return im ? launch_last_t<N, TPP, 10, true, RAD...>(a, s) : launch_last_t<N, TPP, 10, false, RAD...>(a, s);
-        case 12: return im ? launch_last_t<N, TPP, 12, true, RAD...>(a, s) : launch_last_t<N, TPP, 12, false, RAD...>(a, s);
-        default: return im ? launch_last_t<N, TPP, 16, true, RAD...>(a, s) : launch_last_t<N, TPP, 16, false, RAD...>(a, s);
+        case 4: return launch_last_m<N, TPP, 4, RAD...>(a, s);
+        case 8: return launch_last_m<N, TPP, 8, RAD...>(a, s);
+        case 10: return launch_last_m<N, TPP, 10, RAD...>(a, s);
+        case 12: return launch_last_m<N, TPP, 12, RAD...>(a, s);
+        default: return launch_last_m<N, TPP, 16, RAD...>(a, s);
     }
 }
 

@@ -49,7 +49,7 @@ __global__ void kgen_kernel(KgenArgs a) {
     float2 *out = a.out;
     const int64_t ng = a.ng;
     if (bin < 0) {
-        for (int k = 0; k < a.nlm * nb; ++k) out[(int64_t)k * ng + cell] = make_float2(0.f, 0.f);
+        for (int k = 0; k < (a.nlm + a.npack) * nb; ++k) out[(int64_t)k * ng + cell] = make_float2(0.f, 0.f);
         return;
     }
     const double r = sqrt((double)s);
@@ -70,6 +70,7 @@ __global__ void kgen_kernel(KgenArgs a) {
     const double t = (double)c[2] / r;
     double pr = 1.0, pi = 0.0;   // ((x - i y)/r)^m
     double qmm = 1.0;            // Q_m^m
+    float k0[kMaxL + 1];         // the real m = 0 kernels, for the packed pairs
     for (int m = 0; m <= a.lmax; ++m) {
         double qlm2 = 0.0, qlm1 = qmm;  // Q_{l-2}, Q_{l-1} as l advances
         for (int l = m; l <= a.lmax; ++l) {
@@ -81,6 +82,7 @@ __global__ void kgen_kernel(KgenArgs a) {
             const int lm = l * (l + 1) / 2 + m;
             const double f = a.norm[lm] * q * sc;
             const float2 v = make_float2((float)(f * pr), (float)(f * pi));
+            if (m == 0) k0[l] = v.x;
             for (int b = 0; b < nb; ++b)
                 out[(int64_t)(lm * nb + b) * ng + cell] = (b == bin) ? v : make_float2(0.f, 0.f);
         }
@@ -89,6 +91,12 @@ __global__ void kgen_kernel(KgenArgs a) {
         const double nr = pr * ux + pi * uy;
         const double ni = pi * ux - pr * uy;
         pr = nr; pi = ni;
+    }
+    // packed pairs: K_{l_a 0} + i K_{l_b 0}, both real
+    for (int i = 0; i < a.npack; ++i) {
+        const float2 v = make_float2(k0[a.pack_l[2 * i]], k0[a.pack_l[2 * i + 1]]);
+        for (int b = 0; b < nb; ++b)
+            out[(int64_t)((a.nlm + i) * nb + b) * ng + cell] = (b == bin) ? v : make_float2(0.f, 0.f);
     }
 }
 

@@ -212,6 +212,34 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
     const int NB = prob->nbins;
     p->nlm = prob->ndim == 3 ? (prob->lmax + 1) * (prob->lmax + 2) / 2 : prob->lmax + 1;
     p->nk = p->nlm * NB;
+    // array groups of the fused 3D 3PCF forward path: the real m = 0 kernels go two to a
+    // complex transform (K_{l0} of eq. 7 is real), packed pairs first, then one (l, m) per group
+    {
+        bool pack = prob->ndim == 3 && prob->npcf == 3 && prob->lmax >= 1 &&
+                    (prob->flags & (SB_FLAG_UNFUSED | SB_FLAG_KEEP_COEFFS | SB_FLAG_NO_PACK)) == 0;
+        for (const auto &G : p->groups)
+            if (fused_last_rows((int)G.n[prob->ndim - 1], NB) <= 0) pack = false;
+        if (pack) {
+            p->npack = (prob->lmax + 1) / 2;
+            for (int i = 0; i < p->npack; ++i) {
+                const int la = 2 * i, lb = 2 * i + 1;
+                p->pack_l[2 * i] = la;
+                p->pack_l[2 * i + 1] = lb;
+                p->ag_kmap.push_back(p->nlm + i);
+                p->ag_rowmap.push_back(la * (la + 1) / 2);
+                p->ag_rowmap.push_back(lb * (lb + 1) / 2);
+            }
+            for (int l = 0; l <= prob->lmax; ++l)
+                for (int m = 0; m <= l; ++m) {
+                    if (m == 0 && l < 2 * p->npack) continue;   // in a packed pair
+                    const int lm = l * (l + 1) / 2 + m;
+                    p->ag_kmap.push_back(lm);
+                    p->ag_rowmap.push_back(lm);
+                    p->ag_rowmap.push_back(-1);
+                }
+            p->nag = (int)p->ag_kmap.size();
+        }
+    }
     // bin counts per group (host enumeration of the same integer test as the kernels)
     for (auto &G : p->groups) {
         for (int b = 0; b < NB; ++b) G.counts[b] = 0;
@@ -333,6 +361,11 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
         for (const auto &x : p->p4_canon) { pr.push_back(x.first); pr.push_back(x.second); }
         off_pairs = put(pr.data(), pr.size() * sizeof(int));
     }
+    size_t off_kmap = 0, off_rowmap = 0;
+    if (p->npack > 0) {
+        off_kmap = put(p->ag_kmap.data(), p->ag_kmap.size() * sizeof(int));
+        off_rowmap = put(p->ag_rowmap.data(), p->ag_rowmap.size() * sizeof(int));
+    }
     std::vector<int> gptr, gidx;
     std::vector<double> gcoef;
     build_gather(p, gptr, gidx, gcoef);
@@ -356,6 +389,10 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
         for (const Lam &C : p->f4.canon) p->quad_mfma &= quad_mfma_available(C.l[0], C.l[1], C.l[2], prob->nbins);
     }
     if (prob->npcf == 4 && prob->ndim == 2) p->d_pairs = reinterpret_cast<const int *>(base + off_pairs);
+    if (p->npack > 0) {
+        p->d_kmap = reinterpret_cast<const int *>(base + off_kmap);
+        p->d_rowmap = reinterpret_cast<const int *>(base + off_rowmap);
+    }
     p->d_gptr = reinterpret_cast<const int *>(base + off_gptr);
     p->d_gidx = reinterpret_cast<const int *>(base + off_gidx);
     p->d_gcoef = reinterpret_cast<const double *>(base + off_gcoef);
@@ -370,7 +407,7 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
         G.r0 = (int)std::min<int64_t>(r0, G.n[0]);
         G.np = support_planes(G.n[0], G.r0);
         G.khat_off = pers;
-        pers += align256((size_t)p->nk * G.np * G.plane * sizeof(float2));
+        pers += align256((size_t)p->kernel_groups() * NB * G.np * G.plane * sizeof(float2));
         // fused last pass: rows per tile fixed by the kernel's compile-time tile shape
         const int nl = (int)G.n[prob->ndim - 1];
         G.rows = NB <= kMaxBins ? fused_last_rows(nl, NB) : 0;
@@ -453,6 +490,8 @@ sb_status prepare(sb_plan *p, hipStream_t s) {
         for (int b = 0; b <= p->prob.nbins; ++b) a.thr[b] = p->thr[b];
         a.lmax = p->prob.lmax;
         a.nlm = p->nlm;
+        a.npack = p->npack;
+        for (int i = 0; i < 2 * p->npack; ++i) a.pack_l[i] = p->pack_l[i];
         if (nd == 3)
             for (int l = 0; l <= p->prob.lmax; ++l)
                 for (int m = 0; m <= l; ++m) a.norm[l * (l + 1) / 2 + m] = ylm_norm(l, m);
@@ -463,7 +502,8 @@ sb_status prepare(sb_plan *p, hipStream_t s) {
         // forward transform along every axis but 0 (axis 0 is redone per field in the first pass)
         const int64_t cn[3] = {G.np, G.n[1], G.n[2]};
         const int axes[2] = {1, 2};
-        const sb_status st = fft_axes(p, cn, nd, ncell, axes, nd - 1, -1, LOAD_C, kc, ncell, kc, ncell, p->nk, s);
+        const sb_status st = fft_axes(p, cn, nd, ncell, axes, nd - 1, -1, LOAD_C, kc, ncell, kc, ncell,
+                                      p->kernel_groups() * p->prob.nbins, s);
         if (st != SB_OK) return st;
     }
     p->prepared = true;
@@ -471,8 +511,9 @@ sb_status prepare(sb_plan *p, hipStream_t s) {
 }
 
 // First inverse pass: axis-0 correlation of every kernel group with the density spectrum.
+// kmap (optional): kernel group of each of the ngr output groups, else groups g0 .. g0 + ngr - 1.
 static sb_status axis0_corr(sb_plan *p, const ShapeGroup &G, const float2 *dhat, float2 *out, int g0, int ngr,
-                            hipStream_t s) {
+                            hipStream_t s, const int *kmap = nullptr) {
     const int NB = p->prob.nbins;
     Axis0Args a{};
     a.n = (int)G.n[0];
@@ -482,7 +523,8 @@ static sb_status axis0_corr(sb_plan *p, const ShapeGroup &G, const float2 *dhat,
     a.r0 = G.r0;
     a.mode = 0;
     a.dhat = dhat;
-    a.kc = reinterpret_cast<const float2 *>(p->persist + G.khat_off) + (int64_t)g0 * NB * G.np * G.plane;
+    a.kc = reinterpret_cast<const float2 *>(p->persist + G.khat_off) + (kmap ? 0 : (int64_t)g0 * NB * G.np * G.plane);
+    a.kmap = kmap;
     a.out = out;
     a.nb = NB;
     a.groups = ngr;
@@ -541,32 +583,49 @@ static sb_status fused_3pcf(sb_plan *p, int f, const void *delta, double *zeta_f
     const int nblocks = (int)((nrows + G.rows_per_block - 1) / G.rows_per_block);
     const int nv = NB * (NB + 1) / 2 * (nd == 2 ? 2 : 1);
     hipError_t e = hipSuccess;
-    for (int g0 = 0; g0 < p->nlm; g0 += p->chunk_groups) {
-        const int ngr = std::min(p->chunk_groups, p->nlm - g0);
-        st = axis0_corr(p, G, dhat, coef, g0, ngr, s);
+    // array groups: (l, m) groups, or with packing the packed m = 0 pairs and then the rest
+    const bool packing = p->npack > 0;
+    const int nag = packing ? p->nag : p->nlm;
+    for (int g0 = 0; g0 < nag; g0 += p->chunk_groups) {
+        const int ngr = std::min(p->chunk_groups, nag - g0);
+        st = axis0_corr(p, G, dhat, coef, g0, ngr, s, packing ? p->d_kmap + g0 : nullptr);
         if (st != SB_OK) return st;
         if (nd == 3) {
             const int axes[1] = {1};
             st = fft_axes(p, G.n, nd, G.ng, axes, 1, +1, LOAD_C, coef, G.ng, coef, G.ng, ngr * NB, s);
             if (st != SB_OK) return st;
         }
-        LastArgs a{};
-        a.n = (int)G.n[nd - 1];
-        a.ng = G.ng;
-        a.in = coef;
-        a.w = w;
-        a.nb = NB;
-        a.groups = ngr;
-        a.rows = G.rows;
-        a.rows_per_block = G.rows_per_block;
-        a.nblocks = nblocks;
-        a.want_imag = nd == 2;
-        a.partial = part + (int64_t)g0 * nv * nblocks;
-        a.tw = p->tw.at(a.n);
-        const double bytes = (double)ngr * NB * 8.0 * G.ng + (double)ngr * 4.0 * G.ng;
-        const double flops = (double)G.ng * ngr * (2.0 * NB + NB * (NB + 1) / 2.0 * (nd == 2 ? 8.0 : 4.0));
-        e = p->timed_launch(STAGE_CONTRACT, K_LAST, s, [&]() { return launch_last_contract(a, s); }, a.n, 1, ngr * NB,
-                            bytes, flops);
+        // last pass over array groups [gs, gs + cnt) of this chunk (all packed or none)
+        auto last = [&](int gs, int cnt, bool packed) -> hipError_t {
+            LastArgs a{};
+            a.n = (int)G.n[nd - 1];
+            a.ng = G.ng;
+            a.in = coef + (int64_t)(gs - g0) * NB * G.ng;
+            a.w = w;
+            a.nb = NB;
+            a.groups = cnt;
+            a.rows = G.rows;
+            a.rows_per_block = G.rows_per_block;
+            a.nblocks = nblocks;
+            a.want_imag = nd == 2;
+            a.packed = packed;
+            // with packing the row map places each part's partials at its (l, m) row
+            a.rowmap = packing ? p->d_rowmap + 2 * gs : nullptr;
+            a.partial = packing ? part : part + (int64_t)gs * nv * nblocks;
+            a.tw = p->tw.at(a.n);
+            const double bytes = (double)cnt * NB * 8.0 * G.ng + (double)cnt * 4.0 * G.ng;
+            const double flops = (double)G.ng * cnt * (2.0 * NB + NB * (NB + 1) / 2.0 * (nd == 2 ? 8.0 : 4.0));
+            return p->timed_launch(STAGE_CONTRACT, K_LAST, s, [&]() { return launch_last_contract(a, s); }, a.n, 1,
+                                   cnt * NB, bytes, flops);
+        };
+        if (packing) {
+            const int pe = std::min(g0 + ngr, p->npack);
+            if (pe > g0) e = last(g0, pe - g0, true);
+            const int us = std::max(g0, p->npack);
+            if (e == hipSuccess && g0 + ngr > us) e = last(us, g0 + ngr - us, false);
+        } else {
+            e = last(g0, ngr, false);
+        }
         if (e != hipSuccess) return hip_fail(e, "fused last pass");
     }
     e = launch_block_sum(part, p->nlm, nblocks, nv, tot, s);

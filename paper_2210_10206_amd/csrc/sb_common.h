@@ -80,6 +80,8 @@ struct Axis0Args {
     int nb;               // kernels per group (mode 0: per grid.y; mode 1: in this launch)
     int groups;           // grid.y (mode 0: kernel groups; mode 1: 1)
     int kfirst;           // mode 1: index of the first kernel of this launch
+    const int *kmap;      // mode 0, optional: kernel group of grid row y (kc is then the
+                          // whole kernel store; without it grid row y reads group y of kc)
     const float2 *tw;
 };
 hipError_t launch_axis0(const Axis0Args &a, hipStream_t s);
@@ -96,7 +98,12 @@ struct LastArgs {
     int64_t rows_per_block;
     int nblocks;
     int want_imag;
-    double *partial;      // [group][value][block], value = b1 <= b2 pair (then imaginary parts)
+    int packed;           // each array carries two real coefficient fields (real and imaginary
+                          // part): their pair sums are kept apart (value = part * npairs + pair)
+    double *partial;      // [row][block]; row = group * nvalues + value, value = b1 <= b2 pair
+                          // (then imaginary parts or the second packed field)
+    const int *rowmap;    // optional: 2 per grid row, the group row of part 0 and part 1
+                          // (row = rowmap[2 y + part] * npairs + pair)
     const float2 *tw;
 };
 hipError_t launch_last_contract(const LastArgs &a, hipStream_t s);

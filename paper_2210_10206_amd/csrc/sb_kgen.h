@@ -9,6 +9,7 @@ constexpr int kMaxBins = 16;
 constexpr int kMaxL = 10;                                   // 3D lmax
 constexpr int kMaxM = 16;                                   // 2D mmax
 constexpr int kMaxLM = (kMaxL + 1) * (kMaxL + 2) / 2;       // (l, m >= 0) pairs at lmax 10
+constexpr int kMaxPack = (kMaxL + 1) / 2;                   // pairs of real m = 0 kernels
 
 struct KgenArgs {
     int ndim;
@@ -21,7 +22,9 @@ struct KgenArgs {
     int nlm;                     // kernels per bin: (lmax+1)(lmax+2)/2 in 3D, mmax+1 in 2D
     double norm[kMaxLM];         // N_lm = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!), index l(l+1)/2 + m
     float scale;                 // 1 / N_g
-    float2 *out;                 // nlm * nbins arrays of ng cells, array k = lm * nbins + b
+    int npack;                   // 3D: packed m = 0 pairs written after the nlm groups
+    int pack_l[2 * kMaxPack];    // (l_a, l_b) of each pair: K_{l_a 0} + i K_{l_b 0}
+    float2 *out;                 // (nlm + npack) * nbins arrays of ng cells, array k = group * nbins + b
 };
 // Axis-0 planes kept for a kernel support of radius r0 (|c_0| <= r0) on an axis of n cells.
 inline int support_planes(int64_t n, int64_t r0) { return (int)((2 * r0 + 1 >= n) ? n : 2 * r0 + 1); }

@@ -212,6 +212,26 @@ def test_chunked_kernel_groups_match_whole(sb):
     chunked.close()
 
 
+@pytest.mark.parametrize("shape,nbins,lmax", [((32, 32, 32), 4, 1), ((8, 16, 256), 10, 6), ((8, 16, 256), 3, 5),
+                                              ((12, 8, 96), 8, 4), ((16, 16, 64), 16, 2)])
+def test_packed_m0_arrays(sb, shape, nbins, lmax):
+    # the default fused 3D 3PCF carries the real m = 0 coefficient fields two to a transform;
+    # every last-pass family (LDS-staged, register-resident 256, radix-list 96) against the
+    # oracle and against the plan with one transform per (l, m)
+    say(f"case: {shape} full 3PCF, {nbins} bins to 8, lmax {lmax}: packed m = 0 pairs vs one per (l, m)")
+    d = lognormal_field(shape, seed=50 + lmax, sigma=1.0)
+    edges = linear_edges(8, nbins)
+    plan, dev, z = run_plan(sb, [d], edges, lmax)
+    plan0, _, z0 = run_plan(sb, [d], edges, lmax, pack=False)
+    assert plan.persistent_bytes > plan0.persistent_bytes   # the packed kernels are stored besides
+    ref = oracle.zeta3_full(d.astype(np.float64), edges, lmax).real
+    err, err0, diff = rel_err(z[0], ref), rel_err(z0[0], ref), rel_err(z[0], z0[0])
+    say(f"  packed err={err:.3e}  unpacked err={err0:.3e}  packed vs unpacked {diff:.3e}")
+    assert err < TOL32 and err0 < TOL32
+    plan.close()
+    plan0.close()
+
+
 @pytest.mark.parametrize("shape", [(8, 64, 16), (8, 128, 16), (8, 256, 16)])
 def test_every_fft_variant(sb, shape):
     # every launch shape of the passes of each axis (what the autotuner may pick) gives the
