@@ -54,14 +54,15 @@ TRAFFIC_SRCS = {0: ["paper_2210_10206_amd/csrc/fft.hip", "paper_2210_10206_amd/c
                 3: ["paper_2210_10206_amd/csrc/contract.hip"]}
 
 
-def write_traffic(counter_dir, n=256, copy_mib=1024, min_gib=4.0):
+def write_traffic(counter_dir, n=256, copy_mib=1024, min_gib=1.0):
     """Turn two rocprofv3 counter runs of `bench.py --steps 1 --copy-probe-mib <copy_mib>`
     (counter_dir/FETCH_SIZE and counter_dir/WRITE_SIZE, csv output) into
     profiles/traffic.json.  Each counter is scaled by bytes / counter of the plain
     copy_mib MiB device copy in the same run (the __amd_rocclr_copyBuffer dispatches of that
     size); the passes over all kernel arrays are the dispatches of each kernel family with at
     least min_gib GiB of either counter, and of the middle pass only the variant the run
-    launched most often (the one the autotuner picked and the timed steps used)."""
+    launched most often (the one the autotuner picked and the timed steps used).  The last
+    pass is two launches per field (packed m = 0 pairs, other groups): their bytes are summed."""
     import csv
     import re
     reg = {256: 16}.get(n)   # lengths with the register-resident forms (n = r * r)
@@ -97,11 +98,16 @@ def write_traffic(counter_dir, n=256, copy_mib=1024, min_gib=4.0):
             per_name.setdefault(name, []).append((fv, wv))
         if not per_name:
             continue
-        name = max(per_name, key=lambda q: len(per_name[q]))
-        v = per_name[name]
-        fetch = sum(x[0] for x in v) / len(v) * 1024 * scale["FETCH_SIZE"]
-        write = sum(x[1] for x in v) / len(v) * 1024 * scale["WRITE_SIZE"]
-        out[f"kernel{k}_n{n}"] = {"kernel": name, "dispatches": len(v), "fetch_bytes": round(fetch),
+        # one pass over a field's arrays: the most frequent dispatch (the axis-0 and middle
+        # passes), or for the last pass every dispatch name launched that often (the packed
+        # m = 0 pairs and the other groups are two launches per field), summed
+        nmax = max(len(v) for v in per_name.values())
+        names = [q for q in per_name if len(per_name[q]) == nmax]
+        if k != 2:
+            names = [max(names)]
+        fetch = sum(sum(x[0] for x in per_name[q]) / nmax for q in names) * 1024 * scale["FETCH_SIZE"]
+        write = sum(sum(x[1] for x in per_name[q]) / nmax for q in names) * 1024 * scale["WRITE_SIZE"]
+        out[f"kernel{k}_n{n}"] = {"kernel": " + ".join(names), "dispatches": nmax, "fetch_bytes": round(fetch),
                                   "write_bytes": round(write), "bytes_per_launch": round(fetch + write),
                                   "source_hash": source_hash(TRAFFIC_SRCS[k])}
     with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
@@ -446,7 +452,7 @@ def main():
                 f"variant chosen by sb_autotune)",
              1: (f"axis0_reg_kernel<16,16,...>" if n == 256 else f"axis0_kernel<{n},...>")
                 + " (axis-0 pass: kernel-spectrum regeneration + product + inverse transform)",
-             2: (f"last_reg_kernel<16,16,{(nbins + 3) // 4 * 4},PS_PACKED|PS_REAL>" if n == 256
+             2: (f"last_reg_kernel<16,16,{(nbins + 3) // 4 * 4},PS_PACKED+PS_REAL>" if n == 256
                  else f"last_contract_kernel<{n},...>")
                 + " (last inverse pass fused with the MFMA pair sums; two launches per field: the packed "
                   "m = 0 pairs, then the rest)",

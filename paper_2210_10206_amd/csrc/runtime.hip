@@ -90,7 +90,8 @@ sb_status sb_autotune(sb_plan *p, void *stream) {
                 ps.in = coef;
                 ps.out = coef;
                 ps.in_bs = ps.out_bs = G.ng;
-                ps.batch = p->chunk_groups * p->prob.nbins;   // the arrays the scratch holds at once
+                // the arrays a forward pass transforms at once (fewer with packed m = 0 pairs)
+                ps.batch = (p->npack > 0 ? std::min(p->chunk_groups, p->nag) : p->chunk_groups) * p->prob.nbins;
                 ps.tw = p->tw.at(n);
                 ps.variant = v;
                 float tot = 0.f;
