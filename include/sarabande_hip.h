@@ -81,7 +81,7 @@ enum {
                                  imaginary part of the sum, whose real part vanishes for a real
                                  density */
     SB_FLAG_NO_PACK = 16u     /* full 3PCF, fused path: one complex transform per (l, m) array.  By
-                                 default the real m = 0 coefficient fields a_{l0} (Alg. 5, eq. 7:
+                                 default the real m = 0 coefficient fields a_{l0} (Alg. 5; eq. almconv:
                                  the m = 0 kernels are real) are carried two to a transform, as
                                  real and imaginary part, which removes floor((lmax + 1) / 2) of
                                  the (lmax + 1)(lmax + 2) / 2 arrays per bin */
@@ -118,12 +118,13 @@ sb_status sb_plan_create(const sb_problem *prob, int32_t batch, const int64_t *s
 void sb_plan_destroy(sb_plan *plan);
 
 /* Device bytes the caller must provide: `persistent` holds the kernel spectra of every
- * distinct shape (kept between calls), `scratch` the per-field working arrays. */
+ * distinct shape (kept between calls; for a fused 3D 3PCF plan also the packed m = 0 pairs,
+ * see SB_FLAG_NO_PACK), `scratch` the per-field working arrays. */
 sb_status sb_plan_workspace(const sb_plan *plan, size_t *persistent_bytes, size_t *scratch_bytes);
 
 /* Cap the scratch a 3PCF plan uses for its kernel arrays (default 48 GiB).  When all
  * N_k = nbins (lmax+1)(lmax+2)/2 arrays of the largest field would exceed `bytes`, sb_forward
- * (fused path) and sb_backward run the three passes over chunks of (l, m) groups, so that
+ * (fused path) and sb_backward run the three passes over chunks of kernel groups, so that
  * grids such as 512^3 fit next to their kernel cache.  Call between sb_plan_create and
  * sb_plan_bind (SB_ESTATE afterwards); sb_plan_workspace then reports the new scratch size.
  * Plans that need every array at once (4PCFs, SB_FLAG_KEEP_COEFFS) ignore the cap;

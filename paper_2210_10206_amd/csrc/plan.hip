@@ -213,7 +213,7 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
     p->nlm = prob->ndim == 3 ? (prob->lmax + 1) * (prob->lmax + 2) / 2 : prob->lmax + 1;
     p->nk = p->nlm * NB;
     // array groups of the fused 3D 3PCF forward path: the real m = 0 kernels go two to a
-    // complex transform (K_{l0} of eq. 7 is real), packed pairs first, then one (l, m) per group
+    // complex transform (the kernel Y*_{l0} Phi_b of eq. almconv is real), packed pairs first, then one (l, m) per group
     {
         bool pack = prob->ndim == 3 && prob->npcf == 3 && prob->lmax >= 1 &&
                     (prob->flags & (SB_FLAG_UNFUSED | SB_FLAG_KEEP_COEFFS | SB_FLAG_NO_PACK)) == 0;
