@@ -12,6 +12,11 @@
 //              out^b(flip(row), k) = V^b(row, (n - k) mod n).
 // This replaces a write and a read of the coefficient arrays, of v and of the first forward
 // pass of v, per (l, m) group.
+//
+// A packed group carries two real m = 0 fields as a^b = a^b_{l_a 0} + i a^b_{l_b 0}.  Its h takes
+// G_{l_a} on the real parts and G_{l_b} on the imaginary parts (PACK: a second matrix, gz2):
+// h = G_{l_a} Re a - i G_{l_b} Im a.  D and v keep their form (w_m = 1), and since the packed
+// kernel is K_{l_a 0} + i K_{l_b 0}, 2 Re of its accumulation adds both fields' terms.
 #pragma once
 #include "fft_core.h"
 
@@ -25,6 +30,7 @@ struct AdjLastArgs {
     const float2 *in;       // NB arrays of the group, transformed along every axis but the last
     const float *w;         // density
     const double *gz;       // g_l (NB x NB)
+    const double *gz2;      // packed groups: g_{l_b} for the imaginary parts (null: gz for both)
     float wm;               // 1 for m = 0, 2 for m > 0
     int nb;
     int64_t rows_per_block; // rows walked by one workgroup
@@ -38,21 +44,29 @@ hipError_t launch_adj_last(const AdjLastArgs &a, hipStream_t s);
 namespace adjlast {
 using namespace fftcore;
 
-template <int N, int TPP, int NBT, int R, int... RAD>
+// G (and, for PACK, the second matrix at G + NBT * NBT) into LDS: NBT x NBT, zero beyond nb.
+template <int NBT, bool PACK>
+__device__ __forceinline__ void load_weights(float *G, const AdjLastArgs &a, int tid, int nt) {
+    const int nb = a.nb;
+    for (int i = tid; i < (PACK ? 2 : 1) * NBT * NBT; i += nt) {
+        const int k = i / (NBT * NBT), b1 = i % (NBT * NBT) / NBT, b2 = i % NBT;
+        const double *g = k ? a.gz2 : a.gz;
+        G[i] = (b1 < nb && b2 < nb) ? (float)(0.5 * (g[b1 * nb + b2] + g[b2 * nb + b1])) : 0.f;
+    }
+}
+
+template <int N, int TPP, int NBT, int R, bool PACK, int... RAD>
 __global__ __launch_bounds__(NBT * R * TPP) void adj_last_kernel(AdjLastArgs a) {
     constexpr int P = NBT * R, PITCH = P + 1, NT = P * TPP;
     constexpr int EPT = N / TPP;
     extern __shared__ float2 smem[];
     float2 *sm = smem;
     float2 *tw = smem + N * PITCH;
-    float *G = reinterpret_cast<float *>(tw + N);   // NBT x NBT, zero beyond nb
+    float *G = reinterpret_cast<float *>(tw + N);   // (PACK ? 2 : 1) x NBT x NBT
     const int nb = a.nb;
     const int tid = threadIdx.x;
     for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
-    for (int i = tid; i < NBT * NBT; i += NT) {
-        const int b1 = i / NBT, b2 = i % NBT;
-        G[i] = (b1 < nb && b2 < nb) ? (float)(0.5 * (a.gz[b1 * nb + b2] + a.gz[b2 * nb + b1])) : 0.f;
-    }
+    load_weights<NBT, PACK>(G, a, tid, NT);
     const int64_t nrows = a.ng / N;
     const int64_t r_begin = (int64_t)blockIdx.x * a.rows_per_block;
     const int64_t r_end = min(r_begin + a.rows_per_block, nrows);
@@ -122,8 +136,9 @@ __global__ __launch_bounds__(NBT * R * TPP) void adj_last_kernel(AdjLastArgs a) 
 #pragma unroll
                 for (int b2 = 0; b2 < NBT; ++b2) {
                     const float g = G[b1 * NBT + b2];
+                    const float g2 = PACK ? G[NBT * NBT + b1 * NBT + b2] : g;
                     hx = __builtin_fmaf(g, av[b2].x, hx);
-                    hy = __builtin_fmaf(-g, av[b2].y, hy);   // conj(a)
+                    hy = __builtin_fmaf(-g2, av[b2].y, hy);   // conj(a)
                 }
                 d = __builtin_fmaf(av[b1].x, hx, d);
                 d = __builtin_fmaf(-av[b1].y, hy, d);
@@ -150,7 +165,7 @@ __global__ __launch_bounds__(NBT * R * TPP) void adj_last_kernel(AdjLastArgs a) 
 // N / R0 of pencil pp (= bin) holds elements q + T s of it, so the loads, both transforms and
 // the stores stay in registers and LDS is used for the stage exchanges and for the [cell][bin]
 // view of the per-cell phase.
-template <int N, int NBT, int R0, int... REST>
+template <int N, int NBT, bool PACK, int R0, int... REST>
 __global__ __launch_bounds__(NBT * (N / R0)) void adj_rs_kernel(AdjLastArgs a) {
     constexpr int T = N / R0;
     constexpr int P = NBT, PITCH = P + 1, NT = P * T;
@@ -160,15 +175,12 @@ __global__ __launch_bounds__(NBT * (N / R0)) void adj_rs_kernel(AdjLastArgs a) {
     static_assert(NSTAGE >= 2, "two stages or more");
     __shared__ float2 ex[2][N * PITCH];
     __shared__ float2 tw[N];
-    __shared__ float G[NBT * NBT];               // NBT x NBT, zero beyond nb
+    __shared__ float G[(PACK ? 2 : 1) * NBT * NBT];   // NBT x NBT (each), zero beyond nb
     const int nb = a.nb;
     const int tid = threadIdx.x;
     const int q = tid % T, pp = tid / T;         // element column, pencil (= bin)
     for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
-    for (int i = tid; i < NBT * NBT; i += NT) {
-        const int b1 = i / NBT, b2 = i % NBT;
-        G[i] = (b1 < nb && b2 < nb) ? (float)(0.5 * (a.gz[b1 * nb + b2] + a.gz[b2 * nb + b1])) : 0.f;
-    }
+    load_weights<NBT, PACK>(G, a, tid, NT);
     const int64_t nrows = a.ng / N;
     const int64_t r_begin = (int64_t)blockIdx.x * a.rows_per_block;
     const int64_t r_end = min(r_begin + a.rows_per_block, nrows);
@@ -225,8 +237,9 @@ __global__ __launch_bounds__(NBT * (N / R0)) void adj_rs_kernel(AdjLastArgs a) {
 #pragma unroll
                 for (int b2 = 0; b2 < NBT; ++b2) {
                     const float g = G[b1 * NBT + b2];
+                    const float g2 = PACK ? G[NBT * NBT + b1 * NBT + b2] : g;
                     hx = __builtin_fmaf(g, av[b2].x, hx);
-                    hy = __builtin_fmaf(-g, av[b2].y, hy);   // conj(a)
+                    hy = __builtin_fmaf(-g2, av[b2].y, hy);   // conj(a)
                 }
                 d = __builtin_fmaf(av[b1].x, hx, d);
                 d = __builtin_fmaf(-av[b1].y, hy, d);
@@ -266,7 +279,8 @@ hipError_t launch_rs(const AdjLastArgs &a, hipStream_t s) {
 #define SB_AR(NBT)                                                                               \
     case NBT:                                                                                    \
         if constexpr ((NBT * T) % 64 == 0 && NBT * T <= 1024) {                                  \
-            hipLaunchKernelGGL((adj_rs_kernel<N, NBT, R0, REST...>), grid, dim3(NBT * T), 0, s, a); \
+            if (a.gz2) hipLaunchKernelGGL((adj_rs_kernel<N, NBT, true, R0, REST...>), grid, dim3(NBT * T), 0, s, a);  \
+            else hipLaunchKernelGGL((adj_rs_kernel<N, NBT, false, R0, REST...>), grid, dim3(NBT * T), 0, s, a); \
             return hipGetLastError();                                                            \
         } else {                                                                                 \
             return hipErrorInvalidValue;                                                         \
@@ -284,22 +298,28 @@ constexpr int tile_rows(int tpp, int nbt) {
     return r;
 }
 
-template <int N, int TPP, int NBT, int... RAD>
-hipError_t launch_t(const AdjLastArgs &a, hipStream_t s) {
+template <int N, int TPP, int NBT, bool PACK, int... RAD>
+hipError_t launch_tp(const AdjLastArgs &a, hipStream_t s) {
     constexpr int R = tile_rows(TPP, NBT);
     constexpr int P = NBT * R, NT = P * TPP;
     static_assert(NT <= 1024, "workgroup size");
-    const size_t shm = (size_t)(N * (P + 1) + N) * sizeof(float2) + (size_t)NBT * NBT * sizeof(float);
+    const size_t shm = (size_t)(N * (P + 1) + N) * sizeof(float2) + (size_t)(PACK ? 2 : 1) * NBT * NBT * sizeof(float);
     if (shm > 160 * 1024) return hipErrorInvalidValue;
     if (shm > 64 * 1024) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&adj_last_kernel<N, TPP, NBT, R, RAD...>),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        const hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&adj_last_kernel<N, TPP, NBT, R, PACK, RAD...>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
     }
     const int64_t nrows = a.ng / N;
     dim3 grid((unsigned)((nrows + a.rows_per_block - 1) / a.rows_per_block));
-    hipLaunchKernelGGL((adj_last_kernel<N, TPP, NBT, R, RAD...>), grid, dim3(NT), shm, s, a);
+    hipLaunchKernelGGL((adj_last_kernel<N, TPP, NBT, R, PACK, RAD...>), grid, dim3(NT), shm, s, a);
     return hipGetLastError();
+}
+
+template <int N, int TPP, int NBT, int... RAD>
+hipError_t launch_t(const AdjLastArgs &a, hipStream_t s) {
+    return a.gz2 ? launch_tp<N, TPP, NBT, true, RAD...>(a, s) : launch_tp<N, TPP, NBT, false, RAD...>(a, s);
 }
 
 template <int N, int TPP, int... RAD>

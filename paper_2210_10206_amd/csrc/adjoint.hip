@@ -126,86 +126,100 @@ sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "adjoint zero");
         const double *gz_f = grad_zeta + (int64_t)f * p->zeta_doubles;
-        int g0 = 0, gend = 0;   // kernel groups whose coefficients are in scratch
-        for (int l = 0; l <= p->prob.lmax; ++l)
-            for (int m = 0; m <= l; ++m) {
-                const int lm = l * (l + 1) / 2 + m;
-                if (lm >= gend) {   // recompute a for the next chunk of groups (never stored across calls)
-                    g0 = lm;
-                    gend = std::min(p->nlm, lm + p->chunk_groups);
-                    // a stops before the last axis: the fused pass below finishes it
-                    st = coefficients(p, f, g0, gend - g0, s, !p->adj_fused);
-                    if (st != SB_OK) return st;
-                }
-                if (p->adj_fused) {
-                    // last inverse pass + h, D and v + forward transform of v(-x) along the last axis
-                    AdjLastArgs a{};
-                    a.n = (int)G.n[2];
-                    a.ndim = 3;
-                    for (int d = 0; d < 3; ++d) a.shape[d] = G.n[d];
-                    a.ng = G.ng;
-                    a.in = coef + (int64_t)(lm - g0) * NB * G.ng;
-                    a.w = w;
-                    a.gz = gz_f + (int64_t)l * NB * NB;
-                    a.wm = m == 0 ? 1.f : 2.f;
-                    a.nb = NB;
-                    const int64_t nrows = G.ng / a.n;
-                    // about 4096 workgroups (the small grids need them all to fill the chip),
-                    // at most 16 rows each
-                    a.rows_per_block = std::max<int64_t>(1, std::min<int64_t>(16, nrows / 4096));
-                    a.first = lm == 0;
-                    a.dsum = dsum;
-                    a.out = vtmp;
-                    a.tw = p->tw.at(a.n);
-                    e = p->timed_launch(STAGE_OTHER, K_ADJPREP, s, [&]() { return launch_adj_last(a, s); }, a.n, 0, NB,
-                                        16.0 * NB * G.ng + 8.0 * G.ng);
-                    if (e != hipSuccess) return hip_fail(e, "adjoint fused last pass");
-                    const int axes[1] = {1};
-                    st = fft_axes(p, G.n, 3, G.ng, axes, 1, -1, LOAD_C, vtmp, G.ng, vtmp, G.ng, NB, s);
-                    if (st != SB_OK) return st;
-                } else {
-                    AdjPrepArgs a{};
-                    a.coef = coef + (int64_t)(lm - g0) * NB * G.ng;
-                    a.w = w;
-                    a.gz = gz_f + (int64_t)l * NB * NB;
-                    a.nbins = NB;
-                    a.wm = m == 0 ? 1.f : 2.f;
-                    a.ndim = 3;
-                    for (int d = 0; d < 3; ++d) a.n[d] = G.n[d];
-                    a.ng = G.ng;
-                    a.vtmp = vtmp;
-                    a.dsum = dsum;
-                    a.first = lm == 0;
-                    e = p->timed_launch(STAGE_OTHER, K_ADJPREP, s, [&]() {
-                        hipLaunchKernelGGL(adj_prep_kernel, dim3(nblk), dim3(nt), 0, s, a);
-                        return hipGetLastError();
-                    });
-                    if (e != hipSuccess) return hip_fail(e, "adjoint prep");
-                    // transform v_b(-.) along axes 2..1 in place
-                    const int axes[2] = {2, 1};
-                    st = fft_axes(p, G.n, 3, G.ng, axes, 2, -1, LOAD_C, vtmp, G.ng, vtmp, G.ng, NB, s);
-                    if (st != SB_OK) return st;
-                }
-                // acc += sum_b FFT(w_m v_b(-.)) * Khat_b: the axis-0 pass regenerates each kernel
-                // spectrum and accumulates
-                Axis0Args x{};
-                x.n = (int)G.n[0];
-                x.plane = G.plane;
-                x.ng = G.ng;
-                x.np = G.np;
-                x.r0 = G.r0;
-                x.mode = 1;
-                x.kc = khat;
-                x.out = acc;
-                x.vin = vtmp;
-                x.nb = NB;
-                x.groups = 1;
-                x.kfirst = lm * NB;
-                x.tw = p->tw.at(x.n);
-                e = p->timed_launch(STAGE_FFT, K_AXIS0, s, [&]() { return launch_axis0(x, s); }, x.n, -1, NB,
-                                    (double)NB * (8.0 * G.ng + 8.0 * G.np * G.plane) + 16.0 * G.ng);
-                if (e != hipSuccess) return hip_fail(e, "adjoint axis-0 pass");
+        // groups: one per (l, m), or with the fused pass of a packed plan the forward's array
+        // groups (the packed m = 0 pairs first)
+        const bool packing = p->npack > 0 && p->adj_fused;
+        const int ngrp = packing ? p->nag : p->nlm;
+        auto l_of = [](int lm, int *m) {
+            int l = 0;
+            while ((l + 1) * (l + 2) / 2 <= lm) ++l;
+            *m = lm - l * (l + 1) / 2;
+            return l;
+        };
+        int g0 = 0, gend = 0;   // groups whose coefficients are in scratch
+        for (int g = 0; g < ngrp; ++g) {
+            // (l, m) of group g; a packed group also has l2 (m = 0)
+            int m = 0, m2 = 0, l2 = -1;
+            const int l = l_of(packing ? p->ag_rowmap[2 * g] : g, &m);
+            if (packing && p->ag_rowmap[2 * g + 1] >= 0) l2 = l_of(p->ag_rowmap[2 * g + 1], &m2);
+            const int kgroup = packing ? p->ag_kmap[g] : g;
+            if (g >= gend) {   // recompute a for the next chunk of groups (never stored across calls)
+                g0 = g;
+                gend = std::min(ngrp, g + p->chunk_groups);
+                // a stops before the last axis: the fused pass below finishes it
+                st = coefficients(p, f, g0, gend - g0, s, !p->adj_fused, packing ? p->d_kmap + g0 : nullptr);
+                if (st != SB_OK) return st;
             }
+            if (p->adj_fused) {
+                // last inverse pass + h, D and v + forward transform of v(-x) along the last axis
+                AdjLastArgs a{};
+                a.n = (int)G.n[2];
+                a.ndim = 3;
+                for (int d = 0; d < 3; ++d) a.shape[d] = G.n[d];
+                a.ng = G.ng;
+                a.in = coef + (int64_t)(g - g0) * NB * G.ng;
+                a.w = w;
+                a.gz = gz_f + (int64_t)l * NB * NB;
+                a.gz2 = l2 >= 0 ? gz_f + (int64_t)l2 * NB * NB : nullptr;
+                a.wm = m == 0 ? 1.f : 2.f;
+                a.nb = NB;
+                const int64_t nrows = G.ng / a.n;
+                // about 4096 workgroups (the small grids need them all to fill the chip),
+                // at most 16 rows each
+                a.rows_per_block = std::max<int64_t>(1, std::min<int64_t>(16, nrows / 4096));
+                a.first = g == 0;
+                a.dsum = dsum;
+                a.out = vtmp;
+                a.tw = p->tw.at(a.n);
+                e = p->timed_launch(STAGE_OTHER, K_ADJPREP, s, [&]() { return launch_adj_last(a, s); }, a.n, 0, NB,
+                                    16.0 * NB * G.ng + 8.0 * G.ng);
+                if (e != hipSuccess) return hip_fail(e, "adjoint fused last pass");
+                const int axes[1] = {1};
+                st = fft_axes(p, G.n, 3, G.ng, axes, 1, -1, LOAD_C, vtmp, G.ng, vtmp, G.ng, NB, s);
+                if (st != SB_OK) return st;
+            } else {
+                AdjPrepArgs a{};
+                a.coef = coef + (int64_t)(g - g0) * NB * G.ng;
+                a.w = w;
+                a.gz = gz_f + (int64_t)l * NB * NB;
+                a.nbins = NB;
+                a.wm = m == 0 ? 1.f : 2.f;
+                a.ndim = 3;
+                for (int d = 0; d < 3; ++d) a.n[d] = G.n[d];
+                a.ng = G.ng;
+                a.vtmp = vtmp;
+                a.dsum = dsum;
+                a.first = g == 0;
+                e = p->timed_launch(STAGE_OTHER, K_ADJPREP, s, [&]() {
+                    hipLaunchKernelGGL(adj_prep_kernel, dim3(nblk), dim3(nt), 0, s, a);
+                    return hipGetLastError();
+                });
+                if (e != hipSuccess) return hip_fail(e, "adjoint prep");
+                // transform v_b(-.) along axes 2..1 in place
+                const int axes[2] = {2, 1};
+                st = fft_axes(p, G.n, 3, G.ng, axes, 2, -1, LOAD_C, vtmp, G.ng, vtmp, G.ng, NB, s);
+                if (st != SB_OK) return st;
+            }
+            // acc += sum_b FFT(w_m v_b(-.)) * Khat_b: the axis-0 pass regenerates each kernel
+            // spectrum and accumulates
+            Axis0Args x{};
+            x.n = (int)G.n[0];
+            x.plane = G.plane;
+            x.ng = G.ng;
+            x.np = G.np;
+            x.r0 = G.r0;
+            x.mode = 1;
+            x.kc = khat;
+            x.out = acc;
+            x.vin = vtmp;
+            x.nb = NB;
+            x.groups = 1;
+            x.kfirst = kgroup * NB;
+            x.tw = p->tw.at(x.n);
+            e = p->timed_launch(STAGE_FFT, K_AXIS0, s, [&]() { return launch_axis0(x, s); }, x.n, -1, NB,
+                                (double)NB * (8.0 * G.ng + 8.0 * G.np * G.plane) + 16.0 * G.ng);
+            if (e != hipSuccess) return hip_fail(e, "adjoint axis-0 pass");
+        }
         st = fft_all_axes(p, G, +1, LOAD_C, acc, 0, acc, 0, 1, s);
         if (st != SB_OK) return st;
         hipLaunchKernelGGL(adj_finish_kernel, dim3(nblk), dim3(nt), 0, s, acc, dsum, 3, G.n[0], G.n[1], G.n[2], G.ng,

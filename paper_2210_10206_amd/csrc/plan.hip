@@ -548,11 +548,11 @@ sb_status density_spectrum(sb_plan *p, const ShapeGroup &G, const void *delta, h
 
 // Coefficients of kernel groups [g0, g0 + ngr) of one field into scratch (Alg. 3 / Alg. 4
 // as a correlation); the density spectrum is already in scratch.
-sb_status coefficients(sb_plan *p, int f, int g0, int ngr, hipStream_t s, bool last_axis) {
+sb_status coefficients(sb_plan *p, int f, int g0, int ngr, hipStream_t s, bool last_axis, const int *kmap) {
     const ShapeGroup &G = p->groups[p->field_group[f]];
     float2 *dhat = reinterpret_cast<float2 *>(p->scratch + p->off_dhat);
     float2 *coef = reinterpret_cast<float2 *>(p->scratch + p->off_coef);
-    sb_status st = axis0_corr(p, G, dhat, coef, g0, ngr, s);
+    sb_status st = axis0_corr(p, G, dhat, coef, g0, ngr, s, kmap);
     if (st != SB_OK) return st;
     const int axes[2] = {1, 2};
     const int naxes = p->prob.ndim - 1 - (last_axis ? 0 : 1);

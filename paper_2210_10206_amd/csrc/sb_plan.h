@@ -158,8 +158,10 @@ sb_status forward(sb_plan *p, const void *const *delta, double *zeta, hipStream_
 sb_status density_spectrum(sb_plan *p, const sb::ShapeGroup &G, const void *delta, hipStream_t s);
 // Coefficients of kernel groups [g0, g0 + ng) of field f into scratch (group g0 first); the
 // density spectrum must be in scratch already.  last_axis = false stops before the inverse
-// transform along the last axis.
-sb_status coefficients(sb_plan *p, int f, int g0, int ngroups, hipStream_t s, bool last_axis = true);
+// transform along the last axis.  kmap (device, optional): the kernel group of each of the ng
+// output groups (array groups of a packed plan) instead of g0 .. g0 + ng - 1.
+sb_status coefficients(sb_plan *p, int f, int g0, int ngroups, hipStream_t s, bool last_axis = true,
+                       const int *kmap = nullptr);
 void layout_scratch(sb_plan *p);
 sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s);
 // FFT passes over the listed axes (in order) of arrays with extents n[0..ndim) and ncell

@@ -228,6 +228,15 @@ def test_packed_m0_arrays(sb, shape, nbins, lmax):
     err, err0, diff = rel_err(z[0], ref), rel_err(z0[0], ref), rel_err(z[0], z0[0])
     say(f"  packed err={err:.3e}  unpacked err={err0:.3e}  packed vs unpacked {diff:.3e}")
     assert err < TOL32 and err0 < TOL32
+    # the adjoint runs the same array groups: its gradient against the one-per-(l, m) adjoint
+    G = torch.from_numpy(np.random.Generator(np.random.PCG64(60 + lmax)).standard_normal(
+        (1, lmax + 1, nbins, nbins))).cuda()
+    g1 = plan.backward(dev, G)[0].cpu().numpy()
+    g0 = plan0.backward(dev, G)[0].cpu().numpy()
+    torch.cuda.synchronize()
+    gdiff = rel_err(g1, g0)
+    say(f"  adjoint packed vs unpacked {gdiff:.3e}")
+    assert gdiff < TOL32
     plan.close()
     plan0.close()
 
