@@ -474,6 +474,83 @@ __global__ __launch_bounds__(NT) void fft_pass_pf_kernel(FftPass a, int tiles) {
     }
 }
 
+// Register-resident pass along a strided axis for n = R1 * R2 (R2 divides R1): P adjacent
+// pencils of the faster axes per tile, thread q < R2 of a pencil owns elements q + R2 s (the
+// inputs of first-stage butterfly q and the outputs of second-stage butterflies q + R2 t), so
+// loads and stores are coalesced over the P pencils and LDS holds only the one exchange between
+// the two radix stages.  A workgroup walks `tiles` consecutive tiles with the next one's loads
+// in flight.
+template <int R1, int R2, int P, int SIGN>
+__global__ __launch_bounds__(P * R2, 3) void mid_reg_kernel(FftPass a, int tiles) {
+    constexpr int N = R1 * R2;
+    constexpr int T = R1 / R2;   // second-stage butterflies per thread
+    static_assert(R1 % R2 == 0, "R2 must divide R1");
+    constexpr int PITCH = P + 1;
+    __shared__ float2 ex[N * PITCH];
+    __shared__ float2 twl[N];    // [t][r][q]: second-stage twiddles w^{(q + R2 t) r}, w = e^{-2 pi i / N}
+    const int tid = threadIdx.x;
+    const int p = tid % P, q = tid / P;
+    for (int i = tid; i < N; i += P * R2) {
+        const int t = i / (R2 * R2), r = i / R2 % R2, qq = i % R2;
+        twl[i] = a.tw[((qq + R2 * t) * r) % N];
+    }
+    const int64_t npencil = a.ng / N;
+    const int64_t ntile = (npencil + P - 1) / P;
+    const float2 *in = reinterpret_cast<const float2 *>(a.in) + blockIdx.y * a.in_bs;
+    float2 *out = a.out + blockIdx.y * a.out_bs;
+    auto base = [&](int64_t g) -> int64_t { return (g / a.stride) * (int64_t)N * a.stride + (g % a.stride); };
+    const int64_t t0 = (int64_t)blockIdx.x * tiles;
+    const int64_t t1 = min(t0 + tiles, ntile);
+    float2 nx[R1];
+    auto load = [&](int64_t t) {
+        const int64_t g = t * P + p;
+        const int64_t b = base(g);
+#pragma unroll
+        for (int r = 0; r < R1; ++r)
+            nx[r] = g < npencil ? ld_stream(&in[b + (int64_t)(q + R2 * r) * a.stride]) : make_float2(0.f, 0.f);
+    };
+    if (t0 < t1) load(t0);
+    for (int64_t t = t0; t < t1; ++t) {
+        float2 v[R1];
+#pragma unroll
+        for (int r = 0; r < R1; ++r) v[r] = nx[r];
+        if (t + 1 < t1) load(t + 1);   // in flight during the transform
+        Dft<R1, SIGN>::run(v);
+        __syncthreads();                 // the previous tile's exchange has been read
+#pragma unroll
+        for (int r = 0; r < R1; ++r) ex[(R1 * q + r) * PITCH + p] = v[r];
+        __syncthreads();
+        const int64_t g = t * P + p;
+        const int64_t b = base(g);
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) {
+            float2 u[R2];
+#pragma unroll
+            for (int r = 0; r < R2; ++r) {
+                const float2 x = ex[(q + R2 * tt + R1 * r) * PITCH + p];
+                const float2 tv = twl[(tt * R2 + r) * R2 + q];   // the inverse takes the conjugate
+                const float2 w = SIGN < 0 ? tv : make_float2(tv.x, -tv.y);
+                u[r] = r == 0 ? x : cmul(x, w);
+            }
+            Dft<R2, SIGN>::run(u);
+            if (g < npencil)
+#pragma unroll
+                for (int r = 0; r < R2; ++r) st_stream(&out[b + (int64_t)(q + R2 * tt + R1 * r) * a.stride], u[r]);
+        }
+    }
+}
+
+template <int R1, int R2>
+hipError_t launch_mid_reg(const FftPass &a, hipStream_t s, int tiles) {
+    constexpr int P = 16;
+    constexpr int N = R1 * R2;
+    const int64_t ntile = (a.ng / N + P - 1) / P;
+    dim3 grid((unsigned)((ntile + tiles - 1) / tiles), (unsigned)a.batch);
+    if (a.sign < 0) hipLaunchKernelGGL((mid_reg_kernel<R1, R2, P, -1>), grid, dim3(P * R2), 0, s, a, tiles);
+    else hipLaunchKernelGGL((mid_reg_kernel<R1, R2, P, 1>), grid, dim3(P * R2), 0, s, a, tiles);
+    return hipGetLastError();
+}
+
 template <int N, int TPP, int NT, int... RAD>
 hipError_t launch_pf(const FftPass &a, hipStream_t s, int tiles) {
     constexpr int P = NT / TPP;
@@ -504,10 +581,18 @@ hipError_t launch(const FftPass &a, hipStream_t s) {
 // The variants are the autotuner's candidates.
 hipError_t launch_fft_pass(const FftPass &a, hipStream_t s) {
     const int v = a.variant;
+    // variants 6 and 7 (lengths 64, 128, 256 along a strided axis whose stride is a multiple of
+    // 16): register-resident, 4 / 16 tiles; elsewhere they run as variants 4 and 5
+    if (v >= 6 && a.load == LOAD_C && a.store == STORE_C && a.stride > 1 && a.stride % 16 == 0) {
+        const int tiles = v == 6 ? 4 : 16;
+        if (a.n == 256) return launch_mid_reg<16, 16>(a, s, tiles);
+        if (a.n == 128) return launch_mid_reg<16, 8>(a, s, tiles);
+        if (a.n == 64) return launch_mid_reg<8, 8>(a, s, tiles);
+    }
     // variants 4 and 5: persistent with few, wide radix stages (64: 8 x 8, 96: 12 x 4 x 2,
     // 128: 16 x 8, 160: 20 x 4 x 2, 192: 12 x 4 x 4, 256: 16 x 16), 4 / 16 tiles
     if (v >= 4 && a.load == LOAD_C && a.store == STORE_C) {
-        const int tiles = v == 4 ? 4 : 16;
+        const int tiles = v % 2 == 0 ? 4 : 16;
         if (a.n == 256) return launch_pf<256, 16, 256, 16, 16>(a, s, tiles);
         if (a.n == 128) return launch_pf<128, 8, 256, 16, 8>(a, s, tiles);
         if (a.n == 64) return launch_pf<64, 8, 256, 8, 8>(a, s, tiles);
@@ -624,8 +709,10 @@ bool fft_supported(int n) {
 
 int fft_num_variants(int n) {
     // 0, 1: one tile per workgroup (two shapes where defined); 2, 3: persistent, 4 / 16 tiles;
-    // 4, 5 (lengths 64, 128, 256): persistent with two register-sized radix stages
-    return (n == 256 || n == 128 || n == 64 || n == 192 || n == 160 || n == 96) ? 6 : 4;
+    // 4, 5 (lengths 64-256): persistent with few, wide radix stages; 6, 7 (64, 128, 256):
+    // register-resident along a strided axis
+    if (n == 256 || n == 128 || n == 64) return 8;
+    return (n == 192 || n == 160 || n == 96) ? 6 : 4;
 }
 
 }  // namespace sb
