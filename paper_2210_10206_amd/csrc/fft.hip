@@ -475,7 +475,7 @@ __global__ __launch_bounds__(NT) void fft_pass_pf_kernel(FftPass a, int tiles) {
 }
 
 // Register-resident pass along a strided axis for n = R1 * R2 (R2 divides R1): P adjacent
-// pencils of the faster axes per tile, thread q < R2 of a pencil owns elements q + R2 s (the
+// pencils of the faster axes per tile (16 or 32: rows of 128 or 256 contiguous bytes), thread q < R2 of a pencil owns elements q + R2 s (the
 // inputs of first-stage butterfly q and the outputs of second-stage butterflies q + R2 t), so
 // loads and stores are coalesced over the P pencils and LDS holds only the one exchange between
 // the two radix stages.  A workgroup walks `tiles` consecutive tiles with the next one's loads
@@ -540,9 +540,8 @@ __global__ __launch_bounds__(P * R2, 3) void mid_reg_kernel(FftPass a, int tiles
     }
 }
 
-template <int R1, int R2>
+template <int R1, int R2, int P>
 hipError_t launch_mid_reg(const FftPass &a, hipStream_t s, int tiles) {
-    constexpr int P = 16;
     constexpr int N = R1 * R2;
     const int64_t ntile = (a.ng / N + P - 1) / P;
     dim3 grid((unsigned)((ntile + tiles - 1) / tiles), (unsigned)a.batch);
@@ -582,12 +581,14 @@ hipError_t launch(const FftPass &a, hipStream_t s) {
 hipError_t launch_fft_pass(const FftPass &a, hipStream_t s) {
     const int v = a.variant;
     // variants 6 and 7 (lengths 64, 128, 256 along a strided axis whose stride is a multiple of
-    // 16): register-resident, 4 / 16 tiles; elsewhere they run as variants 4 and 5
+    // 16): register-resident; 6: tiles of 32 pencils (16 if the stride is not a multiple of 32),
+    // 8 per workgroup, 7: 16 pencils, 16 per workgroup.  Elsewhere they run as variants 4 and 5.
     if (v >= 6 && a.load == LOAD_C && a.store == STORE_C && a.stride > 1 && a.stride % 16 == 0) {
-        const int tiles = v == 6 ? 4 : 16;
-        if (a.n == 256) return launch_mid_reg<16, 16>(a, s, tiles);
-        if (a.n == 128) return launch_mid_reg<16, 8>(a, s, tiles);
-        if (a.n == 64) return launch_mid_reg<8, 8>(a, s, tiles);
+        const bool wide = v == 6 && a.stride % 32 == 0;
+        const int tiles = v == 6 ? 8 : 16;
+        if (a.n == 256) return wide ? launch_mid_reg<16, 16, 32>(a, s, tiles) : launch_mid_reg<16, 16, 16>(a, s, tiles);
+        if (a.n == 128) return wide ? launch_mid_reg<16, 8, 32>(a, s, tiles) : launch_mid_reg<16, 8, 16>(a, s, tiles);
+        if (a.n == 64) return wide ? launch_mid_reg<8, 8, 32>(a, s, tiles) : launch_mid_reg<8, 8, 16>(a, s, tiles);
     }
     // variants 4 and 5: persistent with few, wide radix stages (64: 8 x 8, 96: 12 x 4 x 2,
     // 128: 16 x 8, 160: 20 x 4 x 2, 192: 12 x 4 x 4, 256: 16 x 16), 4 / 16 tiles
