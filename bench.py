@@ -60,13 +60,15 @@ def write_traffic(counter_dir, n=256, copy_mib=1024, min_gib=1.0):
     profiles/traffic.json.  Each counter is scaled by bytes / counter of the plain
     copy_mib MiB device copy in the same run (the __amd_rocclr_copyBuffer dispatches of that
     size); the passes over all kernel arrays are the dispatches of each kernel family with at
-    least min_gib GiB of either counter, and of the middle pass only the variant the run
-    launched most often (the one the autotuner picked and the timed steps used).  The last
-    pass is two launches per field (packed m = 0 pairs, other groups): their bytes are summed."""
+    least min_gib GiB of either counter, and of the axis-0 and middle passes only the variant
+    of the run's last dispatch (the one the autotuner picked and the timed step used).  The
+    last pass is two launches per field (packed m = 0 pairs, other groups): their bytes are
+    summed."""
     import csv
     import re
     reg = {256: 16}.get(n)   # lengths with the register-resident forms (n = r * r)
-    fams = {0: re.compile(rf"fft_pass(_pf)?_kernel<{n}, \d+, \d+, 1,"),
+    fams = {0: re.compile(rf"fft_pass(_pf)?_kernel<{n}, \d+, \d+, 1,|mid_reg_kernel<{reg}, {n // reg}, \d+, 1>"
+                          if reg else rf"fft_pass(_pf)?_kernel<{n}, \d+, \d+, 1,"),
             1: re.compile(rf"axis0_kernel<{n},|axis0_reg_kernel<{reg}, " if reg else rf"axis0_kernel<{n},"),
             2: re.compile(rf"last_contract_kernel<{n},|last_reg_kernel<{reg}, " if reg else
                           rf"last_contract_kernel<{n},")}
@@ -89,22 +91,28 @@ def write_traffic(counter_dir, n=256, copy_mib=1024, min_gib=1.0):
            "_scale": {k: round(v, 4) for k, v in scale.items()}}
     for k, rx in fams.items():
         per_name = {}
-        for did, (name, fv) in raw["FETCH_SIZE"].items():
+        last_name = None
+        for did in sorted(raw["FETCH_SIZE"]):
+            name, fv = raw["FETCH_SIZE"][did]
             if not rx.search(name) or did not in raw["WRITE_SIZE"]:
                 continue
             wv = raw["WRITE_SIZE"][did][1]
             if max(fv, wv) * 1024 < min_gib * 2 ** 30:
                 continue
             per_name.setdefault(name, []).append((fv, wv))
+            last_name = name
         if not per_name:
             continue
-        # one pass over a field's arrays: the most frequent dispatch (the axis-0 and middle
-        # passes), or for the last pass every dispatch name launched that often (the packed
-        # m = 0 pairs and the other groups are two launches per field), summed
-        nmax = max(len(v) for v in per_name.values())
-        names = [q for q in per_name if len(per_name[q]) == nmax]
+        # one pass over a field's arrays: for the axis-0 and middle passes the variant of the
+        # last dispatch (the timed step runs last, with the variant the autotuner chose), for
+        # the last pass every dispatch name launched as often as the most frequent one (the
+        # packed m = 0 pairs and the other groups are two launches per field), summed
         if k != 2:
-            names = [max(names)]
+            names = [last_name]
+            nmax = len(per_name[last_name])
+        else:
+            nmax = max(len(v) for v in per_name.values())
+            names = [q for q in per_name if len(per_name[q]) == nmax]
         fetch = sum(sum(x[0] for x in per_name[q]) / nmax for q in names) * 1024 * scale["FETCH_SIZE"]
         write = sum(sum(x[1] for x in per_name[q]) / nmax for q in names) * 1024 * scale["WRITE_SIZE"]
         out[f"kernel{k}_n{n}"] = {"kernel": " + ".join(names), "dispatches": nmax, "fetch_bytes": round(fetch),
@@ -448,8 +456,8 @@ def main():
     # over all kernel arrays), from the live per-launch HIP-event records
     # arrays per field: one per (l, m) and bin, less the packed m = 0 pairs of the fused path
     narr = ((lmax + 1) * (lmax + 2) // 2 - (lmax + 1) // 2) * nbins
-    names = {0: f"fft_pass(_pf)_kernel<{n},...,+1> (middle inverse pass over all {narr} arrays, "
-                f"variant chosen by sb_autotune)",
+    names = {0: f"middle inverse pass over all {narr} arrays (fft_pass_kernel, fft_pass_pf_kernel or "
+                f"mid_reg_kernel<...,+1>: the variant sb_autotune chose)",
              1: (f"axis0_reg_kernel<16,16,...>" if n == 256 else f"axis0_kernel<{n},...>")
                 + " (axis-0 pass: kernel-spectrum regeneration + product + inverse transform)",
              2: (f"last_reg_kernel<16,16,{(nbins + 3) // 4 * 4},PS_PACKED+PS_REAL>" if n == 256
