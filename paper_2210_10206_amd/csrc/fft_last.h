@@ -80,7 +80,8 @@ struct PairSums {
         const int slot = lane >> 2, j = lane & 3;
         const int cg = slot >> 1;
         const bool im_slot = (slot & 1) != 0;
-#pragma unroll 1
+        constexpr int UNROLL = MODE == PS_COMPLEX ? 1 : 2;   // the complex form has no registers to spare
+#pragma unroll UNROLL
         for (int k = 0; k < (NG + NW - 1) / NW; ++k) {
             const int grp = wave + k * NW;
             if (grp < NG) {
