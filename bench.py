@@ -343,7 +343,7 @@ def run_proj(api, steps, warmup):
             q = [x for x in recs if x["kernel"] == 5]
             ms, fl = sum(x["ms"] for x in q), sum(x["flops"] for x in q)
             if ms:
-                r["contraction"] = {"kernel": "proj4_mfma_kernel<10> (float32 MFMA, one launch per canonical m triple)",
+                r["contraction"] = {"kernel": "proj4_mfma_kernel<10> (float32 MFMA, one launch, a grid row per canonical m triple)",
                                     "achieved_tflops": round(fl / (ms * 1e-3) / 1e12, 2),
                                     "peak_tflops": 157.3, "peak_note": "float32 MFMA",
                                     "frac": round(fl / (ms * 1e-3) / 1e12 / 157.3, 4)}

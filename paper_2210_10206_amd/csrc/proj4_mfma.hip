@@ -1,4 +1,5 @@
-// Projected 4PCF contraction (Alg. 8) on the matrix cores, one launch per canonical m triple.
+// Projected 4PCF contraction (Alg. 8) on the matrix cores: one launch, one grid row (blockIdx.y)
+// per canonical m triple.
 //
 // For the triple (m1, m2, m3 = -(m1 + m2)) and every cell x:
 //   L[b1 b2](x)    = w(x) c^b1_m1(x) c^b2_m2(x)          (vector ALU, one complex product)
