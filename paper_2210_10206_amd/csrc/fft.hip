@@ -327,7 +327,9 @@ __global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void
 // Axis-0 correlation pass on the register-resident Stockham stages of reg_stages (any radix
 // list whose last radix divides the first; two or more stages): thread q < T = n / R0 of a
 // pencil owns rows q + T s.  P adjacent pencils of the contiguous axes per workgroup.
-template <int N, int P, int MODE, int R0, int... REST>
+// KR as in axis0_reg_kernel: rows r <= KR and r >= R0 - KR of a thread are the only ones the
+// compact kernel support can reach (KR >= R0 / 2: all rows).
+template <int N, int P, int MODE, int KR, int R0, int... REST>
 __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
     constexpr int T = N / R0;
     constexpr int PITCH = P + 1;
@@ -343,6 +345,10 @@ __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
         const float2 *kc = a.kc + k * kstride;
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
+            if (r > KR && r < R0 - KR) {
+                dst[r] = make_float2(0.f, 0.f);
+                continue;
+            }
             const int j = q + T * r;
             const int pl = (a.np == N || j <= a.r0) ? j : (j >= N - a.r0 ? a.np - (N - j) : -1);
             dst[r] = (ok && pl >= 0) ? ld_stream(&kc[(int64_t)pl * a.plane + g]) : make_float2(0.f, 0.f);
@@ -639,13 +645,16 @@ hipError_t launch_axis0(const Axis0Args &a, hipStream_t s) {
             constexpr int M = decltype(mode_c)::value;
             if constexpr (M == 0) {
                 if (a.n == 512) {
-                    hipLaunchKernelGGL((axis0_rs_kernel<512, P, 0, 16, 8, 4>), grid, dim3(32 * P), 0, s, a);
+                    const int kr = support_rows(a, 16, 32);
+                    if (kr <= 1) hipLaunchKernelGGL((axis0_rs_kernel<512, P, 0, 1, 16, 8, 4>), grid, dim3(32 * P), 0, s, a);
+                    else if (kr <= 2) hipLaunchKernelGGL((axis0_rs_kernel<512, P, 0, 2, 16, 8, 4>), grid, dim3(32 * P), 0, s, a);
+                    else hipLaunchKernelGGL((axis0_rs_kernel<512, P, 0, 16, 16, 8, 4>), grid, dim3(32 * P), 0, s, a);
                     return;
                 }
             }
-            if (a.n == 192) hipLaunchKernelGGL((axis0_rs_kernel<192, P, M, 12, 4, 4>), grid, dim3(16 * P), 0, s, a);
-            else if (a.n == 160) hipLaunchKernelGGL((axis0_rs_kernel<160, P, M, 20, 4, 2>), grid, dim3(8 * P), 0, s, a);
-            else hipLaunchKernelGGL((axis0_rs_kernel<96, P, M, 12, 4, 2>), grid, dim3(8 * P), 0, s, a);
+            if (a.n == 192) hipLaunchKernelGGL((axis0_rs_kernel<192, P, M, 12, 12, 4, 4>), grid, dim3(16 * P), 0, s, a);
+            else if (a.n == 160) hipLaunchKernelGGL((axis0_rs_kernel<160, P, M, 20, 20, 4, 2>), grid, dim3(8 * P), 0, s, a);
+            else hipLaunchKernelGGL((axis0_rs_kernel<96, P, M, 12, 12, 4, 2>), grid, dim3(8 * P), 0, s, a);
         };
         if (a.mode == 1) go(std::integral_constant<int, 1>{});
         else go(std::integral_constant<int, 0>{});
