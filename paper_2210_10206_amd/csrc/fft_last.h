@@ -286,7 +286,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // pair sums read.  The exchange stays inside a wave; the workgroup meets at two barriers per tile
 // (regions written, regions read).  The second-stage twiddles come from an LDS table ordered so
 // that the threads of a pencil read adjacent entries, and the pair sums are flushed to float64
-// every FLUSH rows.
+// every FLUSH (8) rows.
 template <int R1, int R2, int NBT, int MODE>
 __global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
     constexpr int N = R1 * R2;
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
     constexpr int REG = pencil_region(R2 * EXR, N);
     constexpr int WPT = (N + NT - 1) / NT;
     static_assert(NT % 64 == 0, "whole waves");
-    constexpr int FLUSH = NBT * PairSums<NBT, MODE>::NACC <= 12 ? 4 : 1;   // larger accumulators would not stay in registers
+    constexpr int FLUSH = NBT * PairSums<NBT, MODE>::NACC <= 12 ? 8 : 1;   // larger accumulators would not stay in registers
     __shared__ float2 lds[P * REG];
     __shared__ float2 twl[N];              // [t][r][q]: w^{(q + R2 t) r}, w = e^{-2 pi i / N}
     __shared__ float wsm[N];
