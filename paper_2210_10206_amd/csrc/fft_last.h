@@ -73,9 +73,12 @@ struct PairSums {
 
     // Adds one tile of NCELL cells to the float32 sums: the value of bin b at cell c is
     // stage[off(c) + b * bstride] and its weight wsm[c].  The waves take groups of 8 cells in turn.
-    template <int NCELL, int NW, class Off>
+    // PLANE > 0 (not PS_COMPLEX): the stage holds separate real and imaginary planes, the part of
+    // (c, b) at float offset off(c) + b * bstride + part * PLANE, so each lane reads its own part.
+    template <int NCELL, int NW, int PLANE = 0, class Off>
     __device__ __forceinline__ void accumulate(const float2 *stage, int bstride, const float *wsm, Off off, int wave,
                                                int lane) {
+        static_assert(PLANE == 0 || MODE != PS_COMPLEX, "the complex form reads both parts");
         constexpr int NG = (NCELL + CPG - 1) / CPG;
         const int slot = lane >> 2, j = lane & 3;
         const int cg = slot >> 1;
@@ -92,9 +95,15 @@ struct PairSums {
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
                     const bool in = ok && (NBT % 4 == 0 || 4 * q + j < NBT);
-                    const float2 v = in ? stage[off(c) + (4 * q + j) * bstride] : make_float2(0.f, 0.f);
-                    x[q] = im_slot ? v.y : v.x;
-                    xo[q] = im_slot ? v.x : v.y;
+                    if constexpr (PLANE > 0) {
+                        const float *sf = reinterpret_cast<const float *>(stage);
+                        x[q] = in ? sf[off(c) + (4 * q + j) * bstride + (im_slot ? PLANE : 0)] : 0.f;
+                        xo[q] = 0.f;
+                    } else {
+                        const float2 v = in ? stage[off(c) + (4 * q + j) * bstride] : make_float2(0.f, 0.f);
+                        x[q] = im_slot ? v.y : v.x;
+                        xo[q] = im_slot ? v.x : v.y;
+                    }
                 }
                 int p = 0;
 #pragma unroll
@@ -297,7 +306,12 @@ __global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
     constexpr int NW = NT / 64;
     constexpr int NOUT = PairSums<NBT, MODE>::NOUT;
     constexpr int EXR = R1 + 1;            // exchange row pitch (R2 rows)
-    constexpr int REG = pencil_region(R2 * EXR, N);
+    // the transformed row as separate real and imaginary planes (PLANE = 8 mod 64 floats apart,
+    // so a group's reads of both parts fall into distinct banks), except for the complex sums
+    constexpr bool SPLIT = MODE != PS_COMPLEX;
+    constexpr int PLANE = N + 8;
+    static_assert(N % 64 == 0, "plane offset 8 mod 64");
+    constexpr int REG = pencil_region(R2 * EXR, SPLIT ? PLANE : N);
     constexpr int WPT = (N + NT - 1) / NT;
     static_assert(NT % 64 == 0, "whole waves");
     constexpr int FLUSH = NBT * PairSums<NBT, MODE>::NACC <= 12 ? 8 : 1;   // larger accumulators would not stay in registers
@@ -362,15 +376,29 @@ __global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
             Dft<R2, 1>::run(u);
         }
         wave_lds_sync();                                    // the pencil's exchange rows are read
+        if constexpr (SPLIT) {
+            float *ownf = reinterpret_cast<float *>(own);
 #pragma unroll
-        for (int t = 0; t < T; ++t)
+            for (int t = 0; t < T; ++t)
 #pragma unroll
-            for (int r = 0; r < R2; ++r) own[q + R2 * t + R1 * r] = v[t * R2 + r];
+                for (int r = 0; r < R2; ++r) {
+                    ownf[q + R2 * t + R1 * r] = v[t * R2 + r].x;
+                    ownf[PLANE + q + R2 * t + R1 * r] = v[t * R2 + r].y;
+                }
+        } else {
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int r = 0; r < R2; ++r) own[q + R2 * t + R1 * r] = v[t * R2 + r];
+        }
 #pragma unroll
         for (int e = 0; e < WPT; ++e)
             if (tid + e * NT < N) wsm[tid + e * NT] = wv[e];
         __syncthreads();
-        ps.template accumulate<N, NW>(lds, REG, wsm, [](int c) { return c; }, wave, lane);
+        if constexpr (SPLIT)
+            ps.template accumulate<N, NW, PLANE>(lds, 2 * REG, wsm, [](int c) { return c; }, wave, lane);
+        else
+            ps.template accumulate<N, NW>(lds, REG, wsm, [](int c) { return c; }, wave, lane);
         if ((row - r_begin) % FLUSH == FLUSH - 1 || row + 1 == r_end) ps.flush(lane);
     }
     // float64 combine over the waves in wave order (as in last_contract_kernel)
