@@ -546,6 +546,47 @@ __global__ __launch_bounds__(P * R2, 3) void mid_reg_kernel(FftPass a, int tiles
     }
 }
 
+// The same for the three-stage radix lists (reg_stages): thread q < T = n / R0 of a pencil owns
+// elements q + T s, the stages exchange through one LDS buffer (two barriers per exchange), so
+// that two 512-thread workgroups share a CU.  Tiles are loaded as they are reached.
+template <int N, int P, int SIGN, int R0, int... REST>
+__global__ __launch_bounds__(P * (N / R0), 4) void mid_rs_kernel(FftPass a, int tiles) {
+    constexpr int T = N / R0;
+    constexpr int PITCH = P + 1;
+    __shared__ float2 ex[N * PITCH];
+    __shared__ float2 tw[N];
+    const int tid = threadIdx.x;
+    const int p = tid % P, q = tid / P;
+    for (int i = tid; i < N; i += P * T) tw[i] = a.tw[i];
+    const int64_t npencil = a.ng / N;
+    const int64_t ntile = (npencil + P - 1) / P;
+    const float2 *in = reinterpret_cast<const float2 *>(a.in) + blockIdx.y * a.in_bs;
+    float2 *out = a.out + blockIdx.y * a.out_bs;
+    auto base = [&](int64_t g) -> int64_t { return (g / a.stride) * (int64_t)N * a.stride + (g % a.stride); };
+    const int64_t t0 = (int64_t)blockIdx.x * tiles;
+    const int64_t t1 = min(t0 + tiles, ntile);
+    for (int64_t t = t0; t < t1; ++t) {
+        // no register prefetch (it would not fit next to the transform at 4 waves per SIMD): the
+        // other workgroup on the CU covers the load latency
+        float2 v[R0];
+        {
+            const int64_t g = t * P + p;
+            const int64_t b = base(g);
+#pragma unroll
+            for (int r = 0; r < R0; ++r)
+                v[r] = g < npencil ? ld_stream(&in[b + (int64_t)(q + T * r) * a.stride]) : make_float2(0.f, 0.f);
+        }
+        __syncthreads();                 // the previous tile's last stage has read the buffer
+        reg_stages<N, SIGN, R0, REST...>(v, ex, ex, tw, q, p, PITCH);
+        const int64_t g = t * P + p;
+        if (g < npencil) {
+            const int64_t b = base(g);
+#pragma unroll
+            for (int r = 0; r < R0; ++r) st_stream(&out[b + (int64_t)(q + T * r) * a.stride], v[r]);
+        }
+    }
+}
+
 template <int R1, int R2, int P>
 hipError_t launch_mid_reg(const FftPass &a, hipStream_t s, int tiles) {
     constexpr int N = R1 * R2;
@@ -595,6 +636,14 @@ hipError_t launch_fft_pass(const FftPass &a, hipStream_t s) {
         if (a.n == 256) return wide ? launch_mid_reg<16, 16, 32>(a, s, tiles) : launch_mid_reg<16, 16, 16>(a, s, tiles);
         if (a.n == 128) return wide ? launch_mid_reg<16, 8, 32>(a, s, tiles) : launch_mid_reg<16, 8, 16>(a, s, tiles);
         if (a.n == 64) return wide ? launch_mid_reg<8, 8, 32>(a, s, tiles) : launch_mid_reg<8, 8, 16>(a, s, tiles);
+        if (a.n == 512) {
+            constexpr int P = 16;
+            const int64_t ntile = (a.ng / 512 + P - 1) / P;
+            dim3 grid((unsigned)((ntile + tiles - 1) / tiles), (unsigned)a.batch);
+            if (a.sign < 0) hipLaunchKernelGGL((mid_rs_kernel<512, P, -1, 16, 8, 4>), grid, dim3(32 * P), 0, s, a, tiles);
+            else hipLaunchKernelGGL((mid_rs_kernel<512, P, 1, 16, 8, 4>), grid, dim3(32 * P), 0, s, a, tiles);
+            return hipGetLastError();
+        }
     }
     // variants 4 and 5: persistent with few, wide radix stages (64: 8 x 8, 96: 12 x 4 x 2,
     // 128: 16 x 8, 160: 20 x 4 x 2, 192: 12 x 4 x 4, 256: 16 x 16), 4 / 16 tiles
@@ -721,7 +770,7 @@ int fft_num_variants(int n) {
     // 0, 1: one tile per workgroup (two shapes where defined); 2, 3: persistent, 4 / 16 tiles;
     // 4, 5 (lengths 64-256): persistent with few, wide radix stages; 6, 7 (64, 128, 256):
     // register-resident along a strided axis
-    if (n == 256 || n == 128 || n == 64) return 8;
+    if (n == 256 || n == 128 || n == 64 || n == 512) return 8;
     return (n == 192 || n == 160 || n == 96) ? 6 : 4;
 }
 

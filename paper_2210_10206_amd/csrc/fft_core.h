@@ -255,8 +255,8 @@ __device__ __forceinline__ void stages(float2 *sm, const float2 *tw, int p, int 
 // q + T s (s < R0): the inputs of first-stage butterfly q and the outputs of last-stage
 // butterflies q + T t (t < R0 / RL), which write positions q + T t + (n / RL) r.  The stages in
 // between exchange through two LDS buffers stored as buf[j * pitch + p] (pencil p), used
-// alternately, so each exchange needs one barrier.  v[s] holds element q + T s on entry and
-// on exit.
+// alternately, so each exchange needs one barrier (passing the same buffer twice costs a
+// second barrier per exchange).  v[s] holds element q + T s on entry and on exit.
 template <int N, int T, int SIGN, int NS, int R, int... REST>
 __device__ __forceinline__ void reg_stage_rest(float2 *v, float2 *b0, float2 *b1, const float2 *tw, int q, int p,
                                                int pitch) {
@@ -288,6 +288,7 @@ __device__ __forceinline__ void reg_stage_rest(float2 *v, float2 *b0, float2 *b1
 #pragma unroll
             for (int r = 0; r < R; ++r) v[t + (NS / T) * r] = u[t][r];
     } else {
+        if (b1 == b0) __syncthreads();   // one buffer: every thread has read this stage's inputs
 #pragma unroll
         for (int t = 0; t < PER; ++t) {
             const int k = q + T * t;
