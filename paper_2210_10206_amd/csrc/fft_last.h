@@ -288,10 +288,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // Register-resident form for n = R1 * R2 (R2 threads per row): a tile is one row of the NBT
-// (padded) bins of one (l, m).  Thread q of a pencil loads elements q + R2 s (coalesced: the R2
-// threads of a pencil are adjacent lanes), runs the first radix-R1 stage in registers, exchanges
-// through its pencil's LDS region (row q of R1 values written, column q + R2 t read), runs the
-// second stage and writes the transformed row into the same region as [bin][cell], which the MFMA
+// (padded) bins of one array group.  Thread q of a pencil loads elements q + R2 s (coalesced: the
+// R2 threads of a pencil are adjacent lanes), runs the first radix-R1 stage in registers,
+// exchanges through its pencil's LDS region (row q of R1 values written, column q + R2 t read),
+// runs the second stage and writes the transformed row into the same region, as separate real
+// and imaginary float planes (interleaved complex values for the complex sums), which the MFMA
 // pair sums read.  The exchange stays inside a wave; the workgroup meets at two barriers per tile
 // (regions written, regions read).  The second-stage twiddles come from an LDS table ordered so
 // that the threads of a pencil read adjacent entries, and the pair sums are flushed to float64
