@@ -80,11 +80,12 @@ enum {
                                  ones Alg. 6 skips) instead of the even ones; each value is the
                                  imaginary part of the sum, whose real part vanishes for a real
                                  density */
-    SB_FLAG_NO_PACK = 16u     /* full 3PCF, fused forward and adjoint: one complex transform per
-                                 (l, m) array.  By default the real m = 0 coefficient fields a_{l0}
-                                 (Alg. 5; eq. almconv: the m = 0 kernels are real) are carried two
-                                 to a transform, as real and imaginary part, which removes
-                                 floor((lmax + 1) / 2) of the (lmax + 1)(lmax + 2) / 2 arrays per bin */
+    SB_FLAG_NO_PACK = 16u     /* full 3PCF (fused forward and adjoint) and full 4PCF: one complex
+                                 transform per (l, m) array.  By default the real m = 0 coefficient
+                                 fields a_{l0} (Alg. 5, Alg. 6; eq. almconv: the m = 0 kernels are
+                                 real) are carried two to a transform, as real and imaginary part,
+                                 which removes floor((lmax + 1) / 2) of the (lmax + 1)(lmax + 2) / 2
+                                 arrays per bin */
 };
 
 /* Problem statement: the grid, bins, lmax, full or projected, 3 or 4 PCF

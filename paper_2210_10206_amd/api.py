@@ -45,8 +45,8 @@ class Plan:
     mfma       : full 4PCF: use the matrix-core contraction where it exists (l <= 4, <= 8 bins);
                  projected 4PCF: the matrix-core contraction (False = the vector-ALU kernel)
     parity     : full 4PCF: "even" (Alg. 6) or "odd" Lambda (the imaginary part of those sums)
-    pack       : full 3PCF, fused path: carry the real m = 0 coefficient fields two to a complex
-                 transform (False = one transform per (l, m))
+    pack       : full 3PCF (fused path) and full 4PCF: carry the real m = 0 coefficient fields two
+                 to a complex transform (False = one transform per (l, m))
     scratch_limit: bytes of kernel arrays a 3PCF plan keeps at once (default 48 GiB); above it
                  the passes run over chunks of (l, m) groups (sb_plan_set_scratch_limit)
     """

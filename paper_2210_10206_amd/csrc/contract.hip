@@ -116,7 +116,11 @@ __global__ __launch_bounds__(256) void quad_kernel(QuadArgs a) {
             const int c = f % a.tile, kb = f / a.tile;
             const int k = kb / NB, b = kb % NB;
             float2 v = make_float2(0.f, 0.f);
-            if (c < ncell) v = a.coef[((int64_t)scol[k] * NB + b) * a.ng + tc + c];
+            const int lm = scol[k];
+            const int arr = a.lm_src ? a.lm_src[2 * lm] : lm, part = a.lm_src ? a.lm_src[2 * lm + 1] : 0;
+            if (c < ncell) v = a.coef[((int64_t)arr * NB + b) * a.ng + tc + c];
+            if (part == 1) v.y = 0.f;                          // packed m = 0 arrays: one real column each
+            else if (part == 2) v = make_float2(v.y, 0.f);
             tile[c * width + kb] = v;
         }
         __syncthreads();

@@ -215,10 +215,14 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
     // array groups of the fused 3D 3PCF forward path: the real m = 0 kernels go two to a
     // complex transform (the kernel Y*_{l0} Phi_b of eq. almconv is real), packed pairs first, then one (l, m) per group
     {
-        bool pack = prob->ndim == 3 && prob->npcf == 3 && prob->lmax >= 1 &&
-                    (prob->flags & (SB_FLAG_UNFUSED | SB_FLAG_KEEP_COEFFS | SB_FLAG_NO_PACK)) == 0;
-        for (const auto &G : p->groups)
-            if (fused_last_rows((int)G.n[prob->ndim - 1], NB) <= 0) pack = false;
+        // 3PCF: the fused path (forward and adjoint); 4PCF: the coefficients the contraction reads
+        // (its kernels take each m = 0 column from its packed array through lm_src)
+        bool pack = prob->ndim == 3 && prob->lmax >= 1 && (prob->flags & (SB_FLAG_KEEP_COEFFS | SB_FLAG_NO_PACK)) == 0;
+        if (prob->npcf == 3) {
+            if (prob->flags & SB_FLAG_UNFUSED) pack = false;
+            for (const auto &G : p->groups)
+                if (fused_last_rows((int)G.n[prob->ndim - 1], NB) <= 0) pack = false;
+        }
         if (pack) {
             p->npack = (prob->lmax + 1) / 2;
             for (int i = 0; i < p->npack; ++i) {
@@ -238,6 +242,15 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
                     p->ag_rowmap.push_back(-1);
                 }
             p->nag = (int)p->ag_kmap.size();
+            // (array group, part) of every (l, m): part 1 / 2 for the real / imaginary part of a pair
+            p->lm_src.assign(2 * p->nlm, 0);
+            for (int g = 0; g < p->nag; ++g)
+                for (int part = 0; part < 2; ++part) {
+                    const int lm = p->ag_rowmap[2 * g + part];
+                    if (lm < 0) continue;
+                    p->lm_src[2 * lm] = g;
+                    p->lm_src[2 * lm + 1] = g < p->npack ? part + 1 : 0;
+                }
         }
     }
     // bin counts per group (host enumeration of the same integer test as the kernels)
@@ -361,10 +374,11 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
         for (const auto &x : p->p4_canon) { pr.push_back(x.first); pr.push_back(x.second); }
         off_pairs = put(pr.data(), pr.size() * sizeof(int));
     }
-    size_t off_kmap = 0, off_rowmap = 0;
+    size_t off_kmap = 0, off_rowmap = 0, off_lmsrc = 0;
     if (p->npack > 0) {
         off_kmap = put(p->ag_kmap.data(), p->ag_kmap.size() * sizeof(int));
         off_rowmap = put(p->ag_rowmap.data(), p->ag_rowmap.size() * sizeof(int));
+        off_lmsrc = put(p->lm_src.data(), p->lm_src.size() * sizeof(int));
     }
     std::vector<int> gptr, gidx;
     std::vector<double> gcoef;
@@ -392,6 +406,7 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
     if (p->npack > 0) {
         p->d_kmap = reinterpret_cast<const int *>(base + off_kmap);
         p->d_rowmap = reinterpret_cast<const int *>(base + off_rowmap);
+        p->d_lmsrc = reinterpret_cast<const int *>(base + off_lmsrc);
     }
     p->d_gptr = reinterpret_cast<const int *>(base + off_gptr);
     p->d_gidx = reinterpret_cast<const int *>(base + off_gidx);
@@ -679,6 +694,7 @@ sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
         a.partial = part;
         a.nblocks = nblocks;
         a.odd = (p->prob.flags & SB_FLAG_ODD_PARITY) != 0;
+        a.lm_src = p->npack > 0 ? p->d_lmsrc : nullptr;
         // algorithmic flops per cell and Lambda: 8 per nonzero coupling term and bin pair, then
         // per mc the weight (2) and the b3 contraction (4 per bin) for each bin pair
         auto lam_flops = [&](size_t c) {
@@ -702,6 +718,7 @@ sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
                 m.nblocks = nblocks;
                 m.precision = p->prob.precision == SB_PREC_SPLIT_BF16 ? 1 : 0;
                 m.partial = part;
+                m.lm_src = a.lm_src;
                 int ncol = 0;
                 for (int q = 0; q < 3; ++q) {
                     bool dup = false;
@@ -762,7 +779,8 @@ sb_status forward(sb_plan *p, const void *const *delta, double *zeta, hipStream_
             st = fused_3pcf(p, f, delta[f], zf, s);
         } else {
             st = density_spectrum(p, G, delta[f], s);
-            if (st == SB_OK) st = coefficients(p, f, 0, p->nlm, s);
+            if (st == SB_OK)   // array groups (packed m = 0 pairs first) where the plan packs
+                st = p->npack > 0 ? coefficients(p, f, 0, p->nag, s, true, p->d_kmap) : coefficients(p, f, 0, p->nlm, s);
             if (st == SB_OK) st = contract(p, f, zf, s);
         }
         if (st != SB_OK) return st;

@@ -230,14 +230,22 @@ __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
     // load k of this thread: cell = lane, (column, bin) row = wave + 4 k
     float2 pf[NLD];
     float pw = 0.f;
+    // coefficient array and part of each load (packed m = 0 arrays hold two real columns)
+    int karr[NLD], kpart[NLD];
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+        const int lm = CL::lm_of((wave + 4 * k) / kMaxNB);
+        karr[k] = a.lm_src ? a.lm_src[2 * lm] : lm;
+        kpart[k] = a.lm_src ? a.lm_src[2 * lm + 1] : 0;
+    }
     auto gload = [&](int64_t tc) {
         const bool in = tc + lane < c1;
 #pragma unroll
         for (int k = 0; k < NLD; ++k) {
             const int kb = wave + 4 * k;
-            const int col = kb / kMaxNB, b = kb % kMaxNB;
-            const float2 *src = a.coef + ((int64_t)CL::lm_of(col) * nb + b) * a.ng + tc;
-            pf[k] = (in && b < nb) ? src[lane] : make_float2(0.f, 0.f);
+            const int b = kb % kMaxNB;
+            const float2 *src = a.coef + ((int64_t)karr[k] * nb + b) * a.ng + tc;
+            pf[k] = (in && b < nb) ? src[lane] : make_float2(0.f, 0.f);   // part taken when staged
         }
         if (wave == 0) pw = in ? a.w[tc + lane] : 0.f;
     };
@@ -247,7 +255,10 @@ __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
 #pragma unroll
         for (int k = 0; k < NLD; ++k) {
             const int kb = wave + 4 * k;
-            tile[lane * S + kb] = pf[k];   // kb = column * 8 + bin
+            float2 v = pf[k];
+            if (kpart[k] == 1) v.y = 0.f;                       // packed m = 0 column: one real part
+            else if (kpart[k] == 2) v = make_float2(v.y, 0.f);
+            tile[lane * S + kb] = v;   // kb = column * 8 + bin
         }
         if (wave == 0) wt[lane] = pw;
         __syncthreads();

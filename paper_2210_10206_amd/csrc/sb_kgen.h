@@ -73,6 +73,8 @@ struct QuadArgs {
     double *partial;          // [lam][block][nbins^3]
     int nblocks;
     bool odd;                 // odd Lambda: the imaginary part of the sums (the real part vanishes)
+    const int *lm_src;        // optional, 2 per lm: coefficient array and part (0: the complex array,
+                              // 1 / 2: the real / imaginary part of a packed m = 0 array)
 };
 hipError_t launch_quad_contract(const QuadArgs &a, hipStream_t s);
 
@@ -88,6 +90,7 @@ struct QuadMArgs {
     int nblocks;
     int precision;            // 0 float32 MFMA, 1 split-BF16 MFMA
     double *partial;          // [lam][nbins^3][block]
+    const int *lm_src;        // optional, as in QuadArgs
 };
 // Returns hipErrorInvalidValue when no kernel exists for (la, lb, lc).
 hipError_t launch_quad_mfma(int la, int lb, int lc, const QuadMArgs &a, hipStream_t s);

@@ -47,14 +47,15 @@ struct sb_plan {
     std::vector<int> field_group;
     std::vector<sb::ShapeGroup> groups;
     int nlm = 0, nk = 0;
-    // fused 3D 3PCF: array groups of the forward path.  The first npack carry two real m = 0
+    // fused 3D 3PCF and full 4PCF: array groups of the forward path.  The first npack carry two real m = 0
     // kernels (l_a, l_b) as K_{l_a 0} + i K_{l_b 0}, stored as kernel groups nlm .. nlm + npack - 1;
     // the others are one (l, m) each.  kmap: kernel group of each array group; rowmap: the (l, m)
     // group of part 0 and part 1 of its pair sums (-1: none).
     int npack = 0, nag = 0;
     int pack_l[2 * sb::kMaxPack] = {};
     std::vector<int> ag_kmap, ag_rowmap;
-    const int *d_kmap = nullptr, *d_rowmap = nullptr;
+    std::vector<int> lm_src;       // 2 per (l, m): array group and part (0 complex, 1 / 2 re / im of a pair)
+    const int *d_kmap = nullptr, *d_rowmap = nullptr, *d_lmsrc = nullptr;
     int kernel_groups() const { return nlm + npack; }
     int64_t max_ng = 0;
     int64_t last_ng = 0;

@@ -429,6 +429,28 @@ def test_full4pcf_small(sb, precision, mfma):
     plan.close()
 
 
+@pytest.mark.parametrize("mfma,parity,lmax", [(True, "even", 4), (False, "even", 3), (True, "odd", 4), (False, "odd", 2)])
+def test_full4pcf_packed_m0_arrays(sb, mfma, parity, lmax):
+    # the 4PCF coefficients carry the real m = 0 fields two to an array by default; the
+    # contraction kernels read those columns through the (array, part) table
+    say(f"case: 24^3 full 4PCF, 4 bins to 6, lmax {lmax}, {parity} parity, matrix cores {mfma}: packed vs unpacked")
+    d = lognormal_field((24, 24, 24), seed=9, sigma=1.0)
+    edges = linear_edges(6, 4)
+    plan, dev, z = run_plan(sb, [d], edges, lmax, npcf=4, mfma=mfma, parity=parity)
+    plan0, _, z0 = run_plan(sb, [d], edges, lmax, npcf=4, mfma=mfma, parity=parity, pack=False)
+    assert plan.persistent_bytes > plan0.persistent_bytes
+    diff = rel_err(z[0], z0[0])
+    say(f"  packed vs unpacked {diff:.3e}")
+    assert diff < TOL32
+    if parity == "even":
+        lams, ref = oracle.zeta4_full(d.astype(np.float64), edges, lmax)
+        err = rel_err(z[0], ref.real)
+        say(f"  packed err vs oracle {err:.3e}")
+        assert err < TOL32
+    plan.close()
+    plan0.close()
+
+
 @pytest.mark.parametrize("precision,mfma", [("fp32", True), ("split_bf16", True), ("fp32", False)])
 def test_full4pcf_odd_parity(sb, precision, mfma):
     # the 23 odd Lambda at lmax 4: the imaginary part of the sums (their real part vanishes)
