@@ -112,7 +112,8 @@ sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta
     float2 *acc = reinterpret_cast<float2 *>(p->scratch + p->off_grad);
     float2 *vtmp = reinterpret_cast<float2 *>(p->scratch + p->off_vtmp);
     float *dsum = reinterpret_cast<float *>(p->scratch + p->off_dsum);
-    const float2 *coef = reinterpret_cast<const float2 *>(p->scratch + p->off_coef);
+    float2 *coef_w = reinterpret_cast<float2 *>(p->scratch + p->off_coef);
+    const float2 *coef = coef_w;
     const float *w = reinterpret_cast<const float *>(p->scratch + p->off_w);
     for (int f = 0; f < p->batch; ++f) {
         if (!delta[f] || !grad_delta[f]) return fail(SB_EINVAL, "null field pointer");
@@ -136,72 +137,17 @@ sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta
             *m = lm - l * (l + 1) / 2;
             return l;
         };
-        int g0 = 0, gend = 0;   // groups whose coefficients are in scratch
-        for (int g = 0; g < ngrp; ++g) {
-            // (l, m) of group g; a packed group also has l2 (m = 0)
-            int m = 0, m2 = 0, l2 = -1;
-            const int l = l_of(packing ? p->ag_rowmap[2 * g] : g, &m);
-            if (packing && p->ag_rowmap[2 * g + 1] >= 0) l2 = l_of(p->ag_rowmap[2 * g + 1], &m2);
-            const int kgroup = packing ? p->ag_kmap[g] : g;
-            if (g >= gend) {   // recompute a for the next chunk of groups (never stored across calls)
-                g0 = g;
-                gend = std::min(ngrp, g + p->chunk_groups);
-                // a stops before the last axis: the fused pass below finishes it
-                st = coefficients(p, f, g0, gend - g0, s, !p->adj_fused, packing ? p->d_kmap + g0 : nullptr);
-                if (st != SB_OK) return st;
-            }
-            if (p->adj_fused) {
-                // last inverse pass + h, D and v + forward transform of v(-x) along the last axis
-                AdjLastArgs a{};
-                a.n = (int)G.n[2];
-                a.ndim = 3;
-                for (int d = 0; d < 3; ++d) a.shape[d] = G.n[d];
-                a.ng = G.ng;
-                a.in = coef + (int64_t)(g - g0) * NB * G.ng;
-                a.w = w;
-                a.gz = gz_f + (int64_t)l * NB * NB;
-                a.gz2 = l2 >= 0 ? gz_f + (int64_t)l2 * NB * NB : nullptr;
-                a.wm = m == 0 ? 1.f : 2.f;
-                a.nb = NB;
-                const int64_t nrows = G.ng / a.n;
-                // about 4096 workgroups (the small grids need them all to fill the chip),
-                // at most 16 rows each
-                a.rows_per_block = std::max<int64_t>(1, std::min<int64_t>(16, nrows / 4096));
-                a.first = g == 0;
-                a.dsum = dsum;
-                a.out = vtmp;
-                a.tw = p->tw.at(a.n);
-                e = p->timed_launch(STAGE_OTHER, K_ADJPREP, s, [&]() { return launch_adj_last(a, s); }, a.n, 0, NB,
-                                    16.0 * NB * G.ng + 8.0 * G.ng);
-                if (e != hipSuccess) return hip_fail(e, "adjoint fused last pass");
-                const int axes[1] = {1};
-                st = fft_axes(p, G.n, 3, G.ng, axes, 1, -1, LOAD_C, vtmp, G.ng, vtmp, G.ng, NB, s);
-                if (st != SB_OK) return st;
-            } else {
-                AdjPrepArgs a{};
-                a.coef = coef + (int64_t)(g - g0) * NB * G.ng;
-                a.w = w;
-                a.gz = gz_f + (int64_t)l * NB * NB;
-                a.nbins = NB;
-                a.wm = m == 0 ? 1.f : 2.f;
-                a.ndim = 3;
-                for (int d = 0; d < 3; ++d) a.n[d] = G.n[d];
-                a.ng = G.ng;
-                a.vtmp = vtmp;
-                a.dsum = dsum;
-                a.first = g == 0;
-                e = p->timed_launch(STAGE_OTHER, K_ADJPREP, s, [&]() {
-                    hipLaunchKernelGGL(adj_prep_kernel, dim3(nblk), dim3(nt), 0, s, a);
-                    return hipGetLastError();
-                });
-                if (e != hipSuccess) return hip_fail(e, "adjoint prep");
-                // transform v_b(-.) along axes 2..1 in place
-                const int axes[2] = {2, 1};
-                st = fft_axes(p, G.n, 3, G.ng, axes, 2, -1, LOAD_C, vtmp, G.ng, vtmp, G.ng, NB, s);
-                if (st != SB_OK) return st;
-            }
-            // acc += sum_b FFT(w_m v_b(-.)) * Khat_b: the axis-0 pass regenerates each kernel
-            // spectrum and accumulates
+        // (l, m) of group g; a packed group also has l2 (m = 0)
+        auto group_l = [&](int g, int *m, int *l2) {
+            int m2 = 0;
+            *l2 = -1;
+            const int l = l_of(packing ? p->ag_rowmap[2 * g] : g, m);
+            if (packing && p->ag_rowmap[2 * g + 1] >= 0) *l2 = l_of(p->ag_rowmap[2 * g + 1], &m2);
+            return l;
+        };
+        // acc += sum_{groups, b} FFT(w_m v_b(-.)) * Khat_b over ngr groups whose v arrays start at
+        // vin: the axis-0 pass regenerates each kernel spectrum and adds every group's sum in turn
+        auto accumulate = [&](const float2 *vin, int g0, int ngr) -> hipError_t {
             Axis0Args x{};
             x.n = (int)G.n[0];
             x.plane = G.plane;
@@ -211,14 +157,88 @@ sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta
             x.mode = 1;
             x.kc = khat;
             x.out = acc;
-            x.vin = vtmp;
+            x.vin = vin;
             x.nb = NB;
             x.groups = 1;
-            x.kfirst = kgroup * NB;
+            x.accgroups = ngr;
+            x.kmap = packing ? p->d_kmap + g0 : nullptr;
+            x.kfirst = g0 * NB;
             x.tw = p->tw.at(x.n);
-            e = p->timed_launch(STAGE_FFT, K_AXIS0, s, [&]() { return launch_axis0(x, s); }, x.n, -1, NB,
-                                (double)NB * (8.0 * G.ng + 8.0 * G.np * G.plane) + 16.0 * G.ng);
-            if (e != hipSuccess) return hip_fail(e, "adjoint axis-0 pass");
+            return p->timed_launch(STAGE_FFT, K_AXIS0, s, [&]() { return launch_axis0(x, s); }, x.n, -1, ngr * NB,
+                                   (double)ngr * NB * (8.0 * G.ng + 8.0 * G.np * G.plane) + 16.0 * ngr * G.ng);
+        };
+        for (int g0 = 0; g0 < ngrp; g0 += p->chunk_groups) {
+            const int ngr = std::min(p->chunk_groups, ngrp - g0);
+            // recompute a for this chunk of groups (never stored across calls); with the fused pass
+            // it stops before the last axis, which that pass finishes
+            st = coefficients(p, f, g0, ngr, s, !p->adj_fused, packing ? p->d_kmap + g0 : nullptr);
+            if (st != SB_OK) return st;
+            if (p->adj_fused) {
+                // per group: last inverse pass + h, D and v + forward transform of v(-x) along the
+                // last axis.  v of group g goes to the slot before its own coefficients (the vtmp
+                // arrays for the first group, then the coefficients the previous group consumed),
+                // so the chunk's v arrays end up contiguous from vbase.
+                float2 *vbase = coef_w - (int64_t)NB * G.ng;
+                for (int g = g0; g < g0 + ngr; ++g) {
+                    int m = 0, l2 = -1;
+                    const int l = group_l(g, &m, &l2);
+                    AdjLastArgs a{};
+                    a.n = (int)G.n[2];
+                    a.ndim = 3;
+                    for (int d = 0; d < 3; ++d) a.shape[d] = G.n[d];
+                    a.ng = G.ng;
+                    a.in = coef + (int64_t)(g - g0) * NB * G.ng;
+                    a.w = w;
+                    a.gz = gz_f + (int64_t)l * NB * NB;
+                    a.gz2 = l2 >= 0 ? gz_f + (int64_t)l2 * NB * NB : nullptr;
+                    a.wm = m == 0 ? 1.f : 2.f;
+                    a.nb = NB;
+                    const int64_t nrows = G.ng / a.n;
+                    // about 4096 workgroups (the small grids need them all to fill the chip),
+                    // at most 16 rows each
+                    a.rows_per_block = std::max<int64_t>(1, std::min<int64_t>(16, nrows / 4096));
+                    a.first = g == 0;
+                    a.dsum = dsum;
+                    a.out = vbase + (int64_t)(g - g0) * NB * G.ng;
+                    a.tw = p->tw.at(a.n);
+                    e = p->timed_launch(STAGE_OTHER, K_ADJPREP, s, [&]() { return launch_adj_last(a, s); }, a.n, 0,
+                                        NB, 16.0 * NB * G.ng + 8.0 * G.ng);
+                    if (e != hipSuccess) return hip_fail(e, "adjoint fused last pass");
+                }
+                const int axes[1] = {1};
+                st = fft_axes(p, G.n, 3, G.ng, axes, 1, -1, LOAD_C, vbase, G.ng, vbase, G.ng, ngr * NB, s);
+                if (st != SB_OK) return st;
+                e = accumulate(vbase, g0, ngr);
+                if (e != hipSuccess) return hip_fail(e, "adjoint axis-0 pass");
+            } else {
+                for (int g = g0; g < g0 + ngr; ++g) {
+                    int m = 0, l2 = -1;
+                    const int l = group_l(g, &m, &l2);
+                    AdjPrepArgs a{};
+                    a.coef = coef + (int64_t)(g - g0) * NB * G.ng;
+                    a.w = w;
+                    a.gz = gz_f + (int64_t)l * NB * NB;
+                    a.nbins = NB;
+                    a.wm = m == 0 ? 1.f : 2.f;
+                    a.ndim = 3;
+                    for (int d = 0; d < 3; ++d) a.n[d] = G.n[d];
+                    a.ng = G.ng;
+                    a.vtmp = vtmp;
+                    a.dsum = dsum;
+                    a.first = g == 0;
+                    e = p->timed_launch(STAGE_OTHER, K_ADJPREP, s, [&]() {
+                        hipLaunchKernelGGL(adj_prep_kernel, dim3(nblk), dim3(nt), 0, s, a);
+                        return hipGetLastError();
+                    });
+                    if (e != hipSuccess) return hip_fail(e, "adjoint prep");
+                    // transform v_b(-.) along axes 2..1 in place
+                    const int axes[2] = {2, 1};
+                    st = fft_axes(p, G.n, 3, G.ng, axes, 2, -1, LOAD_C, vtmp, G.ng, vtmp, G.ng, NB, s);
+                    if (st != SB_OK) return st;
+                    e = accumulate(vtmp, g, 1);
+                    if (e != hipSuccess) return hip_fail(e, "adjoint axis-0 pass");
+                }
+            }
         }
         st = fft_all_axes(p, G, +1, LOAD_C, acc, 0, acc, 0, 1, s);
         if (st != SB_OK) return st;

@@ -96,6 +96,11 @@ __global__ __launch_bounds__(NT) void fft_pass_kernel(FftPass a) {
 //   CORR : for each of the nb kernels of the group: K = FFT_0(stored kernel pencil),
 //          T = IFFT_0(delta_hat * K), written out;  delta_hat is read once per group.
 //   ADJ  : acc += sum_b FFT_0(v_b) * FFT_0(stored kernel pencil b)   (adjoint)
+// Mode 1: kernel index of step t of the flattened (group, bin) loop of an accumulation launch.
+__device__ __forceinline__ int64_t acc_kernel(const Axis0Args &a, int t) {
+    return a.kmap ? (int64_t)a.kmap[t / a.nb] * a.nb + t % a.nb : (int64_t)a.kfirst + t;
+}
+
 template <int N, int TPP, int NT, int... RAD>
 __global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
     constexpr int P = NT / TPP;
@@ -161,18 +166,19 @@ __global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
             for (int e = 0; e < EPT; ++e) dst[e] = ok ? vb[(int64_t)(q0 + e * TPP) * a.plane + g] : make_float2(0.f, 0.f);
         };
         float2 nv[EPT], kx[EPT];
+        const int nt = (a.accgroups > 1 ? a.accgroups : 1) * a.nb;   // (group, bin) steps
         load_v(0, nv);
-        load_kernel(a.kfirst, nx);
-        for (int b = 0; b < a.nb; ++b) {
+        load_kernel(acc_kernel(a, 0), nx);
+        for (int t = 0; t < nt; ++t) {
             __syncthreads();
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
                 sm[(q0 + e * TPP) * PITCH + p] = nv[e];
                 kx[e] = nx[e];
             }
-            if (b + 1 < a.nb) {
-                load_v(b + 1, nv);
-                load_kernel(a.kfirst + b + 1, nx);
+            if (t + 1 < nt) {
+                load_v(t + 1, nv);
+                load_kernel(acc_kernel(a, t + 1), nx);
             }
             __syncthreads();
             stages<N, TPP, -1, 1, RAD...>(sm, tw, p, q0, PITCH);
@@ -186,13 +192,17 @@ __global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
             stages<N, TPP, -1, 1, RAD...>(sm, tw, p, q0, PITCH);
 #pragma unroll
             for (int e = 0; e < EPT; ++e) acc[e] = cadd(acc[e], cmul(vr[e], sm[(q0 + e * TPP) * PITCH + p]));
-        }
-        if (ok)
+            if (t % a.nb == a.nb - 1) {   // end of a group: out += its sum, as separate launches would
+                if (ok)
 #pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                float2 *o = a.out + (int64_t)(q0 + e * TPP) * a.plane + g;
-                *o = cadd(*o, acc[e]);
+                    for (int e = 0; e < EPT; ++e) {
+                        float2 *o = a.out + (int64_t)(q0 + e * TPP) * a.plane + g;
+                        *o = cadd(*o, acc[e]);
+                    }
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) acc[e] = make_float2(0.f, 0.f);
             }
+        }
     }
 }
 
@@ -282,24 +292,29 @@ __global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void
         float2 acc[R1], nv[R1];
 #pragma unroll
         for (int r = 0; r < R1; ++r) acc[r] = make_float2(0.f, 0.f);
+        const int nt = (a.accgroups > 1 ? a.accgroups : 1) * a.nb;   // (group, bin) steps
         load_v(0, nv);
-        load_kernel(a.kfirst, nx);
-        for (int b = 0; b < a.nb; ++b) {
+        load_kernel(acc_kernel(a, 0), nx);
+        for (int t = 0; t < nt; ++t) {
             float2 v[R1], k[R1];
 #pragma unroll
             for (int r = 0; r < R1; ++r) { v[r] = nv[r]; k[r] = nx[r]; }
-            if (b + 1 < a.nb) { load_v(b + 1, nv); load_kernel(a.kfirst + b + 1, nx); }
+            if (t + 1 < nt) { load_v(t + 1, nv); load_kernel(acc_kernel(a, t + 1), nx); }
             transform(v, ex, std::integral_constant<int, -1>{});
             transform(k, ex, std::integral_constant<int, -1>{});
 #pragma unroll
             for (int r = 0; r < R1; ++r) acc[r] = cadd(acc[r], cmul(v[r], k[r]));
-        }
-        if (ok)
+            if (t % a.nb == a.nb - 1) {   // end of a group: out += its sum, as separate launches would
+                if (ok)
 #pragma unroll
-            for (int r = 0; r < R1; ++r) {
-                float2 *o = a.out + (int64_t)(q + R2 * r) * a.plane + g;
-                *o = cadd(*o, acc[r]);
+                    for (int r = 0; r < R1; ++r) {
+                        float2 *o = a.out + (int64_t)(q + R2 * r) * a.plane + g;
+                        *o = cadd(*o, acc[r]);
+                    }
+#pragma unroll
+                for (int r = 0; r < R1; ++r) acc[r] = make_float2(0.f, 0.f);
             }
+        }
         return;
     }
     float2 dr[R1];
@@ -368,25 +383,30 @@ __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
         float2 acc[R0], nv[R0];
 #pragma unroll
         for (int r = 0; r < R0; ++r) acc[r] = make_float2(0.f, 0.f);
+        const int nt = (a.accgroups > 1 ? a.accgroups : 1) * a.nb;   // (group, bin) steps
         load_v(0, nv);
-        load_kernel(a.kfirst, nx);
+        load_kernel(acc_kernel(a, 0), nx);
         __syncthreads();   // twiddle table
-        for (int b = 0; b < a.nb; ++b) {
+        for (int t = 0; t < nt; ++t) {
             float2 v[R0], k[R0];
 #pragma unroll
             for (int r = 0; r < R0; ++r) { v[r] = nv[r]; k[r] = nx[r]; }
-            if (b + 1 < a.nb) { load_v(b + 1, nv); load_kernel(a.kfirst + b + 1, nx); }
+            if (t + 1 < nt) { load_v(t + 1, nv); load_kernel(acc_kernel(a, t + 1), nx); }
             reg_stages<N, -1, R0, REST...>(v, ex[0], ex[1], tw, q, p, PITCH);
             reg_stages<N, -1, R0, REST...>(k, ex[0], ex[1], tw, q, p, PITCH);
 #pragma unroll
             for (int r = 0; r < R0; ++r) acc[r] = cadd(acc[r], cmul(v[r], k[r]));
-        }
-        if (ok)
+            if (t % a.nb == a.nb - 1) {   // end of a group: out += its sum, as separate launches would
+                if (ok)
 #pragma unroll
-            for (int r = 0; r < R0; ++r) {
-                float2 *o = a.out + (int64_t)(q + T * r) * a.plane + g;
-                *o = cadd(*o, acc[r]);
+                    for (int r = 0; r < R0; ++r) {
+                        float2 *o = a.out + (int64_t)(q + T * r) * a.plane + g;
+                        *o = cadd(*o, acc[r]);
+                    }
+#pragma unroll
+                for (int r = 0; r < R0; ++r) acc[r] = make_float2(0.f, 0.f);
             }
+        }
         return;
     }
     float2 dr[R0];

@@ -126,6 +126,10 @@ void layout_scratch(sb_plan *p) {
     size_t sc = 0;
     p->off_w = sc; sc += align256((size_t)p->max_ng * sizeof(float));
     p->off_dhat = sc; sc += align256((size_t)p->max_ng * sizeof(float2));
+    const bool adjoint = prob->ndim == 3 && prob->npcf == 3;
+    // the adjoint's v arrays directly before the coefficient arrays: its fused pass writes the v
+    // of each group into the slot before that group's coefficients
+    if (adjoint) { p->off_vtmp = sc; sc += align256((size_t)NB * p->max_ng * sizeof(float2)); }
     p->off_coef = sc; sc += align256((size_t)p->chunk_groups * NB * p->max_ng * sizeof(float2));
     int groups = 0, nvals = 0, nblocks = 0, tile_lo = 0, tile_hi = 0;
     p->contract_tile_range(&tile_lo, &tile_hi);
@@ -138,10 +142,7 @@ void layout_scratch(sb_plan *p) {
     p->off_part = sc; sc += align256((size_t)groups * nvals * nblocks * sizeof(double));
     p->off_tot = sc; sc += align256((size_t)groups * nvals * sizeof(double));
     p->off_grad = sc; sc += align256((size_t)p->max_ng * sizeof(float2));
-    if (prob->ndim == 3 && prob->npcf == 3) {
-        p->off_vtmp = sc; sc += align256((size_t)NB * p->max_ng * sizeof(float2));
-        p->off_dsum = sc; sc += align256((size_t)p->max_ng * sizeof(float));
-    }
+    if (adjoint) { p->off_dsum = sc; sc += align256((size_t)p->max_ng * sizeof(float)); }
     p->scratch_need = sc;
 }
 

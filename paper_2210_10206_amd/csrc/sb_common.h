@@ -80,8 +80,12 @@ struct Axis0Args {
     int nb;               // kernels per group (mode 0: per grid.y; mode 1: in this launch)
     int groups;           // grid.y (mode 0: kernel groups; mode 1: 1)
     int kfirst;           // mode 1: index of the first kernel of this launch
-    const int *kmap;      // mode 0, optional: kernel group of grid row y (kc is then the
-                          // whole kernel store; without it grid row y reads group y of kc)
+    int accgroups;        // mode 1: kernel groups accumulated in turn (0: one), nb arrays of vin
+                          // each; group i reads kernels kmap[i] * nb + b (with kmap) or
+                          // kfirst + i * nb + b, and out += its sum after every group
+    const int *kmap;      // optional: kernel group of grid row y (mode 0) or of accumulated
+                          // group i (mode 1); kc is then the whole kernel store (mode 0 without
+                          // it: grid row y reads group y of kc)
     const float2 *tw;
 };
 hipError_t launch_axis0(const Axis0Args &a, hipStream_t s);
