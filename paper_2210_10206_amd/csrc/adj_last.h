@@ -165,15 +165,24 @@ __global__ __launch_bounds__(NBT * R * TPP) void adj_last_kernel(AdjLastArgs a) 
 // N / R0 of pencil pp (= bin) holds elements q + T s of it, so the loads, both transforms and
 // the stores stay in registers and LDS is used for the stage exchanges and for the [cell][bin]
 // view of the per-cell phase.
+//
+// With two stages the transforms exchange through one buffer, which the [cell][bin] view then
+// reuses (one more barrier per row); that and at most 168 VGPRs (3 waves per SIMD) let four
+// 3-wave workgroups share a CU instead of two at 256 points and 12 padded bins.
+constexpr int adj_rs_min_waves(int nstage, int nt) { return nstage == 2 && nt >= 192 ? 3 : 1; }
+
 template <int N, int NBT, bool PACK, int R0, int... REST>
-__global__ __launch_bounds__(NBT * (N / R0)) void adj_rs_kernel(AdjLastArgs a) {
+__global__ __launch_bounds__(NBT * (N / R0), adj_rs_min_waves(1 + sizeof...(REST), NBT * (N / R0))) void adj_rs_kernel(
+    AdjLastArgs a) {
     constexpr int T = N / R0;
     constexpr int P = NBT, PITCH = P + 1, NT = P * T;
     constexpr int NSTAGE = 1 + sizeof...(REST);
-    constexpr int CSB = (NSTAGE - 1) % 2;       // buffer the last inverse stage does not read
+    constexpr bool ONE = NSTAGE == 2;           // one exchange buffer
+    constexpr int CSB = ONE ? 0 : (NSTAGE - 1) % 2;   // buffer of the [cell][bin] view
     constexpr int CPT = (N + NT - 1) / NT;      // cells per thread in the per-cell phase
     static_assert(NSTAGE >= 2, "two stages or more");
-    __shared__ float2 ex[2][N * PITCH];
+    __shared__ float2 ex[ONE ? 1 : 2][N * PITCH];
+    float2 *ex1 = ex[ONE ? 0 : 1];
     __shared__ float2 tw[N];
     __shared__ float G[(PACK ? 2 : 1) * NBT * NBT];   // NBT x NBT (each), zero beyond nb
     const int nb = a.nb;
@@ -216,8 +225,9 @@ __global__ __launch_bounds__(NBT * (N / R0)) void adj_rs_kernel(AdjLastArgs a) {
         for (int k = 0; k < CPT; ++k) { cw[k] = nw[k]; cd[k] = nd[k]; }
         if (row + 1 < r_end) load_row(row + 1, nx, nw, nd);   // next row in flight
         __syncthreads();                                       // the previous row's buffers are free
-        reg_stages<N, 1, R0, REST...>(v, ex[0], ex[1], tw, q, pp, PITCH);   // inverse
+        reg_stages<N, 1, R0, REST...>(v, ex[0], ex1, tw, q, pp, PITCH);   // inverse
         float2 *cs = ex[CSB];
+        if constexpr (ONE) __syncthreads();   // the last stage has read the exchange buffer
 #pragma unroll
         for (int r = 0; r < R0; ++r) cs[(q + T * r) * PITCH + pp] = v[r];
         __syncthreads();
@@ -251,7 +261,7 @@ __global__ __launch_bounds__(NBT * (N / R0)) void adj_rs_kernel(AdjLastArgs a) {
 #pragma unroll
         for (int r = 0; r < R0; ++r) v[r] = cs[(q + T * r) * PITCH + pp];
         __syncthreads();                                       // cs may be the first exchange buffer
-        reg_stages<N, -1, R0, REST...>(v, ex[0], ex[1], tw, q, pp, PITCH);  // forward
+        reg_stages<N, -1, R0, REST...>(v, ex[0], ex1, tw, q, pp, PITCH);  // forward
         if (live) {
             float2 *out = a.out + (int64_t)pp * a.ng + flip_row(row) * N;
 #pragma unroll
