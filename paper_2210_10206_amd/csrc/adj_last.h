@@ -31,6 +31,8 @@ struct AdjLastArgs {
     const float *w;         // density
     const double *gz;       // g_l (NB x NB)
     const double *gz2;      // packed groups: g_{l_b} for the imaginary parts (null: gz for both)
+    const float *gt;        // G_l as float, 16 x 16, zero beyond nb (register-resident form)
+    const float *gt2;       // packed groups: G_{l_b} likewise (null when gz2 is)
     float wm;               // 1 for m = 0, 2 for m > 0
     int nb;
     int64_t rows_per_block; // rows walked by one workgroup
@@ -164,7 +166,9 @@ __global__ __launch_bounds__(NBT * R * TPP) void adj_last_kernel(AdjLastArgs a) 
 // divides the first (reg_stages): a tile is one row of the NBT (padded) bins; thread q < T =
 // N / R0 of pencil pp (= bin) holds elements q + T s of it, so the loads, both transforms and
 // the stores stay in registers and LDS is used for the stage exchanges and for the [cell][bin]
-// view of the per-cell phase.
+// view of the per-cell phase.  The weights are read from the float table gt through the
+// constant address space: the addresses are uniform, so they become scalar loads and the
+// products take them from SGPRs instead of broadcast LDS reads (up to 2 x 144 per cell).
 //
 // With two stages the transforms exchange through one buffer, which the [cell][bin] view then
 // reuses (one more barrier per row); that and at most 168 VGPRs (3 waves per SIMD) let four
@@ -181,15 +185,17 @@ __global__ __launch_bounds__(NBT * (N / R0), adj_rs_min_waves(1 + sizeof...(REST
     constexpr int CSB = ONE ? 0 : (NSTAGE - 1) % 2;   // buffer of the [cell][bin] view
     constexpr int CPT = (N + NT - 1) / NT;      // cells per thread in the per-cell phase
     static_assert(NSTAGE >= 2, "two stages or more");
+    static_assert(NBT <= 16, "the weight table is 16 x 16");
     __shared__ float2 ex[ONE ? 1 : 2][N * PITCH];
     float2 *ex1 = ex[ONE ? 0 : 1];
     __shared__ float2 tw[N];
-    __shared__ float G[(PACK ? 2 : 1) * NBT * NBT];   // NBT x NBT (each), zero beyond nb
+    typedef const __attribute__((address_space(4))) float cfloat;
+    cfloat *G = (cfloat *)a.gt;                   // 16 x 16, zero beyond nb
+    cfloat *G2 = PACK ? (cfloat *)a.gt2 : G;
     const int nb = a.nb;
     const int tid = threadIdx.x;
     const int q = tid % T, pp = tid / T;         // element column, pencil (= bin)
     for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
-    load_weights<NBT, PACK>(G, a, tid, NT);
     const int64_t nrows = a.ng / N;
     const int64_t r_begin = (int64_t)blockIdx.x * a.rows_per_block;
     const int64_t r_end = min(r_begin + a.rows_per_block, nrows);
@@ -246,8 +252,8 @@ __global__ __launch_bounds__(NBT * (N / R0), adj_rs_min_waves(1 + sizeof...(REST
                 float hx = 0.f, hy = 0.f;
 #pragma unroll
                 for (int b2 = 0; b2 < NBT; ++b2) {
-                    const float g = G[b1 * NBT + b2];
-                    const float g2 = PACK ? G[NBT * NBT + b1 * NBT + b2] : g;
+                    const float g = G[b1 * 16 + b2];
+                    const float g2 = PACK ? G2[b1 * 16 + b2] : g;
                     hx = __builtin_fmaf(g, av[b2].x, hx);
                     hy = __builtin_fmaf(-g2, av[b2].y, hy);   // conj(a)
                 }

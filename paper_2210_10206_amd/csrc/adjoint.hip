@@ -73,6 +73,15 @@ __global__ void adj_finish_kernel(const float2 *U, const float *dsum, int ndim, 
     out[y] = dsum[y] + 2.f * U[yf].x;
 }
 
+// G_l = (g_l + g_l^T) / 2 of every l as float, 16 x 16 with zeros beyond nb
+__global__ void adj_weights_kernel(const double *gz, int nl, int nb, float *gt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nl * 256) return;
+    const int l = i / 256, b1 = i % 256 / 16, b2 = i % 16;
+    const double *g = gz + (int64_t)l * nb * nb;
+    gt[i] = (b1 < nb && b2 < nb) ? (float)(0.5 * (g[b1 * nb + b2] + g[b2 * nb + b1])) : 0.f;
+}
+
 __global__ void zero_c_kernel(float2 *x, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) x[i] = make_float2(0.f, 0.f);
@@ -115,6 +124,8 @@ sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta
     float2 *coef_w = reinterpret_cast<float2 *>(p->scratch + p->off_coef);
     const float2 *coef = coef_w;
     const float *w = reinterpret_cast<const float *>(p->scratch + p->off_w);
+    float *gtab = reinterpret_cast<float *>(p->scratch + p->off_gtab);
+    const int nl = p->prob.lmax + 1;
     for (int f = 0; f < p->batch; ++f) {
         if (!delta[f] || !grad_delta[f]) return fail(SB_EINVAL, "null field pointer");
         const ShapeGroup &G = p->groups[p->field_group[f]];
@@ -127,6 +138,9 @@ sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "adjoint zero");
         const double *gz_f = grad_zeta + (int64_t)f * p->zeta_doubles;
+        hipLaunchKernelGGL(adj_weights_kernel, dim3((nl * 256 + 255) / 256), dim3(256), 0, s, gz_f, nl, NB, gtab);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "adjoint weights");
         // groups: one per (l, m), or with the fused pass of a packed plan the forward's array
         // groups (the packed m = 0 pairs first)
         const bool packing = p->npack > 0 && p->adj_fused;
@@ -191,6 +205,8 @@ sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta
                     a.w = w;
                     a.gz = gz_f + (int64_t)l * NB * NB;
                     a.gz2 = l2 >= 0 ? gz_f + (int64_t)l2 * NB * NB : nullptr;
+                    a.gt = gtab + (int64_t)l * 256;
+                    a.gt2 = l2 >= 0 ? gtab + (int64_t)l2 * 256 : nullptr;
                     a.wm = m == 0 ? 1.f : 2.f;
                     a.nb = NB;
                     const int64_t nrows = G.ng / a.n;

@@ -142,7 +142,10 @@ void layout_scratch(sb_plan *p) {
     p->off_part = sc; sc += align256((size_t)groups * nvals * nblocks * sizeof(double));
     p->off_tot = sc; sc += align256((size_t)groups * nvals * sizeof(double));
     p->off_grad = sc; sc += align256((size_t)p->max_ng * sizeof(float2));
-    if (adjoint) { p->off_dsum = sc; sc += align256((size_t)p->max_ng * sizeof(float)); }
+    if (adjoint) {
+        p->off_dsum = sc; sc += align256((size_t)p->max_ng * sizeof(float));
+        p->off_gtab = sc; sc += align256((size_t)(prob->lmax + 1) * 256 * sizeof(float));   // G_l, 16 x 16
+    }
     p->scratch_need = sc;
 }
 

@@ -79,7 +79,7 @@ struct sb_plan {
     char *persist = nullptr, *scratch = nullptr;
     size_t persist_need = 0, scratch_need = 0;
     size_t off_w = 0, off_dhat = 0, off_coef = 0, off_part = 0, off_tot = 0, off_grad = 0;
-    size_t off_vtmp = 0, off_dsum = 0;
+    size_t off_vtmp = 0, off_dsum = 0, off_gtab = 0;
     // kernel groups ((l, m) multiplets) whose arrays share the scratch at once: all of them,
     // unless a 3PCF plan's full set would exceed coef_limit (then the passes run in chunks)
     uint64_t coef_limit = 48ull << 30;
