@@ -2,7 +2,7 @@
 
 This module holds no arithmetic of the correlation method itself: it only draws
 inputs.  The recipe stands in for the turbulent-ISM simulation cubes the paper
-measures (Sec. 3, the CATS MHD run), which are not available here:
+measures (Sec. 4, the CATS MHD run), which are not available here:
 
 1. white noise w ~ N(0, 1) in float64 from numpy's PCG64 with the given seed;
 2. g_hat = FFT(w) * sqrt(P(|k|)), k = 2*pi*fftfreq(N) per axis, P(0) = 0,
@@ -96,7 +96,7 @@ def c5_batch(count: int = 48, base_seed: int = 0):
 
 def sparse_unit_field(shape, count: int, seed: int, dtype=np.float64) -> np.ndarray:
     """Empty grid with ``count`` randomly chosen cells set to weight one (the
-    particle-on-grid inputs of the paper's validation, Sec. 3.2)."""
+    particle-on-grid inputs of the validation described in Sec. 2.5)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     n = int(np.prod(shape))
     idx = rng.choice(n, size=count, replace=False)

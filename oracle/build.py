@@ -11,7 +11,7 @@ def build(verbose: bool = False) -> str:
     src = os.path.join(_HERE, "core.c")
     out = os.path.join(_HERE, "_liboracle.so")
     tmp = out + ".tmp"
-    cmd = ["gcc", "-O3", "-march=x86-64-v3", "-fcx-limited-range", "-fopenmp", "-fPIC",
+    cmd = ["gcc", "-O3", "-march=x86-64-v3", "-ffp-contract=off", "-fcx-limited-range", "-fopenmp", "-fPIC",
            "-shared", "-Wall", "-o", tmp, src]
     if verbose:
         print(" ".join(cmd))

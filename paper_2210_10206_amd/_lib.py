@@ -7,10 +7,13 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsarabande_hip.so")
 
-SB_OK, SB_EINVAL, SB_EUNSUPPORTED, SB_EWORKSPACE, SB_EHIP, SB_ENOMEM, SB_ESTATE = 0, -1, -2, -3, -4, -5, -6
+SB_OK, SB_EINVAL, SB_EUNSUPPORTED, SB_EWORKSPACE, SB_EHIP, SB_ENOMEM, SB_ENONFINITE, SB_ESTATE = (
+    0, -1, -2, -3, -4, -5, -6, -7)
 SB_PREC_FP32, SB_PREC_SPLIT_BF16 = 0, 1
 SB_IN_F32, SB_IN_F64 = 0, 1
 SB_FLAG_KEEP_COEFFS, SB_FLAG_UNFUSED, SB_FLAG_NO_MFMA, SB_FLAG_ODD_PARITY, SB_FLAG_NO_PACK = 1, 2, 4, 8, 16
+SB_FLAG_CHECK_FINITE = 32
+SB_WARN_BOX_TRUNCATED = 1
 
 # Every function the header declares, with its ctypes signature.
 c_i32, c_i64, c_u32, c_dbl, c_vp, c_sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double,
@@ -44,10 +47,12 @@ SIGNATURES = {
     "sb_zeta_size": (c_i32, [c_vp, P(c_i64)]),
     "sb_zeta_index": (c_i32, [c_vp, P(c_i32), P(c_i32), P(P(c_i32))]),
     "sb_bin_counts": (c_i32, [c_vp, c_i32, P(c_i64)]),
+    "sb_plan_warnings": (c_i32, [c_vp, P(c_u32)]),
     "sb_forward": (c_i32, [c_vp, P(c_vp), c_vp, c_vp]),
+    "sb_normalize": (c_i32, [c_vp, P(c_vp), c_vp, c_vp, c_vp]),
     "sb_backward": (c_i32, [c_vp, P(c_vp), c_vp, P(c_vp), c_vp]),
     "sb_coeffs": (c_i32, [c_vp, c_i32, P(c_vp)]),
-    "sb_autotune": (c_i32, [c_vp, c_vp]),
+    "sb_autotune": (c_i32, [c_vp, c_vp, ctypes.c_char_p]),
     "sb_forward_graph": (c_i32, [c_vp, P(c_vp), c_vp, c_vp]),
     "sb_profile": (c_i32, [c_vp, c_i32]),
     "sb_stage_times": (c_i32, [c_vp, P(c_dbl), P(c_i32), P(c_dbl), P(c_i32)]),

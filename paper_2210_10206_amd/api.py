@@ -49,11 +49,12 @@ class Plan:
                  to a complex transform (False = one transform per (l, m))
     scratch_limit: bytes of kernel arrays a 3PCF plan keeps at once (default 48 GiB); above it
                  the passes run over chunks of (l, m) groups (sb_plan_set_scratch_limit)
+    check_finite: scan the inputs of every call for NaN / Inf first (SB_FLAG_CHECK_FINITE)
     """
 
     def __init__(self, shapes, bin_edges, lmax, npcf=3, precision="fp32", input_dtype=torch.float32,
                  device=None, stream=None, prepare=True, keep_coeffs=False, fused=True, mfma=True,
-                 scratch_limit=None, parity="even", pack=True):
+                 scratch_limit=None, parity="even", pack=True, check_finite=False):
         self.lib = _lib.load()
         shapes = [tuple(int(x) for x in s) for s in shapes]
         ndim = len(shapes[0])
@@ -72,7 +73,8 @@ class Plan:
                                (_lib.SB_FLAG_KEEP_COEFFS if keep_coeffs else 0) | (0 if fused else _lib.SB_FLAG_UNFUSED)
                                | (0 if mfma else _lib.SB_FLAG_NO_MFMA)
                                | (_lib.SB_FLAG_ODD_PARITY if parity == "odd" else 0)
-                               | (0 if pack else _lib.SB_FLAG_NO_PACK))
+                               | (0 if pack else _lib.SB_FLAG_NO_PACK)
+                               | (_lib.SB_FLAG_CHECK_FINITE if check_finite else 0))
         if parity not in ("even", "odd"):
             raise ValueError("parity must be 'even' or 'odd'")
         self.parity = parity
@@ -119,9 +121,12 @@ class Plan:
             check(self.lib.sb_prepare(self.handle, _stream_ptr(stream)), "sb_prepare")
         self.prepared = True
 
-    def autotune(self, stream=None):
+    def autotune(self, stream=None, cache_path=None):
+        """Time the launch shapes (sb_autotune); cache_path: JSON file of tuned choices, read
+        when it holds this plan's entry, extended otherwise."""
+        path = None if cache_path is None else str(cache_path).encode()
         with torch.cuda.device(self.device):
-            check(self.lib.sb_autotune(self.handle, _stream_ptr(stream)), "sb_autotune")
+            check(self.lib.sb_autotune(self.handle, _stream_ptr(stream), path), "sb_autotune")
 
     # ------------------------------------------------------------------ layout
     def zeta_index(self):
@@ -137,6 +142,13 @@ class Plan:
         check(self.lib.sb_bin_counts(self.handle, int(field), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
               "sb_bin_counts")
         return out
+
+    def warnings(self) -> int:
+        """SB_WARN_* bits of the plan (SB_WARN_BOX_TRUNCATED: the outer edge reaches half a grid
+        edge, so the zero-centred kernel support is cut by the box)."""
+        bits = ctypes.c_uint32()
+        check(self.lib.sb_plan_warnings(self.handle, ctypes.byref(bits)), "sb_plan_warnings")
+        return bits.value
 
     def zeta_shape(self):
         rows = self.zeta_index().shape[0]
@@ -182,10 +194,30 @@ class Plan:
             return torch.view_as_complex(raw.reshape((b,) + shp + (2,)))
         return raw.reshape((b,) + shp)
 
+    def normalize_raw(self, deltas, raw, stream=None, want_norm=False):
+        """Divide a raw result buffer (batch, zeta_doubles), in place on the device, by the N of
+        Sec. 2.5 of each field (sb_normalize); optionally return the factors (batch, nb, nb[, nb])."""
+        self._check_fields(deltas)
+        if tuple(raw.shape) != (len(self.shapes), self.zeta_doubles) or raw.dtype != torch.float64 \
+                or raw.device != self.device or not raw.is_contiguous():
+            raise ValueError("raw must be the contiguous (batch, zeta_doubles) float64 result of this plan")
+        nt = self.nbins ** (self.npcf - 1)
+        norm = torch.empty((len(self.shapes), nt), dtype=torch.float64, device=self.device) if want_norm else None
+        with torch.cuda.device(self.device):
+            check(self.lib.sb_normalize(self.handle, self._ptrs(deltas), ctypes.c_void_p(raw.data_ptr()),
+                                        ctypes.c_void_p(norm.data_ptr() if norm is not None else None),
+                                        _stream_ptr(stream)), "sb_normalize")
+        if norm is not None:
+            return norm.reshape((len(self.shapes),) + (self.nbins,) * (self.npcf - 1))
+        return None
+
     def backward(self, deltas, grad_zeta, stream=None):
         """d loss / d delta for the full 3PCF given d loss / d Z (batch, lmax+1, nb, nb) float64."""
         self._check_fields(deltas)
         gz = grad_zeta.to(device=self.device, dtype=torch.float64).contiguous()
+        if gz.numel() != len(self.shapes) * self.zeta_doubles:
+            raise ValueError(f"grad_zeta has {gz.numel()} values; this plan needs "
+                             f"{len(self.shapes)} x {self.zeta_doubles}")
         grads = [torch.empty(s, dtype=torch.float32, device=self.device) for s in self.shapes]
         with torch.cuda.device(self.device):
             check(self.lib.sb_backward(self.handle, self._ptrs(deltas), ctypes.c_void_p(gz.data_ptr()),
@@ -260,17 +292,11 @@ class Plan:
 
 
 def normalization(plan: Plan, deltas, field: int = 0) -> np.ndarray:
-    """Sec. 2.5: N = N_gal prod_{n=1}^{N-1} nbar V_bin,n with unit cells (box side = grid
-    resolution, as in the paper's validation): V_bin = cells in bin, nbar = N_gal / N_g,
-    N_gal = sum (delta + 1).  Returned with the broadcast shape of the result's bin axes."""
-    d = deltas[field]
-    ng = float(np.prod(plan.shapes[field]))
-    ngal = float(torch.sum(d.to(torch.float64)).item()) + ng
-    nbar = ngal / ng
-    v = plan.bin_counts(field).astype(np.float64)
-    if plan.npcf == 3:
-        return ngal * (nbar * v)[:, None] * (nbar * v)[None, :]
-    return ngal * (nbar * v)[:, None, None] * (nbar * v)[None, :, None] * (nbar * v)[None, None, :]
+    """The N of Sec. 2.5 of one field (sb_normalize: N_gal = sum (delta + 1) on the device, unit
+    cells, V_bin = cells in bin, nbar = N_gal / N_g), shaped like the result's bin axes."""
+    raw = torch.zeros((len(plan.shapes), plan.zeta_doubles), dtype=torch.float64, device=plan.device)
+    norm = plan.normalize_raw(deltas, raw, want_norm=True)
+    return norm[field].cpu().numpy()
 
 
 def measure(delta, bin_edges, lmax, projected=False, npcf=3, precision="fp32", normalized=False):
@@ -288,10 +314,11 @@ def measure(delta, bin_edges, lmax, projected=False, npcf=3, precision="fp32", n
         raise ValueError("projected=True needs a 2D field, projected=False a 3D field")
     plan = Plan([tuple(delta.shape)], bin_edges, lmax, npcf=npcf, precision=precision,
                 input_dtype=delta.dtype, device=delta.device)
-    z = plan.forward([delta])[0]
-    idx = plan.zeta_index()
+    raw = plan.forward_raw([delta])
     if normalized:
-        z = z / torch.as_tensor(normalization(plan, [delta]), device=z.device)
+        plan.normalize_raw([delta], raw)
+    z = plan.unpack(raw)[0]
+    idx = plan.zeta_index()
     torch.cuda.synchronize(delta.device)
     plan.close()
     return z, idx

@@ -12,6 +12,8 @@
 #include "sb_plan.h"
 #include "adj_last.h"
 
+#include <vector>
+
 namespace sb {
 namespace {
 
@@ -126,8 +128,19 @@ sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta
     const float *w = reinterpret_cast<const float *>(p->scratch + p->off_w);
     float *gtab = reinterpret_cast<float *>(p->scratch + p->off_gtab);
     const int nl = p->prob.lmax + 1;
-    for (int f = 0; f < p->batch; ++f) {
+    for (int f = 0; f < p->batch; ++f)
         if (!delta[f] || !grad_delta[f]) return fail(SB_EINVAL, "null field pointer");
+    if (p->prob.flags & SB_FLAG_CHECK_FINITE) {
+        std::vector<const void *> in(delta, delta + p->batch);
+        std::vector<int64_t> n;
+        std::vector<int> dt(p->batch, p->prob.input_dtype);
+        for (int f = 0; f < p->batch; ++f) n.push_back(p->groups[p->field_group[f]].ng);
+        in.push_back(grad_zeta);
+        n.push_back((int64_t)p->batch * p->zeta_doubles);
+        dt.push_back(1);
+        if (sb_status st = check_finite(p, (int)in.size(), in.data(), n.data(), dt.data(), s); st != SB_OK) return st;
+    }
+    for (int f = 0; f < p->batch; ++f) {
         const ShapeGroup &G = p->groups[p->field_group[f]];
         const float2 *khat = reinterpret_cast<const float2 *>(p->persist + G.khat_off);
         sb_status st = density_spectrum(p, G, delta[f], s);

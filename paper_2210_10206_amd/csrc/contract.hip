@@ -11,6 +11,8 @@
 //  proj4 : sum_x w(x) c_m1 c_m2 c_m3 for one canonical (m1, m2) (projected 4PCF, Alg. 8)
 #include "sb_kgen.h"
 
+#include <algorithm>
+
 namespace sb {
 namespace {
 
@@ -274,6 +276,70 @@ __global__ void to_f32_kernel(const void *in, int dtype, int64_t n, float *out) 
     out[i] = dtype == 1 ? (float)reinterpret_cast<const double *>(in)[i] : reinterpret_cast<const float *>(in)[i];
 }
 
+// ----------------------------------------------------------------- input checks
+// count[0] += number of NaN / Inf values among n float32 (dtype 0) or float64 (dtype 1) values
+__global__ void nonfinite_kernel(const void *in, int dtype, int64_t n, unsigned int *count) {
+    unsigned int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const bool ok = dtype == 1 ? isfinite(reinterpret_cast<const double *>(in)[i])
+                                   : isfinite(reinterpret_cast<const float *>(in)[i]);
+        bad += ok ? 0u : 1u;
+    }
+    for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o, 64);
+    if ((threadIdx.x & 63) == 0 && bad) atomicAdd(count, bad);
+}
+
+__global__ void fill_u32_kernel(unsigned int *x, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0u;
+}
+
+// ----------------------------------------------------------------- normalization (Sec. 2.5)
+// Block partials of sum_x delta(x) in float64: block b sums cells [b * chunk, (b + 1) * chunk).
+__global__ __launch_bounds__(256) void density_sum_kernel(const void *in, int dtype, int64_t n, int64_t chunk,
+                                                          double *partial) {
+    __shared__ double red[4];
+    const int64_t c0 = (int64_t)blockIdx.x * chunk;
+    const int64_t c1 = min(c0 + chunk, n);
+    double s = 0.0;
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += 256)
+        s += dtype == 1 ? reinterpret_cast<const double *>(in)[i] : (double)reinterpret_cast<const float *>(in)[i];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// One block: N_gal = sum (delta + 1) from the partials (fixed order), nbar = N_gal / N_g and
+// norm[t] = N_gal prod_i nbar V_{b_i} for every bin tuple t of (npcf - 1) bins; then every value
+// of the field's result (rows x tuples x parts) is divided by the norm of its tuple.
+__global__ __launch_bounds__(256) void normalize_kernel(const double *partial, int nparts, int64_t ng, NormArgs a,
+                                                         double *zeta, int64_t nvals, double *norm_out) {
+    __shared__ double s_ngal;
+    __shared__ double s_norm[kMaxBins * kMaxBins * kMaxBins];
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < nparts; ++i) s += partial[i];
+        s_ngal = s + (double)ng;
+    }
+    __syncthreads();
+    const double ngal = s_ngal, nbar = ngal / (double)ng;
+    int ntup = 1;
+    for (int k = 0; k < a.order; ++k) ntup *= a.nbins;
+    for (int t = threadIdx.x; t < ntup; t += blockDim.x) {
+        double v = ngal;
+        int rem = t;
+        for (int k = 0; k < a.order; ++k) {
+            v *= nbar * a.vbin[rem % a.nbins];
+            rem /= a.nbins;
+        }
+        s_norm[t] = v;
+        if (norm_out) norm_out[t] = v;
+    }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < nvals; i += blockDim.x) zeta[i] /= s_norm[(i / a.parts) % ntup];
+}
+
 }  // namespace
 
 hipError_t launch_pair_contract(const PairArgs &a, hipStream_t s) {
@@ -347,6 +413,28 @@ hipError_t launch_gather(const double *src, const int *ptr, const int *idx, cons
 
 hipError_t launch_to_f32(const void *in, int dtype, int64_t n, float *out, hipStream_t s) {
     hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, dtype, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_nonfinite(const void *in, int dtype, int64_t n, unsigned int *count, hipStream_t s) {
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    if (blocks > 0) hipLaunchKernelGGL(nonfinite_kernel, dim3((unsigned)blocks), dim3(256), 0, s, in, dtype, n, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(unsigned int *x, int n, hipStream_t s) {
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, x, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_normalize(const void *delta, int dtype, int64_t ng, const NormArgs &a, double *partial,
+                            double *zeta, int64_t nvals, double *norm_out, hipStream_t s) {
+    const int nparts = kNormParts;
+    const int64_t chunk = (ng + nparts - 1) / nparts;
+    hipLaunchKernelGGL(density_sum_kernel, dim3(nparts), dim3(256), 0, s, delta, dtype, ng, chunk, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(256), 0, s, partial, nparts, ng, a, zeta, nvals, norm_out);
     return hipGetLastError();
 }
 

@@ -139,14 +139,40 @@ void layout_scratch(sb_plan *p) {
             const int64_t nrows = G.ng / G.n[prob->ndim - 1];
             nblocks = std::max<int>(nblocks, (int)((nrows + G.rows_per_block - 1) / G.rows_per_block));
         }
-    p->off_part = sc; sc += align256((size_t)groups * nvals * nblocks * sizeof(double));
+    p->off_part = sc;
+    sc += align256(std::max<size_t>((size_t)groups * nvals * nblocks, kNormParts) * sizeof(double));
     p->off_tot = sc; sc += align256((size_t)groups * nvals * sizeof(double));
     p->off_grad = sc; sc += align256((size_t)p->max_ng * sizeof(float2));
+    p->off_flag = sc; sc += 256;
+    p->off_zt = sc; sc += align256((size_t)p->zeta_doubles * sizeof(double));
     if (adjoint) {
         p->off_dsum = sc; sc += align256((size_t)p->max_ng * sizeof(float));
         p->off_gtab = sc; sc += align256((size_t)(prob->lmax + 1) * 256 * sizeof(float));   // G_l, 16 x 16
     }
     p->scratch_need = sc;
+}
+
+// Device addresses of the tables in the bound persistent buffer (filled by sb_prepare).
+static void table_pointers(sb_plan *p) {
+    char *base = p->persist;
+    p->tw.clear();
+    for (auto &kv : p->tw_off) p->tw[kv.first] = reinterpret_cast<const float2 *>(base + kv.second);
+    if (p->prob.npcf == 4 && p->prob.ndim == 3) {
+        p->d_terms = reinterpret_cast<const QuadTerm *>(base + p->off_terms);
+        p->d_term_ptr = reinterpret_cast<const int *>(base + p->off_tptr);
+        p->d_lam_l = reinterpret_cast<const int *>(base + p->off_laml);
+        p->d_stage = reinterpret_cast<const int *>(base + p->off_stage);
+        p->d_coefw = reinterpret_cast<const float *>(base + p->off_coefw);
+    }
+    if (p->prob.npcf == 4 && p->prob.ndim == 2) p->d_pairs = reinterpret_cast<const int *>(base + p->off_pairs);
+    if (p->npack > 0) {
+        p->d_kmap = reinterpret_cast<const int *>(base + p->off_kmap);
+        p->d_rowmap = reinterpret_cast<const int *>(base + p->off_rowmap);
+        p->d_lmsrc = reinterpret_cast<const int *>(base + p->off_lmsrc);
+    }
+    p->d_gptr = reinterpret_cast<const int *>(base + p->off_gptr);
+    p->d_gidx = reinterpret_cast<const int *>(base + p->off_gidx);
+    p->d_gcoef = reinterpret_cast<const double *>(base + p->off_gcoef);
 }
 
 sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shapes, sb_plan **out) {
@@ -310,28 +336,27 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
         p->idx_cols = 2;
         for (const auto &pr : p->p4_pairs) { p->idx_table.push_back(pr.first); p->idx_table.push_back(pr.second); }
     }
-    // ---- device tables: twiddles per distinct length, 4PCF terms, gather map
+    // ---- device tables: twiddles per distinct length, 4PCF terms, gather map.  Built on the
+    // host here; sb_prepare copies them into the head of the caller's persistent buffer.
     std::vector<int> lens;
     for (const auto &G : p->groups)
         for (int d = 0; d < prob->ndim; ++d)
             if (std::find(lens.begin(), lens.end(), (int)G.n[d]) == lens.end()) lens.push_back((int)G.n[d]);
-    std::vector<char> host;
+    std::vector<char> &host = p->host_tab;
     auto put = [&](const void *src, size_t bytes) {
         const size_t off = align256(host.size());
         host.resize(off + bytes);
         if (bytes) std::memcpy(host.data() + off, src, bytes);
         return off;
     };
-    std::map<int, size_t> tw_off;
     for (int n : lens) {
         std::vector<float2> tw(n);
         for (int j = 0; j < n; ++j) {
             const double ang = -2.0 * M_PI * (double)j / (double)n;
             tw[j] = make_float2((float)std::cos(ang), (float)std::sin(ang));
         }
-        tw_off[n] = put(tw.data(), tw.size() * sizeof(float2));
+        p->tw_off[n] = put(tw.data(), tw.size() * sizeof(float2));
     }
-    size_t off_terms = 0, off_tptr = 0, off_laml = 0, off_stage = 0, off_pairs = 0, off_coefw = 0;
     if (prob->npcf == 4 && prob->ndim == 3) {
         std::vector<QuadTerm> terms;
         std::vector<int> tptr(1, 0), laml, stage;
@@ -367,60 +392,42 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
             p->max_cols = std::max(p->max_cols, ncol);
             stage.insert(stage.end(), st.begin(), st.end());
         }
-        off_terms = put(terms.data(), terms.size() * sizeof(QuadTerm));
-        off_tptr = put(tptr.data(), tptr.size() * sizeof(int));
-        off_laml = put(laml.data(), laml.size() * sizeof(int));
-        off_stage = put(stage.data(), stage.size() * sizeof(int));
-        off_coefw = put(coefw.data(), coefw.size() * sizeof(float));
+        p->off_terms = put(terms.data(), terms.size() * sizeof(QuadTerm));
+        p->off_tptr = put(tptr.data(), tptr.size() * sizeof(int));
+        p->off_laml = put(laml.data(), laml.size() * sizeof(int));
+        p->off_stage = put(stage.data(), stage.size() * sizeof(int));
+        p->off_coefw = put(coefw.data(), coefw.size() * sizeof(float));
+        p->quad_mfma = (prob->flags & SB_FLAG_NO_MFMA) == 0;
+        for (const Lam &C : p->f4.canon) p->quad_mfma &= quad_mfma_available(C.l[0], C.l[1], C.l[2], prob->nbins);
     }
     if (prob->npcf == 4 && prob->ndim == 2) {
         std::vector<int> pr;
         for (const auto &x : p->p4_canon) { pr.push_back(x.first); pr.push_back(x.second); }
-        off_pairs = put(pr.data(), pr.size() * sizeof(int));
+        p->off_pairs = put(pr.data(), pr.size() * sizeof(int));
     }
-    size_t off_kmap = 0, off_rowmap = 0, off_lmsrc = 0;
     if (p->npack > 0) {
-        off_kmap = put(p->ag_kmap.data(), p->ag_kmap.size() * sizeof(int));
-        off_rowmap = put(p->ag_rowmap.data(), p->ag_rowmap.size() * sizeof(int));
-        off_lmsrc = put(p->lm_src.data(), p->lm_src.size() * sizeof(int));
+        p->off_kmap = put(p->ag_kmap.data(), p->ag_kmap.size() * sizeof(int));
+        p->off_rowmap = put(p->ag_rowmap.data(), p->ag_rowmap.size() * sizeof(int));
+        p->off_lmsrc = put(p->lm_src.data(), p->lm_src.size() * sizeof(int));
     }
     std::vector<int> gptr, gidx;
     std::vector<double> gcoef;
     build_gather(p, gptr, gidx, gcoef);
     p->gather_nout = (int)gptr.size() - 1;
-    const size_t off_gptr = put(gptr.data(), gptr.size() * sizeof(int));
-    const size_t off_gidx = put(gidx.data(), gidx.size() * sizeof(int));
-    const size_t off_gcoef = put(gcoef.data(), gcoef.size() * sizeof(double));
-    hipError_t e = hipMalloc(&p->dtab, align256(host.size()) + 256);
-    if (e != hipSuccess) { delete p; return hip_fail(e, "hipMalloc(tables)"); }
-    e = hipMemcpy(p->dtab, host.data(), host.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) { (void)hipFree(p->dtab); delete p; return hip_fail(e, "hipMemcpy(tables)"); }
-    char *base = static_cast<char *>(p->dtab);
-    for (auto &kv : tw_off) p->tw[kv.first] = reinterpret_cast<const float2 *>(base + kv.second);
-    if (prob->npcf == 4 && prob->ndim == 3) {
-        p->d_terms = reinterpret_cast<const QuadTerm *>(base + off_terms);
-        p->d_term_ptr = reinterpret_cast<const int *>(base + off_tptr);
-        p->d_lam_l = reinterpret_cast<const int *>(base + off_laml);
-        p->d_stage = reinterpret_cast<const int *>(base + off_stage);
-        p->d_coefw = reinterpret_cast<const float *>(base + off_coefw);
-        p->quad_mfma = (prob->flags & SB_FLAG_NO_MFMA) == 0;
-        for (const Lam &C : p->f4.canon) p->quad_mfma &= quad_mfma_available(C.l[0], C.l[1], C.l[2], prob->nbins);
-    }
-    if (prob->npcf == 4 && prob->ndim == 2) p->d_pairs = reinterpret_cast<const int *>(base + off_pairs);
-    if (p->npack > 0) {
-        p->d_kmap = reinterpret_cast<const int *>(base + off_kmap);
-        p->d_rowmap = reinterpret_cast<const int *>(base + off_rowmap);
-        p->d_lmsrc = reinterpret_cast<const int *>(base + off_lmsrc);
-    }
-    p->d_gptr = reinterpret_cast<const int *>(base + off_gptr);
-    p->d_gidx = reinterpret_cast<const int *>(base + off_gidx);
-    p->d_gcoef = reinterpret_cast<const double *>(base + off_gcoef);
+    p->off_gptr = put(gptr.data(), gptr.size() * sizeof(int));
+    p->off_gidx = put(gidx.data(), gidx.size() * sizeof(int));
+    p->off_gcoef = put(gcoef.data(), gcoef.size() * sizeof(double));
+    p->tab_bytes = align256(host.size());
     // ---- kernel support along axis 0, fused-pass tiling, workspace layout
     int64_t r0 = 0;
     while ((r0 + 1) * (r0 + 1) <= p->thr[NB]) ++r0;      // largest |c_0| with c_0^2 <= e_max^2
     p->fused = (prob->flags & (SB_FLAG_UNFUSED | SB_FLAG_KEEP_COEFFS)) == 0;
     p->adj_fused = (prob->flags & SB_FLAG_UNFUSED) == 0;
-    size_t pers = 0;
+    // an offset coordinate of magnitude r0 with 2 r0 >= N does not fit the zero-centred box
+    for (const auto &G : p->groups)
+        for (int d = 0; d < prob->ndim; ++d)
+            if (2 * r0 >= G.n[d]) p->warnings |= SB_WARN_BOX_TRUNCATED;
+    size_t pers = p->tab_bytes;
     for (auto &G : p->groups) {
         G.plane = G.ng / G.n[0];
         G.r0 = (int)std::min<int64_t>(r0, G.n[0]);
@@ -439,6 +446,23 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
         }
     }
     p->persist_need = pers;
+    // split-BF16 exists for the contractions on the matrix cores only
+    if (prob->precision == SB_PREC_SPLIT_BF16) {
+        bool ok = true;
+        if (prob->npcf == 3) {
+            ok = p->fused;
+            for (const auto &G : p->groups) ok &= G.rows > 0;
+        } else if (prob->ndim == 3) {
+            ok = p->quad_mfma;
+        } else {
+            ok = (prob->flags & SB_FLAG_NO_MFMA) == 0;
+        }
+        if (!ok) {
+            delete p;
+            return fail(SB_EUNSUPPORTED, "split-BF16 applies to the contractions on the matrix cores; this path has "
+                                         "no split form");
+        }
+    }
     layout_scratch(p);
     *out = p;
     return SB_OK;
@@ -496,6 +520,9 @@ sb_status fft_all_axes(sb_plan *p, const ShapeGroup &G, int sign, int first_load
 sb_status prepare(sb_plan *p, hipStream_t s) {
     if (!p->persist || !p->scratch) return fail(SB_EWORKSPACE, "workspace not bound");
     const int nd = p->prob.ndim;
+    // the plan's tables go to the head of the persistent buffer (the host copy stays with the plan)
+    hipError_t te = hipMemcpyAsync(p->persist, p->host_tab.data(), p->host_tab.size(), hipMemcpyHostToDevice, s);
+    if (te != hipSuccess) return hip_fail(te, "table upload");
     for (auto &G : p->groups) {
         float2 *kc = reinterpret_cast<float2 *>(p->persist + G.khat_off);
         const int64_t ncell = (int64_t)G.np * G.plane;
@@ -767,13 +794,48 @@ sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
     return SB_OK;
 }
 
+sb_status check_finite(sb_plan *p, int count, const void *const *in, const int64_t *n, const int *dtype,
+                       hipStream_t s) {
+    if ((p->prob.flags & SB_FLAG_CHECK_FINITE) == 0) return SB_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        return fail(SB_ESTATE, "the finite-value scan waits for the stream and cannot be captured");
+    unsigned int *cnt = reinterpret_cast<unsigned int *>(p->scratch + p->off_flag);
+    hipError_t e = launch_zero_u32(cnt, 1, s);
+    for (int i = 0; i < count && e == hipSuccess; ++i) e = launch_count_nonfinite(in[i], dtype[i], n[i], cnt, s);
+    unsigned int host = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&host, cnt, sizeof(host), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "finite-value scan");
+    if (host) return fail(SB_ENONFINITE, std::to_string(host) + " NaN / Inf input values");
+    return SB_OK;
+}
+
+// The densities of every field as scan inputs (plus one extra array when extra != nullptr).
+static sb_status check_fields_finite(sb_plan *p, const void *const *delta, hipStream_t s,
+                                     const void *extra = nullptr, int64_t extra_n = 0) {
+    if ((p->prob.flags & SB_FLAG_CHECK_FINITE) == 0) return SB_OK;
+    std::vector<const void *> in(delta, delta + p->batch);
+    std::vector<int64_t> n;
+    std::vector<int> dt(p->batch, p->prob.input_dtype);
+    for (int f = 0; f < p->batch; ++f) n.push_back(p->groups[p->field_group[f]].ng);
+    if (extra) {
+        in.push_back(extra);
+        n.push_back(extra_n);
+        dt.push_back(1);
+    }
+    return check_finite(p, (int)in.size(), in.data(), n.data(), dt.data(), s);
+}
+
 sb_status forward(sb_plan *p, const void *const *delta, double *zeta, hipStream_t s) {
     if (!p) return fail(SB_EINVAL, "null plan");
     if (!delta || !zeta) return fail(SB_EINVAL, "null pointer");
     if (!p->persist || !p->scratch) return fail(SB_EWORKSPACE, "workspace not bound");
     if (!p->prepared) return fail(SB_ESTATE, "sb_prepare has not run on the bound workspace");
-    for (int f = 0; f < p->batch; ++f) {
+    for (int f = 0; f < p->batch; ++f)
         if (!delta[f]) return fail(SB_EINVAL, "null field pointer");
+    if (sb_status st = check_fields_finite(p, delta, s); st != SB_OK) return st;
+    for (int f = 0; f < p->batch; ++f) {
         double *zf = zeta + (int64_t)f * p->zeta_doubles;
         const ShapeGroup &G = p->groups[p->field_group[f]];
         sb_status st;
@@ -807,7 +869,6 @@ void sb_plan_destroy(sb_plan *plan) {
     if (!plan) return;
     plan->release_graph();
     plan->release_timing();
-    if (plan->dtab) (void)hipFree(plan->dtab);
     delete plan;
 }
 
@@ -836,6 +897,7 @@ sb_status sb_plan_bind(sb_plan *p, void *persistent, size_t persistent_bytes, vo
         return fail(SB_EINVAL, "workspace must be 256-byte aligned");
     p->persist = static_cast<char *>(persistent);
     p->scratch = static_cast<char *>(scratch);
+    table_pointers(p);
     p->prepared = false;
     p->release_graph();
     return SB_OK;
@@ -872,6 +934,37 @@ sb_status sb_forward(sb_plan *p, const void *const *delta, double *zeta, void *s
     return forward(p, delta, zeta, static_cast<hipStream_t>(stream));
 }
 
+sb_status sb_normalize(sb_plan *p, const void *const *delta, double *zeta, double *norm, void *stream) {
+    if (!p || !delta || !zeta) return fail(SB_EINVAL, "null argument");
+    if (!p->scratch) return fail(SB_EWORKSPACE, "workspace not bound");
+    for (int f = 0; f < p->batch; ++f)
+        if (!delta[f]) return fail(SB_EINVAL, "null field pointer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (sb_status st = check_fields_finite(p, delta, s); st != SB_OK) return st;
+    NormArgs a{};
+    a.nbins = p->prob.nbins;
+    a.order = p->prob.npcf - 1;
+    a.parts = p->prob.ndim == 2 ? 2 : 1;
+    int64_t ntup = 1;
+    for (int k = 0; k < a.order; ++k) ntup *= a.nbins;
+    double *partial = reinterpret_cast<double *>(p->scratch + p->off_part);
+    for (int f = 0; f < p->batch; ++f) {
+        const ShapeGroup &G = p->groups[p->field_group[f]];
+        for (int b = 0; b < a.nbins; ++b) a.vbin[b] = (double)G.counts[b];
+        const hipError_t e = launch_normalize(delta[f], p->prob.input_dtype, G.ng, a, partial,
+                                              zeta + (int64_t)f * p->zeta_doubles, p->zeta_doubles,
+                                              norm ? norm + (int64_t)f * ntup : nullptr, s);
+        if (e != hipSuccess) return hip_fail(e, "normalization");
+    }
+    return SB_OK;
+}
+
+sb_status sb_plan_warnings(const sb_plan *p, uint32_t *bits) {
+    if (!p || !bits) return fail(SB_EINVAL, "null argument");
+    *bits = p->warnings;
+    return SB_OK;
+}
+
 sb_status sb_coeffs(const sb_plan *p, int32_t k, const void **ptr) {
     if (!p || !ptr) return fail(SB_EINVAL, "null argument");
     if (k < 0 || k >= p->nk) return fail(SB_EINVAL, "kernel index out of range");
@@ -888,6 +981,7 @@ const char *sb_status_str(sb_status s) {
         case SB_EWORKSPACE: return "workspace missing or too small";
         case SB_EHIP: return "HIP runtime error";
         case SB_ENOMEM: return "out of host memory";
+        case SB_ENONFINITE: return "non-finite input";
         case SB_ESTATE: return "call out of order";
         default: return "unknown status";
     }

@@ -125,4 +125,22 @@ hipError_t launch_gather(const double *src, const int *ptr, const int *idx, cons
 // ---- density ingest: float32 copy of the field (and float64 -> float32 cast)
 hipError_t launch_to_f32(const void *in, int dtype, int64_t n, float *out, hipStream_t s);
 
+// ---- input check: count[0] += NaN / Inf values among n float32 (dtype 0) or float64 (1) values
+hipError_t launch_count_nonfinite(const void *in, int dtype, int64_t n, unsigned int *count, hipStream_t s);
+hipError_t launch_zero_u32(unsigned int *x, int n, hipStream_t s);
+
+// ---- normalization of Sec. 2.5: N_gal = sum (delta + 1) by a float64 reduction in a fixed
+//      order (kNormParts block partials, then one block), nbar = N_gal / N_g, and per bin tuple
+//      t = (b_1 .. b_order) (b_1 slowest) norm[t] = N_gal prod_i nbar vbin[b_i]; every value of
+//      the field's result, taken as rows x tuples x parts, is divided by the norm of its tuple.
+constexpr int kNormParts = 1024;
+struct NormArgs {
+    int nbins;
+    int order;                 // npcf - 1 bins per tuple
+    int parts;                 // 2 for complex results, else 1
+    double vbin[kMaxBins];     // V_bin: offsets per bin (unit cells)
+};
+hipError_t launch_normalize(const void *delta, int dtype, int64_t ng, const NormArgs &a, double *partial,
+                            double *zeta, int64_t nvals, double *norm_out, hipStream_t s);
+
 }  // namespace sb

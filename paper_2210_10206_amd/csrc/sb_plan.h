@@ -66,8 +66,13 @@ struct sb_plan {
     sb::Full4Plan f4;
     std::vector<std::pair<int, int>> p4_pairs, p4_canon;
     std::map<std::pair<int, int>, int> p4_canon_index;
-    // device tables (owned)
-    void *dtab = nullptr;
+    // device tables: built on the host at creation, copied into the head of the caller's
+    // persistent buffer by sb_prepare (tab_bytes bytes; the kernel spectra follow)
+    std::vector<char> host_tab;
+    size_t tab_bytes = 0;
+    std::map<int, size_t> tw_off;
+    size_t off_terms = 0, off_tptr = 0, off_laml = 0, off_stage = 0, off_pairs = 0, off_coefw = 0;
+    size_t off_kmap = 0, off_rowmap = 0, off_lmsrc = 0, off_gptr = 0, off_gidx = 0, off_gcoef = 0;
     std::map<int, const float2 *> tw;
     const sb::QuadTerm *d_terms = nullptr;
     const int *d_term_ptr = nullptr, *d_lam_l = nullptr, *d_stage = nullptr, *d_pairs = nullptr;
@@ -80,6 +85,9 @@ struct sb_plan {
     size_t persist_need = 0, scratch_need = 0;
     size_t off_w = 0, off_dhat = 0, off_coef = 0, off_part = 0, off_tot = 0, off_grad = 0;
     size_t off_vtmp = 0, off_dsum = 0, off_gtab = 0;
+    size_t off_flag = 0;          // 256 B: the non-finite counter of SB_FLAG_CHECK_FINITE
+    size_t off_zt = 0;            // one field's result: the autotuner's output buffer
+    uint32_t warnings = 0;        // SB_WARN_* bits
     // kernel groups ((l, m) multiplets) whose arrays share the scratch at once: all of them,
     // unless a 3PCF plan's full set would exceed coef_limit (then the passes run in chunks)
     uint64_t coef_limit = 48ull << 30;
@@ -165,6 +173,11 @@ sb_status coefficients(sb_plan *p, int f, int g0, int ngroups, hipStream_t s, bo
                        const int *kmap = nullptr);
 void layout_scratch(sb_plan *p);
 sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s);
+// SB_FLAG_CHECK_FINITE: count the NaN / Inf values of the inputs (n[i] values of dtype[i] at in[i]),
+// wait for the stream and return SB_ENONFINITE when there are any; SB_OK otherwise (and at once
+// when the flag is clear).
+sb_status check_finite(sb_plan *p, int count, const void *const *in, const int64_t *n, const int *dtype,
+                       hipStream_t s);
 // FFT passes over the listed axes (in order) of arrays with extents n[0..ndim) and ncell
 // cells; the first pass reads `in` with load mode `first_load`, later passes work in place
 // on `out`; the last pass stores with `store` into final_out (or out).

@@ -9,6 +9,7 @@ Calls only the FP64 oracle (``oracle/``) and the seeded field generator
   c4  fields 0 and 1 of the 16-field 128^3 batch, 8 bins to 24, even Lambda, lmax 4
   c5  one field of each grid edge of the uneven 48-field batch, 8 bins to 16, lmax 4
   c5g the same fields: gradient of sum G Z (G seeded normal) at 32 seeded cells each
+  c5x a sixth field of the uneven batch: the second field of edge 64
 """
 from __future__ import annotations
 
@@ -98,13 +99,28 @@ def make_c5g(nt):
               seconds=time.time() - t)
 
 
+def c5_extra_field():
+    """(edge, index) of the sixth checked field of the uneven batch: the second one of edge 64."""
+    idx = [i for i, n in enumerate(c5_shapes()) if n == 64]
+    return 64, idx[1]
+
+
+def make_c5x(nt):
+    n, i = c5_extra_field()
+    d = lognormal_field((n, n, n), seed=i, sigma=1.0)
+    edges = linear_edges(16, 8)
+    t = time.time()
+    z = oracle.zeta3_full(d.astype(np.float64), edges, 4, nthreads=nt)
+    _save(f"c5_full3_{n}_field{i}.npz", zeta3=z, edges=edges, field=i, seconds=time.time() - t)
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["c2", "c3", "c4", "c5", "c5g"])
+    ap.add_argument("what", choices=["c2", "c3", "c4", "c5", "c5g", "c5x"])
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--seeds", type=int, nargs="*", default=None)
     a = ap.parse_args()
     if a.what == "c3":
         make_c3(a.threads, tuple(a.seeds) if a.seeds else (0, 1))
     else:
-        {"c2": make_c2, "c4": make_c4, "c5": make_c5, "c5g": make_c5g}[a.what](a.threads)
+        {"c2": make_c2, "c4": make_c4, "c5": make_c5, "c5g": make_c5g, "c5x": make_c5x}[a.what](a.threads)

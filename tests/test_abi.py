@@ -71,6 +71,97 @@ def test_argument_validation_without_gpu(kw, shape, expect):
 def test_status_strings():
     from paper_2210_10206_amd import _lib
     lib = _lib.load()
-    for s in range(-6, 1):
-        assert lib.sb_status_str(s)
+    names = set()
+    for s in range(-7, 1):
+        name = lib.sb_status_str(s)
+        assert name and name != b"unknown status"
+        names.add(name)
+    assert len(names) == 8
+    assert lib.sb_status_str(-6) == b"non-finite input" and lib.sb_status_str(-7) == b"call out of order"
     assert lib.sb_version() >= 1
+
+
+def _plan(lib, prob, shapes):
+    import numpy as np
+    sh = np.ascontiguousarray(np.array(shapes, dtype=np.int64).ravel())
+    out = ctypes.c_void_p()
+    rc = lib.sb_plan_create(ctypes.byref(prob), len(shapes), sh.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                            ctypes.byref(out))
+    return rc, out
+
+
+def test_plan_creation_needs_no_device_and_reports_truncation():
+    """Plan creation is host-only (the device tables are copied by sb_prepare into the caller's
+    persistent buffer), so the layout, the exact bin counts and the box-truncation warning of
+    the zero-centred kernel support can be read without a GPU."""
+    import numpy as np
+    import oracle
+    from fieldgen import linear_edges
+    from paper_2210_10206_amd import _lib
+    lib = _lib.load()
+    # the uneven workload's finite-difference case: 8 bins to 16 on 24^3 reaches past N/2 = 12
+    for shape, edges, warn in (((24, 24, 24), linear_edges(16, 8), 1), ((64, 64, 64), linear_edges(16, 8), 0),
+                               ((32, 32, 32), linear_edges(16, 8), 1), ((48, 48, 48), linear_edges(23.9, 4), 0)):
+        prob, e = _problem(edges=tuple(edges), lmax=4)
+        rc, h = _plan(lib, prob, [shape])
+        assert rc == 0, lib.sb_last_error()
+        bits = ctypes.c_uint32()
+        assert lib.sb_plan_warnings(h, ctypes.byref(bits)) == 0
+        assert bits.value == warn, (shape, edges[-1])
+        counts = np.zeros(len(edges) - 1, dtype=np.int64)
+        assert lib.sb_bin_counts(h, 0, counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))) == 0
+        assert list(counts) == list(oracle.bin_counts(shape, edges))
+        pb, sbytes = ctypes.c_size_t(), ctypes.c_size_t()
+        assert lib.sb_plan_workspace(h, ctypes.byref(pb), ctypes.byref(sbytes)) == 0
+        assert pb.value > 0 and sbytes.value > 0
+        lib.sb_plan_destroy(h)
+
+
+def test_result_index_tables_match_the_oracle():
+    """The Lambda list of the full 4PCF (Alg. 6 loop order) and the (m1, m2) list of the
+    projected 4PCF (Alg. 8 loop order) equal the oracle's enumerations."""
+    import numpy as np
+    import oracle
+    from paper_2210_10206_amd import _lib
+    lib = _lib.load()
+    for ndim, lmax, flags, want in ((3, 4, 0, oracle.lambdas(4)), (3, 4, 8, oracle.lambdas(4, parity="odd")),
+                                    (2, 10, 0, oracle.mpairs(10)), (2, 3, 0, oracle.mpairs(3))):
+        prob, e = _problem(ndim=ndim, npcf=4, edges=(0.0, 2.0, 4.0), lmax=lmax, flags=flags)
+        rc, h = _plan(lib, prob, [(32,) * ndim])
+        assert rc == 0, lib.sb_last_error()
+        rows, cols = ctypes.c_int32(), ctypes.c_int32()
+        tab = ctypes.POINTER(ctypes.c_int32)()
+        assert lib.sb_zeta_index(h, ctypes.byref(rows), ctypes.byref(cols), ctypes.byref(tab)) == 0
+        got = [tuple(tab[r * cols.value + c] for c in range(cols.value)) for r in range(rows.value)]
+        assert got == [tuple(x) for x in want]
+        lib.sb_plan_destroy(h)
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(prec=1, flags=2), -2),              # unfused 3PCF pair kernel: no split form
+    (dict(prec=1, flags=1), -2),              # coefficients kept: the unfused path again
+    (dict(prec=1, npcf=4, flags=4), -2),      # plain vector-ALU 4PCF kernel
+    (dict(prec=1, npcf=4, lmax=5), -2),       # no matrix-core kernel beyond l = 4
+    (dict(prec=1, ndim=2, npcf=4, flags=4), -2),
+    (dict(prec=1, npcf=4), 0),                # full 4PCF on the matrix cores
+])
+def test_split_bf16_only_where_a_split_form_exists(kw, expect):
+    from paper_2210_10206_amd import _lib
+    lib = _lib.load()
+    prob, e = _problem(**kw)
+    rc, h = _plan(lib, prob, [(16,) * prob.ndim])
+    assert rc == expect, lib.sb_last_error()
+    if h.value:
+        lib.sb_plan_destroy(h)
+
+
+def test_autotune_and_normalize_reject_an_unbound_plan():
+    from paper_2210_10206_amd import _lib
+    lib = _lib.load()
+    prob, e = _problem()
+    rc, h = _plan(lib, prob, [(16, 16, 16)])
+    assert rc == 0
+    assert lib.sb_autotune(h, None, None) == -3
+    ptrs = (ctypes.c_void_p * 1)(None)
+    assert lib.sb_normalize(h, ptrs, None, None, None) == -1
+    lib.sb_plan_destroy(h)

@@ -358,3 +358,54 @@ def test_normalization_constant_field_closed_form():
     N4 = oracle.normalization(d, edges, 4)
     assert np.allclose(z4[0].real / N4, c ** 4 / ((4 * np.pi) ** 1.5 * (1 + c) ** 4), rtol=1e-12)
 
+
+
+def test_correlation_core_equals_the_cell_by_cell_loop():
+    """The C core's correlation visits cells in blocks of 512 and offsets in runs of at most 64
+    of one bin, cells outermost within a run (a loop interchange only).  Against the plain
+    definition a^b_j(x) = sum_{r in b} B_j(r) delta(x + r), each product and sum rounded in
+    float64 in offset order, written here cell by cell in numpy: bit-identical, on a grid of
+    several cell blocks with bins of several offset runs, and at an unordered cell list."""
+    from oracle import api as oapi
+    rng = np.random.Generator(np.random.PCG64(2024))
+    shape = (12, 10, 14)                                     # 1680 cells: blocks of 512, 512, 512, 144
+    d = rng.standard_normal(shape)
+    edges = np.array([0.0, 1.5, 2.6, 4.0])                   # 32, 82 and 194 offsets: runs of 64
+    off, bins, counts = oapi.support(shape, edges)
+    assert counts.max() > 128
+    B = oapi.basis_full(off, 2)
+    ref = np.zeros((d.size, 3, B.shape[1]), dtype=np.complex128)
+    coords = np.stack(np.unravel_index(np.arange(d.size), shape), axis=1)
+    for o in range(off.shape[0]):   # offsets in table order; the same running totals for every cell
+        nbr = np.ravel_multi_index(((coords + off[o]) % np.array(shape)).T, shape)
+        v = d.reshape(-1)[nbr]
+        b = bins[o]
+        ref[:, b, :].real = ref[:, b, :].real + B[o].real[None, :] * v[:, None]
+        ref[:, b, :].imag = ref[:, b, :].imag + B[o].imag[None, :] * v[:, None]
+    got = oapi.coeffs_full(d, edges, 2)
+    assert np.array_equal(got.real, ref.real) and np.array_equal(got.imag, ref.imag)
+    cells = rng.permutation(d.size)[:700]
+    got_c = oapi.coeffs_full(d, edges, 2, cells=cells)
+    assert np.array_equal(got_c, ref[cells])
+
+
+def test_grid_sum_accumulation_error_is_negligible():
+    """The oracle adds per-cell contributions in float64, sequentially within each thread's
+    cell range, then the thread totals in order.  Against an exactly rounded sum (math.fsum)
+    of the per-cell contributions, the difference stays at the float64 level, far below the
+    1e-5 parity bound."""
+    import math
+    from oracle import api as oapi
+    d = lognormal_field((16, 16, 16), seed=77, sigma=1.0, dtype=np.float64)
+    edges = np.array([0.0, 2.0, 4.0])
+    z = oracle.zeta3_full(d, edges, 2, nthreads=3).real
+    a = oapi.coeffs_full(d, edges, 2)                       # (cells, bins, (lmax+1)^2), bit-exact per cell
+    exact = np.zeros_like(z)
+    for l in range(3):
+        cols = slice(l * l, (l + 1) ** 2)
+        for b1 in range(2):
+            for b2 in range(2):
+                terms = d.reshape(-1) * np.sum(a[:, b1, cols] * np.conj(a[:, b2, cols]), axis=1).real
+                exact[l, b1, b2] = math.fsum(terms)
+    scale = np.max(np.abs(exact))
+    assert np.max(np.abs(z - exact)) <= 1e-12 * scale
