@@ -206,6 +206,18 @@ sb_status sb_plan_warnings(const sb_plan *plan, uint32_t *bits);
  * (a path that needs every kernel array at once under a scratch limit), SB_EHIP. */
 sb_status sb_forward(sb_plan *plan, const void *const *delta, double *zeta, void *stream);
 
+/* Forward pass for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same work and results
+ * as sb_forward, but the per-field working arrays live in a fixed array of the library (one
+ * 64 MiB array per device, held until the process ends) instead of the caller's scratch, so
+ * only the persistent buffer has to be bound (sb_plan_bind accepts a NULL scratch of size 0).
+ * Calls no allocating routine.  The plan's scratch need (sb_plan_workspace) must fit the
+ * 64 MiB, else SB_EWORKSPACE (sb_plan_set_scratch_limit can lower it for 3PCF plans).  Every
+ * call on one device shares that device's array: calls that overlap on one device (several
+ * streams, threads or plans at once) race and must be serialised by the caller.  Errors: as
+ * sb_forward, plus SB_ESTATE while per-launch timing is on. */
+sb_status sb_forward_noalloc(sb_plan *plan, const void *const *delta, double *zeta, void *stream);
+
 /* Normalization of Sec. 2.5 (eq. num_gals and the N of that section, with unit cells: box
  * side = grid resolution, V_bin = the offsets of the bin from sb_bin_counts), applied on the
  * device: for every field f, N_gal = sum_x (delta_f(x) + 1) by a float64 reduction in a

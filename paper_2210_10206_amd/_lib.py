@@ -50,6 +50,7 @@ SIGNATURES = {
     "sb_plan_warnings": (c_i32, [c_vp, P(c_u32)]),
     "sb_forward": (c_i32, [c_vp, P(c_vp), c_vp, c_vp]),
     "sb_normalize": (c_i32, [c_vp, P(c_vp), c_vp, c_vp, c_vp]),
+    "sb_forward_noalloc": (c_i32, [c_vp, P(c_vp), c_vp, c_vp]),
     "sb_backward": (c_i32, [c_vp, P(c_vp), c_vp, P(c_vp), c_vp]),
     "sb_coeffs": (c_i32, [c_vp, c_i32, P(c_vp)]),
     "sb_autotune": (c_i32, [c_vp, c_vp, ctypes.c_char_p]),

@@ -518,7 +518,7 @@ sb_status fft_all_axes(sb_plan *p, const ShapeGroup &G, int sign, int first_load
 }
 
 sb_status prepare(sb_plan *p, hipStream_t s) {
-    if (!p->persist || !p->scratch) return fail(SB_EWORKSPACE, "workspace not bound");
+    if (!p->persist) return fail(SB_EWORKSPACE, "workspace not bound");
     const int nd = p->prob.ndim;
     // the plan's tables go to the head of the persistent buffer (the host copy stays with the plan)
     hipError_t te = hipMemcpyAsync(p->persist, p->host_tab.data(), p->host_tab.size(), hipMemcpyHostToDevice, s);
@@ -881,7 +881,7 @@ sb_status sb_plan_workspace(const sb_plan *p, size_t *persistent_bytes, size_t *
 
 sb_status sb_plan_set_scratch_limit(sb_plan *p, uint64_t bytes) {
     if (!p) return fail(SB_EINVAL, "null plan");
-    if (p->scratch) return fail(SB_ESTATE, "the scratch limit must be set before sb_plan_bind");
+    if (p->persist) return fail(SB_ESTATE, "the scratch limit must be set before sb_plan_bind");
     if (bytes == 0) return fail(SB_EINVAL, "limit must be positive");
     p->coef_limit = bytes;
     layout_scratch(p);
@@ -890,8 +890,10 @@ sb_status sb_plan_set_scratch_limit(sb_plan *p, uint64_t bytes) {
 
 sb_status sb_plan_bind(sb_plan *p, void *persistent, size_t persistent_bytes, void *scratch, size_t scratch_bytes) {
     if (!p) return fail(SB_EINVAL, "null plan");
-    if (!persistent || !scratch) return fail(SB_EINVAL, "null workspace");
-    if (persistent_bytes < p->persist_need || scratch_bytes < p->scratch_need)
+    if (!persistent) return fail(SB_EINVAL, "null persistent workspace");
+    // scratch may be left out (NULL, 0 bytes) by callers that only run sb_forward_noalloc
+    if (!scratch && scratch_bytes != 0) return fail(SB_EINVAL, "null scratch with a nonzero size");
+    if (persistent_bytes < p->persist_need || (scratch && scratch_bytes < p->scratch_need))
         return fail(SB_EWORKSPACE, "workspace smaller than sb_plan_workspace requires");
     if ((reinterpret_cast<uintptr_t>(persistent) & 255) || (reinterpret_cast<uintptr_t>(scratch) & 255))
         return fail(SB_EINVAL, "workspace must be 256-byte aligned");
