@@ -44,7 +44,32 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 // The outputs are part-major: value v = part * npairs + pair.
 enum PairMode : int { PS_REAL = 0, PS_COMPLEX = 1, PS_PACKED = 2 };
 
-template <int NBT, int MODE>
+typedef short s4v __attribute__((ext_vector_type(4)));
+
+// Split-BF16 operands of the 4 x 4 x 4 bf16 MFMA: v = hi + lo with hi = bf16(v) and
+// lo = bf16(v - hi), both rounded to nearest.  The row operand carries (hi, hi, lo, 0) and the
+// column operand (hi, lo, hi, 0) in the four K slots, so one instruction adds
+// hi_a hi_b + hi_a lo_b + lo_a hi_b (the lo * lo term, below 2^-16 of the product, is dropped).
+__device__ __forceinline__ void bf16_split(float v, short &h, short &l) {
+    const __bf16 hb = (__bf16)v;
+    const __bf16 lb = (__bf16)(v - (float)hb);
+    h = __builtin_bit_cast(short, hb);
+    l = __builtin_bit_cast(short, lb);
+}
+__device__ __forceinline__ s4v split_row(float v) {
+    short h, l;
+    bf16_split(v, h, l);
+    return s4v{h, h, l, 0};
+}
+__device__ __forceinline__ s4v split_col(float v) {
+    short h, l;
+    bf16_split(v, h, l);
+    return s4v{h, l, h, 0};
+}
+
+// PREC 0: float32 4 x 4 x 1 MFMA.  PREC 1: split-BF16 4 x 4 x 4 MFMA (split_row / split_col),
+// float32 accumulation; the blocks, slots and lanes are the same.
+template <int NBT, int MODE, int PREC = 0>
 struct PairSums {
     static constexpr int Q = (NBT + 3) / 4;           // bin quads (bins >= NBT read as zero)
     static constexpr int NPB = Q * (Q + 1) / 2;       // quad pairs qa <= qb
@@ -106,15 +131,37 @@ struct PairSums {
                     }
                 }
                 int p = 0;
+                if constexpr (PREC == 0) {
 #pragma unroll
-                for (int qa = 0; qa < Q; ++qa) {
-                    const float aw = w * x[qa];
+                    for (int qa = 0; qa < Q; ++qa) {
+                        const float aw = w * x[qa];
 #pragma unroll
-                    for (int qb = qa; qb < Q; ++qb, ++p) {
-                        acc[0][p] = __builtin_amdgcn_mfma_f32_4x4x1f32(aw, x[qb], acc[0][p], 0, 0, 0);
-                        if constexpr (MODE == PS_COMPLEX)
-                            acc[NACC - 1][p] =
-                                __builtin_amdgcn_mfma_f32_4x4x1f32(im_slot ? aw : -aw, xo[qb], acc[NACC - 1][p], 0, 0, 0);
+                        for (int qb = qa; qb < Q; ++qb, ++p) {
+                            acc[0][p] = __builtin_amdgcn_mfma_f32_4x4x1f32(aw, x[qb], acc[0][p], 0, 0, 0);
+                            if constexpr (MODE == PS_COMPLEX)
+                                acc[NACC - 1][p] = __builtin_amdgcn_mfma_f32_4x4x1f32(im_slot ? aw : -aw, xo[qb],
+                                                                                      acc[NACC - 1][p], 0, 0, 0);
+                        }
+                    }
+                } else {
+                    s4v bx[Q], bxo[Q];
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        bx[q] = split_col(x[q]);
+                        if constexpr (MODE == PS_COMPLEX) bxo[q] = split_col(xo[q]);
+                    }
+#pragma unroll
+                    for (int qa = 0; qa < Q; ++qa) {
+                        const s4v ar = split_row(w * x[qa]);
+                        // -(hi + lo) = (-hi) + (-lo) exactly: flip the sign bits
+                        const s4v an = ar ^ s4v{(short)0x8000, (short)0x8000, (short)0x8000, 0};
+#pragma unroll
+                        for (int qb = qa; qb < Q; ++qb, ++p) {
+                            acc[0][p] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(ar, bx[qb], acc[0][p], 0, 0, 0);
+                            if constexpr (MODE == PS_COMPLEX)
+                                acc[NACC - 1][p] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(im_slot ? ar : an, bxo[qb],
+                                                                                          acc[NACC - 1][p], 0, 0, 0);
+                        }
                     }
                 }
             }
@@ -200,11 +247,12 @@ __device__ __forceinline__ int64_t partial_row(const LastArgs &a, int y, int nv,
     return (int64_t)a.rowmap[2 * y + v / npn] * npn + v % npn;
 }
 
-template <int N, int TPP, int NBT, int R, int MODE, int... RAD>
+template <int N, int TPP, int NBT, int R, int MODE, int PREC, int... RAD>
 __global__ __launch_bounds__(NBT * R * TPP) void last_contract_kernel(LastArgs a) {
+    using PS = PairSums<NBT, MODE, PREC>;
     constexpr int P = NBT * R, PITCH = P + 1, NT = P * TPP;
     constexpr int NW = NT / 64;       // waves
-    constexpr int NOUT = PairSums<NBT, MODE>::NOUT;
+    constexpr int NOUT = PS::NOUT;
     constexpr int EPT = N / TPP;      // tile elements loaded per thread
     static_assert(NT % 64 == 0, "whole waves");
     extern __shared__ float2 smem[];
@@ -214,7 +262,7 @@ __global__ __launch_bounds__(NBT * R * TPP) void last_contract_kernel(LastArgs a
     float *wsm = reinterpret_cast<float *>(tw + N);   // the tile's weights w(x), R N values
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
-    PairSums<NBT, MODE> ps;
+    PS ps;
     ps.zero();
     const int64_t nrows = a.ng / N;
     const int64_t r_begin = (int64_t)blockIdx.x * a.rows_per_block;
@@ -267,7 +315,7 @@ __global__ __launch_bounds__(NBT * R * TPP) void last_contract_kernel(LastArgs a
     const int nv = nb * (nb + 1) / 2 * NOUT;
     for (int v = tid; v < nv; v += NT)
         a.partial[partial_row(a, blockIdx.y, nv, nv / NOUT, v) * a.nblocks + blockIdx.x] =
-            PairSums<NBT, MODE>::block_value(red, NW, nb, v);
+            PS::block_value(red, NW, nb, v);
 }
 
 // LDS region of one pencil in the register-resident last pass: it holds the pencil's exchange
@@ -297,15 +345,16 @@ __device__ __forceinline__ void wave_lds_sync() {
 // (regions written, regions read).  The second-stage twiddles come from an LDS table ordered so
 // that the threads of a pencil read adjacent entries, and the pair sums are flushed to float64
 // every FLUSH (8) rows.
-template <int R1, int R2, int NBT, int MODE>
+template <int R1, int R2, int NBT, int MODE, int PREC>
 __global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
+    using PS = PairSums<NBT, MODE, PREC>;
     constexpr int N = R1 * R2;
     constexpr int T = R1 / R2;             // second-stage butterflies per thread
     static_assert(R1 % R2 == 0 && 64 % R2 == 0, "R2 divides R1 and the wave");
     constexpr int P = NBT;                 // pencils (bins) per tile
     constexpr int NT = P * R2;
     constexpr int NW = NT / 64;
-    constexpr int NOUT = PairSums<NBT, MODE>::NOUT;
+    constexpr int NOUT = PS::NOUT;
     constexpr int EXR = R1 + 1;            // exchange row pitch (R2 rows)
     // the transformed row as separate real and imaginary planes (PLANE = 8 mod 64 floats apart,
     // so a group's reads of both parts fall into distinct banks), except for the complex sums
@@ -315,7 +364,7 @@ __global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
     constexpr int REG = pencil_region(R2 * EXR, SPLIT ? PLANE : N);
     constexpr int WPT = (N + NT - 1) / NT;
     static_assert(NT % 64 == 0, "whole waves");
-    constexpr int FLUSH = NBT * PairSums<NBT, MODE>::NACC <= 12 ? 8 : 1;   // larger accumulators would not stay in registers
+    constexpr int FLUSH = NBT * PS::NACC <= 12 ? 8 : 1;   // larger accumulators would not stay in registers
     __shared__ float2 lds[P * REG];
     __shared__ float2 twl[N];              // [t][r][q]: w^{(q + R2 t) r}, w = e^{-2 pi i / N}
     __shared__ float wsm[N];
@@ -327,7 +376,7 @@ __global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
         const int t = i / (R2 * R2), r = i / R2 % R2, qq = i % R2;
         twl[i] = a.tw[((qq + R2 * t) * r) % N];
     }
-    PairSums<NBT, MODE> ps;
+    PS ps;
     ps.zero();
     const int64_t nrows = a.ng / N;
     const int64_t r_begin = (int64_t)blockIdx.x * a.rows_per_block;
@@ -404,14 +453,14 @@ __global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
     }
     // float64 combine over the waves in wave order (as in last_contract_kernel)
     __syncthreads();
-    static_assert(PairSums<NBT, MODE>::red_doubles(NW) * sizeof(double) <= sizeof(lds), "block reduction fits");
+    static_assert(PS::red_doubles(NW) * sizeof(double) <= sizeof(lds), "block reduction fits");
     double *red = reinterpret_cast<double *>(lds);   // [wave][part][quad pair][4 x 4]
     ps.to_lds(red, wave, lane);
     __syncthreads();
     const int nv = nb * (nb + 1) / 2 * NOUT;
     for (int vv = tid; vv < nv; vv += NT)
         a.partial[partial_row(a, blockIdx.y, nv, nv / NOUT, vv) * a.nblocks + blockIdx.x] =
-            PairSums<NBT, MODE>::block_value(red, NW, nb, vv);
+            PS::block_value(red, NW, nb, vv);
 }
 
 // bins padded to the instantiated tile widths 4, 8, 12, 16 so that NBT * t threads make whole
@@ -425,9 +474,8 @@ constexpr int reg_padded_bins(int nb, int t) {
 // Pair-sum mode of a launch.
 inline int pair_mode(const LastArgs &a) { return a.want_imag ? PS_COMPLEX : (a.packed ? PS_PACKED : PS_REAL); }
 
-template <int R1, int R2>
-hipError_t launch_last_reg(const LastArgs &a, hipStream_t s) {
-    if (a.rows != 1) return hipErrorInvalidValue;
+template <int R1, int R2, int PREC>
+hipError_t launch_last_reg_p(const LastArgs &a, hipStream_t s) {
     dim3 grid((unsigned)a.nblocks, (unsigned)a.groups);
     const int mode = pair_mode(a);
     const int nbt = reg_padded_bins(a.nb, R2);
@@ -435,11 +483,11 @@ hipError_t launch_last_reg(const LastArgs &a, hipStream_t s) {
     case NBT:                                                                                                        \
         if constexpr ((NBT * R2) % 64 == 0) {                                                                        \
             if (mode == PS_COMPLEX)                                                                                  \
-                hipLaunchKernelGGL((last_reg_kernel<R1, R2, NBT, PS_COMPLEX>), grid, dim3(NBT * R2), 0, s, a);       \
+                hipLaunchKernelGGL((last_reg_kernel<R1, R2, NBT, PS_COMPLEX, PREC>), grid, dim3(NBT * R2), 0, s, a); \
             else if (mode == PS_PACKED)                                                                              \
-                hipLaunchKernelGGL((last_reg_kernel<R1, R2, NBT, PS_PACKED>), grid, dim3(NBT * R2), 0, s, a);        \
+                hipLaunchKernelGGL((last_reg_kernel<R1, R2, NBT, PS_PACKED, PREC>), grid, dim3(NBT * R2), 0, s, a);  \
             else                                                                                                     \
-                hipLaunchKernelGGL((last_reg_kernel<R1, R2, NBT, PS_REAL>), grid, dim3(NBT * R2), 0, s, a);          \
+                hipLaunchKernelGGL((last_reg_kernel<R1, R2, NBT, PS_REAL, PREC>), grid, dim3(NBT * R2), 0, s, a);    \
             break;                                                                                                   \
         } else {                                                                                                     \
             return hipErrorInvalidValue;                                                                             \
@@ -452,18 +500,25 @@ hipError_t launch_last_reg(const LastArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int R1, int R2>
+hipError_t launch_last_reg(const LastArgs &a, hipStream_t s) {
+    if (a.rows != 1) return hipErrorInvalidValue;
+    return a.prec ? launch_last_reg_p<R1, R2, 1>(a, s) : launch_last_reg_p<R1, R2, 0>(a, s);
+}
+
 // Register-resident form for any radix list R0, ... (each radix divides R0; see reg_stages):
 // a tile is one row of the NBT (padded) bins of one (l, m); thread q < T = n / R0 of a
 // pencil loads elements q + T s.  The stages exchange through two LDS buffers laid out
 // [position][bin]; the transformed row is written to the buffer the last stage did not read,
 // which is then the [cell][bin] tile of the MFMA pair sums.
-template <int N, int NBT, int MODE, int R0, int... REST>
+template <int N, int NBT, int MODE, int PREC, int R0, int... REST>
 __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
+    using PS = PairSums<NBT, MODE, PREC>;
     constexpr int T = N / R0;
     constexpr int P = NBT;
     constexpr int NT = P * T;
     constexpr int NW = NT / 64;
-    constexpr int NOUT = PairSums<NBT, MODE>::NOUT;
+    constexpr int NOUT = PS::NOUT;
     constexpr int PITCH = P + 1;
     constexpr int NSTAGE = 1 + sizeof...(REST);
     constexpr int CSB = (NSTAGE - 1) % 2;       // buffer the last stage does not read
@@ -476,7 +531,7 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int q = tid % T, pp = tid / T;        // element column, pencil (= bin)
     for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
-    PairSums<NBT, MODE> ps;
+    PS ps;
     ps.zero();
     const int64_t nrows = a.ng / N;
     const int64_t r_begin = (int64_t)blockIdx.x * a.rows_per_block;
@@ -516,20 +571,19 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
     }
     // float64 combine over the waves in wave order (as in last_contract_kernel)
     __syncthreads();
-    static_assert(PairSums<NBT, MODE>::red_doubles(NW) * sizeof(double) <= sizeof(ex), "block reduction fits");
+    static_assert(PS::red_doubles(NW) * sizeof(double) <= sizeof(ex), "block reduction fits");
     double *red = reinterpret_cast<double *>(&ex[0][0]);
     ps.to_lds(red, wave, lane);
     __syncthreads();
     const int nv = nb * (nb + 1) / 2 * NOUT;
     for (int vv = tid; vv < nv; vv += NT)
         a.partial[partial_row(a, blockIdx.y, nv, nv / NOUT, vv) * a.nblocks + blockIdx.x] =
-            PairSums<NBT, MODE>::block_value(red, NW, nb, vv);
+            PS::block_value(red, NW, nb, vv);
 }
 
-template <int N, int R0, int... REST>
-hipError_t launch_last_rs(const LastArgs &a, hipStream_t s) {
+template <int N, int PREC, int R0, int... REST>
+hipError_t launch_last_rs_p(const LastArgs &a, hipStream_t s) {
     constexpr int T = N / R0;
-    if (a.rows != 1) return hipErrorInvalidValue;
     dim3 grid((unsigned)a.nblocks, (unsigned)a.groups);
     const int mode = pair_mode(a);
     const int nbt = reg_padded_bins(a.nb, T);
@@ -537,11 +591,13 @@ hipError_t launch_last_rs(const LastArgs &a, hipStream_t s) {
     case NBT:                                                                                                         \
         if constexpr ((NBT * T) % 64 == 0 && NBT * T <= 1024) {                                                       \
             if (mode == PS_COMPLEX)                                                                                   \
-                hipLaunchKernelGGL((last_rs_kernel<N, NBT, PS_COMPLEX, R0, REST...>), grid, dim3(NBT * T), 0, s, a);  \
+                hipLaunchKernelGGL((last_rs_kernel<N, NBT, PS_COMPLEX, PREC, R0, REST...>), grid, dim3(NBT * T), 0, s, \
+                                   a);                                                                                \
             else if (mode == PS_PACKED)                                                                               \
-                hipLaunchKernelGGL((last_rs_kernel<N, NBT, PS_PACKED, R0, REST...>), grid, dim3(NBT * T), 0, s, a);   \
+                hipLaunchKernelGGL((last_rs_kernel<N, NBT, PS_PACKED, PREC, R0, REST...>), grid, dim3(NBT * T), 0, s,  \
+                                   a);                                                                                \
             else                                                                                                      \
-                hipLaunchKernelGGL((last_rs_kernel<N, NBT, PS_REAL, R0, REST...>), grid, dim3(NBT * T), 0, s, a);     \
+                hipLaunchKernelGGL((last_rs_kernel<N, NBT, PS_REAL, PREC, R0, REST...>), grid, dim3(NBT * T), 0, s, a); \
             break;                                                                                                    \
         } else {                                                                                                      \
             return hipErrorInvalidValue;                                                                              \
@@ -554,6 +610,12 @@ hipError_t launch_last_rs(const LastArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int N, int R0, int... REST>
+hipError_t launch_last_rs(const LastArgs &a, hipStream_t s) {
+    if (a.rows != 1) return hipErrorInvalidValue;
+    return a.prec ? launch_last_rs_p<N, 1, R0, REST...>(a, s) : launch_last_rs_p<N, 0, R0, REST...>(a, s);
+}
+
 template <int N, int TPP, int NBT, int MODE, int... RAD>
 hipError_t launch_last_t(const LastArgs &a, hipStream_t s) {
     constexpr int R = fused_rows(N, TPP, NBT);
@@ -563,7 +625,10 @@ hipError_t launch_last_t(const LastArgs &a, hipStream_t s) {
     const size_t red = (size_t)PairSums<NBT, MODE>::red_doubles(NT / 64) * sizeof(double);
     const size_t shm = tile > red ? tile : red;
     dim3 grid((unsigned)a.nblocks, (unsigned)a.groups);
-    hipLaunchKernelGGL((last_contract_kernel<N, TPP, NBT, R, MODE, RAD...>), grid, dim3(NT), shm, s, a);
+    if (a.prec)
+        hipLaunchKernelGGL((last_contract_kernel<N, TPP, NBT, R, MODE, 1, RAD...>), grid, dim3(NT), shm, s, a);
+    else
+        hipLaunchKernelGGL((last_contract_kernel<N, TPP, NBT, R, MODE, 0, RAD...>), grid, dim3(NT), shm, s, a);
     return hipGetLastError();
 }
 

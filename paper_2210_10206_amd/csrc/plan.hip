@@ -655,6 +655,7 @@ static sb_status fused_3pcf(sb_plan *p, int f, const void *delta, double *zeta_f
             a.nblocks = nblocks;
             a.want_imag = nd == 2;
             a.packed = packed;
+            a.prec = p->prob.precision == SB_PREC_SPLIT_BF16 ? 1 : 0;
             // with packing the row map places each part's partials at its (l, m) row
             a.rowmap = packing ? p->d_rowmap + 2 * gs : nullptr;
             a.partial = packing ? part : part + (int64_t)gs * nv * nblocks;

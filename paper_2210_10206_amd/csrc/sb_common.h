@@ -108,6 +108,7 @@ struct LastArgs {
                           // (then imaginary parts or the second packed field)
     const int *rowmap;    // optional: 2 per grid row, the group row of part 0 and part 1
                           // (row = rowmap[2 y + part] * npairs + pair)
+    int prec;             // 0: float32 MFMA pair sums, 1: split-BF16 MFMA pair sums
     const float2 *tw;
 };
 hipError_t launch_last_contract(const LastArgs &a, hipStream_t s);

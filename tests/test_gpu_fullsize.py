@@ -101,17 +101,18 @@ def test_uneven_batch_sizes(api):
     plan.close()
 
 
-@pytest.mark.parametrize("seed,sigma", [(0, 0.5), (1, 1.5)])
-def test_full3pcf_256(api, seed, sigma):
-    say(f"case: 256^3 full 3PCF seed {seed} sigma {sigma}, 10 bins to 32, lmax 6")
+@pytest.mark.parametrize("seed,sigma,precision", [(0, 0.5, "fp32"), (1, 1.5, "fp32"), (0, 0.5, "split_bf16"),
+                                                   (1, 1.5, "split_bf16")])
+def test_full3pcf_256(api, seed, sigma, precision):
+    say(f"case: 256^3 full 3PCF seed {seed} sigma {sigma}, 10 bins to 32, lmax 6, {precision} pair sums")
     g = golden(f"c3_full3_256_seed{seed}.npz")
     d = lognormal_field((256,) * 3, seed=seed, sigma=sigma)
     edges = linear_edges(32, 10)
-    plan = api.Plan([d.shape], edges, 6, npcf=3)
+    plan = api.Plan([d.shape], edges, 6, npcf=3, precision=precision)
     z = plan.forward([torch.from_numpy(d).cuda()])[0].cpu().numpy()
     torch.cuda.synchronize()
     ref = g["zeta3"].real
-    check(z, ref, TOL32, say, "l blocks: ")
+    check(z, ref, TOL_SPLIT if precision == "split_bf16" else TOL32, say, "l blocks: ")
     # and per zeta_l^{b1 b2} entry, relative to max |Z_l| of its l
     per_entry = np.abs(z - ref) / np.max(np.abs(ref), axis=(1, 2), keepdims=True)
     say(f"  worst entry (relative to its l block) {np.max(per_entry):.3e}")

@@ -541,3 +541,34 @@ def test_adjoint_matches_oracle_gradient(sb, fused):
     say(f"  grad err={err:.3e}")
     assert err < TOL32
     plan.close()
+
+
+# ------------------------------------------------------------------ split-BF16 pair sums
+
+@pytest.mark.parametrize("shape,nbins,lmax,pack", [((16, 16, 32), 4, 3, True), ((8, 16, 256), 10, 6, True),
+                                                   ((8, 16, 256), 10, 6, False), ((12, 8, 96), 8, 4, True),
+                                                   ((8, 8, 512), 4, 2, True), ((16, 16, 64), 16, 2, True),
+                                                   ((16, 8, 160), 6, 4, True), ((8, 12, 128), 12, 5, True)])
+def test_split_bf16_full3pcf(sb, shape, nbins, lmax, pack):
+    # the fused pair sums on bf16 4x4x4 MFMA with hi + lo splits, on every last-pass family
+    # (LDS-staged 32 / 512, register-resident 64 / 128 / 256, radix lists 96 / 160), packed m = 0
+    # pairs and one transform per (l, m)
+    say(f"case: {shape} full 3PCF split-BF16 pair sums, {nbins} bins to 8, lmax {lmax}, pack {pack}")
+    d = lognormal_field(shape, seed=80 + nbins, sigma=1.0)
+    edges = linear_edges(8, nbins)
+    plan, dev, z = run_plan(sb, [d], edges, lmax, precision="split_bf16", pack=pack)
+    _, _, z32 = run_plan(sb, [d], edges, lmax, pack=pack)
+    ref = oracle.zeta3_full(d.astype(np.float64), edges, lmax).real
+    check(z[0], ref, TOL_SPLIT, say, "split-BF16: ")
+    check(z32[0], ref, TOL32, say, "float32: ")
+    plan.close()
+
+
+@pytest.mark.parametrize("shape", [(16, 160), (16, 128), (64, 96), (32, 48), (8, 512)])
+def test_split_bf16_projected3pcf(sb, shape):
+    say(f"case: {shape} projected 3PCF split-BF16 pair sums, 4 bins to 6, mmax 4")
+    d = lognormal_field(shape, seed=13, sigma=1.0)
+    edges = linear_edges(6, 4)
+    _, _, z3 = run_plan(sb, [d], edges, 4, npcf=3, precision="split_bf16")
+    ref3 = oracle.zeta3_proj(d.astype(np.float64), edges, 4)
+    check(z3[0], ref3, TOL_SPLIT, say, "split-BF16 proj3: ")
