@@ -783,6 +783,7 @@ sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
         a.partial = part;
         a.nblocks = nblocks;
         a.mfma = (p->prob.flags & SB_FLAG_NO_MFMA) == 0;
+        a.precision = p->prob.precision == SB_PREC_SPLIT_BF16 ? 1 : 0;
         const double fl = (double)G.ng * groups * NB * NB * (8.0 + 8.0 * NB);
         const double by = (double)G.ng * (8.0 * p->nk + 4.0);
         e = p->timed_launch(STAGE_CONTRACT, K_PROJ4, s, [&]() { return launch_proj4_contract(a, s); }, 0, 0, groups, by, fl);

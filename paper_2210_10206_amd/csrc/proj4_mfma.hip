@@ -130,10 +130,149 @@ __global__ __launch_bounds__(256) void proj4_mfma_kernel(Proj4Args a) {
     }
 }
 
+// Split-BF16 form on v_mfma_f32_16x16x32_bf16.  Each lane group g takes one cell per
+// instruction in K slots 8 g .. 8 g + 7; the N columns carry (b3, part) = (8 t + i / 2, i % 2)
+// for lane i of N tile t, so one row operand serves both parts:
+//   row    (pair p):            (Lr_h, Lr_h, Lr_l, nLi_h, nLi_h, nLi_l, 0, 0),   nLi = -Li
+//   column (b3, real part):     (Br_h, Br_l, Br_h,  Bi_h,  Bi_l,  Bi_h, 0, 0)  -> Lr Br - Li Bi
+//   column (b3, imaginary part):(Bi_h, Bi_l, Bi_h, nBr_h, nBr_l, nBr_h, 0, 0)  -> Lr Bi + Li Br
+// with v = v_h + v_l split as hi = bf16(v), lo = bf16(v - hi) (the lo * lo terms dropped).
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split2(float v, __bf16 &h, __bf16 &l) {
+    h = (__bf16)v;
+    l = (__bf16)(v - (float)h);
+}
+
+template <int NB>
+__global__ __launch_bounds__(256, 2) void proj4_split_kernel(Proj4Args a) {
+    constexpr int NP = NB * NB;
+    constexpr int NMT = (NP + 15) / 16;        // M tiles of 16 pairs
+    constexpr int NNT = (2 * NB + 15) / 16;    // N tiles of 8 (b3, part) column pairs
+    constexpr int TC = 64;
+    constexpr int W = 3 * NB;
+    constexpr int S = (W + 7) / 8 * 8 + 2;
+    constexpr int NLD = (TC * W + 255) / 256;
+    constexpr int NV = NB * NB * NB * 2;
+    constexpr int NTILE = TC * S > 2 * NV ? TC * S : 2 * NV;
+    __shared__ float2 tile[NTILE];
+    __shared__ float wt[TC];
+    float *red = reinterpret_cast<float *>(tile);
+    const int pr_ = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int i = lane & 15, g = lane >> 4;
+    const int m1 = a.pairs[2 * pr_], m2 = a.pairs[2 * pr_ + 1];
+    const int ms[3] = {m1, m2, -(m1 + m2)};
+    int b1s[NMT], b2s[NMT];
+#pragma unroll
+    for (int mt = 0; mt < NMT; ++mt) {
+        const int p = 16 * mt + i;
+        b1s[mt] = p < NP ? p / NB : -1;
+        b2s[mt] = p < NP ? p % NB : 0;
+    }
+    f4v acc[NMT][NNT];
+#pragma unroll
+    for (int mt = 0; mt < NMT; ++mt)
+#pragma unroll
+        for (int t = 0; t < NNT; ++t) acc[mt][t] = f4v{0.f, 0.f, 0.f, 0.f};
+    const int64_t c0 = (int64_t)blockIdx.x * a.cells_per_block;
+    const int64_t c1 = min(c0 + a.cells_per_block, a.ng);
+    float2 pf[NLD];
+    float pw = 0.f;
+    auto gload = [&](int64_t tc) {
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int f = tid + 256 * k;
+            const int c = f % TC, kb = f / TC;
+            float2 v = make_float2(0.f, 0.f);
+            if (kb < W && tc + c < c1) {
+                const int slot = kb / NB, b = kb % NB;
+                const int m = ms[slot];
+                v = a.coef[((int64_t)(m < 0 ? -m : m) * NB + b) * a.ng + tc + c];
+                if (m < 0) v.y = -v.y;   // c_{-m} = conj(c_m)
+            }
+            pf[k] = v;
+        }
+        if (wave == 0) pw = tc + lane < c1 ? a.w[tc + lane] : 0.f;
+    };
+    const bool imag_col = (i & 1) != 0;
+    gload(c0);
+    for (int64_t tc = c0; tc < c1; tc += TC) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int f = tid + 256 * k;
+            const int c = f % TC, kb = f / TC;
+            if (kb < W) tile[c * S + kb] = pf[k];
+        }
+        if (wave == 0) wt[lane] = pw;
+        __syncthreads();
+        if (tc + TC < c1) gload(tc + TC);
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+            const int c = 16 * wave + 4 * g + cc;
+            const float2 *row = tile + c * S;
+            const float wv = wt[c];
+            bf8v bop[NNT];
+#pragma unroll
+            for (int t = 0; t < NNT; ++t) {
+                const int b3 = 8 * t + (i >> 1);
+                const float2 bv = b3 < NB ? row[2 * NB + b3] : make_float2(0.f, 0.f);
+                // real column: (Br, Bi); imaginary column: (Bi, -Br)
+                const float u0 = imag_col ? bv.y : bv.x, u1 = imag_col ? -bv.x : bv.y;
+                __bf16 h0, l0, h1, l1;
+                split2(u0, h0, l0);
+                split2(u1, h1, l1);
+                bop[t] = bf8v{h0, l0, h0, h1, l1, h1, (__bf16)0.f, (__bf16)0.f};
+            }
+#pragma unroll
+            for (int mt = 0; mt < NMT; ++mt) {
+                float lr = 0.f, nli = 0.f;
+                if (b1s[mt] >= 0) {
+                    const float2 x1 = row[b1s[mt]], x2 = row[NB + b2s[mt]];
+                    const float2 u = make_float2(wv * x1.x, wv * x1.y);
+                    lr = __builtin_fmaf(u.x, x2.x, -u.y * x2.y);
+                    nli = -__builtin_fmaf(u.x, x2.y, u.y * x2.x);
+                }
+                __bf16 h0, l0, h1, l1;
+                split2(lr, h0, l0);
+                split2(nli, h1, l1);
+                const bf8v aop = {h0, h0, l0, h1, h1, l1, (__bf16)0.f, (__bf16)0.f};
+#pragma unroll
+                for (int t = 0; t < NNT; ++t)
+                    acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop[t], acc[mt][t], 0, 0, 0);
+            }
+        }
+    }
+    // accumulator (mt, t): lane l holds rows 4 g + r (pair 16 mt + 4 g + r), column (b3, part)
+    __syncthreads();
+    for (int v = tid; v < 4 * NV; v += 256) red[v] = 0.f;
+    __syncthreads();
+#pragma unroll
+    for (int mt = 0; mt < NMT; ++mt)
+#pragma unroll
+        for (int t = 0; t < NNT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int p = 16 * mt + 4 * g + r;
+                const int b3 = 8 * t + (i >> 1);
+                if (p < NP && b3 < NB) red[wave * NV + (p * NB + b3) * 2 + (i & 1)] = acc[mt][t][r];
+            }
+    __syncthreads();
+    for (int v = tid; v < NV; v += 256) {
+        const double s = ((double)red[v] + (double)red[NV + v]) + ((double)red[2 * NV + v] + (double)red[3 * NV + v]);
+        a.partial[((int64_t)pr_ * NV + v) * a.nblocks + blockIdx.x] = s;
+    }
+}
+
 template <int NB>
 hipError_t launch_nb(const Proj4Args &a, hipStream_t s) {
     dim3 grid((unsigned)a.nblocks, (unsigned)a.npairs);
-    hipLaunchKernelGGL((proj4_mfma_kernel<NB>), grid, dim3(256), 0, s, a);
+    if (a.precision == 1)
+        hipLaunchKernelGGL((proj4_split_kernel<NB>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((proj4_mfma_kernel<NB>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -110,6 +110,7 @@ struct Proj4Args {
     double *partial;          // [pair][block][nbins^3 * 2]
     int nblocks;
     int mfma;                 // 1: the matrix-core kernel (proj4_mfma.hip), 0: the vector kernel
+    int precision;            // matrix-core kernel: 0 float32 MFMA, 1 split-BF16 MFMA
 };
 hipError_t launch_proj4_contract(const Proj4Args &a, hipStream_t s);
 hipError_t launch_proj4_mfma(const Proj4Args &a, hipStream_t s);

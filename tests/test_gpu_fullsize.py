@@ -44,20 +44,22 @@ def api():
     return a
 
 
-def test_projected_512(api):
-    say("case: 512^2 float32 lognormal seed 0, 10 bins to 40, m up to 10: projected 3PCF + 4PCF")
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_projected_512(api, precision):
+    say(f"case: 512^2 float32 lognormal seed 0, 10 bins to 40, m up to 10: projected 3PCF + 4PCF, {precision}")
     g = golden("c2_proj_512.npz")
     d = lognormal_field((512, 512), seed=0, sigma=1.0)
     edges = linear_edges(40, 10)
     dev = [torch.from_numpy(d).cuda()]
-    p3 = api.Plan([d.shape], edges, 10, npcf=3)
+    p3 = api.Plan([d.shape], edges, 10, npcf=3, precision=precision)
     z3 = p3.forward(dev)[0].cpu().numpy()
-    p4 = api.Plan([d.shape], edges, 10, npcf=4)
+    p4 = api.Plan([d.shape], edges, 10, npcf=4, precision=precision)
     z4 = p4.forward(dev)[0].cpu().numpy()
     torch.cuda.synchronize()
     assert [tuple(x) for x in p4.zeta_index()] == [tuple(x) for x in g["pairs"]]
-    check(z3, g["zeta3"], TOL32, say, "proj3 (m blocks): ")
-    check(z4, g["zeta4"], TOL32, say, "proj4 ((m1, m2) blocks): ")
+    tol = TOL_SPLIT if precision == "split_bf16" else TOL32
+    check(z3, g["zeta3"], tol, say, "proj3 (m blocks): ")
+    check(z4, g["zeta4"], tol, say, "proj4 ((m1, m2) blocks): ")
     p3.close()
     p4.close()
 

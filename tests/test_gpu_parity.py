@@ -572,3 +572,18 @@ def test_split_bf16_projected3pcf(sb, shape):
     _, _, z3 = run_plan(sb, [d], edges, 4, npcf=3, precision="split_bf16")
     ref3 = oracle.zeta3_proj(d.astype(np.float64), edges, 4)
     check(z3[0], ref3, TOL_SPLIT, say, "split-BF16 proj3: ")
+
+
+@pytest.mark.parametrize("shape,nbins,mmax", [((64, 96), 5, 4), ((32, 48), 8, 3), ((48, 32), 3, 2), ((64, 64), 10, 5),
+                                              ((16, 128), 1, 2)])
+def test_split_bf16_projected4pcf(sb, shape, nbins, mmax):
+    # the projected-4PCF contraction on bf16 16x16x32 MFMA with hi + lo splits; N tiles of
+    # 8 (b3, part) column pairs: 3, 5 and 10 bins leave part of a tile empty, 8 fill it
+    say(f"case: {shape} projected 4PCF split-BF16, {nbins} bins to 8, mmax {mmax}")
+    d = lognormal_field(shape, seed=90 + nbins, sigma=1.0)
+    edges = linear_edges(8, nbins)
+    _, _, z = run_plan(sb, [d], edges, mmax, npcf=4, precision="split_bf16")
+    _, _, z32 = run_plan(sb, [d], edges, mmax, npcf=4)
+    pairs, ref = oracle.zeta4_proj(d.astype(np.float64), edges, mmax)
+    check(z[0], ref, TOL_SPLIT, say, "split-BF16: ")
+    check(z32[0], ref, TOL32, say, "float32: ")
