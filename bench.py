@@ -123,6 +123,91 @@ def write_traffic(counter_dir, n=256, copy_mib=1024, min_gib=1.0):
     print(json.dumps(out, indent=1))
 
 
+def block_errors(z, ref):
+    """Whole-result error, per-block errors along the leading axis (each relative to that block's
+    max |ref|) and the worst entry relative to its own block: the parity measure of the tests."""
+    import numpy as np
+    z, ref = np.asarray(z), np.asarray(ref)
+    per = [float(np.max(np.abs(z[i] - ref[i])) / np.max(np.abs(ref[i]))) for i in range(ref.shape[0])]
+    return {"max_rel_err": float(np.max(np.abs(z - ref)) / np.max(np.abs(ref))), "worst_block": max(per),
+            "per_block": [round(e, 10) for e in per]}
+
+
+def counters_for(kernel_key, src_files):
+    """MFMA / VALU figures of a contraction kernel from rocprofv3 counter runs (committed under
+    profiles/), or None when the kernel source changed after the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "mfma_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    e = t.get(kernel_key)
+    if not e or e.get("source_hash") != source_hash(src_files):
+        return None
+    return {k: v for k, v in e.items() if k != "source_hash"}
+
+
+COUNTER_SRCS = {"quad_mfma": ["paper_2210_10206_amd/csrc/quad_mfma.h"],
+                "proj4_mfma": ["paper_2210_10206_amd/csrc/proj4_mfma.hip"]}
+
+
+def write_counters(counter_csv):
+    """Turn a rocprofv3 counter run of `bench.py --lines c4,c4var,proj --c4-steps 1 --proj-steps 1`
+    (--pmc MfmaUtil VALUBusy MfmaFlopsF32 MfmaFlopsBF16 SQ_INSTS_VALU SQ_INSTS_MFMA, csv output)
+    into profiles/mfma_counters.json: per contraction family (4PCF matrix-core kernels by
+    precision and parity, projected-4PCF kernels by precision), the duration-weighted MfmaUtil and
+    VALUBusy over its dispatches and the issued MFMA flops and instructions of one field (the sum
+    over the family's kernels of their mean per dispatch: every dispatch of one kernel does the
+    same work)."""
+    import csv
+    import re
+    rows = {}
+    with open(counter_csv) as f:
+        for r in csv.DictReader(f):
+            d = rows.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"]})
+            d[r["Counter_Name"]] = float(r["Counter_Value"])
+            if r.get("Start_Timestamp") and r.get("End_Timestamp"):
+                d["ns"] = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+
+    def family(name):
+        m = re.search(r"quad_mfma_kernel<(\d+), (\d+), (\d+), (\d+)>", name)
+        if m:
+            la, lb, lc, prec = (int(x) for x in m.groups())
+            return f"quad_mfma_prec{prec}_{'odd' if (la + lb + lc) % 2 else 'even'}", (la, lb, lc)
+        m = re.search(r"proj4_(mfma|split)_kernel<(\d+)>", name)
+        if m:
+            return f"proj4_prec{1 if m.group(1) == 'split' else 0}", (int(m.group(2)),)
+        return None, None
+
+    fams = {}
+    for d in rows.values():
+        fam, key = family(d["name"])
+        if fam is None:
+            continue
+        fams.setdefault(fam, {}).setdefault(key, []).append(d)
+    out = {"_note": "rocprofv3 counters per contraction family: MfmaUtil = sum SQ_VALU_MFMA_BUSY_CYCLES / "
+                    "(GRBM_GUI_ACTIVE x SIMDs), VALUBusy = sum SQ_ACTIVE_INST_VALU / CUs / GRBM_GUI_ACTIVE (both "
+                    "percent, weighted by dispatch duration); issued MFMA flops (MOPS x 512) and instruction "
+                    "counts per field"}
+    for fam, kernels in fams.items():
+        w = sum(d.get("ns", 1.0) for ds in kernels.values() for d in ds)
+        util = sum(d.get("MfmaUtil", 0.0) * d.get("ns", 1.0) for ds in kernels.values() for d in ds) / w
+        valu = sum(d.get("VALUBusy", 0.0) * d.get("ns", 1.0) for ds in kernels.values() for d in ds) / w
+        per_field = {}
+        for c in ("MfmaFlopsF32", "MfmaFlopsBF16", "SQ_INSTS_VALU", "SQ_INSTS_MFMA"):
+            per_field[c] = sum(sum(d.get(c, 0.0) for d in ds) / len(ds) for ds in kernels.values())
+        out[fam] = {"kernels": len(kernels), "dispatches": sum(len(ds) for ds in kernels.values()),
+                    "mfma_util_pct": round(util, 2), "valu_busy_pct": round(valu, 2),
+                    "mfma_flops_f32_per_field": per_field["MfmaFlopsF32"],
+                    "mfma_flops_bf16_per_field": per_field["MfmaFlopsBF16"],
+                    "valu_insts_per_field": per_field["SQ_INSTS_VALU"],
+                    "mfma_insts_per_field": per_field["SQ_INSTS_MFMA"],
+                    "source_hash": source_hash(COUNTER_SRCS["quad_mfma" if fam.startswith("quad") else "proj4_mfma"])}
+    with open(os.path.join(ROOT, "profiles", "mfma_counters.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def cpu_baseline(field, edges, lmax, target_s=10.0):
     """Oracle throughput on a bounded sample of cells of field 0: two probe sizes give the
     per-cell rate without the oracle's one-off table set-up, then a sample sized for about
@@ -142,7 +227,17 @@ def cpu_baseline(field, edges, lmax, target_s=10.0):
     n = int(min(ng, max(2560, target_s / per_cell)))
     n = (n // 256) * 256
     dt = run(n)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": (n / ng) / dt, "unit": "fields/s", "cores": int(oracle.max_threads()), "kind": "oracle",
+            "cpu_model": model,
             "sample": f"full-3PCF oracle (direct FP64 correlation + contraction) over the first {n} of the "
                       f"{ng} cells of field 0, {dt:.1f} s wall including its table set-up; value scaled to whole "
                       f"fields"}
@@ -193,19 +288,34 @@ def run_4pcf_batch(api, steps, warmup, count=16, precision="fp32", mfma=True, pa
     if mfma:
         kname = ("quad_mfma_kernel<la,lb,lc," + ("1> (split-BF16 MFMA" if precision == "split_bf16" else "0> (float32 MFMA")
                  + ", one launch per canonical Lambda)")
-        peak = 2500.0 if precision == "split_bf16" else 157.3
     else:
-        kname, peak = "quad_kernel (3j-coupled contraction, float32 VALU)", 157.3
+        kname = "quad_kernel (3j-coupled contraction, float32 VALU)"
     res = {"workload": f"full 4PCF, {count} lognormal 128^3 float32 fields (sigma ~ U[0.5,2]), 8 bins over (0,24], "
-                       "even Lambda with l <= 4 (42)",
+                       f"{parity} Lambda with l <= 4 ({'42' if parity == 'even' else '23'})",
            "precision": precision, "matrix_cores": bool(mfma), "contract_tile": plan.contract_tile()[0],
            "value": round(count * steps / el, 3), "unit": "fields/s", "ms_per_step": round(el / steps * 1e3, 2),
            "graph_replay": {"value": round(count * steps / el_graph, 3), "ms_per_step": round(el_graph / steps * 1e3, 2)},
            "contraction": {"kernel": kname,
+                           "flops_note": "executed floating-point work of the kernel on real bins (its symmetric pair "
+                                         "tiles and paired +-m at m_c = 0 counted as computed; padding excluded), "
+                                         "VALU coupling and MFMA contraction together, against the float32 peak",
                            "achieved_tflops": round(fl / (ms * 1e-3) / 1e12, 2) if ms else None,
-                           "peak_tflops": peak, "frac": round(fl / (ms * 1e-3) / 1e12 / peak, 4) if ms else None,
-                           "ms_per_field": round(ms / (count * steps), 3)},
+                           "peak_tflops": 157.3, "frac": round(fl / (ms * 1e-3) / 1e12 / 157.3, 4) if ms else None,
+                           "ms_per_field": round(ms / (count * steps), 3),
+                           "counters": counters_for(f"quad_mfma_prec{1 if precision == 'split_bf16' else 0}_{parity}",
+                                                    COUNTER_SRCS["quad_mfma"]) if mfma else None},
            "stage_ms_per_field": {}}
+    if parity == "even":
+        import numpy as np
+        z = out.cpu().numpy()
+        errs = {}
+        for i in (0, 1):
+            g = os.path.join(ROOT, "tests", "golden", f"c4_full4_128_field{i}.npz")
+            if os.path.exists(g):
+                ref = np.load(g)["zeta4"].real
+                e = block_errors(z[i].reshape(ref.shape), ref)
+                errs[f"field{i}"] = {"max_rel_err": e["max_rel_err"], "worst_lambda_block": e["worst_block"]}
+        res["err_vs_oracle"] = errs or None
     for r in recs:
         k = {0: "fft", 1: "fft", 4: "contract", 7: "contract"}.get(r["kernel"], "other")
         res["stage_ms_per_field"][k] = res["stage_ms_per_field"].get(k, 0.0) + r["ms"] / (count * steps)
@@ -242,6 +352,27 @@ def run_c5(api, steps, warmup, synth_steps=200):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     ncell = sum(int(np.prod(f.shape)) for f in fields)
+    # parity of the same plan against the stored oracle values (outside the timed region): the
+    # sums of every stored field, and the gradient at the stored cells for the stored weights
+    fwd_err, grad_err = {}, {}
+    z = plan.forward_raw(dev).cpu().numpy()
+    Gg = np.zeros((len(dev), 5, 8, 8))
+    gold_g = {}
+    for i, n in enumerate(edges_list):
+        fz = os.path.join(ROOT, "tests", "golden", f"c5_full3_{n}_field{i}.npz")
+        if os.path.exists(fz):
+            ref = np.load(fz)["zeta3"].real
+            e = block_errors(z[i].reshape(ref.shape), ref)
+            fwd_err[f"{n}^3 field {i}"] = {"max_rel_err": e["max_rel_err"], "worst_l_block": e["worst_block"]}
+        fg = os.path.join(ROOT, "tests", "golden", f"c5_grad3_{n}_field{i}.npz")
+        if os.path.exists(fg):
+            gold_g[i] = np.load(fg)
+            Gg[i] = gold_g[i]["G"]
+    if gold_g:
+        grads = plan.backward(dev, torch.from_numpy(Gg).cuda())
+        for i, g in gold_g.items():
+            got = grads[i].reshape(-1)[torch.from_numpy(g["cells"]).cuda()].double().cpu().numpy()
+            grad_err[f"{edges_list[i]}^3 field {i}"] = float(np.max(np.abs(got - g["grad"])) / np.max(np.abs(g["grad"])))
     plan.close()
     del dev
     n = 128
@@ -261,6 +392,8 @@ def run_c5(api, steps, warmup, synth_steps=200):
             "forward_fields_per_s": round(len(fields) * steps / (t1 - t0), 2),
             "adjoint_fields_per_s": round(len(fields) * steps / (t2 - t1), 2),
             "forward_plus_adjoint_fields_per_s": round(len(fields) * steps / (t2 - t0), 2),
+            "forward_err_vs_oracle": fwd_err or None,
+            "gradient_err_vs_oracle_at_stored_cells": grad_err or None,
             "synthesis": {"grid": n, "steps": synth_steps, "seconds": round(t4 - t3, 3),
                           "ms_per_step": round((t4 - t3) / synth_steps * 1e3, 3),
                           "loss_start": losses[0], "loss_end": losses[-1]}}
@@ -305,8 +438,9 @@ def run_512(api, steps, warmup):
 
 def run_proj(api, steps, warmup):
     """Projected 3PCF and 4PCF (Alg. 7, 8) of the 512^2 sigma 1 lognormal field (seed 0), 10
-    bins over (0,40], m up to 10: fields/s of each, the per-stage times and the live rate of the
-    projected 4PCF contraction, and the error against the stored oracle sums."""
+    bins over (0,40], m up to 10, with float32 and split-BF16 contractions: fields/s of each, the
+    per-stage times, the live rate of the projected 4PCF contraction, and the error against the
+    stored oracle sums (whole result and worst m / (m1, m2) block)."""
     import numpy as np
     import torch
     from fieldgen import lognormal_field, linear_edges
@@ -317,45 +451,103 @@ def run_proj(api, steps, warmup):
     stream = torch.cuda.Stream()
     res = {"workload": "projected 3PCF and 4PCF of one 512^2 float32 lognormal field (sigma 1), 10 bins over (0,40], "
                        "m up to 10 (331 (m1, m2) pairs)"}
-    for npcf in (3, 4):
-        plan = api.Plan([d.shape], linear_edges(40, 10), 10, npcf=npcf, prepare=False)
-        with torch.cuda.stream(stream):
-            plan.prepare(stream)
-        plan.autotune(stream)
-        out = torch.empty((1, plan.zeta_doubles), dtype=torch.float64, device="cuda")
-        with torch.cuda.stream(stream):
-            for _ in range(warmup):
-                plan.forward_raw(dev, out=out, stream=stream)
-        stream.synchronize()
-        plan.profile(True)
-        t0 = time.perf_counter()
-        with torch.cuda.stream(stream):
-            for _ in range(steps):
-                plan.forward_raw(dev, out=out, stream=stream)
-        stream.synchronize()
-        el = time.perf_counter() - t0
-        recs = plan.launch_records()
-        plan.profile(False)
-        r = {"value": round(steps / el, 2), "unit": "fields/s", "ms_per_field": round(el / steps * 1e3, 3),
-             "fft_ms_per_field": round(sum(x["ms"] for x in recs if x["stage"] == 0) / steps, 3),
-             "contract_ms_per_field": round(sum(x["ms"] for x in recs if x["stage"] == 1) / steps, 3)}
-        if npcf == 4:
-            q = [x for x in recs if x["kernel"] == 5]
-            ms, fl = sum(x["ms"] for x in q), sum(x["flops"] for x in q)
-            if ms:
-                r["contraction"] = {"kernel": "proj4_mfma_kernel<10> (float32 MFMA, one launch, a grid row per canonical m triple)",
-                                    "achieved_tflops": round(fl / (ms * 1e-3) / 1e12, 2),
-                                    "peak_tflops": 157.3, "peak_note": "float32 MFMA",
-                                    "frac": round(fl / (ms * 1e-3) / 1e12 / 157.3, 4)}
-        if gold is not None:
-            z = out.cpu().numpy()[0]
-            ref = gold["zeta3" if npcf == 3 else "zeta4"].reshape(-1)
-            zz = z.view(np.complex128) if ref.dtype.kind == "c" else z
-            zz = zz.reshape(-1)[: ref.size]
-            r["max_rel_err_vs_oracle"] = float(np.max(np.abs(zz - ref)) / np.max(np.abs(ref)))
-        res[f"proj{npcf}pcf"] = r
-        plan.close()
+    for precision in ("fp32", "split_bf16"):
+        for npcf in (3, 4):
+            plan = api.Plan([d.shape], linear_edges(40, 10), 10, npcf=npcf, prepare=False, precision=precision)
+            with torch.cuda.stream(stream):
+                plan.prepare(stream)
+            plan.autotune(stream)
+            out = torch.empty((1, plan.zeta_doubles), dtype=torch.float64, device="cuda")
+            with torch.cuda.stream(stream):
+                for _ in range(warmup):
+                    plan.forward_raw(dev, out=out, stream=stream)
+            stream.synchronize()
+            plan.profile(True)
+            t0 = time.perf_counter()
+            with torch.cuda.stream(stream):
+                for _ in range(steps):
+                    plan.forward_raw(dev, out=out, stream=stream)
+            stream.synchronize()
+            el = time.perf_counter() - t0
+            recs = plan.launch_records()
+            plan.profile(False)
+            r = {"value": round(steps / el, 2), "unit": "fields/s", "ms_per_field": round(el / steps * 1e3, 3),
+                 "fft_ms_per_field": round(sum(x["ms"] for x in recs if x["stage"] == 0) / steps, 3),
+                 "contract_ms_per_field": round(sum(x["ms"] for x in recs if x["stage"] == 1) / steps, 3)}
+            if npcf == 4:
+                q = [x for x in recs if x["kernel"] == 5]
+                ms, fl = sum(x["ms"] for x in q), sum(x["flops"] for x in q)
+                if ms:
+                    kn = ("proj4_split_kernel<10> (split-BF16 bf16 16x16x32 MFMA" if precision == "split_bf16"
+                          else "proj4_mfma_kernel<10> (float32 16x16x4 MFMA")
+                    r["contraction"] = {
+                        "kernel": kn + ", one launch, a grid row per canonical m triple)",
+                        "flops_note": "executed work: per cell and canonical triple NB^2 (8 + 8 NB) flops, the pair "
+                                      "products on the VALU and the complex b3 contraction on MFMA, against the "
+                                      "float32 peak",
+                        "achieved_tflops": round(fl / (ms * 1e-3) / 1e12, 2), "peak_tflops": 157.3,
+                        "frac": round(fl / (ms * 1e-3) / 1e12 / 157.3, 4),
+                        "counters": counters_for(f"proj4_prec{1 if precision == 'split_bf16' else 0}",
+                                                 COUNTER_SRCS["proj4_mfma"])}
+            if gold is not None:
+                z = out.cpu().numpy()[0].view(np.complex128)
+                ref = gold["zeta3" if npcf == 3 else "zeta4"]
+                e = block_errors(z.reshape(ref.shape), ref)
+                r["max_rel_err_vs_oracle"] = e["max_rel_err"]
+                r["worst_block_err_vs_oracle"] = e["worst_block"]
+            res[f"proj{npcf}pcf_{precision}"] = r
+            plan.close()
     return res
+
+
+def run_256_leg(api, fields, dev, edges, lmax, steps, warmup, precision, fused=True, autotune=True):
+    """Full 3PCF of the two 256^3 fields with one plan: fields/s over `steps` forward passes,
+    the fused last pass's time per field and the error against the stored oracle sums (whole
+    result, per l block, and per zeta_l^{b1 b2} entry relative to its own magnitude)."""
+    import numpy as np
+    import torch
+    n = fields[0].shape[0]
+    nbins = len(edges) - 1
+    stream = torch.cuda.Stream()
+    plan = api.Plan([f.shape for f in fields], edges, lmax, npcf=3, prepare=False, fused=fused, precision=precision)
+    with torch.cuda.stream(stream):
+        plan.prepare(stream)
+    if autotune:
+        plan.autotune(stream)
+    out = torch.empty((len(dev), plan.zeta_doubles), dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            plan.forward_raw(dev, out=out, stream=stream)
+    stream.synchronize()
+    plan.profile(True)
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(steps):
+            plan.forward_raw(dev, out=out, stream=stream)
+    stream.synchronize()
+    el = time.perf_counter() - t0
+    recs = plan.launch_records()
+    plan.profile(False)
+    plan.close()
+    z = out.cpu().numpy().reshape(len(dev), lmax + 1, nbins, nbins)
+    res = {"precision": precision, "fused": fused, "value": round(len(dev) * steps / el, 4), "unit": "fields/s",
+           "ms_per_field": round(el / (steps * len(dev)) * 1e3, 3),
+           "fused_last_pass_ms_per_field": round(sum(r["ms"] for r in recs if r["kernel"] == 2) / (steps * len(dev)), 3)
+           if fused else None,
+           "contraction_ms_per_field": round(sum(r["ms"] for r in recs if r["kernel"] == 3) / (steps * len(dev)), 3)
+           if not fused else None}
+    errs = []
+    for i in range(len(dev)):
+        g = os.path.join(ROOT, "tests", "golden", f"c3_full3_256_seed{i}.npz")
+        if n == 256 and os.path.exists(g):
+            ref = np.load(g)["zeta3"].real
+            e = block_errors(z[i], ref)
+            rel_entry = np.abs(z[i] - ref) / np.abs(ref)
+            errs.append({"max_rel_err": e["max_rel_err"], "per_l": e["per_block"],
+                         "worst_entry_rel_to_itself": float(np.max(rel_entry)),
+                         "median_entry_rel_to_itself": float(np.median(rel_entry))})
+    res["err_vs_oracle"] = errs or None
+    return res, z
 
 
 def main():
@@ -369,6 +561,10 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay the forward from a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unfused", action="store_true", help="plain path: write the coefficients, then contract")
+    ap.add_argument("--lines", default="main,split,plain,c4,c4var,big,proj,c5,cpu",
+                    help="comma list of the lines to run: main (the metric line), split (its split-BF16 leg), plain "
+                         "(the unfused float32 path), c4 (128^3 4PCF batch), c4var (its other contraction paths), "
+                         "big (512^3), proj (512^2 projected), c5 (uneven batch + adjoint + synthesis), cpu (oracle)")
     ap.add_argument("--c4-steps", type=int, default=1, help="steps of the 128^3 4PCF batch (0 skips it)")
     ap.add_argument("--c5-steps", type=int, default=1,
                     help="steps of the uneven-batch forward + adjoint and the synthesis demo (0 skips them)")
@@ -378,19 +574,27 @@ def main():
                     help="per-step HIP-event samples (eager and graph replay) after the timed steps")
     ap.add_argument("--plain-steps", type=int, default=2,
                     help="steps of the plain unfused float32 path on the same fields (0 skips it)")
+    ap.add_argument("--split-steps", type=int, default=3,
+                    help="steps of the split-BF16 leg of the metric workload (0 skips it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times (the reference "
                          "dispatch that scales the HBM byte counters of a counter run)")
     ap.add_argument("--write-traffic", metavar="COUNTER_DIR",
                     help="no GPU work: write profiles/traffic.json from two counter runs and exit")
+    ap.add_argument("--write-counters", metavar="COUNTER_CSV",
+                    help="no GPU work: write profiles/mfma_counters.json from a counter run and exit")
     args = ap.parse_args()
     if args.write_traffic:
         write_traffic(args.write_traffic, n=args.grid, copy_mib=1024)
+        return
+    if args.write_counters:
+        write_counters(args.write_counters)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    lines = set(x.strip() for x in args.lines.split(",") if x.strip())
 
     import numpy as np
     import torch
@@ -400,9 +604,11 @@ def main():
     n = args.grid
     nbins, rmax, lmax = 10, 32.0, 6
     edges = linear_edges(rmax, nbins)
-    print(f"bench: generating 2 lognormal {n}^3 fields", file=sys.stderr, flush=True)
-    fields = [lognormal_field((n, n, n), seed=0, sigma=0.5), lognormal_field((n, n, n), seed=1, sigma=1.5)]
-    dev = [torch.from_numpy(f).cuda() for f in fields]
+    fields = dev = None
+    if lines & {"main", "split", "plain", "cpu"}:
+        print(f"bench: generating 2 lognormal {n}^3 fields", file=sys.stderr, flush=True)
+        fields = [lognormal_field((n, n, n), seed=0, sigma=0.5), lognormal_field((n, n, n), seed=1, sigma=1.5)]
+        dev = [torch.from_numpy(f).cuda() for f in fields]
     if args.copy_probe_mib > 0:
         src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -410,176 +616,183 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    stream = torch.cuda.Stream()
-    torch.cuda.synchronize()
-    plan = api.Plan([f.shape for f in fields], edges, lmax, npcf=3, prepare=False, fused=not args.unfused)
-    t0 = time.perf_counter()
-    with torch.cuda.stream(stream):
-        plan.prepare(stream)
-    stream.synchronize()
-    cold_ms = (time.perf_counter() - t0) * 1e3
-    if not args.no_autotune:
-        plan.autotune(stream)
-    out = torch.empty((len(dev), plan.zeta_doubles), dtype=torch.float64, device="cuda")
-    print("bench: warmup", file=sys.stderr, flush=True)
-    with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            plan.forward_raw(dev, out=out, stream=stream, graph=args.graph)
-    stream.synchronize()
-    torch.cuda.synchronize()
-    print("bench: timed steps", file=sys.stderr, flush=True)
-    if not args.graph:
-        plan.profile(True)
-    t0 = time.perf_counter()
-    with torch.cuda.stream(stream):
-        for _ in range(args.steps):
-            plan.forward_raw(dev, out=out, stream=stream, graph=args.graph)
-    stream.synchronize()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    recs = plan.launch_records() if not args.graph else []
-    plan.profile(False)
-    value = len(dev) * args.steps / elapsed
-
-    # parity of this very run against the stored oracle values (when present)
-    z = out.cpu().numpy().reshape(len(dev), lmax + 1, nbins, nbins)
-    errs, errs_l = [], []
-    for i in range(len(dev)):
-        g = os.path.join(ROOT, "tests", "golden", f"c3_full3_256_seed{i}.npz")
-        if n == 256 and os.path.exists(g):
-            ref = np.load(g)["zeta3"].real
-            errs.append(float(np.max(np.abs(z[i] - ref)) / np.max(np.abs(ref))))
-            # per multipole: max over (b1, b2) of |Z - Z_oracle| / max |Z_oracle| of that l
-            errs_l.append([float(np.max(np.abs(z[i, l] - ref[l])) / np.max(np.abs(ref[l]))) for l in range(lmax + 1)])
-
-    # roofline of the dominant kernel (largest share of the timed region among the passes
-    # over all kernel arrays), from the live per-launch HIP-event records
-    # arrays per field: one per (l, m) and bin, less the packed m = 0 pairs of the fused path
-    narr = ((lmax + 1) * (lmax + 2) // 2 - (lmax + 1) // 2) * nbins
-    names = {0: f"middle inverse pass over all {narr} arrays (fft_pass_kernel, fft_pass_pf_kernel or "
-                f"mid_reg_kernel<...,+1>: the variant sb_autotune chose)",
-             1: (f"axis0_reg_kernel<16,16,...>" if n == 256 else f"axis0_kernel<{n},...>")
-                + " (axis-0 pass: kernel-spectrum regeneration + product + inverse transform)",
-             2: (f"last_reg_kernel<16,16,{(nbins + 3) // 4 * 4},PS_PACKED+PS_REAL>" if n == 256
-                 else f"last_contract_kernel<{n},...>")
-                + " (last inverse pass fused with the MFMA pair sums; two launches per field: the packed "
-                  "m = 0 pairs, then the rest)",
-             3: "pair_kernel (unfused 3PCF contraction)"}
-    srcs = TRAFFIC_SRCS
-    per = {}
-    for r in recs:
-        # the passes over all arrays of a field: one launch each for the axis-0 and middle
-        # passes, two for the last pass (counted as one pass over narr arrays)
-        if r["kernel"] not in names or (r["kernel"] in (0, 1, 3) and r["batch"] != narr):
-            continue
-        e = per.setdefault(r["kernel"], {"ms": 0.0, "bytes": 0.0, "arrays": 0})
-        e["ms"] += r["ms"]
-        e["bytes"] += r["bytes"]
-        e["arrays"] += r["batch"]
-    for e in per.values():
-        e["n"] = e["arrays"] / narr
+    value = elapsed = None
     roof = None
-    per_kernel = {}
-    for k, e in per.items():
-        per_kernel[names[k]] = {"passes": round(e["n"]), "avg_pass_ms": round(e["ms"] / e["n"], 4),
-                                "achieved_GBs": round(e["bytes"] / (e["ms"] * 1e-3) / 1e9, 1)}
-    if per:
-        k = max(per, key=lambda q: per[q]["ms"])
-        e = per[k]
-        achieved = e["bytes"] / (e["ms"] * 1e-3) / 1e9
-        traffic = traffic_for(f"kernel{k}_n{n}", srcs[k])
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": names[k],
-                "launches": round(e["n"]), "avg_launch_ms": round(e["ms"] / e["n"], 4),
-                "algorithmic_bytes_per_launch": e["bytes"] / e["n"]}
-    stages = {}
-    for r in recs:
-        k = {0: "fft", 1: "contract", 2: "other"}[r["stage"]]
-        stages.setdefault(k, [0.0, 0])
-        stages[k][0] += r["ms"]
-        stages[k][1] += 1
-    # per-step HIP-event times (median), eager and replayed from a HIP graph
-    step_ms = {}
-    if args.step_samples > 0:
-        for mode in ("eager", "graph"):
-            ms = []
-            with torch.cuda.stream(stream):
-                plan.forward_raw(dev, out=out, stream=stream, graph=mode == "graph")   # capture / warm
-                for _ in range(args.step_samples):
-                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    e0.record(stream)
-                    plan.forward_raw(dev, out=out, stream=stream, graph=mode == "graph")
-                    e1.record(stream)
-                    e1.synchronize()
-                    ms.append(e0.elapsed_time(e1))
-            ms.sort()
-            step_ms[mode] = {"median_ms": round(ms[len(ms) // 2], 3), "min_ms": round(ms[0], 3),
-                             "samples": len(ms), "fields_per_s_at_median": round(len(dev) / (ms[len(ms) // 2] * 1e-3), 3)}
-    plan.close()
-    del plan, out
-    torch.cuda.empty_cache()
-    # the plain float32 path of the same workload: every coefficient array written by the three
-    # passes, then the separate pair contraction (no fusion, no autotuning, no graph)
-    plain = None
-    if args.plain_steps > 0:
-        print("bench: plain unfused path", file=sys.stderr, flush=True)
-        pp = api.Plan([f.shape for f in fields], edges, lmax, npcf=3, fused=False)
-        pout = torch.empty((len(dev), pp.zeta_doubles), dtype=torch.float64, device="cuda")
-        pp.forward_raw(dev, out=pout)
+    per_kernel, stages, step_ms = {}, {}, {}
+    errs, errs_l = [], []
+    cold_ms = None
+    z = None
+    if "main" in lines:
+        stream = torch.cuda.Stream()
         torch.cuda.synchronize()
+        plan = api.Plan([f.shape for f in fields], edges, lmax, npcf=3, prepare=False, fused=not args.unfused)
         t0 = time.perf_counter()
-        for _ in range(args.plain_steps):
-            pp.forward_raw(dev, out=pout)
+        with torch.cuda.stream(stream):
+            plan.prepare(stream)
+        stream.synchronize()
+        cold_ms = (time.perf_counter() - t0) * 1e3
+        if not args.no_autotune:
+            plan.autotune(stream)
+        out = torch.empty((len(dev), plan.zeta_doubles), dtype=torch.float64, device="cuda")
+        print("bench: warmup", file=sys.stderr, flush=True)
+        with torch.cuda.stream(stream):
+            for _ in range(args.warmup):
+                plan.forward_raw(dev, out=out, stream=stream, graph=args.graph)
+        stream.synchronize()
         torch.cuda.synchronize()
-        pel = time.perf_counter() - t0
-        pz = pout.cpu().numpy().reshape(len(dev), lmax + 1, nbins, nbins)
-        plain = {"value": round(len(dev) * args.plain_steps / pel, 4), "unit": "fields/s",
-                 "speedup_of_default_path": round(value / (len(dev) * args.plain_steps / pel), 3),
-                 "max_abs_diff_vs_default_rel": float(np.max(np.abs(pz - z)) / np.max(np.abs(z)))}
-        pp.close()
-        del pp, pout
+        print("bench: timed steps", file=sys.stderr, flush=True)
+        if not args.graph:
+            plan.profile(True)
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            for _ in range(args.steps):
+                plan.forward_raw(dev, out=out, stream=stream, graph=args.graph)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        recs = plan.launch_records() if not args.graph else []
+        plan.profile(False)
+        value = len(dev) * args.steps / elapsed
+
+        # parity of this very run against the stored oracle values (when present)
+        z = out.cpu().numpy().reshape(len(dev), lmax + 1, nbins, nbins)
+        for i in range(len(dev)):
+            g = os.path.join(ROOT, "tests", "golden", f"c3_full3_256_seed{i}.npz")
+            if n == 256 and os.path.exists(g):
+                ref = np.load(g)["zeta3"].real
+                e = block_errors(z[i], ref)
+                errs.append(e["max_rel_err"])
+                # per multipole: max over (b1, b2) of |Z - Z_oracle| / max |Z_oracle| of that l
+                errs_l.append(e["per_block"])
+
+        # roofline of the dominant kernel (largest share of the timed region among the passes
+        # over all kernel arrays), from the live per-launch HIP-event records
+        # arrays per field: one per (l, m) and bin, less the packed m = 0 pairs of the fused path
+        narr = ((lmax + 1) * (lmax + 2) // 2 - (lmax + 1) // 2) * nbins
+        names = {0: f"middle inverse pass over all {narr} arrays (fft_pass_kernel, fft_pass_pf_kernel or "
+                    f"mid_reg_kernel<...,+1>: the variant sb_autotune chose)",
+                 1: (f"axis0_reg_kernel<16,16,...>" if n == 256 else f"axis0_kernel<{n},...>")
+                    + " (axis-0 pass: kernel-spectrum regeneration + product + inverse transform)",
+                 2: (f"last_reg_kernel<16,16,{(nbins + 3) // 4 * 4},PS_PACKED+PS_REAL,0>" if n == 256
+                     else f"last_contract_kernel<{n},...>")
+                    + " (last inverse pass fused with the MFMA pair sums; two launches per field: the packed "
+                      "m = 0 pairs, then the rest)",
+                 3: "pair_kernel (unfused 3PCF contraction)"}
+        srcs = TRAFFIC_SRCS
+        per = {}
+        for r in recs:
+            # the passes over all arrays of a field: one launch each for the axis-0 and middle
+            # passes, two for the last pass (counted as one pass over narr arrays)
+            if r["kernel"] not in names or (r["kernel"] in (0, 1, 3) and r["batch"] != narr):
+                continue
+            e = per.setdefault(r["kernel"], {"ms": 0.0, "bytes": 0.0, "arrays": 0})
+            e["ms"] += r["ms"]
+            e["bytes"] += r["bytes"]
+            e["arrays"] += r["batch"]
+        for e in per.values():
+            e["n"] = e["arrays"] / narr
+        for k, e in per.items():
+            per_kernel[names[k]] = {"passes": round(e["n"]), "avg_pass_ms": round(e["ms"] / e["n"], 4),
+                                    "achieved_GBs": round(e["bytes"] / (e["ms"] * 1e-3) / 1e9, 1)}
+        if per:
+            k = max(per, key=lambda q: per[q]["ms"])
+            e = per[k]
+            achieved = e["bytes"] / (e["ms"] * 1e-3) / 1e9
+            traffic = traffic_for(f"kernel{k}_n{n}", srcs[k])
+            roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": names[k],
+                    "launches": round(e["n"]), "avg_launch_ms": round(e["ms"] / e["n"], 4),
+                    "algorithmic_bytes_per_launch": e["bytes"] / e["n"]}
+        for r in recs:
+            k = {0: "fft", 1: "contract", 2: "other"}[r["stage"]]
+            stages.setdefault(k, [0.0, 0])
+            stages[k][0] += r["ms"]
+            stages[k][1] += 1
+        # per-step HIP-event times (median), eager and replayed from a HIP graph
+        if args.step_samples > 0:
+            for mode in ("eager", "graph"):
+                ms = []
+                with torch.cuda.stream(stream):
+                    plan.forward_raw(dev, out=out, stream=stream, graph=mode == "graph")   # capture / warm
+                    for _ in range(args.step_samples):
+                        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                        e0.record(stream)
+                        plan.forward_raw(dev, out=out, stream=stream, graph=mode == "graph")
+                        e1.record(stream)
+                        e1.synchronize()
+                        ms.append(e0.elapsed_time(e1))
+                ms.sort()
+                step_ms[mode] = {"median_ms": round(ms[len(ms) // 2], 3), "min_ms": round(ms[0], 3),
+                                 "samples": len(ms),
+                                 "fields_per_s_at_median": round(len(dev) / (ms[len(ms) // 2] * 1e-3), 3)}
+        plan.close()
+        del plan, out
+        torch.cuda.empty_cache()
+    # the split-BF16 leg of the same workload (fused pair sums on bf16 MFMA with hi + lo splits)
+    # and the plain float32 path (every coefficient array written by the three passes, then the
+    # separate pair contraction; no fusion, no autotuning, no graph), each with its own error
+    split = plain = None
+    if "split" in lines and args.split_steps > 0:
+        print("bench: split-BF16 leg", file=sys.stderr, flush=True)
+        split, _ = run_256_leg(api, fields, dev, edges, lmax, args.split_steps, 1, "split_bf16")
+        if value:
+            split["speedup_vs_plain_fp32"] = None
+        torch.cuda.empty_cache()
+    if "plain" in lines and args.plain_steps > 0:
+        print("bench: plain unfused path", file=sys.stderr, flush=True)
+        plain, pz = run_256_leg(api, fields, dev, edges, lmax, args.plain_steps, 1, "fp32", fused=False,
+                                autotune=False)
+        if value:
+            plain["speedup_of_default_path"] = round(value / plain["value"], 3)
+            plain["max_abs_diff_vs_default_rel"] = float(np.max(np.abs(pz - z)) / np.max(np.abs(z)))
+        if split:
+            split["speedup_vs_plain_fp32"] = round(split["value"] / plain["value"], 3)
         torch.cuda.empty_cache()
     c4 = None
-    if args.c4_steps > 0:
+    if "c4" in lines and args.c4_steps > 0:
         print("bench: 128^3 4PCF batch", file=sys.stderr, flush=True)
         c4 = run_4pcf_batch(api, args.c4_steps, 1)
-        variants = {}
-        for prec, mf, par in (("split_bf16", True, "even"), ("fp32", False, "even"), ("fp32", True, "odd")):
-            r = run_4pcf_batch(api, args.c4_steps, 1, precision=prec, mfma=mf, parity=par)
-            key = f"{prec}_{'mfma' if mf else 'valu'}" + ("_odd_parity_23_lambda" if par == "odd" else "")
-            variants[key] = {
-                "value": r["value"], "contraction_ms_per_field": r["contraction"]["ms_per_field"],
-                "achieved_tflops": r["contraction"]["achieved_tflops"], "kernel": r["contraction"]["kernel"]}
-        c4["other_contraction_paths"] = variants
+        if "c4var" in lines:
+            variants = {}
+            for prec, mf, par in (("split_bf16", True, "even"), ("fp32", False, "even"), ("fp32", True, "odd")):
+                r = run_4pcf_batch(api, args.c4_steps, 1, precision=prec, mfma=mf, parity=par)
+                key = f"{prec}_{'mfma' if mf else 'valu'}" + ("_odd_parity_23_lambda" if par == "odd" else "")
+                variants[key] = {
+                    "value": r["value"], "contraction_ms_per_field": r["contraction"]["ms_per_field"],
+                    "achieved_tflops": r["contraction"]["achieved_tflops"], "kernel": r["contraction"]["kernel"],
+                    "counters": r["contraction"]["counters"], "err_vs_oracle": r.get("err_vs_oracle")}
+            c4["other_contraction_paths"] = variants
     big = None
-    if args.big_steps > 0:
+    if "big" in lines and args.big_steps > 0:
         print("bench: 512^3 3PCF", file=sys.stderr, flush=True)
         big = run_512(api, args.big_steps, 1)
         torch.cuda.empty_cache()
     proj = None
-    if args.proj_steps > 0:
+    if "proj" in lines and args.proj_steps > 0:
         print("bench: 512^2 projected 3PCF and 4PCF", file=sys.stderr, flush=True)
         proj = run_proj(api, args.proj_steps, 1)
     c5 = None
-    if args.c5_steps > 0:
+    if "c5" in lines and args.c5_steps > 0:
         print("bench: uneven batch forward + adjoint, synthesis demo", file=sys.stderr, flush=True)
         c5 = run_c5(api, args.c5_steps, 1)
     cpu = None
-    if not args.no_cpu_baseline:
+    if "cpu" in lines and not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(fields[0], edges, lmax)
     line = {
-        "metric": METRIC, "value": round(value, 4), "unit": "fields/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
+        "metric": METRIC, "value": round(value, 4) if value else None, "unit": "fields/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3) if elapsed else None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"full 3PCF, 2 lognormal {n}^3 float32 fields (sigma 0.5, 1.5), 10 bins over (0,32], "
-                               f"lmax 6, kernel spectra resident", "grid": n, "nbins": nbins, "lmax": lmax,
-                   "batch": len(dev), "graph": bool(args.graph), "fused": not args.unfused,
+                               f"lmax 6, kernel spectra resident, float32 fused pair sums", "grid": n, "nbins": nbins,
+                   "lmax": lmax, "batch": 2, "graph": bool(args.graph), "fused": not args.unfused,
                    "autotuned": not args.no_autotune},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "cold_setup_ms": round(cold_ms, 1),
+        "cold_setup_ms": round(cold_ms, 1) if cold_ms else None,
         "step_times": step_ms or None,
+        "split_bf16_leg": split,
         "plain_fp32_unfused": plain,
         "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
         "per_kernel": per_kernel,

@@ -727,12 +727,34 @@ sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
         a.nblocks = nblocks;
         a.odd = (p->prob.flags & SB_FLAG_ODD_PARITY) != 0;
         a.lm_src = p->npack > 0 ? p->d_lmsrc : nullptr;
-        // algorithmic flops per cell and Lambda: 8 per nonzero coupling term and bin pair, then
-        // per mc the weight (2) and the b3 contraction (4 per bin) for each bin pair
+        // flops per cell and canonical Lambda of the plain kernel: per bin pair, 8 per nonzero
+        // coupling term, then per mc the weight (2) and the b3 contraction (4 per bin)
         auto lam_flops = [&](size_t c) {
             double nt = 0.0;
             for (const auto &t : p->f4.terms[c]) nt += t.c != 0.0 ? 1.0 : 0.0;
             return (double)NB * NB * (nt * 8.0 + (p->f4.canon[c].l[2] + 1) * (2.0 + 4.0 * NB));
+        };
+        // flops per cell and canonical Lambda the matrix-core kernel executes on real bins (padding
+        // excluded), per computed bin pair (NB^2, or NB (NB + 1) / 2 when la = lb): the weight times
+        // the b1 coefficients (2 per m of la), the coupling FMAs (mc = 0: the +-ma terms paired, 1
+        // FMA for ma = 0 and 2 per ma > 0 for even Lambda, 2 per ma > 0 for odd; mc > 0: 4 per term,
+        // 2 when ma or mb is 0) and the b3 contraction (per mc and b3: 1 FMA for mc = 0, 2 above),
+        // 2 flops per FMA
+        auto lam_flops_mfma = [&](size_t c) {
+            const Lam &C = p->f4.canon[c];
+            const int la = C.l[0], lb = C.l[1], lc = C.l[2];
+            const bool odd = ((la + lb + lc) & 1) != 0;
+            const double pairs = la == lb ? NB * (NB + 1) / 2.0 : (double)NB * NB;
+            double fma = 0.0;
+            for (int ma = 0; ma <= std::min(la, lb); ++ma) fma += ma == 0 ? (odd ? 0.0 : 1.0) : 2.0;
+            for (int mc = 1; mc <= lc; ++mc)
+                for (int ma = -la; ma <= la; ++ma) {
+                    const int mb = -ma - mc;
+                    if (mb < -lb || mb > lb) continue;
+                    fma += (ma == 0 || mb == 0) ? 2.0 : 4.0;
+                }
+            fma += NB * (1.0 + 2.0 * lc);
+            return pairs * (2.0 * fma + 2.0 * (la + 1));
         };
         if (p->quad_mfma) {
             // one launch per canonical Lambda: its coefficients stay in registers
@@ -760,7 +782,7 @@ sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
                 by = (double)G.ng * (8.0 * NB * ncol + 4.0);
                 e = p->timed_launch(STAGE_CONTRACT, K_QUAD_MFMA, s,
                                     [&]() { return launch_quad_mfma(C.l[0], C.l[1], C.l[2], m, s); }, 0, 0, 1, by,
-                                    (double)G.ng * lam_flops(c));
+                                    (double)G.ng * lam_flops_mfma(c));
             }
         } else {
             double fl = 0.0;
