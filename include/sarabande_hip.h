@@ -90,6 +90,13 @@ enum {
                                  real) are carried two to a transform, as real and imaginary part,
                                  which removes floor((lmax + 1) / 2) of the (lmax + 1)(lmax + 2) / 2
                                  arrays per bin */
+    SB_FLAG_REGEN_KERNELS = 64u, /* fused 3PCF plans: keep no kernel spectra in the persistent buffer;
+                                 every call regenerates the stored axis-0 planes of each chunk of
+                                 kernel groups (Alg. 1 / Alg. 2 and the transforms along the other
+                                 axes) in scratch before using them.  Chosen automatically when the
+                                 cache of every shape would exceed 64 GiB (1024^3 grids); such plans
+                                 have no adjoint (sb_backward returns SB_EUNSUPPORTED) and no packed
+                                 m = 0 pairs.  SB_EUNSUPPORTED on other paths */
     SB_FLAG_CHECK_FINITE = 32u /* sb_forward / sb_backward / sb_normalize first scan every input array
                                  (densities, and grad_zeta) for NaN and Inf and return SB_ENONFINITE,
                                  with no other work done, when one holds any.  The scan waits for the
@@ -133,7 +140,7 @@ typedef struct sb_plan sb_plan;
 /* Create a plan for a batch of `batch` fields whose shapes are given row by row in
  * `shapes` (host, batch x ndim int64, C order of each field's extents).  Fields may differ
  * in shape (uneven batch); each grid edge must be one of 8, 12, 16, 24, 32, 48, 64, 96,
- * 128, 160, 192, 256, 512 (lengths whose transforms are built: SB_EUNSUPPORTED otherwise).
+ * 128, 160, 192, 256, 512, 1024 (lengths whose transforms are built: SB_EUNSUPPORTED otherwise).
  * The problem statement is that of the measure(**kwargs) of Sec. 3.3; bins follow the mask
  * of Alg. 1 / Alg. 2.  `prob` and its edges are copied.  Host memory only; *out is NULL on
  * failure.  Errors: SB_EINVAL (null pointer, ndim not 2 / 3, npcf not 3 / 4, nbins < 1, edges

@@ -50,11 +50,13 @@ class Plan:
     scratch_limit: bytes of kernel arrays a 3PCF plan keeps at once (default 48 GiB); above it
                  the passes run over chunks of (l, m) groups (sb_plan_set_scratch_limit)
     check_finite: scan the inputs of every call for NaN / Inf first (SB_FLAG_CHECK_FINITE)
+    regen_kernels: fused 3PCF: keep no kernel spectra, regenerate them per call in scratch
+                 (SB_FLAG_REGEN_KERNELS; automatic when the cache would exceed 64 GiB)
     """
 
     def __init__(self, shapes, bin_edges, lmax, npcf=3, precision="fp32", input_dtype=torch.float32,
                  device=None, stream=None, prepare=True, keep_coeffs=False, fused=True, mfma=True,
-                 scratch_limit=None, parity="even", pack=True, check_finite=False):
+                 scratch_limit=None, parity="even", pack=True, check_finite=False, regen_kernels=False):
         self.lib = _lib.load()
         shapes = [tuple(int(x) for x in s) for s in shapes]
         ndim = len(shapes[0])
@@ -74,7 +76,8 @@ class Plan:
                                | (0 if mfma else _lib.SB_FLAG_NO_MFMA)
                                | (_lib.SB_FLAG_ODD_PARITY if parity == "odd" else 0)
                                | (0 if pack else _lib.SB_FLAG_NO_PACK)
-                               | (_lib.SB_FLAG_CHECK_FINITE if check_finite else 0))
+                               | (_lib.SB_FLAG_CHECK_FINITE if check_finite else 0)
+                               | (_lib.SB_FLAG_REGEN_KERNELS if regen_kernels else 0))
         if parity not in ("even", "odd"):
             raise ValueError("parity must be 'even' or 'odd'")
         self.parity = parity

@@ -119,6 +119,12 @@ sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta
     if (p->prob.ndim != 3 || p->prob.npcf != 3) return fail(SB_EUNSUPPORTED, "adjoint is implemented for the full 3PCF");
     if (!p->persist || !p->scratch) return fail(SB_EWORKSPACE, "workspace not bound");
     if (!p->prepared) return fail(SB_ESTATE, "sb_prepare has not run on the bound workspace");
+    if (p->regen) return fail(SB_EUNSUPPORTED, "the adjoint reads cached kernel spectra; this plan regenerates them");
+    if (p->adj_fused)
+        for (const auto &G : p->groups)
+            if (fused_last_rows((int)G.n[2], p->prob.nbins) <= 0)
+                return fail(SB_EUNSUPPORTED, "no fused adjoint last pass for a last axis of " + std::to_string(G.n[2]) +
+                                                 " (use SB_FLAG_UNFUSED)");
     const int NB = p->prob.nbins;
     float2 *acc = reinterpret_cast<float2 *>(p->scratch + p->off_grad);
     float2 *vtmp = reinterpret_cast<float2 *>(p->scratch + p->off_vtmp);

@@ -700,6 +700,7 @@ hipError_t launch_fft_pass(const FftPass &a, hipStream_t s) {
         case 192: return launch<192, 8, 128, 8, 8, 3>(a, s);
         case 256: return v == 1 ? launch<256, 32, 256, 8, 8, 4>(a, s) : launch<256, 16, 256, 8, 8, 4>(a, s);
         case 512: return v == 1 ? launch<512, 64, 256, 8, 8, 8>(a, s) : launch<512, 32, 256, 8, 8, 8>(a, s);
+        case 1024: return v == 1 ? launch<1024, 128, 512, 8, 8, 4, 4>(a, s) : launch<1024, 64, 256, 16, 16, 4>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -771,8 +772,8 @@ int fused_last_rows(int n, int nb) {
 
 hipError_t launch_last_contract(const LastArgs &a, hipStream_t s) {
     switch (a.n) {
-#define SB_X(N, TPP, NT, ...) case N: return launch_last_for<N>(a, s);
-        SB_FFT_CONFIGS(SB_X)
+#define SB_X(N, TPP, ...) case N: return launch_last_for<N>(a, s);
+        SB_LAST_CONFIGS(SB_X)
 #undef SB_X
         default: return hipErrorInvalidValue;
     }
@@ -781,7 +782,7 @@ hipError_t launch_last_contract(const LastArgs &a, hipStream_t s) {
 bool fft_supported(int n) {
     switch (n) {
         case 8: case 12: case 16: case 24: case 32: case 48: case 64: case 96:
-        case 128: case 160: case 192: case 256: case 512: return true;
+        case 128: case 160: case 192: case 256: case 512: case 1024: return true;
         default: return false;
     }
 }

@@ -324,7 +324,7 @@ __device__ __forceinline__ double wave_sum64(double v) {
     X(8, 1, 64, 8) X(12, 1, 64, 4, 3) X(16, 4, 64, 4, 4) X(24, 2, 128, 4, 2, 3)             \
     X(32, 4, 64, 4, 8) X(48, 4, 64, 4, 4, 3) X(64, 8, 128, 8, 8) X(96, 4, 64, 4, 8, 3)      \
     X(128, 16, 256, 8, 8, 2) X(160, 4, 64, 4, 8, 5) X(192, 8, 128, 8, 8, 3)                  \
-    X(256, 16, 256, 8, 8, 4) X(512, 32, 256, 8, 8, 8)
+    X(256, 16, 256, 8, 8, 4) X(512, 32, 256, 8, 8, 8) X(1024, 64, 256, 16, 16, 4)
 
 // Shape of the fused passes (axis-0 correlation, last pass + contraction): more threads
 // per pencil than the plain passes, so that each thread holds at most ~12 elements and
@@ -334,10 +334,12 @@ __device__ __forceinline__ double wave_sum64(double v) {
     X(8, 1, 64, 8) X(12, 1, 64, 4, 3) X(16, 4, 64, 4, 4) X(24, 2, 128, 4, 2, 3)              \
     X(32, 4, 64, 4, 8) X(48, 4, 64, 4, 4, 3) X(64, 8, 128, 8, 8) X(96, 8, 128, 4, 4, 2, 3)   \
     X(128, 16, 256, 8, 8, 2) X(160, 8, 128, 4, 4, 2, 5) X(192, 16, 256, 4, 4, 4, 3)          \
-    X(256, 16, 256, 16, 16) X(512, 64, 512, 8, 8, 8)
+    X(256, 16, 256, 16, 16) X(512, 64, 512, 8, 8, 8) X(1024, 128, 512, 8, 8, 4, 4)
 
 // Threads per pencil of the fused last pass (the axis-0 pass uses SB_FUSED_CONFIGS):
-// at most 512 threads per workgroup for up to 16 bins.
+// at most 512 threads per workgroup for up to 16 bins.  1024 has no fused last pass (a tile of
+// all bins of a row would not fit the LDS): its 3PCFs run the plain last pass and the pair
+// contraction.
 #define SB_LAST_CONFIGS(X)                                                                   \
     X(8, 1, 8) X(12, 1, 4, 3) X(16, 4, 4, 4) X(24, 2, 4, 2, 3) X(32, 4, 4, 8) X(48, 4, 4, 4, 3) \
     X(64, 8, 8, 8) X(96, 8, 4, 4, 2, 3) X(128, 16, 8, 8, 2) X(160, 8, 4, 4, 2, 5)              \

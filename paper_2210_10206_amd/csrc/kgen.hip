@@ -46,10 +46,13 @@ __global__ void kgen_kernel(KgenArgs a) {
             if (a.thr[b] < s && s <= a.thr[b + 1]) { bin = b; break; }
     }
     const int nb = a.nbins;
-    float2 *out = a.out;
     const int64_t ng = a.ng;
+    // array base of kernel group g (nullptr: not written by this launch)
+    auto group_out = [&](int g) -> float2 * {
+        return (g >= a.gfirst && g < a.gfirst + a.gcount) ? a.out + (int64_t)(g - a.gfirst) * nb * ng : nullptr;
+    };
     if (bin < 0) {
-        for (int k = 0; k < (a.nlm + a.npack) * nb; ++k) out[(int64_t)k * ng + cell] = make_float2(0.f, 0.f);
+        for (int k = 0; k < a.gcount * nb; ++k) a.out[(int64_t)k * ng + cell] = make_float2(0.f, 0.f);
         return;
     }
     const double r = sqrt((double)s);
@@ -58,9 +61,10 @@ __global__ void kgen_kernel(KgenArgs a) {
     if (a.ndim == 2) {
         double pr = 1.0, pi = 0.0;  // ((x - i y)/r)^m
         for (int m = 0; m <= a.lmax; ++m) {
-            for (int b = 0; b < nb; ++b)
-                out[(int64_t)(m * nb + b) * ng + cell] =
-                    (b == bin) ? make_float2((float)(pr * sc), (float)(pi * sc)) : make_float2(0.f, 0.f);
+            if (float2 *o = group_out(m))
+                for (int b = 0; b < nb; ++b)
+                    o[(int64_t)b * ng + cell] =
+                        (b == bin) ? make_float2((float)(pr * sc), (float)(pi * sc)) : make_float2(0.f, 0.f);
             const double nr = pr * ux + pi * uy;   // (pr + i pi)(ux - i uy)
             const double ni = pi * ux - pr * uy;
             pr = nr; pi = ni;
@@ -83,8 +87,8 @@ __global__ void kgen_kernel(KgenArgs a) {
             const double f = a.norm[lm] * q * sc;
             const float2 v = make_float2((float)(f * pr), (float)(f * pi));
             if (m == 0) k0[l] = v.x;
-            for (int b = 0; b < nb; ++b)
-                out[(int64_t)(lm * nb + b) * ng + cell] = (b == bin) ? v : make_float2(0.f, 0.f);
+            if (float2 *o = group_out(lm))
+                for (int b = 0; b < nb; ++b) o[(int64_t)b * ng + cell] = (b == bin) ? v : make_float2(0.f, 0.f);
         }
         // advance to m + 1
         qmm = -(2.0 * m + 1.0) * qmm;
@@ -95,8 +99,8 @@ __global__ void kgen_kernel(KgenArgs a) {
     // packed pairs: K_{l_a 0} + i K_{l_b 0}, both real
     for (int i = 0; i < a.npack; ++i) {
         const float2 v = make_float2(k0[a.pack_l[2 * i]], k0[a.pack_l[2 * i + 1]]);
-        for (int b = 0; b < nb; ++b)
-            out[(int64_t)((a.nlm + i) * nb + b) * ng + cell] = (b == bin) ? v : make_float2(0.f, 0.f);
+        if (float2 *o = group_out(a.nlm + i))
+            for (int b = 0; b < nb; ++b) o[(int64_t)b * ng + cell] = (b == bin) ? v : make_float2(0.f, 0.f);
     }
 }
 

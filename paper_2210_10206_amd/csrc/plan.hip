@@ -30,7 +30,7 @@ sb_status hip_fail(hipError_t e, const char *what) {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static bool supported_edge(int64_t n) {
-    return fft_supported((int)n) && n >= 8 && n <= 512;
+    return n >= 8 && n <= 1024 && fft_supported((int)n);
 }
 
 // ------------------------------------------------------------------ plan creation
@@ -126,11 +126,16 @@ void layout_scratch(sb_plan *p) {
     size_t sc = 0;
     p->off_w = sc; sc += align256((size_t)p->max_ng * sizeof(float));
     p->off_dhat = sc; sc += align256((size_t)p->max_ng * sizeof(float2));
-    const bool adjoint = prob->ndim == 3 && prob->npcf == 3;
+    const bool adjoint = prob->ndim == 3 && prob->npcf == 3 && !p->regen;
     // the adjoint's v arrays directly before the coefficient arrays: its fused pass writes the v
     // of each group into the slot before that group's coefficients
     if (adjoint) { p->off_vtmp = sc; sc += align256((size_t)NB * p->max_ng * sizeof(float2)); }
     p->off_coef = sc; sc += align256((size_t)p->chunk_groups * NB * p->max_ng * sizeof(float2));
+    if (p->regen) {   // the stored axis-0 planes of one chunk's kernels
+        int64_t kc = 0;
+        for (const auto &G : p->groups) kc = std::max<int64_t>(kc, (int64_t)G.np * G.plane);
+        p->off_kc = sc; sc += align256((size_t)p->chunk_groups * NB * kc * sizeof(float2));
+    }
     int groups = 0, nvals = 0, nblocks = 0, tile_lo = 0, tile_hi = 0;
     p->contract_tile_range(&tile_lo, &tile_hi);
     contraction_shape(p, p->max_ng, &groups, &nvals, &nblocks, tile_lo);
@@ -220,7 +225,7 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
             if (!supported_edge(sh[d])) {
                 delete p;
                 return fail(SB_EUNSUPPORTED, "grid edge " + std::to_string(sh[d]) +
-                                                 " not in {8,12,16,24,32,48,64,96,128,160,192,256,512}");
+                                                 " not in {8,12,16,24,32,48,64,96,128,160,192,256,512,1024}");
             }
             ng *= sh[d];
         }
@@ -244,12 +249,30 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
     p->nk = p->nlm * NB;
     // array groups of the fused 3D 3PCF forward path: the real m = 0 kernels go two to a
     // complex transform (the kernel Y*_{l0} Phi_b of eq. almconv is real), packed pairs first, then one (l, m) per group
+    // Kernel spectra regenerated per call instead of cached (fused 3PCF plans only): on request, or
+    // when the compact cache of every shape would exceed kKernelCacheCap (1024^3 at 10 bins and
+    // lmax 6 would need about 169 GB).
+    {
+        int64_t r0c = 0;
+        while ((r0c + 1) * (r0c + 1) <= p->thr[NB]) ++r0c;
+        double cache = 0.0;
+        for (const auto &G : p->groups)
+            cache += (double)p->nlm * NB * support_planes(G.n[0], std::min<int64_t>(r0c, G.n[0])) *
+                     (double)(G.ng / G.n[0]) * sizeof(float2);
+        const bool fused3 = prob->npcf == 3 && (prob->flags & (SB_FLAG_UNFUSED | SB_FLAG_KEEP_COEFFS)) == 0;
+        if ((prob->flags & SB_FLAG_REGEN_KERNELS) && !fused3) {
+            delete p;
+            return fail(SB_EUNSUPPORTED, "kernel regeneration applies to the fused 3PCF path only");
+        }
+        p->regen = fused3 && ((prob->flags & SB_FLAG_REGEN_KERNELS) || cache > kKernelCacheCap);
+    }
     {
         // 3PCF: the fused path (forward and adjoint); 4PCF: the coefficients the contraction reads
         // (its kernels take each m = 0 column from its packed array through lm_src)
         bool pack = prob->ndim == 3 && prob->lmax >= 1 && (prob->flags & (SB_FLAG_KEEP_COEFFS | SB_FLAG_NO_PACK)) == 0;
         if (prob->npcf == 3) {
             if (prob->flags & SB_FLAG_UNFUSED) pack = false;
+            if (p->regen) pack = false;
             for (const auto &G : p->groups)
                 if (fused_last_rows((int)G.n[prob->ndim - 1], NB) <= 0) pack = false;
         }
@@ -433,7 +456,7 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
         G.r0 = (int)std::min<int64_t>(r0, G.n[0]);
         G.np = support_planes(G.n[0], G.r0);
         G.khat_off = pers;
-        pers += align256((size_t)p->kernel_groups() * NB * G.np * G.plane * sizeof(float2));
+        if (!p->regen) pers += align256((size_t)p->kernel_groups() * NB * G.np * G.plane * sizeof(float2));
         // fused last pass: rows per tile fixed by the kernel's compile-time tile shape
         const int nl = (int)G.n[prob->ndim - 1];
         G.rows = NB <= kMaxBins ? fused_last_rows(nl, NB) : 0;
@@ -517,41 +540,49 @@ sb_status fft_all_axes(sb_plan *p, const ShapeGroup &G, int sign, int first_load
     return fft_axes(p, G.n, p->prob.ndim, G.ng, axes, p->prob.ndim, sign, first_load, in, in_bs, out, out_bs, batch, s);
 }
 
+// Kernel groups [g0, g0 + count) of shape G (Alg. 1 / Alg. 2: the stored axis-0 planes of the
+// binned kernels), transformed along every axis but 0, written to out (count * nbins arrays of
+// np * plane cells); axis 0 is transformed on the fly by the first inverse pass.
+static sb_status gen_kernels(sb_plan *p, const ShapeGroup &G, int g0, int count, float2 *out, hipStream_t s) {
+    const int nd = p->prob.ndim;
+    const int64_t ncell = (int64_t)G.np * G.plane;
+    KgenArgs a{};
+    a.ndim = nd;
+    for (int d = 0; d < 3; ++d) a.n[d] = G.n[d];
+    a.ng = ncell;
+    a.np = G.np;
+    a.r0 = G.r0;
+    a.nbins = p->prob.nbins;
+    for (int b = 0; b <= p->prob.nbins; ++b) a.thr[b] = p->thr[b];
+    a.lmax = p->prob.lmax;
+    a.nlm = p->nlm;
+    a.npack = p->npack;
+    for (int i = 0; i < 2 * p->npack; ++i) a.pack_l[i] = p->pack_l[i];
+    if (nd == 3)
+        for (int l = 0; l <= p->prob.lmax; ++l)
+            for (int m = 0; m <= l; ++m) a.norm[l * (l + 1) / 2 + m] = ylm_norm(l, m);
+    a.scale = (float)(1.0 / (double)G.ng);
+    a.gfirst = g0;
+    a.gcount = count;
+    a.out = out;
+    hipError_t e = launch_kgen(a, s);
+    if (e != hipSuccess) return hip_fail(e, "kernel generation");
+    const int64_t cn[3] = {G.np, G.n[1], G.n[2]};
+    const int axes[2] = {1, 2};
+    return fft_axes(p, cn, nd, ncell, axes, nd - 1, -1, LOAD_C, out, ncell, out, ncell, count * p->prob.nbins, s);
+}
+
 sb_status prepare(sb_plan *p, hipStream_t s) {
     if (!p->persist) return fail(SB_EWORKSPACE, "workspace not bound");
-    const int nd = p->prob.ndim;
     // the plan's tables go to the head of the persistent buffer (the host copy stays with the plan)
     hipError_t te = hipMemcpyAsync(p->persist, p->host_tab.data(), p->host_tab.size(), hipMemcpyHostToDevice, s);
     if (te != hipSuccess) return hip_fail(te, "table upload");
-    for (auto &G : p->groups) {
-        float2 *kc = reinterpret_cast<float2 *>(p->persist + G.khat_off);
-        const int64_t ncell = (int64_t)G.np * G.plane;
-        KgenArgs a{};
-        a.ndim = nd;
-        for (int d = 0; d < 3; ++d) a.n[d] = G.n[d];
-        a.ng = ncell;
-        a.np = G.np;
-        a.r0 = G.r0;
-        a.nbins = p->prob.nbins;
-        for (int b = 0; b <= p->prob.nbins; ++b) a.thr[b] = p->thr[b];
-        a.lmax = p->prob.lmax;
-        a.nlm = p->nlm;
-        a.npack = p->npack;
-        for (int i = 0; i < 2 * p->npack; ++i) a.pack_l[i] = p->pack_l[i];
-        if (nd == 3)
-            for (int l = 0; l <= p->prob.lmax; ++l)
-                for (int m = 0; m <= l; ++m) a.norm[l * (l + 1) / 2 + m] = ylm_norm(l, m);
-        a.scale = (float)(1.0 / (double)G.ng);
-        a.out = kc;
-        hipError_t e = launch_kgen(a, s);
-        if (e != hipSuccess) return hip_fail(e, "kernel generation");
-        // forward transform along every axis but 0 (axis 0 is redone per field in the first pass)
-        const int64_t cn[3] = {G.np, G.n[1], G.n[2]};
-        const int axes[2] = {1, 2};
-        const sb_status st = fft_axes(p, cn, nd, ncell, axes, nd - 1, -1, LOAD_C, kc, ncell, kc, ncell,
-                                      p->kernel_groups() * p->prob.nbins, s);
-        if (st != SB_OK) return st;
-    }
+    if (!p->regen)
+        for (auto &G : p->groups) {
+            float2 *kc = reinterpret_cast<float2 *>(p->persist + G.khat_off);
+            const sb_status st = gen_kernels(p, G, 0, p->kernel_groups(), kc, s);
+            if (st != SB_OK) return st;
+        }
     p->prepared = true;
     return SB_OK;
 }
@@ -559,7 +590,7 @@ sb_status prepare(sb_plan *p, hipStream_t s) {
 // First inverse pass: axis-0 correlation of every kernel group with the density spectrum.
 // kmap (optional): kernel group of each of the ngr output groups, else groups g0 .. g0 + ngr - 1.
 static sb_status axis0_corr(sb_plan *p, const ShapeGroup &G, const float2 *dhat, float2 *out, int g0, int ngr,
-                            hipStream_t s, const int *kmap = nullptr) {
+                            hipStream_t s, const int *kmap = nullptr, const float2 *kstore = nullptr) {
     const int NB = p->prob.nbins;
     Axis0Args a{};
     a.n = (int)G.n[0];
@@ -569,7 +600,9 @@ static sb_status axis0_corr(sb_plan *p, const ShapeGroup &G, const float2 *dhat,
     a.r0 = G.r0;
     a.mode = 0;
     a.dhat = dhat;
-    a.kc = reinterpret_cast<const float2 *>(p->persist + G.khat_off) + (kmap ? 0 : (int64_t)g0 * NB * G.np * G.plane);
+    // kstore: the planes of exactly these ngr groups (regenerated); else the cached store
+    a.kc = kstore ? kstore
+                  : reinterpret_cast<const float2 *>(p->persist + G.khat_off) + (kmap ? 0 : (int64_t)g0 * NB * G.np * G.plane);
     a.kmap = kmap;
     a.out = out;
     a.nb = NB;
@@ -625,21 +658,51 @@ static sb_status fused_3pcf(sb_plan *p, int f, const void *delta, double *zeta_f
     double *tot = reinterpret_cast<double *>(p->scratch + p->off_tot);
     sb_status st = density_spectrum(p, G, delta, s);
     if (st != SB_OK) return st;
+    // lengths without a fused last pass (1024) run the plain last pass and the pair contraction
+    const bool fused_last = G.rows > 0;
     const int64_t nrows = G.ng / G.n[nd - 1];
-    const int nblocks = (int)((nrows + G.rows_per_block - 1) / G.rows_per_block);
+    const int nblocks = fused_last ? (int)((nrows + G.rows_per_block - 1) / G.rows_per_block)
+                                   : (int)((G.ng + p->cpb_pair - 1) / p->cpb_pair);
     const int nv = NB * (NB + 1) / 2 * (nd == 2 ? 2 : 1);
     hipError_t e = hipSuccess;
     // array groups: (l, m) groups, or with packing the packed m = 0 pairs and then the rest
     const bool packing = p->npack > 0;
     const int nag = packing ? p->nag : p->nlm;
+    float2 *kstore = p->regen ? reinterpret_cast<float2 *>(p->scratch + p->off_kc) : nullptr;
     for (int g0 = 0; g0 < nag; g0 += p->chunk_groups) {
         const int ngr = std::min(p->chunk_groups, nag - g0);
-        st = axis0_corr(p, G, dhat, coef, g0, ngr, s, packing ? p->d_kmap + g0 : nullptr);
+        if (p->regen) {   // this chunk's kernel planes (Alg. 1 / Alg. 2), regenerated into scratch
+            st = gen_kernels(p, G, g0, ngr, kstore, s);
+            if (st != SB_OK) return st;
+        }
+        st = axis0_corr(p, G, dhat, coef, g0, ngr, s, packing ? p->d_kmap + g0 : nullptr, kstore);
         if (st != SB_OK) return st;
         if (nd == 3) {
             const int axes[1] = {1};
             st = fft_axes(p, G.n, nd, G.ng, axes, 1, +1, LOAD_C, coef, G.ng, coef, G.ng, ngr * NB, s);
             if (st != SB_OK) return st;
+        }
+        if (!fused_last) {
+            const int axes[1] = {nd - 1};
+            st = fft_axes(p, G.n, nd, G.ng, axes, 1, +1, LOAD_C, coef, G.ng, coef, G.ng, ngr * NB, s);
+            if (st != SB_OK) return st;
+            PairArgs a{};
+            a.coef = coef;
+            a.gstride = (int64_t)NB * G.ng;
+            a.w = w;
+            a.ng = G.ng;
+            a.nbins = NB;
+            a.ngroups = ngr;
+            a.cells_per_block = p->cpb_pair;
+            a.want_imag = nd == 2;
+            a.partial = part + (int64_t)g0 * nv * nblocks;
+            a.nblocks = nblocks;
+            const double fl = (double)G.ng * ngr * (2.0 + NB * (NB + 1) / 2.0 * (nd == 2 ? 8.0 : 4.0));
+            const double by = (double)G.ng * (8.0 * ngr * NB + 4.0);
+            e = p->timed_launch(STAGE_CONTRACT, K_PAIR, s, [&]() { return launch_pair_contract(a, s); }, 0, 0, ngr,
+                                by, fl);
+            if (e != hipSuccess) return hip_fail(e, "pair contraction");
+            continue;
         }
         // last pass over array groups [gs, gs + cnt) of this chunk (all packed or none)
         auto last = [&](int gs, int cnt, bool packed) -> hipError_t {
@@ -863,9 +926,9 @@ sb_status forward(sb_plan *p, const void *const *delta, double *zeta, hipStream_
         double *zf = zeta + (int64_t)f * p->zeta_doubles;
         const ShapeGroup &G = p->groups[p->field_group[f]];
         sb_status st;
-        if (p->chunk_groups < p->nlm && !(p->prob.npcf == 3 && p->fused && G.rows > 0))
+        if (p->chunk_groups < p->nlm && !(p->prob.npcf == 3 && p->fused))
             return fail(SB_EUNSUPPORTED, "this path needs every kernel array at once; raise the scratch limit");
-        if (p->prob.npcf == 3 && p->fused && G.rows > 0) {
+        if (p->prob.npcf == 3 && p->fused) {
             st = fused_3pcf(p, f, delta[f], zf, s);
         } else {
             st = density_spectrum(p, G, delta[f], s);

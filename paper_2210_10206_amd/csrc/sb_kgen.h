@@ -24,7 +24,9 @@ struct KgenArgs {
     float scale;                 // 1 / N_g
     int npack;                   // 3D: packed m = 0 pairs written after the nlm groups
     int pack_l[2 * kMaxPack];    // (l_a, l_b) of each pair: K_{l_a 0} + i K_{l_b 0}
-    float2 *out;                 // (nlm + npack) * nbins arrays of ng cells, array k = group * nbins + b
+    int gfirst, gcount;          // kernel groups written: gfirst .. gfirst + gcount - 1 of the
+                                 // (nlm + npack) groups, group g to arrays (g - gfirst) * nbins + b
+    float2 *out;                 // gcount * nbins arrays of ng cells
 };
 // Axis-0 planes kept for a kernel support of radius r0 (|c_0| <= r0) on an axis of n cells.
 inline int support_planes(int64_t n, int64_t r0) { return (int)((2 * r0 + 1 >= n) ? n : 2 * r0 + 1); }

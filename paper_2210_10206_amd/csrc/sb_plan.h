@@ -13,6 +13,8 @@
 
 namespace sb {
 
+constexpr double kKernelCacheCap = 64.0 * 1024 * 1024 * 1024;   // bytes of kernel spectra kept at most
+
 enum Stage : int { STAGE_FFT = 0, STAGE_CONTRACT = 1, STAGE_OTHER = 2, STAGE_COUNT = 3 };
 
 struct ShapeGroup {
@@ -88,6 +90,10 @@ struct sb_plan {
     size_t off_flag = 0;          // 256 B: the non-finite counter of SB_FLAG_CHECK_FINITE
     size_t off_zt = 0;            // one field's result: the autotuner's output buffer
     uint32_t warnings = 0;        // SB_WARN_* bits
+    // kernel spectra regenerated per chunk of kernel groups on every call (no cache in the
+    // persistent buffer); their stored planes then sit in scratch at off_kc
+    bool regen = false;
+    size_t off_kc = 0;
     // kernel groups ((l, m) multiplets) whose arrays share the scratch at once: all of them,
     // unless a 3PCF plan's full set would exceed coef_limit (then the passes run in chunks)
     uint64_t coef_limit = 48ull << 30;

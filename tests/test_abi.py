@@ -165,3 +165,32 @@ def test_autotune_and_normalize_reject_an_unbound_plan():
     ptrs = (ctypes.c_void_p * 1)(None)
     assert lib.sb_normalize(h, ptrs, None, None, None) == -1
     lib.sb_plan_destroy(h)
+
+
+def test_1024_grid_plan_regenerates_kernels():
+    """At 1024^3 (10 bins to 32, lmax 6) the compact kernel cache would take about 169 GB, so the
+    fused 3PCF plan keeps none (regenerating each chunk's kernel planes in scratch): its
+    persistent buffer holds only tables and its scratch fits one chunk of (l, m) groups."""
+    import numpy as np
+    from fieldgen import linear_edges
+    from paper_2210_10206_amd import _lib
+    lib = _lib.load()
+    prob, e = _problem(edges=tuple(linear_edges(32, 10)), lmax=6)
+    rc, h = _plan(lib, prob, [(1024, 1024, 1024)])
+    assert rc == 0, lib.sb_last_error()
+    pb, sbytes = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.sb_plan_workspace(h, ctypes.byref(pb), ctypes.byref(sbytes)) == 0
+    assert pb.value < 1 << 20
+    assert sbytes.value < 140 << 30
+    lib.sb_plan_destroy(h)
+    # the same problem at 256^3 keeps its cache
+    rc, h = _plan(lib, prob, [(256, 256, 256)])
+    assert lib.sb_plan_workspace(h, ctypes.byref(pb), ctypes.byref(sbytes)) == 0
+    assert pb.value > 8 << 30
+    lib.sb_plan_destroy(h)
+    # regeneration on request is a fused-3PCF option only
+    for kw in (dict(npcf=4), dict(flags=2)):
+        prob4, _ = _problem(edges=(0.0, 2.0, 4.0), lmax=2, **kw)
+        prob4.flags |= 64
+        rc, h = _plan(lib, prob4, [(16, 16, 16)])
+        assert rc == -2 and not h.value

@@ -143,6 +143,30 @@ def test_full3pcf_512_sparse_field(api):
     check(z, ref, TOL32, say, "l blocks: ")
 
 
+def test_full3pcf_1024_sparse_field(api):
+    """1024^3: the kernel spectra are not cached (they would take about 169 GB): each chunk of
+    (l, m) groups regenerates its kernel planes, and the length-1024 last axis runs the plain
+    last pass and the pair contraction.  16384 unit-weight cells scattered over the box, 10 bins
+    to 32, lmax 6, against the oracle at the occupied cells."""
+    say("case: 16384 particles on 1024^3, 10 bins to 32, lmax 6: full 3PCF vs the oracle at the occupied cells")
+    torch.cuda.empty_cache()
+    d = sparse_unit_field((1024,) * 3, 16384, seed=1024)
+    cells = np.flatnonzero(d.reshape(-1))
+    edges = linear_edges(32, 10)
+    dev = torch.from_numpy(d.astype(np.float32)).cuda()
+    plan = api.Plan([d.shape], edges, 6, npcf=3)
+    say(f"  1024^3 plan: persistent {plan.persistent_bytes / 2**30:.3f} GiB, scratch {plan.scratch_bytes / 2**30:.1f} GiB")
+    z = plan.forward([dev])[0].cpu().numpy()
+    torch.cuda.synchronize()
+    plan.close()
+    del plan, dev
+    torch.cuda.empty_cache()
+    say("  oracle at the occupied cells")
+    ref = oracle.zeta3_full(d, edges, 6, cells=cells).real
+    del d
+    check(z, ref, TOL32, say, "l blocks: ")
+
+
 def test_coefficients_256_sampled(api):
     say("case: 256^3 coefficients at 24 sampled cells vs the oracle, 10 bins to 32, lmax 6")
     d = lognormal_field((256,) * 3, seed=0, sigma=0.5)

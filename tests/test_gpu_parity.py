@@ -227,7 +227,8 @@ def test_packed_m0_arrays(sb, shape, nbins, lmax):
     plan0.close()
 
 
-@pytest.mark.parametrize("shape", [(8, 64, 16), (8, 128, 16), (8, 256, 16), (8, 512, 16), (512, 8, 32)])
+@pytest.mark.parametrize("shape", [(8, 64, 16), (8, 128, 16), (8, 256, 16), (8, 512, 16), (512, 8, 32),
+                                   (8, 1024, 16), (1024, 8, 16)])
 def test_every_fft_variant(sb, shape):
     # every launch shape of the passes of each axis (what the autotuner may pick) gives the
     # oracle's sums; the middle axis (a plain pass in the forward, kernel-cache and density
@@ -587,3 +588,47 @@ def test_split_bf16_projected4pcf(sb, shape, nbins, mmax):
     pairs, ref = oracle.zeta4_proj(d.astype(np.float64), edges, mmax)
     check(z[0], ref, TOL_SPLIT, say, "split-BF16: ")
     check(z32[0], ref, TOL32, say, "float32: ")
+
+
+# ------------------------------------------------------------------ kernel regeneration, 1024 axes
+
+@pytest.mark.parametrize("shape,nbins,lmax,limit_groups", [((32, 32, 32), 4, 4, None), ((16, 24, 32), 6, 3, 2),
+                                                           ((8, 16, 256), 10, 6, 3)])
+def test_regenerated_kernels_match_cached(sb, shape, nbins, lmax, limit_groups):
+    # a plan that keeps no kernel spectra regenerates each chunk's planes with the same kernel
+    # generation and transforms: bit-identical to the cached plan without packed pairs
+    say(f"case: {shape} full 3PCF, {nbins} bins to 6, lmax {lmax}: regenerated kernels "
+        f"(chunks of {limit_groups or 'all'} groups) vs cached")
+    d = lognormal_field(shape, seed=60 + nbins, sigma=1.0)
+    edges = linear_edges(6, nbins)
+    kw = {} if limit_groups is None else dict(scratch_limit=limit_groups * nbins * d.size * 8)
+    plan, dev, z = run_plan(sb, [d], edges, lmax, regen_kernels=True, **kw)
+    plan0, _, z0 = run_plan(sb, [d], edges, lmax, pack=False, **kw)
+    assert plan.persistent_bytes < plan0.persistent_bytes
+    assert np.array_equal(z, z0)
+    check(z[0], oracle.zeta3_full(d.astype(np.float64), edges, lmax).real, TOL32, say)
+    with pytest.raises(Exception):     # no adjoint without the cached spectra
+        plan.backward(dev, torch.zeros((1, lmax + 1, nbins, nbins), dtype=torch.float64, device="cuda"))
+    plan.close()
+    plan0.close()
+
+
+@pytest.mark.parametrize("shape,npcf", [((8, 16, 1024), 3), ((1024, 8, 16), 3), ((8, 1024, 16), 3), ((16, 1024), 3),
+                                        ((1024, 16), 3), ((8, 8, 1024), 4), ((16, 1024), 4)])
+def test_axes_of_1024(sb, shape, npcf):
+    # transforms of length 1024 on every axis: the axis-0 correlation pass, the middle pass, and the
+    # plain last pass followed by the pair contraction (no fused last pass at this length)
+    say(f"case: {shape} npcf {npcf}, 4 bins to 4, lmax 3")
+    d = lognormal_field(shape, seed=44, sigma=1.0)
+    edges = linear_edges(4, 4)
+    plan, dev, z = run_plan(sb, [d], edges, 3, npcf=npcf)
+    d64 = d.astype(np.float64)
+    if len(shape) == 3:
+        ref = oracle.zeta3_full(d64, edges, 3).real if npcf == 3 else oracle.zeta4_full(d64, edges, 3)[1].real
+    else:
+        ref = oracle.zeta3_proj(d64, edges, 3) if npcf == 3 else oracle.zeta4_proj(d64, edges, 3)[1]
+    check(z[0], ref, TOL32, say)
+    if npcf == 3 and len(shape) == 3 and shape[2] == 1024:
+        with pytest.raises(Exception):   # the fused adjoint has no last pass at 1024
+            plan.backward(dev, torch.zeros((1, 4, 4, 4), dtype=torch.float64, device="cuda"))
+    plan.close()
