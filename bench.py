@@ -293,6 +293,7 @@ def run_4pcf_batch(api, steps, warmup, count=16, precision="fp32", mfma=True, pa
     res = {"workload": f"full 4PCF, {count} lognormal 128^3 float32 fields (sigma ~ U[0.5,2]), 8 bins over (0,24], "
                        f"{parity} Lambda with l <= 4 ({'42' if parity == 'even' else '23'})",
            "precision": precision, "matrix_cores": bool(mfma), "contract_tile": plan.contract_tile()[0],
+           "fields_per_launch": plan.field_batch, "pass_launches_per_batch": round(len(recs) / steps, 1),
            "value": round(count * steps / el, 3), "unit": "fields/s", "ms_per_step": round(el / steps * 1e3, 2),
            "graph_replay": {"value": round(count * steps / el_graph, 3), "ms_per_step": round(el_graph / steps * 1e3, 2)},
            "contraction": {"kernel": kname,
@@ -342,6 +343,23 @@ def run_c5(api, steps, warmup, synth_steps=200):
         plan.forward(dev)
         plan.backward(dev, G)
     torch.cuda.synchronize()
+    plan.profile(True)
+    plan.forward_raw(dev)
+    torch.cuda.synchronize()
+    fwd_launches = len(plan.launch_records())
+    plan.profile(False)
+    # the same forward replayed from a HIP graph of the whole batch
+    gs = torch.cuda.Stream()
+    gout = torch.empty((len(dev), plan.zeta_doubles), dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(gs):
+        plan.forward_raw(dev, out=gout, stream=gs, graph=True)
+    gs.synchronize()
+    tg = time.perf_counter()
+    with torch.cuda.stream(gs):
+        for _ in range(steps):
+            plan.forward_raw(dev, out=gout, stream=gs, graph=True)
+    gs.synchronize()
+    graph_fps = len(fields) * steps / (time.perf_counter() - tg)
     t0 = time.perf_counter()
     for _ in range(steps):
         plan.forward_raw(dev)
@@ -373,6 +391,7 @@ def run_c5(api, steps, warmup, synth_steps=200):
         for i, g in gold_g.items():
             got = grads[i].reshape(-1)[torch.from_numpy(g["cells"]).cuda()].double().cpu().numpy()
             grad_err[f"{edges_list[i]}^3 field {i}"] = float(np.max(np.abs(got - g["grad"])) / np.max(np.abs(g["grad"])))
+    plan_fb = plan.field_batch
     plan.close()
     del dev
     n = 128
@@ -389,7 +408,9 @@ def run_c5(api, steps, warmup, synth_steps=200):
     return {"workload": f"uneven batch of {len(fields)} sigma-1 lognormal float32 cubes, edges from "
                         f"64/96/128/160/192 ({ncell / len(fields) / 1e6:.2f} M cells on average), 8 bins over "
                         "(0,16], lmax 4, one plan",
+            "fields_per_launch": plan_fb, "pass_launches_per_forward": fwd_launches,
             "forward_fields_per_s": round(len(fields) * steps / (t1 - t0), 2),
+            "forward_graph_replay_fields_per_s": round(graph_fps, 2),
             "adjoint_fields_per_s": round(len(fields) * steps / (t2 - t1), 2),
             "forward_plus_adjoint_fields_per_s": round(len(fields) * steps / (t2 - t0), 2),
             "forward_err_vs_oracle": fwd_err or None,
@@ -433,6 +454,54 @@ def run_512(api, steps, warmup):
            "persistent_GiB": round(plan.persistent_bytes / 2 ** 30, 2),
            "scratch_GiB": round(plan.scratch_bytes / 2 ** 30, 2)}
     plan.close()
+    return res
+
+
+def run_1024(api, steps, warmup):
+    """Full 3PCF of one 1024^3 field (the 4x4x4 tiling of the sigma 0.5 seed 0 256^3 field), 10
+    bins to 32, lmax 6: no kernel cache (it would take about 169 GB); each chunk of (l, m) groups
+    regenerates its kernel planes, and the 1024 last axis runs the plain pass and the pair
+    contraction.  Fields/s and the per-stage times."""
+    import torch
+    from fieldgen import lognormal_field, linear_edges
+    d = torch.from_numpy(lognormal_field((256,) * 3, seed=0, sigma=0.5)).cuda().repeat(4, 4, 4).contiguous()
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = api.Plan([tuple(d.shape)], linear_edges(32, 10), 6, npcf=3, prepare=False)
+    with torch.cuda.stream(stream):
+        plan.prepare(stream)
+    stream.synchronize()
+    cold = time.perf_counter() - t0
+    out = torch.empty((1, plan.zeta_doubles), dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            plan.forward_raw([d], out=out, stream=stream)
+    stream.synchronize()
+    plan.profile(True)
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(steps):
+            plan.forward_raw([d], out=out, stream=stream)
+    stream.synchronize()
+    el = time.perf_counter() - t0
+    recs = plan.launch_records()
+    plan.profile(False)
+    kinds = {0: "fft_passes", 1: "axis0_correlation", 3: "pair_contraction"}
+    per = {}
+    for r in recs:
+        k = kinds.get(r["kernel"], "other")
+        per[k] = per.get(k, 0.0) + r["ms"] / steps
+    res = {"workload": "full 3PCF of one 1024^3 float32 field (4x4x4 tiling of the 256^3 sigma 0.5 field), "
+                       "10 bins over (0,32], lmax 6, kernel spectra regenerated per chunk of (l, m) groups",
+           "value": round(steps / el, 4), "unit": "fields/s", "ms_per_field": round(el / steps * 1e3, 1),
+           "setup_ms": round(cold * 1e3, 1),
+           "persistent_GiB": round(plan.persistent_bytes / 2 ** 30, 4),
+           "scratch_GiB": round(plan.scratch_bytes / 2 ** 30, 2),
+           "stage_ms_per_field": {k: round(v, 1) for k, v in per.items()}}
+    plan.close()
+    del d, out
+    torch.cuda.empty_cache()
     return res
 
 
@@ -509,7 +578,8 @@ def run_256_leg(api, fields, dev, edges, lmax, steps, warmup, precision, fused=T
     n = fields[0].shape[0]
     nbins = len(edges) - 1
     stream = torch.cuda.Stream()
-    plan = api.Plan([f.shape for f in fields], edges, lmax, npcf=3, prepare=False, fused=fused, precision=precision)
+    plan = api.Plan([f.shape for f in fields], edges, lmax, npcf=3, prepare=False, fused=fused, precision=precision,
+                    field_batch=None if fused else 1)
     with torch.cuda.stream(stream):
         plan.prepare(stream)
     if autotune:
@@ -561,10 +631,11 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay the forward from a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unfused", action="store_true", help="plain path: write the coefficients, then contract")
-    ap.add_argument("--lines", default="main,split,plain,c4,c4var,big,proj,c5,cpu",
+    ap.add_argument("--lines", default="main,split,plain,c4,c4var,big,huge,proj,c5,cpu",
                     help="comma list of the lines to run: main (the metric line), split (its split-BF16 leg), plain "
                          "(the unfused float32 path), c4 (128^3 4PCF batch), c4var (its other contraction paths), "
-                         "big (512^3), proj (512^2 projected), c5 (uneven batch + adjoint + synthesis), cpu (oracle)")
+                         "big (512^3), huge (1024^3), proj (512^2 projected), c5 (uneven batch + adjoint + "
+                         "synthesis), cpu (oracle)")
     ap.add_argument("--c4-steps", type=int, default=1, help="steps of the 128^3 4PCF batch (0 skips it)")
     ap.add_argument("--c5-steps", type=int, default=1,
                     help="steps of the uneven-batch forward + adjoint and the synthesis demo (0 skips them)")
@@ -767,6 +838,10 @@ def main():
         print("bench: 512^3 3PCF", file=sys.stderr, flush=True)
         big = run_512(api, args.big_steps, 1)
         torch.cuda.empty_cache()
+    huge = None
+    if "huge" in lines and args.big_steps > 0:
+        print("bench: 1024^3 3PCF", file=sys.stderr, flush=True)
+        huge = run_1024(api, args.big_steps, 1)
     proj = None
     if "proj" in lines and args.proj_steps > 0:
         print("bench: 512^2 projected 3PCF and 4PCF", file=sys.stderr, flush=True)
@@ -801,6 +876,7 @@ def main():
         "secondary_4pcf_128": c4,
         "secondary_uneven_adjoint": c5,
         "secondary_3pcf_512": big,
+        "secondary_3pcf_1024": huge,
         "secondary_projected_512": proj,
     }
     print(json.dumps(line), flush=True)

@@ -170,6 +170,17 @@ sb_status sb_plan_workspace(const sb_plan *plan, size_t *persistent_bytes, size_
  * from sb_forward when chunked.  Errors: SB_EINVAL (null plan, bytes = 0), SB_ESTATE. */
 sb_status sb_plan_set_scratch_limit(sb_plan *plan, uint64_t bytes);
 
+/* Fields of one shape run through the passes together, one launch per pass for the whole
+ * batch (the field is the launch's third grid dimension), in batches of up to `max_fields`:
+ * 0 (the default) takes as many as 32 GiB of kernel arrays allow, 1 runs every field through
+ * its own launch sequence in field order.  Plans whose passes run in chunks of kernel groups,
+ * and SB_FLAG_KEEP_COEFFS plans, use 1.  Results do not depend on the batch (each field's sums
+ * are computed by the same launches in the same order).  Call before sb_plan_bind (SB_ESTATE
+ * afterwards); sb_plan_workspace then reports the scratch for the batch.  get: the batch the
+ * plan uses.  Errors: SB_EINVAL (null plan, max_fields < 0), SB_ESTATE. */
+sb_status sb_plan_set_field_batch(sb_plan *plan, int32_t max_fields);
+sb_status sb_plan_get_field_batch(const sb_plan *plan, int32_t *fields);
+
 /* Bind caller-owned device buffers (at least the sizes of sb_plan_workspace, 256-byte
  * aligned, on the device current at sb_plan_create).  The library keeps the pointers until
  * the next bind or sb_plan_destroy and never frees them.  A bind invalidates sb_prepare and

@@ -38,6 +38,8 @@ SIGNATURES = {
     "sb_plan_destroy": (None, [c_vp]),
     "sb_plan_workspace": (c_i32, [c_vp, P(c_sz), P(c_sz)]),
     "sb_plan_set_scratch_limit": (c_i32, [c_vp, ctypes.c_uint64]),
+    "sb_plan_set_field_batch": (c_i32, [c_vp, c_i32]),
+    "sb_plan_get_field_batch": (c_i32, [c_vp, P(c_i32)]),
     "sb_fft_variants": (c_i32, [c_i32]),
     "sb_plan_set_fft_variant": (c_i32, [c_vp, c_i32, c_i32, c_i32]),
     "sb_plan_get_fft_variant": (c_i32, [c_vp, c_i32, c_i32, P(c_i32)]),

@@ -52,11 +52,14 @@ class Plan:
     check_finite: scan the inputs of every call for NaN / Inf first (SB_FLAG_CHECK_FINITE)
     regen_kernels: fused 3PCF: keep no kernel spectra, regenerate them per call in scratch
                  (SB_FLAG_REGEN_KERNELS; automatic when the cache would exceed 64 GiB)
+    field_batch: fields of one shape per launch of each pass (sb_plan_set_field_batch): None or 0 =
+                 as many as 32 GiB of kernel arrays allow, 1 = one launch sequence per field
     """
 
     def __init__(self, shapes, bin_edges, lmax, npcf=3, precision="fp32", input_dtype=torch.float32,
                  device=None, stream=None, prepare=True, keep_coeffs=False, fused=True, mfma=True,
-                 scratch_limit=None, parity="even", pack=True, check_finite=False, regen_kernels=False):
+                 scratch_limit=None, parity="even", pack=True, check_finite=False, regen_kernels=False,
+                 field_batch=None):
         self.lib = _lib.load()
         shapes = [tuple(int(x) for x in s) for s in shapes]
         ndim = len(shapes[0])
@@ -92,6 +95,11 @@ class Plan:
         if scratch_limit is not None:
             check(self.lib.sb_plan_set_scratch_limit(self.handle, ctypes.c_uint64(int(scratch_limit))),
                   "sb_plan_set_scratch_limit")
+        if field_batch is not None:
+            check(self.lib.sb_plan_set_field_batch(self.handle, int(field_batch)), "sb_plan_set_field_batch")
+        fb = ctypes.c_int32()
+        check(self.lib.sb_plan_get_field_batch(self.handle, ctypes.byref(fb)), "sb_plan_get_field_batch")
+        self.field_batch = fb.value
         pb, sbytes = ctypes.c_size_t(), ctypes.c_size_t()
         check(self.lib.sb_plan_workspace(self.handle, ctypes.byref(pb), ctypes.byref(sbytes)), "sb_plan_workspace")
         self.persistent_bytes, self.scratch_bytes = pb.value, sbytes.value

@@ -43,6 +43,9 @@ __device__ __forceinline__ void block_combine(const float *acc, double *red /* L
 // ----------------------------------------------------------------- pair contraction
 template <int NB, bool IMAG>
 __global__ __launch_bounds__(256) void pair_kernel(PairArgs a) {
+    a.coef += (int64_t)blockIdx.z * a.coef_fs;   // field of the launch (grid.z)
+    a.w += (int64_t)blockIdx.z * a.w_fs;
+    a.partial += (int64_t)blockIdx.z * a.part_fs;
     constexpr int NP = NB * (NB + 1) / 2;
     constexpr int NV = NP * (IMAG ? 2 : 1);
     __shared__ double red[4 * NV];
@@ -74,7 +77,7 @@ __global__ __launch_bounds__(256) void pair_kernel(PairArgs a) {
 
 template <int NB>
 hipError_t launch_pair_nb(const PairArgs &a, hipStream_t s) {
-    dim3 grid(a.nblocks, a.ngroups);
+    dim3 grid(a.nblocks, a.ngroups, (unsigned)(a.fields > 1 ? a.fields : 1));
     if (a.want_imag) hipLaunchKernelGGL((pair_kernel<NB, true>), grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL((pair_kernel<NB, false>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
@@ -87,6 +90,9 @@ hipError_t launch_pair_nb(const PairArgs &a, hipStream_t s) {
 // (Im for odd Lambda: the m3 < 0 half is minus the conjugate of the m3 > 0 half there).
 template <int NB, bool ODD>
 __global__ __launch_bounds__(256) void quad_kernel(QuadArgs a) {
+    a.coef += (int64_t)blockIdx.z * a.coef_fs;   // field of the launch (grid.z)
+    a.w += (int64_t)blockIdx.z * a.w_fs;
+    a.partial += (int64_t)blockIdx.z * a.part_fs;
     constexpr int NPAIR = NB * NB;
     constexpr int SLOTS = (NPAIR + 63) / 64;
     constexpr int NV = NB * NB * NB;
@@ -180,6 +186,9 @@ __global__ __launch_bounds__(256) void quad_kernel(QuadArgs a) {
 // ----------------------------------------------------------------- projected 4PCF
 template <int NB>
 __global__ __launch_bounds__(256) void proj4_kernel(Proj4Args a) {
+    a.coef += (int64_t)blockIdx.z * a.coef_fs;   // field of the launch (grid.z)
+    a.w += (int64_t)blockIdx.z * a.w_fs;
+    a.partial += (int64_t)blockIdx.z * a.part_fs;
     constexpr int NPAIR = NB * NB;
     constexpr int SLOTS = (NPAIR + 63) / 64;
     constexpr int NV = NB * NB * NB * 2;
@@ -358,7 +367,7 @@ static hipError_t launch_quad_nb(const QuadArgs &a, hipStream_t s) {
     const size_t tile_bytes = (size_t)a.tile * a.max_cols * NB * sizeof(float2);
     const size_t red_bytes = (size_t)4 * NV * sizeof(double);
     const size_t shm = tile_bytes > red_bytes ? tile_bytes : red_bytes;
-    dim3 grid(a.nblocks, a.nlam);
+    dim3 grid(a.nblocks, a.nlam, (unsigned)(a.fields > 1 ? a.fields : 1));
     if (a.odd)
         hipLaunchKernelGGL((quad_kernel<NB, true>), grid, dim3(256), shm, s, a);
     else
@@ -382,7 +391,7 @@ static hipError_t launch_proj4_nb(const Proj4Args &a, hipStream_t s) {
     size_t tile_bytes = (size_t)a.tile * 3 * NB * sizeof(float2);
     size_t red_bytes = (size_t)4 * NV * sizeof(double);
     size_t shm = tile_bytes > red_bytes ? tile_bytes : red_bytes;
-    dim3 grid(a.nblocks, a.npairs);
+    dim3 grid(a.nblocks, a.npairs, (unsigned)(a.fields > 1 ? a.fields : 1));
     hipLaunchKernelGGL((proj4_kernel<NB>), grid, dim3(256), shm, s, a);
     return hipGetLastError();
 }

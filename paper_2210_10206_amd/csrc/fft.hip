@@ -103,6 +103,8 @@ __device__ __forceinline__ int64_t acc_kernel(const Axis0Args &a, int t) {
 
 template <int N, int TPP, int NT, int... RAD>
 __global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
+    a.dhat += (int64_t)blockIdx.z * a.dhat_fs;   // field of the launch (grid.z)
+    a.out += (int64_t)blockIdx.z * a.out_fs;
     constexpr int P = NT / TPP;
     constexpr int PITCH = P + 1;
     constexpr int EPT = N / TPP;      // tile elements per thread: pencil p, rows q0 + e TPP
@@ -230,6 +232,8 @@ inline int support_rows(const Axis0Args &a, int r1, int r2) {
 // them away.
 template <int R1, int R2, int P, int MODE, int KR>
 __global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void axis0_reg_kernel(Axis0Args a) {
+    a.dhat += (int64_t)blockIdx.z * a.dhat_fs;   // field of the launch (grid.z)
+    a.out += (int64_t)blockIdx.z * a.out_fs;
     constexpr int N = R1 * R2;
     constexpr int T = R1 / R2;   // second-stage butterflies per thread
     static_assert(R1 % R2 == 0, "R2 must divide R1");
@@ -346,6 +350,8 @@ __global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void
 // compact kernel support can reach (KR >= R0 / 2: all rows).
 template <int N, int P, int MODE, int KR, int R0, int... REST>
 __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
+    a.dhat += (int64_t)blockIdx.z * a.dhat_fs;   // field of the launch (grid.z)
+    a.out += (int64_t)blockIdx.z * a.out_fs;
     constexpr int T = N / R0;
     constexpr int PITCH = P + 1;
     __shared__ float2 ex[2][N * PITCH];
@@ -435,7 +441,7 @@ __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
 template <int N, int TPP, int NT, int... RAD>
 hipError_t launch_axis0_t(const Axis0Args &a, hipStream_t s) {
     constexpr int P = NT / TPP;
-    dim3 grid((unsigned)((a.plane + P - 1) / P), (unsigned)a.groups);
+    dim3 grid((unsigned)((a.plane + P - 1) / P), (unsigned)a.groups, (unsigned)(a.fields > 1 ? a.fields : 1));
     hipLaunchKernelGGL((axis0_kernel<N, TPP, NT, RAD...>), grid, dim3(NT), 0, s, a);
     return hipGetLastError();
 }
@@ -710,7 +716,7 @@ hipError_t launch_axis0(const Axis0Args &a, hipStream_t s) {
         // register-resident stages: 512 = 16 x 8 x 4, 192 = 12 x 4 x 4, 160 = 20 x 4 x 2, 96 = 12 x 4 x 2
         // (the adjoint accumulation at 512 keeps the LDS-staged kernel: its registers would spill)
         constexpr int P = 16;
-        dim3 grid((unsigned)((a.plane + P - 1) / P), (unsigned)a.groups);
+        dim3 grid((unsigned)((a.plane + P - 1) / P), (unsigned)a.groups, (unsigned)(a.fields > 1 ? a.fields : 1));
         auto go = [&](auto mode_c) {
             constexpr int M = decltype(mode_c)::value;
             if constexpr (M == 0) {
@@ -732,7 +738,7 @@ hipError_t launch_axis0(const Axis0Args &a, hipStream_t s) {
     }
     if (a.n == 256 || a.n == 128 || a.n == 64) {
         constexpr int P = 16;
-        dim3 grid((unsigned)((a.plane + P - 1) / P), (unsigned)a.groups);
+        dim3 grid((unsigned)((a.plane + P - 1) / P), (unsigned)a.groups, (unsigned)(a.fields > 1 ? a.fields : 1));
         auto go = [&](auto mode_c) {
             constexpr int M = decltype(mode_c)::value;
             if (a.n == 256) {

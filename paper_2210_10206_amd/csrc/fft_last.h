@@ -249,6 +249,9 @@ __device__ __forceinline__ int64_t partial_row(const LastArgs &a, int y, int nv,
 
 template <int N, int TPP, int NBT, int R, int MODE, int PREC, int... RAD>
 __global__ __launch_bounds__(NBT * R * TPP) void last_contract_kernel(LastArgs a) {
+    a.in += (int64_t)blockIdx.z * a.in_fs;   // field of the launch (grid.z)
+    a.w += (int64_t)blockIdx.z * a.w_fs;
+    a.partial += (int64_t)blockIdx.z * a.part_fs;
     using PS = PairSums<NBT, MODE, PREC>;
     constexpr int P = NBT * R, PITCH = P + 1, NT = P * TPP;
     constexpr int NW = NT / 64;       // waves
@@ -347,6 +350,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 // every FLUSH (8) rows.
 template <int R1, int R2, int NBT, int MODE, int PREC>
 __global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
+    a.in += (int64_t)blockIdx.z * a.in_fs;   // field of the launch (grid.z)
+    a.w += (int64_t)blockIdx.z * a.w_fs;
+    a.partial += (int64_t)blockIdx.z * a.part_fs;
     using PS = PairSums<NBT, MODE, PREC>;
     constexpr int N = R1 * R2;
     constexpr int T = R1 / R2;             // second-stage butterflies per thread
@@ -476,7 +482,7 @@ inline int pair_mode(const LastArgs &a) { return a.want_imag ? PS_COMPLEX : (a.p
 
 template <int R1, int R2, int PREC>
 hipError_t launch_last_reg_p(const LastArgs &a, hipStream_t s) {
-    dim3 grid((unsigned)a.nblocks, (unsigned)a.groups);
+    dim3 grid((unsigned)a.nblocks, (unsigned)a.groups, (unsigned)(a.fields > 1 ? a.fields : 1));
     const int mode = pair_mode(a);
     const int nbt = reg_padded_bins(a.nb, R2);
 #define SB_LR(NBT)                                                                                                  \
@@ -513,6 +519,9 @@ hipError_t launch_last_reg(const LastArgs &a, hipStream_t s) {
 // which is then the [cell][bin] tile of the MFMA pair sums.
 template <int N, int NBT, int MODE, int PREC, int R0, int... REST>
 __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
+    a.in += (int64_t)blockIdx.z * a.in_fs;   // field of the launch (grid.z)
+    a.w += (int64_t)blockIdx.z * a.w_fs;
+    a.partial += (int64_t)blockIdx.z * a.part_fs;
     using PS = PairSums<NBT, MODE, PREC>;
     constexpr int T = N / R0;
     constexpr int P = NBT;
@@ -584,7 +593,7 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
 template <int N, int PREC, int R0, int... REST>
 hipError_t launch_last_rs_p(const LastArgs &a, hipStream_t s) {
     constexpr int T = N / R0;
-    dim3 grid((unsigned)a.nblocks, (unsigned)a.groups);
+    dim3 grid((unsigned)a.nblocks, (unsigned)a.groups, (unsigned)(a.fields > 1 ? a.fields : 1));
     const int mode = pair_mode(a);
     const int nbt = reg_padded_bins(a.nb, T);
 #define SB_LR(NBT)                                                                                                   \
@@ -624,7 +633,7 @@ hipError_t launch_last_t(const LastArgs &a, hipStream_t s) {
     const size_t tile = (size_t)(N * (P + 1) + N) * sizeof(float2) + (size_t)R * N * sizeof(float);
     const size_t red = (size_t)PairSums<NBT, MODE>::red_doubles(NT / 64) * sizeof(double);
     const size_t shm = tile > red ? tile : red;
-    dim3 grid((unsigned)a.nblocks, (unsigned)a.groups);
+    dim3 grid((unsigned)a.nblocks, (unsigned)a.groups, (unsigned)(a.fields > 1 ? a.fields : 1));
     if (a.prec)
         hipLaunchKernelGGL((last_contract_kernel<N, TPP, NBT, R, MODE, 1, RAD...>), grid, dim3(NT), shm, s, a);
     else

@@ -123,14 +123,24 @@ void layout_scratch(sb_plan *p) {
     const bool chunkable = prob->npcf == 3 && (prob->flags & SB_FLAG_KEEP_COEFFS) == 0;
     if (chunkable && per_group * p->nlm > p->coef_limit)
         p->chunk_groups = (int)std::max<uint64_t>(1, std::min<uint64_t>(p->nlm, p->coef_limit / per_group));
+    // fields per batch (the region of each per-field buffer below is fbatch fields long)
+    int maxf = 1;
+    for (const auto &G : p->groups) maxf = std::max<int>(maxf, (int)G.fields.size());
+    p->fbatch = 1;
+    if (p->chunk_groups == p->nlm && !p->regen && (prob->flags & SB_FLAG_KEEP_COEFFS) == 0) {
+        const double per_field = (double)per_group * p->nlm;
+        p->fbatch = p->fbatch_req > 0 ? std::min(maxf, p->fbatch_req)
+                                      : std::max(1, std::min(maxf, (int)(kBatchBytes / per_field)));
+    }
+    const size_t FB = (size_t)p->fbatch;
     size_t sc = 0;
-    p->off_w = sc; sc += align256((size_t)p->max_ng * sizeof(float));
-    p->off_dhat = sc; sc += align256((size_t)p->max_ng * sizeof(float2));
+    p->off_w = sc; sc += align256(FB * p->max_ng * sizeof(float));
+    p->off_dhat = sc; sc += align256(FB * p->max_ng * sizeof(float2));
     const bool adjoint = prob->ndim == 3 && prob->npcf == 3 && !p->regen;
     // the adjoint's v arrays directly before the coefficient arrays: its fused pass writes the v
     // of each group into the slot before that group's coefficients
     if (adjoint) { p->off_vtmp = sc; sc += align256((size_t)NB * p->max_ng * sizeof(float2)); }
-    p->off_coef = sc; sc += align256((size_t)p->chunk_groups * NB * p->max_ng * sizeof(float2));
+    p->off_coef = sc; sc += align256(FB * p->chunk_groups * NB * p->max_ng * sizeof(float2));
     if (p->regen) {   // the stored axis-0 planes of one chunk's kernels
         int64_t kc = 0;
         for (const auto &G : p->groups) kc = std::max<int64_t>(kc, (int64_t)G.np * G.plane);
@@ -145,8 +155,8 @@ void layout_scratch(sb_plan *p) {
             nblocks = std::max<int>(nblocks, (int)((nrows + G.rows_per_block - 1) / G.rows_per_block));
         }
     p->off_part = sc;
-    sc += align256(std::max<size_t>((size_t)groups * nvals * nblocks, kNormParts) * sizeof(double));
-    p->off_tot = sc; sc += align256((size_t)groups * nvals * sizeof(double));
+    sc += align256(std::max<size_t>(FB * groups * nvals * nblocks, kNormParts) * sizeof(double));
+    p->off_tot = sc; sc += align256(FB * groups * nvals * sizeof(double));
     p->off_grad = sc; sc += align256((size_t)p->max_ng * sizeof(float2));
     p->off_flag = sc; sc += 256;
     p->off_zt = sc; sc += align256((size_t)p->zeta_doubles * sizeof(double));
@@ -590,7 +600,7 @@ sb_status prepare(sb_plan *p, hipStream_t s) {
 // First inverse pass: axis-0 correlation of every kernel group with the density spectrum.
 // kmap (optional): kernel group of each of the ngr output groups, else groups g0 .. g0 + ngr - 1.
 static sb_status axis0_corr(sb_plan *p, const ShapeGroup &G, const float2 *dhat, float2 *out, int g0, int ngr,
-                            hipStream_t s, const int *kmap = nullptr, const float2 *kstore = nullptr) {
+                            hipStream_t s, const int *kmap = nullptr, const float2 *kstore = nullptr, int nf = 1) {
     const int NB = p->prob.nbins;
     Axis0Args a{};
     a.n = (int)G.n[0];
@@ -608,30 +618,42 @@ static sb_status axis0_corr(sb_plan *p, const ShapeGroup &G, const float2 *dhat,
     a.nb = NB;
     a.groups = ngr;
     a.tw = p->tw.at(a.n);
+    // nf fields of this shape in one launch: field i's spectrum at dhat + i ng, its arrays after
+    // the previous field's ngr * NB arrays
+    a.fields = nf;
+    a.dhat_fs = G.ng;
+    a.out_fs = (int64_t)ngr * NB * G.ng;
     // traffic: stored kernel planes read, outputs written, density spectrum read once per group
-    const int nk = ngr * NB;
-    const double bytes = (double)nk * (8.0 * G.np * G.plane + 8.0 * G.ng) + (double)ngr * 8.0 * G.ng;
+    const int nk = ngr * NB * nf;
+    const double bytes = (double)nk * (8.0 * G.np * G.plane + 8.0 * G.ng) + (double)ngr * nf * 8.0 * G.ng;
     const hipError_t e = p->timed_launch(STAGE_FFT, K_AXIS0, s, [&]() { return launch_axis0(a, s); }, a.n, 1, nk, bytes);
     if (e != hipSuccess) return hip_fail(e, "axis-0 correlation pass");
     return SB_OK;
 }
 
-// Density ingest and spectrum (the first step of Alg. 3 / Alg. 4).
-sb_status density_spectrum(sb_plan *p, const ShapeGroup &G, const void *delta, hipStream_t s) {
+// Density ingest and spectrum (the first step of Alg. 3 / Alg. 4) of nf fields of shape G:
+// field i's density at w + i ng, its spectrum at dhat + i ng.
+sb_status density_spectrum(sb_plan *p, const ShapeGroup &G, const void *const *deltas, int nf, hipStream_t s) {
     float *w = reinterpret_cast<float *>(p->scratch + p->off_w);
     float2 *dhat = reinterpret_cast<float2 *>(p->scratch + p->off_dhat);
-    hipError_t e = launch_to_f32(delta, p->prob.input_dtype, G.ng, w, s);
-    if (e != hipSuccess) return hip_fail(e, "density ingest");
-    return fft_all_axes(p, G, -1, LOAD_R32, w, 0, dhat, 0, 1, s);
+    for (int i = 0; i < nf; ++i) {
+        const hipError_t e = launch_to_f32(deltas[i], p->prob.input_dtype, G.ng, w + (int64_t)i * G.ng, s);
+        if (e != hipSuccess) return hip_fail(e, "density ingest");
+    }
+    return fft_all_axes(p, G, -1, LOAD_R32, w, G.ng, dhat, G.ng, nf, s);
+}
+
+sb_status density_spectrum(sb_plan *p, const ShapeGroup &G, const void *delta, hipStream_t s) {
+    return density_spectrum(p, G, &delta, 1, s);
 }
 
 // Coefficients of kernel groups [g0, g0 + ngr) of one field into scratch (Alg. 3 / Alg. 4
 // as a correlation); the density spectrum is already in scratch.
-sb_status coefficients(sb_plan *p, int f, int g0, int ngr, hipStream_t s, bool last_axis, const int *kmap) {
+sb_status coefficients(sb_plan *p, int f, int g0, int ngr, hipStream_t s, bool last_axis, const int *kmap, int nf) {
     const ShapeGroup &G = p->groups[p->field_group[f]];
     float2 *dhat = reinterpret_cast<float2 *>(p->scratch + p->off_dhat);
     float2 *coef = reinterpret_cast<float2 *>(p->scratch + p->off_coef);
-    sb_status st = axis0_corr(p, G, dhat, coef, g0, ngr, s, kmap);
+    sb_status st = axis0_corr(p, G, dhat, coef, g0, ngr, s, kmap, nullptr, nf);
     if (st != SB_OK) return st;
     const int axes[2] = {1, 2};
     const int naxes = p->prob.ndim - 1 - (last_axis ? 0 : 1);
@@ -640,7 +662,7 @@ sb_status coefficients(sb_plan *p, int f, int g0, int ngr, hipStream_t s, bool l
         return SB_OK;
     }
     st = fft_axes(p, G.n, p->prob.ndim, G.ng, axes, naxes, +1, LOAD_C, coef, G.ng, coef, G.ng,
-                  ngr * p->prob.nbins, s);
+                  nf * ngr * p->prob.nbins, s);
     if (st != SB_OK) return st;
     p->last_ng = G.ng;
     return SB_OK;
@@ -648,15 +670,18 @@ sb_status coefficients(sb_plan *p, int f, int g0, int ngr, hipStream_t s, bool l
 
 // 3PCF of one field with the contraction fused into the last inverse pass (the
 // coefficient arrays are never written).
-static sb_status fused_3pcf(sb_plan *p, int f, const void *delta, double *zeta_f, hipStream_t s) {
-    const ShapeGroup &G = p->groups[p->field_group[f]];
+// nf fields of shape G in one launch per pass (nf > 1 only when every array group fits the scratch
+// at once); field i's result goes to zout[i].
+static sb_status fused_3pcf(sb_plan *p, const ShapeGroup &G, const void *const *deltas, double *const *zout, int nf,
+                            hipStream_t s) {
     const int nd = p->prob.ndim, NB = p->prob.nbins;
     float2 *dhat = reinterpret_cast<float2 *>(p->scratch + p->off_dhat);
     float2 *coef = reinterpret_cast<float2 *>(p->scratch + p->off_coef);
     const float *w = reinterpret_cast<const float *>(p->scratch + p->off_w);
     double *part = reinterpret_cast<double *>(p->scratch + p->off_part);
     double *tot = reinterpret_cast<double *>(p->scratch + p->off_tot);
-    sb_status st = density_spectrum(p, G, delta, s);
+    if (nf > 1 && p->chunk_groups < p->nlm) return fail(SB_EUNSUPPORTED, "fields batched with chunked kernel groups");
+    sb_status st = density_spectrum(p, G, deltas, nf, s);
     if (st != SB_OK) return st;
     // lengths without a fused last pass (1024) run the plain last pass and the pair contraction
     const bool fused_last = G.rows > 0;
@@ -664,6 +689,7 @@ static sb_status fused_3pcf(sb_plan *p, int f, const void *delta, double *zeta_f
     const int nblocks = fused_last ? (int)((nrows + G.rows_per_block - 1) / G.rows_per_block)
                                    : (int)((G.ng + p->cpb_pair - 1) / p->cpb_pair);
     const int nv = NB * (NB + 1) / 2 * (nd == 2 ? 2 : 1);
+    const int64_t part_fs = (int64_t)p->nlm * nv * nblocks;   // one field's block partials
     hipError_t e = hipSuccess;
     // array groups: (l, m) groups, or with packing the packed m = 0 pairs and then the rest
     const bool packing = p->npack > 0;
@@ -675,16 +701,16 @@ static sb_status fused_3pcf(sb_plan *p, int f, const void *delta, double *zeta_f
             st = gen_kernels(p, G, g0, ngr, kstore, s);
             if (st != SB_OK) return st;
         }
-        st = axis0_corr(p, G, dhat, coef, g0, ngr, s, packing ? p->d_kmap + g0 : nullptr, kstore);
+        st = axis0_corr(p, G, dhat, coef, g0, ngr, s, packing ? p->d_kmap + g0 : nullptr, kstore, nf);
         if (st != SB_OK) return st;
         if (nd == 3) {
             const int axes[1] = {1};
-            st = fft_axes(p, G.n, nd, G.ng, axes, 1, +1, LOAD_C, coef, G.ng, coef, G.ng, ngr * NB, s);
+            st = fft_axes(p, G.n, nd, G.ng, axes, 1, +1, LOAD_C, coef, G.ng, coef, G.ng, nf * ngr * NB, s);
             if (st != SB_OK) return st;
         }
         if (!fused_last) {
             const int axes[1] = {nd - 1};
-            st = fft_axes(p, G.n, nd, G.ng, axes, 1, +1, LOAD_C, coef, G.ng, coef, G.ng, ngr * NB, s);
+            st = fft_axes(p, G.n, nd, G.ng, axes, 1, +1, LOAD_C, coef, G.ng, coef, G.ng, nf * ngr * NB, s);
             if (st != SB_OK) return st;
             PairArgs a{};
             a.coef = coef;
@@ -697,8 +723,12 @@ static sb_status fused_3pcf(sb_plan *p, int f, const void *delta, double *zeta_f
             a.want_imag = nd == 2;
             a.partial = part + (int64_t)g0 * nv * nblocks;
             a.nblocks = nblocks;
-            const double fl = (double)G.ng * ngr * (2.0 + NB * (NB + 1) / 2.0 * (nd == 2 ? 8.0 : 4.0));
-            const double by = (double)G.ng * (8.0 * ngr * NB + 4.0);
+            a.fields = nf;
+            a.coef_fs = (int64_t)ngr * NB * G.ng;
+            a.w_fs = G.ng;
+            a.part_fs = part_fs;
+            const double fl = (double)nf * G.ng * ngr * (2.0 + NB * (NB + 1) / 2.0 * (nd == 2 ? 8.0 : 4.0));
+            const double by = (double)nf * G.ng * (8.0 * ngr * NB + 4.0);
             e = p->timed_launch(STAGE_CONTRACT, K_PAIR, s, [&]() { return launch_pair_contract(a, s); }, 0, 0, ngr,
                                 by, fl);
             if (e != hipSuccess) return hip_fail(e, "pair contraction");
@@ -723,10 +753,14 @@ static sb_status fused_3pcf(sb_plan *p, int f, const void *delta, double *zeta_f
             a.rowmap = packing ? p->d_rowmap + 2 * gs : nullptr;
             a.partial = packing ? part : part + (int64_t)gs * nv * nblocks;
             a.tw = p->tw.at(a.n);
-            const double bytes = (double)cnt * NB * 8.0 * G.ng + (double)cnt * 4.0 * G.ng;
-            const double flops = (double)G.ng * cnt * (2.0 * NB + NB * (NB + 1) / 2.0 * (nd == 2 ? 8.0 : 4.0));
+            a.fields = nf;
+            a.in_fs = (int64_t)ngr * NB * G.ng;
+            a.w_fs = G.ng;
+            a.part_fs = part_fs;
+            const double bytes = nf * ((double)cnt * NB * 8.0 * G.ng + (double)cnt * 4.0 * G.ng);
+            const double flops = (double)nf * G.ng * cnt * (2.0 * NB + NB * (NB + 1) / 2.0 * (nd == 2 ? 8.0 : 4.0));
             return p->timed_launch(STAGE_CONTRACT, K_LAST, s, [&]() { return launch_last_contract(a, s); }, a.n, 1,
-                                   cnt * NB, bytes, flops);
+                                   nf * cnt * NB, bytes, flops);
         };
         if (packing) {
             const int pe = std::min(g0 + ngr, p->npack);
@@ -738,15 +772,17 @@ static sb_status fused_3pcf(sb_plan *p, int f, const void *delta, double *zeta_f
         }
         if (e != hipSuccess) return hip_fail(e, "fused last pass");
     }
-    e = launch_block_sum(part, p->nlm, nblocks, nv, tot, s);
+    e = launch_block_sum(part, nf * p->nlm, nblocks, nv, tot, s);
     if (e != hipSuccess) return hip_fail(e, "block sum");
-    e = launch_gather(tot, p->d_gptr, p->d_gidx, p->d_gcoef, p->gather_nout, zeta_f, s);
+    for (int i = 0; i < nf && e == hipSuccess; ++i)
+        e = launch_gather(tot + (int64_t)i * p->nlm * nv, p->d_gptr, p->d_gidx, p->d_gcoef, p->gather_nout, zout[i], s);
     if (e != hipSuccess) return hip_fail(e, "gather");
     return SB_OK;
 }
 
-sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
-    const ShapeGroup &G = p->groups[p->field_group[f]];
+// Cell-parallel contraction of nf fields of shape G whose coefficient arrays are in scratch (field
+// i after the previous field's arrays); field i's result goes to zout[i].
+sb_status contract(sb_plan *p, const ShapeGroup &G, double *const *zout, int nf, hipStream_t s) {
     const float *w = reinterpret_cast<const float *>(p->scratch + p->off_w);
     const float2 *coef = reinterpret_cast<const float2 *>(p->scratch + p->off_coef);
     double *part = reinterpret_cast<double *>(p->scratch + p->off_part);
@@ -755,6 +791,9 @@ sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
     contraction_shape(p, G.ng, &groups, &nvals, &nblocks);
     hipError_t e = hipSuccess;
     const int NB = p->prob.nbins;
+    // field strides: every array group of a field, its density, its block partials
+    const int64_t coef_fs = (int64_t)(p->npack > 0 ? p->nag : p->nlm) * NB * G.ng;
+    const int64_t part_fs = (int64_t)groups * nvals * nblocks;
     if (p->prob.npcf == 3) {
         PairArgs a{};
         a.coef = coef;
@@ -767,9 +806,13 @@ sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
         a.want_imag = p->prob.ndim == 2;
         a.partial = part;
         a.nblocks = nblocks;
+        a.fields = nf;
+        a.coef_fs = coef_fs;
+        a.w_fs = G.ng;
+        a.part_fs = part_fs;
         const double np_ = NB * (NB + 1) / 2.0;
-        const double fl = (double)G.ng * groups * (2.0 + np_ * (a.want_imag ? 8.0 : 4.0));
-        const double by = (double)G.ng * (8.0 * p->nk + 4.0);
+        const double fl = (double)nf * G.ng * groups * (2.0 + np_ * (a.want_imag ? 8.0 : 4.0));
+        const double by = (double)nf * G.ng * (8.0 * p->nk + 4.0);
         e = p->timed_launch(STAGE_CONTRACT, K_PAIR, s, [&]() { return launch_pair_contract(a, s); }, 0, 0, groups, by, fl);
     } else if (p->prob.ndim == 3) {
         QuadArgs a{};
@@ -790,6 +833,10 @@ sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
         a.nblocks = nblocks;
         a.odd = (p->prob.flags & SB_FLAG_ODD_PARITY) != 0;
         a.lm_src = p->npack > 0 ? p->d_lmsrc : nullptr;
+        a.fields = nf;
+        a.coef_fs = coef_fs;
+        a.w_fs = G.ng;
+        a.part_fs = part_fs;
         // flops per cell and canonical Lambda of the plain kernel: per bin pair, 8 per nonzero
         // coupling term, then per mc the weight (2) and the b3 contraction (4 per bin)
         auto lam_flops = [&](size_t c) {
@@ -836,22 +883,26 @@ sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
                 m.precision = p->prob.precision == SB_PREC_SPLIT_BF16 ? 1 : 0;
                 m.partial = part;
                 m.lm_src = a.lm_src;
+                m.fields = nf;
+                m.coef_fs = coef_fs;
+                m.w_fs = G.ng;
+                m.part_fs = part_fs;
                 int ncol = 0;
                 for (int q = 0; q < 3; ++q) {
                     bool dup = false;
                     for (int r = 0; r < q; ++r) dup |= C.l[r] == C.l[q];
                     if (!dup) ncol += C.l[q] + 1;
                 }
-                by = (double)G.ng * (8.0 * NB * ncol + 4.0);
+                by = (double)nf * G.ng * (8.0 * NB * ncol + 4.0);
                 e = p->timed_launch(STAGE_CONTRACT, K_QUAD_MFMA, s,
-                                    [&]() { return launch_quad_mfma(C.l[0], C.l[1], C.l[2], m, s); }, 0, 0, 1, by,
-                                    (double)G.ng * lam_flops_mfma(c));
+                                    [&]() { return launch_quad_mfma(C.l[0], C.l[1], C.l[2], m, s); }, 0, 0, nf, by,
+                                    (double)nf * G.ng * lam_flops_mfma(c));
             }
         } else {
             double fl = 0.0;
             for (size_t c = 0; c < p->f4.canon.size(); ++c) fl += lam_flops(c);
-            fl *= (double)G.ng;
-            const double by = (double)G.ng * (8.0 * p->nk + 4.0);
+            fl *= (double)nf * G.ng;
+            const double by = (double)nf * G.ng * (8.0 * p->nk + 4.0);
             e = p->timed_launch(STAGE_CONTRACT, K_QUAD, s, [&]() { return launch_quad_contract(a, s); }, 0, 0, groups, by, fl);
         }
     } else {
@@ -869,14 +920,19 @@ sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s) {
         a.nblocks = nblocks;
         a.mfma = (p->prob.flags & SB_FLAG_NO_MFMA) == 0;
         a.precision = p->prob.precision == SB_PREC_SPLIT_BF16 ? 1 : 0;
-        const double fl = (double)G.ng * groups * NB * NB * (8.0 + 8.0 * NB);
-        const double by = (double)G.ng * (8.0 * p->nk + 4.0);
+        a.fields = nf;
+        a.coef_fs = coef_fs;
+        a.w_fs = G.ng;
+        a.part_fs = part_fs;
+        const double fl = (double)nf * G.ng * groups * NB * NB * (8.0 + 8.0 * NB);
+        const double by = (double)nf * G.ng * (8.0 * p->nk + 4.0);
         e = p->timed_launch(STAGE_CONTRACT, K_PROJ4, s, [&]() { return launch_proj4_contract(a, s); }, 0, 0, groups, by, fl);
     }
     if (e != hipSuccess) return hip_fail(e, "contraction");
-    e = launch_block_sum(part, groups, nblocks, nvals, tot, s);
+    e = launch_block_sum(part, nf * groups, nblocks, nvals, tot, s);
     if (e != hipSuccess) return hip_fail(e, "block sum");
-    e = launch_gather(tot, p->d_gptr, p->d_gidx, p->d_gcoef, p->gather_nout, zeta_f, s);
+    for (int i = 0; i < nf && e == hipSuccess; ++i)
+        e = launch_gather(tot + (int64_t)i * groups * nvals, p->d_gptr, p->d_gidx, p->d_gcoef, p->gather_nout, zout[i], s);
     if (e != hipSuccess) return hip_fail(e, "gather");
     return SB_OK;
 }
@@ -922,22 +978,38 @@ sb_status forward(sb_plan *p, const void *const *delta, double *zeta, hipStream_
     for (int f = 0; f < p->batch; ++f)
         if (!delta[f]) return fail(SB_EINVAL, "null field pointer");
     if (sb_status st = check_fields_finite(p, delta, s); st != SB_OK) return st;
-    for (int f = 0; f < p->batch; ++f) {
-        double *zf = zeta + (int64_t)f * p->zeta_doubles;
-        const ShapeGroup &G = p->groups[p->field_group[f]];
-        sb_status st;
+    // fields of one shape go through the passes together, fbatch at a time (one launch per pass
+    // for the whole batch); with fbatch = 1 the fields run one by one in their order
+    auto run = [&](const ShapeGroup &G, const int *fidx, int nf) -> sb_status {
+        std::vector<const void *> dl(nf);
+        std::vector<double *> zo(nf);
+        for (int i = 0; i < nf; ++i) {
+            dl[i] = delta[fidx[i]];
+            zo[i] = zeta + (int64_t)fidx[i] * p->zeta_doubles;
+        }
         if (p->chunk_groups < p->nlm && !(p->prob.npcf == 3 && p->fused))
             return fail(SB_EUNSUPPORTED, "this path needs every kernel array at once; raise the scratch limit");
-        if (p->prob.npcf == 3 && p->fused) {
-            st = fused_3pcf(p, f, delta[f], zf, s);
-        } else {
-            st = density_spectrum(p, G, delta[f], s);
-            if (st == SB_OK)   // array groups (packed m = 0 pairs first) where the plan packs
-                st = p->npack > 0 ? coefficients(p, f, 0, p->nag, s, true, p->d_kmap) : coefficients(p, f, 0, p->nlm, s);
-            if (st == SB_OK) st = contract(p, f, zf, s);
+        if (p->prob.npcf == 3 && p->fused) return fused_3pcf(p, G, dl.data(), zo.data(), nf, s);
+        sb_status st = density_spectrum(p, G, dl.data(), nf, s);
+        if (st == SB_OK)   // array groups (packed m = 0 pairs first) where the plan packs
+            st = p->npack > 0 ? coefficients(p, fidx[0], 0, p->nag, s, true, p->d_kmap, nf)
+                              : coefficients(p, fidx[0], 0, p->nlm, s, true, nullptr, nf);
+        if (st == SB_OK) st = contract(p, G, zo.data(), nf, s);
+        return st;
+    };
+    if (p->fbatch <= 1) {
+        for (int f = 0; f < p->batch; ++f) {
+            const sb_status st = run(p->groups[p->field_group[f]], &f, 1);
+            if (st != SB_OK) return st;
         }
-        if (st != SB_OK) return st;
+        return SB_OK;
     }
+    for (const auto &G : p->groups)
+        for (size_t b0 = 0; b0 < G.fields.size(); b0 += p->fbatch) {
+            const int nf = (int)std::min<size_t>(p->fbatch, G.fields.size() - b0);
+            const sb_status st = run(G, G.fields.data() + b0, nf);
+            if (st != SB_OK) return st;
+        }
     return SB_OK;
 }
 
@@ -1045,6 +1117,21 @@ sb_status sb_normalize(sb_plan *p, const void *const *delta, double *zeta, doubl
                                               norm ? norm + (int64_t)f * ntup : nullptr, s);
         if (e != hipSuccess) return hip_fail(e, "normalization");
     }
+    return SB_OK;
+}
+
+sb_status sb_plan_set_field_batch(sb_plan *p, int32_t max_fields) {
+    if (!p) return fail(SB_EINVAL, "null plan");
+    if (p->persist) return fail(SB_ESTATE, "the field batch must be set before sb_plan_bind");
+    if (max_fields < 0) return fail(SB_EINVAL, "max_fields must be >= 0");
+    p->fbatch_req = max_fields;
+    layout_scratch(p);
+    return SB_OK;
+}
+
+sb_status sb_plan_get_field_batch(const sb_plan *p, int32_t *fields) {
+    if (!p || !fields) return fail(SB_EINVAL, "null argument");
+    *fields = p->fbatch;
     return SB_OK;
 }
 

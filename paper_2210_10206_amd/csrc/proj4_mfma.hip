@@ -24,6 +24,9 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 
 template <int NB>
 __global__ __launch_bounds__(256) void proj4_mfma_kernel(Proj4Args a) {
+    a.coef += (int64_t)blockIdx.z * a.coef_fs;   // field of the launch (grid.z)
+    a.w += (int64_t)blockIdx.z * a.w_fs;
+    a.partial += (int64_t)blockIdx.z * a.part_fs;
     constexpr int NP = NB * NB;
     constexpr int NMT = (NP + 15) / 16;        // M tiles of 16 pairs
     constexpr int TC = 64;                     // cells per staged tile (16 per wave)
@@ -146,6 +149,9 @@ __device__ __forceinline__ void split2(float v, __bf16 &h, __bf16 &l) {
 
 template <int NB>
 __global__ __launch_bounds__(256, 2) void proj4_split_kernel(Proj4Args a) {
+    a.coef += (int64_t)blockIdx.z * a.coef_fs;   // field of the launch (grid.z)
+    a.w += (int64_t)blockIdx.z * a.w_fs;
+    a.partial += (int64_t)blockIdx.z * a.part_fs;
     constexpr int NP = NB * NB;
     constexpr int NMT = (NP + 15) / 16;        // M tiles of 16 pairs
     constexpr int NNT = (2 * NB + 15) / 16;    // N tiles of 8 (b3, part) column pairs
@@ -268,7 +274,7 @@ __global__ __launch_bounds__(256, 2) void proj4_split_kernel(Proj4Args a) {
 
 template <int NB>
 hipError_t launch_nb(const Proj4Args &a, hipStream_t s) {
-    dim3 grid((unsigned)a.nblocks, (unsigned)a.npairs);
+    dim3 grid((unsigned)a.nblocks, (unsigned)a.npairs, (unsigned)(a.fields > 1 ? a.fields : 1));
     if (a.precision == 1)
         hipLaunchKernelGGL((proj4_split_kernel<NB>), grid, dim3(256), 0, s, a);
     else

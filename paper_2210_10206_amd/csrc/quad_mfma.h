@@ -200,6 +200,9 @@ __device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
 // before the current tile is contracted, so their latency hides behind the coupling work.
 template <int LA, int LB, int LC, int PREC>
 __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
+    a.coef += (int64_t)blockIdx.z * a.coef_fs;   // field of the launch (grid.z)
+    a.w += (int64_t)blockIdx.z * a.w_fs;
+    a.partial += (int64_t)blockIdx.z * a.part_fs;
     constexpr bool ODD = ((LA + LB + LC) & 1) != 0;
     constexpr bool SYM = LA == LB;                // only the pairs b1 <= b2 (SymPairs)
     constexpr int NMT = SYM ? 3 : 4;              // M tiles of 16 pairs
@@ -364,7 +367,7 @@ __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
 
 template <int LA, int LB, int LC>
 hipError_t launch_lambda(const QuadMArgs &a, hipStream_t s) {
-    dim3 grid((unsigned)a.nblocks);
+    dim3 grid((unsigned)a.nblocks, 1u, (unsigned)(a.fields > 1 ? a.fields : 1));
     if (a.precision == 1)
         hipLaunchKernelGGL((quad_mfma_kernel<LA, LB, LC, 1>), grid, dim3(256), 0, s, a);
     else

@@ -243,7 +243,8 @@ sb_status sb_autotune(sb_plan *p, void *stream, const char *cache_path) {
             float tot = 0.f;
             for (int rep = 0; rep < 3 && st == SB_OK; ++rep) {
                 (void)hipEventRecord(a, s);
-                st = contract(p, f0, zt, s);
+                double *zo[1] = {zt};
+                st = contract(p, p->groups[p->field_group[f0]], zo, 1, s);
                 (void)hipEventRecord(b, s);
                 (void)hipEventSynchronize(b);
                 float ms = 0.f;

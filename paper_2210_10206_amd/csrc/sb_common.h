@@ -87,6 +87,8 @@ struct Axis0Args {
                           // group i (mode 1); kc is then the whole kernel store (mode 0 without
                           // it: grid row y reads group y of kc)
     const float2 *tw;
+    int fields;           // mode 0: fields of one shape in the launch (grid.z; 0 counts as 1)
+    int64_t dhat_fs, out_fs;   // mode 0: element strides between the fields' dhat and out
 };
 hipError_t launch_axis0(const Axis0Args &a, hipStream_t s);
 
@@ -110,6 +112,8 @@ struct LastArgs {
                           // (row = rowmap[2 y + part] * npairs + pair)
     int prec;             // 0: float32 MFMA pair sums, 1: split-BF16 MFMA pair sums
     const float2 *tw;
+    int fields;           // fields of one shape in the launch (grid.z; 0 counts as 1)
+    int64_t in_fs, w_fs, part_fs;   // strides between the fields' in, w and partial
 };
 hipError_t launch_last_contract(const LastArgs &a, hipStream_t s);
 int fused_last_rows(int n, int nb);   // rows per tile the fused last pass uses (0: no kernel)

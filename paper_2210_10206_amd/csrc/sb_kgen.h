@@ -45,6 +45,8 @@ struct PairArgs {
     int want_imag;        // also accumulate the imaginary part (projected 3PCF)
     double *partial;      // [group][block][npairs * (want_imag ? 2 : 1)]
     int nblocks;
+    int fields;           // fields of one shape in the launch (grid.z; 0 counts as 1)
+    int64_t coef_fs, w_fs, part_fs;   // strides between the fields' coef, w and partial
 };
 hipError_t launch_pair_contract(const PairArgs &a, hipStream_t s);
 
@@ -77,6 +79,8 @@ struct QuadArgs {
     bool odd;                 // odd Lambda: the imaginary part of the sums (the real part vanishes)
     const int *lm_src;        // optional, 2 per lm: coefficient array and part (0: the complex array,
                               // 1 / 2: the real / imaginary part of a packed m = 0 array)
+    int fields;               // fields of one shape in the launch (grid.z; 0 counts as 1)
+    int64_t coef_fs, w_fs, part_fs;
 };
 hipError_t launch_quad_contract(const QuadArgs &a, hipStream_t s);
 
@@ -93,6 +97,8 @@ struct QuadMArgs {
     int precision;            // 0 float32 MFMA, 1 split-BF16 MFMA
     double *partial;          // [lam][nbins^3][block]
     const int *lm_src;        // optional, as in QuadArgs
+    int fields;               // fields of one shape in the launch (grid.z; 0 counts as 1)
+    int64_t coef_fs, w_fs, part_fs;
 };
 // Returns hipErrorInvalidValue when no kernel exists for (la, lb, lc).
 hipError_t launch_quad_mfma(int la, int lb, int lc, const QuadMArgs &a, hipStream_t s);
@@ -113,6 +119,8 @@ struct Proj4Args {
     int nblocks;
     int mfma;                 // 1: the matrix-core kernel (proj4_mfma.hip), 0: the vector kernel
     int precision;            // matrix-core kernel: 0 float32 MFMA, 1 split-BF16 MFMA
+    int fields;               // fields of one shape in the launch (grid.z; 0 counts as 1)
+    int64_t coef_fs, w_fs, part_fs;
 };
 hipError_t launch_proj4_contract(const Proj4Args &a, hipStream_t s);
 hipError_t launch_proj4_mfma(const Proj4Args &a, hipStream_t s);

@@ -14,6 +14,7 @@
 namespace sb {
 
 constexpr double kKernelCacheCap = 64.0 * 1024 * 1024 * 1024;   // bytes of kernel spectra kept at most
+constexpr double kBatchBytes = 32.0 * 1024 * 1024 * 1024;       // kernel arrays of a field batch by default
 
 enum Stage : int { STAGE_FFT = 0, STAGE_CONTRACT = 1, STAGE_OTHER = 2, STAGE_COUNT = 3 };
 
@@ -98,6 +99,10 @@ struct sb_plan {
     // unless a 3PCF plan's full set would exceed coef_limit (then the passes run in chunks)
     uint64_t coef_limit = 48ull << 30;
     int chunk_groups = 0;
+    // fields of one shape run through the passes together, up to fbatch at a time (one launch
+    // per pass for all of them): as many as kBatchBytes of kernel arrays allow, at most
+    // fbatch_req when the caller set it (sb_plan_set_field_batch), 1 when the passes run in chunks
+    int fbatch = 1, fbatch_req = 0;
     bool prepared = false;
     // launch shapes (autotuned): cells per workgroup of the cell-parallel contractions (unfused
     // 3PCF pair sums, full 4PCF, projected 4PCF); the scratch holds the partial sums of the
@@ -176,9 +181,9 @@ sb_status density_spectrum(sb_plan *p, const sb::ShapeGroup &G, const void *delt
 // transform along the last axis.  kmap (device, optional): the kernel group of each of the ng
 // output groups (array groups of a packed plan) instead of g0 .. g0 + ng - 1.
 sb_status coefficients(sb_plan *p, int f, int g0, int ngroups, hipStream_t s, bool last_axis = true,
-                       const int *kmap = nullptr);
+                       const int *kmap = nullptr, int nf = 1);
 void layout_scratch(sb_plan *p);
-sb_status contract(sb_plan *p, int f, double *zeta_f, hipStream_t s);
+sb_status contract(sb_plan *p, const ShapeGroup &G, double *const *zout, int nf, hipStream_t s);
 // SB_FLAG_CHECK_FINITE: count the NaN / Inf values of the inputs (n[i] values of dtype[i] at in[i]),
 // wait for the stream and return SB_ENONFINITE when there are any; SB_OK otherwise (and at once
 // when the flag is clear).

@@ -632,3 +632,57 @@ def test_axes_of_1024(sb, shape, npcf):
         with pytest.raises(Exception):   # the fused adjoint has no last pass at 1024
             plan.backward(dev, torch.zeros((1, 4, 4, 4), dtype=torch.float64, device="cuda"))
     plan.close()
+
+
+# ------------------------------------------------------------------ batched launches
+
+@pytest.mark.parametrize("kind", ["full3", "full4_mfma", "full4_split", "full4_valu", "full4_odd", "proj3", "proj4",
+                                  "proj4_split", "proj4_valu"])
+def test_field_batches_match_single_fields(sb, kind):
+    # fields of one shape share every pass launch (the field is the launch's third grid dimension):
+    # each field's sums equal those of one launch sequence per field, bit for bit, on an uneven
+    # batch whose shapes interleave
+    say(f"case: field batches vs one launch sequence per field, {kind}")
+    full = kind.startswith("full")
+    shapes = [(16, 16, 16), (24, 24, 24), (16, 16, 16), (24, 24, 24), (16, 16, 16)] if full else \
+             [(64, 96), (32, 48), (64, 96), (64, 96), (32, 48)]
+    fields = [lognormal_field(sh, seed=100 + i, sigma=1.0) for i, sh in enumerate(shapes)]
+    edges = linear_edges(6, 4)
+    kw = dict(npcf=3 if kind in ("full3", "proj3") else 4)
+    if kind.endswith("split"):
+        kw["precision"] = "split_bf16"
+    if kind.endswith("valu"):
+        kw["mfma"] = False
+    if kind.endswith("odd"):
+        kw["parity"] = "odd"
+    lmax = 4 if full else 3
+    pb, dev, zb = run_plan(sb, fields, edges, lmax, **kw)
+    p1, _, z1 = run_plan(sb, fields, edges, lmax, field_batch=1, **kw)
+    say(f"  fields per launch: {pb.field_batch} (batched plan), {p1.field_batch}")
+    assert pb.field_batch == 3 and p1.field_batch == 1
+    assert np.array_equal(zb, z1)
+    # the batched plan replayed from a HIP graph, three times with eager work between
+    s = torch.cuda.Stream()
+    out = torch.empty((len(fields), pb.zeta_doubles), dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        with torch.cuda.stream(s):
+            pb.forward_raw(dev, out=out, stream=s, graph=True)
+        s.synchronize()
+        assert np.array_equal(pb.unpack(out).cpu().numpy(), zb), f"graph replay {rep}"
+        _ = p1.forward(dev)
+        torch.cuda.synchronize()
+    # and against the oracle for one field of each shape
+    for i in (0, 1):
+        d64 = fields[i].astype(np.float64)
+        if kind == "full3":
+            ref = oracle.zeta3_full(d64, edges, lmax).real
+        elif kind.startswith("full4"):
+            lams, r = oracle.zeta4_full(d64, edges, lmax, parity="odd" if kind.endswith("odd") else "even")
+            ref = r.imag if kind.endswith("odd") else r.real
+        elif kind == "proj3":
+            ref = oracle.zeta3_proj(d64, edges, lmax)
+        else:
+            ref = oracle.zeta4_proj(d64, edges, lmax)[1]
+        check(zb[i], ref, TOL_SPLIT if kind.endswith("split") else TOL32, say, f"field {i} {shapes[i]}: ")
+    pb.close()
+    p1.close()
