@@ -33,8 +33,12 @@ _LIB = None
 def _lib():
     global _LIB
     if _LIB is None:
-        path = os.path.join(_HERE, "_liboracle.so")
+        # SB_ORACLE_LIB names another build of the same core (the sanitizer build of
+        # build.build(sanitize=True)); the default one is compiled on first use.
+        path = os.environ.get("SB_ORACLE_LIB") or os.path.join(_HERE, "_liboracle.so")
         if not os.path.exists(path):
+            if "SB_ORACLE_LIB" in os.environ:
+                raise FileNotFoundError(path)
             from .build import build
             build()
         lib = ctypes.CDLL(path)

@@ -7,11 +7,18 @@ import subprocess
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def build(verbose: bool = False) -> str:
+# AddressSanitizer + UndefinedBehaviorSanitizer build: same arithmetic flags, checks abort the
+# process at the first finding.
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=all"]
+
+
+def build(verbose: bool = False, sanitize: bool = False, out: str | None = None) -> str:
     src = os.path.join(_HERE, "core.c")
-    out = os.path.join(_HERE, "_liboracle.so")
+    out = out or os.path.join(_HERE, "_liboracle_san.so" if sanitize else "_liboracle.so")
     tmp = out + ".tmp"
-    cmd = ["gcc", "-O3", "-march=x86-64-v3", "-ffp-contract=off", "-fcx-limited-range", "-fopenmp", "-fPIC",
+    opt = SANITIZE_FLAGS if sanitize else ["-O3"]
+    cmd = ["gcc", *opt, "-march=x86-64-v3", "-ffp-contract=off", "-fcx-limited-range", "-fopenmp", "-fPIC",
            "-shared", "-Wall", "-o", tmp, src]
     if verbose:
         print(" ".join(cmd))

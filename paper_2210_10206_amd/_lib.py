@@ -5,7 +5,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsarabande_hip.so")
+# SB_LIB_PATH names another build of the same sources (the host-sanitizer build of
+# build.build(sanitize=True)); the in-tree library is the default.
+LIB_PATH = os.environ.get("SB_LIB_PATH") or os.path.join(_HERE, "libsarabande_hip.so")
 
 SB_OK, SB_EINVAL, SB_EUNSUPPORTED, SB_EWORKSPACE, SB_EHIP, SB_ENOMEM, SB_ENONFINITE, SB_ESTATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
