@@ -690,6 +690,7 @@ def main():
     value = elapsed = None
     roof = None
     per_kernel, stages, step_ms = {}, {}, {}
+    tuned = None
     errs, errs_l = [], []
     cold_ms = None
     z = None
@@ -723,6 +724,7 @@ def main():
         elapsed = time.perf_counter() - t0
         recs = plan.launch_records() if not args.graph else []
         plan.profile(False)
+        tuned = plan.choices()
         value = len(dev) * args.steps / elapsed
 
         # parity of this very run against the stored oracle values (when present)
@@ -871,6 +873,7 @@ def main():
         "plain_fp32_unfused": plain,
         "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
         "per_kernel": per_kernel,
+        "tuned_launch_shapes": tuned,
         "max_rel_err_vs_oracle": errs or None,
         "max_rel_err_vs_oracle_per_l": errs_l or None,
         "secondary_4pcf_128": c4,

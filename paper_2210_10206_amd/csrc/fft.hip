@@ -507,11 +507,12 @@ __global__ __launch_bounds__(NT) void fft_pass_pf_kernel(FftPass a, int tiles) {
 }
 
 // Register-resident pass along a strided axis for n = R1 * R2 (R2 divides R1): P adjacent
-// pencils of the faster axes per tile (16 or 32: rows of 128 or 256 contiguous bytes), thread q < R2 of a pencil owns elements q + R2 s (the
-// inputs of first-stage butterfly q and the outputs of second-stage butterflies q + R2 t), so
-// loads and stores are coalesced over the P pencils and LDS holds only the one exchange between
-// the two radix stages.  A workgroup walks `tiles` consecutive tiles with the next one's loads
-// in flight.
+// pencils of the faster axes per tile (16, 32 or 64: rows of 128, 256 or 512 contiguous bytes),
+// thread q < R2 of a pencil owns elements q + R2 s (the inputs of first-stage butterfly q and the
+// outputs of second-stage butterflies q + R2 t), so loads and stores are coalesced over the P
+// pencils and LDS holds only the one exchange between the two radix stages (130 KB at n = 256,
+// P = 64: one 1024-thread workgroup per CU).  A workgroup walks `tiles` consecutive tiles with
+// the next one's loads in flight.
 template <int R1, int R2, int P, int SIGN>
 __global__ __launch_bounds__(P * R2, 3) void mid_reg_kernel(FftPass a, int tiles) {
     constexpr int N = R1 * R2;
@@ -528,18 +529,26 @@ __global__ __launch_bounds__(P * R2, 3) void mid_reg_kernel(FftPass a, int tiles
     }
     const int64_t npencil = a.ng / N;
     const int64_t ntile = (npencil + P - 1) / P;
-    const float2 *in = reinterpret_cast<const float2 *>(a.in) + blockIdx.y * a.in_bs;
-    float2 *out = a.out + blockIdx.y * a.out_bs;
-    auto base = [&](int64_t g) -> int64_t { return (g / a.stride) * (int64_t)N * a.stride + (g % a.stride); };
+    // one array per grid row: every address is the array's base plus a 32-bit byte offset (the
+    // launcher checks that an array spans less than 4 GiB), so loads and stores take a uniform
+    // base and one offset register
+    const char *in = reinterpret_cast<const char *>(reinterpret_cast<const float2 *>(a.in) + blockIdx.y * a.in_bs);
+    char *out = reinterpret_cast<char *>(a.out + blockIdx.y * a.out_bs);
+    const uint32_t rstride = (uint32_t)a.stride * (uint32_t)sizeof(float2) * R2;   // bytes between rows r, r + 1
+    auto base = [&](int64_t g) -> uint32_t {
+        return (uint32_t)(((g / a.stride) * (int64_t)N * a.stride + (g % a.stride) + (int64_t)q * a.stride) *
+                          (int64_t)sizeof(float2));
+    };
     const int64_t t0 = (int64_t)blockIdx.x * tiles;
     const int64_t t1 = min(t0 + tiles, ntile);
     float2 nx[R1];
     auto load = [&](int64_t t) {
         const int64_t g = t * P + p;
-        const int64_t b = base(g);
+        const uint32_t b = base(g);
 #pragma unroll
         for (int r = 0; r < R1; ++r)
-            nx[r] = g < npencil ? ld_stream(&in[b + (int64_t)(q + R2 * r) * a.stride]) : make_float2(0.f, 0.f);
+            nx[r] = g < npencil ? ld_stream(reinterpret_cast<const float2 *>(in + (b + (uint32_t)r * rstride)))
+                                : make_float2(0.f, 0.f);
     };
     if (t0 < t1) load(t0);
     for (int64_t t = t0; t < t1; ++t) {
@@ -553,7 +562,8 @@ __global__ __launch_bounds__(P * R2, 3) void mid_reg_kernel(FftPass a, int tiles
         for (int r = 0; r < R1; ++r) ex[(R1 * q + r) * PITCH + p] = v[r];
         __syncthreads();
         const int64_t g = t * P + p;
-        const int64_t b = base(g);
+        // element q + R2 tt + R1 r of the pencil
+        const uint32_t b = base(g);
 #pragma unroll
         for (int tt = 0; tt < T; ++tt) {
             float2 u[R2];
@@ -567,7 +577,8 @@ __global__ __launch_bounds__(P * R2, 3) void mid_reg_kernel(FftPass a, int tiles
             Dft<R2, SIGN>::run(u);
             if (g < npencil)
 #pragma unroll
-                for (int r = 0; r < R2; ++r) st_stream(&out[b + (int64_t)(q + R2 * tt + R1 * r) * a.stride], u[r]);
+                for (int r = 0; r < R2; ++r)
+                    st_stream(reinterpret_cast<float2 *>(out + (b + (uint32_t)(tt + T * r) * rstride)), u[r]);
         }
     }
 }
@@ -653,15 +664,26 @@ hipError_t launch(const FftPass &a, hipStream_t s) {
 // The variants are the autotuner's candidates.
 hipError_t launch_fft_pass(const FftPass &a, hipStream_t s) {
     const int v = a.variant;
-    // variants 6 and 7 (lengths 64, 128, 256 along a strided axis whose stride is a multiple of
+    // variants 6 to 9 (lengths 64, 128, 256 along a strided axis whose stride is a multiple of
     // 16): register-resident; 6: tiles of 32 pencils (16 if the stride is not a multiple of 32),
-    // 8 per workgroup, 7: 16 pencils, 16 per workgroup.  Elsewhere they run as variants 4 and 5.
-    if (v >= 6 && a.load == LOAD_C && a.store == STORE_C && a.stride > 1 && a.stride % 16 == 0) {
-        const bool wide = v == 6 && a.stride % 32 == 0;
-        const int tiles = v == 6 ? 8 : 16;
-        if (a.n == 256) return wide ? launch_mid_reg<16, 16, 32>(a, s, tiles) : launch_mid_reg<16, 16, 16>(a, s, tiles);
-        if (a.n == 128) return wide ? launch_mid_reg<16, 8, 32>(a, s, tiles) : launch_mid_reg<16, 8, 16>(a, s, tiles);
-        if (a.n == 64) return wide ? launch_mid_reg<8, 8, 32>(a, s, tiles) : launch_mid_reg<8, 8, 16>(a, s, tiles);
+    // 8 per workgroup, 7: 16 pencils, 16 per workgroup; 8 and 9: 64 pencils (rows of 512
+    // contiguous bytes; 32 or 16 where the stride allows no more), 8 and 4 tiles per workgroup.
+    // Elsewhere they run as variants 4 and 5.
+    // (an array must span less than 4 GiB: the register-resident kernels address it by 32-bit offsets)
+    if (v >= 6 && a.load == LOAD_C && a.store == STORE_C && a.stride > 1 && a.stride % 16 == 0 &&
+        a.ng * (int64_t)sizeof(float2) <= (int64_t)UINT32_MAX) {
+        const bool x64 = v >= 8 && a.stride % 64 == 0;
+        const bool wide = v != 7 && a.stride % 32 == 0;
+        const int tiles = v == 7 ? 16 : (v == 9 ? 4 : 8);
+        if (a.n == 256)
+            return x64 ? launch_mid_reg<16, 16, 64>(a, s, tiles)
+                       : wide ? launch_mid_reg<16, 16, 32>(a, s, tiles) : launch_mid_reg<16, 16, 16>(a, s, tiles);
+        if (a.n == 128)
+            return x64 ? launch_mid_reg<16, 8, 64>(a, s, tiles)
+                       : wide ? launch_mid_reg<16, 8, 32>(a, s, tiles) : launch_mid_reg<16, 8, 16>(a, s, tiles);
+        if (a.n == 64)
+            return x64 ? launch_mid_reg<8, 8, 64>(a, s, tiles)
+                       : wide ? launch_mid_reg<8, 8, 32>(a, s, tiles) : launch_mid_reg<8, 8, 16>(a, s, tiles);
         if (a.n == 512) {
             constexpr int P = 16;
             const int64_t ntile = (a.ng / 512 + P - 1) / P;
@@ -795,9 +817,10 @@ bool fft_supported(int n) {
 
 int fft_num_variants(int n) {
     // 0, 1: one tile per workgroup (two shapes where defined); 2, 3: persistent, 4 / 16 tiles;
-    // 4, 5 (lengths 64-256): persistent with few, wide radix stages; 6, 7 (64, 128, 256):
-    // register-resident along a strided axis
-    if (n == 256 || n == 128 || n == 64 || n == 512) return 8;
+    // 4, 5 (lengths 64-256): persistent with few, wide radix stages; 6 to 9 (64, 128, 256; 6, 7
+    // at 512): register-resident along a strided axis
+    if (n == 256 || n == 128 || n == 64) return 10;
+    if (n == 512) return 8;
     return (n == 192 || n == 160 || n == 96) ? 6 : 4;
 }
 

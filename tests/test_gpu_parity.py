@@ -228,12 +228,12 @@ def test_packed_m0_arrays(sb, shape, nbins, lmax):
 
 
 @pytest.mark.parametrize("shape", [(8, 64, 16), (8, 128, 16), (8, 256, 16), (8, 512, 16), (512, 8, 32),
-                                   (8, 1024, 16), (1024, 8, 16)])
+                                   (8, 1024, 16), (1024, 8, 16), (8, 256, 64), (8, 128, 64), (8, 64, 64)])
 def test_every_fft_variant(sb, shape):
     # every launch shape of the passes of each axis (what the autotuner may pick) gives the
     # oracle's sums; the middle axis (a plain pass in the forward, kernel-cache and density
     # transforms too) has length 64 / 128 / 256 / 512, or 512 is the first axis (density and
-    # kernel-cache transforms, stride 256)
+    # kernel-cache transforms, stride 256); a last axis of 64 lets the 64-pencil middle-pass tiles run
     say(f"case: {shape} full 3PCF, 4 bins to 4, lmax 3, every FFT variant of every axis")
     d = lognormal_field(shape, seed=40, sigma=1.0)
     edges = linear_edges(4, 4)
