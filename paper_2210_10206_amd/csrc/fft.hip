@@ -244,6 +244,9 @@ __global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void
     const int p = tid % P, q = tid / P;
     const int64_t g = (int64_t)blockIdx.x * P + p;
     const bool ok = g < a.plane;
+    // 32-bit byte offsets within one array (the launcher checks that an array spans less than
+    // 4 GiB): element (j, g) of an array is at j * pb + gb
+    const uint32_t pb = (uint32_t)a.plane * (uint32_t)sizeof(float2), gb = (uint32_t)g * (uint32_t)sizeof(float2);
     for (int i = tid; i < N; i += P * R2) {
         const int t = i / (R2 * R2), r = i / R2 % R2, qq = i % R2;
         twl[i] = a.tw[((qq + R2 * t) * r) % N];
@@ -259,7 +262,7 @@ __global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void
             }
             const int j = q + R2 * r;
             const int pl = (a.np == N || j <= a.r0) ? j : (j >= N - a.r0 ? a.np - (N - j) : -1);
-            dst[r] = (ok && pl >= 0) ? ld_stream(&kc[(int64_t)pl * a.plane + g]) : make_float2(0.f, 0.f);
+            dst[r] = (ok && pl >= 0) ? ld_stream(at_bytes(kc, (uint32_t)pl * pb + gb)) : make_float2(0.f, 0.f);
         }
     };
     // one transform: radix-R1 DFT of the own rows, exchange, twiddle, radix-R2 DFTs -> own rows
@@ -291,7 +294,7 @@ __global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void
         auto load_v = [&](int b, float2 *dst) {
             const float2 *vb = a.vin + (int64_t)b * a.ng;
 #pragma unroll
-            for (int r = 0; r < R1; ++r) dst[r] = ok ? vb[(int64_t)(q + R2 * r) * a.plane + g] : make_float2(0.f, 0.f);
+            for (int r = 0; r < R1; ++r) dst[r] = ok ? *at_bytes(vb, (uint32_t)(q + R2 * r) * pb + gb) : make_float2(0.f, 0.f);
         };
         float2 acc[R1], nv[R1];
 #pragma unroll
@@ -312,7 +315,7 @@ __global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void
                 if (ok)
 #pragma unroll
                     for (int r = 0; r < R1; ++r) {
-                        float2 *o = a.out + (int64_t)(q + R2 * r) * a.plane + g;
+                        float2 *o = at_bytes(a.out, (uint32_t)(q + R2 * r) * pb + gb);
                         *o = cadd(*o, acc[r]);
                     }
 #pragma unroll
@@ -323,7 +326,7 @@ __global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void
     }
     float2 dr[R1];
 #pragma unroll
-    for (int r = 0; r < R1; ++r) dr[r] = ok ? a.dhat[(int64_t)(q + R2 * r) * a.plane + g] : make_float2(0.f, 0.f);
+    for (int r = 0; r < R1; ++r) dr[r] = ok ? *at_bytes(a.dhat, (uint32_t)(q + R2 * r) * pb + gb) : make_float2(0.f, 0.f);
     const int64_t kbase = (int64_t)(a.kmap ? a.kmap[blockIdx.y] : blockIdx.y) * a.nb;   // kernel group
     const int64_t obase = (int64_t)blockIdx.y * a.nb;                                 // output arrays
     load_kernel(kbase, nx);
@@ -339,7 +342,7 @@ __global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void
         float2 *out = a.out + (obase + b) * a.ng;
         if (ok)
 #pragma unroll
-            for (int r = 0; r < R1; ++r) st_stream(&out[(int64_t)(q + R2 * r) * a.plane + g], v[r]);
+            for (int r = 0; r < R1; ++r) st_stream(at_bytes(out, (uint32_t)(q + R2 * r) * pb + gb), v[r]);
     }
 }
 

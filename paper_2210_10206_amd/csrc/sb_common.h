@@ -26,6 +26,15 @@ __device__ __forceinline__ void st_stream(float2 *p, float2 v) {
     __builtin_nontemporal_store(f2nt{v.x, v.y}, reinterpret_cast<f2nt *>(p));
 }
 
+// Element at a 32-bit byte offset from an array base (arrays under 4 GiB): with a uniform base
+// the loads and stores take one offset register instead of a 64-bit address.
+__device__ __forceinline__ const float2 *at_bytes(const float2 *base, uint32_t bytes) {
+    return reinterpret_cast<const float2 *>(reinterpret_cast<const char *>(base) + bytes);
+}
+__device__ __forceinline__ float2 *at_bytes(float2 *base, uint32_t bytes) {
+    return reinterpret_cast<float2 *>(reinterpret_cast<char *>(base) + bytes);
+}
+
 // ---------------------------------------------------------------- FFT passes
 // One pass = 1D transforms of length n along one axis of a C-ordered array of
 // `ng` complex cells.  The axis has element stride `stride` (product of the later
