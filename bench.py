@@ -460,8 +460,8 @@ def run_512(api, steps, warmup):
 def run_1024(api, steps, warmup):
     """Full 3PCF of one 1024^3 field (the 4x4x4 tiling of the sigma 0.5 seed 0 256^3 field), 10
     bins to 32, lmax 6: no kernel cache (it would take about 169 GB); each chunk of (l, m) groups
-    regenerates its kernel planes, and the 1024 last axis runs the plain pass and the pair
-    contraction.  Fields/s and the per-stage times."""
+    regenerates its kernel planes, and the 1024-point last pass is fused with the pair sums.
+    Fields/s and the per-stage times."""
     import torch
     from fieldgen import lognormal_field, linear_edges
     d = torch.from_numpy(lognormal_field((256,) * 3, seed=0, sigma=0.5)).cuda().repeat(4, 4, 4).contiguous()
@@ -487,7 +487,7 @@ def run_1024(api, steps, warmup):
     el = time.perf_counter() - t0
     recs = plan.launch_records()
     plan.profile(False)
-    kinds = {0: "fft_passes", 1: "axis0_correlation", 3: "pair_contraction"}
+    kinds = {0: "fft_passes", 1: "axis0_correlation", 2: "fused_last_pass", 3: "pair_contraction"}
     per = {}
     for r in recs:
         k = kinds.get(r["kernel"], "other")

@@ -273,8 +273,10 @@ sb_status sb_autotune(sb_plan *plan, void *stream, const char *cache_path);
 
 /* Number of launch shapes ("variants") of the FFT passes of length n (0: unsupported
  * length), and the choice of one for the passes of length n along `axis` of this plan
- * (what sb_autotune sets by timing; e.g. to reuse tuned choices).  Results do not depend on
- * the variant beyond float32 rounding.  Errors: SB_EINVAL (length, axis or variant). */
+ * (what sb_autotune sets by timing; e.g. to reuse tuned choices).  Untuned passes take
+ * variant 0, except those of length 1024 along a strided axis (variant 6, the register-resident
+ * form).  Results do not depend on the variant beyond float32 rounding.  Errors: SB_EINVAL
+ * (length, axis or variant). */
 int32_t sb_fft_variants(int32_t n);
 sb_status sb_plan_set_fft_variant(sb_plan *plan, int32_t n, int32_t axis, int32_t variant);
 sb_status sb_plan_get_fft_variant(const sb_plan *plan, int32_t n, int32_t axis, int32_t *variant);

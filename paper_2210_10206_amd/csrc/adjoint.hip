@@ -105,8 +105,11 @@ hipError_t launch_adj_last(const AdjLastArgs &a, hipStream_t s) {
         default: break;
     }
     if (e == hipSuccess) return e;
-    switch (a.n) {
-#define SB_X(N, TPP, ...) case N: return adjlast::launch_n<N, TPP, __VA_ARGS__>(a, s);
+    switch (a.n) {   // (none at 1024: a tile of every bin of a row would not fit the LDS)
+#define SB_X(N, TPP, ...)                                                             \
+    case N:                                                                           \
+        if constexpr (N <= 512) return adjlast::launch_n<N, TPP, __VA_ARGS__>(a, s); \
+        else return hipErrorInvalidValue;
         SB_LAST_CONFIGS(SB_X)
 #undef SB_X
         default: return hipErrorInvalidValue;
@@ -122,7 +125,7 @@ sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta
     if (p->regen) return fail(SB_EUNSUPPORTED, "the adjoint reads cached kernel spectra; this plan regenerates them");
     if (p->adj_fused)
         for (const auto &G : p->groups)
-            if (fused_last_rows((int)G.n[2], p->prob.nbins) <= 0)
+            if (fused_last_rows((int)G.n[2], p->prob.nbins) <= 0 || G.n[2] > 512)
                 return fail(SB_EUNSUPPORTED, "no fused adjoint last pass for a last axis of " + std::to_string(G.n[2]) +
                                                  " (use SB_FLAG_UNFUSED)");
     const int NB = p->prob.nbins;

@@ -351,18 +351,23 @@ __global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void
 // pencil owns rows q + T s.  P adjacent pencils of the contiguous axes per workgroup.
 // KR as in axis0_reg_kernel: rows r <= KR and r >= R0 - KR of a thread are the only ones the
 // compact kernel support can reach (KR >= R0 / 2: all rows).
-template <int N, int P, int MODE, int KR, int R0, int... REST>
+template <int N, int P, int MODE, int KR, bool ONE, int R0, int... REST>
 __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
     a.dhat += (int64_t)blockIdx.z * a.dhat_fs;   // field of the launch (grid.z)
     a.out += (int64_t)blockIdx.z * a.out_fs;
     constexpr int T = N / R0;
     constexpr int PITCH = P + 1;
-    __shared__ float2 ex[2][N * PITCH];
+    __shared__ float2 ex[ONE ? 1 : 2][N * PITCH];   // ONE: a single exchange buffer
+    float2 *ex1 = ex[ONE ? 0 : 1];
     __shared__ float2 tw[N];
     const int tid = threadIdx.x;
     const int p = tid % P, q = tid / P;
     const int64_t g = (int64_t)blockIdx.x * P + p;
     const bool ok = g < a.plane;
+    // element q + T r of a pencil: the uniform row pointer of r plus the lane's 32-bit byte offset
+    // (q plane + g) * 8 (under 4 GiB: q < T <= 64 and plane <= 2^20 cells)
+    const uint32_t lane_off = (uint32_t)(((int64_t)q * a.plane + g) * (int64_t)sizeof(float2));
+    auto row = [&](const float2 *base, int r) { return base + (int64_t)(T * r) * a.plane; };
     for (int i = tid; i < N; i += P * T) tw[i] = a.tw[i];
     const int64_t kstride = (int64_t)a.np * a.plane;
     auto load_kernel = [&](int64_t k, float2 *dst) {
@@ -401,8 +406,10 @@ __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
 #pragma unroll
             for (int r = 0; r < R0; ++r) { v[r] = nv[r]; k[r] = nx[r]; }
             if (t + 1 < nt) { load_v(t + 1, nv); load_kernel(acc_kernel(a, t + 1), nx); }
-            reg_stages<N, -1, R0, REST...>(v, ex[0], ex[1], tw, q, p, PITCH);
-            reg_stages<N, -1, R0, REST...>(k, ex[0], ex[1], tw, q, p, PITCH);
+            if constexpr (ONE) __syncthreads();   // the previous transform has read the buffer
+            reg_stages<N, -1, R0, REST...>(v, ex[0], ex1, tw, q, p, PITCH);
+            if constexpr (ONE) __syncthreads();
+            reg_stages<N, -1, R0, REST...>(k, ex[0], ex1, tw, q, p, PITCH);
 #pragma unroll
             for (int r = 0; r < R0; ++r) acc[r] = cadd(acc[r], cmul(v[r], k[r]));
             if (t % a.nb == a.nb - 1) {   // end of a group: out += its sum, as separate launches would
@@ -420,7 +427,7 @@ __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
     }
     float2 dr[R0];
 #pragma unroll
-    for (int r = 0; r < R0; ++r) dr[r] = ok ? a.dhat[(int64_t)(q + T * r) * a.plane + g] : make_float2(0.f, 0.f);
+    for (int r = 0; r < R0; ++r) dr[r] = ok ? *at_bytes(row(a.dhat, r), lane_off) : make_float2(0.f, 0.f);
     const int64_t kbase = (int64_t)(a.kmap ? a.kmap[blockIdx.y] : blockIdx.y) * a.nb;   // kernel group
     const int64_t obase = (int64_t)blockIdx.y * a.nb;                                 // output arrays
     load_kernel(kbase, nx);
@@ -430,14 +437,16 @@ __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
 #pragma unroll
         for (int r = 0; r < R0; ++r) v[r] = nx[r];
         if (b + 1 < a.nb) load_kernel(kbase + b + 1, nx);   // in flight during the transforms
-        reg_stages<N, -1, R0, REST...>(v, ex[0], ex[1], tw, q, p, PITCH);
+        if constexpr (ONE) __syncthreads();   // the previous transform has read the buffer
+        reg_stages<N, -1, R0, REST...>(v, ex[0], ex1, tw, q, p, PITCH);
 #pragma unroll
         for (int r = 0; r < R0; ++r) v[r] = cmul(v[r], dr[r]);
-        reg_stages<N, 1, R0, REST...>(v, ex[0], ex[1], tw, q, p, PITCH);
+        if constexpr (ONE) __syncthreads();
+        reg_stages<N, 1, R0, REST...>(v, ex[0], ex1, tw, q, p, PITCH);
         float2 *out = a.out + (obase + b) * a.ng;
         if (ok)
 #pragma unroll
-            for (int r = 0; r < R0; ++r) st_stream(&out[(int64_t)(q + T * r) * a.plane + g], v[r]);
+            for (int r = 0; r < R0; ++r) st_stream(at_bytes(const_cast<float2 *>(row(out, r)), lane_off), v[r]);
     }
 }
 
@@ -532,26 +541,26 @@ __global__ __launch_bounds__(P * R2, 3) void mid_reg_kernel(FftPass a, int tiles
     }
     const int64_t npencil = a.ng / N;
     const int64_t ntile = (npencil + P - 1) / P;
-    // one array per grid row: every address is the array's base plus a 32-bit byte offset (the
-    // launcher checks that an array spans less than 4 GiB), so loads and stores take a uniform
-    // base and one offset register
-    const char *in = reinterpret_cast<const char *>(reinterpret_cast<const float2 *>(a.in) + blockIdx.y * a.in_bs);
-    char *out = reinterpret_cast<char *>(a.out + blockIdx.y * a.out_bs);
-    const uint32_t rstride = (uint32_t)a.stride * (uint32_t)sizeof(float2) * R2;   // bytes between rows r, r + 1
-    auto base = [&](int64_t g) -> uint32_t {
-        return (uint32_t)(((g / a.stride) * (int64_t)N * a.stride + (g % a.stride) + (int64_t)q * a.stride) *
-                          (int64_t)sizeof(float2));
+    const float2 *in = reinterpret_cast<const float2 *>(a.in) + blockIdx.y * a.in_bs;
+    float2 *out = a.out + blockIdx.y * a.out_bs;
+    // P divides the stride, so a tile's pencils share one uniform base; a lane addresses element
+    // j of its pencil as the uniform row pointer of j plus its own 32-bit byte offset (the
+    // launcher checks that n * stride elements span less than 4 GiB)
+    auto tile_base = [&](int64_t t) -> int64_t {
+        const int64_t g0 = t * P;
+        return (g0 / a.stride) * (int64_t)N * a.stride + (g0 % a.stride);
     };
+    const uint32_t es = (uint32_t)a.stride * (uint32_t)sizeof(float2);   // bytes between elements
+    const uint32_t lane_off = (uint32_t)p * (uint32_t)sizeof(float2) + (uint32_t)q * es;
     const int64_t t0 = (int64_t)blockIdx.x * tiles;
     const int64_t t1 = min(t0 + tiles, ntile);
     float2 nx[R1];
     auto load = [&](int64_t t) {
-        const int64_t g = t * P + p;
-        const uint32_t b = base(g);
+        const float2 *tin = in + tile_base(t);
+        const bool ok = t * P + p < npencil;
 #pragma unroll
-        for (int r = 0; r < R1; ++r)
-            nx[r] = g < npencil ? ld_stream(reinterpret_cast<const float2 *>(in + (b + (uint32_t)r * rstride)))
-                                : make_float2(0.f, 0.f);
+        for (int r = 0; r < R1; ++r)   // element q + R2 r
+            nx[r] = ok ? ld_stream(at_bytes(at_bytes(tin, (uint32_t)(R2 * r) * es), lane_off)) : make_float2(0.f, 0.f);
     };
     if (t0 < t1) load(t0);
     for (int64_t t = t0; t < t1; ++t) {
@@ -564,9 +573,8 @@ __global__ __launch_bounds__(P * R2, 3) void mid_reg_kernel(FftPass a, int tiles
 #pragma unroll
         for (int r = 0; r < R1; ++r) ex[(R1 * q + r) * PITCH + p] = v[r];
         __syncthreads();
-        const int64_t g = t * P + p;
-        // element q + R2 tt + R1 r of the pencil
-        const uint32_t b = base(g);
+        const bool ok = t * P + p < npencil;
+        float2 *tout = out + tile_base(t);
 #pragma unroll
         for (int tt = 0; tt < T; ++tt) {
             float2 u[R2];
@@ -578,18 +586,20 @@ __global__ __launch_bounds__(P * R2, 3) void mid_reg_kernel(FftPass a, int tiles
                 u[r] = r == 0 ? x : cmul(x, w);
             }
             Dft<R2, SIGN>::run(u);
-            if (g < npencil)
+            if (ok)
 #pragma unroll
-                for (int r = 0; r < R2; ++r)
-                    st_stream(reinterpret_cast<float2 *>(out + (b + (uint32_t)(tt + T * r) * rstride)), u[r]);
+                for (int r = 0; r < R2; ++r)   // element q + R2 (tt + T r)
+                    st_stream(at_bytes(at_bytes(tout, (uint32_t)(R2 * (tt + T * r)) * es), lane_off), u[r]);
         }
     }
 }
 
 // The same for the three-stage radix lists (reg_stages): thread q < T = n / R0 of a pencil owns
 // elements q + T s, the stages exchange through one LDS buffer (two barriers per exchange), so
-// that two 512-thread workgroups share a CU.  Tiles are loaded as they are reached.
-template <int N, int P, int SIGN, int R0, int... REST>
+// that two 512-thread workgroups share a CU.  P divides
+// the stride, so a tile's pencils share one uniform base and a lane addresses its elements by
+// 32-bit byte offsets from it (the launcher checks that n * stride elements span less than 4 GiB).
+template <int N, int P, int SIGN, bool PF, int R0, int... REST>
 __global__ __launch_bounds__(P * (N / R0), 4) void mid_rs_kernel(FftPass a, int tiles) {
     constexpr int T = N / R0;
     constexpr int PITCH = P + 1;
@@ -602,27 +612,43 @@ __global__ __launch_bounds__(P * (N / R0), 4) void mid_rs_kernel(FftPass a, int 
     const int64_t ntile = (npencil + P - 1) / P;
     const float2 *in = reinterpret_cast<const float2 *>(a.in) + blockIdx.y * a.in_bs;
     float2 *out = a.out + blockIdx.y * a.out_bs;
-    auto base = [&](int64_t g) -> int64_t { return (g / a.stride) * (int64_t)N * a.stride + (g % a.stride); };
+    // first element of tile t (pencils t P .. t P + P - 1, adjacent along the faster axes)
+    auto tile_base = [&](int64_t t) -> int64_t {
+        const int64_t g0 = t * P;
+        return (g0 / a.stride) * (int64_t)N * a.stride + (g0 % a.stride);
+    };
+    const uint32_t es = (uint32_t)a.stride * (uint32_t)sizeof(float2);        // bytes between elements
+    const uint32_t lane_off = (uint32_t)p * (uint32_t)sizeof(float2) + (uint32_t)q * es;
     const int64_t t0 = (int64_t)blockIdx.x * tiles;
     const int64_t t1 = min(t0 + tiles, ntile);
-    for (int64_t t = t0; t < t1; ++t) {
-        // no register prefetch (it would not fit next to the transform at 4 waves per SIMD): the
-        // other workgroup on the CU covers the load latency
-        float2 v[R0];
-        {
-            const int64_t g = t * P + p;
-            const int64_t b = base(g);
+    // element q + T r of a tile: the uniform row pointer of r plus the lane's offset
+    auto load = [&](int64_t t, float2 *dst) {
+        const float2 *tin = in + tile_base(t);
+        const bool ok = t * P + p < npencil;
 #pragma unroll
-            for (int r = 0; r < R0; ++r)
-                v[r] = g < npencil ? ld_stream(&in[b + (int64_t)(q + T * r) * a.stride]) : make_float2(0.f, 0.f);
+        for (int r = 0; r < R0; ++r)
+            dst[r] = ok ? ld_stream(at_bytes(at_bytes(tin, (uint32_t)(T * r) * es), lane_off)) : make_float2(0.f, 0.f);
+    };
+    // PF: the next tile's loads are in flight during the transform; otherwise the other
+    // workgroup's waves cover the load latency
+    float2 nx[PF ? R0 : 1];
+    if (PF && t0 < t1) load(t0, nx);
+    for (int64_t t = t0; t < t1; ++t) {
+        const bool ok = t * P + p < npencil;
+        float2 v[R0];
+        if constexpr (PF) {
+#pragma unroll
+            for (int r = 0; r < R0; ++r) v[r] = nx[r];
+            if (t + 1 < t1) load(t + 1, nx);
+        } else {
+            load(t, v);
         }
         __syncthreads();                 // the previous tile's last stage has read the buffer
         reg_stages<N, SIGN, R0, REST...>(v, ex, ex, tw, q, p, PITCH);
-        const int64_t g = t * P + p;
-        if (g < npencil) {
-            const int64_t b = base(g);
+        if (ok) {
+            float2 *tout = out + tile_base(t);
 #pragma unroll
-            for (int r = 0; r < R0; ++r) st_stream(&out[b + (int64_t)(q + T * r) * a.stride], v[r]);
+            for (int r = 0; r < R0; ++r) st_stream(at_bytes(at_bytes(tout, (uint32_t)(T * r) * es), lane_off), v[r]);
         }
     }
 }
@@ -672,9 +698,10 @@ hipError_t launch_fft_pass(const FftPass &a, hipStream_t s) {
     // 8 per workgroup, 7: 16 pencils, 16 per workgroup; 8 and 9: 64 pencils (rows of 512
     // contiguous bytes; 32 or 16 where the stride allows no more), 8 and 4 tiles per workgroup.
     // Elsewhere they run as variants 4 and 5.
-    // (an array must span less than 4 GiB: the register-resident kernels address it by 32-bit offsets)
-    if (v >= 6 && a.load == LOAD_C && a.store == STORE_C && a.stride > 1 && a.stride % 16 == 0 &&
-        a.ng * (int64_t)sizeof(float2) <= (int64_t)UINT32_MAX) {
+    // (the register-resident kernels address a tile's n * stride elements by 32-bit byte offsets,
+    // so those must span less than 4 GiB)
+    const bool off32 = (int64_t)a.n * a.stride * (int64_t)sizeof(float2) <= (int64_t)UINT32_MAX;
+    if (v >= 6 && a.load == LOAD_C && a.store == STORE_C && a.stride > 1 && a.stride % 16 == 0 && off32) {
         const bool x64 = v >= 8 && a.stride % 64 == 0;
         const bool wide = v != 7 && a.stride % 32 == 0;
         const int tiles = v == 7 ? 16 : (v == 9 ? 4 : 8);
@@ -691,8 +718,28 @@ hipError_t launch_fft_pass(const FftPass &a, hipStream_t s) {
             constexpr int P = 16;
             const int64_t ntile = (a.ng / 512 + P - 1) / P;
             dim3 grid((unsigned)((ntile + tiles - 1) / tiles), (unsigned)a.batch);
-            if (a.sign < 0) hipLaunchKernelGGL((mid_rs_kernel<512, P, -1, 16, 8, 4>), grid, dim3(32 * P), 0, s, a, tiles);
-            else hipLaunchKernelGGL((mid_rs_kernel<512, P, 1, 16, 8, 4>), grid, dim3(32 * P), 0, s, a, tiles);
+            // variant 7 keeps the next tile's loads in flight
+            if (v == 6) {
+                if (a.sign < 0) hipLaunchKernelGGL((mid_rs_kernel<512, P, -1, false, 16, 8, 4>), grid, dim3(32 * P), 0, s, a, tiles);
+                else hipLaunchKernelGGL((mid_rs_kernel<512, P, 1, false, 16, 8, 4>), grid, dim3(32 * P), 0, s, a, tiles);
+            } else {
+                if (a.sign < 0) hipLaunchKernelGGL((mid_rs_kernel<512, P, -1, true, 16, 8, 4>), grid, dim3(32 * P), 0, s, a, tiles);
+                else hipLaunchKernelGGL((mid_rs_kernel<512, P, 1, true, 16, 8, 4>), grid, dim3(32 * P), 0, s, a, tiles);
+            }
+            return hipGetLastError();
+        }
+        if (a.n == 1024) {
+            // 16 x 16 x 4 in registers, 64 threads per pencil: 16 pencils (1024 threads, 139 KB of LDS)
+            // for variant 6, 8 pencils (512 threads) for variant 7
+            auto go = [&](auto p_c) {
+                constexpr int P = decltype(p_c)::value;
+                const int64_t ntile = (a.ng / 1024 + P - 1) / P;
+                dim3 grid((unsigned)((ntile + tiles - 1) / tiles), (unsigned)a.batch);
+                if (a.sign < 0) hipLaunchKernelGGL((mid_rs_kernel<1024, P, -1, false, 16, 16, 4>), grid, dim3(64 * P), 0, s, a, tiles);
+                else hipLaunchKernelGGL((mid_rs_kernel<1024, P, 1, false, 16, 16, 4>), grid, dim3(64 * P), 0, s, a, tiles);
+            };
+            if (v == 6) go(std::integral_constant<int, 16>{});
+            else go(std::integral_constant<int, 8>{});
             return hipGetLastError();
         }
     }
@@ -737,6 +784,18 @@ hipError_t launch_fft_pass(const FftPass &a, hipStream_t s) {
 }
 
 hipError_t launch_axis0(const Axis0Args &a, hipStream_t s) {
+    if (a.n == 1024 && a.mode == 0) {
+        // 8 x 8 x 4 x 4 in registers, 128 threads per pencil (8 elements each, which leaves room
+        // for the density spectrum), 8 pencils (rows of 64 contiguous bytes) per 1024-thread
+        // workgroup, one exchange buffer (74 KB of LDS)
+        constexpr int P = 8;
+        dim3 grid((unsigned)((a.plane + P - 1) / P), (unsigned)a.groups, (unsigned)(a.fields > 1 ? a.fields : 1));
+        const int kr = support_rows(a, 8, 128);
+        if (kr <= 1) hipLaunchKernelGGL((axis0_rs_kernel<1024, P, 0, 1, true, 8, 8, 4, 4>), grid, dim3(128 * P), 0, s, a);
+        else if (kr <= 2) hipLaunchKernelGGL((axis0_rs_kernel<1024, P, 0, 2, true, 8, 8, 4, 4>), grid, dim3(128 * P), 0, s, a);
+        else hipLaunchKernelGGL((axis0_rs_kernel<1024, P, 0, 8, true, 8, 8, 4, 4>), grid, dim3(128 * P), 0, s, a);
+        return hipGetLastError();
+    }
     if ((a.n == 512 && a.mode == 0) || a.n == 192 || a.n == 160 || a.n == 96) {
         // register-resident stages: 512 = 16 x 8 x 4, 192 = 12 x 4 x 4, 160 = 20 x 4 x 2, 96 = 12 x 4 x 2
         // (the adjoint accumulation at 512 keeps the LDS-staged kernel: its registers would spill)
@@ -747,15 +806,15 @@ hipError_t launch_axis0(const Axis0Args &a, hipStream_t s) {
             if constexpr (M == 0) {
                 if (a.n == 512) {
                     const int kr = support_rows(a, 16, 32);
-                    if (kr <= 1) hipLaunchKernelGGL((axis0_rs_kernel<512, P, 0, 1, 16, 8, 4>), grid, dim3(32 * P), 0, s, a);
-                    else if (kr <= 2) hipLaunchKernelGGL((axis0_rs_kernel<512, P, 0, 2, 16, 8, 4>), grid, dim3(32 * P), 0, s, a);
-                    else hipLaunchKernelGGL((axis0_rs_kernel<512, P, 0, 16, 16, 8, 4>), grid, dim3(32 * P), 0, s, a);
+                    if (kr <= 1) hipLaunchKernelGGL((axis0_rs_kernel<512, P, 0, 1, false, 16, 8, 4>), grid, dim3(32 * P), 0, s, a);
+                    else if (kr <= 2) hipLaunchKernelGGL((axis0_rs_kernel<512, P, 0, 2, false, 16, 8, 4>), grid, dim3(32 * P), 0, s, a);
+                    else hipLaunchKernelGGL((axis0_rs_kernel<512, P, 0, 16, false, 16, 8, 4>), grid, dim3(32 * P), 0, s, a);
                     return;
                 }
             }
-            if (a.n == 192) hipLaunchKernelGGL((axis0_rs_kernel<192, P, M, 12, 12, 4, 4>), grid, dim3(16 * P), 0, s, a);
-            else if (a.n == 160) hipLaunchKernelGGL((axis0_rs_kernel<160, P, M, 20, 20, 4, 2>), grid, dim3(8 * P), 0, s, a);
-            else hipLaunchKernelGGL((axis0_rs_kernel<96, P, M, 12, 12, 4, 2>), grid, dim3(8 * P), 0, s, a);
+            if (a.n == 192) hipLaunchKernelGGL((axis0_rs_kernel<192, P, M, 12, false, 12, 4, 4>), grid, dim3(16 * P), 0, s, a);
+            else if (a.n == 160) hipLaunchKernelGGL((axis0_rs_kernel<160, P, M, 20, false, 20, 4, 2>), grid, dim3(8 * P), 0, s, a);
+            else hipLaunchKernelGGL((axis0_rs_kernel<96, P, M, 12, false, 12, 4, 2>), grid, dim3(8 * P), 0, s, a);
         };
         if (a.mode == 1) go(std::integral_constant<int, 1>{});
         else go(std::integral_constant<int, 0>{});
@@ -821,9 +880,9 @@ bool fft_supported(int n) {
 int fft_num_variants(int n) {
     // 0, 1: one tile per workgroup (two shapes where defined); 2, 3: persistent, 4 / 16 tiles;
     // 4, 5 (lengths 64-256): persistent with few, wide radix stages; 6 to 9 (64, 128, 256; 6, 7
-    // at 512): register-resident along a strided axis
+    // at 512 and 1024): register-resident along a strided axis
     if (n == 256 || n == 128 || n == 64) return 10;
-    if (n == 512) return 8;
+    if (n == 512 || n == 1024) return 8;
     return (n == 192 || n == 160 || n == 96) ? 6 : 4;
 }
 

@@ -337,13 +337,12 @@ __device__ __forceinline__ double wave_sum64(double v) {
     X(256, 16, 256, 16, 16) X(512, 64, 512, 8, 8, 8) X(1024, 128, 512, 8, 8, 4, 4)
 
 // Threads per pencil of the fused last pass (the axis-0 pass uses SB_FUSED_CONFIGS):
-// at most 512 threads per workgroup for up to 16 bins.  1024 has no fused last pass (a tile of
-// all bins of a row would not fit the LDS): its 3PCFs run the plain last pass and the pair
-// contraction.
+// at most 512 threads per workgroup for up to 16 bins, except 1024 (64 threads per pencil, up
+// to 1024 per workgroup, register-resident 16 x 16 x 4 stages with one exchange buffer).
 #define SB_LAST_CONFIGS(X)                                                                   \
     X(8, 1, 8) X(12, 1, 4, 3) X(16, 4, 4, 4) X(24, 2, 4, 2, 3) X(32, 4, 4, 8) X(48, 4, 4, 4, 3) \
     X(64, 8, 8, 8) X(96, 8, 4, 4, 2, 3) X(128, 16, 8, 8, 2) X(160, 8, 4, 4, 2, 5)              \
-    X(192, 16, 4, 4, 4, 3) X(256, 32, 8, 8, 4) X(512, 32, 8, 8, 8)
+    X(192, 16, 4, 4, 4, 3) X(256, 32, 8, 8, 4) X(512, 32, 8, 8, 8) X(1024, 64, 16, 16, 4)
 
 // Fused last pass + contraction for one length (defined in fft_last_*.hip), and the
 // rows per tile it needs for nb bins.

@@ -533,7 +533,11 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
     constexpr int CSB = (NSTAGE - 1) % 2;       // buffer the last stage does not read
     constexpr int WPT = (N + NT - 1) / NT;
     static_assert(NT % 64 == 0 && NSTAGE >= 2, "whole waves, two stages or more");
-    __shared__ float2 ex[2][N * PITCH];
+    // ONE: a single exchange buffer, which the [cell][bin] view then reuses (one more barrier per
+    // row), where two would not fit the LDS (1024 points)
+    constexpr bool ONE = 2 * N * PITCH * sizeof(float2) + N * (sizeof(float2) + sizeof(float)) > 160 * 1024;
+    __shared__ float2 ex[ONE ? 1 : 2][N * PITCH];
+    float2 *ex1 = ex[ONE ? 0 : 1];
     __shared__ float2 tw[N];
     __shared__ float wsm[N];
     const int nb = a.nb;
@@ -556,20 +560,28 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
             wdst[e] = c < N ? a.w[row * N + c] : 0.f;
         }
     };
-    float2 nx[R0];
-    float nw[WPT];
-    if (r_begin < r_end) load_row(r_begin, nx, nw);
+    // PF: the next row's loads are in flight during this row (registers allow it except for the
+    // 1024-point tiles of more than 8 bins, where the other waves of the workgroup cover them)
+    constexpr bool PF = !ONE || NBT <= 8;
+    float2 nx[PF ? R0 : 1];
+    float nw[PF ? WPT : 1];
+    if (PF && r_begin < r_end) load_row(r_begin, nx, nw);
     for (int64_t row = r_begin; row < r_end; ++row) {
         float2 v[R0];
-#pragma unroll
-        for (int r = 0; r < R0; ++r) v[r] = nx[r];
         float wv[WPT];
+        if constexpr (PF) {
 #pragma unroll
-        for (int e = 0; e < WPT; ++e) wv[e] = nw[e];
-        if (row + 1 < r_end) load_row(row + 1, nx, nw);    // next row in flight
+            for (int r = 0; r < R0; ++r) v[r] = nx[r];
+#pragma unroll
+            for (int e = 0; e < WPT; ++e) wv[e] = nw[e];
+            if (row + 1 < r_end) load_row(row + 1, nx, nw);    // next row in flight
+        } else {
+            load_row(row, v, wv);
+        }
         __syncthreads();                                    // the previous row's pair sums are done
-        reg_stages<N, 1, R0, REST...>(v, ex[0], ex[1], tw, q, pp, PITCH);
-        float2 *cs = ex[CSB];
+        reg_stages<N, 1, R0, REST...>(v, ex[0], ex1, tw, q, pp, PITCH);
+        float2 *cs = ex[ONE ? 0 : CSB];
+        if constexpr (ONE) __syncthreads();                 // the last stage has read the buffer
 #pragma unroll
         for (int r = 0; r < R0; ++r) cs[(q + T * r) * PITCH + pp] = v[r];
 #pragma unroll

@@ -683,7 +683,8 @@ static sb_status fused_3pcf(sb_plan *p, const ShapeGroup &G, const void *const *
     if (nf > 1 && p->chunk_groups < p->nlm) return fail(SB_EUNSUPPORTED, "fields batched with chunked kernel groups");
     sb_status st = density_spectrum(p, G, deltas, nf, s);
     if (st != SB_OK) return st;
-    // lengths without a fused last pass (1024) run the plain last pass and the pair contraction
+    // bin counts without a fused last pass (more than 12 bins on a 1024-point last axis) run the
+    // plain last pass and the pair contraction
     const bool fused_last = G.rows > 0;
     const int64_t nrows = G.ng / G.n[nd - 1];
     const int nblocks = fused_last ? (int)((nrows + G.rows_per_block - 1) / G.rows_per_block)

@@ -129,9 +129,12 @@ struct sb_plan {
     bool adj_fused = true;        // adjoint: last pass fused with the adjoint weights (SB_FLAG_UNFUSED clears it)
     int quad_tile = 32, proj4_tile = 64;
     std::map<std::pair<int, int>, int> fft_var;   // (length, axis) -> variant
+    // untuned default: variant 0, except the register-resident 16-pencil pass along a strided axis
+    // of length 1024 (about 3x the LDS-staged pass there, where autotuning takes long)
     int fft_variant(int n, int axis) const {
         auto it = fft_var.find({n, axis});
-        return it == fft_var.end() ? 0 : it->second;
+        if (it != fft_var.end()) return it->second;
+        return n == 1024 && axis < prob.ndim - 1 ? 6 : 0;
     }
     // per-launch timing
     bool timing = false;

@@ -257,7 +257,7 @@ def test_every_fft_variant(sb, shape):
 
 
 @pytest.mark.parametrize("shape", [(512, 8, 16), (8, 16, 512), (64, 16, 128), (160, 8, 192), (96, 8, 160),
-                                   (192, 8, 96)])
+                                   (192, 8, 96), (1024, 8, 16), (8, 8, 1024)])
 def test_long_axes(sb, shape):
     # axis lengths of 512 (the three-stage register-resident forms) and the 64 / 128 pairs,
     # each on the axis-0 pass and on the fused last pass
@@ -268,6 +268,31 @@ def test_long_axes(sb, shape):
     ref = oracle.zeta3_full(d.astype(np.float64), edges, 3).real
     check(z[0], ref, TOL32, say)
     plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_fused_last_pass_1024(sb, precision):
+    # a last axis of 1024 points: the register-resident fused last pass with one exchange buffer,
+    # at 10 bins (12-bin tiles) with the packed m = 0 groups (real and packed pair sums), and its
+    # regenerated-kernel form
+    say(f"case: 8 x 16 x 1024 full 3PCF, 10 bins to 5, lmax 2, {precision}; the same regenerated")
+    d = lognormal_field((8, 16, 1024), seed=43, sigma=1.0)
+    edges = linear_edges(5, 10)
+    ref = oracle.zeta3_full(d.astype(np.float64), edges, 2).real
+    tol = TOL_SPLIT if precision == "split_bf16" else TOL32
+    for regen in (False, True):
+        plan, dev, z = run_plan(sb, [d], edges, 2, precision=precision, regen_kernels=regen)
+        check(z[0], ref, tol, say, f"regenerated {regen}: ")
+        plan.close()
+
+
+def test_fused_last_pass_1024_projected(sb):
+    # the complex pair sums of the projected 3PCF on a 1024-point last axis (12-bin tiles)
+    say("case: 16 x 1024 projected 3PCF, 9 bins to 9, mmax 4")
+    d = lognormal_field((16, 1024), seed=44, sigma=1.0)
+    edges = linear_edges(9, 9)
+    _, _, z3 = run_plan(sb, [d], edges, 4, npcf=3)
+    check(z3[0], oracle.zeta3_proj(d.astype(np.float64), edges, 4), TOL32, say, "proj3: ")
 
 
 def test_call_order_and_argument_errors(sb):
@@ -617,7 +642,7 @@ def test_regenerated_kernels_match_cached(sb, shape, nbins, lmax, limit_groups):
                                         ((1024, 16), 3), ((8, 8, 1024), 4), ((16, 1024), 4)])
 def test_axes_of_1024(sb, shape, npcf):
     # transforms of length 1024 on every axis: the axis-0 correlation pass, the middle pass, and the
-    # plain last pass followed by the pair contraction (no fused last pass at this length)
+    # last pass (fused with the pair sums for the 3PCF; the 4PCF's plain pass)
     say(f"case: {shape} npcf {npcf}, 4 bins to 4, lmax 3")
     d = lognormal_field(shape, seed=44, sigma=1.0)
     edges = linear_edges(4, 4)
@@ -629,7 +654,7 @@ def test_axes_of_1024(sb, shape, npcf):
         ref = oracle.zeta3_proj(d64, edges, 3) if npcf == 3 else oracle.zeta4_proj(d64, edges, 3)[1]
     check(z[0], ref, TOL32, say)
     if npcf == 3 and len(shape) == 3 and shape[2] == 1024:
-        with pytest.raises(Exception):   # the fused adjoint has no last pass at 1024
+        with pytest.raises(Exception):   # the adjoint has no last pass at 1024
             plan.backward(dev, torch.zeros((1, 4, 4, 4), dtype=torch.float64, device="cuda"))
     plan.close()
 
