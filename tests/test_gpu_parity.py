@@ -270,13 +270,14 @@ def test_long_axes(sb, shape):
     plan.close()
 
 
+@pytest.mark.parametrize("n", [512, 1024])
 @pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
-def test_fused_last_pass_1024(sb, precision):
-    # a last axis of 1024 points: the register-resident fused last pass with one exchange buffer,
-    # at 10 bins (12-bin tiles) with the packed m = 0 groups (real and packed pair sums), and its
-    # regenerated-kernel form
-    say(f"case: 8 x 16 x 1024 full 3PCF, 10 bins to 5, lmax 2, {precision}; the same regenerated")
-    d = lognormal_field((8, 16, 1024), seed=43, sigma=1.0)
+def test_fused_last_pass_long(sb, precision, n):
+    # a last axis of 512 or 1024 points: the register-resident fused last pass with one exchange
+    # buffer, at 10 bins (12-bin tiles) with the packed m = 0 groups (real and packed pair sums),
+    # and its regenerated-kernel form
+    say(f"case: 8 x 16 x {n} full 3PCF, 10 bins to 5, lmax 2, {precision}; the same regenerated")
+    d = lognormal_field((8, 16, n), seed=43, sigma=1.0)
     edges = linear_edges(5, 10)
     ref = oracle.zeta3_full(d.astype(np.float64), edges, 2).real
     tol = TOL_SPLIT if precision == "split_bf16" else TOL32
@@ -286,10 +287,11 @@ def test_fused_last_pass_1024(sb, precision):
         plan.close()
 
 
-def test_fused_last_pass_1024_projected(sb):
-    # the complex pair sums of the projected 3PCF on a 1024-point last axis (12-bin tiles)
-    say("case: 16 x 1024 projected 3PCF, 9 bins to 9, mmax 4")
-    d = lognormal_field((16, 1024), seed=44, sigma=1.0)
+@pytest.mark.parametrize("n", [512, 1024])
+def test_fused_last_pass_long_projected(sb, n):
+    # the complex pair sums of the projected 3PCF on a 512- or 1024-point last axis (12-bin tiles)
+    say(f"case: 16 x {n} projected 3PCF, 9 bins to 9, mmax 4")
+    d = lognormal_field((16, n), seed=44, sigma=1.0)
     edges = linear_edges(9, 9)
     _, _, z3 = run_plan(sb, [d], edges, 4, npcf=3)
     check(z3[0], oracle.zeta3_proj(d.astype(np.float64), edges, 4), TOL32, say, "proj3: ")
