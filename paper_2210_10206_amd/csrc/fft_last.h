@@ -79,7 +79,14 @@ struct PairSums {
     static_assert(NBT >= 1 && NBT <= 16, "at most 16 bins");
     static constexpr int red_doubles(int nw) { return nw * NOUT * NPB * 16; }
     static constexpr int NV = NACC * NPB * 4;         // accumulator values per lane
-    static constexpr int NT2 = (NV + 1) / 2;          // float64 totals per lane (see flush)
+    // The slots of lanes that differ only in the folded lane bits add into the same sums: all 16
+    // slots (bits 2-5), or for PS_PACKED the 8 slots of one part (bits 3-5).  A flush folds those
+    // lanes' values into float64 totals spread over them: NT2 totals per lane (see flush).
+    static constexpr int FB0 = MODE == PS_PACKED ? 3 : 2;   // first folded lane bit
+    static constexpr int NFB = 6 - FB0;                      // folded lane bits
+    static constexpr int GS = 1 << NFB;                      // lanes sharing a sum
+    static constexpr int NVP = (NV + GS - 1) / GS * GS;      // values per lane, padded to GS
+    static constexpr int NT2 = NVP / GS;                     // float64 totals per lane
     double tot[NT2];
     f4v acc[NACC][NPB];                               // float32 sums since the last flush
 
@@ -168,30 +175,49 @@ struct PairSums {
         }
     }
 
-    // Lane distance of the fold in flush: lanes l and l ^ FOLD always end up in the same sum
-    // (the two part slots of a cell, or for PS_PACKED two cells of the same part).
-    static constexpr int FOLD = MODE == PS_PACKED ? 8 : 4;
-
-    // Adds the float32 sums to the float64 totals and clears them.  The slots of lanes l and
-    // l ^ FOLD are folded here so that each lane keeps half of the values (value 2 m on lanes
-    // with the FOLD bit clear, 2 m + 1 on the others).
+    // Adds the float32 sums to the float64 totals and clears them.  Recursive halving over the
+    // folded lane bits: at bit FB0 + s a lane keeps the half of its values that the bit selects
+    // and adds the partner lane's values of that half, so after NFB steps it holds NT2 sums, each
+    // over all GS lanes of its group: value index k + sum_s bit_s NVP / 2^(s+1) (value_index).
     __device__ __forceinline__ void flush(int lane) {
-        const bool odd = (lane & FOLD) != 0;
-        float flat[2 * NT2];
+        float flat[NVP];
 #pragma unroll
         for (int u = 0; u < NACC; ++u)
 #pragma unroll
             for (int p = 0; p < NPB; ++p)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) flat[(u * NPB + p) * 4 + r] = acc[u][p][r];
-        if constexpr (NV % 2 != 0) flat[NV] = 0.f;
 #pragma unroll
-        for (int m = 0; m < NT2; ++m) {
-            const float send = odd ? flat[2 * m] : flat[2 * m + 1];
-            const float keep = odd ? flat[2 * m + 1] : flat[2 * m];
-            tot[m] += (double)(keep + __shfl_xor(send, FOLD));
-        }
+        for (int v = NV; v < NVP; ++v) flat[v] = 0.f;
+        halve<0>(flat, lane);
+#pragma unroll
+        for (int k = 0; k < NT2; ++k) tot[k] += (double)flat[k];
         clear_acc();
+    }
+
+    // one halving step of flush (compile-time lengths, so flat stays in registers)
+    template <int ST>
+    __device__ __forceinline__ static void halve(float *flat, int lane) {
+        if constexpr (ST < NFB) {
+            constexpr int HALF = NVP >> (ST + 1);
+            const bool up = ((lane >> (FB0 + ST)) & 1) != 0;
+#pragma unroll
+            for (int k = 0; k < HALF; ++k) {
+                const float keep = up ? flat[HALF + k] : flat[k];
+                const float send = up ? flat[k] : flat[HALF + k];
+                flat[k] = keep + __shfl_xor(send, 1 << (FB0 + ST));
+            }
+            halve<ST + 1>(flat, lane);
+        }
+    }
+
+    // Value index (into the flattened (accumulator set, pair, r) values) of this lane's total 0.
+    __device__ __forceinline__ static int value_index(int lane) {
+        int v = 0;
+#pragma unroll
+        for (int st = 0; st < NFB; ++st)
+            if ((lane >> (FB0 + st)) & 1) v += NVP >> (st + 1);
+        return v;
     }
 
     // One tile added and flushed.
@@ -202,25 +228,20 @@ struct PairSums {
         flush(lane);
     }
 
-    // Sum the cells of the slots (lanes 8 c + 4 s + j, fixed butterfly over c) and write this
-    // wave's totals to red[((wave * NOUT + part) * NPB + p) * 16 + r * 4 + j]; call with the
-    // whole block.  PS_REAL, PS_COMPLEX: lanes 0..3 end with the values 2 m, lanes 4..7 with
-    // the values 2 m + 1 (flattened (part, pair, r)).  PS_PACKED: lanes 4 s + 8 h + j end with
-    // value 2 m + h of part s.
+    // Writes this wave's totals to red[((wave * NOUT + part) * NPB + p) * 16 + r * 4 + j] (lane j
+    // of a block holds column j; part: the accumulator set, or for PS_PACKED the lane's slot part).
+    // Each (part, pair, r, j) is held by exactly one lane of the wave after the flushes.
     __device__ __forceinline__ void to_lds(double *red, int wave, int lane) {
+        const int j = lane & 3;
+        const int v0 = value_index(lane);
+        const int lane_part = MODE == PS_PACKED ? (lane >> 2) & 1 : 0;
 #pragma unroll
-        for (int m = 0; m < NT2; ++m) {
-            double v = tot[m];
-            if constexpr (MODE != PS_PACKED) v += __shfl_xor(v, 8);
-            v += __shfl_xor(v, 16);
-            v += __shfl_xor(v, 32);
-            if constexpr (MODE == PS_PACKED) {
-                const int i = 2 * m + ((lane >> 3) & 1);                // (pair, r) within the part
-                const int idx = ((lane >> 2) & 1) * NV + i;
-                if (lane < 16 && i < NV) red[(wave * 2 * NV + idx) * 4 + (lane & 3)] = v;
-            } else {
-                const int idx = 2 * m + ((lane >> 2) & 1);   // flattened (part, pair, r)
-                if (lane < 8 && idx < NV) red[(wave * NV + idx) * 4 + (lane & 3)] = v;
+        for (int k = 0; k < NT2; ++k) {
+            const int v = v0 + k;
+            if (v < NV) {
+                const int u = v / (NPB * 4), p = (v / 4) % NPB, r = v % 4;
+                const int part = MODE == PS_PACKED ? lane_part : u;
+                red[((wave * NOUT + part) * NPB + p) * 16 + r * 4 + j] = tot[k];
             }
         }
     }
@@ -349,7 +370,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // that the threads of a pencil read adjacent entries, and the pair sums are flushed to float64
 // every FLUSH (8) rows.
 template <int R1, int R2, int NBT, int MODE, int PREC>
-__global__ __launch_bounds__(NBT * R2, 3) void last_reg_kernel(LastArgs a) {
+__global__ __launch_bounds__(NBT * R2, NBT <= 12 ? 4 : 3) void last_reg_kernel(LastArgs a) {
     a.in += (int64_t)blockIdx.z * a.in_fs;   // field of the launch (grid.z)
     a.w += (int64_t)blockIdx.z * a.w_fs;
     a.partial += (int64_t)blockIdx.z * a.part_fs;
