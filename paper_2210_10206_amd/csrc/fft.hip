@@ -728,6 +728,43 @@ hipError_t launch_fft_pass(const FftPass &a, hipStream_t s) {
             }
             return hipGetLastError();
         }
+        if (a.n == 96 || a.n == 160 || a.n == 192) {
+            // three-stage forms (96 = 12 x 4 x 2, 160 = 20 x 4 x 2, 192 = 12 x 4 x 4): 32 pencils
+            // (16 where the stride allows no more) for 6, 16 for 7, 64 (or fewer) for 8 and 9;
+            // variant 9 keeps the next tile's loads in flight
+            const int pw = v == 7 ? 16 : (v >= 8 && a.stride % 64 == 0) ? 64 : a.stride % 32 == 0 ? 32 : 16;
+            auto go = [&](auto p_c, auto pf_c) {
+                constexpr int P = decltype(p_c)::value;
+                constexpr bool PF = decltype(pf_c)::value;
+                const int64_t ntile = (a.ng / a.n + P - 1) / P;
+                dim3 grid((unsigned)((ntile + tiles - 1) / tiles), (unsigned)a.batch);
+                auto l3 = [&](auto kern, int t) { hipLaunchKernelGGL(kern, grid, dim3(P * t), 0, s, a, tiles); };
+                if (a.n == 96) {
+                    if (a.sign < 0) l3(mid_rs_kernel<96, P, -1, PF, 12, 4, 2>, 8);
+                    else l3(mid_rs_kernel<96, P, 1, PF, 12, 4, 2>, 8);
+                } else if (a.n == 160) {
+                    constexpr bool PF160 = PF && P > 16;   // 16 pencils with the prefetch would spill
+                    if (a.sign < 0) l3(mid_rs_kernel<160, P, -1, PF160, 20, 4, 2>, 8);
+                    else l3(mid_rs_kernel<160, P, 1, PF160, 20, 4, 2>, 8);
+                } else {
+                    if (a.sign < 0) l3(mid_rs_kernel<192, P, -1, PF, 12, 4, 4>, 16);
+                    else l3(mid_rs_kernel<192, P, 1, PF, 12, 4, 4>, 16);
+                }
+            };
+            using T_ = std::true_type;
+            using F_ = std::false_type;
+            if (pw == 64) {
+                if (v == 9) go(std::integral_constant<int, 64>{}, T_{});
+                else go(std::integral_constant<int, 64>{}, F_{});
+            } else if (pw == 32) {
+                if (v == 9) go(std::integral_constant<int, 32>{}, T_{});
+                else go(std::integral_constant<int, 32>{}, F_{});
+            } else {
+                if (v == 9) go(std::integral_constant<int, 16>{}, T_{});
+                else go(std::integral_constant<int, 16>{}, F_{});
+            }
+            return hipGetLastError();
+        }
         if (a.n == 1024) {
             // 16 x 16 x 4 in registers, 64 threads per pencil: 16 pencils (1024 threads, 139 KB of LDS)
             // for variant 6, 8 pencils (512 threads) for variant 7
@@ -879,11 +916,11 @@ bool fft_supported(int n) {
 
 int fft_num_variants(int n) {
     // 0, 1: one tile per workgroup (two shapes where defined); 2, 3: persistent, 4 / 16 tiles;
-    // 4, 5 (lengths 64-256): persistent with few, wide radix stages; 6 to 9 (64, 128, 256; 6, 7
-    // at 512 and 1024): register-resident along a strided axis
-    if (n == 256 || n == 128 || n == 64) return 10;
+    // 4, 5 (lengths 64-256): persistent with few, wide radix stages; 6 to 9 (64 - 256; 6, 7 at
+    // 512 and 1024): register-resident along a strided axis
+    if (n == 256 || n == 128 || n == 64 || n == 192 || n == 160 || n == 96) return 10;
     if (n == 512 || n == 1024) return 8;
-    return (n == 192 || n == 160 || n == 96) ? 6 : 4;
+    return 4;
 }
 
 }  // namespace sb

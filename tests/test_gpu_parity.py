@@ -228,7 +228,8 @@ def test_packed_m0_arrays(sb, shape, nbins, lmax):
 
 
 @pytest.mark.parametrize("shape", [(8, 64, 16), (8, 128, 16), (8, 256, 16), (8, 512, 16), (512, 8, 32),
-                                   (8, 1024, 16), (1024, 8, 16), (8, 256, 64), (8, 128, 64), (8, 64, 64)])
+                                   (8, 1024, 16), (1024, 8, 16), (8, 256, 64), (8, 128, 64), (8, 64, 64),
+                                   (8, 160, 64), (8, 192, 32), (8, 96, 16)])
 def test_every_fft_variant(sb, shape):
     # every launch shape of the passes of each axis (what the autotuner may pick) gives the
     # oracle's sums; the middle axis (a plain pass in the forward, kernel-cache and density
