@@ -365,7 +365,8 @@ __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
     const int64_t g = (int64_t)blockIdx.x * P + p;
     const bool ok = g < a.plane;
     // element q + T r of a pencil: the uniform row pointer of r plus the lane's 32-bit byte offset
-    // (q plane + g) * 8 (under 4 GiB: q < T <= 64 and plane <= 2^20 cells)
+    // (q plane + g) * 8 (under 4 GiB: q < T <= 128 and plane <= 2^20 cells, as the plan's edges are
+    // at most 1024)
     const uint32_t lane_off = (uint32_t)(((int64_t)q * a.plane + g) * (int64_t)sizeof(float2));
     auto row = [&](const float2 *base, int r) { return base + (int64_t)(T * r) * a.plane; };
     for (int i = tid; i < N; i += P * T) tw[i] = a.tw[i];
@@ -392,7 +393,7 @@ __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
         auto load_v = [&](int b, float2 *dst) {
             const float2 *vb = a.vin + (int64_t)b * a.ng;
 #pragma unroll
-            for (int r = 0; r < R0; ++r) dst[r] = ok ? vb[(int64_t)(q + T * r) * a.plane + g] : make_float2(0.f, 0.f);
+            for (int r = 0; r < R0; ++r) dst[r] = ok ? *at_bytes(row(vb, r), lane_off) : make_float2(0.f, 0.f);
         };
         float2 acc[R0], nv[R0];
 #pragma unroll
@@ -416,7 +417,7 @@ __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
                 if (ok)
 #pragma unroll
                     for (int r = 0; r < R0; ++r) {
-                        float2 *o = a.out + (int64_t)(q + T * r) * a.plane + g;
+                        float2 *o = at_bytes(const_cast<float2 *>(row(a.out, r)), lane_off);
                         *o = cadd(*o, acc[r]);
                     }
 #pragma unroll
@@ -857,7 +858,8 @@ hipError_t launch_axis0(const Axis0Args &a, hipStream_t s) {
         else go(std::integral_constant<int, 0>{});
         return hipGetLastError();
     }
-    if (a.n == 256 || a.n == 128 || a.n == 64) {
+    // the register-resident kernels of 64-256 address an array by 32-bit byte offsets
+    if ((a.n == 256 || a.n == 128 || a.n == 64) && a.ng * (int64_t)sizeof(float2) <= (int64_t)UINT32_MAX) {
         constexpr int P = 16;
         dim3 grid((unsigned)((a.plane + P - 1) / P), (unsigned)a.groups, (unsigned)(a.fields > 1 ? a.fields : 1));
         auto go = [&](auto mode_c) {
