@@ -97,6 +97,14 @@ enum {
                                  cache of every shape would exceed 64 GiB (1024^3 grids); such plans
                                  have no adjoint (sb_backward returns SB_EUNSUPPORTED) and no packed
                                  m = 0 pairs.  SB_EUNSUPPORTED on other paths */
+    SB_FLAG_HALF_KERNELS = 128u, /* 3D plans: store only the axis-0 planes c_0 = 0 .. r0 of each kernel
+                                 spectrum and take the planes c_0 < 0 from them by parity (the
+                                 kernels Y*_lm Phi_b change by (-1)^l under r -> -r, Sec. 2), on
+                                 the shapes whose support radius r0 is below half of every edge.
+                                 Halves the persistent buffer; each pass still reads as many bytes.
+                                 Chosen automatically when the full cache would exceed 64 GiB and
+                                 with SB_FLAG_REGEN_KERNELS (it halves the planes generated);
+                                 without effect on 2D plans and on the other shapes */
     SB_FLAG_CHECK_FINITE = 32u /* sb_forward / sb_backward / sb_normalize first scan every input array
                                  (densities, and grad_zeta) for NaN and Inf and return SB_ENONFINITE,
                                  with no other work done, when one holds any.  The scan waits for the

@@ -52,6 +52,9 @@ class Plan:
     check_finite: scan the inputs of every call for NaN / Inf first (SB_FLAG_CHECK_FINITE)
     regen_kernels: fused 3PCF: keep no kernel spectra, regenerate them per call in scratch
                  (SB_FLAG_REGEN_KERNELS; automatic when the cache would exceed 64 GiB)
+    half_kernels: 3D: keep only the axis-0 planes c_0 >= 0 of each kernel spectrum and take the
+                 others by parity (SB_FLAG_HALF_KERNELS; automatic when the full cache would exceed
+                 64 GiB, and with regen_kernels); half the persistent buffer, same traffic
     field_batch: fields of one shape per launch of each pass (sb_plan_set_field_batch): None or 0 =
                  as many as 32 GiB of kernel arrays allow, 1 = one launch sequence per field
     """
@@ -59,7 +62,7 @@ class Plan:
     def __init__(self, shapes, bin_edges, lmax, npcf=3, precision="fp32", input_dtype=torch.float32,
                  device=None, stream=None, prepare=True, keep_coeffs=False, fused=True, mfma=True,
                  scratch_limit=None, parity="even", pack=True, check_finite=False, regen_kernels=False,
-                 field_batch=None):
+                 field_batch=None, half_kernels=False):
         self.lib = _lib.load()
         shapes = [tuple(int(x) for x in s) for s in shapes]
         ndim = len(shapes[0])
@@ -80,7 +83,8 @@ class Plan:
                                | (_lib.SB_FLAG_ODD_PARITY if parity == "odd" else 0)
                                | (0 if pack else _lib.SB_FLAG_NO_PACK)
                                | (_lib.SB_FLAG_CHECK_FINITE if check_finite else 0)
-                               | (_lib.SB_FLAG_REGEN_KERNELS if regen_kernels else 0))
+                               | (_lib.SB_FLAG_REGEN_KERNELS if regen_kernels else 0)
+                               | (_lib.SB_FLAG_HALF_KERNELS if half_kernels else 0))
         if parity not in ("even", "odd"):
             raise ValueError("parity must be 'even' or 'odd'")
         self.parity = parity

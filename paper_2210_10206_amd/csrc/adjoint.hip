@@ -192,6 +192,7 @@ sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta
             x.r0 = G.r0;
             x.mode = 1;
             x.kc = khat;
+            mirror_args(p, G, 0, x);
             x.out = acc;
             x.vin = vin;
             x.nb = NB;

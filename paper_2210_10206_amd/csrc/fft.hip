@@ -101,10 +101,68 @@ __device__ __forceinline__ int64_t acc_kernel(const Axis0Args &a, int t) {
     return a.kmap ? (int64_t)a.kmap[t / a.nb] * a.nb + t % a.nb : (int64_t)a.kfirst + t;
 }
 
+// Half store: the in-plane cell of -k for cell g ((i1, i2) -> (-i1, -i2) modulo the extents).
+// (The helpers take scalars: a reference to the kernel's argument copy would keep it in scratch.)
+__device__ __forceinline__ int64_t mirror_cell(int64_t n1, int64_t n2, int64_t g) {
+    const int64_t i1 = g / n2, i2 = g - i1 * n2;
+    return ((n1 - i1) % n1) * n2 + (n2 - i2) % n2;
+}
+
+// Half store: how a kernel of global group g gives a plane c_0 < 0: 0 the stored plane -c_0 at
+// -k, 1 the same negated, 2 the stored plane -c_0 conjugated.
+__device__ __forceinline__ int mirror_rule(int g, int nflip, uint64_t odd_lo, uint64_t odd_hi) {
+    if (g >= nflip) return 2;
+    const uint64_t bits = g < 64 ? odd_lo : odd_hi;
+    return (int)((bits >> (g & 63)) & 1);
+}
+
+// Where a kernel keeps its planes c_0 < 0 (axis-0 indices j in the upper half of the axis): plane
+// pa + pb j, scaled by (sx, sy).  Full store: the stored plane np - n + j as it is (or every plane
+// j when the store is dense, np = n).  Half store: plane n - j = -c_0, at -k (rules 0, 1:
+// mirrored) or at k (rule 2), with the sign or conjugation of mirror_rule.  All uniform.
+struct UpperPlanes {
+    int pa, pb;
+    bool dense, mirrored;
+    float sx, sy;
+    // (bit arithmetic on the rule, not selects over its values: those become a lookup table in
+    // scratch memory)
+    __device__ __forceinline__ UpperPlanes(int half, int rule, int np, int n) {
+        const unsigned neg = (unsigned)rule & 1u, conj = (unsigned)rule >> 1;
+        pa = half ? n : np - n;
+        pb = half ? -1 : 1;
+        dense = !half && np == n;
+        mirrored = half && !conj;
+        sx = __uint_as_float(0x3f800000u | (neg << 31));
+        sy = __uint_as_float(0x3f800000u | ((neg | conj) << 31));
+    }
+};
+
+// Stored-kernel value at axis-0 index j of this thread's cell g (gm: the cell of -k): `upper`
+// (compile-time in the callers) says whether j lies in the upper half of the axis.  Zero outside
+// the support |c_0| <= r0.
+__device__ __forceinline__ float2 kernel_elem(const float2 *kc, int64_t plane, int r0, int j, int n, bool upper, int64_t g,
+                                              int64_t gm, const UpperPlanes &u) {
+    if (!upper) return (j <= r0 || u.dense) ? ld_stream(&kc[(int64_t)j * plane + g]) : make_float2(0.f, 0.f);
+    if (j < n - r0 && !u.dense) return make_float2(0.f, 0.f);
+    const float2 v = ld_stream(&kc[(int64_t)(u.pa + u.pb * j) * plane + (u.mirrored ? gm : g)]);
+    return make_float2(u.sx * v.x, u.sy * v.y);
+}
+
+// The rule of global kernel group grp in an axis-0 launch (0 for a full store).  The groups come
+// from 32-bit arithmetic: a 64-bit division would be a call, whose stack frame puts the kernel's
+// argument copy in scratch memory.
+#define SB_MIRROR_RULE(a, grp) ((a).half ? mirror_rule((grp), (a).nflip, (a).odd_lo, (a).odd_hi) : 0)
+
+// Global kernel group of step t of an accumulation launch (mode 1; see acc_kernel).
+__device__ __forceinline__ int acc_group(const Axis0Args &a, int t) {
+    return a.kgroup0 + (a.kmap ? a.kmap[t / a.nb] : (a.kfirst + t) / a.nb);
+}
+
 template <int N, int TPP, int NT, int... RAD>
 __global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
-    a.dhat += (int64_t)blockIdx.z * a.dhat_fs;   // field of the launch (grid.z)
-    a.out += (int64_t)blockIdx.z * a.out_fs;
+    // field of the launch (grid.z); local pointers, so the argument struct is never written
+    const float2 *dhat0 = a.dhat + (int64_t)blockIdx.z * a.dhat_fs;
+    float2 *out0 = a.out + (int64_t)blockIdx.z * a.out_fs;
     constexpr int P = NT / TPP;
     constexpr int PITCH = P + 1;
     constexpr int EPT = N / TPP;      // tile elements per thread: pencil p, rows q0 + e TPP
@@ -116,33 +174,28 @@ __global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
     const bool ok = g < a.plane;
     for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
     const int64_t kstride = (int64_t)a.np * a.plane;
-    // stored plane of axis-0 row j (-1: outside the kernel support)
-    auto plane_of = [&](int j) -> int {
-        if (a.np == N || j <= a.r0) return j;
-        if (j >= N - a.r0) return a.np - (N - j);
-        return -1;
-    };
-    auto load_kernel = [&](int64_t k, float2 *dst) {
+    const int64_t gm = (a.half && ok) ? mirror_cell(a.n1, a.n2, g) : g;
+    auto load_kernel = [&](int64_t k, int grp, float2 *dst) {
         const float2 *kc = a.kc + k * kstride;
+        const UpperPlanes up(a.half, SB_MIRROR_RULE(a, grp), a.np, N);
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const int pl = plane_of(q0 + e * TPP);
-            dst[e] = (ok && pl >= 0) ? kc[(int64_t)pl * a.plane + g] : make_float2(0.f, 0.f);
-        }
+        for (int e = 0; e < EPT; ++e)   // rows e >= EPT / 2 lie in the upper half of the axis
+            dst[e] = ok ? kernel_elem(kc, a.plane, a.r0, q0 + e * TPP, N, 2 * e >= EPT, g, gm, up) : make_float2(0.f, 0.f);
     };
     float2 nx[EPT];
     if (a.mode == 0) {
         float2 dr[EPT];
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) dr[e] = ok ? a.dhat[(int64_t)(q0 + e * TPP) * a.plane + g] : make_float2(0.f, 0.f);
+        for (int e = 0; e < EPT; ++e) dr[e] = ok ? dhat0[(int64_t)(q0 + e * TPP) * a.plane + g] : make_float2(0.f, 0.f);
         const int64_t kbase = (int64_t)(a.kmap ? a.kmap[blockIdx.y] : blockIdx.y) * a.nb;   // kernel group
+        const int kgrp = a.kgroup0 + (int)(a.kmap ? a.kmap[blockIdx.y] : blockIdx.y);       // its global index
         const int64_t obase = (int64_t)blockIdx.y * a.nb;                                 // output arrays
-        load_kernel(kbase, nx);
+        load_kernel(kbase, kgrp, nx);
         for (int b = 0; b < a.nb; ++b) {
             __syncthreads();
 #pragma unroll
             for (int e = 0; e < EPT; ++e) sm[(q0 + e * TPP) * PITCH + p] = nx[e];
-            if (b + 1 < a.nb) load_kernel(kbase + b + 1, nx);   // in flight during the transforms
+            if (b + 1 < a.nb) load_kernel(kbase + b + 1, kgrp, nx);   // in flight during the transforms
             __syncthreads();
             stages<N, TPP, -1, 1, RAD...>(sm, tw, p, q0, PITCH);
 #pragma unroll
@@ -152,7 +205,7 @@ __global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
             }
             __syncthreads();
             stages<N, TPP, 1, 1, RAD...>(sm, tw, p, q0, PITCH);
-            float2 *out = a.out + (obase + b) * a.ng;
+            float2 *out = out0 + (obase + b) * a.ng;
             if (ok)
 #pragma unroll
                 for (int e = 0; e < EPT; ++e) out[(int64_t)(q0 + e * TPP) * a.plane + g] = sm[(q0 + e * TPP) * PITCH + p];
@@ -170,7 +223,7 @@ __global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
         float2 nv[EPT], kx[EPT];
         const int nt = (a.accgroups > 1 ? a.accgroups : 1) * a.nb;   // (group, bin) steps
         load_v(0, nv);
-        load_kernel(acc_kernel(a, 0), nx);
+        load_kernel(acc_kernel(a, 0), acc_group(a, 0), nx);
         for (int t = 0; t < nt; ++t) {
             __syncthreads();
 #pragma unroll
@@ -180,7 +233,7 @@ __global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
             }
             if (t + 1 < nt) {
                 load_v(t + 1, nv);
-                load_kernel(acc_kernel(a, t + 1), nx);
+                load_kernel(acc_kernel(a, t + 1), acc_group(a, t + 1), nx);
             }
             __syncthreads();
             stages<N, TPP, -1, 1, RAD...>(sm, tw, p, q0, PITCH);
@@ -198,7 +251,7 @@ __global__ __launch_bounds__(NT) void axis0_kernel(Axis0Args a) {
                 if (ok)
 #pragma unroll
                     for (int e = 0; e < EPT; ++e) {
-                        float2 *o = a.out + (int64_t)(q0 + e * TPP) * a.plane + g;
+                        float2 *o = out0 + (int64_t)(q0 + e * TPP) * a.plane + g;
                         *o = cadd(*o, acc[e]);
                     }
 #pragma unroll
@@ -232,8 +285,9 @@ inline int support_rows(const Axis0Args &a, int r1, int r2) {
 // them away.
 template <int R1, int R2, int P, int MODE, int KR>
 __global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void axis0_reg_kernel(Axis0Args a) {
-    a.dhat += (int64_t)blockIdx.z * a.dhat_fs;   // field of the launch (grid.z)
-    a.out += (int64_t)blockIdx.z * a.out_fs;
+    // field of the launch (grid.z); local pointers, so the argument struct is never written
+    const float2 *dhat0 = a.dhat + (int64_t)blockIdx.z * a.dhat_fs;
+    float2 *out0 = a.out + (int64_t)blockIdx.z * a.out_fs;
     constexpr int N = R1 * R2;
     constexpr int T = R1 / R2;   // second-stage butterflies per thread
     static_assert(R1 % R2 == 0, "R2 must divide R1");
@@ -252,8 +306,20 @@ __global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void
         twl[i] = a.tw[((qq + R2 * t) * r) % N];
     }
     const int64_t kstride = (int64_t)a.np * a.plane;
-    auto load_kernel = [&](int64_t k, float2 *dst) {
+    // kernel planes: uniform row pointers plus 32-bit lane offsets (R2 planes of a kernel span
+    // under 4 GiB); the lower rows read plane j = q + R2 r, the upper ones plane pa + pb j at the
+    // cell of k or, mirrored, of -k
+    const uint32_t lane_lo = (uint32_t)q * pb + gb;
+    const uint32_t lane_rev = (uint32_t)(R2 - 1 - q) * pb + gb;
+    const uint32_t lane_mir =
+        (uint32_t)(R2 - 1 - q) * pb + (uint32_t)((a.half && ok) ? mirror_cell(a.n1, a.n2, g) : g) * (uint32_t)sizeof(float2);
+    auto load_kernel = [&](int64_t k, int grp, float2 *dst) {
         const float2 *kc = a.kc + k * kstride;
+        const UpperPlanes up(a.half, SB_MIRROR_RULE(a, grp), a.np, N);
+        // copies first: a conditional over the captured variables themselves would select their
+        // addresses and keep them (and the whole capture) in scratch memory
+        const uint32_t llo = lane_lo, lrev = lane_rev, lmir = lane_mir;
+        const uint32_t lane_hi = up.pb > 0 ? llo : (up.mirrored ? lmir : lrev);
 #pragma unroll
         for (int r = 0; r < R1; ++r) {
             if (r > KR && r < R1 - KR) {
@@ -261,8 +327,15 @@ __global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void
                 continue;
             }
             const int j = q + R2 * r;
-            const int pl = (a.np == N || j <= a.r0) ? j : (j >= N - a.r0 ? a.np - (N - j) : -1);
-            dst[r] = (ok && pl >= 0) ? ld_stream(at_bytes(kc, (uint32_t)pl * pb + gb)) : make_float2(0.f, 0.f);
+            if (2 * r < R1) {
+                dst[r] = (ok && (j <= a.r0 || up.dense)) ? ld_stream(at_bytes(kc + (int64_t)(R2 * r) * a.plane, lane_lo))
+                                                           : make_float2(0.f, 0.f);
+            } else {
+                const int p0 = up.pb > 0 ? up.pa + R2 * r : up.pa - R2 * r - (R2 - 1);   // lowest plane of the row
+                const float2 v = (ok && (j >= N - a.r0 || up.dense)) ? ld_stream(at_bytes(kc + (int64_t)p0 * a.plane, lane_hi))
+                                                                     : make_float2(0.f, 0.f);
+                dst[r] = make_float2(up.sx * v.x, up.sy * v.y);
+            }
         }
     };
     // one transform: radix-R1 DFT of the own rows, exchange, twiddle, radix-R2 DFTs -> own rows
@@ -301,12 +374,12 @@ __global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void
         for (int r = 0; r < R1; ++r) acc[r] = make_float2(0.f, 0.f);
         const int nt = (a.accgroups > 1 ? a.accgroups : 1) * a.nb;   // (group, bin) steps
         load_v(0, nv);
-        load_kernel(acc_kernel(a, 0), nx);
+        load_kernel(acc_kernel(a, 0), acc_group(a, 0), nx);
         for (int t = 0; t < nt; ++t) {
             float2 v[R1], k[R1];
 #pragma unroll
             for (int r = 0; r < R1; ++r) { v[r] = nv[r]; k[r] = nx[r]; }
-            if (t + 1 < nt) { load_v(t + 1, nv); load_kernel(acc_kernel(a, t + 1), nx); }
+            if (t + 1 < nt) { load_v(t + 1, nv); load_kernel(acc_kernel(a, t + 1), acc_group(a, t + 1), nx); }
             transform(v, ex, std::integral_constant<int, -1>{});
             transform(k, ex, std::integral_constant<int, -1>{});
 #pragma unroll
@@ -315,7 +388,7 @@ __global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void
                 if (ok)
 #pragma unroll
                     for (int r = 0; r < R1; ++r) {
-                        float2 *o = at_bytes(a.out, (uint32_t)(q + R2 * r) * pb + gb);
+                        float2 *o = at_bytes(out0, (uint32_t)(q + R2 * r) * pb + gb);
                         *o = cadd(*o, acc[r]);
                     }
 #pragma unroll
@@ -326,20 +399,21 @@ __global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void
     }
     float2 dr[R1];
 #pragma unroll
-    for (int r = 0; r < R1; ++r) dr[r] = ok ? *at_bytes(a.dhat, (uint32_t)(q + R2 * r) * pb + gb) : make_float2(0.f, 0.f);
+    for (int r = 0; r < R1; ++r) dr[r] = ok ? *at_bytes(dhat0, (uint32_t)(q + R2 * r) * pb + gb) : make_float2(0.f, 0.f);
     const int64_t kbase = (int64_t)(a.kmap ? a.kmap[blockIdx.y] : blockIdx.y) * a.nb;   // kernel group
+    const int kgrp = a.kgroup0 + (int)(a.kmap ? a.kmap[blockIdx.y] : blockIdx.y);       // its global index
     const int64_t obase = (int64_t)blockIdx.y * a.nb;                                 // output arrays
-    load_kernel(kbase, nx);
+    load_kernel(kbase, kgrp, nx);
     for (int b = 0; b < a.nb; ++b) {
         float2 v[R1];
 #pragma unroll
         for (int r = 0; r < R1; ++r) v[r] = nx[r];
-        if (b + 1 < a.nb) load_kernel(kbase + b + 1, nx);   // in flight during the transforms
+        if (b + 1 < a.nb) load_kernel(kbase + b + 1, kgrp, nx);   // in flight during the transforms
         transform(v, ex, std::integral_constant<int, -1>{});
 #pragma unroll
         for (int r = 0; r < R1; ++r) v[r] = cmul(v[r], dr[r]);
         transform(v, ex, std::integral_constant<int, 1>{});
-        float2 *out = a.out + (obase + b) * a.ng;
+        float2 *out = out0 + (obase + b) * a.ng;
         if (ok)
 #pragma unroll
             for (int r = 0; r < R1; ++r) st_stream(at_bytes(out, (uint32_t)(q + R2 * r) * pb + gb), v[r]);
@@ -353,8 +427,9 @@ __global__ __launch_bounds__(P * R2, MODE == 0 ? (2 * KR < R1 ? 3 : 2) : 1) void
 // compact kernel support can reach (KR >= R0 / 2: all rows).
 template <int N, int P, int MODE, int KR, bool ONE, int R0, int... REST>
 __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
-    a.dhat += (int64_t)blockIdx.z * a.dhat_fs;   // field of the launch (grid.z)
-    a.out += (int64_t)blockIdx.z * a.out_fs;
+    // field of the launch (grid.z); local pointers, so the argument struct is never written
+    const float2 *dhat0 = a.dhat + (int64_t)blockIdx.z * a.dhat_fs;
+    float2 *out0 = a.out + (int64_t)blockIdx.z * a.out_fs;
     constexpr int T = N / R0;
     constexpr int PITCH = P + 1;
     __shared__ float2 ex[ONE ? 1 : 2][N * PITCH];   // ONE: a single exchange buffer
@@ -371,8 +446,21 @@ __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
     auto row = [&](const float2 *base, int r) { return base + (int64_t)(T * r) * a.plane; };
     for (int i = tid; i < N; i += P * T) tw[i] = a.tw[i];
     const int64_t kstride = (int64_t)a.np * a.plane;
-    auto load_kernel = [&](int64_t k, float2 *dst) {
+    // kernel planes as in axis0_reg_kernel: the lower rows read plane j = q + T r, the upper ones
+    // plane pa + pb j, from uniform row pointers plus 32-bit lane offsets
+    const uint32_t kpb = (uint32_t)a.plane * (uint32_t)sizeof(float2);
+    const uint32_t gbk = (uint32_t)g * (uint32_t)sizeof(float2);
+    const uint32_t lane_lo = (uint32_t)q * kpb + gbk;
+    const uint32_t lane_rev = (uint32_t)(T - 1 - q) * kpb + gbk;
+    const uint32_t lane_mir =
+        (uint32_t)(T - 1 - q) * kpb + (uint32_t)((a.half && ok) ? mirror_cell(a.n1, a.n2, g) : g) * (uint32_t)sizeof(float2);
+    auto load_kernel = [&](int64_t k, int grp, float2 *dst) {
         const float2 *kc = a.kc + k * kstride;
+        const UpperPlanes up(a.half, SB_MIRROR_RULE(a, grp), a.np, N);
+        // copies first: a conditional over the captured variables themselves would select their
+        // addresses and keep them (and the whole capture) in scratch memory
+        const uint32_t llo = lane_lo, lrev = lane_rev, lmir = lane_mir;
+        const uint32_t lane_hi = up.pb > 0 ? llo : (up.mirrored ? lmir : lrev);
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             if (r > KR && r < R0 - KR) {
@@ -380,8 +468,15 @@ __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
                 continue;
             }
             const int j = q + T * r;
-            const int pl = (a.np == N || j <= a.r0) ? j : (j >= N - a.r0 ? a.np - (N - j) : -1);
-            dst[r] = (ok && pl >= 0) ? ld_stream(&kc[(int64_t)pl * a.plane + g]) : make_float2(0.f, 0.f);
+            if (2 * r < R0) {
+                dst[r] = (ok && (j <= a.r0 || up.dense)) ? ld_stream(at_bytes(kc + (int64_t)(T * r) * a.plane, lane_lo))
+                                                           : make_float2(0.f, 0.f);
+            } else {
+                const int p0 = up.pb > 0 ? up.pa + T * r : up.pa - T * r - (T - 1);   // lowest plane of the row
+                const float2 v = (ok && (j >= N - a.r0 || up.dense)) ? ld_stream(at_bytes(kc + (int64_t)p0 * a.plane, lane_hi))
+                                                                     : make_float2(0.f, 0.f);
+                dst[r] = make_float2(up.sx * v.x, up.sy * v.y);
+            }
         }
     };
     float2 nx[R0];
@@ -400,13 +495,13 @@ __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
         for (int r = 0; r < R0; ++r) acc[r] = make_float2(0.f, 0.f);
         const int nt = (a.accgroups > 1 ? a.accgroups : 1) * a.nb;   // (group, bin) steps
         load_v(0, nv);
-        load_kernel(acc_kernel(a, 0), nx);
+        load_kernel(acc_kernel(a, 0), acc_group(a, 0), nx);
         __syncthreads();   // twiddle table
         for (int t = 0; t < nt; ++t) {
             float2 v[R0], k[R0];
 #pragma unroll
             for (int r = 0; r < R0; ++r) { v[r] = nv[r]; k[r] = nx[r]; }
-            if (t + 1 < nt) { load_v(t + 1, nv); load_kernel(acc_kernel(a, t + 1), nx); }
+            if (t + 1 < nt) { load_v(t + 1, nv); load_kernel(acc_kernel(a, t + 1), acc_group(a, t + 1), nx); }
             if constexpr (ONE) __syncthreads();   // the previous transform has read the buffer
             reg_stages<N, -1, R0, REST...>(v, ex[0], ex1, tw, q, p, PITCH);
             if constexpr (ONE) __syncthreads();
@@ -417,7 +512,7 @@ __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
                 if (ok)
 #pragma unroll
                     for (int r = 0; r < R0; ++r) {
-                        float2 *o = at_bytes(const_cast<float2 *>(row(a.out, r)), lane_off);
+                        float2 *o = at_bytes(const_cast<float2 *>(row(out0, r)), lane_off);
                         *o = cadd(*o, acc[r]);
                     }
 #pragma unroll
@@ -428,23 +523,24 @@ __global__ __launch_bounds__(P * (N / R0)) void axis0_rs_kernel(Axis0Args a) {
     }
     float2 dr[R0];
 #pragma unroll
-    for (int r = 0; r < R0; ++r) dr[r] = ok ? *at_bytes(row(a.dhat, r), lane_off) : make_float2(0.f, 0.f);
+    for (int r = 0; r < R0; ++r) dr[r] = ok ? *at_bytes(row(dhat0, r), lane_off) : make_float2(0.f, 0.f);
     const int64_t kbase = (int64_t)(a.kmap ? a.kmap[blockIdx.y] : blockIdx.y) * a.nb;   // kernel group
+    const int kgrp = a.kgroup0 + (int)(a.kmap ? a.kmap[blockIdx.y] : blockIdx.y);       // its global index
     const int64_t obase = (int64_t)blockIdx.y * a.nb;                                 // output arrays
-    load_kernel(kbase, nx);
+    load_kernel(kbase, kgrp, nx);
     __syncthreads();   // twiddle table
     for (int b = 0; b < a.nb; ++b) {
         float2 v[R0];
 #pragma unroll
         for (int r = 0; r < R0; ++r) v[r] = nx[r];
-        if (b + 1 < a.nb) load_kernel(kbase + b + 1, nx);   // in flight during the transforms
+        if (b + 1 < a.nb) load_kernel(kbase + b + 1, kgrp, nx);   // in flight during the transforms
         if constexpr (ONE) __syncthreads();   // the previous transform has read the buffer
         reg_stages<N, -1, R0, REST...>(v, ex[0], ex1, tw, q, p, PITCH);
 #pragma unroll
         for (int r = 0; r < R0; ++r) v[r] = cmul(v[r], dr[r]);
         if constexpr (ONE) __syncthreads();
         reg_stages<N, 1, R0, REST...>(v, ex[0], ex1, tw, q, p, PITCH);
-        float2 *out = a.out + (obase + b) * a.ng;
+        float2 *out = out0 + (obase + b) * a.ng;
         if (ok)
 #pragma unroll
             for (int r = 0; r < R0; ++r) st_stream(at_bytes(const_cast<float2 *>(row(out, r)), lane_off), v[r]);
@@ -850,9 +946,18 @@ hipError_t launch_axis0(const Axis0Args &a, hipStream_t s) {
                     return;
                 }
             }
-            if (a.n == 192) hipLaunchKernelGGL((axis0_rs_kernel<192, P, M, 12, false, 12, 4, 4>), grid, dim3(16 * P), 0, s, a);
-            else if (a.n == 160) hipLaunchKernelGGL((axis0_rs_kernel<160, P, M, 20, false, 20, 4, 2>), grid, dim3(8 * P), 0, s, a);
-            else hipLaunchKernelGGL((axis0_rs_kernel<96, P, M, 12, false, 12, 4, 2>), grid, dim3(8 * P), 0, s, a);
+            // rows of a thread that the compact support can reach: KR = 2 where it allows (r0 below
+            // about a tenth of the axis), all rows otherwise
+            if (a.n == 192) {
+                if (support_rows(a, 12, 16) <= 2) hipLaunchKernelGGL((axis0_rs_kernel<192, P, M, 2, false, 12, 4, 4>), grid, dim3(16 * P), 0, s, a);
+                else hipLaunchKernelGGL((axis0_rs_kernel<192, P, M, 12, false, 12, 4, 4>), grid, dim3(16 * P), 0, s, a);
+            } else if (a.n == 160) {
+                if (support_rows(a, 20, 8) <= 2) hipLaunchKernelGGL((axis0_rs_kernel<160, P, M, 2, false, 20, 4, 2>), grid, dim3(8 * P), 0, s, a);
+                else hipLaunchKernelGGL((axis0_rs_kernel<160, P, M, 20, false, 20, 4, 2>), grid, dim3(8 * P), 0, s, a);
+            } else {
+                if (support_rows(a, 12, 8) <= 2) hipLaunchKernelGGL((axis0_rs_kernel<96, P, M, 2, false, 12, 4, 2>), grid, dim3(8 * P), 0, s, a);
+                else hipLaunchKernelGGL((axis0_rs_kernel<96, P, M, 12, false, 12, 4, 2>), grid, dim3(8 * P), 0, s, a);
+            }
         };
         if (a.mode == 1) go(std::integral_constant<int, 1>{});
         else go(std::integral_constant<int, 0>{});

@@ -33,6 +33,44 @@ static bool supported_edge(int64_t n) {
     return n >= 8 && n <= 1024 && fft_supported((int)n);
 }
 
+// Half kernel store: the kernels Y*_lm Phi_b have parity (-1)^l under r -> -r (Sec. 2, the
+// spherical-harmonic basis), so the stored planes c_0 = 0 .. r0 give the planes c_0 < 0 -- as
+// long as no axis truncates the support (2 r0 < N on every axis, where the zero-centred offsets
+// cover +-r0 whole).  3D grids only: the 2D planes are small, and there the mirrored rounding
+// moved the smallest projected-4PCF blocks past the float32 bound.  The plan takes it where the
+// full store would not fit (want = true), since it saves memory but no traffic: the mirrored
+// planes are read all the same.
+bool half_store(const ShapeGroup &G, int ndim, int64_t r0, bool want) {
+    if (!want || ndim != 3) return false;
+    for (int d = 0; d < ndim; ++d)
+        if (2 * r0 >= G.n[d]) return false;
+    return true;
+}
+
+// Axis-0 planes stored per kernel for support radius r0.
+int stored_planes(const ShapeGroup &G, int ndim, int64_t r0, bool want) {
+    const int64_t r = std::min<int64_t>(r0, G.n[0]);
+    return half_store(G, ndim, r0, want) ? (int)r + 1 : support_planes(G.n[0], r);
+}
+
+// The half-store fields of an axis-0 launch whose kernel group 0 is global group kgroup0.
+void mirror_args(const sb_plan *p, const ShapeGroup &G, int kgroup0, Axis0Args &a) {
+    a.half = G.half ? 1 : 0;
+    a.nflip = p->nlm;   // (l, m) or m groups; the packed m = 0 pairs (3D) come after them
+    a.kgroup0 = kgroup0;
+    a.odd_lo = a.odd_hi = 0;
+    for (int g = 0; g < p->nlm && g < 128; ++g) {
+        int l = g;   // 2D: group g is m = g
+        if (p->prob.ndim == 3) {
+            l = 0;
+            while ((l + 1) * (l + 2) / 2 <= g) ++l;
+        }
+        if (l & 1) (g < 64 ? a.odd_lo : a.odd_hi) |= (uint64_t)1 << (g & 63);
+    }
+    a.n1 = G.n[1];
+    a.n2 = p->prob.ndim == 3 ? G.n[2] : 1;
+}
+
 // ------------------------------------------------------------------ plan creation
 
 static sb_status build_gather(sb_plan *p, std::vector<int> &gptr, std::vector<int> &gidx, std::vector<double> &gcoef) {
@@ -265,16 +303,23 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
     {
         int64_t r0c = 0;
         while ((r0c + 1) * (r0c + 1) <= p->thr[NB]) ++r0c;
-        double cache = 0.0;
-        for (const auto &G : p->groups)
-            cache += (double)p->nlm * NB * support_planes(G.n[0], std::min<int64_t>(r0c, G.n[0])) *
-                     (double)(G.ng / G.n[0]) * sizeof(float2);
+        auto cache = [&](bool half) {
+            double c = 0.0;
+            for (const auto &G : p->groups)
+                c += (double)p->nlm * NB * stored_planes(G, prob->ndim, r0c, half) * (double)(G.ng / G.n[0]) *
+                     sizeof(float2);
+            return c;
+        };
         const bool fused3 = prob->npcf == 3 && (prob->flags & (SB_FLAG_UNFUSED | SB_FLAG_KEEP_COEFFS)) == 0;
         if ((prob->flags & SB_FLAG_REGEN_KERNELS) && !fused3) {
             delete p;
             return fail(SB_EUNSUPPORTED, "kernel regeneration applies to the fused 3PCF path only");
         }
-        p->regen = fused3 && ((prob->flags & SB_FLAG_REGEN_KERNELS) || cache > kKernelCacheCap);
+        // half store on request or where the full one would pass the cap; regeneration where even
+        // the half store would (and then the half store too: it halves the planes generated)
+        p->half = (prob->flags & SB_FLAG_HALF_KERNELS) || cache(false) > kKernelCacheCap;
+        p->regen = fused3 && ((prob->flags & SB_FLAG_REGEN_KERNELS) || cache(p->half) > kKernelCacheCap);
+        if (p->regen) p->half = true;
     }
     {
         // 3PCF: the fused path (forward and adjoint); 4PCF: the coefficients the contraction reads
@@ -464,7 +509,8 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
     for (auto &G : p->groups) {
         G.plane = G.ng / G.n[0];
         G.r0 = (int)std::min<int64_t>(r0, G.n[0]);
-        G.np = support_planes(G.n[0], G.r0);
+        G.half = half_store(G, prob->ndim, r0, p->half);
+        G.np = stored_planes(G, prob->ndim, r0, p->half);
         G.khat_off = pers;
         if (!p->regen) pers += align256((size_t)p->kernel_groups() * NB * G.np * G.plane * sizeof(float2));
         // fused last pass: rows per tile fixed by the kernel's compile-time tile shape
@@ -614,6 +660,7 @@ static sb_status axis0_corr(sb_plan *p, const ShapeGroup &G, const float2 *dhat,
     a.kc = kstore ? kstore
                   : reinterpret_cast<const float2 *>(p->persist + G.khat_off) + (kmap ? 0 : (int64_t)g0 * NB * G.np * G.plane);
     a.kmap = kmap;
+    mirror_args(p, G, kmap ? 0 : g0, a);   // kc's group 0 is the store's (with kmap) or group g0
     a.out = out;
     a.nb = NB;
     a.groups = ngr;

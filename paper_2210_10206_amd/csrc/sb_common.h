@@ -98,6 +98,17 @@ struct Axis0Args {
     const float2 *tw;
     int fields;           // mode 0: fields of one shape in the launch (grid.z; 0 counts as 1)
     int64_t dhat_fs, out_fs;   // mode 0: element strides between the fields' dhat and out
+    // Half store (half = 1): only the planes c_0 = 0 .. r0 are kept (np = r0 + 1).  A kernel with
+    // definite parity under r -> -r gives the planes c_0 < 0 from them: K(-c_0, k) = s K(c_0, -k)
+    // for global kernel groups g below nflip (s = -1 where bit g of odd_lo, or bit g - 64 of
+    // odd_hi, is set: odd l), and K(-c_0, k) = conj K(c_0, k) for the packed m = 0 pairs from
+    // nflip on.  (Scalars, not an array: an array member keeps the kernel's argument copy in
+    // scratch memory.)
+    int half;
+    int nflip;
+    int kgroup0;          // global kernel group of group 0 of kc
+    uint64_t odd_lo, odd_hi;
+    int64_t n1, n2;       // in-plane extents (n2 = 1 on 2D grids): the cell of -k
 };
 hipError_t launch_axis0(const Axis0Args &a, hipStream_t s);
 

@@ -23,6 +23,7 @@ struct ShapeGroup {
     int64_t ng = 0;
     int64_t plane = 0;            // cells per axis-0 plane
     int np = 0, r0 = 0;           // stored axis-0 planes of the kernels, support radius along axis 0
+    bool half = false;            // only the planes c_0 = 0 .. r0 stored (the others by parity)
     int rows = 0;                 // rows per tile of the fused last pass (0: not available)
     int64_t rows_per_block = 0;
     std::vector<int> fields;
@@ -95,6 +96,9 @@ struct sb_plan {
     // persistent buffer); their stored planes then sit in scratch at off_kc
     bool regen = false;
     size_t off_kc = 0;
+    // half kernel store (ShapeGroup::half on the shapes it applies to): on request, when the
+    // full store would pass kKernelCacheCap, and with regeneration
+    bool half = false;
     // kernel groups ((l, m) multiplets) whose arrays share the scratch at once: all of them,
     // unless a 3PCF plan's full set would exceed coef_limit (then the passes run in chunks)
     uint64_t coef_limit = 48ull << 30;
@@ -187,6 +191,11 @@ sb_status coefficients(sb_plan *p, int f, int g0, int ngroups, hipStream_t s, bo
                        const int *kmap = nullptr, int nf = 1);
 void layout_scratch(sb_plan *p);
 sb_status contract(sb_plan *p, const ShapeGroup &G, double *const *zout, int nf, hipStream_t s);
+// Half kernel store (plan.hip): whether a shape keeps only the planes c_0 = 0 .. r0, the planes
+// stored per kernel, and the half-store fields of an axis-0 launch.
+bool half_store(const ShapeGroup &G, int ndim, int64_t r0, bool want);
+int stored_planes(const ShapeGroup &G, int ndim, int64_t r0, bool want);
+void mirror_args(const sb_plan *p, const ShapeGroup &G, int kgroup0, Axis0Args &a);
 // SB_FLAG_CHECK_FINITE: count the NaN / Inf values of the inputs (n[i] values of dtype[i] at in[i]),
 // wait for the stream and return SB_ENONFINITE when there are any; SB_OK otherwise (and at once
 // when the flag is clear).

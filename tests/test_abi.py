@@ -183,10 +183,25 @@ def test_1024_grid_plan_regenerates_kernels():
     assert pb.value < 1 << 20
     assert sbytes.value < 140 << 30
     lib.sb_plan_destroy(h)
-    # the same problem at 256^3 keeps its cache
-    rc, h = _plan(lib, prob, [(256, 256, 256)])
+    # the same problem at 256^3 keeps its cache: 31 kernel groups (28 (l, m) and 3 packed m = 0
+    # pairs) of 10 bins, 65 stored axis-0 planes each (|c_0| <= 32); with the half store on
+    # request 33 (c_0 = 0 .. 32, the rest by parity)
+    for flags, planes in ((0, 65), (128, 33)):
+        prob.flags = flags
+        rc, h = _plan(lib, prob, [(256, 256, 256)])
+        assert lib.sb_plan_workspace(h, ctypes.byref(pb), ctypes.byref(sbytes)) == 0
+        size = 31 * 10 * planes * 256 * 256 * 8
+        assert size <= pb.value < size + (64 << 20)
+        lib.sb_plan_destroy(h)
+    prob.flags = 0
+    # 512^3, 16 bins to 16, lmax 10: the full cache (66 (l, m) groups x 16 bins x 33 planes, 73 GB)
+    # passes the 64 GiB cap, the half one (17 planes) does not, so the plan keeps the half store
+    prob16, e16 = _problem(edges=tuple(linear_edges(16, 16)), lmax=10)
+    rc, h = _plan(lib, prob16, [(512, 512, 512)])
+    assert rc == 0, lib.sb_last_error()
     assert lib.sb_plan_workspace(h, ctypes.byref(pb), ctypes.byref(sbytes)) == 0
-    assert pb.value > 8 << 30
+    size = 71 * 16 * 17 * 512 * 512 * 8   # 66 groups and 5 packed m = 0 pairs
+    assert size <= pb.value < size + (64 << 20) and pb.value < 64 << 30
     lib.sb_plan_destroy(h)
     # regeneration on request is a fused-3PCF option only
     for kw in (dict(npcf=4), dict(flags=2)):

@@ -624,14 +624,15 @@ def test_split_bf16_projected4pcf(sb, shape, nbins, mmax):
                                                            ((8, 16, 256), 10, 6, 3)])
 def test_regenerated_kernels_match_cached(sb, shape, nbins, lmax, limit_groups):
     # a plan that keeps no kernel spectra regenerates each chunk's planes with the same kernel
-    # generation and transforms: bit-identical to the cached plan without packed pairs
+    # generation and transforms: bit-identical to the cached plan without packed pairs that keeps
+    # the same planes (regeneration takes the half store where it applies)
     say(f"case: {shape} full 3PCF, {nbins} bins to 6, lmax {lmax}: regenerated kernels "
         f"(chunks of {limit_groups or 'all'} groups) vs cached")
     d = lognormal_field(shape, seed=60 + nbins, sigma=1.0)
     edges = linear_edges(6, nbins)
     kw = {} if limit_groups is None else dict(scratch_limit=limit_groups * nbins * d.size * 8)
     plan, dev, z = run_plan(sb, [d], edges, lmax, regen_kernels=True, **kw)
-    plan0, _, z0 = run_plan(sb, [d], edges, lmax, pack=False, **kw)
+    plan0, _, z0 = run_plan(sb, [d], edges, lmax, pack=False, half_kernels=True, **kw)
     assert plan.persistent_bytes < plan0.persistent_bytes
     assert np.array_equal(z, z0)
     check(z[0], oracle.zeta3_full(d.astype(np.float64), edges, lmax).real, TOL32, say)
@@ -639,6 +640,40 @@ def test_regenerated_kernels_match_cached(sb, shape, nbins, lmax, limit_groups):
         plan.backward(dev, torch.zeros((1, lmax + 1, nbins, nbins), dtype=torch.float64, device="cuda"))
     plan.close()
     plan0.close()
+
+
+@pytest.mark.parametrize("shape", [(64, 16, 16), (128, 16, 24), (256, 16, 16), (96, 16, 16), (160, 16, 16),
+                                   (192, 24, 16), (512, 16, 16), (1024, 16, 16), (32, 24, 16), (48, 16, 24)])
+def test_half_kernel_store(sb, shape):
+    # kernel planes c_0 < 0 taken from c_0 > 0 by parity (packed m = 0 pairs by conjugation) in
+    # every axis-0 kernel family: register-resident 64 / 128 / 256, radix lists 96 / 160 / 192 /
+    # 512 / 1024, LDS-staged 32 / 48; the fused and unfused 3PCF, the full 4PCF and the adjoint
+    say(f"case: {shape} half kernel store, 4 bins to 4, lmax 3: fused, unfused, 4PCF, adjoint")
+    d = lognormal_field(shape, seed=45, sigma=1.0)
+    edges = linear_edges(4, 4)
+    d64 = d.astype(np.float64)
+    ref3 = oracle.zeta3_full(d64, edges, 3).real
+    plan, dev, z = run_plan(sb, [d], edges, 3, half_kernels=True)
+    full, _, zf = run_plan(sb, [d], edges, 3)
+    assert plan.persistent_bytes < full.persistent_bytes
+    check(z[0], ref3, TOL32, say, "fused: ")
+    check(zf[0], ref3, TOL32, say, "full store: ")
+    if shape[0] <= 512:
+        rng = np.random.Generator(np.random.PCG64(7))
+        G = rng.standard_normal((4, 4, 4))
+        cells = np.sort(rng.choice(d.size, 16, replace=False))
+        g = plan.backward(dev, torch.from_numpy(G)[None].cuda())[0].reshape(-1).double().cpu().numpy()[cells]
+        ref = oracle.grad3_full(d64, edges, 3, G, cells=cells)
+        err = float(np.max(np.abs(g - ref)) / np.max(np.abs(ref)))
+        say(f"  adjoint err={err:.3e}")
+        assert err < TOL32
+    plan.close()
+    full.close()
+    if shape[0] <= 192:
+        _, _, zu = run_plan(sb, [d], edges, 3, half_kernels=True, fused=False)
+        check(zu[0], ref3, TOL32, say, "unfused: ")
+        _, _, z4 = run_plan(sb, [d], edges, 3, npcf=4, half_kernels=True)
+        check(z4[0], oracle.zeta4_full(d64, edges, 3)[1].real, TOL32, say, "4PCF: ")
 
 
 @pytest.mark.parametrize("shape,npcf", [((8, 16, 1024), 3), ((1024, 8, 16), 3), ((8, 1024, 16), 3), ((16, 1024), 3),

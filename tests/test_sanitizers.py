@@ -111,7 +111,7 @@ def test_host_plan_sweep():
                 for nb in (1, 3, 8, 16):
                     if npcf == 4 and (nb > 10 or (ndim == 3 and lmax > 6)):
                         continue
-                    for flags in ((0, 1, 2, 4, 16, 32) if npcf == 3 else (0, 4, 8, 32)):
+                    for flags in ((0, 1, 2, 4, 16, 32, 128) if npcf == 3 else (0, 4, 8, 32, 128)):
                         if flags == 8 and ndim == 2:
                             continue
                         cases.append((ndim, npcf, lmax, nb, flags))
