@@ -893,11 +893,11 @@ sb_status contract(sb_plan *p, const ShapeGroup &G, double *const *zout, int nf,
             return (double)NB * NB * (nt * 8.0 + (p->f4.canon[c].l[2] + 1) * (2.0 + 4.0 * NB));
         };
         // flops per cell and canonical Lambda the matrix-core kernel executes on real bins (padding
-        // excluded), per computed bin pair (NB^2, or NB (NB + 1) / 2 when la = lb): the weight times
-        // the b1 coefficients (2 per m of la), the coupling FMAs (mc = 0: the +-ma terms paired, 1
-        // FMA for ma = 0 and 2 per ma > 0 for even Lambda, 2 per ma > 0 for odd; mc > 0: 4 per term,
-        // 2 when ma or mb is 0) and the b3 contraction (per mc and b3: 1 FMA for mc = 0, 2 above),
-        // 2 flops per FMA
+        // excluded): per computed bin pair (NB^2, or NB (NB + 1) / 2 when la = lb) the coupling FMAs
+        // (mc = 0: the +-ma terms paired, 1 FMA for ma = 0 and 2 per ma > 0 for even Lambda, 2 per
+        // ma > 0 for odd; mc > 0: 4 per term, 2 when ma or mb is 0) and the b3 contraction (per mc
+        // and b3: 1 FMA for mc = 0, 2 above), 2 flops per FMA; then the weight times the b3
+        // coefficients (2 per mc and bin)
         auto lam_flops_mfma = [&](size_t c) {
             const Lam &C = p->f4.canon[c];
             const int la = C.l[0], lb = C.l[1], lc = C.l[2];
@@ -912,7 +912,7 @@ sb_status contract(sb_plan *p, const ShapeGroup &G, double *const *zout, int nf,
                     fma += (ma == 0 || mb == 0) ? 2.0 : 4.0;
                 }
             fma += NB * (1.0 + 2.0 * lc);
-            return pairs * (2.0 * fma + 2.0 * (la + 1));
+            return pairs * 2.0 * fma + 2.0 * NB * (lc + 1);
         };
         if (p->quad_mfma) {
             // one launch per canonical Lambda: its coefficients stay in registers

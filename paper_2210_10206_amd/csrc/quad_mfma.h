@@ -5,6 +5,7 @@
 // For one Lambda, with mc >= 0 and the weighted 3j symbols C (factor 2 for mc > 0, Alg. 6):
 //   L_mc[b1 b2](x) = w(x) sum_ma C(ma, mb, mc) a^b1_{LA,ma}(x) a^b2_{LB,mb}(x),  mb = -ma - mc
 //   Z[b1 b2][b3]  += sum_x Re( L_mc[b1 b2](x) a^b3_{LC,mc}(x) )
+// (the kernels multiply w(x) into a^b3 instead of L: the same sums for fewer products).
 // The coupling (first line) runs on the vector ALUs with every coefficient index known at
 // compile time, so the per-lane coefficients stay in registers; the contraction over the
 // cells (second line) is a real GEMM with M = b1 b2 pairs (tiles of 16), N = b3 (padded to
@@ -198,8 +199,23 @@ __device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
 // over 16 lanes) and the per-lane reads (cells 4 apart in the four lane groups land 8 float2
 // apart, bins fill the slots between).  The next tile's global loads are issued into registers
 // before the current tile is contracted, so their latency hides behind the coupling work.
+// Workgroups per CU the kernel is compiled for: 4 (4 waves per SIMD, at most 128 VGPRs) for the
+// float32 forms that fit that without spilling, else 1 (the compiler's own choice, 2-3 waves per
+// SIMD).  The excluded Lambda spill at 128 VGPRs (resource usage of this compiler); the split-BF16
+// forms, with their extra split registers, keep the compiler's choice.
+constexpr bool quad_spills_at_128(int la, int lb, int lc) {
+    constexpr int ex[][3] = {{3, 3, 4}, {3, 4, 3}, {3, 4, 4}, {4, 1, 4}, {4, 2, 2},
+                             {4, 2, 4}, {4, 3, 3}, {4, 3, 4}, {4, 4, 2}, {4, 4, 3}};
+    for (const auto &e : ex)
+        if (e[0] == la && e[1] == lb && e[2] == lc) return true;
+    return false;
+}
+constexpr int quad_blocks_per_cu(int la, int lb, int lc, int prec) {
+    return prec == 0 && !quad_spills_at_128(la, lb, lc) ? 4 : 1;
+}
+
 template <int LA, int LB, int LC, int PREC>
-__global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
+__global__ __launch_bounds__(256, quad_blocks_per_cu(LA, LB, LC, PREC)) void quad_mfma_kernel(QuadMArgs a) {
     a.coef += (int64_t)blockIdx.z * a.coef_fs;   // field of the launch (grid.z)
     a.w += (int64_t)blockIdx.z * a.w_fs;
     a.partial += (int64_t)blockIdx.z * a.part_fs;
@@ -275,16 +291,16 @@ __global__ __launch_bounds__(256) void quad_mfma_kernel(QuadMArgs a) {
 #pragma unroll
             for (int mt = 0; mt < NMT; ++mt)
 #pragma unroll
-                for (int m = 0; m <= LA; ++m) {
-                    const float2 v = (!SYM || b1s[mt] >= 0) ? row[(CL::offA + m) * kMaxNB + b1s[mt]]   // zero beyond nbins
-                                                            : make_float2(0.f, 0.f);
-                    A1[mt][m] = make_float2(wv * v.x, wv * v.y);
-                }
+                for (int m = 0; m <= LA; ++m)   // zero beyond nbins
+                    A1[mt][m] = (!SYM || b1s[mt] >= 0) ? row[(CL::offA + m) * kMaxNB + b1s[mt]] : make_float2(0.f, 0.f);
 #pragma unroll
             for (int m = 0; m <= LB; ++m) A2[m] = row[(CL::offB + m) * kMaxNB + b2];
+            // the weight w(x) goes with the b3 operand: LC + 1 values per cell instead of NMT (LA + 1)
 #pragma unroll
-            for (int mc = 0; mc <= LC; ++mc)
-                bv[mc] = i < kMaxNB ? row[(CL::offC + mc) * kMaxNB + i] : make_float2(0.f, 0.f);
+            for (int mc = 0; mc <= LC; ++mc) {
+                const float2 v = i < kMaxNB ? row[(CL::offC + mc) * kMaxNB + i] : make_float2(0.f, 0.f);
+                bv[mc] = make_float2(wv * v.x, wv * v.y);
+            }
             // one mc: couple, then contract on the matrix cores (unrolled over mc below)
             auto step = [&](auto mc_c) {
                 constexpr int MC = decltype(mc_c)::value;
