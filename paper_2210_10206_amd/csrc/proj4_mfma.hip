@@ -8,7 +8,12 @@
 // rows: row i of tile mt is pair p = 16 mt + i = b1 NB + b2), N = b3 (padded to 16) and K = the
 // cells, taken as v_mfma_f32_16x16x4f32 with the four lane groups' cells as K: the real part
 // Lr Br - Li Bi and the imaginary part Lr Bi + Li Br are two MFMAs each.  Lane l = i + 16 g
-// supplies row i of each A tile and column i (b3 = i) of B for cell g of the four.
+// supplies row i of the A tile and column i (b3 = i) of B for cell g of the four.
+//
+// The float32 kernel has one wave per M tile: every wave contracts all cells of a staged tile
+// against its own 16 pairs, so it holds one tile's accumulators (8 registers), the waves need no
+// combine at the end, and the small register count leaves room for several workgroups per CU.
+// The float32 sums of each staged tile are added to float64 totals.
 //
 // Staging as in the full-4PCF matrix-core kernels: a tile of 64 cells in LDS, cell-major, one
 // row of 3 NB float2 (the m1, m2, m3 columns) per cell padded to a stride = 2 (mod 8) float2
@@ -23,49 +28,43 @@ namespace {
 typedef float f4v __attribute__((ext_vector_type(4)));
 
 template <int NB>
-__global__ __launch_bounds__(256) void proj4_mfma_kernel(Proj4Args a) {
+constexpr int proj4_tiles() { return (NB * NB + 15) / 16; }
+
+template <int NB>
+__global__ __launch_bounds__(64 * proj4_tiles<NB>()) void proj4_mfma_kernel(Proj4Args a) {
     a.coef += (int64_t)blockIdx.z * a.coef_fs;   // field of the launch (grid.z)
     a.w += (int64_t)blockIdx.z * a.w_fs;
     a.partial += (int64_t)blockIdx.z * a.part_fs;
     constexpr int NP = NB * NB;
-    constexpr int NMT = (NP + 15) / 16;        // M tiles of 16 pairs
-    constexpr int TC = 64;                     // cells per staged tile (16 per wave)
+    constexpr int NMT = proj4_tiles<NB>();     // M tiles of 16 pairs = waves
+    constexpr int NT = 64 * NMT;
+    constexpr int TC = 64;                     // cells per staged tile
     constexpr int W = 3 * NB;                  // staged float2 per cell
     constexpr int S = (W + 7) / 8 * 8 + 2;     // padded row stride, = 2 (mod 8)
-    constexpr int NLD = (TC * W + 255) / 256;  // staged float2 per thread and tile
+    constexpr int NLD = (TC * W + NT - 1) / NT;   // staged float2 per thread and tile
     constexpr int NV = NB * NB * NB * 2;
-    constexpr int NTILE = TC * S > 2 * NV ? TC * S : 2 * NV;   // also holds 4 NV floats of reduction
-    __shared__ float2 tile[NTILE];
+    __shared__ float2 tile[TC * S];
     __shared__ float wt[TC];
-    float *red = reinterpret_cast<float *>(tile);
     const int pr_ = blockIdx.y;
     const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int mt = __builtin_amdgcn_readfirstlane(tid >> 6);   // this wave's M tile
     const int i = lane & 15, g = lane >> 4;
     const int m1 = a.pairs[2 * pr_], m2 = a.pairs[2 * pr_ + 1];
     const int ms[3] = {m1, m2, -(m1 + m2)};
-    int b1s[NMT], b2s[NMT];   // pair of this lane's row in each tile (-1: beyond NB^2)
-#pragma unroll
-    for (int mt = 0; mt < NMT; ++mt) {
-        const int p = 16 * mt + i;
-        b1s[mt] = p < NP ? p / NB : -1;
-        b2s[mt] = p < NP ? p % NB : 0;
-    }
-    f4v accr[NMT], acci[NMT];
-#pragma unroll
-    for (int mt = 0; mt < NMT; ++mt) {
-        accr[mt] = f4v{0.f, 0.f, 0.f, 0.f};
-        acci[mt] = f4v{0.f, 0.f, 0.f, 0.f};
-    }
+    const int p = 16 * mt + i;                 // pair of this lane's row
+    const bool prow = p < NP;
+    const int b1 = prow ? p / NB : 0, b2 = prow ? p % NB : 0;
+    f4v accr = f4v{0.f, 0.f, 0.f, 0.f}, acci = f4v{0.f, 0.f, 0.f, 0.f};
+    double totr[4] = {0.0, 0.0, 0.0, 0.0}, toti[4] = {0.0, 0.0, 0.0, 0.0};
     const int64_t c0 = (int64_t)blockIdx.x * a.cells_per_block;
     const int64_t c1 = min(c0 + a.cells_per_block, a.ng);
-    // load k of this thread: f = tid + 256 k -> cell f % 64, staged column (k3 = slot, bin) f / 64
+    // load k of this thread: f = tid + NT k -> cell f % 64, staged column (k3 = slot, bin) f / 64
     float2 pf[NLD];
     float pw = 0.f;
     auto gload = [&](int64_t tc) {
 #pragma unroll
         for (int k = 0; k < NLD; ++k) {
-            const int f = tid + 256 * k;
+            const int f = tid + NT * k;
             const int c = f % TC, kb = f / TC;
             float2 v = make_float2(0.f, 0.f);
             if (kb < W && tc + c < c1) {
@@ -76,60 +75,56 @@ __global__ __launch_bounds__(256) void proj4_mfma_kernel(Proj4Args a) {
             }
             pf[k] = v;
         }
-        if (wave == 0) pw = tc + lane < c1 ? a.w[tc + lane] : 0.f;
+        if (mt == 0) pw = tc + lane < c1 ? a.w[tc + lane] : 0.f;
     };
     gload(c0);
     for (int64_t tc = c0; tc < c1; tc += TC) {
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < NLD; ++k) {
-            const int f = tid + 256 * k;
+            const int f = tid + NT * k;
             const int c = f % TC, kb = f / TC;
             if (kb < W) tile[c * S + kb] = pf[k];
         }
-        if (wave == 0) wt[lane] = pw;
+        if (mt == 0) wt[lane] = pw;
         __syncthreads();
         if (tc + TC < c1) gload(tc + TC);
-#pragma unroll
-        for (int cc = 0; cc < 4; ++cc) {
-            const int c = 16 * wave + 4 * g + cc;
+#pragma unroll 4
+        for (int cc = 0; cc < TC / 4; ++cc) {
+            const int c = 4 * cc + g;
             const float2 *row = tile + c * S;
             const float wv = wt[c];
             const float2 bv = i < NB ? row[2 * NB + i] : make_float2(0.f, 0.f);
-#pragma unroll
-            for (int mt = 0; mt < NMT; ++mt) {
-                float2 L = make_float2(0.f, 0.f);
-                if (b1s[mt] >= 0) {
-                    const float2 x1 = row[b1s[mt]], x2 = row[NB + b2s[mt]];
-                    const float2 u = make_float2(wv * x1.x, wv * x1.y);
-                    L.x = __builtin_fmaf(u.x, x2.x, -u.y * x2.y);
-                    L.y = __builtin_fmaf(u.x, x2.y, u.y * x2.x);
-                }
-                accr[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(L.x, bv.x, accr[mt], 0, 0, 0);
-                accr[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-L.y, bv.y, accr[mt], 0, 0, 0);
-                acci[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(L.x, bv.y, acci[mt], 0, 0, 0);
-                acci[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(L.y, bv.x, acci[mt], 0, 0, 0);
+            float2 L = make_float2(0.f, 0.f);
+            if (prow) {
+                const float2 x1 = row[b1], x2 = row[NB + b2];
+                const float2 u = make_float2(wv * x1.x, wv * x1.y);
+                L.x = __builtin_fmaf(u.x, x2.x, -u.y * x2.y);
+                L.y = __builtin_fmaf(u.x, x2.y, u.y * x2.x);
             }
+            accr = __builtin_amdgcn_mfma_f32_16x16x4f32(L.x, bv.x, accr, 0, 0, 0);
+            accr = __builtin_amdgcn_mfma_f32_16x16x4f32(-L.y, bv.y, accr, 0, 0, 0);
+            acci = __builtin_amdgcn_mfma_f32_16x16x4f32(L.x, bv.y, acci, 0, 0, 0);
+            acci = __builtin_amdgcn_mfma_f32_16x16x4f32(L.y, bv.x, acci, 0, 0, 0);
         }
-    }
-    // accumulator tile mt: lane l holds rows 4 g + r (pair 16 mt + 4 g + r), column i (bin b3)
-    __syncthreads();
-    for (int v = tid; v < 4 * NV; v += 256) red[v] = 0.f;
-    __syncthreads();
-#pragma unroll
-    for (int mt = 0; mt < NMT; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int p = 16 * mt + 4 * g + r;
-            if (p < NP && i < NB) {
-                red[wave * NV + (p * NB + i) * 2] = accr[mt][r];
-                red[wave * NV + (p * NB + i) * 2 + 1] = acci[mt][r];
-            }
+            totr[r] += (double)accr[r];
+            toti[r] += (double)acci[r];
         }
-    __syncthreads();
-    for (int v = tid; v < NV; v += 256) {
-        const double s = ((double)red[v] + (double)red[NV + v]) + ((double)red[2 * NV + v] + (double)red[3 * NV + v]);
-        a.partial[((int64_t)pr_ * NV + v) * a.nblocks + blockIdx.x] = s;
+        accr = f4v{0.f, 0.f, 0.f, 0.f};
+        acci = f4v{0.f, 0.f, 0.f, 0.f};
+    }
+    // accumulator: lane l holds rows 4 g + r (pair 16 mt + 4 g + r), column i (bin b3); each
+    // (pair, b3, part) of the block is held by exactly one lane
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int pp = 16 * mt + 4 * g + r;
+        if (pp < NP && i < NB) {
+            const int64_t v = (int64_t)pr_ * NV + (pp * NB + i) * 2;
+            a.partial[v * a.nblocks + blockIdx.x] = totr[r];
+            a.partial[(v + 1) * a.nblocks + blockIdx.x] = toti[r];
+        }
     }
 }
 
@@ -278,7 +273,7 @@ hipError_t launch_nb(const Proj4Args &a, hipStream_t s) {
     if (a.precision == 1)
         hipLaunchKernelGGL((proj4_split_kernel<NB>), grid, dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL((proj4_mfma_kernel<NB>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((proj4_mfma_kernel<NB>), grid, dim3(64 * proj4_tiles<NB>()), 0, s, a);
     return hipGetLastError();
 }
 
