@@ -147,6 +147,7 @@ def counters_for(kernel_key, src_files):
     return {k: v for k, v in e.items() if k != "source_hash"}
 
 
+FIELDS_PER_LAUNCH = {"quad": 16, "proj4": 1}   # fields of one timed launch in the c4 / c4var and proj lines
 COUNTER_SRCS = {"quad_mfma": ["paper_2210_10206_amd/csrc/quad_mfma.h"],
                 "proj4_mfma": ["paper_2210_10206_amd/csrc/proj4_mfma.hip"]}
 
@@ -156,9 +157,11 @@ def write_counters(counter_csv):
     (--pmc MfmaUtil VALUBusy MfmaFlopsF32 MfmaFlopsBF16 SQ_INSTS_VALU SQ_INSTS_MFMA, csv output)
     into profiles/mfma_counters.json: per contraction family (4PCF matrix-core kernels by
     precision and parity, projected-4PCF kernels by precision), the duration-weighted MfmaUtil and
-    VALUBusy over its dispatches and the issued MFMA flops and instructions of one field (the sum
-    over the family's kernels of their mean per dispatch: every dispatch of one kernel does the
-    same work)."""
+    VALUBusy over its dispatches and the issued MFMA flops and instructions of one field: the sum
+    over the family's kernels of the counts of each kernel's last dispatch (a timed step's batch
+    launch) divided by the fields of that launch, FIELDS_PER_LAUNCH of the family (the 4PCF lines
+    run 16-field batches in one launch per Lambda; the autotuner's earlier single-field
+    candidates are left out of the counts)."""
     import csv
     import re
     rows = {}
@@ -180,7 +183,7 @@ def write_counters(counter_csv):
         return None, None
 
     fams = {}
-    for d in rows.values():
+    for _, d in sorted(rows.items()):   # dispatch order: each kernel's list ends with its last dispatch
         fam, key = family(d["name"])
         if fam is None:
             continue
@@ -194,8 +197,9 @@ def write_counters(counter_csv):
         util = sum(d.get("MfmaUtil", 0.0) * d.get("ns", 1.0) for ds in kernels.values() for d in ds) / w
         valu = sum(d.get("VALUBusy", 0.0) * d.get("ns", 1.0) for ds in kernels.values() for d in ds) / w
         per_field = {}
+        nf = FIELDS_PER_LAUNCH["quad" if fam.startswith("quad") else "proj4"]
         for c in ("MfmaFlopsF32", "MfmaFlopsBF16", "SQ_INSTS_VALU", "SQ_INSTS_MFMA"):
-            per_field[c] = sum(sum(d.get(c, 0.0) for d in ds) / len(ds) for ds in kernels.values())
+            per_field[c] = sum(ds[-1].get(c, 0.0) / nf for ds in kernels.values())
         out[fam] = {"kernels": len(kernels), "dispatches": sum(len(ds) for ds in kernels.values()),
                     "mfma_util_pct": round(util, 2), "valu_busy_pct": round(valu, 2),
                     "mfma_flops_f32_per_field": per_field["MfmaFlopsF32"],
