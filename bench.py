@@ -398,6 +398,18 @@ def run_c5(api, steps, warmup, synth_steps=200):
     plan_fb = plan.field_batch
     plan.close()
     del dev
+    res = {"workload": f"uneven batch of {len(fields)} sigma-1 lognormal float32 cubes, edges from "
+                       f"64/96/128/160/192 ({ncell / len(fields) / 1e6:.2f} M cells on average), 8 bins over "
+                       "(0,16], lmax 4, one plan",
+           "fields_per_launch": plan_fb, "pass_launches_per_forward": fwd_launches,
+           "forward_fields_per_s": round(len(fields) * steps / (t1 - t0), 2),
+           "forward_graph_replay_fields_per_s": round(graph_fps, 2),
+           "adjoint_fields_per_s": round(len(fields) * steps / (t2 - t1), 2),
+           "forward_plus_adjoint_fields_per_s": round(len(fields) * steps / (t2 - t0), 2),
+           "forward_err_vs_oracle": fwd_err or None,
+           "gradient_err_vs_oracle_at_stored_cells": grad_err or None, "synthesis": None}
+    if synth_steps <= 0:
+        return res
     n = 128
     sp = api.Plan([(n, n, n)], edges, 4, npcf=3)
     sp.autotune(torch.cuda.current_stream())
@@ -409,19 +421,10 @@ def run_c5(api, steps, warmup, synth_steps=200):
     torch.cuda.synchronize()
     t4 = time.perf_counter()
     sp.close()
-    return {"workload": f"uneven batch of {len(fields)} sigma-1 lognormal float32 cubes, edges from "
-                        f"64/96/128/160/192 ({ncell / len(fields) / 1e6:.2f} M cells on average), 8 bins over "
-                        "(0,16], lmax 4, one plan",
-            "fields_per_launch": plan_fb, "pass_launches_per_forward": fwd_launches,
-            "forward_fields_per_s": round(len(fields) * steps / (t1 - t0), 2),
-            "forward_graph_replay_fields_per_s": round(graph_fps, 2),
-            "adjoint_fields_per_s": round(len(fields) * steps / (t2 - t1), 2),
-            "forward_plus_adjoint_fields_per_s": round(len(fields) * steps / (t2 - t0), 2),
-            "forward_err_vs_oracle": fwd_err or None,
-            "gradient_err_vs_oracle_at_stored_cells": grad_err or None,
-            "synthesis": {"grid": n, "steps": synth_steps, "seconds": round(t4 - t3, 3),
-                          "ms_per_step": round((t4 - t3) / synth_steps * 1e3, 3),
-                          "loss_start": losses[0], "loss_end": losses[-1]}}
+    res["synthesis"] = {"grid": n, "steps": synth_steps, "seconds": round(t4 - t3, 3),
+                        "ms_per_step": round((t4 - t3) / synth_steps * 1e3, 3),
+                        "loss_start": losses[0], "loss_end": losses[-1]}
+    return res
 
 
 def run_512(api, steps, warmup):
@@ -641,6 +644,8 @@ def main():
                          "big (512^3), huge (1024^3), proj (512^2 projected), c5 (uneven batch + adjoint + "
                          "synthesis), cpu (oracle)")
     ap.add_argument("--c4-steps", type=int, default=1, help="steps of the 128^3 4PCF batch (0 skips it)")
+    ap.add_argument("--synth-steps", type=int, default=200,
+                    help="Adam steps of the synthesis demo after the uneven batch (0 skips it)")
     ap.add_argument("--c5-steps", type=int, default=1,
                     help="steps of the uneven-batch forward + adjoint and the synthesis demo (0 skips them)")
     ap.add_argument("--big-steps", type=int, default=1, help="steps of the 512^3 3PCF line (0 skips it)")
@@ -855,7 +860,7 @@ def main():
     c5 = None
     if "c5" in lines and args.c5_steps > 0:
         print("bench: uneven batch forward + adjoint, synthesis demo", file=sys.stderr, flush=True)
-        c5 = run_c5(api, args.c5_steps, 1)
+        c5 = run_c5(api, args.c5_steps, 1, synth_steps=args.synth_steps)
     cpu = None
     if "cpu" in lines and not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle sample)", file=sys.stderr, flush=True)
