@@ -448,18 +448,28 @@ def run_512(api, steps, warmup):
         for _ in range(warmup):
             plan.forward_raw([d], out=out, stream=stream)
     stream.synchronize()
+    plan.profile(True)
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
         for _ in range(steps):
             plan.forward_raw([d], out=out, stream=stream)
     stream.synchronize()
     el = time.perf_counter() - t0
+    recs = plan.launch_records()
+    plan.profile(False)
+    kinds = {0: "fft_passes", 1: "axis0_correlation", 2: "fused_last_pass", 3: "pair_contraction"}
+    per = {}
+    for r in recs:
+        k = kinds.get(r["kernel"], "other")
+        per[k] = per.get(k, 0.0) + r["ms"] / steps
     res = {"workload": "full 3PCF of one 512^3 float32 field (2x2x2 tiling of the 256^3 sigma 0.5 field), "
                        "10 bins over (0,32], lmax 6",
            "value": round(steps / el, 3), "unit": "fields/s", "ms_per_field": round(el / steps * 1e3, 2),
            "cold_setup_ms": round(cold * 1e3, 1),
            "persistent_GiB": round(plan.persistent_bytes / 2 ** 30, 2),
-           "scratch_GiB": round(plan.scratch_bytes / 2 ** 30, 2)}
+           "scratch_GiB": round(plan.scratch_bytes / 2 ** 30, 2),
+           "stage_ms_per_field": {k: round(v, 1) for k, v in per.items()},
+           "tuned_launch_shapes": plan.choices()}
     plan.close()
     return res
 
