@@ -581,23 +581,25 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
             wdst[e] = c < N ? a.w[row * N + c] : 0.f;
         }
     };
-    // PF: the next row's loads are in flight during this row (registers allow it except for the
-    // 1024-point tiles of more than 8 bins, where the other waves of the workgroup cover them)
+    // PF: the next row's loads are in flight during this row.  The registers allow it except for
+    // the 1024-point tiles of more than 8 bins; there the next row loads into the row's own
+    // registers once they are stored to LDS, so its loads are in flight during the pair sums.
     constexpr bool PF = !ONE || NBT <= 8;
     float2 nx[PF ? R0 : 1];
     float nw[PF ? WPT : 1];
-    if (PF && r_begin < r_end) load_row(r_begin, nx, nw);
+    float2 v[R0];
+    float wv[WPT];
+    if (r_begin < r_end) {
+        if constexpr (PF) load_row(r_begin, nx, nw);
+        else load_row(r_begin, v, wv);
+    }
     for (int64_t row = r_begin; row < r_end; ++row) {
-        float2 v[R0];
-        float wv[WPT];
         if constexpr (PF) {
 #pragma unroll
             for (int r = 0; r < R0; ++r) v[r] = nx[r];
 #pragma unroll
             for (int e = 0; e < WPT; ++e) wv[e] = nw[e];
             if (row + 1 < r_end) load_row(row + 1, nx, nw);    // next row in flight
-        } else {
-            load_row(row, v, wv);
         }
         __syncthreads();                                    // the previous row's pair sums are done
         reg_stages<N, 1, R0, REST...>(v, ex[0], ex1, tw, q, pp, PITCH);
@@ -609,6 +611,8 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
         for (int e = 0; e < WPT; ++e)
             if (tid + e * NT < N) wsm[tid + e * NT] = wv[e];
         __syncthreads();
+        if constexpr (!PF)
+            if (row + 1 < r_end) load_row(row + 1, v, wv);   // in flight during the pair sums
         ps.template tile<N, NW>(cs, 1, wsm, [](int c) { return c * PITCH; }, wave, lane);
     }
     // float64 combine over the waves in wave order (as in last_contract_kernel)
