@@ -627,6 +627,7 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
             PS::block_value(red, NW, nb, vv);
 }
 
+// (1024 points: at most 12 bins, as last_rows<1024> allows; wider tiles would spill)
 template <int N, int PREC, int R0, int... REST>
 hipError_t launch_last_rs_p(const LastArgs &a, hipStream_t s) {
     constexpr int T = N / R0;
@@ -635,7 +636,7 @@ hipError_t launch_last_rs_p(const LastArgs &a, hipStream_t s) {
     const int nbt = reg_padded_bins(a.nb, T);
 #define SB_LR(NBT)                                                                                                   \
     case NBT:                                                                                                         \
-        if constexpr ((NBT * T) % 64 == 0 && NBT * T <= 1024) {                                                       \
+        if constexpr ((NBT * T) % 64 == 0 && NBT * T <= 1024 && (N < 1024 || NBT <= 12)) {                           \
             if (mode == PS_COMPLEX)                                                                                   \
                 hipLaunchKernelGGL((last_rs_kernel<N, NBT, PS_COMPLEX, PREC, R0, REST...>), grid, dim3(NBT * T), 0, s, \
                                    a);                                                                                \
