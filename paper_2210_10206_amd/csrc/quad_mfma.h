@@ -13,7 +13,8 @@
 //   PREC 0: v_mfma_f32_16x16x4f32, K = the cells of the four lane groups, re and im in turn;
 //   PREC 1: v_mfma_f32_16x16x32_bf16 with both operands split into bf16 hi + lo parts and
 //           hi*hi + hi*lo + lo*hi accumulated in float32 (split-BF16); each lane group
-//           fills two of its eight K slots (re, im of its cell).
+//           fills six of its eight K slots (the three split products of re and im of its
+//           cell), one instruction per product.
 // Lane l of a wave is (i = l % 16, g = l / 16): row i of each A tile, column i of the B tile
 // (bin b3 = i); the lane walks cells 4 g .. 4 g + 3 of the wave's 16-cell step in turn.
 #pragma once
@@ -329,19 +330,20 @@ __global__ __launch_bounds__(256, quad_blocks_per_cu(LA, LB, LC, PREC)) void qua
                         }
                     }
                 } else {
-                    // K slots 0 and 1 of each lane group carry the two products of its cell, the rest zero
-                    bf8v bhv = {}, blv = {};
-                    __bf16 h, l;
-                    split_bf16(bv[MC].x, h, l); bhv[0] = h; blv[0] = l;
-                    split_bf16(bv[MC].y, h, l); bhv[1] = h; blv[1] = l;
+                    // K slots 8 g .. 8 g + 5 of lane group g carry the split products of its cell's two
+                    // terms a0 b0 + a1 b1 (even: a = (Lr, -Li), b = (Br, Bi); odd: a = (Li, Lr)):
+                    //   row (a0_h, a0_h, a0_l, a1_h, a1_h, a1_l, 0, 0), column (b0_h, b0_l, b0_h, b1_h, b1_l, b1_h, 0, 0)
+                    // so one instruction adds hi*hi + hi*lo + lo*hi of both (the lo*lo terms dropped)
+                    __bf16 h0, l0, h1, l1;
+                    split_bf16(bv[MC].x, h0, l0);
+                    split_bf16(bv[MC].y, h1, l1);
+                    const bf8v bop = {h0, l0, h0, h1, l1, h1, (__bf16)0.f, (__bf16)0.f};
 #pragma unroll
                     for (int mt = 0; mt < NMT; ++mt) {
-                        bf8v ahv = {}, alv = {};
-                        split_bf16(ODD ? L[mt].y : L[mt].x, h, l); ahv[0] = h; alv[0] = l;
-                        split_bf16(ODD ? L[mt].x : -L[mt].y, h, l); ahv[1] = h; alv[1] = l;
-                        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahv, bhv, acc[mt], 0, 0, 0);
-                        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahv, blv, acc[mt], 0, 0, 0);
-                        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alv, bhv, acc[mt], 0, 0, 0);
+                        split_bf16(ODD ? L[mt].y : L[mt].x, h0, l0);
+                        split_bf16(ODD ? L[mt].x : -L[mt].y, h1, l1);
+                        const bf8v aop = {h0, h0, l0, h1, h1, l1, (__bf16)0.f, (__bf16)0.f};
+                        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop, acc[mt], 0, 0, 0);
                     }
                 }
             };
