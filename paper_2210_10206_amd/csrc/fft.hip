@@ -947,16 +947,18 @@ hipError_t launch_axis0(const Axis0Args &a, hipStream_t s) {
                 }
             }
             // rows of a thread that the compact support can reach: KR = 2 where it allows (r0 below
-            // about a tenth of the axis), all rows otherwise
+            // about a tenth of the axis), all rows otherwise.  One exchange buffer (one more barrier
+            // per exchange): with two, the LDS (27-54 KB per workgroup) held these lengths to 2-5
+            // workgroups per CU, below what their registers allow
             if (a.n == 192) {
-                if (support_rows(a, 12, 16) <= 2) hipLaunchKernelGGL((axis0_rs_kernel<192, P, M, 2, false, 12, 4, 4>), grid, dim3(16 * P), 0, s, a);
-                else hipLaunchKernelGGL((axis0_rs_kernel<192, P, M, 12, false, 12, 4, 4>), grid, dim3(16 * P), 0, s, a);
+                if (support_rows(a, 12, 16) <= 2) hipLaunchKernelGGL((axis0_rs_kernel<192, P, M, 2, true, 12, 4, 4>), grid, dim3(16 * P), 0, s, a);
+                else hipLaunchKernelGGL((axis0_rs_kernel<192, P, M, 12, true, 12, 4, 4>), grid, dim3(16 * P), 0, s, a);
             } else if (a.n == 160) {
-                if (support_rows(a, 20, 8) <= 2) hipLaunchKernelGGL((axis0_rs_kernel<160, P, M, 2, false, 20, 4, 2>), grid, dim3(8 * P), 0, s, a);
-                else hipLaunchKernelGGL((axis0_rs_kernel<160, P, M, 20, false, 20, 4, 2>), grid, dim3(8 * P), 0, s, a);
+                if (support_rows(a, 20, 8) <= 2) hipLaunchKernelGGL((axis0_rs_kernel<160, P, M, 2, true, 20, 4, 2>), grid, dim3(8 * P), 0, s, a);
+                else hipLaunchKernelGGL((axis0_rs_kernel<160, P, M, 20, true, 20, 4, 2>), grid, dim3(8 * P), 0, s, a);
             } else {
-                if (support_rows(a, 12, 8) <= 2) hipLaunchKernelGGL((axis0_rs_kernel<96, P, M, 2, false, 12, 4, 2>), grid, dim3(8 * P), 0, s, a);
-                else hipLaunchKernelGGL((axis0_rs_kernel<96, P, M, 12, false, 12, 4, 2>), grid, dim3(8 * P), 0, s, a);
+                if (support_rows(a, 12, 8) <= 2) hipLaunchKernelGGL((axis0_rs_kernel<96, P, M, 2, true, 12, 4, 2>), grid, dim3(8 * P), 0, s, a);
+                else hipLaunchKernelGGL((axis0_rs_kernel<96, P, M, 12, true, 12, 4, 2>), grid, dim3(8 * P), 0, s, a);
             }
         };
         if (a.mode == 1) go(std::integral_constant<int, 1>{});
