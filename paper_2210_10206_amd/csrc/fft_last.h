@@ -555,8 +555,10 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
     constexpr int WPT = (N + NT - 1) / NT;
     static_assert(NT % 64 == 0 && NSTAGE >= 2, "whole waves, two stages or more");
     // ONE: a single exchange buffer, which the [cell][bin] view then reuses (one more barrier per
-    // row), where two would not fit the LDS (1024 points)
-    constexpr bool ONE = 2 * N * PITCH * sizeof(float2) + N * (sizeof(float2) + sizeof(float)) > 160 * 1024;
+    // row).  Two would not fit the LDS at 1024 points, and below that they held the workgroups
+    // per CU under what the registers allow (one buffer: uneven 64-192^3 forward 401 -> 412
+    // fields/s); the two-buffer form stays behind this constant
+    constexpr bool ONE = true;
     __shared__ float2 ex[ONE ? 1 : 2][N * PITCH];
     float2 *ex1 = ex[ONE ? 0 : 1];
     __shared__ float2 tw[N];
@@ -584,7 +586,7 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
     // PF: the next row's loads are in flight during this row.  The registers allow it except for
     // the 1024-point tiles of more than 8 bins; there the next row loads into the row's own
     // registers once they are stored to LDS, so its loads are in flight during the pair sums.
-    constexpr bool PF = !ONE || NBT <= 8;
+    constexpr bool PF = N < 1024 || NBT <= 8;
     float2 nx[PF ? R0 : 1];
     float nw[PF ? WPT : 1];
     float2 v[R0];
