@@ -535,9 +535,11 @@ hipError_t launch_last_reg(const LastArgs &a, hipStream_t s) {
 
 // Register-resident form for any radix list R0, ... (each radix divides R0; see reg_stages):
 // a tile is one row of the NBT (padded) bins of one (l, m); thread q < T = n / R0 of a
-// pencil loads elements q + T s.  The stages exchange through two LDS buffers laid out
-// [position][bin]; the transformed row is written to the buffer the last stage did not read,
-// which is then the [cell][bin] tile of the MFMA pair sums.
+// pencil loads elements q + T s.  The stages exchange through one LDS buffer laid out
+// [position][bin], which, once the last stage has read it, takes the transformed row as the
+// [cell][bin] tile of the MFMA pair sums (one more barrier per row).  Two buffers (one barrier
+// fewer) would not fit the LDS at 1024 points, and below that they held the workgroups per CU
+// under what the registers allow (one buffer: uneven 64-192^3 forward 401 -> 412 fields/s).
 template <int N, int NBT, int MODE, int PREC, int R0, int... REST>
 __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
     a.in += (int64_t)blockIdx.z * a.in_fs;   // field of the launch (grid.z)
@@ -551,16 +553,9 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
     constexpr int NOUT = PS::NOUT;
     constexpr int PITCH = P + 1;
     constexpr int NSTAGE = 1 + sizeof...(REST);
-    constexpr int CSB = (NSTAGE - 1) % 2;       // buffer the last stage does not read
     constexpr int WPT = (N + NT - 1) / NT;
     static_assert(NT % 64 == 0 && NSTAGE >= 2, "whole waves, two stages or more");
-    // ONE: a single exchange buffer, which the [cell][bin] view then reuses (one more barrier per
-    // row).  Two would not fit the LDS at 1024 points, and below that they held the workgroups
-    // per CU under what the registers allow (one buffer: uneven 64-192^3 forward 401 -> 412
-    // fields/s); the two-buffer form stays behind this constant
-    constexpr bool ONE = true;
-    __shared__ float2 ex[ONE ? 1 : 2][N * PITCH];
-    float2 *ex1 = ex[ONE ? 0 : 1];
+    __shared__ float2 ex[N * PITCH];
     __shared__ float2 tw[N];
     __shared__ float wsm[N];
     const int nb = a.nb;
@@ -604,9 +599,9 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
             if (row + 1 < r_end) load_row(row + 1, nx, nw);    // next row in flight
         }
         __syncthreads();                                    // the previous row's pair sums are done
-        reg_stages<N, 1, R0, REST...>(v, ex[0], ex1, tw, q, pp, PITCH);
-        float2 *cs = ex[ONE ? 0 : CSB];
-        if constexpr (ONE) __syncthreads();                 // the last stage has read the buffer
+        reg_stages<N, 1, R0, REST...>(v, ex, ex, tw, q, pp, PITCH);
+        float2 *cs = ex;
+        __syncthreads();                                    // the last stage has read the buffer
 #pragma unroll
         for (int r = 0; r < R0; ++r) cs[(q + T * r) * PITCH + pp] = v[r];
 #pragma unroll
@@ -620,7 +615,7 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
     // float64 combine over the waves in wave order (as in last_contract_kernel)
     __syncthreads();
     static_assert(PS::red_doubles(NW) * sizeof(double) <= sizeof(ex), "block reduction fits");
-    double *red = reinterpret_cast<double *>(&ex[0][0]);
+    double *red = reinterpret_cast<double *>(ex);
     ps.to_lds(red, wave, lane);
     __syncthreads();
     const int nv = nb * (nb + 1) / 2 * NOUT;
