@@ -676,6 +676,29 @@ def test_half_kernel_store(sb, shape):
         check(z4[0], oracle.zeta4_full(d64, edges, 3)[1].real, TOL32, say, "4PCF: ")
 
 
+@pytest.mark.parametrize("shape,npcf", [((64, 96), 3), ((48, 64), 4), ((24, 24, 12), 3), ((16, 8, 32), 4)])
+def test_half_kernel_store_not_applicable(sb, shape, npcf):
+    # the half store applies to 3D shapes whose support radius stays below half of every edge:
+    # on a 2D plan, or with an edge of at most 2 r0 (here r0 = 6 against edges of 12 and 8), the
+    # flag leaves the plan unchanged, bit for bit (and a 16-point edge, above 2 r0, takes it)
+    say(f"case: {shape} npcf {npcf}, 4 bins to 6, lmax 3: half-store flag where it does not apply")
+    d = lognormal_field(shape, seed=46, sigma=1.0)
+    edges = linear_edges(6, 4)
+    p1, _, z1 = run_plan(sb, [d], edges, 3, npcf=npcf, half_kernels=True)
+    p0, _, z0 = run_plan(sb, [d], edges, 3, npcf=npcf)
+    assert p1.persistent_bytes == p0.persistent_bytes
+    assert np.array_equal(z1, z0)
+    p1.close()
+    p0.close()
+    if len(shape) == 3:
+        p2, _, _ = run_plan(sb, [lognormal_field((24, 24, 16), seed=46, sigma=1.0)], edges, 3, npcf=npcf,
+                            half_kernels=True)
+        p3, _, _ = run_plan(sb, [lognormal_field((24, 24, 16), seed=46, sigma=1.0)], edges, 3, npcf=npcf)
+        assert p2.persistent_bytes < p3.persistent_bytes
+        p2.close()
+        p3.close()
+
+
 @pytest.mark.parametrize("shape,npcf", [((8, 16, 1024), 3), ((1024, 8, 16), 3), ((8, 1024, 16), 3), ((16, 1024), 3),
                                         ((1024, 16), 3), ((8, 8, 1024), 4), ((16, 1024), 4)])
 def test_axes_of_1024(sb, shape, npcf):
