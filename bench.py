@@ -681,7 +681,7 @@ def main():
         write_counters(args.write_counters)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "bench.py measures one GPU: the library has no multi-GPU path",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     lines = set(x.strip() for x in args.lines.split(",") if x.strip())

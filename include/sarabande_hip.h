@@ -60,7 +60,7 @@ extern "C" {
 typedef enum {
     SB_OK = 0,
     SB_EINVAL = -1,        /* invalid argument (shape, edges, lmax, npcf, ndim, null pointer) */
-    SB_EUNSUPPORTED = -2,  /* valid but not supported by this build (grid edge, bin count) */
+    SB_EUNSUPPORTED = -2,  /* valid but not supported by the library (grid edge, bin count) */
     SB_EWORKSPACE = -3,    /* bound workspace too small or not bound */
     SB_EHIP = -4,          /* a HIP runtime call failed (detail in sb_last_error) */
     SB_ENOMEM = -5,        /* host allocation failed */
