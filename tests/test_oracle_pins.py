@@ -409,3 +409,24 @@ def test_grid_sum_accumulation_error_is_negligible():
                 exact[l, b1, b2] = math.fsum(terms)
     scale = np.max(np.abs(exact))
     assert np.max(np.abs(z - exact)) <= 1e-12 * scale
+
+
+def test_kernels_have_parity_under_inversion():
+    """The binned kernels conj(Y_lm(r^)) on the support of a bin change by (-1)^l under r -> -r,
+    and the support of every bin is symmetric, when 2 r0 stays below every edge: the identity
+    the half kernel store uses to take the planes c_0 < 0 from c_0 > 0.  At an edge of 2 r0 the
+    zero-centred offsets of that axis lose the symmetry (-r0 is kept, +r0 folds onto it), which
+    is why plans keep every plane there."""
+    from oracle.api import basis_full
+    lmax = 4
+    off, bins, _ = support((16, 20, 18), linear_edges(6, 3))   # r0 = 6, 2 r0 = 12 < every edge
+    key = {tuple(o): b for o, b in zip(off.tolist(), bins.tolist())}
+    neg = -off
+    assert all(key.get(tuple(o)) == b for o, b in zip(neg.tolist(), bins.tolist()))
+    B, Bn = basis_full(off, lmax), basis_full(neg, lmax)
+    for l in range(lmax + 1):
+        cols = slice(l * l, (l + 1) ** 2)
+        np.testing.assert_allclose(Bn[:, cols], (-1) ** l * B[:, cols], rtol=0, atol=1e-13)
+    off12, _, _ = support((12, 20, 18), linear_edges(6, 3))  # an edge of exactly 2 r0
+    keys12 = {tuple(o) for o in off12.tolist()}
+    assert any(tuple(-o) not in keys12 for o in off12)
