@@ -397,6 +397,38 @@ def run_c5(api, steps, warmup, synth_steps=200):
             grad_err[f"{edges_list[i]}^3 field {i}"] = float(np.max(np.abs(got - g["grad"])) / np.max(np.abs(g["grad"])))
     plan_fb = plan.field_batch
     plan.close()
+    del plan
+    torch.cuda.empty_cache()
+    # the same batch with the coefficient arrays kept from each forward for the adjoint
+    # (SB_FLAG_KEEP_FOR_ADJOINT): every field's arrays at once in scratch
+    kp = api.Plan([f.shape for f in fields], edges, 4, npcf=3, keep_for_adjoint=True)
+    kp.autotune(torch.cuda.current_stream())
+    for _ in range(warmup):
+        kp.forward_raw(dev)
+        kp.backward(dev, G)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
+    tk0 = time.perf_counter()
+    for i in range(steps):
+        kp.forward_raw(dev)
+        ev[2 * i].record()
+        kp.backward(dev, G)
+        ev[2 * i + 1].record()
+    torch.cuda.synchronize()
+    tk1 = time.perf_counter()
+    kept_adj_ms = sum(ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(steps))
+    kept_grad_err = {}
+    if gold_g:
+        kp.forward_raw(dev)
+        grads = kp.backward(dev, torch.from_numpy(Gg).cuda())
+        for i, g in gold_g.items():
+            got = grads[i].reshape(-1)[torch.from_numpy(g["cells"]).cuda()].double().cpu().numpy()
+            kept_grad_err[f"{edges_list[i]}^3 field {i}"] = float(np.max(np.abs(got - g["grad"]))
+                                                                 / np.max(np.abs(g["grad"])))
+    kept_scratch_gb = kp._scratch.numel() / 1e9
+    kp.close()
+    del kp
+    torch.cuda.empty_cache()
     del dev
     res = {"workload": f"uneven batch of {len(fields)} sigma-1 lognormal float32 cubes, edges from "
                        f"64/96/128/160/192 ({ncell / len(fields) / 1e6:.2f} M cells on average), 8 bins over "
@@ -406,6 +438,10 @@ def run_c5(api, steps, warmup, synth_steps=200):
            "forward_graph_replay_fields_per_s": round(graph_fps, 2),
            "adjoint_fields_per_s": round(len(fields) * steps / (t2 - t1), 2),
            "forward_plus_adjoint_fields_per_s": round(len(fields) * steps / (t2 - t0), 2),
+           "kept_for_adjoint": {"scratch_gb": round(kept_scratch_gb, 1),
+                                "adjoint_fields_per_s": round(len(fields) * steps / (kept_adj_ms / 1e3), 2),
+                                "forward_plus_adjoint_fields_per_s": round(len(fields) * steps / (tk1 - tk0), 2),
+                                "gradient_err_vs_oracle_at_stored_cells": kept_grad_err or None},
            "forward_err_vs_oracle": fwd_err or None,
            "gradient_err_vs_oracle_at_stored_cells": grad_err or None, "synthesis": None}
     if synth_steps <= 0:

@@ -17,6 +17,7 @@ SB_FLAG_KEEP_COEFFS, SB_FLAG_UNFUSED, SB_FLAG_NO_MFMA, SB_FLAG_ODD_PARITY, SB_FL
 SB_FLAG_CHECK_FINITE = 32
 SB_FLAG_REGEN_KERNELS = 64
 SB_FLAG_HALF_KERNELS = 128
+SB_FLAG_KEEP_FOR_ADJOINT = 256
 SB_WARN_BOX_TRUNCATED = 1
 
 # Every function the header declares, with its ctypes signature.

@@ -57,12 +57,15 @@ class Plan:
                  64 GiB, and with regen_kernels); half the persistent buffer, same traffic
     field_batch: fields of one shape per launch of each pass (sb_plan_set_field_batch): None or 0 =
                  as many as 32 GiB of kernel arrays allow, 1 = one launch sequence per field
+    keep_for_adjoint: fused 3D 3PCF: every forward keeps each field's arrays before the last axis
+                 in scratch, and a backward on the same fields reads them instead of recomputing
+                 them (SB_FLAG_KEEP_FOR_ADJOINT; the scratch holds every field's arrays at once)
     """
 
     def __init__(self, shapes, bin_edges, lmax, npcf=3, precision="fp32", input_dtype=torch.float32,
                  device=None, stream=None, prepare=True, keep_coeffs=False, fused=True, mfma=True,
                  scratch_limit=None, parity="even", pack=True, check_finite=False, regen_kernels=False,
-                 field_batch=None, half_kernels=False):
+                 field_batch=None, half_kernels=False, keep_for_adjoint=False):
         self.lib = _lib.load()
         shapes = [tuple(int(x) for x in s) for s in shapes]
         ndim = len(shapes[0])
@@ -84,7 +87,8 @@ class Plan:
                                | (0 if pack else _lib.SB_FLAG_NO_PACK)
                                | (_lib.SB_FLAG_CHECK_FINITE if check_finite else 0)
                                | (_lib.SB_FLAG_REGEN_KERNELS if regen_kernels else 0)
-                               | (_lib.SB_FLAG_HALF_KERNELS if half_kernels else 0))
+                               | (_lib.SB_FLAG_HALF_KERNELS if half_kernels else 0)
+                               | (_lib.SB_FLAG_KEEP_FOR_ADJOINT if keep_for_adjoint else 0))
         if parity not in ("even", "odd"):
             raise ValueError("parity must be 'even' or 'odd'")
         self.parity = parity

@@ -149,6 +149,12 @@ sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta
         dt.push_back(1);
         if (sb_status st = check_finite(p, (int)in.size(), in.data(), n.data(), dt.data(), s); st != SB_OK) return st;
     }
+    // arrays the last forward kept for these fields (SB_FLAG_KEEP_FOR_ADJOINT) replace the
+    // recomputed ones; they are only read, so they stay for another backward.  Recomputing
+    // overwrites them.
+    bool use_kept = p->keep && p->kept && p->adj_fused && (int)p->kept_delta.size() == p->batch;
+    for (int f = 0; use_kept && f < p->batch; ++f) use_kept = p->kept_delta[f] == delta[f];
+    if (!use_kept) p->kept = false;
     for (int f = 0; f < p->batch; ++f) {
         const ShapeGroup &G = p->groups[p->field_group[f]];
         const float2 *khat = reinterpret_cast<const float2 *>(p->persist + G.khat_off);
@@ -206,16 +212,22 @@ sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta
         };
         for (int g0 = 0; g0 < ngrp; g0 += p->chunk_groups) {
             const int ngr = std::min(p->chunk_groups, ngrp - g0);
-            // recompute a for this chunk of groups (never stored across calls); with the fused pass
+            // recompute a for this chunk of groups, unless the forward kept it; with the fused pass
             // it stops before the last axis, which that pass finishes
-            st = coefficients(p, f, g0, ngr, s, !p->adj_fused, packing ? p->d_kmap + g0 : nullptr);
-            if (st != SB_OK) return st;
+            const float2 *cf = use_kept ? reinterpret_cast<const float2 *>(p->scratch + p->off_coef + p->keep_off[f])
+                                        : coef;
+            if (!use_kept) {
+                st = coefficients(p, f, g0, ngr, s, !p->adj_fused, packing ? p->d_kmap + g0 : nullptr);
+                if (st != SB_OK) return st;
+            }
             if (p->adj_fused) {
                 // per group: last inverse pass + h, D and v + forward transform of v(-x) along the
                 // last axis.  v of group g goes to the slot before its own coefficients (the vtmp
                 // arrays for the first group, then the coefficients the previous group consumed),
-                // so the chunk's v arrays end up contiguous from vbase.
-                float2 *vbase = coef_w - (int64_t)NB * G.ng;
+                // so the chunk's v arrays end up contiguous from vbase; kept arrays stay intact,
+                // the v arrays going to a region of their own.
+                float2 *vbase = use_kept ? reinterpret_cast<float2 *>(p->scratch + p->off_vkeep)
+                                         : coef_w - (int64_t)NB * G.ng;
                 for (int g = g0; g < g0 + ngr; ++g) {
                     int m = 0, l2 = -1;
                     const int l = group_l(g, &m, &l2);
@@ -224,7 +236,7 @@ sb_status backward(sb_plan *p, const void *const *delta, const double *grad_zeta
                     a.ndim = 3;
                     for (int d = 0; d < 3; ++d) a.shape[d] = G.n[d];
                     a.ng = G.ng;
-                    a.in = coef + (int64_t)(g - g0) * NB * G.ng;
+                    a.in = cf + (int64_t)(g - g0) * NB * G.ng;
                     a.w = w;
                     a.gz = gz_f + (int64_t)l * NB * NB;
                     a.gz2 = l2 >= 0 ? gz_f + (int64_t)l2 * NB * NB : nullptr;

@@ -58,5 +58,6 @@ extern "C" sb_status sb_forward_noalloc(sb_plan *p, const void *const *delta, do
     p->scratch = ptr;
     const sb_status st = forward(p, delta, zeta, static_cast<hipStream_t>(stream));
     p->scratch = bound;
+    p->kept = false;   // whatever this call kept went to the static array
     return st;
 }

@@ -158,7 +158,8 @@ void layout_scratch(sb_plan *p) {
     const int NB = prob->nbins;
     const uint64_t per_group = (uint64_t)NB * p->max_ng * sizeof(float2);
     p->chunk_groups = p->nlm;
-    const bool chunkable = prob->npcf == 3 && (prob->flags & SB_FLAG_KEEP_COEFFS) == 0;
+    p->kept = false;
+    const bool chunkable = prob->npcf == 3 && (prob->flags & SB_FLAG_KEEP_COEFFS) == 0 && !p->keep;
     if (chunkable && per_group * p->nlm > p->coef_limit)
         p->chunk_groups = (int)std::max<uint64_t>(1, std::min<uint64_t>(p->nlm, p->coef_limit / per_group));
     // fields per batch (the region of each per-field buffer below is fbatch fields long)
@@ -178,7 +179,24 @@ void layout_scratch(sb_plan *p) {
     // the adjoint's v arrays directly before the coefficient arrays: its fused pass writes the v
     // of each group into the slot before that group's coefficients
     if (adjoint) { p->off_vtmp = sc; sc += align256((size_t)NB * p->max_ng * sizeof(float2)); }
-    p->off_coef = sc; sc += align256(FB * p->chunk_groups * NB * p->max_ng * sizeof(float2));
+    p->off_coef = sc;
+    if (p->keep) {
+        // one region per field: the forward's array groups (packed m = 0 pairs first) of all bins
+        const int nag = p->npack > 0 ? p->nag : p->nlm;
+        p->keep_off.assign(p->batch, 0);
+        size_t k = 0;
+        for (const auto &G : p->groups)
+            for (const int f : G.fields) {
+                p->keep_off[f] = k;
+                k += (size_t)nag * NB * G.ng * sizeof(float2);
+            }
+        // at least the region the recomputing backward uses (one field of every (l, m) group)
+        sc += align256(std::max(k, (size_t)p->nlm * NB * p->max_ng * sizeof(float2)));
+        p->off_vkeep = sc;
+        sc += align256((size_t)nag * NB * p->max_ng * sizeof(float2));
+    } else {
+        sc += align256(FB * p->chunk_groups * NB * p->max_ng * sizeof(float2));
+    }
     if (p->regen) {   // the stored axis-0 planes of one chunk's kernels
         int64_t kc = 0;
         for (const auto &G : p->groups) kc = std::max<int64_t>(kc, (int64_t)G.np * G.plane);
@@ -501,6 +519,14 @@ sb_status plan_create(const sb_problem *prob, int32_t batch, const int64_t *shap
     while ((r0 + 1) * (r0 + 1) <= p->thr[NB]) ++r0;      // largest |c_0| with c_0^2 <= e_max^2
     p->fused = (prob->flags & (SB_FLAG_UNFUSED | SB_FLAG_KEEP_COEFFS)) == 0;
     p->adj_fused = (prob->flags & SB_FLAG_UNFUSED) == 0;
+    if (prob->flags & SB_FLAG_KEEP_FOR_ADJOINT) {
+        if (prob->ndim != 3 || prob->npcf != 3 || !p->fused || p->regen) {
+            delete p;
+            return fail(SB_EUNSUPPORTED, "keeping the arrays for the adjoint applies to fused 3D 3PCF plans that "
+                                         "cache their kernel spectra");
+        }
+        p->keep = true;
+    }
     // an offset coordinate of magnitude r0 with 2 r0 >= N does not fit the zero-centred box
     for (const auto &G : p->groups)
         for (int d = 0; d < prob->ndim; ++d)
@@ -719,11 +745,12 @@ sb_status coefficients(sb_plan *p, int f, int g0, int ngr, hipStream_t s, bool l
 // coefficient arrays are never written).
 // nf fields of shape G in one launch per pass (nf > 1 only when every array group fits the scratch
 // at once); field i's result goes to zout[i].
+// coef_off: byte offset of the batch's coefficient arrays past off_coef (a kept field's region).
 static sb_status fused_3pcf(sb_plan *p, const ShapeGroup &G, const void *const *deltas, double *const *zout, int nf,
-                            hipStream_t s) {
+                            size_t coef_off, hipStream_t s) {
     const int nd = p->prob.ndim, NB = p->prob.nbins;
     float2 *dhat = reinterpret_cast<float2 *>(p->scratch + p->off_dhat);
-    float2 *coef = reinterpret_cast<float2 *>(p->scratch + p->off_coef);
+    float2 *coef = reinterpret_cast<float2 *>(p->scratch + p->off_coef + coef_off);
     const float *w = reinterpret_cast<const float *>(p->scratch + p->off_w);
     double *part = reinterpret_cast<double *>(p->scratch + p->off_part);
     double *tot = reinterpret_cast<double *>(p->scratch + p->off_tot);
@@ -1026,6 +1053,7 @@ sb_status forward(sb_plan *p, const void *const *delta, double *zeta, hipStream_
     for (int f = 0; f < p->batch; ++f)
         if (!delta[f]) return fail(SB_EINVAL, "null field pointer");
     if (sb_status st = check_fields_finite(p, delta, s); st != SB_OK) return st;
+    p->kept = false;
     // fields of one shape go through the passes together, fbatch at a time (one launch per pass
     // for the whole batch); with fbatch = 1 the fields run one by one in their order
     auto run = [&](const ShapeGroup &G, const int *fidx, int nf) -> sb_status {
@@ -1037,7 +1065,8 @@ sb_status forward(sb_plan *p, const void *const *delta, double *zeta, hipStream_
         }
         if (p->chunk_groups < p->nlm && !(p->prob.npcf == 3 && p->fused))
             return fail(SB_EUNSUPPORTED, "this path needs every kernel array at once; raise the scratch limit");
-        if (p->prob.npcf == 3 && p->fused) return fused_3pcf(p, G, dl.data(), zo.data(), nf, s);
+        if (p->prob.npcf == 3 && p->fused)
+            return fused_3pcf(p, G, dl.data(), zo.data(), nf, p->keep ? p->keep_off[fidx[0]] : 0, s);
         sb_status st = density_spectrum(p, G, dl.data(), nf, s);
         if (st == SB_OK)   // array groups (packed m = 0 pairs first) where the plan packs
             st = p->npack > 0 ? coefficients(p, fidx[0], 0, p->nag, s, true, p->d_kmap, nf)
@@ -1050,14 +1079,18 @@ sb_status forward(sb_plan *p, const void *const *delta, double *zeta, hipStream_
             const sb_status st = run(p->groups[p->field_group[f]], &f, 1);
             if (st != SB_OK) return st;
         }
-        return SB_OK;
+    } else {
+        for (const auto &G : p->groups)
+            for (size_t b0 = 0; b0 < G.fields.size(); b0 += p->fbatch) {
+                const int nf = (int)std::min<size_t>(p->fbatch, G.fields.size() - b0);
+                const sb_status st = run(G, G.fields.data() + b0, nf);
+                if (st != SB_OK) return st;
+            }
     }
-    for (const auto &G : p->groups)
-        for (size_t b0 = 0; b0 < G.fields.size(); b0 += p->fbatch) {
-            const int nf = (int)std::min<size_t>(p->fbatch, G.fields.size() - b0);
-            const sb_status st = run(G, G.fields.data() + b0, nf);
-            if (st != SB_OK) return st;
-        }
+    if (p->keep) {   // every field's arrays now sit in its region for sb_backward
+        p->kept = true;
+        p->kept_delta.assign(delta, delta + p->batch);
+    }
     return SB_OK;
 }
 
@@ -1106,6 +1139,7 @@ sb_status sb_plan_bind(sb_plan *p, void *persistent, size_t persistent_bytes, vo
         return fail(SB_EINVAL, "workspace must be 256-byte aligned");
     p->persist = static_cast<char *>(persistent);
     p->scratch = static_cast<char *>(scratch);
+    p->kept = false;
     table_pointers(p);
     p->prepared = false;
     p->release_graph();

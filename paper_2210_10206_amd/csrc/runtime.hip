@@ -341,6 +341,7 @@ sb_status sb_forward_graph(sb_plan *p, const void *const *delta, double *zeta, v
     if (p->timing) return fail(SB_ESTATE, "disable per-launch timing before graph replay");
     if (p->prob.flags & SB_FLAG_CHECK_FINITE)
         return fail(SB_ESTATE, "a plan with SB_FLAG_CHECK_FINITE waits for its stream and cannot be captured");
+    p->kept = false;
     bool same = p->graph_exec && p->graph_zeta == zeta && p->graph_stream == s &&
                 (int)p->graph_delta.size() == p->batch;
     for (int f = 0; same && f < p->batch; ++f) same = p->graph_delta[f] == delta[f];
@@ -366,8 +367,13 @@ sb_status sb_forward_graph(sb_plan *p, const void *const *delta, double *zeta, v
         p->graph_zeta = zeta;
         p->graph_stream = s;
     }
+    p->kept = false;   // set by the capture, which ran nothing
     const hipError_t e = hipGraphLaunch(p->graph_exec, s);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    if (p->keep) {   // the replay keeps the arrays of the captured fields, which are these
+        p->kept = true;
+        p->kept_delta.assign(delta, delta + p->batch);
+    }
     return SB_OK;
 }
 

@@ -99,6 +99,15 @@ struct sb_plan {
     // half kernel store (ShapeGroup::half on the shapes it applies to): on request, when the
     // full store would pass kKernelCacheCap, and with regeneration
     bool half = false;
+    // SB_FLAG_KEEP_FOR_ADJOINT: each field's coefficient arrays (the middle pass's output) at
+    // off_coef + keep_off[f], the fields of a shape in its order (so every field batch of the
+    // forward sits at its own stride); the backward's v arrays at off_vkeep.  kept: the arrays
+    // hold the last forward's fields kept_delta and no backward has consumed them yet.
+    bool keep = false;
+    std::vector<size_t> keep_off;
+    size_t off_vkeep = 0;
+    bool kept = false;
+    std::vector<const void *> kept_delta;
     // kernel groups ((l, m) multiplets) whose arrays share the scratch at once: all of them,
     // unless a 3PCF plan's full set would exceed coef_limit (then the passes run in chunks)
     uint64_t coef_limit = 48ull << 30;

@@ -209,3 +209,32 @@ def test_1024_grid_plan_regenerates_kernels():
         prob4.flags |= 64
         rc, h = _plan(lib, prob4, [(16, 16, 16)])
         assert rc == -2 and not h.value
+
+
+def test_keep_for_adjoint_layout_and_scope():
+    """SB_FLAG_KEEP_FOR_ADJOINT gives every field its own region of coefficient arrays (the array
+    groups of the forward: with lmax 2 the packed (0, 0) + (1, 0) pair and the four other (l, m),
+    each with every bin) and the backward one more field's worth for its v arrays; it is refused
+    outside the fused 3D 3PCF path and with regenerated kernels."""
+    from paper_2210_10206_amd import _lib
+    lib = _lib.load()
+    shapes = [(16, 16, 16), (24, 24, 24), (16, 16, 16)]
+    sizes = {}
+    for flags in (0, 256, 256 | 16):
+        prob, e = _problem(edges=(0.0, 2.0, 4.0), lmax=2, flags=flags)
+        rc, h = _plan(lib, prob, shapes)
+        assert rc == 0, lib.sb_last_error()
+        pb, sbytes = ctypes.c_size_t(), ctypes.c_size_t()
+        assert lib.sb_plan_workspace(h, ctypes.byref(pb), ctypes.byref(sbytes)) == 0
+        sizes[flags] = sbytes.value
+        lib.sb_plan_destroy(h)
+    cells = 16 ** 3 * 2 + 24 ** 3
+    for flags, nag in ((256, 5), (256 | 16, 6)):
+        kept = nag * 2 * cells * 8 + nag * 2 * 24 ** 3 * 8
+        assert sizes[flags] >= kept
+        assert sizes[flags] - sizes[0] >= kept - 2 * 6 * 2 * 24 ** 3 * 8   # at most two fields' arrays at once before
+    for kw in (dict(ndim=2), dict(npcf=4), dict(flags=2), dict(flags=64), dict(flags=1)):
+        prob, _ = _problem(edges=(0.0, 2.0, 4.0), lmax=2, **kw)
+        prob.flags |= 256
+        rc, h = _plan(lib, prob, [(16, 16, 16)[:prob.ndim]])
+        assert rc == -2 and not h.value, kw

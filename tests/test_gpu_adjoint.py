@@ -224,3 +224,93 @@ def test_synthesis_reduces_loss(api):
     assert np.isfinite(losses[-1])
     assert losses[-1] < 0.2 * losses[0]
     plan.close()
+
+
+def test_keep_for_adjoint_matches_recompute(api):
+    """A plan that keeps each field's coefficient arrays through the forward
+    (SB_FLAG_KEEP_FOR_ADJOINT) gives the forward and the gradient of a plan that recomputes them:
+    the kept arrays are the forward's own middle-pass output, the recomputing backward runs the same
+    passes again.  Checked on an uneven batch (two shapes interleaved, so the kept regions are not
+    in field order) after sb_forward, for a second backward on the same arrays, after a forward on
+    other pointers (the backward must recompute), after graph replay and after sb_forward_noalloc."""
+    import ctypes
+    shapes = [(24, 24, 24), (16, 16, 16), (24, 24, 24), (16, 32, 16)]
+    edges, lmax = linear_edges(6, 3), 3
+    say(f"case: keep for adjoint, shapes {shapes}, 3 bins to 6, lmax {lmax}")
+    fields = [torch.from_numpy(lognormal_field(s, seed=40 + i, sigma=1.0)).cuda() for i, s in enumerate(shapes)]
+    rng = np.random.default_rng(7)
+    plain = api.Plan(shapes, edges, lmax, npcf=3)
+    keep = api.Plan(shapes, edges, lmax, npcf=3, keep_for_adjoint=True)
+    G = torch.from_numpy(rng.standard_normal((len(shapes), plain.zeta_doubles))).cuda()
+    z0 = plain.forward_raw(fields)
+    g0 = [g.cpu().numpy() for g in plain.backward(fields, G)]
+
+    def same_grads(got, what):
+        got = [g.cpu().numpy() for g in got]
+        for i, (a, b) in enumerate(zip(got, g0)):
+            e = float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+            say(f"  {what}: field {i} {shapes[i]} max rel diff {e:.2e}")
+            assert np.array_equal(a, b), (what, i)
+
+    z1 = keep.forward_raw(fields)
+    torch.cuda.synchronize()
+    assert torch.equal(z0, z1)
+
+    def axis0_launches(fn):
+        # axis-0 correlation passes of one backward: the accumulation per field, plus the
+        # recomputation of the coefficient arrays when they were not kept
+        keep.profile(True)
+        fn()
+        n = sum(r["kernel"] == 1 for r in keep.launch_records())
+        keep.profile(False)
+        return n
+
+    assert axis0_launches(lambda: same_grads(keep.backward(fields, G), "kept after sb_forward")) == len(shapes)
+    same_grads(keep.backward(fields, G), "kept, second backward")
+    G2 = torch.from_numpy(rng.standard_normal((len(shapes), plain.zeta_doubles))).cuda()
+    g2 = [g.cpu().numpy() for g in plain.backward(fields, G2)]
+    got2 = [g.cpu().numpy() for g in keep.backward(fields, G2)]
+    assert all(np.array_equal(a, b) for a, b in zip(got2, g2))
+    others = [f.clone() for f in fields]
+    keep.forward_raw(others)
+    assert axis0_launches(lambda: same_grads(keep.backward(fields, G), "recomputed after a forward on other pointers")) \
+        == 2 * len(shapes)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        z2 = keep.forward_raw(fields, stream=s, graph=True)
+        z2 = keep.forward_raw(fields, out=z2, stream=s, graph=True)
+    s.synchronize()
+    assert torch.equal(z0, z2)
+    same_grads(keep.backward(fields, G), "kept after graph replay")
+    out = torch.empty_like(z0)
+    rc = keep.lib.sb_forward_noalloc(keep.handle, keep._ptrs(fields), ctypes.c_void_p(out.data_ptr()), None)
+    assert rc == 0, keep.lib.sb_last_error()
+    torch.cuda.synchronize()
+    assert torch.equal(z0, out)
+    same_grads(keep.backward(fields, G), "recomputed after sb_forward_noalloc")
+    plain.close()
+    keep.close()
+
+
+def test_keep_for_adjoint_matches_recompute_at_192(api):
+    """The kept arrays at the uneven workload's largest edge (192^3, batched two fields per
+    launch with a 64^3 field between them; 8 bins to 16, lmax 4) give the recomputing plan's
+    gradient bit for bit, with both plans on the default launch shapes."""
+    shapes = [(192, 192, 192), (64, 64, 64), (192, 192, 192)]
+    edges, lmax = linear_edges(16, 8), 4
+    say(f"case: keep for adjoint, shapes {shapes}, 8 bins to 16, lmax {lmax}")
+    fields = [torch.from_numpy(lognormal_field(s, seed=60 + i, sigma=1.0)).cuda() for i, s in enumerate(shapes)]
+    G = torch.from_numpy(np.random.default_rng(8).standard_normal((len(shapes), 5 * 8 * 8))).cuda()
+    plain = api.Plan(shapes, edges, lmax, npcf=3)
+    z0 = plain.forward_raw(fields)
+    g0 = [g.cpu().numpy() for g in plain.backward(fields, G)]
+    plain.close()
+    del plain
+    keep = api.Plan(shapes, edges, lmax, npcf=3, keep_for_adjoint=True)
+    z1 = keep.forward_raw(fields)
+    g1 = [g.cpu().numpy() for g in keep.backward(fields, G)]
+    keep.close()
+    assert torch.equal(z0, z1)
+    for i, (a, b) in enumerate(zip(g1, g0)):
+        say(f"  field {i} {shapes[i]}: max rel diff {float(np.max(np.abs(a - b)) / np.max(np.abs(b))):.2e}")
+        assert np.array_equal(a, b), i
