@@ -1,24 +1,29 @@
-// Projected 4PCF contraction (Alg. 8) on the matrix cores: one launch, one grid row (blockIdx.y)
-// per canonical m triple.
+// Projected 4PCF contraction (Alg. 8) on the matrix cores: one launch over every (cell block,
+// canonical m triple), in an XCD-aware order (xcd_work).
 //
 // For the triple (m1, m2, m3 = -(m1 + m2)) and every cell x:
 //   L[b1 b2](x)    = w(x) c^b1_m1(x) c^b2_m2(x)          (vector ALU, one complex product)
 //   Z[b1 b2][b3]  += L[b1 b2](x) c^b3_m3(x)               (complex, on MFMA)
 // with c_{-m} = conj(c_m).  The second line is a GEMM with M = the NB^2 bin pairs (tiles of 16
 // rows: row i of tile mt is pair p = 16 mt + i = b1 NB + b2), N = b3 (padded to 16) and K = the
-// cells, taken as v_mfma_f32_16x16x4f32 with the four lane groups' cells as K: the real part
-// Lr Br - Li Bi and the imaginary part Lr Bi + Li Br are two MFMAs each.  Lane l = i + 16 g
-// supplies row i of the A tile and column i (b3 = i) of B for cell g of the four.
+// cells, taken as v_mfma_f32_16x16x4f32 with the four lane groups' cells as K.  The complex
+// product takes three real products instead of four (Gauss): with
+//   P1 = sum (Lr + Li) Br,   P2 = sum Lr (Bi - Br),   P3 = sum Li (Br + Bi)
+// the real part is P1 - P3 and the imaginary part P1 + P2, three MFMAs per four cells.  The
+// rounding error grows by at most about a factor of two (each product's operand is a sum of
+// two).  Lane l = i + 16 g supplies row i of the A tile and column i (b3 = i) of B for cell g
+// of the four.
 //
 // The float32 kernel has one wave per M tile: every wave contracts all cells of a staged tile
 // against its own 16 pairs, so it holds one tile's accumulators (8 registers), the waves need no
 // combine at the end, and the small register count leaves room for several workgroups per CU.
-// The float32 sums of each staged tile are added to float64 totals.
+// The float32 sums of each staged tile are combined into the real and imaginary parts in
+// float64 (exactly) and added to float64 totals.
 //
 // Staging as in the full-4PCF matrix-core kernels: a tile of 64 cells in LDS, cell-major, one
 // row of 3 NB float2 (the m1, m2, m3 columns) per cell padded to a stride = 2 (mod 8) float2
 // (bank-conflict free stores and reads), the next tile's global loads issued before the current
-// one is contracted.  Block partials: partial[(pair * NB^3 * 2 + (p NB + b3) 2 + part) * nblocks
+// one is contracted and staged into a second buffer after it.  Block partials: partial[(pair * NB^3 * 2 + (p NB + b3) 2 + part) * nblocks
 // + block], as for the vector kernel.
 #include "sb_kgen.h"
 
@@ -30,35 +35,54 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 template <int NB>
 constexpr int proj4_tiles() { return (NB * NB + 15) / 16; }
 
+// Work of block b: the chip deals the workgroups of a launch to its eight XCDs in turn (b to
+// XCD b mod 8), and each XCD has an L2 of its own.  Work item w = c T + t (cell block c, triple
+// t of T) goes to block b with w = (b mod 8) per + b / 8, so an XCD runs a contiguous range of
+// w: all triples of a cell block one after the other, while that block's coefficient columns
+// (every m of the cell range) stay in its L2.  Blocks past the last item return false.
+__device__ __forceinline__ bool xcd_work(int b, int nblocks, int ntriples, int *cb, int *tr) {
+    const int total = nblocks * ntriples;
+    const int per = (total + 7) / 8;
+    const int w = (b % 8) * per + b / 8;
+    if (w >= total) return false;
+    *cb = w / ntriples;
+    *tr = w % ntriples;
+    return true;
+}
+
 template <int NB>
 __global__ __launch_bounds__(64 * proj4_tiles<NB>()) void proj4_mfma_kernel(Proj4Args a) {
     a.coef += (int64_t)blockIdx.z * a.coef_fs;   // field of the launch (grid.z)
     a.w += (int64_t)blockIdx.z * a.w_fs;
     a.partial += (int64_t)blockIdx.z * a.part_fs;
+    int cb = 0, pr_ = 0;
+    if (!xcd_work(blockIdx.x, a.nblocks, a.npairs, &cb, &pr_)) return;
     constexpr int NP = NB * NB;
     constexpr int NMT = proj4_tiles<NB>();     // M tiles of 16 pairs = waves
     constexpr int NT = 64 * NMT;
     constexpr int TC = 64;                     // cells per staged tile
-    constexpr int W = 3 * NB;                  // staged float2 per cell
+    constexpr int WL = 3 * NB;                 // loaded float2 per cell (m1, m2, m3 columns)
+    constexpr int W = 4 * NB;                  // staged float2 per cell (see stage)
     constexpr int S = (W + 7) / 8 * 8 + 2;     // padded row stride, = 2 (mod 8)
-    constexpr int NLD = (TC * W + NT - 1) / NT;   // staged float2 per thread and tile
+    constexpr int NLD = (TC * WL + NT - 1) / NT;   // loaded float2 per thread and tile
     constexpr int NV = NB * NB * NB * 2;
-    __shared__ float2 tile[TC * S];
-    __shared__ float wt[TC];
-    const int pr_ = blockIdx.y;
+    static_assert(NT % TC == 0, "every load of a thread is of the cell of its lane");
+    __shared__ float2 tiles[2][TC * S];        // double-buffered: one barrier per staged tile
     const int tid = threadIdx.x, lane = tid & 63;
     const int mt = __builtin_amdgcn_readfirstlane(tid >> 6);   // this wave's M tile
     const int i = lane & 15, g = lane >> 4;
     const int m1 = a.pairs[2 * pr_], m2 = a.pairs[2 * pr_ + 1];
     const int ms[3] = {m1, m2, -(m1 + m2)};
     const int p = 16 * mt + i;                 // pair of this lane's row
-    const bool prow = p < NP;
-    const int b1 = prow ? p / NB : 0, b2 = prow ? p % NB : 0;
-    f4v accr = f4v{0.f, 0.f, 0.f, 0.f}, acci = f4v{0.f, 0.f, 0.f, 0.f};
+    // rows past the last pair and columns past the last bin read bin 0 / bin NB - 1 (valid LDS
+    // addresses, no branch in the cell loop); their sums are never written
+    const int b1 = p < NP ? p / NB : 0, b2 = p < NP ? p % NB : 0;
+    const int ib = i < NB ? i : NB - 1;
+    f4v acc1 = f4v{0.f, 0.f, 0.f, 0.f}, acc2 = acc1, acc3 = acc1;
     double totr[4] = {0.0, 0.0, 0.0, 0.0}, toti[4] = {0.0, 0.0, 0.0, 0.0};
-    const int64_t c0 = (int64_t)blockIdx.x * a.cells_per_block;
+    const int64_t c0 = (int64_t)cb * a.cells_per_block;
     const int64_t c1 = min(c0 + a.cells_per_block, a.ng);
-    // load k of this thread: f = tid + NT k -> cell f % 64, staged column (k3 = slot, bin) f / 64
+    // load k of this thread: f = tid + NT k -> cell f % 64 (= lane), loaded column (slot, bin) f / 64
     float2 pf[NLD];
     float pw = 0.f;
     auto gload = [&](int64_t tc) {
@@ -67,7 +91,7 @@ __global__ __launch_bounds__(64 * proj4_tiles<NB>()) void proj4_mfma_kernel(Proj
             const int f = tid + NT * k;
             const int c = f % TC, kb = f / TC;
             float2 v = make_float2(0.f, 0.f);
-            if (kb < W && tc + c < c1) {
+            if (kb < WL && tc + c < c1) {
                 const int slot = kb / NB, b = kb % NB;
                 const int m = ms[slot];
                 v = a.coef[((int64_t)(m < 0 ? -m : m) * NB + b) * a.ng + tc + c];
@@ -75,45 +99,64 @@ __global__ __launch_bounds__(64 * proj4_tiles<NB>()) void proj4_mfma_kernel(Proj
             }
             pf[k] = v;
         }
-        if (mt == 0) pw = tc + lane < c1 ? a.w[tc + lane] : 0.f;
+        pw = tc + lane < c1 ? a.w[tc + lane] : 0.f;
     };
-    gload(c0);
-    for (int64_t tc = c0; tc < c1; tc += TC) {
-        __syncthreads();
+    // a staged row holds, per bin, w c_m1 (the weight folded in once here instead of in every
+    // wave), c_m2, (Br, Bi - Br) and (Br + Bi, 0) of B = c_m3: every operand of the three
+    // products, formed once per cell rather than once per wave
+    auto stage = [&](int buf) {
 #pragma unroll
         for (int k = 0; k < NLD; ++k) {
             const int f = tid + NT * k;
             const int c = f % TC, kb = f / TC;
-            if (kb < W) tile[c * S + kb] = pf[k];
+            float2 *row = tiles[buf] + c * S;
+            const float2 v = pf[k];
+            if (kb < NB) {
+                row[kb] = make_float2(pw * v.x, pw * v.y);
+            } else if (kb < 2 * NB) {
+                row[kb] = v;
+            } else if (kb < WL) {
+                row[kb] = make_float2(v.x, v.y - v.x);
+                row[kb + NB] = make_float2(v.x + v.y, 0.f);
+            }
         }
-        if (mt == 0) wt[lane] = pw;
-        __syncthreads();
-        if (tc + TC < c1) gload(tc + TC);
-#pragma unroll 4
+    };
+    // tile t is contracted from buffer t % 2 while tile t + 1 is loaded into registers, then
+    // staged into the other buffer; the barrier after it makes that buffer readable and frees
+    // this one for tile t + 2
+    gload(c0);
+    stage(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t tc = c0; tc < c1; tc += TC, buf ^= 1) {
+        const bool more = tc + TC < c1;
+        if (more) gload(tc + TC);
+        const float2 *tile = tiles[buf];
+#pragma unroll 2
         for (int cc = 0; cc < TC / 4; ++cc) {
             const int c = 4 * cc + g;
             const float2 *row = tile + c * S;
-            const float wv = wt[c];
-            const float2 bv = i < NB ? row[2 * NB + i] : make_float2(0.f, 0.f);
-            float2 L = make_float2(0.f, 0.f);
-            if (prow) {
-                const float2 x1 = row[b1], x2 = row[NB + b2];
-                const float2 u = make_float2(wv * x1.x, wv * x1.y);
-                L.x = __builtin_fmaf(u.x, x2.x, -u.y * x2.y);
-                L.y = __builtin_fmaf(u.x, x2.y, u.y * x2.x);
-            }
-            accr = __builtin_amdgcn_mfma_f32_16x16x4f32(L.x, bv.x, accr, 0, 0, 0);
-            accr = __builtin_amdgcn_mfma_f32_16x16x4f32(-L.y, bv.y, accr, 0, 0, 0);
-            acci = __builtin_amdgcn_mfma_f32_16x16x4f32(L.x, bv.y, acci, 0, 0, 0);
-            acci = __builtin_amdgcn_mfma_f32_16x16x4f32(L.y, bv.x, acci, 0, 0, 0);
+            const float2 bv = row[2 * NB + ib];       // (Br, Bi - Br)
+            const float bs = row[3 * NB + ib].x;      // Br + Bi
+            const float2 u = row[b1], x2 = row[NB + b2];   // u = w c_m1
+            float2 L;
+            L.x = __builtin_fmaf(u.x, x2.x, -u.y * x2.y);
+            L.y = __builtin_fmaf(u.x, x2.y, u.y * x2.x);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(L.x + L.y, bv.x, acc1, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(L.x, bv.y, acc2, 0, 0, 0);
+            acc3 = __builtin_amdgcn_mfma_f32_16x16x4f32(L.y, bs, acc3, 0, 0, 0);
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            totr[r] += (double)accr[r];
-            toti[r] += (double)acci[r];
+        for (int r = 0; r < 4; ++r) {   // P1 - P3 and P1 + P2, exact in float64
+            const double p1 = (double)acc1[r];
+            totr[r] += p1 - (double)acc3[r];
+            toti[r] += p1 + (double)acc2[r];
         }
-        accr = f4v{0.f, 0.f, 0.f, 0.f};
-        acci = f4v{0.f, 0.f, 0.f, 0.f};
+        acc1 = f4v{0.f, 0.f, 0.f, 0.f};
+        acc2 = acc1;
+        acc3 = acc1;
+        if (more) stage(buf ^ 1);
+        __syncthreads();
     }
     // accumulator: lane l holds rows 4 g + r (pair 16 mt + 4 g + r), column i (bin b3); each
     // (pair, b3, part) of the block is held by exactly one lane
@@ -122,8 +165,8 @@ __global__ __launch_bounds__(64 * proj4_tiles<NB>()) void proj4_mfma_kernel(Proj
         const int pp = 16 * mt + 4 * g + r;
         if (pp < NP && i < NB) {
             const int64_t v = (int64_t)pr_ * NV + (pp * NB + i) * 2;
-            a.partial[v * a.nblocks + blockIdx.x] = totr[r];
-            a.partial[(v + 1) * a.nblocks + blockIdx.x] = toti[r];
+            a.partial[v * a.nblocks + cb] = totr[r];
+            a.partial[(v + 1) * a.nblocks + cb] = toti[r];
         }
     }
 }
@@ -147,6 +190,8 @@ __global__ __launch_bounds__(256, 2) void proj4_split_kernel(Proj4Args a) {
     a.coef += (int64_t)blockIdx.z * a.coef_fs;   // field of the launch (grid.z)
     a.w += (int64_t)blockIdx.z * a.w_fs;
     a.partial += (int64_t)blockIdx.z * a.part_fs;
+    int cb = 0, pr_ = 0;
+    if (!xcd_work(blockIdx.x, a.nblocks, a.npairs, &cb, &pr_)) return;
     constexpr int NP = NB * NB;
     constexpr int NMT = (NP + 15) / 16;        // M tiles of 16 pairs
     constexpr int NNT = (2 * NB + 15) / 16;    // N tiles of 8 (b3, part) column pairs
@@ -159,7 +204,6 @@ __global__ __launch_bounds__(256, 2) void proj4_split_kernel(Proj4Args a) {
     __shared__ float2 tile[NTILE];
     __shared__ float wt[TC];
     float *red = reinterpret_cast<float *>(tile);
-    const int pr_ = blockIdx.y;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int i = lane & 15, g = lane >> 4;
@@ -177,7 +221,7 @@ __global__ __launch_bounds__(256, 2) void proj4_split_kernel(Proj4Args a) {
     for (int mt = 0; mt < NMT; ++mt)
 #pragma unroll
         for (int t = 0; t < NNT; ++t) acc[mt][t] = f4v{0.f, 0.f, 0.f, 0.f};
-    const int64_t c0 = (int64_t)blockIdx.x * a.cells_per_block;
+    const int64_t c0 = (int64_t)cb * a.cells_per_block;
     const int64_t c1 = min(c0 + a.cells_per_block, a.ng);
     float2 pf[NLD];
     float pw = 0.f;
@@ -263,13 +307,14 @@ __global__ __launch_bounds__(256, 2) void proj4_split_kernel(Proj4Args a) {
     __syncthreads();
     for (int v = tid; v < NV; v += 256) {
         const double s = ((double)red[v] + (double)red[NV + v]) + ((double)red[2 * NV + v] + (double)red[3 * NV + v]);
-        a.partial[((int64_t)pr_ * NV + v) * a.nblocks + blockIdx.x] = s;
+        a.partial[((int64_t)pr_ * NV + v) * a.nblocks + cb] = s;
     }
 }
 
 template <int NB>
 hipError_t launch_nb(const Proj4Args &a, hipStream_t s) {
-    dim3 grid((unsigned)a.nblocks, (unsigned)a.npairs, (unsigned)(a.fields > 1 ? a.fields : 1));
+    const int64_t total = (int64_t)a.nblocks * a.npairs;   // one block per item, 8 | grid.x (xcd_work)
+    dim3 grid((unsigned)((total + 7) / 8 * 8), 1, (unsigned)(a.fields > 1 ? a.fields : 1));
     if (a.precision == 1)
         hipLaunchKernelGGL((proj4_split_kernel<NB>), grid, dim3(256), 0, s, a);
     else
