@@ -603,10 +603,12 @@ def run_proj(api, steps, warmup):
                     kn = ("proj4_split_kernel<10> (split-BF16 bf16 16x16x32 MFMA" if precision == "split_bf16"
                           else "proj4_mfma_kernel<10> (float32 16x16x4 MFMA")
                     r["contraction"] = {
-                        "kernel": kn + ", one launch, a grid row per canonical m triple)",
-                        "flops_note": "executed work: per cell and canonical triple NB^2 (8 + 8 NB) flops, the pair "
-                                      "products on the VALU and the complex b3 contraction on MFMA, against the "
-                                      "float32 peak",
+                        "kernel": kn + ", one launch over the (cell block, canonical m triple) items, "
+                                       "XCD-aware order)",
+                        "flops_note": "complex-arithmetic work: per cell and canonical triple NB^2 (8 + 8 NB) flops "
+                                      "(w c_m1 c_m2 per pair, a complex multiply-add per (pair, b3)), against the "
+                                      "float32 peak; the float32 kernel issues the multiply-adds as three real "
+                                      "products (Gauss), 3/4 of these flops on MFMA",
                         "achieved_tflops": round(fl / (ms * 1e-3) / 1e12, 2), "peak_tflops": 157.3,
                         "frac": round(fl / (ms * 1e-3) / 1e12 / 157.3, 4),
                         "counters": counters_for(f"proj4_prec{1 if precision == 'split_bf16' else 0}",
