@@ -331,7 +331,8 @@ def run_4pcf_batch(api, steps, warmup, count=16, precision="fp32", mfma=True, pa
 
 def run_c5(api, steps, warmup, synth_steps=200):
     """Forward + adjoint of the uneven 48-field batch (edges drawn from 64/96/128/160/192,
-    sigma 1 lognormal), 8 bins to 16, lmax 4, one plan; then the synthesis demo: 200 Adam
+    sigma 1 lognormal), 8 bins to 16, lmax 4, one plan, then on a plan that keeps the forward's arrays for
+    the adjoint; then the synthesis demo (a keeping plan): 200 Adam
     steps at 128^3 from a Gaussian field towards the sums of the seed-100 lognormal field."""
     import numpy as np
     import torch
@@ -447,7 +448,7 @@ def run_c5(api, steps, warmup, synth_steps=200):
     if synth_steps <= 0:
         return res
     n = 128
-    sp = api.Plan([(n, n, n)], edges, 4, npcf=3)
+    sp = api.Plan([(n, n, n)], edges, 4, npcf=3, keep_for_adjoint=True)   # each step's backward reads the forward's arrays
     sp.autotune(torch.cuda.current_stream())
     target = sp.forward([torch.from_numpy(lognormal_field((n,) * 3, seed=100, sigma=1.0)).cuda()])[0]
     init = torch.from_numpy(gaussian_field((n,) * 3, seed=101)).cuda()
@@ -459,7 +460,7 @@ def run_c5(api, steps, warmup, synth_steps=200):
     sp.close()
     res["synthesis"] = {"grid": n, "steps": synth_steps, "seconds": round(t4 - t3, 3),
                         "ms_per_step": round((t4 - t3) / synth_steps * 1e3, 3),
-                        "loss_start": losses[0], "loss_end": losses[-1]}
+                        "loss_start": losses[0], "loss_end": losses[-1], "kept_for_adjoint": True}
     return res
 
 

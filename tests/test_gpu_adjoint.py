@@ -224,6 +224,14 @@ def test_synthesis_reduces_loss(api):
     assert np.isfinite(losses[-1])
     assert losses[-1] < 0.2 * losses[0]
     plan.close()
+    # the same run on a plan that keeps the forward's arrays for the adjoint (each step's backward
+    # then reads them) follows the same trajectory bit for bit
+    keep = api.Plan([(n, n, n)], edges, 4, npcf=3, keep_for_adjoint=True)
+    delta_k, losses_k = synthesize(keep, target, init, steps=60, lr=0.05)
+    torch.cuda.synchronize()
+    assert losses_k == losses
+    assert torch.equal(delta_k, delta)
+    keep.close()
 
 
 def test_keep_for_adjoint_matches_recompute(api):
