@@ -173,6 +173,16 @@ __global__ __launch_bounds__(NBT * R * TPP) void adj_last_kernel(AdjLastArgs a) 
 // With two stages the transforms exchange through one buffer, which the [cell][bin] view then
 // reuses (one more barrier per row); that and at most 168 VGPRs (3 waves per SIMD) let four
 // 3-wave workgroups share a CU instead of two at 256 points and 12 padded bins.
+//
+// LDS layout: position j of pencil p at j * (P + 1) + p, and at 256 points with one skew slot
+// every 16 positions (+ j >> 4).  The first stage writes positions q R0 + r: in the plain layout
+// the threads of a pencil sit R0 (P + 1) float2 apart, a multiple of the 16 float2 that span the
+// 32 banks, so they all meet in one bank; the skew spreads them.  A bank model of every exchange,
+// transpose and per-cell access (32 banks, 16 lanes per float2 phase; it reproduces the measured
+// conflict share of the plain layout, 67 % of the LDS cycles at 128 points) puts the skewed
+// layout at 0.21 of the plain one's LDS cycles at 256 points, and the pass there runs 25 %
+// faster (8 bins: 9.8 -> 7.4 ms per 13 launches).  At 128 points (0.31 in the model) the time did
+// not move, and 64 and 160 points were slower with it, so the other lengths keep the plain layout.
 constexpr int adj_rs_min_waves(int nstage, int nt) { return nstage == 2 && nt >= 192 ? 3 : 1; }
 
 template <int N, int NBT, bool PACK, int R0, int... REST>
@@ -180,13 +190,15 @@ __global__ __launch_bounds__(NBT * (N / R0), adj_rs_min_waves(1 + sizeof...(REST
     AdjLastArgs a) {
     constexpr int T = N / R0;
     constexpr int P = NBT, PITCH = P + 1, NT = P * T;
+    constexpr int SKEW = N == 256 ? 1 : 0, GSH = 4;   // layout above
     constexpr int NSTAGE = 1 + sizeof...(REST);
     constexpr bool ONE = NSTAGE == 2;           // one exchange buffer
     constexpr int CSB = ONE ? 0 : (NSTAGE - 1) % 2;   // buffer of the [cell][bin] view
     constexpr int CPT = (N + NT - 1) / NT;      // cells per thread in the per-cell phase
     static_assert(NSTAGE >= 2, "two stages or more");
     static_assert(NBT <= 16, "the weight table is 16 x 16");
-    __shared__ float2 ex[ONE ? 1 : 2][N * PITCH];
+    __shared__ float2 ex[ONE ? 1 : 2][N * PITCH + (N >> GSH) * SKEW];
+    auto at = [](int j, int b) { return j * PITCH + b + (j >> GSH) * SKEW; };
     float2 *ex1 = ex[ONE ? 0 : 1];
     __shared__ float2 tw[N];
     typedef const __attribute__((address_space(4))) float cfloat;
@@ -231,11 +243,11 @@ __global__ __launch_bounds__(NBT * (N / R0), adj_rs_min_waves(1 + sizeof...(REST
         for (int k = 0; k < CPT; ++k) { cw[k] = nw[k]; cd[k] = nd[k]; }
         if (row + 1 < r_end) load_row(row + 1, nx, nw, nd);   // next row in flight
         __syncthreads();                                       // the previous row's buffers are free
-        reg_stages<N, 1, R0, REST...>(v, ex[0], ex1, tw, q, pp, PITCH);   // inverse
+        reg_stages<N, 1, R0, REST...>(v, ex[0], ex1, tw, q, pp, PITCH, SKEW, GSH);   // inverse
         float2 *cs = ex[CSB];
         if constexpr (ONE) __syncthreads();   // the last stage has read the exchange buffer
 #pragma unroll
-        for (int r = 0; r < R0; ++r) cs[(q + T * r) * PITCH + pp] = v[r];
+        for (int r = 0; r < R0; ++r) cs[at(q + T * r, pp)] = v[r];
         __syncthreads();
         // per cell: h = G conj(a), the direct term and v = w_m delta h (whole cells per thread)
 #pragma unroll
@@ -244,7 +256,7 @@ __global__ __launch_bounds__(NBT * (N / R0), adj_rs_min_waves(1 + sizeof...(REST
             if (c >= N) continue;
             float2 av[NBT];
 #pragma unroll
-            for (int b = 0; b < NBT; ++b) av[b] = cs[c * PITCH + b];
+            for (int b = 0; b < NBT; ++b) av[b] = cs[at(c, b)];
             const float dw = a.wm * cw[k];
             float d = 0.f;
 #pragma unroll
@@ -259,15 +271,15 @@ __global__ __launch_bounds__(NBT * (N / R0), adj_rs_min_waves(1 + sizeof...(REST
                 }
                 d = __builtin_fmaf(av[b1].x, hx, d);
                 d = __builtin_fmaf(-av[b1].y, hy, d);
-                cs[c * PITCH + b1] = make_float2(dw * hx, dw * hy);
+                cs[at(c, b1)] = make_float2(dw * hx, dw * hy);
             }
             a.dsum[row * N + c] = cd[k] + a.wm * d;   // cd = 0 on the first group
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < R0; ++r) v[r] = cs[(q + T * r) * PITCH + pp];
+        for (int r = 0; r < R0; ++r) v[r] = cs[at(q + T * r, pp)];
         __syncthreads();                                       // cs may be the first exchange buffer
-        reg_stages<N, -1, R0, REST...>(v, ex[0], ex1, tw, q, pp, PITCH);  // forward
+        reg_stages<N, -1, R0, REST...>(v, ex[0], ex1, tw, q, pp, PITCH, SKEW, GSH);  // forward
         if (live) {
             float2 *out = a.out + (int64_t)pp * a.ng + flip_row(row) * N;
 #pragma unroll

@@ -254,12 +254,15 @@ __device__ __forceinline__ void stages(float2 *sm, const float2 *tw, int p, int 
 // With radices R0, ..., RL (RL divides R0) thread q < T = n / R0 of a pencil owns elements
 // q + T s (s < R0): the inputs of first-stage butterfly q and the outputs of last-stage
 // butterflies q + T t (t < R0 / RL), which write positions q + T t + (n / RL) r.  The stages in
-// between exchange through two LDS buffers stored as buf[j * pitch + p] (pencil p), used
-// alternately, so each exchange needs one barrier (passing the same buffer twice costs a
-// second barrier per exchange).  v[s] holds element q + T s on entry and on exit.
+// between exchange through two LDS buffers stored as buf[j * pitch + p + (j >> gsh) * skew]
+// (pencil p; the skew, one extra slot every 2^gsh positions, is 0 unless a caller lays its
+// buffers out that way), used alternately, so each exchange needs one barrier (passing the
+// same buffer twice costs a second barrier per exchange).  v[s] holds element q + T s on entry
+// and on exit.
 template <int N, int T, int SIGN, int NS, int R, int... REST>
 __device__ __forceinline__ void reg_stage_rest(float2 *v, float2 *b0, float2 *b1, const float2 *tw, int q, int p,
-                                               int pitch) {
+                                               int pitch, int skew = 0, int gsh = 0) {
+    auto at = [&](int j) { return j * pitch + p + (j >> gsh) * skew; };
     constexpr int NBF = N / R;        // butterflies of this stage
     constexpr int PER = NBF / T;      // per thread
     static_assert(NBF % T == 0, "butterflies must split evenly over the threads");
@@ -271,7 +274,7 @@ __device__ __forceinline__ void reg_stage_rest(float2 *v, float2 *b0, float2 *b1
         const int kk = k % NS;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            float2 x = b0[(k + r * NBF) * pitch + p];
+            float2 x = b0[at(k + r * NBF)];
             if (r > 0) {
                 float2 w = tw[kk * r * (N / (NS * R))];
                 if (SIGN > 0) w.y = -w.y;
@@ -294,21 +297,24 @@ __device__ __forceinline__ void reg_stage_rest(float2 *v, float2 *b0, float2 *b1
             const int k = q + T * t;
             const int base = (k / NS) * NS * R + k % NS;
 #pragma unroll
-            for (int r = 0; r < R; ++r) b1[(base + r * NS) * pitch + p] = u[t][r];
+            for (int r = 0; r < R; ++r) b1[at(base + r * NS)] = u[t][r];
         }
         __syncthreads();
-        reg_stage_rest<N, T, SIGN, NS * R, REST...>(v, b1, b0, tw, q, p, pitch);
+        reg_stage_rest<N, T, SIGN, NS * R, REST...>(v, b1, b0, tw, q, p, pitch, skew, gsh);
     }
 }
 
 template <int N, int SIGN, int R0, int... REST>
 __device__ __forceinline__ void reg_stages(float2 *v, float2 *b0, float2 *b1, const float2 *tw, int q, int p,
-                                           int pitch) {
+                                           int pitch, int skew = 0, int gsh = 0) {
     Dft<R0, SIGN>::run(v);   // first stage: butterfly q on the own elements, no twiddles
 #pragma unroll
-    for (int r = 0; r < R0; ++r) b0[(q * R0 + r) * pitch + p] = v[r];
+    for (int r = 0; r < R0; ++r) {
+        const int j = q * R0 + r;
+        b0[j * pitch + p + (j >> gsh) * skew] = v[r];
+    }
     __syncthreads();
-    reg_stage_rest<N, N / R0, SIGN, R0, REST...>(v, b0, b1, tw, q, p, pitch);
+    reg_stage_rest<N, N / R0, SIGN, R0, REST...>(v, b0, b1, tw, q, p, pitch, skew, gsh);
 }
 
 __device__ __forceinline__ double wave_sum64(double v) {

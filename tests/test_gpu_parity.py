@@ -531,11 +531,12 @@ def test_full4pcf_lmax3_six_bins(sb):
 
 # ------------------------------------------------------------------ adjoint
 
-@pytest.mark.parametrize("shape,nbins", [((8, 16, 256), 10), ((8, 12, 64), 3), ((12, 8, 160), 16), ((256, 8, 12), 6)])
+@pytest.mark.parametrize("shape,nbins", [((8, 16, 256), 10), ((8, 12, 64), 3), ((12, 8, 160), 16), ((256, 8, 12), 6),
+                                         ((8, 8, 256), 3), ((8, 12, 256), 7), ((12, 8, 256), 16)])
 def test_adjoint_register_last_pass(sb, shape, nbins):
-    # the register-resident adjoint last pass at last-axis lengths 256, 64 and 160, with 12, 4
-    # and 16 padded bins, and the register-resident adjoint axis-0 accumulation at 256, against
-    # the oracle's gradient at 24 sampled cells
+    # the register-resident adjoint last pass at last-axis lengths 256 (4, 8, 12 and 16 padded
+    # bins: the skewed LDS layout), 64 and 160 (4 and 16 padded bins), and the register-resident
+    # adjoint axis-0 accumulation at 256, against the oracle's gradient at 24 sampled cells
     say(f"case: {shape} adjoint, {nbins} bins to 6, lmax 3, gradient at 24 cells")
     d = lognormal_field(shape, seed=41, sigma=1.0)
     edges = linear_edges(6, nbins)
