@@ -105,19 +105,22 @@ enum {
                                  Chosen automatically when the full cache would exceed 64 GiB and
                                  with SB_FLAG_REGEN_KERNELS (it halves the planes generated);
                                  without effect on 2D plans and on the other shapes */
-    SB_FLAG_KEEP_FOR_ADJOINT = 256u, /* fused 3D full 3PCF plans: every sb_forward keeps each field's coefficient
-                                 arrays before the last axis (the middle pass's output, N_ag array groups x
-                                 N_b bins per field) in scratch, one region per field, and an sb_backward
-                                 that follows on the same density pointers reads them instead of running the
-                                 axis-0 and middle passes again (about half of its work).  The scratch
-                                 grows to every field's arrays at once plus one field's arrays for the
+    SB_FLAG_KEEP_FOR_ADJOINT = 256u, /* fused 3D full 3PCF plans: every sb_forward keeps each
+                                 field's coefficient arrays before the last axis (the middle pass's
+                                 output: N_ag array groups x N_b bins per field) in scratch, one
+                                 region per field, and an sb_backward that follows on the same
+                                 density pointers reads them instead of running the axis-0 and
+                                 middle passes again (about 30 % of its time).  The scratch grows to
+                                 every field's arrays at once plus one field's arrays for the
                                  backward (sb_plan_workspace; the scratch limit does not chunk such
                                  plans).  The kept arrays belong to the last sb_forward /
-                                 sb_forward_graph on the bound scratch; sb_backward only reads them, so
-                                 several may follow.  An sb_backward on other density pointers, and one
-                                 after sb_forward_noalloc, a rebind or a layout change, recomputes them
-                                 (same result) and drops what was kept.  SB_EUNSUPPORTED on other paths
-                                 and with SB_FLAG_REGEN_KERNELS */
+                                 sb_forward_graph on the bound scratch; sb_backward only reads them,
+                                 so several may follow, and the caller must not change the density
+                                 values in between (the pointers are all that is compared).  An
+                                 sb_backward on other density pointers, and one after
+                                 sb_forward_noalloc, sb_autotune, a rebind or a layout change,
+                                 recomputes them (same result) and drops what was kept.
+                                 SB_EUNSUPPORTED on other paths and with SB_FLAG_REGEN_KERNELS */
     SB_FLAG_CHECK_FINITE = 32u /* sb_forward / sb_backward / sb_normalize first scan every input array
                                  (densities, and grad_zeta) for NaN and Inf and return SB_ENONFINITE,
                                  with no other work done, when one holds any.  The scan waits for the

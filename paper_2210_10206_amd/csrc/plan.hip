@@ -1052,8 +1052,8 @@ sb_status forward(sb_plan *p, const void *const *delta, double *zeta, hipStream_
     if (!p->prepared) return fail(SB_ESTATE, "sb_prepare has not run on the bound workspace");
     for (int f = 0; f < p->batch; ++f)
         if (!delta[f]) return fail(SB_EINVAL, "null field pointer");
+    p->kept = false;   // also when the scan below rejects the fields
     if (sb_status st = check_fields_finite(p, delta, s); st != SB_OK) return st;
-    p->kept = false;
     // fields of one shape go through the passes together, fbatch at a time (one launch per pass
     // for the whole batch); with fbatch = 1 the fields run one by one in their order
     auto run = [&](const ShapeGroup &G, const int *fidx, int nf) -> sb_status {

@@ -151,6 +151,7 @@ sb_status sb_autotune(sb_plan *p, void *stream, const char *cache_path) {
     if (!p) return fail(SB_EINVAL, "null plan");
     if (!p->persist || !p->scratch) return fail(SB_EWORKSPACE, "workspace not bound");
     if (!p->prepared) return fail(SB_ESTATE, "sb_prepare has not run");
+    p->kept = false;   // the timed passes run in the scratch the kept arrays live in
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::string key;
     std::vector<std::pair<std::string, std::string>> entries;
