@@ -552,10 +552,10 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
     constexpr int NW = NT / 64;
     constexpr int NOUT = PS::NOUT;
     constexpr int PITCH = P + 1;
-    // at 1024 points (first radix 16) position j of pencil p sits at j PITCH + p + j / 16: the
-    // first stage writes positions q R0 + r, which without the skew put a pencil's threads a
+    // at 512 and 1024 points (first radix 16) position j of pencil p sits at j PITCH + p + j / 16:
+    // the first stage writes positions q R0 + r, which without the skew put a pencil's threads a
     // multiple of 16 float2 (the width of the 32 banks) apart, all in one bank
-    constexpr int SKEW = N == 1024 ? 1 : 0, GSH = 4;
+    constexpr int SKEW = N >= 512 ? 1 : 0, GSH = 4;
     constexpr int NSTAGE = 1 + sizeof...(REST);
     constexpr int WPT = (N + NT - 1) / NT;
     static_assert(NT % 64 == 0 && NSTAGE >= 2, "whole waves, two stages or more");
