@@ -2,7 +2,7 @@
 // canonical m triple), in an XCD-aware order (xcd_work).
 //
 // For the triple (m1, m2, m3 = -(m1 + m2)) and every cell x:
-//   L[b1 b2](x)    = w(x) c^b1_m1(x) c^b2_m2(x)          (vector ALU, one complex product)
+//   L[b1 b2](x)    = (w c^b1_m1)(x) c^b2_m2(x)           (vector ALU, one complex product)
 //   Z[b1 b2][b3]  += L[b1 b2](x) c^b3_m3(x)               (complex, on MFMA)
 // with c_{-m} = conj(c_m).  The second line is a GEMM with M = the NB^2 bin pairs (tiles of 16
 // rows: row i of tile mt is pair p = 16 mt + i = b1 NB + b2), N = b3 (padded to 16) and K = the
@@ -15,16 +15,17 @@
 // of the four.
 //
 // The float32 kernel has one wave per M tile: every wave contracts all cells of a staged tile
-// against its own 16 pairs, so it holds one tile's accumulators (8 registers), the waves need no
-// combine at the end, and the small register count leaves room for several workgroups per CU.
+// against its own 16 pairs, so it holds one tile's three accumulators (12 registers), the waves
+// need no combine at the end, and the small register count leaves room for two workgroups per CU.
 // The float32 sums of each staged tile are combined into the real and imaginary parts in
 // float64 (exactly) and added to float64 totals.
 //
 // Staging as in the full-4PCF matrix-core kernels: a tile of 64 cells in LDS, cell-major, one
-// row of 3 NB float2 (the m1, m2, m3 columns) per cell padded to a stride = 2 (mod 8) float2
-// (bank-conflict free stores and reads), the next tile's global loads issued before the current
-// one is contracted and staged into a second buffer after it.  Block partials: partial[(pair * NB^3 * 2 + (p NB + b3) 2 + part) * nblocks
-// + block], as for the vector kernel.
+// row per cell padded to a stride = 2 (mod 8) float2 (bank-conflict free stores and reads) that
+// holds per bin w c_m1, c_m2, (Br, Bi - Br) and (Br + Bi, 0); the next tile's global loads are
+// issued before the current one is contracted and staged into a second buffer after it.  Block
+// partials: partial[(pair * NB^3 * 2 + (p NB + b3) 2 + part) * nblocks + block], as for the
+// vector kernel.
 #include "sb_kgen.h"
 
 namespace sb {
