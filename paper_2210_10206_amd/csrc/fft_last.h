@@ -552,9 +552,10 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
     constexpr int NW = NT / 64;
     constexpr int NOUT = PS::NOUT;
     constexpr int PITCH = P + 1;
-    // at 512 and 1024 points (first radix 16) position j of pencil p sits at j PITCH + p + j / 16:
-    // the first stage writes positions q R0 + r, which without the skew put a pencil's threads a
-    // multiple of 16 float2 (the width of the 32 banks) apart, all in one bank
+    // the transform's stages at 512 and 1024 points (first radix 16) keep position j of pencil p
+    // at j PITCH + p + j / 16: the first stage writes positions q R0 + r, which without the skew
+    // put a pencil's threads a multiple of 16 float2 (the width of the 32 banks) apart, all in one
+    // bank.  The [cell][bin] view written after the last stage keeps the plain layout.
     constexpr int SKEW = N >= 512 ? 1 : 0, GSH = 4;
     constexpr int NSTAGE = 1 + sizeof...(REST);
     constexpr int WPT = (N + NT - 1) / NT;
@@ -607,17 +608,14 @@ __global__ __launch_bounds__(NBT * (N / R0)) void last_rs_kernel(LastArgs a) {
         float2 *cs = ex;
         __syncthreads();                                    // the last stage has read the buffer
 #pragma unroll
-        for (int r = 0; r < R0; ++r) {
-            const int c = q + T * r;
-            cs[c * PITCH + (c >> GSH) * SKEW + pp] = v[r];
-        }
+        for (int r = 0; r < R0; ++r) cs[(q + T * r) * PITCH + pp] = v[r];
 #pragma unroll
         for (int e = 0; e < WPT; ++e)
             if (tid + e * NT < N) wsm[tid + e * NT] = wv[e];
         __syncthreads();
         if constexpr (!PF)
             if (row + 1 < r_end) load_row(row + 1, v, wv);   // in flight during the pair sums
-        ps.template tile<N, NW>(cs, 1, wsm, [](int c) { return c * PITCH + (c >> GSH) * SKEW; }, wave, lane);
+        ps.template tile<N, NW>(cs, 1, wsm, [](int c) { return c * PITCH; }, wave, lane);
     }
     // float64 combine over the waves in wave order (as in last_contract_kernel)
     __syncthreads();
