@@ -174,8 +174,9 @@ __global__ __launch_bounds__(NBT * R * TPP) void adj_last_kernel(AdjLastArgs a) 
 // reuses (one more barrier per row); that and at most 168 VGPRs (3 waves per SIMD) let four
 // 3-wave workgroups share a CU instead of two at 256 points and 12 padded bins.
 //
-// LDS layout: position j of pencil p at j * (P + 1) + p, and at 256 points with one skew slot
-// every 16 positions (+ j >> 4).  The first stage writes positions q R0 + r: in the plain layout
+// LDS layout: position j of pencil p at j * (P + 1) + p, and at 256 points, in the transform's
+// stages, with one skew slot every 16 positions (+ j >> 4); the [cell][bin] view of the per-cell
+// phase keeps the plain layout (a pencil's threads an odd pitch apart: no conflicts).  The first stage writes positions q R0 + r: in the plain layout
 // the threads of a pencil sit R0 (P + 1) float2 apart, a multiple of the 16 float2 that span the
 // 32 banks, so they all meet in one bank; the skew spreads them.  A bank model of every exchange,
 // transpose and per-cell access (32 banks, 16 lanes per float2 phase; it reproduces the measured
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(NBT * (N / R0), adj_rs_min_waves(1 + sizeof...(REST
     static_assert(NSTAGE >= 2, "two stages or more");
     static_assert(NBT <= 16, "the weight table is 16 x 16");
     __shared__ float2 ex[ONE ? 1 : 2][N * PITCH + (N >> GSH) * SKEW];
-    auto at = [](int j, int b) { return j * PITCH + b + (j >> GSH) * SKEW; };
+    auto at = [](int j, int b) { return j * PITCH + b; };   // the [cell][bin] view: plain layout
     float2 *ex1 = ex[ONE ? 0 : 1];
     __shared__ float2 tw[N];
     typedef const __attribute__((address_space(4))) float cfloat;
